@@ -28,7 +28,7 @@
  *     step keeps its output;
  *   - r is uniform on the odd multiples of 2^-24 in (-1,1);
  *   - randomness: Philox4x32-10 with key = seed and counter
- *     (step, p-bit, trial/4, purpose); trial k uses word k mod 4.
+ *     (step, p-bit/4, trial, purpose); p-bit i uses word i mod 4.
  *   - schedule: I0(t+1) = I0(t)/beta, beta = (I0min/I0max)^(1/(S-1)),
  *     computed in double and rounded to float per step;
  *   - I0min = 0.1/mean(s), I0max = 10/mean(s), s_i = sqrt((n-1) Var(J_i,:))
@@ -78,15 +78,16 @@ void psa_ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
 }
 
 /* Fresh randomness per (step, p-bit, trial): the listing draws a new
- * random vector rnd every cycle.  Counter = (t, i, k/4, tag), word k%4. */
+ * random vector rnd every cycle.  Counter = (t, i/4, k, tag): one block
+ * serves the four p-bits 4(i/4) .. 4(i/4)+3 of trial k, word i%4. */
 uint32_t psa_ref_word(uint64_t seed, uint32_t t, uint32_t i, uint32_t k,
                       uint32_t tag)
 {
-    uint32_t ctr[4] = {t, i, k >> 2, tag};
+    uint32_t ctr[4] = {t, i >> 2, k, tag};
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t out[4];
     psa_ref_philox4x32_10(ctr, key, out);
-    return out[k & 3u];
+    return out[i & 3u];
 }
 
 /* Eq. 1: r_i(t) uniform in (-1,1).  The top 25 bits with the lowest bit

@@ -33,7 +33,8 @@ void psa_ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
                            uint32_t out[4]);
 
 /* The 32-bit random word that p-bit i of trial k draws at step t for the
- * purpose `tag` (0 = initial spin, 1 = r, 2 = timing gate). */
+ * purpose `tag` (0 = initial spin, 1 = r, 2 = timing gate): word i mod 4 of
+ * the Philox block of counter (t, i/4, k, tag). */
 uint32_t psa_ref_word(uint64_t seed, uint32_t t, uint32_t i, uint32_t k,
                       uint32_t tag);
 

@@ -86,14 +86,15 @@ def test_philox_matches_rocrand(rocrand_philox):
 
 
 def test_random_words_match_rocrand_addressing(rocrand_philox):
-    """word(seed, t, i, k, tag) is word k%4 of Philox((t, i, k//4, tag), seed)."""
+    """word(seed, t, i, k, tag) is word i%4 of Philox((t, i//4, k, tag), seed)."""
     seed = 0x123456789ABCDEF
-    cases = [(0, 0, 0, 0), (7, 3, 5, 1), (999, 1999, 99, 2), (4, 19999, 1023, 1)]
-    rows = [[t, i, k >> 2, tag, seed & 0xFFFFFFFF, seed >> 32]
+    cases = [(0, 0, 0, 0), (7, 3, 5, 1), (999, 1999, 99, 2), (4, 19999, 1023, 1),
+             (4, 19998, 1023, 1)]
+    rows = [[t, i >> 2, k, tag, seed & 0xFFFFFFFF, seed >> 32]
             for t, i, k, tag in cases]
     ref = rocrand_philox(rows)
     for (t, i, k, tag), r in zip(cases, ref):
-        assert oracle.word(seed, t, i, k, tag) == int(r[k & 3])
+        assert oracle.word(seed, t, i, k, tag) == int(r[i & 3])
 
 
 def test_philox_words_uniform():
@@ -261,12 +262,12 @@ def test_init_spins_rule(rocrand_philox):
     s = oracle.init_spins(300, 9, 0, 40)
     assert set(np.unique(s)) <= {-1, 1}
     assert abs(s.mean()) < 5 / math.sqrt(s.size)
-    rows = [[0, i, k >> 2, 0, 9, 0] for k in (0, 5, 39) for i in (0, 17, 299)]
+    rows = [[0, i >> 2, k, 0, 9, 0] for k in (0, 5, 39) for i in (0, 17, 299)]
     ref = rocrand_philox(rows)
     q = 0
     for k in (0, 5, 39):
         for i in (0, 17, 299):
-            bit = int(ref[q][k & 3]) >> 31
+            bit = int(ref[q][i & 3]) >> 31
             assert s[k, i] == (1 if bit else -1)
             q += 1
     np.testing.assert_array_equal(oracle.init_spins(300, 9, 5, 12), s[5:12])
