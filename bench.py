@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Throughput of the pSA hot path on one MI355X.
+
+One benchmark step = one whole anneal of the workload with its inputs
+already resident in HBM: reset the spins of every trial (initial-state
+kernel), run all sweeps (the persistent anneal kernel), and reduce energy
+and cut per trial into device buffers.  The metric is p-bit updates per
+second, n * trials * steps per anneal / wall time of the timed steps.
+
+Default workload: random sparse graph n=2,000 (6,000 edges, +-1 weights),
+timing/intensity/offset variability sigma 0.1 (update probability mean 0.8),
+2,000 sweeps, 100 trials.  Other workloads: --workload c1 (G1-shaped ER,
+n=800, 1,000 sweeps, 10 trials) or c3 (G81-shaped 100x200 torus, 5,000 sweeps,
+1,024 trials).
+
+Besides the contract fields the JSON line carries:
+  roofline     -- the anneal kernel's algorithmic VALU lane-operations per
+                  launch over its average duration (HIP events on the
+                  library's stream) against the chip's VALU issue rate;
+  cpu_baseline -- the oracle timed on this host's cores on a bounded sample
+                  of the same workload (trials spread over threads).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic 32-bit lane-operations per p-bit update:
+# one Philox4x32-10 block = 10 rounds x (2 mul_lo + 2 mul_hi + 4 xor) = 80,
+# shared by the 4 trials of a quad; the timing gate needs a second block.
+PHILOX_BLOCK_OPS = 80
+OPS_R_MAP = 4          # shift-or, subtract, convert, scale
+OPS_GATE_MAP = 2       # shift, compare
+OPS_PREACT = 3.25      # int->float, + delta, * a  (a = I0*lambda once per quad)
+OPS_TANH = 17          # |x|, scale, round, sub, 7 fma, ldexp, add, div, sub, sign
+OPS_DECIDE = 2         # compare with r, select
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes, one 32-bit VALU op per lane per clock
+# at 2.4 GHz (the 157.3 TFLOP/s FP32 figure counts an FMA as 2 and dual issue).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def ops_per_update(mean_degree: float, timing: bool) -> float:
+    philox = PHILOX_BLOCK_OPS / 4 * (2 if timing else 1)
+    return (philox + OPS_R_MAP + (OPS_GATE_MAP if timing else 0) + mean_degree
+            + OPS_PREACT + OPS_TANH + OPS_DECIDE)
+
+
+def cpu_baseline(spec, budget_s: float = 15.0):
+    """Time the oracle on a bounded sample: the first `k` trials over the
+    full schedule, k chosen so the single-thread work is about budget_s."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    oracle.build(force=False)
+    n, u, v, w = spec["n"], spec["u"], spec["v"], spec["w"]
+    S = spec["steps"]
+    i0, _, _ = oracle.schedule_paper(n, u, v, -w, S)
+    lam, dlt, thr = oracle.variability(n, spec["seed"], spec["sigma_lambda"],
+                                       spec["sigma_delta"], spec["sigma_nu"],
+                                       spec["p_mean"])
+    # calibrate: one trial, a few steps
+    cal_steps = max(1, min(S, 50))
+    t0 = time.perf_counter()
+    oracle.run(n, u, v, -w, None, i0, lam, dlt, thr, spec["seed"], 0, 1, 0, cal_steps,
+               oracle.init_spins(n, spec["seed"], 0, 1))
+    per_update = (time.perf_counter() - t0) / (n * cal_steps)
+    cores = min(os.cpu_count() or 1, 16)
+    trials = max(1, min(spec["trials"], int(budget_s / (per_update * n * S))))
+    trials = max(min(cores, spec["trials"]), trials)
+    bounds = np.linspace(0, trials, min(cores, trials) + 1).astype(int)
+    parts = [(int(a), int(b)) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(len(parts)) as ex:
+        list(ex.map(lambda ab: oracle.anneal(n, u, v, -w, None, i0, lam, dlt, thr,
+                                             spec["seed"], ab[0], ab[1]), parts))
+    dt = time.perf_counter() - t0
+    updates = n * trials * S
+    return {"value": updates / dt, "unit": "p-bit updates/s", "cores": len(parts),
+            "kind": "oracle",
+            "sample": f"{trials} of {spec['trials']} trials x all {S} steps x n={n} "
+                      f"({updates:.3g} updates, {dt:.2f} s wall on {len(parts)} threads)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--tpw", type=int, default=0, help="trials per workgroup (0 = auto)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "trials and jobs shard across GPUs without communication, but no "
+              "multi-GPU figure is produced here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2601_14476_amd import inputs, psa
+
+    spec = inputs.workload(args.workload)
+    n, u, v, w = spec["n"], spec["u"], spec["v"], spec["w"]
+    T, S = spec["trials"], spec["steps"]
+    torch.cuda.set_device(0)
+    # A non-default torch stream: the library launches on it and the HIP
+    # events below are recorded on it, so they bracket the kernels exactly.
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    ctx = psa.Context(0, stream)
+    g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
+    info = g.info()
+    job = psa.Job(ctx, g, S, T, spec["seed"], sigma_lambda=spec["sigma_lambda"],
+                  sigma_delta=spec["sigma_delta"], sigma_nu=spec["sigma_nu"],
+                  p_mean=spec["p_mean"], block=args.block, trials_per_group=args.tpw)
+    E = torch.empty(T, dtype=torch.int64, device="cuda")
+    C = torch.empty(T, dtype=torch.int64, device="cuda")
+
+    def one_step(ev=None):
+        job.reset()
+        if ev is not None:
+            ev[0].record(stream)
+        job.step(S)
+        if ev is not None:
+            ev[1].record(stream)
+        job.energy_cut(E, C)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        one_step(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+
+    updates = n * T * S
+    value = updates * args.steps / wall
+    timing = spec["sigma_nu"] > 0 or spec["p_mean"] < 1.0
+    mean_deg = info["nnz"] / n
+    opu = ops_per_update(mean_deg, timing)
+    achieved = opu * updates / (kernel_ms * 1e-3) / 1e12
+    line = {
+        "metric": "p-bit updates/s (n x trials x steps / s), 1 GPU",
+        "value": value,
+        "unit": "p-bit updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8 spins / int32 field / f32 pre-activation",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "graph": spec["graph"][0],
+            "n": n, "edges": int(u.size), "trials": T, "sweeps": S,
+            "sigma_lambda": spec["sigma_lambda"], "sigma_delta": spec["sigma_delta"],
+            "sigma_nu": spec["sigma_nu"], "p_mean": spec["p_mean"],
+            "updates_per_anneal": updates,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "anneal_lds_kernel",
+            "achieved": achieved,
+            "peak": VALU_PEAK_TOPS,
+            "unit": "TOP/s",
+            "frac": achieved / VALU_PEAK_TOPS,
+            "traffic": None,
+            "ops_per_update": opu,
+            "kernel_ms": kernel_ms,
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(line), flush=True)
+    job.close()
+    g.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,243 @@
+/*
+ * psa.h -- C ABI of libpsa, an MI355X (gfx950) engine for p-bit simulated
+ * annealing (pSA) with device variability on Ising models of MAX-CUT.
+ *
+ * Method: Onizawa & Hanyu, "GPU-accelerated simulated annealing based on
+ * p-bits with real-world device-variability modeling", arXiv 2601.14476.
+ *   - p-bit output            : Eq. 1, sigma_i(t+1) = sgn(r_i(t) + tanh(I_i(t)))
+ *   - Ising energy            : Eq. 2, H = -sum h_i s_i - sum_{i<j} J_ij s_i s_j
+ *   - p-bit input             : Eq. 3, I_i = I0 (h_i + sum_j J_ij s_j)
+ *   - variability p-bit       : Eq. 6, intensity lambda_i, offset delta_i, timing nu_i
+ *   - variability draws       : Eq. 7, lambda ~ N(1, sl^2), delta ~ N(0, sd^2), nu ~ N(0, sn^2)
+ *   - schedule                : Methods (experimental conditions),
+ *                               I0(t+1) = I0(t)/beta, beta = (I0min/I0max)^(1/(cycle-1)),
+ *                               I0min = 0.1/mean(s_i), I0max = 10/mean(s_i)
+ *   - SimulatedAnnealingModule: the pseudo-code listing of the update kernel
+ *
+ * What one step computes, for every trial k and p-bit i at once (all p-bits
+ * read the spins of the previous step):
+ *     L_i   = h_i + sum_j J_ij m_j                         (int32, exact)
+ *     fire  = thr24_i >= 2^24  or  (u_gate >> 8) < thr24_i  (timing factor)
+ *     x     = (I0[t] * lambda_i) * ((float)L_i + delta_i)   (FP32, this order)
+ *     m_i'  = fire ? (tanh(x) > r ? +1 : -1) : m_i
+ * with r uniform on the odd multiples of 2^-24 in (-1,1) and all random
+ * words from Philox4x32-10 (key = seed, counter = (t, i/4, k, purpose),
+ * word i mod 4).  Results are bit-identical for any launch geometry.
+ *
+ * Conventions
+ *   - Every call returns a psa_status; on failure the outputs are left
+ *     untouched and psa_last_error() describes the failure (thread-local).
+ *   - Nothing throws across the ABI.  No call keeps a pointer it was given:
+ *     host arrays are copied before the call returns.
+ *   - "device pointer" arguments are HIP device addresses on the context's
+ *     device (for instance torch.Tensor.data_ptr() of a cuda tensor); work
+ *     on them is ordered on the context's stream.  Flags select whether an
+ *     output pointer is host or device memory.
+ *   - Objects (context, graph, job) are not thread-safe; use one per thread
+ *     or serialise calls.
+ */
+#ifndef PSA_H
+#define PSA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t psa_status;
+#define PSA_OK 0
+#define PSA_EINVAL (-1)       /* bad argument or invalid graph          */
+#define PSA_ENOMEM (-2)       /* host or device allocation failed        */
+#define PSA_EHIP (-3)         /* a HIP runtime call failed               */
+#define PSA_EUNSUPPORTED (-4) /* valid request this build cannot serve   */
+
+typedef struct psa_ctx psa_ctx;
+typedef struct psa_graph psa_graph;
+typedef struct psa_job psa_job;
+
+/* ------------------------------------------------------------------ */
+/* Context and errors                                                   */
+/* ------------------------------------------------------------------ */
+
+/* Library version string, e.g. "0.1.0 gfx950".  Static storage. */
+const char *psa_version(void);
+
+/* Thread-local text of the last failure on this thread ("" if none).
+ * Valid until the next failing call on the same thread. */
+const char *psa_last_error(void);
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * owned by the caller (NULL = the context creates and owns one).  All
+ * device work of objects made from this context is ordered on it. */
+psa_status psa_ctx_create(int32_t device, void *hip_stream, psa_ctx **out);
+
+/* Wait for all work queued on the context's stream. */
+psa_status psa_ctx_synchronize(psa_ctx *ctx);
+
+/* Destroy the context (after its graphs and jobs).  NULL is ignored. */
+void psa_ctx_destroy(psa_ctx *ctx);
+
+/* ------------------------------------------------------------------ */
+/* Graphs (Eq. 2-3: couplings J and biases h)                           */
+/* ------------------------------------------------------------------ */
+
+#define PSA_GRAPH_ISING 0u  /* edge values are couplings J_uv            */
+#define PSA_GRAPH_MAXCUT 1u /* edge values are MAX-CUT weights w, J = -w */
+
+typedef struct psa_graph_info {
+    int32_t n;             /* p-bits                                      */
+    int64_t edges;         /* undirected edges (pairs i<j with J_ij != 0) */
+    int64_t nnz;           /* 2 * edges: stored directed entries          */
+    int64_t w_total;       /* sum over edges of w_ij = -J_ij              */
+    int32_t max_abs_field; /* max_i |h_i| + sum_j |J_ij|  (< 2^24)        */
+    int32_t max_degree;    /* largest row length                          */
+    int32_t unit_weights;  /* 1 if every |J_ij| == 1                      */
+    double mean_s;         /* mean_i sqrt((n-1) Var(J_i,:)), dense rows   */
+} psa_graph_info;
+
+/* Build a graph from an undirected edge list on the host: edge e joins
+ * u[e] and v[e] (0 <= u,v < n, u != v, each pair at most once) with value
+ * val[e] (a coupling, or a MAX-CUT weight with PSA_GRAPH_MAXCUT).  h may be
+ * NULL (all zero).  The arrays are copied; the graph is uploaded to the
+ * context's device in CSR form.  EINVAL on self loops, repeated pairs,
+ * indices out of range, or max_i |h_i| + sum_j |J_ij| >= 2^24 (which keeps
+ * the float conversion of every field exact). */
+psa_status psa_graph_from_edges(psa_ctx *ctx, int32_t n, int64_t m,
+                                const int32_t *u, const int32_t *v,
+                                const int32_t *val, const int32_t *h,
+                                uint32_t flags, psa_graph **out);
+
+/* Build a graph from a symmetric host CSR (row_ptr[n+1], col[nnz], val[nnz],
+ * no diagonal, no repeated column in a row, val[i->j] == val[j->i]). */
+psa_status psa_graph_from_csr(psa_ctx *ctx, int32_t n, const int64_t *row_ptr,
+                              const int32_t *col, const int32_t *val,
+                              const int32_t *h, uint32_t flags,
+                              psa_graph **out);
+
+psa_status psa_graph_info_get(const psa_graph *g, psa_graph_info *out);
+void psa_graph_destroy(psa_graph *g);
+
+/* ------------------------------------------------------------------ */
+/* Schedule (Methods, experimental conditions)                         */
+/* ------------------------------------------------------------------ */
+
+/* The paper's I0 endpoints for graph g: I0min = 0.1/mean(s_i),
+ * I0max = 10/mean(s_i).  EINVAL if mean(s_i) == 0 (no couplings). */
+psa_status psa_schedule_paper(const psa_graph *g, double *i0_min,
+                              double *i0_max);
+
+/* Fill host i0_out[steps] with I0(0) = i0_min, I0(t+1) = I0(t)/beta,
+ * beta = (i0_min/i0_max)^(1/(steps-1)), evaluated in double and rounded to
+ * float per step.  EINVAL unless steps >= 1 and 0 < i0_min <= i0_max. */
+psa_status psa_schedule_fill(int32_t steps, double i0_min, double i0_max,
+                             float *i0_out);
+
+/* ------------------------------------------------------------------ */
+/* Device variability (Eq. 6-7)                                         */
+/* ------------------------------------------------------------------ */
+
+/* Draw the per-p-bit factors once per run, on the host, from the run seed:
+ *   lambda_i = 1 + sigma_lambda z1     (intensity, Eq. 7a)
+ *   delta_i  = sigma_delta z2          (offset, Eq. 7b)
+ *   p_i      = clip(p_mean + sigma_nu z3, 0, 1), thr24_i = floor(p_i 2^24)
+ *              (timing, Eq. 7c, as a per-step update probability)
+ * with z1..z3 standard normals (Box-Muller, cosine branch) from the Philox
+ * words of counters (0, i, 0, 3) and (0, i, 1, 3).  Outputs are host
+ * arrays of n entries.  EINVAL on negative sigmas or p_mean outside [0,1]. */
+psa_status psa_variability_draw(int32_t n, uint64_t seed, double sigma_lambda,
+                                double sigma_delta, double sigma_nu,
+                                double p_mean, float *lambda_out,
+                                float *delta_out, uint32_t *thr24_out);
+
+/* ------------------------------------------------------------------ */
+/* Runs                                                                  */
+/* ------------------------------------------------------------------ */
+
+/* Description of one anneal.  Optional host arrays (NULL = derived):
+ *   i0[steps]              -- schedule; else psa_schedule_fill(i0_min, i0_max)
+ *                             and, if i0_min <= 0, the paper's endpoints
+ *   lambda/delta/thr24[n]  -- variability; else psa_variability_draw(...)
+ * trials >= 1, steps >= 1.  Launch shape (results never depend on it):
+ * `block` = threads per workgroup (0 = auto, else 256, 512 or 1024) and
+ * `trials_per_group` = trials one workgroup advances (0 = auto, 1 or 4). */
+typedef struct psa_run_desc {
+    int32_t steps;
+    int32_t trials;
+    uint64_t seed;
+    double i0_min;
+    double i0_max;
+    const float *i0;
+    double sigma_lambda;
+    double sigma_delta;
+    double sigma_nu;
+    double p_mean;
+    const float *lambda;
+    const float *delta;
+    const uint32_t *thr24;
+    int32_t block;
+    int32_t trials_per_group;
+    uint32_t flags; /* reserved, 0 */
+} psa_run_desc;
+
+/* Fill *d with the defaults: steps 1000, trials 1, seed 0, the paper's I0
+ * endpoints (i0_min = i0_max = -1), no variability (sigmas 0, p_mean 1),
+ * no explicit arrays, automatic block size. */
+void psa_run_desc_default(psa_run_desc *d);
+
+/* Output placement flags of the read calls and psa_anneal. */
+#define PSA_OUT_HOST 0u
+#define PSA_OUT_DEVICE 1u
+
+/* Create a job: upload the schedule and variability arrays, allocate the
+ * device spin state (int8, [n][trials rounded up to 4], trials innermost)
+ * and set the initial spins (m_i = +1 iff bit 31 of the Philox word of
+ * counter (0, i/4, k, 0), word i mod 4).  The job is at step 0.
+ * EUNSUPPORTED if the spin state of one workgroup's trials does not fit in
+ * LDS (n above about 20,000 with 4 trials per workgroup, 80,000 with 1). */
+psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g,
+                          const psa_run_desc *desc, psa_job **out);
+
+/* Re-initialise the spins of every trial (as at creation) and return to
+ * step 0, on the context's stream; schedule and variability are kept. */
+psa_status psa_job_reset(psa_job *job);
+
+/* Queue `k` more steps (t .. t+k-1, clipped to the schedule length) on the
+ * context's stream; returns once they are queued. */
+psa_status psa_job_step(psa_job *job, int32_t k);
+
+/* Current step index t (the number of steps applied so far). */
+psa_status psa_job_position(const psa_job *job, int32_t *t);
+
+/* Spins as int8 [trials][n] into host or device memory (flags).  Host
+ * outputs synchronise the stream first. */
+psa_status psa_job_read_spins(psa_job *job, int8_t *out, uint32_t flags);
+
+/* Replace the spins of all trials by in[trials][n] (+1/-1 only; host or
+ * device per flags) and set the step index to t (checkpoint / resume). */
+psa_status psa_job_write_spins(psa_job *job, const int8_t *in, int32_t t,
+                               uint32_t flags);
+
+/* Local fields L_i = h_i + sum_j J_ij m_j of the current spins (Eq. 3
+ * without the I0 factor), int32 [trials][n]. */
+psa_status psa_job_local_field(psa_job *job, int32_t *out, uint32_t flags);
+
+/* Energy H (Eq. 2) and cut sum_{i<j} w_ij [m_i != m_j] (w = -J) of the
+ * current spins, int64 [trials] each. */
+psa_status psa_job_energy_cut(psa_job *job, int64_t *energy, int64_t *cut,
+                              uint32_t flags);
+
+void psa_job_destroy(psa_job *job);
+
+/* Whole anneal: create, all steps, energy and cut, read-out.  spins_out
+ * ([trials][n]) may be NULL.  Blocks until the results are written. */
+psa_status psa_anneal(psa_ctx *ctx, const psa_graph *g,
+                      const psa_run_desc *desc, int8_t *spins_out,
+                      int64_t *energy_out, int64_t *cut_out, uint32_t flags);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSA_H */

@@ -1,0 +1,669 @@
+// abi.cpp -- the extern "C" surface of libpsa (declared in include/psa.h):
+// contexts, graph ingestion (edge list or CSR -> validated symmetric CSR on
+// the device), runs (jobs) and their read-outs.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <limits>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "engine.hpp"
+#include "psa.h"
+
+namespace psa {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+const char *last_error_cstr() { return g_last_error.c_str(); }
+
+}  // namespace psa
+
+using psa::set_error;
+
+namespace {
+
+psa_status hip_fail(hipError_t err, const char *what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(err));
+    return PSA_EHIP;
+}
+
+#define PSA_HIP(expr, what)                          \
+    do {                                             \
+        hipError_t _e = (expr);                      \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+template <typename T>
+psa_status dev_upload(T **dst, const T *src, size_t count, const char *what) {
+    *dst = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), count * sizeof(T));
+    if (e != hipSuccess) {
+        *dst = nullptr;
+        set_error(std::string(what) + ": device allocation failed");
+        return PSA_ENOMEM;
+    }
+    if (src) {
+        e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, what);
+    }
+    return PSA_OK;
+}
+
+template <typename T>
+void dev_free(T *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+void graph_free(psa_graph *g) {
+    if (!g) return;
+    dev_free(g->d_row_ptr);
+    dev_free(g->d_col);
+    dev_free(g->d_val);
+    dev_free(g->d_h);
+    dev_free(g->d_pk32);
+    dev_free(g->d_pk16);
+    delete g;
+}
+
+// Sort each row by column, reject repeated columns and diagonal entries.
+psa_status canonical_rows(int32_t n, const std::vector<int64_t> &row_ptr,
+                          std::vector<int32_t> &col, std::vector<int32_t> &val) {
+    std::vector<std::pair<int32_t, int32_t>> tmp;
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t b = row_ptr[i], e = row_ptr[i + 1];
+        tmp.clear();
+        for (int64_t p = b; p < e; ++p) tmp.emplace_back(col[p], val[p]);
+        std::sort(tmp.begin(), tmp.end());
+        for (size_t k = 0; k < tmp.size(); ++k) {
+            if (tmp[k].first == i) {
+                set_error("graph: self loop at p-bit " + std::to_string(i));
+                return PSA_EINVAL;
+            }
+            if (k > 0 && tmp[k].first == tmp[k - 1].first) {
+                set_error("graph: repeated pair (" + std::to_string(i) + ", " +
+                          std::to_string(tmp[k].first) + ")");
+                return PSA_EINVAL;
+            }
+            col[b + static_cast<int64_t>(k)] = tmp[k].first;
+            val[b + static_cast<int64_t>(k)] = tmp[k].second;
+        }
+    }
+    return PSA_OK;
+}
+
+// Statistics, bounds and upload of a canonical symmetric CSR.
+psa_status finish_graph(psa_ctx *ctx, int32_t n, const std::vector<int64_t> &row_ptr,
+                        const std::vector<int32_t> &col, const std::vector<int32_t> &val,
+                        const int32_t *h, psa_graph **out) {
+    const int64_t nnz = row_ptr[n];
+    if (nnz >= (int64_t{1} << 31)) {
+        set_error("graph: more than 2^31 - 1 stored couplings");
+        return PSA_EUNSUPPORTED;
+    }
+    psa_graph_info info{};
+    info.n = n;
+    info.nnz = nnz;
+    info.edges = nnz / 2;
+    int64_t w2 = 0;
+    int64_t max_field = 0;
+    int32_t max_deg = 0;
+    bool unit = true;
+    double sum_s = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        int64_t s1 = 0, s2 = 0, absrow = h ? std::llabs(static_cast<int64_t>(h[i])) : 0;
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            const int64_t J = val[p];
+            s1 += J;
+            s2 += J * J;
+            absrow += std::llabs(J);
+            if (J != 1 && J != -1) unit = false;
+        }
+        w2 += s1;
+        max_field = std::max(max_field, absrow);
+        max_deg = std::max<int32_t>(max_deg, static_cast<int32_t>(row_ptr[i + 1] - row_ptr[i]));
+        // s_i = sqrt((n-1) Var(J_i,:)), population variance over the n
+        // entries of the dense row: Var = (n s2 - s1^2) / n^2.
+        const int64_t num = static_cast<int64_t>(n) * s2 - s1 * s1;
+        const double var = static_cast<double>(num) / (static_cast<double>(n) * static_cast<double>(n));
+        sum_s += sqrt(static_cast<double>(n - 1) * var);
+    }
+    if (max_field >= (int64_t{1} << 24)) {
+        set_error("graph: max_i |h_i| + sum_j |J_ij| must be < 2^24");
+        return PSA_EINVAL;
+    }
+    info.w_total = -(w2 / 2);
+    info.max_abs_field = static_cast<int32_t>(max_field);
+    info.max_degree = max_deg;
+    info.unit_weights = (unit && nnz > 0) ? 1 : 0;
+    info.mean_s = sum_s / static_cast<double>(n);
+
+    std::unique_ptr<psa_graph, void (*)(psa_graph *)> g(new psa_graph(), graph_free);
+    g->ctx = ctx;
+    g->info = info;
+    PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    std::vector<int32_t> rp32(static_cast<size_t>(n) + 1);
+    for (int32_t i = 0; i <= n; ++i) rp32[i] = static_cast<int32_t>(row_ptr[i]);
+    std::vector<int32_t> hz;
+    if (!h) hz.assign(static_cast<size_t>(n), 0);
+    psa_status st;
+    if ((st = dev_upload(&g->d_row_ptr, rp32.data(), rp32.size(), "graph upload")) != PSA_OK) return st;
+    if ((st = dev_upload(&g->d_col, col.data(), col.size(), "graph upload")) != PSA_OK) return st;
+    if ((st = dev_upload(&g->d_val, val.data(), val.size(), "graph upload")) != PSA_OK) return st;
+    if ((st = dev_upload(&g->d_h, h ? h : hz.data(), static_cast<size_t>(n), "graph upload")) != PSA_OK)
+        return st;
+    // Packed copies of the edges for the anneal kernel (one load per edge).
+    bool fits16 = true;
+    for (int64_t p = 0; p < nnz; ++p)
+        if (val[p] < -32768 || val[p] > 32767) fits16 = false;
+    if (n <= 65536 && fits16) {
+        std::vector<uint32_t> pk(static_cast<size_t>(nnz));
+        for (int64_t p = 0; p < nnz; ++p)
+            pk[p] = static_cast<uint32_t>(col[p]) | (static_cast<uint32_t>(val[p]) << 16);
+        if ((st = dev_upload(&g->d_pk32, pk.data(), pk.size(), "graph upload")) != PSA_OK) return st;
+    }
+    if (n <= 32768 && info.unit_weights) {
+        std::vector<uint16_t> pk(static_cast<size_t>(nnz));
+        for (int64_t p = 0; p < nnz; ++p)
+            pk[p] = static_cast<uint16_t>((static_cast<uint32_t>(col[p]) << 1) | (val[p] < 0 ? 1u : 0u));
+        if ((st = dev_upload(&g->d_pk16, pk.data(), pk.size(), "graph upload")) != PSA_OK) return st;
+    }
+    g->dev.pk32 = g->d_pk32;
+    g->dev.pk16 = g->d_pk16;
+    g->dev.n = n;
+    g->dev.nnz = nnz;
+    g->dev.row_ptr = g->d_row_ptr;
+    g->dev.col = g->d_col;
+    g->dev.val = g->d_val;
+    g->dev.h = g->d_h;
+    g->dev.w2 = w2;
+    *out = g.release();
+    return PSA_OK;
+}
+
+void job_free(psa_job *j) {
+    if (!j) return;
+    if (j->ctx) {
+        (void)hipSetDevice(j->ctx->device);
+        (void)hipStreamSynchronize(j->ctx->stream);
+    }
+    dev_free(j->d_i0);
+    dev_free(j->d_lambda);
+    dev_free(j->d_delta);
+    dev_free(j->d_thr24);
+    dev_free(j->d_spins);
+    dev_free(j->d_scratch);
+    delete j;
+}
+
+psa_status ensure_scratch(psa_job *j, size_t bytes) {
+    if (j->scratch_bytes >= bytes) return PSA_OK;
+    PSA_HIP(hipStreamSynchronize(j->ctx->stream), "hipStreamSynchronize");
+    dev_free(j->d_scratch);
+    j->scratch_bytes = 0;
+    if (hipMalloc(&j->d_scratch, bytes) != hipSuccess) {
+        j->d_scratch = nullptr;
+        set_error("job: scratch allocation failed");
+        return PSA_ENOMEM;
+    }
+    j->scratch_bytes = bytes;
+    return PSA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *psa_version(void) { return "0.1.0 gfx950"; }
+
+const char *psa_last_error(void) { return psa::last_error_cstr(); }
+
+psa_status psa_ctx_create(int32_t device, void *hip_stream, psa_ctx **out) {
+    if (!out) {
+        set_error("psa_ctx_create: out is NULL");
+        return PSA_EINVAL;
+    }
+    int count = 0;
+    PSA_HIP(hipGetDeviceCount(&count), "hipGetDeviceCount");
+    if (device < 0 || device >= count) {
+        set_error("psa_ctx_create: no HIP device " + std::to_string(device));
+        return PSA_EINVAL;
+    }
+    PSA_HIP(hipSetDevice(device), "hipSetDevice");
+    std::unique_ptr<psa_ctx> c(new psa_ctx());
+    c->device = device;
+    PSA_HIP(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device),
+            "hipDeviceGetAttribute");
+    int lds = 0;
+    PSA_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device),
+            "hipDeviceGetAttribute");
+    c->max_lds = static_cast<size_t>(lds);
+    if (hip_stream) {
+        c->stream = static_cast<hipStream_t>(hip_stream);
+        c->own_stream = false;
+    } else {
+        PSA_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "hipStreamCreate");
+        c->own_stream = true;
+    }
+    *out = c.release();
+    return PSA_OK;
+}
+
+psa_status psa_ctx_synchronize(psa_ctx *ctx) {
+    if (!ctx) {
+        set_error("psa_ctx_synchronize: ctx is NULL");
+        return PSA_EINVAL;
+    }
+    PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    PSA_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    return PSA_OK;
+}
+
+void psa_ctx_destroy(psa_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+psa_status psa_graph_from_edges(psa_ctx *ctx, int32_t n, int64_t m, const int32_t *u,
+                                const int32_t *v, const int32_t *val, const int32_t *h,
+                                uint32_t flags, psa_graph **out) {
+    if (!ctx || !out || n < 1 || m < 0 || (m > 0 && (!u || !v || !val)) ||
+        (flags & ~PSA_GRAPH_MAXCUT) != 0) {
+        set_error("psa_graph_from_edges: invalid arguments");
+        return PSA_EINVAL;
+    }
+    const bool maxcut = (flags & PSA_GRAPH_MAXCUT) != 0;
+    std::vector<int64_t> row_ptr(static_cast<size_t>(n) + 1, 0);
+    for (int64_t e = 0; e < m; ++e) {
+        if (u[e] < 0 || u[e] >= n || v[e] < 0 || v[e] >= n) {
+            set_error("psa_graph_from_edges: edge " + std::to_string(e) + " out of range");
+            return PSA_EINVAL;
+        }
+        if (u[e] == v[e]) {
+            set_error("psa_graph_from_edges: self loop at edge " + std::to_string(e));
+            return PSA_EINVAL;
+        }
+        if (val[e] == std::numeric_limits<int32_t>::min()) {
+            set_error("psa_graph_from_edges: edge value out of range");
+            return PSA_EINVAL;
+        }
+        ++row_ptr[u[e] + 1];
+        ++row_ptr[v[e] + 1];
+    }
+    for (int32_t i = 0; i < n; ++i) row_ptr[i + 1] += row_ptr[i];
+    std::vector<int32_t> col(static_cast<size_t>(row_ptr[n])), vv(static_cast<size_t>(row_ptr[n]));
+    std::vector<int64_t> fill(row_ptr.begin(), row_ptr.end() - 1);
+    for (int64_t e = 0; e < m; ++e) {
+        const int32_t J = maxcut ? -val[e] : val[e];
+        col[fill[u[e]]] = v[e];
+        vv[fill[u[e]]++] = J;
+        col[fill[v[e]]] = u[e];
+        vv[fill[v[e]]++] = J;
+    }
+    psa_status st = canonical_rows(n, row_ptr, col, vv);
+    if (st != PSA_OK) return st;
+    return finish_graph(ctx, n, row_ptr, col, vv, h, out);
+}
+
+psa_status psa_graph_from_csr(psa_ctx *ctx, int32_t n, const int64_t *row_ptr, const int32_t *col,
+                              const int32_t *val, const int32_t *h, uint32_t flags,
+                              psa_graph **out) {
+    if (!ctx || !out || n < 1 || !row_ptr || (flags & ~PSA_GRAPH_MAXCUT) != 0) {
+        set_error("psa_graph_from_csr: invalid arguments");
+        return PSA_EINVAL;
+    }
+    if (row_ptr[0] != 0) {
+        set_error("psa_graph_from_csr: row_ptr[0] must be 0");
+        return PSA_EINVAL;
+    }
+    for (int32_t i = 0; i < n; ++i)
+        if (row_ptr[i + 1] < row_ptr[i]) {
+            set_error("psa_graph_from_csr: row_ptr is not non-decreasing");
+            return PSA_EINVAL;
+        }
+    const int64_t nnz = row_ptr[n];
+    if (nnz > 0 && (!col || !val)) {
+        set_error("psa_graph_from_csr: col/val NULL");
+        return PSA_EINVAL;
+    }
+    const bool maxcut = (flags & PSA_GRAPH_MAXCUT) != 0;
+    std::vector<int64_t> rp(row_ptr, row_ptr + n + 1);
+    std::vector<int32_t> cc(static_cast<size_t>(nnz)), vv(static_cast<size_t>(nnz));
+    for (int64_t p = 0; p < nnz; ++p) {
+        if (col[p] < 0 || col[p] >= n || val[p] == std::numeric_limits<int32_t>::min()) {
+            set_error("psa_graph_from_csr: entry " + std::to_string(p) + " out of range");
+            return PSA_EINVAL;
+        }
+        cc[p] = col[p];
+        vv[p] = maxcut ? -val[p] : val[p];
+    }
+    psa_status st = canonical_rows(n, rp, cc, vv);
+    if (st != PSA_OK) return st;
+    // symmetry: J_ij == J_ji for every stored entry
+    for (int32_t i = 0; i < n; ++i)
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+            const int32_t j = cc[p];
+            auto b = cc.begin() + rp[j], e = cc.begin() + rp[j + 1];
+            auto it = std::lower_bound(b, e, i);
+            if (it == e || *it != i || vv[it - cc.begin()] != vv[p]) {
+                set_error("psa_graph_from_csr: CSR is not symmetric at (" + std::to_string(i) +
+                          ", " + std::to_string(j) + ")");
+                return PSA_EINVAL;
+            }
+        }
+    return finish_graph(ctx, n, rp, cc, vv, h, out);
+}
+
+psa_status psa_graph_info_get(const psa_graph *g, psa_graph_info *out) {
+    if (!g || !out) {
+        set_error("psa_graph_info_get: NULL argument");
+        return PSA_EINVAL;
+    }
+    *out = g->info;
+    return PSA_OK;
+}
+
+void psa_graph_destroy(psa_graph *g) {
+    if (g && g->ctx) {
+        (void)hipSetDevice(g->ctx->device);
+        (void)hipStreamSynchronize(g->ctx->stream);
+    }
+    graph_free(g);
+}
+
+psa_status psa_schedule_paper(const psa_graph *g, double *i0_min, double *i0_max) {
+    if (!g || !i0_min || !i0_max) {
+        set_error("psa_schedule_paper: NULL argument");
+        return PSA_EINVAL;
+    }
+    if (!(g->info.mean_s > 0.0)) {
+        set_error("psa_schedule_paper: mean(s_i) is zero (graph has no couplings)");
+        return PSA_EINVAL;
+    }
+    *i0_min = 0.1 / g->info.mean_s;
+    *i0_max = 10.0 / g->info.mean_s;
+    return PSA_OK;
+}
+
+psa_status psa_schedule_fill(int32_t steps, double i0_min, double i0_max, float *i0_out) {
+    return psa::fill_schedule(steps, i0_min, i0_max, i0_out);
+}
+
+psa_status psa_variability_draw(int32_t n, uint64_t seed, double sigma_lambda,
+                                double sigma_delta, double sigma_nu, double p_mean,
+                                float *lambda_out, float *delta_out, uint32_t *thr24_out) {
+    return psa::draw_variability(n, seed, sigma_lambda, sigma_delta, sigma_nu, p_mean, lambda_out,
+                                 delta_out, thr24_out);
+}
+
+void psa_run_desc_default(psa_run_desc *d) {
+    if (!d) return;
+    memset(d, 0, sizeof(*d));
+    d->steps = 1000;
+    d->trials = 1;
+    d->i0_min = -1.0;
+    d->i0_max = -1.0;
+    d->p_mean = 1.0;
+}
+
+psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *desc,
+                          psa_job **out) {
+    if (!ctx || !g || !desc || !out) {
+        set_error("psa_job_create: NULL argument");
+        return PSA_EINVAL;
+    }
+    if (g->ctx != ctx) {
+        set_error("psa_job_create: graph belongs to another context");
+        return PSA_EINVAL;
+    }
+    const int32_t n = g->info.n;
+    if (desc->steps < 1 || desc->trials < 1 || desc->trials > (1 << 28)) {
+        set_error("psa_job_create: need steps >= 1 and 1 <= trials <= 2^28");
+        return PSA_EINVAL;
+    }
+    if (desc->block != 0 && desc->block != 256 && desc->block != 512 && desc->block != 1024) {
+        set_error("psa_job_create: block must be 0, 256, 512 or 1024");
+        return PSA_EINVAL;
+    }
+    if (desc->trials_per_group != 0 && desc->trials_per_group != 1 &&
+        desc->trials_per_group != 4) {
+        set_error("psa_job_create: trials_per_group must be 0, 1 or 4");
+        return PSA_EINVAL;
+    }
+    const int32_t S = desc->steps;
+    std::vector<float> i0(static_cast<size_t>(S));
+    if (desc->i0) {
+        for (int32_t t = 0; t < S; ++t) {
+            if (!(std::isfinite(desc->i0[t]))) {
+                set_error("psa_job_create: non-finite I0");
+                return PSA_EINVAL;
+            }
+            i0[t] = desc->i0[t];
+        }
+    } else {
+        double lo = desc->i0_min, hi = desc->i0_max;
+        if (!(lo > 0.0)) {
+            psa_status st = psa_schedule_paper(g, &lo, &hi);
+            if (st != PSA_OK) return st;
+        }
+        psa_status st = psa::fill_schedule(S, lo, hi, i0.data());
+        if (st != PSA_OK) return st;
+    }
+    std::vector<float> lam(static_cast<size_t>(n)), dlt(static_cast<size_t>(n));
+    std::vector<uint32_t> thr(static_cast<size_t>(n));
+    if (!desc->lambda || !desc->delta || !desc->thr24) {
+        psa_status st = psa::draw_variability(n, desc->seed, desc->sigma_lambda, desc->sigma_delta,
+                                              desc->sigma_nu, desc->p_mean, lam.data(), dlt.data(),
+                                              thr.data());
+        if (st != PSA_OK) return st;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        if (desc->lambda) lam[i] = desc->lambda[i];
+        if (desc->delta) dlt[i] = desc->delta[i];
+        if (desc->thr24) thr[i] = desc->thr24[i];
+        if (!std::isfinite(lam[i]) || !std::isfinite(dlt[i]) || thr[i] > psa::kGateOneHost) {
+            set_error("psa_job_create: lambda/delta must be finite and thr24 <= 2^24");
+            return PSA_EINVAL;
+        }
+    }
+    PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    std::unique_ptr<psa_job, void (*)(psa_job *)> j(new psa_job(), job_free);
+    j->ctx = ctx;
+    j->g = g;
+    j->run.trials = desc->trials;
+    j->run.t4 = (desc->trials + 3) / 4 * 4;
+    j->run.steps = S;
+    {
+        std::string why;
+        if (!psa::plan_anneal(g->dev, j->run, desc->trials_per_group, desc->block, ctx->max_lds,
+                              ctx->num_cu, &j->plan, &why)) {
+            set_error("psa_job_create: " + why);
+            return PSA_EUNSUPPORTED;
+        }
+    }
+    j->run.key0 = static_cast<uint32_t>(desc->seed);
+    j->run.key1 = static_cast<uint32_t>(desc->seed >> 32);
+    psa_status st;
+    if ((st = dev_upload(&j->d_i0, i0.data(), i0.size(), "job upload")) != PSA_OK) return st;
+    if ((st = dev_upload(&j->d_lambda, lam.data(), lam.size(), "job upload")) != PSA_OK) return st;
+    if ((st = dev_upload(&j->d_delta, dlt.data(), dlt.size(), "job upload")) != PSA_OK) return st;
+    if ((st = dev_upload(&j->d_thr24, thr.data(), thr.size(), "job upload")) != PSA_OK) return st;
+    const size_t spin_bytes = static_cast<size_t>(n) * static_cast<size_t>(j->run.t4);
+    if ((st = dev_upload<int8_t>(&j->d_spins, nullptr, spin_bytes, "job spins")) != PSA_OK) return st;
+    j->run.i0 = j->d_i0;
+    j->run.lambda = j->d_lambda;
+    j->run.delta = j->d_delta;
+    j->run.thr24 = j->d_thr24;
+    j->run.spins = j->d_spins;
+    PSA_HIP(psa::launch_init_spins(ctx->stream, n, j->run), "init_spins launch");
+    j->t = 0;
+    *out = j.release();
+    return PSA_OK;
+}
+
+psa_status psa_job_reset(psa_job *job) {
+    if (!job) {
+        set_error("psa_job_reset: job is NULL");
+        return PSA_EINVAL;
+    }
+    PSA_HIP(hipSetDevice(job->ctx->device), "hipSetDevice");
+    PSA_HIP(psa::launch_init_spins(job->ctx->stream, job->g->info.n, job->run), "init_spins launch");
+    job->t = 0;
+    return PSA_OK;
+}
+
+psa_status psa_job_step(psa_job *job, int32_t k) {
+    if (!job || k < 0) {
+        set_error("psa_job_step: invalid arguments");
+        return PSA_EINVAL;
+    }
+    const int32_t t_end = static_cast<int32_t>(std::min<int64_t>(int64_t{job->t} + k, job->run.steps));
+    if (t_end <= job->t) return PSA_OK;
+    PSA_HIP(hipSetDevice(job->ctx->device), "hipSetDevice");
+    PSA_HIP(psa::launch_anneal(job->ctx->stream, job->g->dev, job->run, job->plan, job->t, t_end),
+            "anneal launch");
+    job->t = t_end;
+    return PSA_OK;
+}
+
+psa_status psa_job_position(const psa_job *job, int32_t *t) {
+    if (!job || !t) {
+        set_error("psa_job_position: NULL argument");
+        return PSA_EINVAL;
+    }
+    *t = job->t;
+    return PSA_OK;
+}
+
+psa_status psa_job_read_spins(psa_job *job, int8_t *out, uint32_t flags) {
+    if (!job || !out || (flags & ~PSA_OUT_DEVICE) != 0) {
+        set_error("psa_job_read_spins: invalid arguments");
+        return PSA_EINVAL;
+    }
+    PSA_HIP(hipSetDevice(job->ctx->device), "hipSetDevice");
+    const int32_t n = job->g->info.n;
+    const size_t bytes = static_cast<size_t>(n) * job->run.trials;
+    if (flags & PSA_OUT_DEVICE) {
+        PSA_HIP(psa::launch_spins_to_tn(job->ctx->stream, n, job->run, out), "spins read-out");
+        return PSA_OK;
+    }
+    psa_status st = ensure_scratch(job, bytes);
+    if (st != PSA_OK) return st;
+    int8_t *tmp = static_cast<int8_t *>(job->d_scratch);
+    PSA_HIP(psa::launch_spins_to_tn(job->ctx->stream, n, job->run, tmp), "spins read-out");
+    PSA_HIP(hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, job->ctx->stream), "copy-out");
+    PSA_HIP(hipStreamSynchronize(job->ctx->stream), "hipStreamSynchronize");
+    return PSA_OK;
+}
+
+psa_status psa_job_write_spins(psa_job *job, const int8_t *in, int32_t t, uint32_t flags) {
+    if (!job || !in || (flags & ~PSA_OUT_DEVICE) != 0 || t < 0 || t > job->run.steps) {
+        set_error("psa_job_write_spins: invalid arguments");
+        return PSA_EINVAL;
+    }
+    PSA_HIP(hipSetDevice(job->ctx->device), "hipSetDevice");
+    const int32_t n = job->g->info.n;
+    const size_t bytes = static_cast<size_t>(n) * job->run.trials;
+    std::vector<int8_t> host(bytes);
+    if (flags & PSA_OUT_DEVICE) {
+        PSA_HIP(hipStreamSynchronize(job->ctx->stream), "hipStreamSynchronize");
+        PSA_HIP(hipMemcpy(host.data(), in, bytes, hipMemcpyDeviceToHost), "copy-in");
+    } else {
+        memcpy(host.data(), in, bytes);
+    }
+    for (size_t p = 0; p < bytes; ++p)
+        if (host[p] != 1 && host[p] != -1) {
+            set_error("psa_job_write_spins: spins must be +1 or -1");
+            return PSA_EINVAL;
+        }
+    psa_status st = ensure_scratch(job, bytes);
+    if (st != PSA_OK) return st;
+    int8_t *tmp = static_cast<int8_t *>(job->d_scratch);
+    PSA_HIP(hipMemcpyAsync(tmp, host.data(), bytes, hipMemcpyHostToDevice, job->ctx->stream),
+            "copy-in");
+    PSA_HIP(psa::launch_spins_from_tn(job->ctx->stream, n, job->run, tmp), "spins write");
+    PSA_HIP(hipStreamSynchronize(job->ctx->stream), "hipStreamSynchronize");
+    job->t = t;
+    return PSA_OK;
+}
+
+psa_status psa_job_local_field(psa_job *job, int32_t *out, uint32_t flags) {
+    if (!job || !out || (flags & ~PSA_OUT_DEVICE) != 0) {
+        set_error("psa_job_local_field: invalid arguments");
+        return PSA_EINVAL;
+    }
+    PSA_HIP(hipSetDevice(job->ctx->device), "hipSetDevice");
+    const int32_t n = job->g->info.n;
+    const size_t bytes = static_cast<size_t>(n) * job->run.trials * sizeof(int32_t);
+    if (flags & PSA_OUT_DEVICE) {
+        PSA_HIP(psa::launch_local_field(job->ctx->stream, job->g->dev, job->run, out), "local field");
+        return PSA_OK;
+    }
+    psa_status st = ensure_scratch(job, bytes);
+    if (st != PSA_OK) return st;
+    int32_t *tmp = static_cast<int32_t *>(job->d_scratch);
+    PSA_HIP(psa::launch_local_field(job->ctx->stream, job->g->dev, job->run, tmp), "local field");
+    PSA_HIP(hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, job->ctx->stream), "copy-out");
+    PSA_HIP(hipStreamSynchronize(job->ctx->stream), "hipStreamSynchronize");
+    return PSA_OK;
+}
+
+psa_status psa_job_energy_cut(psa_job *job, int64_t *energy, int64_t *cut, uint32_t flags) {
+    if (!job || !energy || !cut || (flags & ~PSA_OUT_DEVICE) != 0) {
+        set_error("psa_job_energy_cut: invalid arguments");
+        return PSA_EINVAL;
+    }
+    PSA_HIP(hipSetDevice(job->ctx->device), "hipSetDevice");
+    if (flags & PSA_OUT_DEVICE) {
+        PSA_HIP(psa::launch_energy_cut(job->ctx->stream, job->g->dev, job->run, energy, cut),
+                "energy/cut");
+        return PSA_OK;
+    }
+    const size_t bytes = static_cast<size_t>(job->run.trials) * sizeof(int64_t);
+    psa_status st = ensure_scratch(job, 2 * bytes);
+    if (st != PSA_OK) return st;
+    int64_t *tmp = static_cast<int64_t *>(job->d_scratch);
+    PSA_HIP(psa::launch_energy_cut(job->ctx->stream, job->g->dev, job->run, tmp,
+                                   tmp + job->run.trials),
+            "energy/cut");
+    PSA_HIP(hipMemcpyAsync(energy, tmp, bytes, hipMemcpyDeviceToHost, job->ctx->stream), "copy-out");
+    PSA_HIP(hipMemcpyAsync(cut, tmp + job->run.trials, bytes, hipMemcpyDeviceToHost,
+                           job->ctx->stream),
+            "copy-out");
+    PSA_HIP(hipStreamSynchronize(job->ctx->stream), "hipStreamSynchronize");
+    return PSA_OK;
+}
+
+void psa_job_destroy(psa_job *job) { job_free(job); }
+
+psa_status psa_anneal(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *desc,
+                      int8_t *spins_out, int64_t *energy_out, int64_t *cut_out, uint32_t flags) {
+    if (!energy_out || !cut_out || (flags & ~PSA_OUT_DEVICE) != 0) {
+        set_error("psa_anneal: energy_out and cut_out are required");
+        return PSA_EINVAL;
+    }
+    psa_job *job = nullptr;
+    psa_status st = psa_job_create(ctx, g, desc, &job);
+    if (st != PSA_OK) return st;
+    std::unique_ptr<psa_job, void (*)(psa_job *)> guard(job, job_free);
+    if ((st = psa_job_step(job, desc->steps)) != PSA_OK) return st;
+    if ((st = psa_job_energy_cut(job, energy_out, cut_out, flags)) != PSA_OK) return st;
+    if (spins_out && (st = psa_job_read_spins(job, spins_out, flags)) != PSA_OK) return st;
+    PSA_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    return PSA_OK;
+}
+
+}  // extern "C"

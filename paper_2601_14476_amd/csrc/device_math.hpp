@@ -1,0 +1,92 @@
+// device_math.hpp -- per-update arithmetic of the p-bit (gfx950 device code).
+//
+// Counter-based randomness, the uniform r of Eq. 1, the timing gate, and a
+// single-precision tanh with a fixed operation order.  Everything here is
+// evaluated with IEEE single-precision operations that round exactly once
+// (explicit fmaf, correctly rounded division, no contraction), so that the
+// result does not depend on how the compiler schedules it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psa {
+
+// Purposes of the random words; part of the Philox counter.
+enum : uint32_t { kTagInit = 0, kTagR = 1, kTagGate = 2, kTagVar = 3 };
+
+constexpr uint32_t kGateOne = 1u << 24;
+
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies by M0 = 0xD2511F53 and M1 = 0xCD9E8D57, with the key
+// advanced by the Weyl increments W0 = 0x9E3779B9, W1 = 0xBB67AE85 between
+// rounds.  Returns the four output words in (x, y, z, w).
+struct Words4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1,
+                                                uint32_t c2, uint32_t c3,
+                                                uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Words4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ uint32_t word_of(const Words4 &w, int k) {
+    return k == 0 ? w.x : k == 1 ? w.y : k == 2 ? w.z : w.w;
+}
+
+// r in (-1, 1): odd multiple of 2^-24 from the top 25 bits of a word.
+__device__ __forceinline__ float r_of(uint32_t u) {
+    const int32_t j = static_cast<int32_t>((u >> 7) | 1u) - static_cast<int32_t>(kGateOne);
+    return static_cast<float>(j) * 0x1p-24f;
+}
+
+// Timing gate for a p-bit whose update probability is thr24 / 2^24 (< 1).
+__device__ __forceinline__ bool fires(uint32_t u, uint32_t thr24) {
+    return (u >> 8) < thr24;
+}
+
+// tanh(x) = sign(x) (1 - 2 / (e^{2|x|} + 1)); e^{2|x|} = 2^v, v = 2|x| log2 e,
+// split v = n + f (n nearest integer, |f| <= 1/2); 2^f from the degree-7
+// Taylor polynomial of e^{f ln 2} (coefficients (ln 2)^k / k!, rounded to
+// float), Horner with fused multiply-add; |x| >= 9 gives exactly +-1.
+__device__ __forceinline__ float tanh_f32(float x) {
+    const float a = fminf(fabsf(x), 9.0f);
+    const float v = a * 0x1.715476p+1f;
+    const float nf = rintf(v);
+    const float f = v - nf;
+    float p = 0x1.ffcbfcp-17f;
+    p = fmaf(p, f, 0x1.430912p-13f);
+    p = fmaf(p, f, 0x1.5d87fep-10f);
+    p = fmaf(p, f, 0x1.3b2ab6p-7f);
+    p = fmaf(p, f, 0x1.c6b08ep-5f);
+    p = fmaf(p, f, 0x1.ebfbe0p-3f);
+    p = fmaf(p, f, 0x1.62e430p-1f);
+    p = fmaf(p, f, 1.0f);
+    const float e = ldexpf(p, static_cast<int>(nf));
+    float y = 1.0f - 2.0f / (e + 1.0f);
+    y = (a >= 9.0f) ? 1.0f : y;
+    return copysignf(y, x);
+}
+
+// Sign-extend byte k of a packed word of four int8 spins.
+__device__ __forceinline__ int32_t spin_of(uint32_t word, int k) {
+    return static_cast<int32_t>(word << (24 - 8 * k)) >> 24;
+}
+
+}  // namespace psa

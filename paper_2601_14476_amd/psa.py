@@ -1,0 +1,360 @@
+"""ctypes binding of libpsa (include/psa.h).
+
+Argument marshalling only: every computation runs in libpsa's HIP kernels
+(or, for the once-per-run schedule and variability draw, in its native host
+code).  The raw functions keep the C names (psa_ctx_create, ...); the small
+classes below wrap them for numpy / torch callers.  torch is used only for
+device memory and streams: a device output is a cuda tensor whose data_ptr()
+is handed to the library on the context's stream.
+
+If libpsa.so has not been built this module raises at import time; there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpsa.so")
+
+PSA_OK = 0
+PSA_EINVAL = -1
+PSA_ENOMEM = -2
+PSA_EHIP = -3
+PSA_EUNSUPPORTED = -4
+
+PSA_GRAPH_ISING = 0
+PSA_GRAPH_MAXCUT = 1
+PSA_OUT_HOST = 0
+PSA_OUT_DEVICE = 1
+
+_P = ctypes.c_void_p
+_i32, _i64, _u32, _u64, _f64 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                ctypes.c_uint64, ctypes.c_double)
+
+
+class psa_graph_info(ctypes.Structure):
+    _fields_ = [("n", _i32), ("edges", _i64), ("nnz", _i64), ("w_total", _i64),
+                ("max_abs_field", _i32), ("max_degree", _i32),
+                ("unit_weights", _i32), ("mean_s", _f64)]
+
+
+class psa_run_desc(ctypes.Structure):
+    _fields_ = [("steps", _i32), ("trials", _i32), ("seed", _u64),
+                ("i0_min", _f64), ("i0_max", _f64), ("i0", _P),
+                ("sigma_lambda", _f64), ("sigma_delta", _f64),
+                ("sigma_nu", _f64), ("p_mean", _f64), ("lambda_", _P),
+                ("delta", _P), ("thr24", _P), ("block", _i32),
+                ("trials_per_group", _i32), ("flags", _u32)]
+
+
+# (name, restype, argtypes) of every exported entry point in include/psa.h
+_SIGNATURES = [
+    ("psa_version", ctypes.c_char_p, []),
+    ("psa_last_error", ctypes.c_char_p, []),
+    ("psa_ctx_create", _i32, [_i32, _P, ctypes.POINTER(_P)]),
+    ("psa_ctx_synchronize", _i32, [_P]),
+    ("psa_ctx_destroy", None, [_P]),
+    ("psa_graph_from_edges", _i32, [_P, _i32, _i64, _P, _P, _P, _P, _u32,
+                                    ctypes.POINTER(_P)]),
+    ("psa_graph_from_csr", _i32, [_P, _i32, _P, _P, _P, _P, _u32,
+                                  ctypes.POINTER(_P)]),
+    ("psa_graph_info_get", _i32, [_P, ctypes.POINTER(psa_graph_info)]),
+    ("psa_graph_destroy", None, [_P]),
+    ("psa_schedule_paper", _i32, [_P, ctypes.POINTER(_f64), ctypes.POINTER(_f64)]),
+    ("psa_schedule_fill", _i32, [_i32, _f64, _f64, _P]),
+    ("psa_variability_draw", _i32, [_i32, _u64, _f64, _f64, _f64, _f64, _P, _P, _P]),
+    ("psa_run_desc_default", None, [ctypes.POINTER(psa_run_desc)]),
+    ("psa_job_create", _i32, [_P, _P, ctypes.POINTER(psa_run_desc), ctypes.POINTER(_P)]),
+    ("psa_job_reset", _i32, [_P]),
+    ("psa_job_step", _i32, [_P, _i32]),
+    ("psa_job_position", _i32, [_P, ctypes.POINTER(_i32)]),
+    ("psa_job_read_spins", _i32, [_P, _P, _u32]),
+    ("psa_job_write_spins", _i32, [_P, _P, _i32, _u32]),
+    ("psa_job_local_field", _i32, [_P, _P, _u32]),
+    ("psa_job_energy_cut", _i32, [_P, _P, _P, _u32]),
+    ("psa_job_destroy", None, [_P]),
+    ("psa_anneal", _i32, [_P, _P, ctypes.POINTER(psa_run_desc), _P, _P, _P, _u32]),
+]
+
+
+def _load():
+    # torch bundles its own HIP runtime (same SONAME as ROCm's).  Loading it
+    # first makes libpsa bind to that one copy, so device pointers and
+    # streams can be shared with torch; otherwise the process would end up
+    # with two HIP runtimes and torch would not see the GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`"
+            " (the pSA path has no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, res, args in _SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = [s[0] for s in _SIGNATURES]
+
+
+class PsaError(RuntimeError):
+    def __init__(self, status, where, message):
+        super().__init__(f"{where} failed ({status}): {message}")
+        self.status = status
+
+
+def _check(status, where):
+    if status != PSA_OK:
+        raise PsaError(status, where, _lib.psa_last_error().decode(errors="replace"))
+
+
+# ----------------------------------------------------------------------------
+# Raw entry points under their C names (thin pass-through).
+# ----------------------------------------------------------------------------
+def __getattr__(name):
+    if name in EXPORTED:
+        return getattr(_lib, name)
+    raise AttributeError(name)
+
+
+def _ptr(a):
+    """Address of a numpy array, a torch tensor, or None."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return a.ctypes.data_as(_P)
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return _P(a.data_ptr())
+    raise TypeError(f"unsupported buffer type {type(a)!r}")
+
+
+def _is_device(a):
+    return hasattr(a, "is_cuda") and a.is_cuda
+
+
+def _flags_for(*bufs):
+    dev = [_is_device(b) for b in bufs if b is not None]
+    if dev and any(dev) != all(dev):
+        raise ValueError("outputs must all be host or all be device buffers")
+    return PSA_OUT_DEVICE if dev and dev[0] else PSA_OUT_HOST
+
+
+def version():
+    return _lib.psa_version().decode()
+
+
+class Context:
+    """HIP device + stream.  `stream` may be a torch.cuda.Stream, a raw
+    hipStream_t address, or None (the library creates one)."""
+
+    def __init__(self, device=0, stream=None):
+        if stream is not None and hasattr(stream, "cuda_stream"):
+            stream = stream.cuda_stream
+        h = _P()
+        _check(_lib.psa_ctx_create(device, _P(stream) if stream else None,
+                                   ctypes.byref(h)), "psa_ctx_create")
+        self.handle = h
+        self.device = device
+
+    def synchronize(self):
+        _check(_lib.psa_ctx_synchronize(self.handle), "psa_ctx_synchronize")
+
+    def close(self):
+        if self.handle:
+            _lib.psa_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    def __init__(self, ctx, handle):
+        self.ctx = ctx
+        self.handle = handle
+
+    @classmethod
+    def from_edges(cls, ctx, n, u, v, val, h=None, maxcut=True):
+        u = np.ascontiguousarray(u, dtype=np.int32)
+        v = np.ascontiguousarray(v, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.int32)
+        hh = None if h is None else np.ascontiguousarray(h, dtype=np.int32)
+        if not (u.shape == v.shape == val.shape) or (hh is not None and hh.shape != (n,)):
+            raise ValueError("edge arrays must have equal length and h shape (n,)")
+        out = _P()
+        _check(_lib.psa_graph_from_edges(ctx.handle, n, u.size, _ptr(u), _ptr(v),
+                                         _ptr(val), _ptr(hh),
+                                         PSA_GRAPH_MAXCUT if maxcut else PSA_GRAPH_ISING,
+                                         ctypes.byref(out)), "psa_graph_from_edges")
+        return cls(ctx, out)
+
+    @classmethod
+    def from_csr(cls, ctx, n, row_ptr, col, val, h=None, maxcut=False):
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.int32)
+        hh = None if h is None else np.ascontiguousarray(h, dtype=np.int32)
+        out = _P()
+        _check(_lib.psa_graph_from_csr(ctx.handle, n, _ptr(rp), _ptr(col), _ptr(val),
+                                       _ptr(hh),
+                                       PSA_GRAPH_MAXCUT if maxcut else PSA_GRAPH_ISING,
+                                       ctypes.byref(out)), "psa_graph_from_csr")
+        return cls(ctx, out)
+
+    def info(self):
+        i = psa_graph_info()
+        _check(_lib.psa_graph_info_get(self.handle, ctypes.byref(i)), "psa_graph_info_get")
+        return {f: getattr(i, f) for f, _ in psa_graph_info._fields_}
+
+    def schedule_paper(self):
+        lo, hi = _f64(), _f64()
+        _check(_lib.psa_schedule_paper(self.handle, ctypes.byref(lo), ctypes.byref(hi)),
+               "psa_schedule_paper")
+        return lo.value, hi.value
+
+    def close(self):
+        if self.handle:
+            _lib.psa_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def schedule_fill(steps, i0_min, i0_max):
+    out = np.zeros(max(int(steps), 1), np.float32)
+    _check(_lib.psa_schedule_fill(int(steps), float(i0_min), float(i0_max), _ptr(out)),
+           "psa_schedule_fill")
+    return out[:steps]
+
+
+def variability_draw(n, seed, sigma_lambda=0.0, sigma_delta=0.0, sigma_nu=0.0, p_mean=1.0):
+    lam = np.zeros(n, np.float32)
+    dlt = np.zeros(n, np.float32)
+    thr = np.zeros(n, np.uint32)
+    _check(_lib.psa_variability_draw(n, seed, sigma_lambda, sigma_delta, sigma_nu, p_mean,
+                                     _ptr(lam), _ptr(dlt), _ptr(thr)), "psa_variability_draw")
+    return lam, dlt, thr
+
+
+def make_desc(steps, trials, seed=0, i0=None, i0_min=None, i0_max=None,
+              sigma_lambda=0.0, sigma_delta=0.0, sigma_nu=0.0, p_mean=1.0,
+              lam=None, delta=None, thr24=None, block=0, trials_per_group=0):
+    """Build a psa_run_desc; returns (desc, keepalive arrays)."""
+    d = psa_run_desc()
+    _lib.psa_run_desc_default(ctypes.byref(d))
+    d.steps, d.trials, d.seed = int(steps), int(trials), int(seed)
+    keep = []
+    if i0 is not None:
+        a = np.ascontiguousarray(i0, dtype=np.float32)
+        keep.append(a)
+        d.i0 = _ptr(a)
+    if i0_min is not None:
+        d.i0_min, d.i0_max = float(i0_min), float(i0_max)
+    d.sigma_lambda, d.sigma_delta, d.sigma_nu = float(sigma_lambda), float(sigma_delta), float(sigma_nu)
+    d.p_mean = float(p_mean)
+    for field, arr, dt in (("lambda_", lam, np.float32), ("delta", delta, np.float32),
+                           ("thr24", thr24, np.uint32)):
+        if arr is not None:
+            a = np.ascontiguousarray(arr, dtype=dt)
+            keep.append(a)
+            setattr(d, field, _ptr(a))
+    d.block = int(block)
+    d.trials_per_group = int(trials_per_group)
+    return d, keep
+
+
+class Job:
+    def __init__(self, ctx, graph, steps, trials, seed=0, **kw):
+        self.ctx, self.graph = ctx, graph
+        self.n = graph.info()["n"]
+        self.trials, self.steps = int(trials), int(steps)
+        desc, keep = make_desc(steps, trials, seed, **kw)
+        out = _P()
+        _check(_lib.psa_job_create(ctx.handle, graph.handle, ctypes.byref(desc),
+                                   ctypes.byref(out)), "psa_job_create")
+        del keep
+        self.handle = out
+
+    def reset(self):
+        _check(_lib.psa_job_reset(self.handle), "psa_job_reset")
+
+    def step(self, k):
+        _check(_lib.psa_job_step(self.handle, int(k)), "psa_job_step")
+
+    @property
+    def position(self):
+        t = _i32()
+        _check(_lib.psa_job_position(self.handle, ctypes.byref(t)), "psa_job_position")
+        return t.value
+
+    def read_spins(self, out=None):
+        if out is None:
+            out = np.zeros((self.trials, self.n), np.int8)
+        _check(_lib.psa_job_read_spins(self.handle, _ptr(out), _flags_for(out)),
+               "psa_job_read_spins")
+        return out
+
+    def write_spins(self, spins, t):
+        if not _is_device(spins):
+            spins = np.ascontiguousarray(spins, dtype=np.int8)
+        _check(_lib.psa_job_write_spins(self.handle, _ptr(spins), int(t), _flags_for(spins)),
+               "psa_job_write_spins")
+
+    def local_field(self, out=None):
+        if out is None:
+            out = np.zeros((self.trials, self.n), np.int32)
+        _check(_lib.psa_job_local_field(self.handle, _ptr(out), _flags_for(out)),
+               "psa_job_local_field")
+        return out
+
+    def energy_cut(self, energy=None, cut=None):
+        if energy is None:
+            energy = np.zeros(self.trials, np.int64)
+            cut = np.zeros(self.trials, np.int64)
+        _check(_lib.psa_job_energy_cut(self.handle, _ptr(energy), _ptr(cut),
+                                       _flags_for(energy, cut)), "psa_job_energy_cut")
+        return energy, cut
+
+    def close(self):
+        if self.handle:
+            _lib.psa_job_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def anneal(ctx, graph, steps, trials, seed=0, spins=True, **kw):
+    """Whole anneal; returns (spins [trials][n] or None, energy, cut) on the host."""
+    n = graph.info()["n"]
+    desc, keep = make_desc(steps, trials, seed, **kw)
+    E = np.zeros(trials, np.int64)
+    C = np.zeros(trials, np.int64)
+    S = np.zeros((trials, n), np.int8) if spins else None
+    _check(_lib.psa_anneal(ctx.handle, graph.handle, ctypes.byref(desc), _ptr(S), _ptr(E),
+                           _ptr(C), PSA_OUT_HOST), "psa_anneal")
+    del keep
+    return S, E, C

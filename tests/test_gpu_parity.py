@@ -1,0 +1,307 @@
+"""GPU parity: every result of the HIP path, through the C ABI, equals the
+oracle's bit for bit (spins, local fields, energies, cuts).
+
+Small cases are compared element by element over whole trajectories; the
+full-size workloads (G1-shaped ER n=800; n=2,000 sparse with variability;
+the G81-shaped 100x200 torus with 1,024 trials and 5,000 steps) run in the
+launch configuration the benchmark times and are compared on sampled
+trials, which the oracle recomputes independently (trials never interact).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_14476_amd import inputs
+
+pytestmark = pytest.mark.gpu
+ONE24 = 1 << 24
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def psa():
+    from paper_2601_14476_amd import psa as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(psa):
+    c = psa.Context(0)
+    yield c
+    c.close()
+
+
+def _graph(psa, ctx, n, u, v, w, h=None):
+    return psa.Graph.from_edges(ctx, n, u, v, w, h=h, maxcut=True)
+
+
+def _oracle_params(n, u, v, w, steps, seed, sl, sd, sn, pm):
+    i0, lo, hi = oracle.schedule_paper(n, u, v, -w, steps)
+    lam, dlt, thr = oracle.variability(n, seed, sl, sd, sn, pm)
+    return i0, lam, dlt, thr
+
+
+def _job(psa, ctx, g, spec, trials=None, steps=None, block=0, tpw=0):
+    return psa.Job(ctx, g, steps or spec["steps"], trials or spec["trials"], spec["seed"],
+                   sigma_lambda=spec["sigma_lambda"], sigma_delta=spec["sigma_delta"],
+                   sigma_nu=spec["sigma_nu"], p_mean=spec["p_mean"], block=block,
+                   trials_per_group=tpw)
+
+
+# ----------------------------------------------------------------------------
+# graph ingestion and schedule endpoints
+# ----------------------------------------------------------------------------
+def test_graph_info_and_paper_schedule(psa, ctx):
+    for name in ("c1", "c2", "c3"):
+        spec = inputs.workload(name)
+        n, u, v, w = spec["n"], spec["u"], spec["v"], spec["w"]
+        g = _graph(psa, ctx, n, u, v, w)
+        info = g.info()
+        assert info["n"] == n and info["edges"] == u.size and info["nnz"] == 2 * u.size
+        assert info["w_total"] == int(w.sum())
+        assert info["mean_s"] == oracle.mean_s(n, u, v, -w)
+        lo, hi = g.schedule_paper()
+        _, olo, ohi = oracle.schedule_paper(n, u, v, -w, 10)
+        assert (lo, hi) == (olo, ohi)
+        g.close()
+
+
+def test_invalid_graphs_rejected(psa, ctx):
+    z = np.array([0], np.int32)
+    o = np.array([1], np.int32)
+    with pytest.raises(psa.PsaError) as e:
+        psa.Graph.from_edges(ctx, 2, z, z, o)               # self loop
+    assert e.value.status == psa.PSA_EINVAL
+    with pytest.raises(psa.PsaError):
+        psa.Graph.from_edges(ctx, 2, np.array([0, 1], np.int32), np.array([1, 0], np.int32),
+                             np.array([1, 1], np.int32))    # repeated pair
+    with pytest.raises(psa.PsaError):
+        psa.Graph.from_edges(ctx, 2, z, np.array([5], np.int32), o)   # out of range
+    with pytest.raises(psa.PsaError):
+        psa.Graph.from_edges(ctx, 2, z, o, np.array([1 << 24], np.int32))
+    with pytest.raises(psa.PsaError):                         # asymmetric CSR
+        psa.Graph.from_csr(ctx, 2, [0, 1, 1], [1], [1])
+
+
+# ----------------------------------------------------------------------------
+# initial spins, local field, energy / cut
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("trials", [1, 3, 4, 10, 101, 1023])
+def test_initial_spins(psa, ctx, trials):
+    n, u, v, w = inputs.gnm(257, 700, 1)
+    g = _graph(psa, ctx, n, u, v, w)
+    job = psa.Job(ctx, g, steps=5, trials=trials, seed=12345)
+    np.testing.assert_array_equal(job.read_spins(), oracle.init_spins(n, 12345, 0, trials))
+
+
+def _random_ising(n, m, seed, jmax=5):
+    rng = np.random.default_rng(seed)
+    _, u, v, _ = inputs.gnm(n, m, seed)
+    j = rng.integers(1, jmax + 1, size=u.size) * rng.choice([-1, 1], size=u.size)
+    h = rng.integers(-7, 8, size=n)
+    return n, u, v, j.astype(np.int32), h.astype(np.int32)
+
+
+@pytest.mark.parametrize("n,m,trials", [(1, 0, 5), (50, 0, 4), (300, 1500, 9), (2048, 9000, 64)])
+def test_local_field_and_energy(psa, ctx, n, m, trials):
+    n, u, v, j, h = _random_ising(n, m, 3)
+    g = psa.Graph.from_edges(ctx, n, u, v, j, h=h, maxcut=False)
+    job = psa.Job(ctx, g, steps=3, trials=trials, seed=1, i0_min=0.1, i0_max=1.0)
+    rng = np.random.default_rng(5)
+    s = rng.choice([-1, 1], size=(trials, n)).astype(np.int8)
+    job.write_spins(s, 0)
+    np.testing.assert_array_equal(job.read_spins(), s)
+    np.testing.assert_array_equal(job.local_field(), oracle.local_field(n, u, v, j, h, s))
+    E, C = job.energy_cut()
+    oE, oC = oracle.energy_cut(n, u, v, j, h, s)
+    np.testing.assert_array_equal(E, oE)
+    np.testing.assert_array_equal(C, oC)
+
+
+# ----------------------------------------------------------------------------
+# trajectories, step by step
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("name,trials,steps,tpw", [("c1", 10, 25, 1), ("c1", 10, 25, 4),
+                                                   ("c2", 100, 12, 1), ("c2", 100, 12, 4)])
+def test_trajectory_every_step(psa, ctx, name, trials, steps, tpw):
+    spec = inputs.workload(name)
+    n, u, v, w = spec["n"], spec["u"], spec["v"], spec["w"]
+    g = _graph(psa, ctx, n, u, v, w)
+    S = spec["steps"]
+    job = _job(psa, ctx, g, spec, trials=trials, tpw=tpw)
+    i0, lam, dlt, thr = _oracle_params(n, u, v, w, S, spec["seed"], spec["sigma_lambda"],
+                                       spec["sigma_delta"], spec["sigma_nu"], spec["p_mean"])
+    ref = oracle.init_spins(n, spec["seed"], 0, trials)
+    np.testing.assert_array_equal(job.read_spins(), ref)
+    for t in range(steps):
+        job.step(1)
+        ref = oracle.run(n, u, v, -w, None, i0, lam, dlt, thr, spec["seed"], 0, trials, t,
+                         t + 1, ref)
+        got = job.read_spins()
+        if not np.array_equal(got, ref):
+            bad = np.argwhere(got != ref)
+            pytest.fail(f"{name} step {t}: {len(bad)} spins differ, first {bad[:5].tolist()}")
+    np.testing.assert_array_equal(job.local_field(), oracle.local_field(n, u, v, -w, None, ref))
+
+
+def _compare_full(psa, ctx, name, sample, block=0, **over):
+    spec = inputs.workload(name, **over)
+    n, u, v, w = spec["n"], spec["u"], spec["v"], spec["w"]
+    T, S = spec["trials"], spec["steps"]
+    _say(f"[parity] {name}: n={n} trials={T} steps={S} block={block} sample={sample}")
+    g = _graph(psa, ctx, n, u, v, w)
+    job = _job(psa, ctx, g, spec, block=block)
+    job.step(S)
+    E, C = job.energy_cut()
+    spins = job.read_spins()
+    i0, lam, dlt, thr = _oracle_params(n, u, v, w, S, spec["seed"], spec["sigma_lambda"],
+                                       spec["sigma_delta"], spec["sigma_nu"], spec["p_mean"])
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(min(len(sample), 16)) as ex:
+        res = list(ex.map(lambda k: oracle.anneal(n, u, v, -w, None, i0, lam, dlt, thr,
+                                                  spec["seed"], k, k + 1), sample))
+    for k, (os_, oE, oC) in zip(sample, res):
+        np.testing.assert_array_equal(spins[k], os_[0], err_msg=f"{name} trial {k} spins")
+        assert E[k] == oE[0] and C[k] == oC[0], (name, k, E[k], oE[0], C[k], oC[0])
+    # energy / cut of every trial against the oracle's evaluation of GPU spins
+    oE_all, oC_all = oracle.energy_cut(n, u, v, -w, None, spins)
+    np.testing.assert_array_equal(E, oE_all)
+    np.testing.assert_array_equal(C, oC_all)
+    return spins, E, C
+
+
+def test_full_c1_all_trials(psa, ctx):
+    _compare_full(psa, ctx, "c1", list(range(10)))
+
+
+def test_full_c2_sampled_trials(psa, ctx):
+    _compare_full(psa, ctx, "c2", [0, 1, 2, 3, 4, 37, 50, 96, 98, 99])
+
+
+def test_full_c3_sampled_trials(psa, ctx):
+    """G81-shaped torus, 1,024 trials, 5,000 steps: trials in the first,
+    a middle and the last workgroup."""
+    _compare_full(psa, ctx, "c3", [0, 513, 1023])
+
+
+# ----------------------------------------------------------------------------
+# edge cases and invariances
+# ----------------------------------------------------------------------------
+def test_launch_geometry_does_not_change_results(psa, ctx):
+    spec = inputs.workload("c2", steps=60, trials=13)
+    n, u, v, w = spec["n"], spec["u"], spec["v"], spec["w"]
+    g = _graph(psa, ctx, n, u, v, w)
+    outs = []
+    for block, tpw in ((256, 1), (512, 4), (1024, 1), (1024, 4), (0, 0)):
+        job = psa.Job(ctx, g, spec["steps"], spec["trials"], spec["seed"],
+                      sigma_lambda=spec["sigma_lambda"], sigma_delta=spec["sigma_delta"],
+                      sigma_nu=spec["sigma_nu"], p_mean=spec["p_mean"], block=block,
+                      trials_per_group=tpw)
+        job.step(spec["steps"])
+        outs.append(job.read_spins())
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+
+
+def test_stepping_composes_and_resumes(psa, ctx):
+    spec = inputs.workload("c2", steps=40, trials=8)
+    n, u, v, w = spec["n"], spec["u"], spec["v"], spec["w"]
+    g = _graph(psa, ctx, n, u, v, w)
+    a = _job(psa, ctx, g, spec)
+    a.step(40)
+    b = _job(psa, ctx, g, spec)
+    for k in (1, 2, 7, 30):
+        b.step(k)
+    assert b.position == 40
+    np.testing.assert_array_equal(a.read_spins(), b.read_spins())
+    # checkpoint at step 17, resume in a fresh job
+    c = _job(psa, ctx, g, spec)
+    c.step(17)
+    ck = c.read_spins()
+    d = _job(psa, ctx, g, spec)
+    d.write_spins(ck, 17)
+    d.step(100)
+    assert d.position == 40
+    np.testing.assert_array_equal(d.read_spins(), a.read_spins())
+    # reset returns to the initial state
+    a.reset()
+    np.testing.assert_array_equal(a.read_spins(), oracle.init_spins(n, spec["seed"], 0, 8))
+
+
+def test_degenerate_cases(psa, ctx):
+    # single p-bit, no couplings, bias and offset
+    e = np.zeros(0, np.int32)
+    g = psa.Graph.from_edges(ctx, 1, e, e, e, h=np.array([2], np.int32), maxcut=False)
+    i0 = oracle.schedule(7, 0.1, 2.0)
+    lam = np.array([1.3], np.float32)
+    dl = np.array([-0.4], np.float32)
+    thr = np.array([ONE24 // 3], np.uint32)
+    job = psa.Job(ctx, g, 7, 6, seed=9, i0=i0, lam=lam, delta=dl, thr24=thr)
+    job.step(7)
+    ref = oracle.anneal(1, e, e, e, np.array([2], np.int32), i0, lam, dl, thr, 9, 0, 6)
+    np.testing.assert_array_equal(job.read_spins(), ref[0])
+    # zero update probability: spins frozen
+    n, u, v, w = inputs.gnm(40, 90, 2)
+    g2 = _graph(psa, ctx, n, u, v, w)
+    job2 = psa.Job(ctx, g2, 20, 5, seed=4, p_mean=0.0)
+    s0 = job2.read_spins()
+    job2.step(20)
+    np.testing.assert_array_equal(job2.read_spins(), s0)
+    # one step, explicit schedule, integer weights > 1 and biases
+    n, u, v, j, h = _random_ising(70, 200, 8)
+    g3 = psa.Graph.from_edges(ctx, n, u, v, j, h=h, maxcut=False)
+    i0 = np.array([0.37], np.float32)
+    lam, dl, thr = oracle.variability(n, 3, 0.2, 0.3, 0.2, 0.7)
+    job3 = psa.Job(ctx, g3, 1, 7, seed=3, i0=i0, sigma_lambda=0.2, sigma_delta=0.3,
+                   sigma_nu=0.2, p_mean=0.7)
+    job3.step(1)
+    ref3 = oracle.anneal(n, u, v, j, h, i0, lam, dl, thr, 3, 0, 7)
+    np.testing.assert_array_equal(job3.read_spins(), ref3[0])
+    E, C = job3.energy_cut()
+    np.testing.assert_array_equal(E, ref3[1])
+    np.testing.assert_array_equal(C, ref3[2])
+
+
+def test_anneal_one_call_matches_job(psa, ctx):
+    spec = inputs.workload("c1", steps=50, trials=6)
+    n, u, v, w = spec["n"], spec["u"], spec["v"], spec["w"]
+    g = _graph(psa, ctx, n, u, v, w)
+    S, E, C = psa.anneal(ctx, g, 50, 6, 0)
+    job = _job(psa, ctx, g, spec)
+    job.step(50)
+    np.testing.assert_array_equal(S, job.read_spins())
+    E2, C2 = job.energy_cut()
+    np.testing.assert_array_equal(E, E2)
+    np.testing.assert_array_equal(C, C2)
+
+
+def test_device_outputs(psa, ctx):
+    import torch
+    spec = inputs.workload("c1", steps=30, trials=10)
+    n, u, v, w = spec["n"], spec["u"], spec["v"], spec["w"]
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    dctx = psa.Context(0, stream)
+    g = _graph(psa, dctx, n, u, v, w)
+    job = _job(psa, dctx, g, spec)
+    job.step(30)
+    s = torch.empty((10, n), dtype=torch.int8, device="cuda")
+    E = torch.empty(10, dtype=torch.int64, device="cuda")
+    C = torch.empty(10, dtype=torch.int64, device="cuda")
+    job.read_spins(s)
+    job.energy_cut(E, C)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(s.cpu().numpy(), job.read_spins())
+    hE, hC = job.energy_cut()
+    np.testing.assert_array_equal(E.cpu().numpy(), hE)
+    np.testing.assert_array_equal(C.cpu().numpy(), hC)
+    job.close()
+    g.close()
+    dctx.close()
+    torch.cuda.set_stream(torch.cuda.default_stream())
