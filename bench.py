@@ -34,10 +34,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic 32-bit lane-operations per p-bit update (see DESIGN.md):
-# one Philox4x32-10 block = 10 rounds x (2 mul_lo + 2 mul_hi + 4 xor) = 80,
-# shared by the 4 trials of a quad; the timing gate needs a second block.
-PHILOX_BLOCK_OPS = 80
+# Algorithmic 32-bit lane-operations per p-bit update:
+# one Philox4x32-10 block = 10 rounds x (2 32x32->64 multiplies + 4 xor) = 60,
+# shared by the 4 p-bits of a task; the timing gate needs a second block.
+PHILOX_BLOCK_OPS = 60
 OPS_R_MAP = 4          # shift-or, subtract, convert, scale
 OPS_GATE_MAP = 2       # shift, compare
 OPS_PREACT = 3.25      # int->float, + delta, * a  (a = I0*lambda once per quad)
@@ -98,7 +98,11 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--tpw", type=int, default=0, help="trials per workgroup (0 = auto)")
+    ap.add_argument("--lpt", type=int, default=0, help="lanes per 4-p-bit task (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes (3 times); "
+                         "used to scale the HBM traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -107,6 +111,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy, "copies": 3}), flush=True)
+        return
     from paper_2601_14476_amd import inputs, psa
 
     spec = inputs.workload(args.workload)
@@ -122,7 +134,8 @@ def main():
     info = g.info()
     job = psa.Job(ctx, g, S, T, spec["seed"], sigma_lambda=spec["sigma_lambda"],
                   sigma_delta=spec["sigma_delta"], sigma_nu=spec["sigma_nu"],
-                  p_mean=spec["p_mean"], block=args.block, trials_per_group=args.tpw)
+                  p_mean=spec["p_mean"], block=args.block, trials_per_group=args.tpw,
+                  lanes_per_task=args.lpt)
     E = torch.empty(T, dtype=torch.int64, device="cuda")
     C = torch.empty(T, dtype=torch.int64, device="cuda")
 

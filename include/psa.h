@@ -160,8 +160,10 @@ psa_status psa_variability_draw(int32_t n, uint64_t seed, double sigma_lambda,
  *                             and, if i0_min <= 0, the paper's endpoints
  *   lambda/delta/thr24[n]  -- variability; else psa_variability_draw(...)
  * trials >= 1, steps >= 1.  Launch shape (results never depend on it):
- * `block` = threads per workgroup (0 = auto, else 256, 512 or 1024) and
- * `trials_per_group` = trials one workgroup advances (0 = auto, 1 or 4). */
+ * `block` = threads per workgroup (0 = auto, else 256, 512 or 1024),
+ * `trials_per_group` = trials one workgroup advances (0 = auto, 1 or 4) and
+ * `lanes_per_task` = lanes sharing one group of four p-bits when a
+ * workgroup advances one trial (0 = auto, 1, 2 or 4). */
 typedef struct psa_run_desc {
     int32_t steps;
     int32_t trials;
@@ -178,6 +180,7 @@ typedef struct psa_run_desc {
     const uint32_t *thr24;
     int32_t block;
     int32_t trials_per_group;
+    int32_t lanes_per_task;
     uint32_t flags; /* reserved, 0 */
 } psa_run_desc;
 

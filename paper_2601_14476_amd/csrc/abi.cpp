@@ -443,6 +443,11 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
         set_error("psa_job_create: trials_per_group must be 0, 1 or 4");
         return PSA_EINVAL;
     }
+    if (desc->lanes_per_task != 0 && desc->lanes_per_task != 1 && desc->lanes_per_task != 2 &&
+        desc->lanes_per_task != 4) {
+        set_error("psa_job_create: lanes_per_task must be 0, 1, 2 or 4");
+        return PSA_EINVAL;
+    }
     const int32_t S = desc->steps;
     std::vector<float> i0(static_cast<size_t>(S));
     if (desc->i0) {
@@ -488,8 +493,8 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
     j->run.steps = S;
     {
         std::string why;
-        if (!psa::plan_anneal(g->dev, j->run, desc->trials_per_group, desc->block, ctx->max_lds,
-                              ctx->num_cu, &j->plan, &why)) {
+        if (!psa::plan_anneal(g->dev, j->run, desc->trials_per_group, desc->lanes_per_task,
+                              desc->block, ctx->max_lds, ctx->num_cu, &j->plan, &why)) {
             set_error("psa_job_create: " + why);
             return PSA_EUNSUPPORTED;
         }

@@ -30,24 +30,29 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1,
                                                 uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        // one 32x32->64 multiply-add instruction per product on gfx950
+        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+        c1 = static_cast<uint32_t>(p1);
+        c3 = static_cast<uint32_t>(p0);
         c0 = n0;
-        c1 = lo1;
         c2 = n2;
-        c3 = lo0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
     return Words4{c0, c1, c2, c3};
 }
 
-__device__ __forceinline__ uint32_t word_of(const Words4 &w, int k) {
+__device__ __forceinline__ uint32_t word_of(const Words4 &w, uint32_t k) {
     return k == 0 ? w.x : k == 1 ? w.y : k == 2 ? w.z : w.w;
+}
+
+// Exchange a value with the neighbouring lane of the pair (lane ^ 1):
+// DPP quad permutation [1, 0, 3, 2].  Both lanes of a pair must be active.
+__device__ __forceinline__ uint32_t swap_pair(uint32_t v) {
+    return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(v), 0xB1, 0xF, 0xF, false));
 }
 
 // r in (-1, 1): odd multiple of 2^-24 from the top 25 bits of a word.

@@ -57,6 +57,7 @@ struct DevRun {
 enum CsrKind : int32_t { kCsrPair = 0, kCsrPack32 = 1, kCsrPack16 = 2 };
 struct AnnealPlan {
     int32_t tpw = 1;          // trials per workgroup: 1 or 4
+    int32_t lpt = 1;          // lanes per 4-p-bit task (tpw == 1): 1, 2 or 4
     int32_t csr = kCsrPair;   // edge encoding read by the kernel
     int32_t csr_lds = 0;      // 1: CSR, biases and per-p-bit factors staged in LDS
     int32_t block = 256;      // threads per workgroup
@@ -64,10 +65,11 @@ struct AnnealPlan {
     size_t lds_bytes = 0;     // dynamic LDS per workgroup
 };
 
-// Choose tpw / CSR placement / block for a run (tpw_req, block_req: 0 =
-// automatic).  Returns false with a reason if n does not fit in LDS.
-bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t block_req,
-                 size_t max_lds, int32_t num_cu, AnnealPlan *plan, std::string *why);
+// Choose tpw / lanes per task / CSR placement / block for a run
+// (tpw_req, lpt_req, block_req: 0 = automatic).  Returns false with a reason if n does not fit in LDS.
+bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t lpt_req,
+                 int32_t block_req, size_t max_lds, int32_t num_cu, AnnealPlan *plan,
+                 std::string *why);
 
 // Kernel launchers (kernels.hip).  All are asynchronous on `stream`.
 hipError_t launch_init_spins(hipStream_t stream, int32_t n, const DevRun &run);

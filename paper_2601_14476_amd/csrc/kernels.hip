@@ -156,44 +156,83 @@ __device__ __forceinline__ void field4(const Views<CSR> &v, int32_t i, const uin
     }
 }
 
-// Task m for one trial k (TPW = 1): p-bits 4m..4m+3 packed in one word.
-template <int CSR>
-__device__ __forceinline__ uint32_t task1(const Views<CSR> &v, int32_t n, int32_t m, uint32_t k,
-                                          uint32_t t, float i0t, const int8_t *cur,
-                                          uint32_t k0, uint32_t k1) {
-    const uint32_t old = reinterpret_cast<const uint32_t *>(cur)[m];
-    uint32_t th[4];
+// Task m for one trial k (TPW = 1), spread over LPT consecutive lanes
+// (1, 2 or 4): lane `sub` owns the P = 4 / LPT p-bits 4m + sub*P + j and
+// returns their new bytes in the low 8P bits.  With the timing gate on and
+// LPT >= 2, even lanes draw the r block and odd lanes the gate block of the
+// task, and the pair swaps the words the other needs (DPP), so the two
+// Philox blocks run side by side instead of one after the other.
+template <int CSR, int LPT>
+__device__ __forceinline__ uint32_t task1(const Views<CSR> &v, int32_t n, int32_t m,
+                                          uint32_t sub, uint32_t k, uint32_t t, float i0t,
+                                          const int8_t *cur, uint32_t k0, uint32_t k1) {
+    constexpr int P = 4 / LPT;
     bool need_gate = false;
-    uint32_t valid = 0u;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const int32_t i = 4 * m + p;
-        const bool ok = i < n;
-        th[p] = ok ? v.thr[i] : 0u;
-        valid |= ok ? (1u << p) : 0u;
-        need_gate |= ok && th[p] < kGateOne;
+        need_gate |= (i < n) && v.thr[i] < kGateOne;
     }
-    uint32_t fire = valid;
-    if (need_gate) {
-        const Words4 g = block_of(t, static_cast<uint32_t>(m), k, kTagGate, k0, k1);
-        const uint32_t gw[4] = {g.x, g.y, g.z, g.w};
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-            if (th[p] < kGateOne && !fires(gw[p], th[p])) fire &= ~(1u << p);
-    }
-    if (fire == 0u) return old;
-    const Words4 r = block_of(t, static_cast<uint32_t>(m), k, kTagR, k0, k1);
-    const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
-    uint32_t out = old;
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        if ((fire >> p) & 1u) {
-            const int32_t i = 4 * m + p;
-            const int32_t L = field1<CSR>(v, i, cur);
-            const float a = i0t * v.lam[i];
-            const uint32_t byte = decide(a, v.dlt[i], L, rw[p]);
-            out = (out & ~(0xFFu << (8 * p))) | (byte << (8 * p));
+    const int32_t base = 4 * m + static_cast<int32_t>(sub) * P;
+    uint32_t rw[P], gw[P];
+    if constexpr (LPT == 1) {
+        const Words4 r = block_of(t, static_cast<uint32_t>(m), k, kTagR, k0, k1);
+        rw[0] = r.x;
+        rw[1] = r.y;
+        rw[2] = r.z;
+        rw[3] = r.w;
+        if (need_gate) {
+            const Words4 g = block_of(t, static_cast<uint32_t>(m), k, kTagGate, k0, k1);
+            gw[0] = g.x;
+            gw[1] = g.y;
+            gw[2] = g.z;
+            gw[3] = g.w;
+        } else {
+            gw[0] = gw[1] = gw[2] = gw[3] = 0u;
         }
+    } else {
+        const uint32_t tag = (need_gate && (sub & 1u)) ? kTagGate : kTagR;
+        const Words4 b = block_of(t, static_cast<uint32_t>(m), k, tag, k0, k1);
+        if constexpr (LPT == 2) {
+            if (need_gate) {  // lane 0 holds r words, lane 1 gate words
+                const uint32_t x0 = swap_pair(sub ? b.x : b.z);
+                const uint32_t x1 = swap_pair(sub ? b.y : b.w);
+                rw[0] = sub ? x0 : b.x;
+                rw[1] = sub ? x1 : b.y;
+                gw[0] = sub ? b.z : x0;
+                gw[1] = sub ? b.w : x1;
+            } else {
+                rw[0] = sub ? b.z : b.x;
+                rw[1] = sub ? b.w : b.y;
+                gw[0] = gw[1] = 0u;
+            }
+        } else {  // LPT == 4: even lanes r block, odd lanes gate block
+            const uint32_t own = word_of(b, sub);
+            if (need_gate) {
+                const uint32_t x = swap_pair(word_of(b, sub ^ 1u));
+                const bool even = (sub & 1u) == 0u;
+                rw[0] = even ? own : x;
+                gw[0] = even ? x : own;
+            } else {
+                rw[0] = own;
+                gw[0] = 0u;
+            }
+        }
+    }
+    uint32_t out = 0u;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const int32_t i = base + j;
+        uint32_t byte = 0x01u;
+        if (i < n) {
+            byte = static_cast<uint8_t>(cur[i]);
+            const uint32_t th = v.thr[i];
+            if (th >= kGateOne || fires(gw[j], th)) {
+                const int32_t L = field1<CSR>(v, i, cur);
+                byte = decide(i0t * v.lam[i], v.dlt[i], L, rw[j]);
+            }
+        }
+        out |= byte << (8 * j);
     }
     return out;
 }
@@ -239,7 +278,6 @@ __device__ __forceinline__ void task4(const Views<CSR> &v, int32_t n, int32_t m,
             for (int p = 0; p < 4; ++p)
                 if (th[p] < kGateOne && !fires(gw[p], th[p])) fire &= ~(1u << p);
         }
-        if (fire == 0u) continue;
         const Words4 r = block_of(t, static_cast<uint32_t>(m), k, kTagR, k0, k1);
         const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
@@ -270,7 +308,7 @@ __host__ __device__ constexpr size_t csr_entry_bytes(int32_t csr) {
     return csr == kCsrPack16 ? 2 : (csr == kCsrPack32 ? 4 : 8);
 }
 
-template <int TPW, int CSR, bool CSR_LDS, int BLOCK>
+template <int TPW, int LPT, int CSR, bool CSR_LDS, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void anneal_kernel(AnnealArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int32_t n = a.n, n4 = a.n4, tasks = n4 / 4;
@@ -344,16 +382,27 @@ __global__ __launch_bounds__(BLOCK) void anneal_kernel(AnnealArgs a) {
     unsigned char *nxt = buf1;
     for (int32_t t = a.t_begin; t < a.t_end; ++t) {
         const float i0t = a.i0[t];
-        for (int32_t m = threadIdx.x; m < tasks; m += BLOCK) {
-            if constexpr (TPW == 1) {
-                reinterpret_cast<uint32_t *>(nxt)[m] =
-                    task1<CSR>(v, n, m, static_cast<uint32_t>(q), static_cast<uint32_t>(t), i0t,
-                               reinterpret_cast<const int8_t *>(cur), a.k0, a.k1);
-            } else {
+        if constexpr (TPW == 1) {
+            // all LPT lanes of a task share m, so they enter and leave together
+            const uint32_t sub = threadIdx.x % LPT;
+            for (int32_t m = threadIdx.x / LPT; m < tasks; m += BLOCK / LPT) {
+                const uint32_t b = task1<CSR, LPT>(v, n, m, sub, static_cast<uint32_t>(q),
+                                                   static_cast<uint32_t>(t), i0t,
+                                                   reinterpret_cast<const int8_t *>(cur), a.k0,
+                                                   a.k1);
+                if constexpr (LPT == 1) {
+                    reinterpret_cast<uint32_t *>(nxt)[m] = b;
+                } else if constexpr (LPT == 2) {
+                    reinterpret_cast<uint16_t *>(nxt)[2 * m + sub] = static_cast<uint16_t>(b);
+                } else {
+                    nxt[4 * m + sub] = static_cast<unsigned char>(b);
+                }
+            }
+        } else {
+            for (int32_t m = threadIdx.x; m < tasks; m += BLOCK)
                 task4<CSR>(v, n, m, q, static_cast<uint32_t>(t), i0t,
                            reinterpret_cast<const uint32_t *>(cur),
                            reinterpret_cast<uint32_t *>(nxt), a.k0, a.k1);
-            }
         }
         __syncthreads();
         unsigned char *tmp = cur;
@@ -486,9 +535,9 @@ inline unsigned grid_for(int64_t items, int block) {
     return static_cast<unsigned>((items + block - 1) / block);
 }
 
-template <int TPW, int CSR, bool LDS, int BLOCK>
+template <int TPW, int LPT, int CSR, bool LDS, int BLOCK>
 hipError_t launch_variant(hipStream_t stream, const AnnealArgs &args, const AnnealPlan &plan) {
-    auto kern = anneal_kernel<TPW, CSR, LDS, BLOCK>;
+    auto kern = anneal_kernel<TPW, LPT, CSR, LDS, BLOCK>;
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                          hipFuncAttributeMaxDynamicSharedMemorySize,
                                          static_cast<int>(plan.lds_bytes));
@@ -497,36 +546,37 @@ hipError_t launch_variant(hipStream_t stream, const AnnealArgs &args, const Anne
     return hipGetLastError();
 }
 
-template <int TPW, int CSR, bool LDS>
+template <int TPW, int LPT, int CSR, bool LDS>
 hipError_t launch_block(hipStream_t stream, const AnnealArgs &args, const AnnealPlan &plan) {
     switch (plan.block) {
-        case 256: return launch_variant<TPW, CSR, LDS, 256>(stream, args, plan);
-        case 512: return launch_variant<TPW, CSR, LDS, 512>(stream, args, plan);
-        case 1024: return launch_variant<TPW, CSR, LDS, 1024>(stream, args, plan);
+        case 256: return launch_variant<TPW, LPT, CSR, LDS, 256>(stream, args, plan);
+        case 512: return launch_variant<TPW, LPT, CSR, LDS, 512>(stream, args, plan);
+        case 1024: return launch_variant<TPW, LPT, CSR, LDS, 1024>(stream, args, plan);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <int TPW, int CSR>
+template <int TPW, int LPT, int CSR>
 hipError_t launch_lds(hipStream_t stream, const AnnealArgs &args, const AnnealPlan &plan) {
-    return plan.csr_lds ? launch_block<TPW, CSR, true>(stream, args, plan)
-                        : launch_block<TPW, CSR, false>(stream, args, plan);
+    return plan.csr_lds ? launch_block<TPW, LPT, CSR, true>(stream, args, plan)
+                        : launch_block<TPW, LPT, CSR, false>(stream, args, plan);
 }
 
-template <int TPW>
+template <int TPW, int LPT>
 hipError_t launch_csr(hipStream_t stream, const AnnealArgs &args, const AnnealPlan &plan) {
     switch (plan.csr) {
-        case kCsrPair: return launch_lds<TPW, kCsrPair>(stream, args, plan);
-        case kCsrPack32: return launch_lds<TPW, kCsrPack32>(stream, args, plan);
-        case kCsrPack16: return launch_lds<TPW, kCsrPack16>(stream, args, plan);
+        case kCsrPair: return launch_lds<TPW, LPT, kCsrPair>(stream, args, plan);
+        case kCsrPack32: return launch_lds<TPW, LPT, kCsrPack32>(stream, args, plan);
+        case kCsrPack16: return launch_lds<TPW, LPT, kCsrPack16>(stream, args, plan);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t block_req,
-                 size_t max_lds, int32_t num_cu, AnnealPlan *plan, std::string *why) {
+bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t lpt_req,
+                 int32_t block_req, size_t max_lds, int32_t num_cu, AnnealPlan *plan,
+                 std::string *why) {
     AnnealPlan p;
     const int32_t n4 = (g.n + 3) / 4 * 4;
     if (tpw_req == 1 || tpw_req == 4) {
@@ -560,10 +610,20 @@ bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t 
         p.lds_bytes = full;
     }
     const int32_t tasks = n4 / 4;
+    if (p.tpw == 4) {
+        p.lpt = 1;
+    } else if (lpt_req == 1 || lpt_req == 2 || lpt_req == 4) {
+        p.lpt = lpt_req;
+    } else {
+        // more lanes per task while the workgroup has lanes to spare: the
+        // small-trial runs are latency-bound, not issue-bound
+        p.lpt = tasks * 4 <= 1024 ? 4 : (tasks * 2 <= 2048 ? 2 : 1);
+    }
+    const int32_t lanes = tasks * p.lpt;
     if (block_req == 256 || block_req == 512 || block_req == 1024) {
         p.block = block_req;
     } else {
-        p.block = tasks > 512 ? 1024 : (tasks > 256 ? 512 : 256);
+        p.block = lanes > 512 ? 1024 : (lanes > 256 ? 512 : 256);
     }
     *plan = p;
     return true;
@@ -600,7 +660,13 @@ hipError_t launch_anneal(hipStream_t stream, const DevGraph &g, const DevRun &ru
     a.k0 = run.key0;
     a.k1 = run.key1;
     a.spins = run.spins;
-    return plan.tpw == 4 ? launch_csr<4>(stream, a, plan) : launch_csr<1>(stream, a, plan);
+    if (plan.tpw == 4) return launch_csr<4, 1>(stream, a, plan);
+    switch (plan.lpt) {
+        case 1: return launch_csr<1, 1>(stream, a, plan);
+        case 2: return launch_csr<1, 2>(stream, a, plan);
+        case 4: return launch_csr<1, 4>(stream, a, plan);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_local_field(hipStream_t stream, const DevGraph &g, const DevRun &run,

@@ -48,7 +48,7 @@ class psa_run_desc(ctypes.Structure):
                 ("sigma_lambda", _f64), ("sigma_delta", _f64),
                 ("sigma_nu", _f64), ("p_mean", _f64), ("lambda_", _P),
                 ("delta", _P), ("thr24", _P), ("block", _i32),
-                ("trials_per_group", _i32), ("flags", _u32)]
+                ("trials_per_group", _i32), ("lanes_per_task", _i32), ("flags", _u32)]
 
 
 # (name, restype, argtypes) of every exported entry point in include/psa.h
@@ -258,7 +258,8 @@ def variability_draw(n, seed, sigma_lambda=0.0, sigma_delta=0.0, sigma_nu=0.0, p
 
 def make_desc(steps, trials, seed=0, i0=None, i0_min=None, i0_max=None,
               sigma_lambda=0.0, sigma_delta=0.0, sigma_nu=0.0, p_mean=1.0,
-              lam=None, delta=None, thr24=None, block=0, trials_per_group=0):
+              lam=None, delta=None, thr24=None, block=0, trials_per_group=0,
+              lanes_per_task=0):
     """Build a psa_run_desc; returns (desc, keepalive arrays)."""
     d = psa_run_desc()
     _lib.psa_run_desc_default(ctypes.byref(d))
@@ -280,6 +281,7 @@ def make_desc(steps, trials, seed=0, i0=None, i0_min=None, i0_max=None,
             setattr(d, field, _ptr(a))
     d.block = int(block)
     d.trials_per_group = int(trials_per_group)
+    d.lanes_per_task = int(lanes_per_task)
     return d, keep
 
 

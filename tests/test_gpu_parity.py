@@ -47,11 +47,11 @@ def _oracle_params(n, u, v, w, steps, seed, sl, sd, sn, pm):
     return i0, lam, dlt, thr
 
 
-def _job(psa, ctx, g, spec, trials=None, steps=None, block=0, tpw=0):
+def _job(psa, ctx, g, spec, trials=None, steps=None, block=0, tpw=0, lpt=0):
     return psa.Job(ctx, g, steps or spec["steps"], trials or spec["trials"], spec["seed"],
                    sigma_lambda=spec["sigma_lambda"], sigma_delta=spec["sigma_delta"],
                    sigma_nu=spec["sigma_nu"], p_mean=spec["p_mean"], block=block,
-                   trials_per_group=tpw)
+                   trials_per_group=tpw, lanes_per_task=lpt)
 
 
 # ----------------------------------------------------------------------------
@@ -127,14 +127,15 @@ def test_local_field_and_energy(psa, ctx, n, m, trials):
 # ----------------------------------------------------------------------------
 # trajectories, step by step
 # ----------------------------------------------------------------------------
-@pytest.mark.parametrize("name,trials,steps,tpw", [("c1", 10, 25, 1), ("c1", 10, 25, 4),
-                                                   ("c2", 100, 12, 1), ("c2", 100, 12, 4)])
-def test_trajectory_every_step(psa, ctx, name, trials, steps, tpw):
+@pytest.mark.parametrize("name,trials,steps,tpw,lpt", [
+    ("c1", 10, 25, 1, 1), ("c1", 10, 25, 1, 4), ("c1", 10, 25, 4, 0),
+    ("c2", 100, 12, 1, 1), ("c2", 100, 12, 1, 2), ("c2", 100, 12, 1, 4), ("c2", 100, 12, 4, 0)])
+def test_trajectory_every_step(psa, ctx, name, trials, steps, tpw, lpt):
     spec = inputs.workload(name)
     n, u, v, w = spec["n"], spec["u"], spec["v"], spec["w"]
     g = _graph(psa, ctx, n, u, v, w)
     S = spec["steps"]
-    job = _job(psa, ctx, g, spec, trials=trials, tpw=tpw)
+    job = _job(psa, ctx, g, spec, trials=trials, tpw=tpw, lpt=lpt)
     i0, lam, dlt, thr = _oracle_params(n, u, v, w, S, spec["seed"], spec["sigma_lambda"],
                                        spec["sigma_delta"], spec["sigma_nu"], spec["p_mean"])
     ref = oracle.init_spins(n, spec["seed"], 0, trials)
@@ -198,11 +199,12 @@ def test_launch_geometry_does_not_change_results(psa, ctx):
     n, u, v, w = spec["n"], spec["u"], spec["v"], spec["w"]
     g = _graph(psa, ctx, n, u, v, w)
     outs = []
-    for block, tpw in ((256, 1), (512, 4), (1024, 1), (1024, 4), (0, 0)):
+    for block, tpw, lpt in ((256, 1, 1), (512, 4, 0), (1024, 1, 1), (1024, 4, 0), (0, 0, 0),
+                            (256, 1, 2), (1024, 1, 2), (512, 1, 4), (1024, 1, 4)):
         job = psa.Job(ctx, g, spec["steps"], spec["trials"], spec["seed"],
                       sigma_lambda=spec["sigma_lambda"], sigma_delta=spec["sigma_delta"],
                       sigma_nu=spec["sigma_nu"], p_mean=spec["p_mean"], block=block,
-                      trials_per_group=tpw)
+                      trials_per_group=tpw, lanes_per_task=lpt)
         job.step(spec["steps"])
         outs.append(job.read_spins())
     for o in outs[1:]:
