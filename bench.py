@@ -95,7 +95,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--rate", type=float, default=50.0, help="c5: arrivals per second")
+    ap.add_argument("--duration", type=float, default=20.0, help="c5: seconds of arrivals")
+    ap.add_argument("--quantum", type=int, default=250, help="c5: steps per scheduling quantum")
+    ap.add_argument("--max-resident", type=int, default=128, help="c5: resident job slots")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--tpw", type=int, default=0, help="trials per workgroup (0 = auto)")
     ap.add_argument("--lpt", type=int, default=0, help="lanes per 4-p-bit task (0 = auto)")
@@ -121,6 +125,10 @@ def main():
         return
     from paper_2601_14476_amd import inputs, psa
 
+    if args.workload == "c4":
+        return bench_batch(args)
+    if args.workload == "c5":
+        return bench_serve(args)
     spec = inputs.workload(args.workload)
     n, u, v, w = spec["n"], spec["u"], spec["v"], spec["w"]
     T, S = spec["trials"], spec["steps"]
@@ -206,6 +214,190 @@ def main():
     job.close()
     g.close()
     ctx.close()
+
+
+def bench_batch(args):
+    """256 graphs of uneven size (n in [800, 5000]; half G(n, p) with +1
+    weights, p in [0.02, 0.1]; half random degree 4-8 with +-1 weights), 64
+    trials, 1,000 sweeps each, all resident: one batched launch per step
+    versus the same jobs one graph at a time on the same stream."""
+    import torch
+    from paper_2601_14476_amd import inputs, psa
+    specs = inputs.batch_jobs()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    ctx = psa.Context(0, stream)
+    graphs, jobs, outs = [], [], []
+    updates = 0
+    ops = 0.0
+    for sp in specs:
+        n, u, v, w = inputs.make_graph(sp["graph"])
+        g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
+        info = g.info()
+        job = psa.Job(ctx, g, sp["steps"], sp["trials"], sp["seed"], trials_per_group=1)
+        graphs.append(g)
+        jobs.append(job)
+        outs.append((torch.empty(sp["trials"], dtype=torch.int64, device="cuda"),
+                     torch.empty(sp["trials"], dtype=torch.int64, device="cuda")))
+        upd = n * sp["trials"] * sp["steps"]
+        updates += upd
+        ops += ops_per_update(info["nnz"] / n, False) * upd
+    S = max(sp["steps"] for sp in specs)
+
+    def batched(ev=None):
+        for j in jobs:
+            j.reset()
+        if ev is not None:
+            ev[0].record(stream)
+        psa.jobs_step_batch(ctx, jobs, S)
+        if ev is not None:
+            ev[1].record(stream)
+        for j, (E, C) in zip(jobs, outs):
+            j.energy_cut(E, C)
+
+    def sequential():
+        for j, (E, C) in zip(jobs, outs):
+            j.reset()
+            j.step(S)
+            j.energy_cut(E, C)
+
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        batched(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    cuts_batched = [c.cpu().numpy().copy() for _, c in outs]
+    sequential()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sequential()
+    torch.cuda.synchronize()
+    wall_seq = time.perf_counter() - t0
+    same = all(np.array_equal(a, c.cpu().numpy()) for a, (_, c) in zip(cuts_batched, outs))
+    value = updates * args.steps / wall
+    achieved = ops / (kernel_ms * 1e-3) / 1e12
+    line = {
+        "metric": "p-bit updates/s (n x trials x steps / s), 1 GPU",
+        "value": value,
+        "unit": "p-bit updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8 spins / int32 field / f32 pre-activation",
+        "data": "synthetic",
+        "config": {
+            "workload": "c4", "graphs": len(specs), "trials": 64, "sweeps": S,
+            "updates_per_batch": updates,
+            "one_graph_at_a_time_updates_per_s": updates / wall_seq,
+            "batched_over_one_at_a_time": wall_seq / (wall / args.steps),
+            "identical_cuts": same,
+        },
+        "roofline": {
+            "bound": "alu", "kernel": "anneal_batch_kernel", "achieved": achieved,
+            "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
+            "traffic": None, "kernel_ms": kernel_ms,
+        },
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(args):
+    """Poisson arrivals at --rate jobs/s for --duration s; per job n in
+    [800, 20000] (random sparse, degree 4-50, +-1), steps in [1000, 10000],
+    trials in [32, 256], sigma in {0, 0.05, 0.1, 0.2}.  Each request carries
+    an edge list that the server ingests; edge lists come from a pool of 40
+    pre-generated graphs (sizes x degrees spanning the ranges), so the client
+    can keep up with the arrival rate.  Reports completed jobs/s, p50/p99
+    latency (submit to result) and served p-bit updates/s."""
+    import threading
+    import torch
+    from paper_2601_14476_amd import inputs, psa
+    trace = inputs.serve_trace(rate=args.rate, duration=args.duration)
+    sizes = [800, 3000, 6000, 10000, 14000, 17000, 20000, 20000]
+    degs = [4, 16, 30, 42, 50]
+    pool = {}
+    for a, n in enumerate(sizes[:7]):
+        for b, d in enumerate(degs):
+            pool[(a, b)] = inputs.gnm(n, n * d // 2, 7000 + 10 * a + b)
+    def pick(spec):
+        _, n, m, _, _ = spec["graph"]
+        d = 2 * m / n
+        a = min(range(7), key=lambda x: abs(sizes[x] - n))
+        b = min(range(5), key=lambda x: abs(degs[x] - d))
+        return pool[(a, b)]
+    torch.cuda.set_device(0)
+    ctx = psa.Context(0)
+    srv = psa.Server(ctx, max_resident=args.max_resident, quantum_steps=args.quantum)
+    tickets = []
+    updates = []
+    t0 = time.perf_counter()
+
+    def client():
+        for at, spec in trace:
+            delay = at - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            n, u, v, w = pick(spec)
+            tk = srv.submit(n, u, v, w, spec["steps"], spec["trials"], spec["seed"],
+                            sigma_lambda=spec["sigma_lambda"], sigma_delta=spec["sigma_delta"],
+                            sigma_nu=spec["sigma_nu"], p_mean=spec["p_mean"])
+            tickets.append(tk)
+            updates.append(n * spec["trials"] * spec["steps"])
+
+    th = threading.Thread(target=client)
+    th.start()
+    th.join()
+    lat = []
+    first_submit, last_end = None, 0
+    done = 0
+    for tk in tickets:
+        r, _ = srv.result(tk)
+        if r.status == psa.PSA_JOB_DONE:
+            done += 1
+            lat.append((r.end_us - r.submit_us) / 1e6)
+            first_submit = r.submit_us if first_submit is None else min(first_submit, r.submit_us)
+            last_end = max(last_end, r.end_us)
+    stats = srv.stats()
+    srv.close()
+    makespan = (last_end - first_submit) / 1e6
+    lat = np.array(lat)
+    line = {
+        "metric": "served jobs/s (p50/p99 latency), 1 GPU",
+        "value": done / makespan,
+        "unit": "jobs/s",
+        "n_gpus": 1,
+        "steps": len(tickets),
+        "warmup": 0,
+        "ms_per_step": makespan / max(done, 1) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8 spins / int32 field / f32 pre-activation",
+        "data": "synthetic",
+        "config": {
+            "workload": "c5", "arrival_rate": args.rate, "duration_s": args.duration,
+            "jobs": len(tickets), "completed": done, "failed": stats["failed"],
+            "quantum_steps": args.quantum, "max_resident": args.max_resident,
+            "latency_p50_s": float(np.percentile(lat, 50)),
+            "latency_p99_s": float(np.percentile(lat, 99)),
+            "latency_mean_s": float(lat.mean()),
+            "served_updates_per_s": float(sum(updates) / makespan),
+            "offered_updates_per_s": float(sum(updates) / args.duration),
+            "makespan_s": makespan, "quanta": stats["quanta"],
+        },
+    }
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

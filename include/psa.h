@@ -52,6 +52,8 @@ typedef int32_t psa_status;
 #define PSA_ENOMEM (-2)       /* host or device allocation failed        */
 #define PSA_EHIP (-3)         /* a HIP runtime call failed               */
 #define PSA_EUNSUPPORTED (-4) /* valid request this build cannot serve   */
+#define PSA_ECANCELED (-6)    /* the job was canceled                    */
+#define PSA_ETIMEDOUT (-7)    /* a wait ended before the job finished    */
 
 typedef struct psa_ctx psa_ctx;
 typedef struct psa_graph psa_graph;
@@ -238,6 +240,117 @@ void psa_job_destroy(psa_job *job);
 psa_status psa_anneal(psa_ctx *ctx, const psa_graph *g,
                       const psa_run_desc *desc, int8_t *spins_out,
                       int64_t *energy_out, int64_t *cut_out, uint32_t flags);
+
+/* ------------------------------------------------------------------ */
+/* Batched runs: many graphs of uneven size in one launch              */
+/* ------------------------------------------------------------------ */
+
+/* Advance every job of `jobs` (all created on ctx, each listed once) by up
+ * to k steps, clipped to each job's schedule, with one launch of the batch
+ * kernel on the context's stream: one work item per (job, trial), each
+ * workgroup dispatching to the kernel variant its job needs.  The results
+ * are identical to stepping each job alone. */
+psa_status psa_jobs_step_batch(psa_ctx *ctx, int32_t count, psa_job *const *jobs,
+                               int32_t k);
+
+/* One anneal of a batch: graph, run description, and where its results go
+ * (host or device memory per the flags of psa_anneal_batch). */
+typedef struct psa_batch_item {
+    const psa_graph *graph;
+    psa_run_desc desc;
+    int64_t *energy_out; /* [trials] */
+    int64_t *cut_out;    /* [trials] */
+    int8_t *spins_out;   /* [trials][n], or NULL */
+} psa_batch_item;
+
+/* Run the items one after the other instead of in one launch (reference). */
+#define PSA_BATCH_SEQUENTIAL 2u
+
+/* Run every item to the end of its schedule -- by default all in one
+ * batched launch -- and write energies, cuts and (optionally) spins.
+ * flags: PSA_OUT_HOST or PSA_OUT_DEVICE, optionally | PSA_BATCH_SEQUENTIAL.
+ * Blocks until the results are written. */
+psa_status psa_anneal_batch(psa_ctx *ctx, int32_t count,
+                            const psa_batch_item *items, uint32_t flags);
+
+/* ------------------------------------------------------------------ */
+/* Serving with continuous batching                                     */
+/* ------------------------------------------------------------------ */
+
+typedef struct psa_server psa_server;
+
+/* Admission limits.  hbm_budget_bytes <= 0: half of the device memory free
+ * at creation; max_resident <= 0: 64 jobs; quantum_steps <= 0: 250. */
+typedef struct psa_server_opts {
+    int64_t hbm_budget_bytes; /* device bytes resident jobs may hold       */
+    int32_t max_resident;     /* jobs advanced together in one launch      */
+    int32_t quantum_steps;    /* steps per launch between scheduling points */
+} psa_server_opts;
+
+/* Job states. */
+#define PSA_JOB_QUEUED 0
+#define PSA_JOB_RUNNING 1
+#define PSA_JOB_DONE 2
+#define PSA_JOB_ERROR 3
+#define PSA_JOB_CANCELED 4
+
+typedef struct psa_result {
+    int32_t status;    /* PSA_JOB_*                                      */
+    int32_t error;     /* psa_status of a failed job (PSA_OK otherwise)  */
+    int64_t submit_us; /* times in microseconds since server creation   */
+    int64_t admit_us;  /* -1 until admitted                              */
+    int64_t end_us;    /* -1 until done, failed or canceled              */
+} psa_result;
+
+typedef struct psa_server_stats {
+    int32_t waiting, resident;
+    int64_t completed, failed, canceled, quanta;
+    int64_t used_bytes, budget_bytes;
+} psa_server_stats;
+
+/* Start a server on ctx.  Its scheduler thread issues all device work on the
+ * context's stream from then on: do not use ctx from other threads while the
+ * server exists.  Between step quanta it retires finished jobs, admits
+ * waiting jobs first come first served while their device footprint fits
+ * the budget and a slot is free, and advances every resident job by one
+ * quantum in a single batched launch (psa_jobs_step_batch).  A job's results
+ * are identical to running it alone. */
+psa_status psa_server_create(psa_ctx *ctx, const psa_server_opts *opts,
+                             psa_server **out);
+
+/* Queue one anneal: a graph as an edge list (as psa_graph_from_edges; the
+ * arrays are copied) and a run description (its optional arrays are
+ * copied).  energy_out / cut_out ([trials]) and spins_out ([trials][n] or
+ * NULL) are host buffers the server fills when the job is done; they must
+ * stay valid until the job reports DONE, ERROR or CANCELED.  A job whose
+ * footprint alone exceeds the budget ends in ERROR with PSA_ENOMEM. */
+psa_status psa_server_submit(psa_server *s, int32_t n, int64_t m,
+                             const int32_t *u, const int32_t *v,
+                             const int32_t *val, const int32_t *h,
+                             uint32_t graph_flags, const psa_run_desc *desc,
+                             int64_t *energy_out, int64_t *cut_out,
+                             int8_t *spins_out, uint64_t *ticket);
+
+/* Current state of a job (never blocks). */
+psa_status psa_server_poll(psa_server *s, uint64_t ticket, psa_result *out);
+
+/* Block until the job is done, failed or canceled, or timeout_us passes
+ * (timeout_us < 0: no limit; PSA_ETIMEDOUT with the current state). */
+psa_status psa_server_wait(psa_server *s, uint64_t ticket, int64_t timeout_us,
+                           psa_result *out);
+
+/* Ask for a job to be dropped (queued: at once; resident: after the current
+ * quantum).  A job that has already finished keeps its results. */
+psa_status psa_server_cancel(psa_server *s, uint64_t ticket);
+
+/* Forget a finished job's record (its ticket becomes unknown). */
+psa_status psa_server_release(psa_server *s, uint64_t ticket);
+
+psa_status psa_server_stats_get(psa_server *s, psa_server_stats *out);
+
+/* Stop the server: queued jobs are canceled, resident jobs are canceled
+ * after the current quantum, the scheduler thread is joined. */
+void psa_server_destroy(psa_server *s);
 
 #ifdef __cplusplus
 }

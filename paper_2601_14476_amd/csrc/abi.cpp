@@ -65,131 +65,6 @@ void dev_free(T *&p) {
     p = nullptr;
 }
 
-void graph_free(psa_graph *g) {
-    if (!g) return;
-    dev_free(g->d_row_ptr);
-    dev_free(g->d_col);
-    dev_free(g->d_val);
-    dev_free(g->d_h);
-    dev_free(g->d_pk32);
-    dev_free(g->d_pk16);
-    delete g;
-}
-
-// Sort each row by column, reject repeated columns and diagonal entries.
-psa_status canonical_rows(int32_t n, const std::vector<int64_t> &row_ptr,
-                          std::vector<int32_t> &col, std::vector<int32_t> &val) {
-    std::vector<std::pair<int32_t, int32_t>> tmp;
-    for (int32_t i = 0; i < n; ++i) {
-        const int64_t b = row_ptr[i], e = row_ptr[i + 1];
-        tmp.clear();
-        for (int64_t p = b; p < e; ++p) tmp.emplace_back(col[p], val[p]);
-        std::sort(tmp.begin(), tmp.end());
-        for (size_t k = 0; k < tmp.size(); ++k) {
-            if (tmp[k].first == i) {
-                set_error("graph: self loop at p-bit " + std::to_string(i));
-                return PSA_EINVAL;
-            }
-            if (k > 0 && tmp[k].first == tmp[k - 1].first) {
-                set_error("graph: repeated pair (" + std::to_string(i) + ", " +
-                          std::to_string(tmp[k].first) + ")");
-                return PSA_EINVAL;
-            }
-            col[b + static_cast<int64_t>(k)] = tmp[k].first;
-            val[b + static_cast<int64_t>(k)] = tmp[k].second;
-        }
-    }
-    return PSA_OK;
-}
-
-// Statistics, bounds and upload of a canonical symmetric CSR.
-psa_status finish_graph(psa_ctx *ctx, int32_t n, const std::vector<int64_t> &row_ptr,
-                        const std::vector<int32_t> &col, const std::vector<int32_t> &val,
-                        const int32_t *h, psa_graph **out) {
-    const int64_t nnz = row_ptr[n];
-    if (nnz >= (int64_t{1} << 31)) {
-        set_error("graph: more than 2^31 - 1 stored couplings");
-        return PSA_EUNSUPPORTED;
-    }
-    psa_graph_info info{};
-    info.n = n;
-    info.nnz = nnz;
-    info.edges = nnz / 2;
-    int64_t w2 = 0;
-    int64_t max_field = 0;
-    int32_t max_deg = 0;
-    bool unit = true;
-    double sum_s = 0.0;
-    for (int32_t i = 0; i < n; ++i) {
-        int64_t s1 = 0, s2 = 0, absrow = h ? std::llabs(static_cast<int64_t>(h[i])) : 0;
-        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
-            const int64_t J = val[p];
-            s1 += J;
-            s2 += J * J;
-            absrow += std::llabs(J);
-            if (J != 1 && J != -1) unit = false;
-        }
-        w2 += s1;
-        max_field = std::max(max_field, absrow);
-        max_deg = std::max<int32_t>(max_deg, static_cast<int32_t>(row_ptr[i + 1] - row_ptr[i]));
-        // s_i = sqrt((n-1) Var(J_i,:)), population variance over the n
-        // entries of the dense row: Var = (n s2 - s1^2) / n^2.
-        const int64_t num = static_cast<int64_t>(n) * s2 - s1 * s1;
-        const double var = static_cast<double>(num) / (static_cast<double>(n) * static_cast<double>(n));
-        sum_s += sqrt(static_cast<double>(n - 1) * var);
-    }
-    if (max_field >= (int64_t{1} << 24)) {
-        set_error("graph: max_i |h_i| + sum_j |J_ij| must be < 2^24");
-        return PSA_EINVAL;
-    }
-    info.w_total = -(w2 / 2);
-    info.max_abs_field = static_cast<int32_t>(max_field);
-    info.max_degree = max_deg;
-    info.unit_weights = (unit && nnz > 0) ? 1 : 0;
-    info.mean_s = sum_s / static_cast<double>(n);
-
-    std::unique_ptr<psa_graph, void (*)(psa_graph *)> g(new psa_graph(), graph_free);
-    g->ctx = ctx;
-    g->info = info;
-    PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-    std::vector<int32_t> rp32(static_cast<size_t>(n) + 1);
-    for (int32_t i = 0; i <= n; ++i) rp32[i] = static_cast<int32_t>(row_ptr[i]);
-    std::vector<int32_t> hz;
-    if (!h) hz.assign(static_cast<size_t>(n), 0);
-    psa_status st;
-    if ((st = dev_upload(&g->d_row_ptr, rp32.data(), rp32.size(), "graph upload")) != PSA_OK) return st;
-    if ((st = dev_upload(&g->d_col, col.data(), col.size(), "graph upload")) != PSA_OK) return st;
-    if ((st = dev_upload(&g->d_val, val.data(), val.size(), "graph upload")) != PSA_OK) return st;
-    if ((st = dev_upload(&g->d_h, h ? h : hz.data(), static_cast<size_t>(n), "graph upload")) != PSA_OK)
-        return st;
-    // Packed copies of the edges for the anneal kernel (one load per edge).
-    bool fits16 = true;
-    for (int64_t p = 0; p < nnz; ++p)
-        if (val[p] < -32768 || val[p] > 32767) fits16 = false;
-    if (n <= 65536 && fits16) {
-        std::vector<uint32_t> pk(static_cast<size_t>(nnz));
-        for (int64_t p = 0; p < nnz; ++p)
-            pk[p] = static_cast<uint32_t>(col[p]) | (static_cast<uint32_t>(val[p]) << 16);
-        if ((st = dev_upload(&g->d_pk32, pk.data(), pk.size(), "graph upload")) != PSA_OK) return st;
-    }
-    if (n <= 32768 && info.unit_weights) {
-        std::vector<uint16_t> pk(static_cast<size_t>(nnz));
-        for (int64_t p = 0; p < nnz; ++p)
-            pk[p] = static_cast<uint16_t>((static_cast<uint32_t>(col[p]) << 1) | (val[p] < 0 ? 1u : 0u));
-        if ((st = dev_upload(&g->d_pk16, pk.data(), pk.size(), "graph upload")) != PSA_OK) return st;
-    }
-    g->dev.pk32 = g->d_pk32;
-    g->dev.pk16 = g->d_pk16;
-    g->dev.n = n;
-    g->dev.nnz = nnz;
-    g->dev.row_ptr = g->d_row_ptr;
-    g->dev.col = g->d_col;
-    g->dev.val = g->d_val;
-    g->dev.h = g->d_h;
-    g->dev.w2 = w2;
-    *out = g.release();
-    return PSA_OK;
-}
 
 void job_free(psa_job *j) {
     if (!j) return;
@@ -201,6 +76,7 @@ void job_free(psa_job *j) {
     dev_free(j->d_lambda);
     dev_free(j->d_delta);
     dev_free(j->d_thr24);
+    dev_free(j->d_order);
     dev_free(j->d_spins);
     dev_free(j->d_scratch);
     delete j;
@@ -273,6 +149,8 @@ void psa_ctx_destroy(psa_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->d_batch_table) (void)hipFree(ctx->d_batch_table);
+    if (ctx->d_batch_work) (void)hipFree(ctx->d_batch_work);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -280,91 +158,27 @@ void psa_ctx_destroy(psa_ctx *ctx) {
 psa_status psa_graph_from_edges(psa_ctx *ctx, int32_t n, int64_t m, const int32_t *u,
                                 const int32_t *v, const int32_t *val, const int32_t *h,
                                 uint32_t flags, psa_graph **out) {
-    if (!ctx || !out || n < 1 || m < 0 || (m > 0 && (!u || !v || !val)) ||
-        (flags & ~PSA_GRAPH_MAXCUT) != 0) {
+    if (!ctx || !out) {
         set_error("psa_graph_from_edges: invalid arguments");
         return PSA_EINVAL;
     }
-    const bool maxcut = (flags & PSA_GRAPH_MAXCUT) != 0;
-    std::vector<int64_t> row_ptr(static_cast<size_t>(n) + 1, 0);
-    for (int64_t e = 0; e < m; ++e) {
-        if (u[e] < 0 || u[e] >= n || v[e] < 0 || v[e] >= n) {
-            set_error("psa_graph_from_edges: edge " + std::to_string(e) + " out of range");
-            return PSA_EINVAL;
-        }
-        if (u[e] == v[e]) {
-            set_error("psa_graph_from_edges: self loop at edge " + std::to_string(e));
-            return PSA_EINVAL;
-        }
-        if (val[e] == std::numeric_limits<int32_t>::min()) {
-            set_error("psa_graph_from_edges: edge value out of range");
-            return PSA_EINVAL;
-        }
-        ++row_ptr[u[e] + 1];
-        ++row_ptr[v[e] + 1];
-    }
-    for (int32_t i = 0; i < n; ++i) row_ptr[i + 1] += row_ptr[i];
-    std::vector<int32_t> col(static_cast<size_t>(row_ptr[n])), vv(static_cast<size_t>(row_ptr[n]));
-    std::vector<int64_t> fill(row_ptr.begin(), row_ptr.end() - 1);
-    for (int64_t e = 0; e < m; ++e) {
-        const int32_t J = maxcut ? -val[e] : val[e];
-        col[fill[u[e]]] = v[e];
-        vv[fill[u[e]]++] = J;
-        col[fill[v[e]]] = u[e];
-        vv[fill[v[e]]++] = J;
-    }
-    psa_status st = canonical_rows(n, row_ptr, col, vv);
+    psa::HostGraph hg;
+    psa_status st = psa::host_graph_from_edges(n, m, u, v, val, h, flags, &hg);
     if (st != PSA_OK) return st;
-    return finish_graph(ctx, n, row_ptr, col, vv, h, out);
+    return psa::upload_graph(ctx, std::move(hg), out);
 }
 
 psa_status psa_graph_from_csr(psa_ctx *ctx, int32_t n, const int64_t *row_ptr, const int32_t *col,
                               const int32_t *val, const int32_t *h, uint32_t flags,
                               psa_graph **out) {
-    if (!ctx || !out || n < 1 || !row_ptr || (flags & ~PSA_GRAPH_MAXCUT) != 0) {
+    if (!ctx || !out) {
         set_error("psa_graph_from_csr: invalid arguments");
         return PSA_EINVAL;
     }
-    if (row_ptr[0] != 0) {
-        set_error("psa_graph_from_csr: row_ptr[0] must be 0");
-        return PSA_EINVAL;
-    }
-    for (int32_t i = 0; i < n; ++i)
-        if (row_ptr[i + 1] < row_ptr[i]) {
-            set_error("psa_graph_from_csr: row_ptr is not non-decreasing");
-            return PSA_EINVAL;
-        }
-    const int64_t nnz = row_ptr[n];
-    if (nnz > 0 && (!col || !val)) {
-        set_error("psa_graph_from_csr: col/val NULL");
-        return PSA_EINVAL;
-    }
-    const bool maxcut = (flags & PSA_GRAPH_MAXCUT) != 0;
-    std::vector<int64_t> rp(row_ptr, row_ptr + n + 1);
-    std::vector<int32_t> cc(static_cast<size_t>(nnz)), vv(static_cast<size_t>(nnz));
-    for (int64_t p = 0; p < nnz; ++p) {
-        if (col[p] < 0 || col[p] >= n || val[p] == std::numeric_limits<int32_t>::min()) {
-            set_error("psa_graph_from_csr: entry " + std::to_string(p) + " out of range");
-            return PSA_EINVAL;
-        }
-        cc[p] = col[p];
-        vv[p] = maxcut ? -val[p] : val[p];
-    }
-    psa_status st = canonical_rows(n, rp, cc, vv);
+    psa::HostGraph hg;
+    psa_status st = psa::host_graph_from_csr(n, row_ptr, col, val, h, flags, &hg);
     if (st != PSA_OK) return st;
-    // symmetry: J_ij == J_ji for every stored entry
-    for (int32_t i = 0; i < n; ++i)
-        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
-            const int32_t j = cc[p];
-            auto b = cc.begin() + rp[j], e = cc.begin() + rp[j + 1];
-            auto it = std::lower_bound(b, e, i);
-            if (it == e || *it != i || vv[it - cc.begin()] != vv[p]) {
-                set_error("psa_graph_from_csr: CSR is not symmetric at (" + std::to_string(i) +
-                          ", " + std::to_string(j) + ")");
-                return PSA_EINVAL;
-            }
-        }
-    return finish_graph(ctx, n, rp, cc, vv, h, out);
+    return psa::upload_graph(ctx, std::move(hg), out);
 }
 
 psa_status psa_graph_info_get(const psa_graph *g, psa_graph_info *out) {
@@ -381,7 +195,7 @@ void psa_graph_destroy(psa_graph *g) {
         (void)hipSetDevice(g->ctx->device);
         (void)hipStreamSynchronize(g->ctx->stream);
     }
-    graph_free(g);
+    psa::graph_release(g);
 }
 
 psa_status psa_schedule_paper(const psa_graph *g, double *i0_min, double *i0_max) {
@@ -502,10 +316,18 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
     j->run.key0 = static_cast<uint32_t>(desc->seed);
     j->run.key1 = static_cast<uint32_t>(desc->seed >> 32);
     psa_status st;
+    // per-p-bit arrays padded to n4: padding p-bits never fire
+    const int32_t n4 = g->dev.n4;
+    lam.resize(static_cast<size_t>(n4), 1.0f);
+    dlt.resize(static_cast<size_t>(n4), 0.0f);
+    thr.resize(static_cast<size_t>(n4), 0u);
+    std::vector<int32_t> order;
+    psa::task_order(g->dev, g->row_ptr_host, j->plan, &order);
     if ((st = dev_upload(&j->d_i0, i0.data(), i0.size(), "job upload")) != PSA_OK) return st;
     if ((st = dev_upload(&j->d_lambda, lam.data(), lam.size(), "job upload")) != PSA_OK) return st;
     if ((st = dev_upload(&j->d_delta, dlt.data(), dlt.size(), "job upload")) != PSA_OK) return st;
     if ((st = dev_upload(&j->d_thr24, thr.data(), thr.size(), "job upload")) != PSA_OK) return st;
+    if ((st = dev_upload(&j->d_order, order.data(), order.size(), "job upload")) != PSA_OK) return st;
     const size_t spin_bytes = static_cast<size_t>(n) * static_cast<size_t>(j->run.t4);
     if ((st = dev_upload<int8_t>(&j->d_spins, nullptr, spin_bytes, "job spins")) != PSA_OK) return st;
     j->run.i0 = j->d_i0;
@@ -538,7 +360,8 @@ psa_status psa_job_step(psa_job *job, int32_t k) {
     const int32_t t_end = static_cast<int32_t>(std::min<int64_t>(int64_t{job->t} + k, job->run.steps));
     if (t_end <= job->t) return PSA_OK;
     PSA_HIP(hipSetDevice(job->ctx->device), "hipSetDevice");
-    PSA_HIP(psa::launch_anneal(job->ctx->stream, job->g->dev, job->run, job->plan, job->t, t_end),
+    PSA_HIP(psa::launch_anneal(job->ctx->stream, job->g->dev, job->run, job->plan, job->d_order,
+                               job->t, t_end),
             "anneal launch");
     job->t = t_end;
     return PSA_OK;

@@ -1,0 +1,712 @@
+// anneal.hip -- the persistent pSA sweep kernel (gfx950).
+//
+// One workgroup owns TPW trials (1 or 4) of a run, keeps their spins of all
+// p-bits in LDS (two buffers, one workgroup barrier per step) and runs every
+// step of the launch inside the kernel.  Work is split into *tasks*: a task
+// is a group of four consecutive p-bits 4m..4m+3, because one Philox block of
+// counter (t, m, k, purpose) supplies the words of exactly those four p-bits
+// of trial k (word i mod 4).
+//
+// Edge encodings (CSR):
+//   kCsrUnit   (TPW 1, every |J| = 1): spins in LDS as 0/1 bytes u = (m+1)/2
+//              with a complemented copy 1-u behind them; edge e of row i is an
+//              index ux16[e] = j (J = +1) or n4 + j (J = -1) into that pair of
+//              arrays, so sum_j J_ij m_j = 2 sum_e x_e - deg_i with x_e the
+//              byte the index selects: one LDS byte load and one add per edge.
+//   kCsrPack16 (TPW 4, every |J| = 1, degree <= 255): four trials' 0/1 bytes
+//              per word; pk16[e] = j << 1 | (J < 0); x_e = word_j XOR
+//              (J < 0 ? 0x01010101 : 0), summed four trials per 32-bit add.
+//   kCsrPack32 pk32[e] = j | J << 16; spins as +-1 bytes; general weights.
+//   kCsrPair   separate col / val arrays; spins as +-1 bytes; general weights.
+// Per-p-bit arrays are padded to n4 = 4 ceil(n/4) entries (padding p-bits have
+// no edges and never fire), row_ptr to n4 + 4 entries.
+#include <hip/hip_runtime.h>
+
+#include "device_math.hpp"
+#include "engine.hpp"
+
+namespace psa {
+namespace {
+
+// Where the kernel reads the graph and per-p-bit factors from (LDS or global).
+struct Views {
+    const int32_t *row_ptr;
+    const int32_t *h;
+    const float *lam;
+    const float *dlt;
+    const uint32_t *thr;
+    const int32_t *order;
+    const int32_t *col;
+    const int32_t *val;
+    const uint32_t *pk32;
+    const uint16_t *pk16;
+    const uint16_t *ux16;
+};
+
+__device__ __forceinline__ Words4 block_of(uint32_t t, uint32_t m, uint32_t k, uint32_t tag,
+                                           uint32_t k0, uint32_t k1) {
+    return philox4x32_10(t, m, k, tag, k0, k1);
+}
+
+// Eq. 6 decision for one p-bit and trial: +1 iff tanh((I0 lambda)(L + delta)) > r.
+__device__ __forceinline__ bool goes_up(float a, float d, int32_t L, uint32_t rword) {
+    const float b = static_cast<float>(L) + d;
+    const float x = a * b;
+    return tanh_f32(x) > r_of(rword);
+}
+
+template <int TPW, int CSR>
+struct Enc {
+    // 0/1 byte encoding in LDS (else +-1 bytes)
+    static constexpr bool kU = (CSR == kCsrUnit) || (TPW == 4 && CSR == kCsrPack16);
+    // complemented copy behind the spins (TPW 1, unit weights)
+    static constexpr bool kMirror = (CSR == kCsrUnit);
+};
+
+// ---------------------------------------------------------------------------
+// Field sums.
+// ---------------------------------------------------------------------------
+
+// One trial, +-1 bytes, general weights: L = h_i + sum_j J_ij m_j.
+template <int CSR>
+__device__ __forceinline__ int32_t field_pm1(const Views &v, int32_t i, const int8_t *cur) {
+    int32_t L = v.h[i];
+    const int32_t e1 = v.row_ptr[i + 1];
+#pragma unroll 2
+    for (int32_t e = v.row_ptr[i]; e < e1; ++e) {
+        if constexpr (CSR == kCsrPack32) {
+            const uint32_t w = v.pk32[e];
+            L += (static_cast<int32_t>(w) >> 16) * static_cast<int32_t>(cur[w & 0xFFFFu]);
+        } else {
+            L += v.val[e] * static_cast<int32_t>(cur[v.col[e]]);
+        }
+    }
+    return L;
+}
+
+// One trial, unit weights, mirrored 0/1 bytes: the rows of p-bits
+// base, base+1 (P = 2) or base (P = 1) walked as one contiguous edge range.
+template <int P>
+__device__ __forceinline__ void field_unit(const Views &v, int32_t base, const uint8_t *cur,
+                                           int32_t L[P]) {
+    const int32_t e0 = v.row_ptr[base];
+    if constexpr (P == 1) {
+        const int32_t e1 = v.row_ptr[base + 1];
+        int32_t acc = 0;
+#pragma unroll 4
+        for (int32_t e = e0; e < e1; ++e) acc += cur[v.ux16[e]];
+        L[0] = v.h[base] + 2 * acc - (e1 - e0);
+    } else {
+        const int32_t split = v.row_ptr[base + 1];
+        const int32_t e2 = v.row_ptr[base + 2];
+        int32_t acc = 0, acc0 = 0;
+#pragma unroll 4
+        for (int32_t e = e0; e < e2; ++e) {
+            acc += cur[v.ux16[e]];
+            acc0 = (e == split - 1) ? acc : acc0;
+        }
+        L[0] = v.h[base] + 2 * acc0 - (split - e0);
+        L[1] = v.h[base + 1] + 2 * (acc - acc0) - (e2 - split);
+    }
+}
+
+// Four trials, unit weights, 0/1 bytes packed per word (SWAR); degree <= 255.
+__device__ __forceinline__ void field_swar(const Views &v, int32_t i, const uint32_t *cur,
+                                           int32_t L[4]) {
+    const int32_t e0 = v.row_ptr[i], e1 = v.row_ptr[i + 1];
+    uint32_t acc = 0u;
+#pragma unroll 2
+    for (int32_t e = e0; e < e1; ++e) {
+        const uint32_t w = v.pk16[e];
+        acc += cur[w >> 1] ^ ((w & 1u) * 0x01010101u);
+    }
+    const int32_t base = v.h[i] - (e1 - e0);
+    L[0] = base + 2 * static_cast<int32_t>(acc & 0xFFu);
+    L[1] = base + 2 * static_cast<int32_t>((acc >> 8) & 0xFFu);
+    L[2] = base + 2 * static_cast<int32_t>((acc >> 16) & 0xFFu);
+    L[3] = base + 2 * static_cast<int32_t>(acc >> 24);
+}
+
+// Four trials, +-1 bytes packed per word, general weights.
+template <int CSR>
+__device__ __forceinline__ void field_words(const Views &v, int32_t i, const uint32_t *cur,
+                                            int32_t L[4]) {
+    const int32_t hi = v.h[i];
+    L[0] = L[1] = L[2] = L[3] = hi;
+    const int32_t e1 = v.row_ptr[i + 1];
+#pragma unroll 2
+    for (int32_t e = v.row_ptr[i]; e < e1; ++e) {
+        int32_t J;
+        uint32_t wj;
+        if constexpr (CSR == kCsrPack32) {
+            const uint32_t w = v.pk32[e];
+            J = static_cast<int32_t>(w) >> 16;
+            wj = cur[w & 0xFFFFu];
+        } else {
+            J = v.val[e];
+            wj = cur[v.col[e]];
+        }
+        L[0] += J * spin_of(wj, 0);
+        L[1] += J * spin_of(wj, 1);
+        L[2] += J * spin_of(wj, 2);
+        L[3] += J * spin_of(wj, 3);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Random words of a task for one trial.  With LPT lanes per task, lane `sub`
+// needs the words of its P = 4/LPT p-bits sub*P .. sub*P+P-1.  When the gate
+// is on and LPT >= 2, even lanes draw the r block and odd lanes the gate
+// block, and each pair swaps the words the other needs (DPP), so the two
+// Philox blocks run side by side.
+// ---------------------------------------------------------------------------
+template <int LPT>
+__device__ __forceinline__ void task_words(uint32_t t, uint32_t m, uint32_t k, uint32_t sub,
+                                           bool need_gate, uint32_t k0, uint32_t k1,
+                                           uint32_t rw[4 / LPT], uint32_t gw[4 / LPT]) {
+    if constexpr (LPT == 1) {
+        const Words4 r = block_of(t, m, k, kTagR, k0, k1);
+        rw[0] = r.x;
+        rw[1] = r.y;
+        rw[2] = r.z;
+        rw[3] = r.w;
+        gw[0] = gw[1] = gw[2] = gw[3] = 0u;
+        if (need_gate) {
+            const Words4 g = block_of(t, m, k, kTagGate, k0, k1);
+            gw[0] = g.x;
+            gw[1] = g.y;
+            gw[2] = g.z;
+            gw[3] = g.w;
+        }
+    } else {
+        const uint32_t tag = (need_gate && (sub & 1u)) ? kTagGate : kTagR;
+        const Words4 b = block_of(t, m, k, tag, k0, k1);
+        if constexpr (LPT == 2) {
+            if (need_gate) {  // lane 0 holds the r words, lane 1 the gate words
+                const uint32_t x0 = swap_pair(sub ? b.x : b.z);
+                const uint32_t x1 = swap_pair(sub ? b.y : b.w);
+                rw[0] = sub ? x0 : b.x;
+                rw[1] = sub ? x1 : b.y;
+                gw[0] = sub ? b.z : x0;
+                gw[1] = sub ? b.w : x1;
+            } else {
+                rw[0] = sub ? b.z : b.x;
+                rw[1] = sub ? b.w : b.y;
+                gw[0] = gw[1] = 0u;
+            }
+        } else {  // LPT == 4: even lanes r block, odd lanes gate block
+            const uint32_t own = word_of(b, sub);
+            if (need_gate) {
+                const uint32_t x = swap_pair(word_of(b, sub ^ 1u));
+                const bool even = (sub & 1u) == 0u;
+                rw[0] = even ? own : x;
+                gw[0] = even ? x : own;
+            } else {
+                rw[0] = own;
+                gw[0] = 0u;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ bool any_gate(const uint32_t *thr, int32_t m) {
+    const uint4 th = *reinterpret_cast<const uint4 *>(thr + 4 * m);
+    return (th.x < kGateOne) | (th.y < kGateOne) | (th.z < kGateOne) | (th.w < kGateOne);
+}
+
+// ---------------------------------------------------------------------------
+// One trial per workgroup: lane `sub` of task m updates its P p-bits and
+// returns their new bytes (in the LDS encoding) in the low 8P bits.
+// ---------------------------------------------------------------------------
+template <int CSR, int LPT>
+__device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, uint32_t sub,
+                                                   uint32_t k, uint32_t t, float i0t,
+                                                   const unsigned char *cur, uint32_t k0,
+                                                   uint32_t k1) {
+    constexpr int P = 4 / LPT;
+    constexpr bool kU = Enc<1, CSR>::kU;
+    const bool need_gate = any_gate(v.thr, m);
+    uint32_t rw[P], gw[P];
+    task_words<LPT>(t, static_cast<uint32_t>(m), k, sub, need_gate, k0, k1, rw, gw);
+    const int32_t base = 4 * m + static_cast<int32_t>(sub) * P;
+    int32_t L[P];
+    if constexpr (CSR == kCsrUnit) {
+        if constexpr (P == 4) {
+            field_unit<2>(v, base, cur, L);
+            field_unit<2>(v, base + 2, cur, L + 2);
+        } else {
+            field_unit<P>(v, base, cur, L);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+            L[j] = field_pm1<CSR>(v, base + j, reinterpret_cast<const int8_t *>(cur));
+    }
+    uint32_t out = 0u;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const int32_t i = base + j;
+        const uint32_t old = cur[i];
+        const uint32_t th = v.thr[i];
+        const bool fire = th >= kGateOne || fires(gw[j], th);
+        const bool up = goes_up(i0t * v.lam[i], v.dlt[i], L[j], rw[j]);
+        const uint32_t nb = kU ? (up ? 1u : 0u) : (up ? 0x01u : 0xFFu);
+        out |= (fire ? nb : old) << (8 * j);
+    }
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// Four trials per workgroup: one lane per task updates 4 p-bits x 4 trials and
+// writes the four packed words of the next step.
+// ---------------------------------------------------------------------------
+template <int CSR>
+__device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int32_t q, uint32_t t,
+                                                 float i0t, const uint32_t *cur, uint32_t *nxt,
+                                                 uint32_t k0, uint32_t k1) {
+    constexpr bool kU = Enc<4, CSR>::kU;
+    int32_t L[4][4];
+    uint32_t word[4], th[4];
+    float a[4], d[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int32_t i = 4 * m + p;
+        word[p] = cur[i];
+        th[p] = v.thr[i];
+        a[p] = i0t * v.lam[i];
+        d[p] = v.dlt[i];
+        if constexpr (CSR == kCsrPack16)
+            field_swar(v, i, cur, L[p]);
+        else
+            field_words<CSR>(v, i, cur, L[p]);
+    }
+    const bool need_gate = (th[0] < kGateOne) | (th[1] < kGateOne) | (th[2] < kGateOne) |
+                           (th[3] < kGateOne);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        const uint32_t k = static_cast<uint32_t>(4 * q + kk);
+        uint32_t gw[4] = {0u, 0u, 0u, 0u};
+        if (need_gate) {
+            const Words4 g = block_of(t, static_cast<uint32_t>(m), k, kTagGate, k0, k1);
+            gw[0] = g.x;
+            gw[1] = g.y;
+            gw[2] = g.z;
+            gw[3] = g.w;
+        }
+        const Words4 r = block_of(t, static_cast<uint32_t>(m), k, kTagR, k0, k1);
+        const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const bool fire = th[p] >= kGateOne || fires(gw[p], th[p]);
+            const bool up = goes_up(a[p], d[p], L[p][kk], rw[p]);
+            const uint32_t nb = kU ? (up ? 1u : 0u) : (up ? 0x01u : 0xFFu);
+            if (fire) word[p] = (word[p] & ~(0xFFu << (8 * kk))) | (nb << (8 * kk));
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) nxt[4 * m + p] = word[p];
+}
+
+// ---------------------------------------------------------------------------
+// LDS carve-up (also used by the host planner):
+//   [buffer 0][buffer 1]                       2 * spin_buf_bytes
+//   [row_ptr n4+4][h n4][lam n4][dlt n4][thr n4][order tasks rounded to 4]  (csr_lds)
+//   [edges: nnz * edge_bytes]                                               (csr_lds)
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+__host__ __device__ constexpr size_t spin_buf_bytes(int32_t n4, int32_t tpw, int32_t csr) {
+    return align16(static_cast<size_t>(n4) * tpw * (csr == kCsrUnit ? 2 : 1));
+}
+
+__host__ __device__ constexpr size_t params_bytes(int32_t n4) {
+    return static_cast<size_t>(n4 + 4 + 4 * n4 + (n4 / 4 + 3) / 4 * 4) * 4;
+}
+
+__host__ __device__ constexpr size_t edge_bytes(int32_t csr) {
+    return (csr == kCsrPack16 || csr == kCsrUnit) ? 2 : (csr == kCsrPack32 ? 4 : 8);
+}
+
+// Whole run of one workgroup: trial group q of the run described by `a`,
+// steps a.t_begin .. a.t_end-1.  `smem` is the dynamic LDS of the launch.
+template <int TPW, int LPT, int CSR, bool CSR_LDS, int BLOCK>
+__device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsigned char *smem) {
+    using E = Enc<TPW, CSR>;
+    const int32_t n = a.n, n4 = a.n4, tasks = a.tasks;
+    const size_t sb = spin_buf_bytes(n4, TPW, CSR);
+    unsigned char *buf0 = smem;
+    unsigned char *buf1 = smem + sb;
+
+    Views v;
+    if constexpr (CSR_LDS) {
+        int32_t *l_rp = reinterpret_cast<int32_t *>(smem + 2 * sb);
+        int32_t *l_h = l_rp + n4 + 4;
+        float *l_lam = reinterpret_cast<float *>(l_h + n4);
+        float *l_dlt = l_lam + n4;
+        uint32_t *l_thr = reinterpret_cast<uint32_t *>(l_dlt + n4);
+        int32_t *l_ord = reinterpret_cast<int32_t *>(l_thr + n4);
+        unsigned char *l_edges = reinterpret_cast<unsigned char *>(l_ord + (tasks + 3) / 4 * 4);
+        for (int32_t i = threadIdx.x; i < n4 + 4; i += BLOCK) l_rp[i] = a.row_ptr[i];
+        for (int32_t i = threadIdx.x; i < n4; i += BLOCK) {
+            l_h[i] = a.h[i];
+            l_lam[i] = a.lam[i];
+            l_dlt[i] = a.dlt[i];
+            l_thr[i] = a.thr[i];
+        }
+        for (int32_t i = threadIdx.x; i < tasks; i += BLOCK) l_ord[i] = a.order[i];
+        if constexpr (CSR == kCsrUnit || CSR == kCsrPack16) {
+            const uint16_t *src = CSR == kCsrUnit ? a.ux16 : a.pk16;
+            uint16_t *c = reinterpret_cast<uint16_t *>(l_edges);
+            for (int32_t e = threadIdx.x; e < a.nnz; e += BLOCK) c[e] = src[e];
+            v.ux16 = c;
+            v.pk16 = c;
+        } else if constexpr (CSR == kCsrPack32) {
+            uint32_t *c = reinterpret_cast<uint32_t *>(l_edges);
+            for (int32_t e = threadIdx.x; e < a.nnz; e += BLOCK) c[e] = a.pk32[e];
+            v.pk32 = c;
+        } else {
+            int32_t *c = reinterpret_cast<int32_t *>(l_edges);
+            int32_t *w = c + a.nnz;
+            for (int32_t e = threadIdx.x; e < a.nnz; e += BLOCK) {
+                c[e] = a.col[e];
+                w[e] = a.val[e];
+            }
+            v.col = c;
+            v.val = w;
+        }
+        v.row_ptr = l_rp;
+        v.h = l_h;
+        v.lam = l_lam;
+        v.dlt = l_dlt;
+        v.thr = l_thr;
+        v.order = l_ord;
+    } else {
+        v.row_ptr = a.row_ptr;
+        v.h = a.h;
+        v.lam = a.lam;
+        v.dlt = a.dlt;
+        v.thr = a.thr;
+        v.order = a.order;
+        v.col = a.col;
+        v.val = a.val;
+        v.pk32 = a.pk32;
+        v.pk16 = a.pk16;
+        v.ux16 = a.ux16;
+    }
+
+    // spins of this workgroup's trials -> LDS (padding p-bits = +1)
+    if constexpr (TPW == 1) {
+        for (int32_t i = threadIdx.x; i < n4; i += BLOCK) {
+            const int8_t s = i < n ? a.spins[static_cast<size_t>(i) * a.t4 + q] : int8_t(1);
+            if constexpr (E::kU) {
+                const unsigned char u = s > 0 ? 1 : 0;
+                buf0[i] = u;
+                if constexpr (E::kMirror) buf0[n4 + i] = u ^ 1u;
+            } else {
+                buf0[i] = static_cast<unsigned char>(s);
+            }
+        }
+    } else {
+        uint32_t *s0 = reinterpret_cast<uint32_t *>(buf0);
+        for (int32_t i = threadIdx.x; i < n4; i += BLOCK) {
+            const uint32_t w = i < n ? *reinterpret_cast<const uint32_t *>(
+                                           a.spins + static_cast<size_t>(i) * a.t4 + 4 * q)
+                                     : 0x01010101u;
+            s0[i] = E::kU ? ((~w >> 7) & 0x01010101u) : w;
+        }
+    }
+    __syncthreads();
+
+    unsigned char *cur = buf0;
+    unsigned char *nxt = buf1;
+    for (int32_t t = a.t_begin; t < a.t_end; ++t) {
+        const float i0t = a.i0[t];
+        if constexpr (TPW == 1) {
+            // the LPT lanes of a task share its slot, so they enter and leave together
+            const uint32_t sub = threadIdx.x % LPT;
+            for (int32_t slot = threadIdx.x / LPT; slot < tasks; slot += BLOCK / LPT) {
+                const int32_t m = v.order[slot];
+                const uint32_t b = task_one_trial<CSR, LPT>(v, m, sub, static_cast<uint32_t>(q),
+                                                            static_cast<uint32_t>(t), i0t, cur,
+                                                            a.k0, a.k1);
+                constexpr int P = 4 / LPT;
+                const int32_t at = 4 * m + static_cast<int32_t>(sub) * P;
+                if constexpr (P == 4) {
+                    *reinterpret_cast<uint32_t *>(nxt + at) = b;
+                    if constexpr (E::kMirror)
+                        *reinterpret_cast<uint32_t *>(nxt + n4 + at) = b ^ 0x01010101u;
+                } else if constexpr (P == 2) {
+                    *reinterpret_cast<uint16_t *>(nxt + at) = static_cast<uint16_t>(b);
+                    if constexpr (E::kMirror)
+                        *reinterpret_cast<uint16_t *>(nxt + n4 + at) =
+                            static_cast<uint16_t>(b ^ 0x0101u);
+                } else {
+                    nxt[at] = static_cast<unsigned char>(b);
+                    if constexpr (E::kMirror) nxt[n4 + at] = static_cast<unsigned char>(b ^ 1u);
+                }
+            }
+        } else {
+            for (int32_t slot = threadIdx.x; slot < tasks; slot += BLOCK)
+                task_four_trials<CSR>(v, v.order[slot], q, static_cast<uint32_t>(t), i0t,
+                                      reinterpret_cast<const uint32_t *>(cur),
+                                      reinterpret_cast<uint32_t *>(nxt), a.k0, a.k1);
+        }
+        __syncthreads();
+        unsigned char *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+
+    if constexpr (TPW == 1) {
+        for (int32_t i = threadIdx.x; i < n; i += BLOCK) {
+            int8_t s;
+            if constexpr (E::kU)
+                s = cur[i] ? int8_t(1) : int8_t(-1);
+            else
+                s = static_cast<int8_t>(cur[i]);
+            a.spins[static_cast<size_t>(i) * a.t4 + q] = s;
+        }
+    } else {
+        const uint32_t *s = reinterpret_cast<const uint32_t *>(cur);
+        for (int32_t i = threadIdx.x; i < n; i += BLOCK) {
+            uint32_t w = s[i];
+            if constexpr (E::kU) w = ((w ^ 0x01010101u) * 0xFEu) ^ 0x01010101u;
+            *reinterpret_cast<uint32_t *>(a.spins + static_cast<size_t>(i) * a.t4 + 4 * q) = w;
+        }
+    }
+}
+
+template <int TPW, int LPT, int CSR, bool CSR_LDS, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void anneal_kernel(AnnealArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    anneal_body<TPW, LPT, CSR, CSR_LDS, BLOCK>(a, static_cast<int32_t>(blockIdx.x), smem);
+}
+
+// ---------------------------------------------------------------------------
+// Batched launch: one grid over the work items of many runs.  Work item b is
+// (run jobs[work[b].x], trial group work[b].y); each run carries its own
+// graph, factors, spins and step range, and names its kernel variant.  All
+// variants share one launch (dynamic LDS = the largest any item needs).
+// ---------------------------------------------------------------------------
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void anneal_batch_kernel(const BatchJob *__restrict__ jobs,
+                                                             const int2 *__restrict__ work) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 w = work[blockIdx.x];
+    if (w.x < 0) return;  // padding slot of the XCD-aware work list
+    const BatchJob &job = jobs[w.x];
+    const AnnealArgs a = job.a;
+    switch (job.variant) {
+        case kBatchUnitLds2: anneal_body<1, 2, kCsrUnit, true, BLOCK>(a, w.y, smem); break;
+        case kBatchUnitGlb2: anneal_body<1, 2, kCsrUnit, false, BLOCK>(a, w.y, smem); break;
+        case kBatchUnitLds4: anneal_body<1, 4, kCsrUnit, true, BLOCK>(a, w.y, smem); break;
+        case kBatchUnitGlb4: anneal_body<1, 4, kCsrUnit, false, BLOCK>(a, w.y, smem); break;
+        case kBatchP32Lds2: anneal_body<1, 2, kCsrPack32, true, BLOCK>(a, w.y, smem); break;
+        case kBatchP32Glb2: anneal_body<1, 2, kCsrPack32, false, BLOCK>(a, w.y, smem); break;
+        case kBatchPairGlb2: anneal_body<1, 2, kCsrPair, false, BLOCK>(a, w.y, smem); break;
+        default: break;
+    }
+}
+
+template <int TPW, int LPT, int CSR, bool LDS, int BLOCK>
+hipError_t launch_variant(hipStream_t stream, const AnnealArgs &args, const AnnealPlan &plan) {
+    auto kern = anneal_kernel<TPW, LPT, CSR, LDS, BLOCK>;
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         static_cast<int>(plan.lds_bytes));
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(kern, dim3(plan.grid), dim3(BLOCK), plan.lds_bytes, stream, args);
+    return hipGetLastError();
+}
+
+template <int TPW, int LPT, int CSR, bool LDS>
+hipError_t launch_block(hipStream_t stream, const AnnealArgs &args, const AnnealPlan &plan) {
+    switch (plan.block) {
+        case 256: return launch_variant<TPW, LPT, CSR, LDS, 256>(stream, args, plan);
+        case 512: return launch_variant<TPW, LPT, CSR, LDS, 512>(stream, args, plan);
+        case 1024: return launch_variant<TPW, LPT, CSR, LDS, 1024>(stream, args, plan);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int TPW, int LPT, int CSR>
+hipError_t launch_lds(hipStream_t stream, const AnnealArgs &args, const AnnealPlan &plan) {
+    return plan.csr_lds ? launch_block<TPW, LPT, CSR, true>(stream, args, plan)
+                        : launch_block<TPW, LPT, CSR, false>(stream, args, plan);
+}
+
+template <int LPT>
+hipError_t launch_one_trial(hipStream_t stream, const AnnealArgs &args, const AnnealPlan &plan) {
+    switch (plan.csr) {
+        case kCsrPair: return launch_lds<1, LPT, kCsrPair>(stream, args, plan);
+        case kCsrPack32: return launch_lds<1, LPT, kCsrPack32>(stream, args, plan);
+        case kCsrUnit: return launch_lds<1, LPT, kCsrUnit>(stream, args, plan);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_four_trials(hipStream_t stream, const AnnealArgs &args, const AnnealPlan &plan) {
+    switch (plan.csr) {
+        case kCsrPair: return launch_lds<4, 1, kCsrPair>(stream, args, plan);
+        case kCsrPack32: return launch_lds<4, 1, kCsrPack32>(stream, args, plan);
+        case kCsrPack16: return launch_lds<4, 1, kCsrPack16>(stream, args, plan);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t lpt_req,
+                 int32_t block_req, size_t max_lds, int32_t num_cu, AnnealPlan *plan,
+                 std::string *why) {
+    AnnealPlan p;
+    const int32_t n4 = g.n4;
+    const int32_t tasks = n4 / 4;
+    if (tpw_req == 1 || tpw_req == 4) {
+        p.tpw = tpw_req;
+    } else {
+        // four trials per workgroup share each CSR walk; one trial per
+        // workgroup exposes four times the workgroups
+        p.tpw = (run.t4 / 4 >= num_cu) ? 4 : 1;
+    }
+    p.grid = p.tpw == 4 ? run.t4 / 4 : run.trials;
+    if (p.tpw == 4) {
+        p.csr = (g.pk16 && g.max_degree <= 255) ? kCsrPack16 : (g.pk32 ? kCsrPack32 : kCsrPair);
+        p.lpt = 1;
+    } else {
+        p.csr = g.ux16 ? kCsrUnit : (g.pk32 ? kCsrPack32 : kCsrPair);
+        if (lpt_req == 1 || lpt_req == 2 || lpt_req == 4)
+            p.lpt = lpt_req;
+        else  // spread tasks over more lanes while the workgroup has lanes to spare
+            p.lpt = tasks * 4 <= 1024 ? 4 : (tasks * 2 <= 1024 ? 2 : 1);
+    }
+    const size_t sp = 2 * spin_buf_bytes(n4, p.tpw, p.csr);
+    if (sp > max_lds) {
+        if (why)
+            *why = "n = " + std::to_string(g.n) + " does not fit the LDS-resident spin state (" +
+                   std::to_string(sp) + " > " + std::to_string(max_lds) + " bytes)";
+        return false;
+    }
+    const size_t full = sp + params_bytes(n4) + align16(static_cast<size_t>(g.nnz) * edge_bytes(p.csr));
+    p.csr_lds = full <= max_lds ? 1 : 0;
+    p.lds_bytes = p.csr_lds ? full : sp;
+    const int32_t lanes = tasks * p.lpt;
+    if (block_req == 256 || block_req == 512 || block_req == 1024)
+        p.block = block_req;
+    else
+        p.block = lanes > 512 ? 1024 : (lanes > 256 ? 512 : 256);
+    *plan = p;
+    return true;
+}
+
+void task_order(const DevGraph &g, const std::vector<int32_t> &row_ptr_host, const AnnealPlan &plan,
+                std::vector<int32_t> *order) {
+    const int32_t tasks = g.n4 / 4;
+    std::vector<int64_t> key(static_cast<size_t>(tasks));
+    for (int32_t m = 0; m < tasks; ++m) {
+        int64_t d[4];
+        for (int p = 0; p < 4; ++p) d[p] = row_ptr_host[4 * m + p + 1] - row_ptr_host[4 * m + p];
+        if (plan.tpw == 1 && plan.lpt == 2)
+            key[m] = std::max(d[0] + d[1], d[2] + d[3]);
+        else if (plan.tpw == 1 && plan.lpt == 4)
+            key[m] = std::max(std::max(d[0], d[1]), std::max(d[2], d[3]));
+        else
+            key[m] = d[0] + d[1] + d[2] + d[3];
+    }
+    order->resize(static_cast<size_t>(tasks));
+    for (int32_t m = 0; m < tasks; ++m) (*order)[m] = m;
+    // heaviest tasks first: lanes of a wavefront walk rows of similar length
+    std::stable_sort(order->begin(), order->end(),
+                     [&](int32_t x, int32_t y) { return key[x] > key[y]; });
+}
+
+hipError_t launch_anneal(hipStream_t stream, const DevGraph &g, const DevRun &run,
+                         const AnnealPlan &plan, const int32_t *order, int32_t t_begin,
+                         int32_t t_end) {
+    if (t_end <= t_begin) return hipSuccess;
+    AnnealArgs a;
+    fill_anneal_args(&a, g, run, order, t_begin, t_end);
+    if (plan.tpw == 4) return launch_four_trials(stream, a, plan);
+    switch (plan.lpt) {
+        case 1: return launch_one_trial<1>(stream, a, plan);
+        case 2: return launch_one_trial<2>(stream, a, plan);
+        case 4: return launch_one_trial<4>(stream, a, plan);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+void fill_anneal_args(AnnealArgs *a, const DevGraph &g, const DevRun &run, const int32_t *order,
+                      int32_t t_begin, int32_t t_end) {
+    a->n = g.n;
+    a->n4 = g.n4;
+    a->t4 = run.t4;
+    a->t_begin = t_begin;
+    a->t_end = t_end;
+    a->nnz = static_cast<int32_t>(g.nnz);
+    a->tasks = g.n4 / 4;
+    a->row_ptr = g.row_ptr;
+    a->col = g.col;
+    a->val = g.val;
+    a->pk32 = g.pk32;
+    a->pk16 = g.pk16;
+    a->ux16 = g.ux16;
+    a->h = g.h;
+    a->i0 = run.i0;
+    a->lam = run.lambda;
+    a->dlt = run.delta;
+    a->thr = run.thr24;
+    a->order = order;
+    a->k0 = run.key0;
+    a->k1 = run.key1;
+    a->spins = run.spins;
+}
+
+bool plan_batch_item(const DevGraph &g, const DevRun &run, int32_t lpt_req, size_t max_lds,
+                     AnnealPlan *plan, int32_t *variant, std::string *why) {
+    AnnealPlan p;
+    if (!plan_anneal(g, run, 1, lpt_req == 4 ? 4 : 2, 0, max_lds, 1 << 30, &p, why)) return false;
+    if (p.csr == kCsrUnit) {
+        *variant = p.lpt == 4 ? (p.csr_lds ? kBatchUnitLds4 : kBatchUnitGlb4)
+                              : (p.csr_lds ? kBatchUnitLds2 : kBatchUnitGlb2);
+    } else {
+        p.lpt = 2;
+        if (p.csr == kCsrPack32) {
+            *variant = p.csr_lds ? kBatchP32Lds2 : kBatchP32Glb2;
+        } else {
+            *variant = kBatchPairGlb2;
+            p.csr_lds = 0;
+            p.lds_bytes = 2 * spin_buf_bytes(g.n4, 1, kCsrPair);
+        }
+    }
+    *plan = p;
+    return true;
+}
+
+hipError_t launch_anneal_batch(hipStream_t stream, const BatchJob *jobs, const int2 *work,
+                               int32_t nwork, int32_t block, size_t lds_bytes) {
+    if (nwork <= 0) return hipSuccess;
+    const void *kern;
+    switch (block) {
+        case 256: kern = reinterpret_cast<const void *>(anneal_batch_kernel<256>); break;
+        case 512: kern = reinterpret_cast<const void *>(anneal_batch_kernel<512>); break;
+        case 1024: kern = reinterpret_cast<const void *>(anneal_batch_kernel<1024>); break;
+        default: return hipErrorInvalidValue;
+    }
+    hipError_t err = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         static_cast<int>(lds_bytes));
+    if (err != hipSuccess) return err;
+    switch (block) {
+        case 256:
+            hipLaunchKernelGGL(anneal_batch_kernel<256>, dim3(nwork), dim3(256), lds_bytes, stream, jobs, work);
+            break;
+        case 512:
+            hipLaunchKernelGGL(anneal_batch_kernel<512>, dim3(nwork), dim3(512), lds_bytes, stream, jobs, work);
+            break;
+        default:
+            hipLaunchKernelGGL(anneal_batch_kernel<1024>, dim3(nwork), dim3(1024), lds_bytes, stream, jobs, work);
+            break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace psa

@@ -1,0 +1,214 @@
+// batch.cpp -- many runs of uneven size in one launch.
+//
+// psa_jobs_step_batch advances a set of existing jobs by up to k steps each
+// with one launch of the batch kernel: a work list holds one item per
+// (job, trial); each workgroup reads its job's arguments from a device table
+// and runs the kernel variant that job needs.  Work items are placed so that
+// a job's workgroups land on one XCD (workgroups are dispatched to the eight
+// XCDs round-robin by index), heaviest jobs first.  psa_anneal_batch wraps it:
+// create the jobs, run them to the end, write energies, cuts and spins.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "engine.hpp"
+#include "psa.h"
+
+using psa::set_error;
+
+namespace {
+
+constexpr int kXcds = 8;
+constexpr int kChunk = 16;  // work items placed on one XCD together
+
+psa_status hip_fail(hipError_t err, const char *what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(err));
+    return PSA_EHIP;
+}
+
+#define PSA_HIP(expr, what)                               \
+    do {                                                  \
+        hipError_t _e = (expr);                           \
+        if (_e != hipSuccess) return hip_fail(_e, what);  \
+    } while (0)
+
+// Grow-only device buffer kept by the context between batched launches.
+psa_status ensure(void **buf, size_t *cap, size_t bytes) {
+    if (*cap >= bytes) return PSA_OK;
+    if (*buf) (void)hipFree(*buf);
+    *buf = nullptr;
+    *cap = 0;
+    if (hipMalloc(buf, bytes) != hipSuccess) {
+        *buf = nullptr;
+        set_error("batch: device allocation failed");
+        return PSA_ENOMEM;
+    }
+    *cap = bytes;
+    return PSA_OK;
+}
+
+}  // namespace
+
+namespace psa {
+
+// Build the XCD-aware work list for `jobs` (cost = trials * n4 * steps).
+void build_work_list(const std::vector<int32_t> &trials, const std::vector<double> &cost,
+                     std::vector<int2> *work) {
+    struct Chunk {
+        int32_t job, q0, q1;
+        double cost;
+    };
+    std::vector<Chunk> chunks;
+    for (size_t j = 0; j < trials.size(); ++j) {
+        const double per = trials[j] > 0 ? cost[j] / trials[j] : 0.0;
+        for (int32_t q = 0; q < trials[j]; q += kChunk) {
+            const int32_t q1 = std::min(trials[j], q + kChunk);
+            chunks.push_back(Chunk{static_cast<int32_t>(j), q, q1, per * (q1 - q)});
+        }
+    }
+    std::stable_sort(chunks.begin(), chunks.end(),
+                     [](const Chunk &a, const Chunk &b) { return a.cost > b.cost; });
+    std::vector<std::vector<int2>> queue(kXcds);
+    std::vector<double> load(kXcds, 0.0);
+    for (const Chunk &c : chunks) {
+        const int x = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+        for (int32_t q = c.q0; q < c.q1; ++q) queue[x].push_back(make_int2(c.job, q));
+        load[x] += c.cost;
+    }
+    size_t len = 0;
+    for (const auto &qu : queue) len = std::max(len, qu.size());
+    work->assign(len * kXcds, make_int2(-1, 0));
+    for (int x = 0; x < kXcds; ++x)
+        for (size_t s = 0; s < queue[x].size(); ++s) (*work)[s * kXcds + x] = queue[x][s];
+}
+
+}  // namespace psa
+
+extern "C" {
+
+psa_status psa_jobs_step_batch(psa_ctx *ctx, int32_t count, psa_job *const *jobs, int32_t k) {
+    if (!ctx || count < 0 || (count > 0 && !jobs) || k < 0) {
+        set_error("psa_jobs_step_batch: invalid arguments");
+        return PSA_EINVAL;
+    }
+    std::vector<psa::BatchJob> table;
+    std::vector<int32_t> trials;
+    std::vector<double> cost;
+    std::vector<int32_t> t_end;
+    size_t lds = 0;
+    int32_t max_lanes = 0;
+    for (int32_t j = 0; j < count; ++j) {
+        psa_job *job = jobs[j];
+        if (!job || job->ctx != ctx) {
+            set_error("psa_jobs_step_batch: job " + std::to_string(j) + " is NULL or belongs to "
+                      "another context");
+            return PSA_EINVAL;
+        }
+        for (int32_t i = 0; i < j; ++i)
+            if (jobs[i] == job) {
+                set_error("psa_jobs_step_batch: job listed twice");
+                return PSA_EINVAL;
+            }
+        const int32_t te = static_cast<int32_t>(
+            std::min<int64_t>(int64_t{job->t} + k, job->run.steps));
+        t_end.push_back(te);
+        if (te <= job->t) continue;
+        psa::AnnealPlan plan;
+        int32_t variant = 0;
+        std::string why;
+        if (!psa::plan_batch_item(job->g->dev, job->run, job->plan.tpw == 1 ? job->plan.lpt : 0,
+                                  ctx->max_lds, &plan, &variant, &why)) {
+            set_error("psa_jobs_step_batch: " + why);
+            return PSA_EUNSUPPORTED;
+        }
+        psa::BatchJob bj;
+        psa::fill_anneal_args(&bj.a, job->g->dev, job->run, job->d_order, job->t, te);
+        bj.variant = variant;
+        table.push_back(bj);
+        trials.push_back(job->run.trials);
+        cost.push_back(static_cast<double>(job->run.trials) * job->g->dev.n4 * (te - job->t));
+        lds = std::max(lds, plan.lds_bytes);
+        max_lanes = std::max(max_lanes, job->g->dev.n4 / 4 * plan.lpt);
+    }
+    if (table.empty()) return PSA_OK;
+    std::vector<int2> work;
+    psa::build_work_list(trials, cost, &work);
+    PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    // the staging buffers are reused: the previous batched launch must be done
+    PSA_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    psa_status st;
+    if ((st = ensure(&ctx->d_batch_table, &ctx->batch_table_cap,
+                     table.size() * sizeof(psa::BatchJob))) != PSA_OK)
+        return st;
+    if ((st = ensure(&ctx->d_batch_work, &ctx->batch_work_cap, work.size() * sizeof(int2))) != PSA_OK)
+        return st;
+    ctx->h_batch_table = table;
+    ctx->h_batch_work = work;
+    PSA_HIP(hipMemcpyAsync(ctx->d_batch_table, ctx->h_batch_table.data(),
+                           table.size() * sizeof(psa::BatchJob), hipMemcpyHostToDevice, ctx->stream),
+            "batch table upload");
+    PSA_HIP(hipMemcpyAsync(ctx->d_batch_work, ctx->h_batch_work.data(), work.size() * sizeof(int2),
+                           hipMemcpyHostToDevice, ctx->stream),
+            "batch work upload");
+    const int32_t block = max_lanes > 1024 ? 1024 : (max_lanes > 256 ? 512 : 256);
+    PSA_HIP(psa::launch_anneal_batch(ctx->stream, static_cast<const psa::BatchJob *>(ctx->d_batch_table),
+                                     static_cast<const int2 *>(ctx->d_batch_work),
+                                     static_cast<int32_t>(work.size()), block, lds),
+            "batch anneal launch");
+    for (int32_t j = 0; j < count; ++j) jobs[j]->t = std::max(jobs[j]->t, t_end[j]);
+    return PSA_OK;
+}
+
+psa_status psa_anneal_batch(psa_ctx *ctx, int32_t count, const psa_batch_item *items,
+                            uint32_t flags) {
+    if (!ctx || count < 0 || (count > 0 && !items) ||
+        (flags & ~(PSA_OUT_DEVICE | PSA_BATCH_SEQUENTIAL)) != 0) {
+        set_error("psa_anneal_batch: invalid arguments");
+        return PSA_EINVAL;
+    }
+    for (int32_t j = 0; j < count; ++j)
+        if (!items[j].graph || !items[j].energy_out || !items[j].cut_out) {
+            set_error("psa_anneal_batch: item " + std::to_string(j) +
+                      " needs a graph, energy_out and cut_out");
+            return PSA_EINVAL;
+        }
+    std::vector<std::unique_ptr<psa_job, void (*)(psa_job *)>> owned;
+    std::vector<psa_job *> jobs;
+    int32_t max_steps = 0;
+    for (int32_t j = 0; j < count; ++j) {
+        psa_run_desc d = items[j].desc;
+        if (!(flags & PSA_BATCH_SEQUENTIAL)) d.trials_per_group = 1;
+        psa_job *job = nullptr;
+        psa_status st = psa_job_create(ctx, items[j].graph, &d, &job);
+        if (st != PSA_OK) {
+            set_error("psa_anneal_batch: item " + std::to_string(j) + ": " + psa_last_error());
+            return st;
+        }
+        owned.emplace_back(job, psa_job_destroy);
+        jobs.push_back(job);
+        max_steps = std::max(max_steps, d.steps);
+    }
+    psa_status st;
+    if (flags & PSA_BATCH_SEQUENTIAL) {
+        for (psa_job *job : jobs)
+            if ((st = psa_job_step(job, job->run.steps)) != PSA_OK) return st;
+    } else {
+        if ((st = psa_jobs_step_batch(ctx, count, jobs.data(), max_steps)) != PSA_OK) return st;
+    }
+    const uint32_t out = flags & PSA_OUT_DEVICE;
+    for (int32_t j = 0; j < count; ++j) {
+        if ((st = psa_job_energy_cut(jobs[j], items[j].energy_out, items[j].cut_out, out)) != PSA_OK)
+            return st;
+        if (items[j].spins_out &&
+            (st = psa_job_read_spins(jobs[j], items[j].spins_out, out)) != PSA_OK)
+            return st;
+    }
+    PSA_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    return PSA_OK;
+}
+
+}  // extern "C"

@@ -22,19 +22,24 @@ void set_error(const std::string &msg);
 void clear_error();
 
 // Device copy of a graph in CSR form.  Row i holds its neighbours j in
-// increasing order with their couplings J_ij; h is never null (zeros).
-// Packed copies of the same entries, when the graph allows them:
-//   pk32[e] = col | J << 16           (n <= 65536, |J| < 2^15)
-//   pk16[e] = col << 1 | (J < 0)      (every |J| == 1, n <= 32768)
+// increasing order with their couplings J_ij.  Per-p-bit arrays are padded to
+// n4 = 4 ceil(n/4) entries (h = 0) and row_ptr to n4 + 4 entries (padding rows
+// are empty).  Packed copies of the edges, when the graph allows them:
+//   pk32[e] = col | J << 16              (n <= 65536, |J| < 2^15)
+//   pk16[e] = col << 1 | (J < 0)         (every |J| == 1, n <= 32768)
+//   ux16[e] = col + (J < 0 ? n4 : 0)     (every |J| == 1, 2 n4 <= 65536)
 struct DevGraph {
     int32_t n = 0;
+    int32_t n4 = 0;
     int64_t nnz = 0;
-    const int32_t *row_ptr = nullptr;  // [n+1]
+    int32_t max_degree = 0;
+    const int32_t *row_ptr = nullptr;  // [n4+4]
     const int32_t *col = nullptr;      // [nnz]
     const int32_t *val = nullptr;      // [nnz]
     const uint32_t *pk32 = nullptr;    // [nnz] or null
     const uint16_t *pk16 = nullptr;    // [nnz] or null
-    const int32_t *h = nullptr;        // [n]
+    const uint16_t *ux16 = nullptr;    // [nnz] or null
+    const int32_t *h = nullptr;        // [n4]
     int64_t w2 = 0;                    // sum_i sum_j J_ij = 2 sum_{i<j} J_ij
 };
 
@@ -47,14 +52,14 @@ struct DevRun {
     int32_t steps = 0;
     uint32_t key0 = 0, key1 = 0;          // Philox key = 64-bit seed
     const float *i0 = nullptr;            // [steps]
-    const float *lambda = nullptr;        // [n]
-    const float *delta = nullptr;         // [n]
-    const uint32_t *thr24 = nullptr;      // [n]
+    const float *lambda = nullptr;        // [n4]
+    const float *delta = nullptr;         // [n4]
+    const uint32_t *thr24 = nullptr;      // [n4] (padding p-bits: 0, never fire)
     int8_t *spins = nullptr;              // [n][t4]
 };
 
 // How the persistent anneal kernel is launched for one run.
-enum CsrKind : int32_t { kCsrPair = 0, kCsrPack32 = 1, kCsrPack16 = 2 };
+enum CsrKind : int32_t { kCsrPair = 0, kCsrPack32 = 1, kCsrPack16 = 2, kCsrUnit = 3 };
 struct AnnealPlan {
     int32_t tpw = 1;          // trials per workgroup: 1 or 4
     int32_t lpt = 1;          // lanes per 4-p-bit task (tpw == 1): 1, 2 or 4
@@ -65,6 +70,42 @@ struct AnnealPlan {
     size_t lds_bytes = 0;     // dynamic LDS per workgroup
 };
 
+// Arguments of one run as the anneal kernels read them.
+struct AnnealArgs {
+    int32_t n, n4, t4, t_begin, t_end, nnz, tasks;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const int32_t *val;
+    const uint32_t *pk32;
+    const uint16_t *pk16;
+    const uint16_t *ux16;
+    const int32_t *h;
+    const float *i0;
+    const float *lam;
+    const float *dlt;
+    const uint32_t *thr;
+    const int32_t *order;
+    uint32_t k0, k1;
+    int8_t *spins;
+};
+
+// Kernel variants a batched launch can mix (one trial per workgroup).
+enum BatchVariant : int32_t {
+    kBatchUnitLds2 = 0,
+    kBatchUnitGlb2 = 1,
+    kBatchUnitLds4 = 2,
+    kBatchUnitGlb4 = 3,
+    kBatchP32Lds2 = 4,
+    kBatchP32Glb2 = 5,
+    kBatchPairGlb2 = 6,
+};
+
+// One run of a batched launch, as stored in the device job table.
+struct BatchJob {
+    AnnealArgs a;
+    int32_t variant;
+};
+
 // Choose tpw / lanes per task / CSR placement / block for a run
 // (tpw_req, lpt_req, block_req: 0 = automatic).  Returns false with a reason if n does not fit in LDS.
 bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t lpt_req,
@@ -73,8 +114,23 @@ bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t 
 
 // Kernel launchers (kernels.hip).  All are asynchronous on `stream`.
 hipError_t launch_init_spins(hipStream_t stream, int32_t n, const DevRun &run);
+// Order in which a workgroup visits the tasks (groups of 4 p-bits): heaviest
+// rows first, so that the lanes of a wavefront walk rows of similar length.
+void task_order(const DevGraph &g, const std::vector<int32_t> &row_ptr_host,
+                const AnnealPlan &plan, std::vector<int32_t> *order);
 hipError_t launch_anneal(hipStream_t stream, const DevGraph &g, const DevRun &run,
-                         const AnnealPlan &plan, int32_t t_begin, int32_t t_end);
+                         const AnnealPlan &plan, const int32_t *order, int32_t t_begin,
+                         int32_t t_end);
+void fill_anneal_args(AnnealArgs *a, const DevGraph &g, const DevRun &run, const int32_t *order,
+                      int32_t t_begin, int32_t t_end);
+// Plan of one run inside a batched launch (one trial per workgroup); sets
+// the variant the batch kernel dispatches to.
+bool plan_batch_item(const DevGraph &g, const DevRun &run, int32_t lpt_req, size_t max_lds,
+                     AnnealPlan *plan, int32_t *variant, std::string *why);
+// One launch over a work list: work[b] = (index into jobs, trial), or
+// (-1, 0) for an empty slot.
+hipError_t launch_anneal_batch(hipStream_t stream, const BatchJob *jobs, const int2 *work,
+                               int32_t nwork, int32_t block, size_t lds_bytes);
 hipError_t launch_local_field(hipStream_t stream, const DevGraph &g,
                               const DevRun &run, int32_t *out_tn);
 hipError_t launch_energy_cut(hipStream_t stream, const DevGraph &g,
@@ -92,6 +148,30 @@ psa_status draw_variability(int32_t n, uint64_t seed, double sigma_lambda,
                             double sigma_delta, double sigma_nu, double p_mean,
                             float *lambda, float *delta, uint32_t *thr24);
 
+// Graph ingestion (graph.cpp): CPU phase, then device upload.
+struct HostGraph {
+    psa_graph_info info{};
+    int32_t n = 0, n4 = 0, max_degree = 0;
+    int64_t nnz = 0, w2 = 0;
+    std::vector<int32_t> rp32;  // [n4+4]
+    std::vector<int32_t> col, val;
+    std::vector<int32_t> h;     // [n4]
+    std::vector<uint32_t> pk32;
+    std::vector<uint16_t> pk16, ux16;
+};
+psa_status host_graph_from_edges(int32_t n, int64_t m, const int32_t *u, const int32_t *v,
+                                 const int32_t *val, const int32_t *h, uint32_t flags,
+                                 HostGraph *out);
+psa_status host_graph_from_csr(int32_t n, const int64_t *row_ptr, const int32_t *col,
+                               const int32_t *val, const int32_t *h, uint32_t flags,
+                               HostGraph *out);
+psa_status upload_graph(psa_ctx *ctx, HostGraph &&hg, psa_graph **out);
+void graph_release(psa_graph *g);
+
+// XCD-aware work list of a batched launch (batch.cpp).
+void build_work_list(const std::vector<int32_t> &trials, const std::vector<double> &cost,
+                     std::vector<int2> *work);
+
 }  // namespace psa
 
 struct psa_ctx {
@@ -100,6 +180,11 @@ struct psa_ctx {
     bool own_stream = false;
     int32_t num_cu = 0;
     size_t max_lds = 0;
+    // staging of batched launches (grow-only; reused after a stream sync)
+    void *d_batch_table = nullptr, *d_batch_work = nullptr;
+    size_t batch_table_cap = 0, batch_work_cap = 0;
+    std::vector<psa::BatchJob> h_batch_table;
+    std::vector<int2> h_batch_work;
 };
 
 struct psa_graph {
@@ -109,7 +194,8 @@ struct psa_graph {
     // owning device pointers
     int32_t *d_row_ptr = nullptr, *d_col = nullptr, *d_val = nullptr, *d_h = nullptr;
     uint32_t *d_pk32 = nullptr;
-    uint16_t *d_pk16 = nullptr;
+    uint16_t *d_pk16 = nullptr, *d_ux16 = nullptr;
+    std::vector<int32_t> row_ptr_host;  // [n4+4]
 };
 
 struct psa_job {
@@ -118,6 +204,7 @@ struct psa_job {
     psa::DevRun run;
     int32_t t = 0;       // steps applied so far
     psa::AnnealPlan plan;
+    int32_t *d_order = nullptr;  // [n4/4] task visiting order
     // owning device pointers
     float *d_i0 = nullptr, *d_lambda = nullptr, *d_delta = nullptr;
     uint32_t *d_thr24 = nullptr;

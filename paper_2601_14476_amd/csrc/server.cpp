@@ -1,0 +1,479 @@
+// server.cpp -- serving loop with continuous batching.
+//
+// A scheduler thread owns the device work of the server's context.  Clients
+// submit anneal jobs (edge list + run description + output buffers) from any
+// thread.  Between step quanta the scheduler
+//   1. retires jobs that reached the end of their schedule (energy, cut and
+//      optional spins into the client's buffers, device memory released),
+//   2. admits waiting jobs first-come first-served while their HBM footprint
+//      fits the budget and a resident slot is free (graph upload, job
+//      creation and initial spins happen here; the CPU part of ingestion --
+//      validation, CSR, packed encodings -- has already been done by a pool
+//      of preparation threads, so it never stalls the device),
+//   3. advances every resident job by one quantum of steps with a single
+//      batched launch, so requests that arrive while others run join the
+//      next launch.
+// Results are identical to running each job alone: every random word is
+// addressed by (seed, step, p-bit, trial) and each job's spins and step
+// counter stay resident between quanta.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "engine.hpp"
+#include "psa.h"
+
+using psa::set_error;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct ServerJob {
+    uint64_t ticket = 0;
+    // request (host copies)
+    int32_t n = 0;
+    std::vector<int32_t> u, v, val, h;
+    uint32_t graph_flags = 0;
+    psa_run_desc desc{};
+    std::vector<float> i0, lambda, delta;
+    std::vector<uint32_t> thr24;
+    int64_t *energy_out = nullptr;
+    int64_t *cut_out = nullptr;
+    int8_t *spins_out = nullptr;
+    psa::HostGraph hg;     // filled by a preparation thread
+    bool prepared = false;
+    // state
+    int32_t status = PSA_JOB_QUEUED;
+    int32_t error = PSA_OK;
+    std::string message;
+    bool cancel = false;
+    size_t footprint = 0;
+    psa_graph *graph = nullptr;
+    psa_job *job = nullptr;
+    int64_t submit_us = 0, admit_us = -1, end_us = -1;
+};
+
+// Device bytes a job holds while resident (graph in all encodings, run
+// arrays, spins, read-out staging).
+size_t footprint_of(int32_t n, int64_t m, int32_t trials, int32_t steps) {
+    const size_t n4 = static_cast<size_t>((n + 3) / 4 * 4);
+    const size_t nnz = static_cast<size_t>(2 * m);
+    const size_t t4 = static_cast<size_t>((trials + 3) / 4 * 4);
+    const size_t graph = (n4 + 4) * 4 + nnz * (4 + 4 + 4 + 2 + 2) + n4 * 4;
+    const size_t run = static_cast<size_t>(steps) * 4 + n4 * 12 + n4 + n4 * t4;
+    const size_t staging = std::max(static_cast<size_t>(n) * trials * 4, static_cast<size_t>(trials) * 16);
+    return graph + run + staging + 8 * 256;  // allocation granularity slack
+}
+
+}  // namespace
+
+struct psa_server {
+    psa_ctx *ctx = nullptr;
+    psa_server_opts opts{};
+    Clock::time_point t0;
+    std::mutex mu;
+    std::condition_variable cv_work;  // submissions, cancels, shutdown
+    std::condition_variable cv_done;  // job completions
+    std::condition_variable cv_prep;  // jobs to prepare
+    std::deque<ServerJob *> to_prepare;
+    std::vector<std::thread> preparers;
+    std::deque<ServerJob *> waiting;  // submit order; admitted once prepared
+    std::vector<ServerJob *> resident;
+    std::unordered_map<uint64_t, std::unique_ptr<ServerJob>> jobs;
+    uint64_t next_ticket = 1;
+    size_t used_bytes = 0;
+    int64_t completed = 0, failed = 0, canceled = 0, quanta = 0;
+    bool stop = false;
+    std::thread worker;
+
+    int64_t now_us() const {
+        return std::chrono::duration_cast<std::chrono::microseconds>(Clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+void release_device(ServerJob *j) {
+    if (j->job) psa_job_destroy(j->job);
+    if (j->graph) psa_graph_destroy(j->graph);
+    j->job = nullptr;
+    j->graph = nullptr;
+}
+
+// CPU part of graph ingestion, on a preparation thread.
+void preparer(psa_server *s) {
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        s->cv_prep.wait(lk, [s] { return s->stop || !s->to_prepare.empty(); });
+        if (s->to_prepare.empty()) return;  // stopping
+        ServerJob *j = s->to_prepare.front();
+        s->to_prepare.pop_front();
+        lk.unlock();
+        psa::HostGraph hg;
+        const psa_status st = psa::host_graph_from_edges(
+            j->n, static_cast<int64_t>(j->u.size()), j->u.data(), j->v.data(), j->val.data(),
+            j->h.empty() ? nullptr : j->h.data(), j->graph_flags, &hg);
+        std::string msg = st == PSA_OK ? "" : psa_last_error();
+        lk.lock();
+        j->prepared = true;
+        if (st == PSA_OK) {
+            j->hg = std::move(hg);
+        } else {
+            j->error = st;
+            j->message = msg;
+        }
+        s->cv_work.notify_one();
+    }
+}
+
+// Upload the graph and create the job on the device (called without the lock).
+psa_status admit_job(psa_server *s, ServerJob *j) {
+    psa_status st = psa::upload_graph(s->ctx, std::move(j->hg), &j->graph);
+    if (st != PSA_OK) return st;
+    psa_run_desc d = j->desc;
+    d.i0 = j->i0.empty() ? nullptr : j->i0.data();
+    d.lambda = j->lambda.empty() ? nullptr : j->lambda.data();
+    d.delta = j->delta.empty() ? nullptr : j->delta.data();
+    d.thr24 = j->thr24.empty() ? nullptr : j->thr24.data();
+    d.trials_per_group = 1;
+    return psa_job_create(s->ctx, j->graph, &d, &j->job);
+}
+
+// Results into the client's buffers (called without the lock).
+psa_status finish_job(ServerJob *j) {
+    psa_status st = psa_job_energy_cut(j->job, j->energy_out, j->cut_out, PSA_OUT_HOST);
+    if (st == PSA_OK && j->spins_out) st = psa_job_read_spins(j->job, j->spins_out, PSA_OUT_HOST);
+    return st;
+}
+
+void scheduler(psa_server *s) {
+    (void)hipSetDevice(s->ctx->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        // drop prepared jobs that were canceled or failed preparation
+        for (auto it = s->waiting.begin(); it != s->waiting.end();) {
+            ServerJob *j = *it;
+            if (j->prepared && (j->cancel || j->error != PSA_OK)) {
+                if (j->cancel) {
+                    j->status = PSA_JOB_CANCELED;
+                    ++s->canceled;
+                } else {
+                    j->status = PSA_JOB_ERROR;
+                    ++s->failed;
+                }
+                j->end_us = s->now_us();
+                it = s->waiting.erase(it);
+                s->cv_done.notify_all();
+            } else {
+                ++it;
+            }
+        }
+        // admission: first come first served among prepared jobs, by
+        // footprint and slot cap
+        while (!s->stop && static_cast<int32_t>(s->resident.size()) < s->opts.max_resident) {
+            auto it = std::find_if(s->waiting.begin(), s->waiting.end(),
+                                   [](const ServerJob *x) { return x->prepared; });
+            if (it == s->waiting.end()) break;
+            ServerJob *j = *it;
+            if (s->used_bytes + j->footprint > static_cast<size_t>(s->opts.hbm_budget_bytes)) {
+                if (!s->resident.empty()) break;  // wait for memory to free up
+                // alone it cannot fit: reject
+                s->waiting.erase(it);
+                j->status = PSA_JOB_ERROR;
+                j->error = PSA_ENOMEM;
+                j->message = "job footprint exceeds the server's HBM budget";
+                j->end_us = s->now_us();
+                ++s->failed;
+                s->cv_done.notify_all();
+                continue;
+            }
+            s->waiting.erase(it);
+            s->used_bytes += j->footprint;
+            j->admit_us = s->now_us();
+            lk.unlock();
+            const psa_status st = admit_job(s, j);
+            std::string msg = st == PSA_OK ? "" : psa_last_error();
+            lk.lock();
+            if (st != PSA_OK) {
+                release_device(j);
+                s->used_bytes -= j->footprint;
+                j->status = PSA_JOB_ERROR;
+                j->error = st;
+                j->message = msg;
+                j->end_us = s->now_us();
+                ++s->failed;
+                s->cv_done.notify_all();
+                continue;
+            }
+            j->status = PSA_JOB_RUNNING;
+            s->resident.push_back(j);
+        }
+        if (s->resident.empty()) {
+            if (s->stop) break;
+            s->cv_work.wait(lk, [s] {
+                if (s->stop) return true;
+                for (const ServerJob *x : s->waiting)
+                    if (x->prepared) return true;
+                return false;
+            });
+            continue;
+        }
+        // one quantum over every resident job
+        std::vector<ServerJob *> batch = s->resident;
+        std::vector<psa_job *> handles;
+        for (ServerJob *j : batch) handles.push_back(j->job);
+        const int32_t quantum = s->opts.quantum_steps;
+        lk.unlock();
+        psa_status st = psa_jobs_step_batch(s->ctx, static_cast<int32_t>(handles.size()),
+                                            handles.data(), quantum);
+        if (st == PSA_OK) st = psa_ctx_synchronize(s->ctx);
+        std::string qmsg = st == PSA_OK ? "" : psa_last_error();
+        // retire finished (or failed / canceled) jobs
+        std::vector<std::pair<ServerJob *, psa_status>> retired;
+        for (ServerJob *j : batch) {
+            int32_t t = 0;
+            psa_job_position(j->job, &t);
+            bool cancel;
+            {
+                std::lock_guard<std::mutex> g(s->mu);
+                cancel = j->cancel;
+            }
+            if (st != PSA_OK) {
+                retired.emplace_back(j, st);
+            } else if (cancel) {
+                retired.emplace_back(j, PSA_ECANCELED);
+            } else if (t >= j->desc.steps) {
+                const psa_status fs = finish_job(j);
+                if (fs != PSA_OK) qmsg = psa_last_error();
+                retired.emplace_back(j, fs);
+            }
+        }
+        for (auto &r : retired) release_device(r.first);
+        lk.lock();
+        ++s->quanta;
+        for (auto &r : retired) {
+            ServerJob *j = r.first;
+            s->resident.erase(std::find(s->resident.begin(), s->resident.end(), j));
+            s->used_bytes -= j->footprint;
+            j->end_us = s->now_us();
+            if (r.second == PSA_OK) {
+                j->status = PSA_JOB_DONE;
+                ++s->completed;
+            } else if (r.second == PSA_ECANCELED) {
+                j->status = PSA_JOB_CANCELED;
+                ++s->canceled;
+            } else {
+                j->status = PSA_JOB_ERROR;
+                j->error = r.second;
+                j->message = qmsg;
+                ++s->failed;
+            }
+        }
+        if (!retired.empty()) s->cv_done.notify_all();
+        if (s->stop && s->waiting.empty() && s->resident.empty()) break;
+    }
+    // shutdown: whatever is still queued is canceled
+    for (ServerJob *j : s->waiting) {
+        j->status = PSA_JOB_CANCELED;
+        j->end_us = s->now_us();
+        ++s->canceled;
+    }
+    s->waiting.clear();
+    s->cv_done.notify_all();
+}
+
+void fill_result(const ServerJob *j, psa_result *out) {
+    out->status = j->status;
+    out->error = j->error;
+    out->submit_us = j->submit_us;
+    out->admit_us = j->admit_us;
+    out->end_us = j->end_us;
+}
+
+}  // namespace
+
+extern "C" {
+
+psa_status psa_server_create(psa_ctx *ctx, const psa_server_opts *opts, psa_server **out) {
+    if (!ctx || !out) {
+        set_error("psa_server_create: NULL argument");
+        return PSA_EINVAL;
+    }
+    psa_server_opts o{};
+    if (opts) o = *opts;
+    if (o.hbm_budget_bytes <= 0) {
+        size_t free_b = 0, total_b = 0;
+        (void)hipSetDevice(ctx->device);
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = size_t{1} << 32;
+        o.hbm_budget_bytes = static_cast<int64_t>(free_b / 2);
+    }
+    if (o.max_resident <= 0) o.max_resident = 64;
+    if (o.quantum_steps <= 0) o.quantum_steps = 250;
+    std::unique_ptr<psa_server> s(new psa_server());
+    s->ctx = ctx;
+    s->opts = o;
+    s->t0 = Clock::now();
+    s->worker = std::thread(scheduler, s.get());
+    const unsigned hw = std::max(2u, std::thread::hardware_concurrency());
+    for (unsigned k = 0; k < std::min(8u, hw / 2); ++k) s->preparers.emplace_back(preparer, s.get());
+    *out = s.release();
+    return PSA_OK;
+}
+
+psa_status psa_server_submit(psa_server *s, int32_t n, int64_t m, const int32_t *u,
+                             const int32_t *v, const int32_t *val, const int32_t *h,
+                             uint32_t graph_flags, const psa_run_desc *desc, int64_t *energy_out,
+                             int64_t *cut_out, int8_t *spins_out, uint64_t *ticket) {
+    if (!s || !desc || !energy_out || !cut_out || !ticket || n < 1 || m < 0 ||
+        (m > 0 && (!u || !v || !val)) || desc->steps < 1 || desc->trials < 1) {
+        set_error("psa_server_submit: invalid arguments");
+        return PSA_EINVAL;
+    }
+    std::unique_ptr<ServerJob> j(new ServerJob());
+    j->n = n;
+    j->u.assign(u, u + m);
+    j->v.assign(v, v + m);
+    j->val.assign(val, val + m);
+    if (h) j->h.assign(h, h + n);
+    j->graph_flags = graph_flags;
+    j->desc = *desc;
+    if (desc->i0) j->i0.assign(desc->i0, desc->i0 + desc->steps);
+    if (desc->lambda) j->lambda.assign(desc->lambda, desc->lambda + n);
+    if (desc->delta) j->delta.assign(desc->delta, desc->delta + n);
+    if (desc->thr24) j->thr24.assign(desc->thr24, desc->thr24 + n);
+    j->energy_out = energy_out;
+    j->cut_out = cut_out;
+    j->spins_out = spins_out;
+    j->footprint = footprint_of(n, m, desc->trials, desc->steps);
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->stop) {
+        set_error("psa_server_submit: server is shutting down");
+        return PSA_ECANCELED;
+    }
+    j->ticket = s->next_ticket++;
+    j->submit_us = s->now_us();
+    *ticket = j->ticket;
+    s->waiting.push_back(j.get());
+    s->to_prepare.push_back(j.get());
+    s->jobs.emplace(j->ticket, std::move(j));
+    s->cv_prep.notify_one();
+    return PSA_OK;
+}
+
+psa_status psa_server_poll(psa_server *s, uint64_t ticket, psa_result *out) {
+    if (!s || !out) {
+        set_error("psa_server_poll: NULL argument");
+        return PSA_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) {
+        set_error("psa_server_poll: unknown ticket");
+        return PSA_EINVAL;
+    }
+    fill_result(it->second.get(), out);
+    if (it->second->status == PSA_JOB_ERROR) set_error(it->second->message);
+    return PSA_OK;
+}
+
+psa_status psa_server_wait(psa_server *s, uint64_t ticket, int64_t timeout_us, psa_result *out) {
+    if (!s || !out) {
+        set_error("psa_server_wait: NULL argument");
+        return PSA_EINVAL;
+    }
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) {
+        set_error("psa_server_wait: unknown ticket");
+        return PSA_EINVAL;
+    }
+    ServerJob *j = it->second.get();
+    auto done = [j] { return j->status >= PSA_JOB_DONE; };
+    if (timeout_us < 0)
+        s->cv_done.wait(lk, done);
+    else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done)) {
+        fill_result(j, out);
+        set_error("psa_server_wait: timed out");
+        return PSA_ETIMEDOUT;
+    }
+    fill_result(j, out);
+    if (j->status == PSA_JOB_ERROR) set_error(j->message);
+    return PSA_OK;
+}
+
+psa_status psa_server_cancel(psa_server *s, uint64_t ticket) {
+    if (!s) {
+        set_error("psa_server_cancel: NULL argument");
+        return PSA_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) {
+        set_error("psa_server_cancel: unknown ticket");
+        return PSA_EINVAL;
+    }
+    it->second->cancel = true;
+    s->cv_work.notify_one();
+    return PSA_OK;
+}
+
+psa_status psa_server_release(psa_server *s, uint64_t ticket) {
+    if (!s) {
+        set_error("psa_server_release: NULL argument");
+        return PSA_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end() || it->second->status < PSA_JOB_DONE) {
+        set_error("psa_server_release: unknown or unfinished ticket");
+        return PSA_EINVAL;
+    }
+    s->jobs.erase(it);
+    return PSA_OK;
+}
+
+psa_status psa_server_stats_get(psa_server *s, psa_server_stats *out) {
+    if (!s || !out) {
+        set_error("psa_server_stats_get: NULL argument");
+        return PSA_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(s->mu);
+    out->waiting = static_cast<int32_t>(s->waiting.size());
+    out->resident = static_cast<int32_t>(s->resident.size());
+    out->completed = s->completed;
+    out->failed = s->failed;
+    out->canceled = s->canceled;
+    out->quanta = s->quanta;
+    out->used_bytes = static_cast<int64_t>(s->used_bytes);
+    out->budget_bytes = s->opts.hbm_budget_bytes;
+    return PSA_OK;
+}
+
+void psa_server_destroy(psa_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+        s->to_prepare.clear();
+        for (ServerJob *j : s->resident) j->cancel = true;  // retired after the current quantum
+        s->cv_work.notify_all();
+        s->cv_prep.notify_all();
+    }
+    for (std::thread &t : s->preparers)
+        if (t.joinable()) t.join();
+    if (s->worker.joinable()) s->worker.join();
+    for (ServerJob *j : s->resident) release_device(j);
+    delete s;
+}
+
+}  // extern "C"

@@ -25,11 +25,15 @@ PSA_EINVAL = -1
 PSA_ENOMEM = -2
 PSA_EHIP = -3
 PSA_EUNSUPPORTED = -4
+PSA_ECANCELED = -6
+PSA_ETIMEDOUT = -7
+PSA_JOB_QUEUED, PSA_JOB_RUNNING, PSA_JOB_DONE, PSA_JOB_ERROR, PSA_JOB_CANCELED = range(5)
 
 PSA_GRAPH_ISING = 0
 PSA_GRAPH_MAXCUT = 1
 PSA_OUT_HOST = 0
 PSA_OUT_DEVICE = 1
+PSA_BATCH_SEQUENTIAL = 2
 
 _P = ctypes.c_void_p
 _i32, _i64, _u32, _u64, _f64 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
@@ -49,6 +53,26 @@ class psa_run_desc(ctypes.Structure):
                 ("sigma_nu", _f64), ("p_mean", _f64), ("lambda_", _P),
                 ("delta", _P), ("thr24", _P), ("block", _i32),
                 ("trials_per_group", _i32), ("lanes_per_task", _i32), ("flags", _u32)]
+
+
+class psa_batch_item(ctypes.Structure):
+    _fields_ = [("graph", _P), ("desc", psa_run_desc), ("energy_out", _P),
+                ("cut_out", _P), ("spins_out", _P)]
+
+
+class psa_server_opts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", _i64), ("max_resident", _i32), ("quantum_steps", _i32)]
+
+
+class psa_result(ctypes.Structure):
+    _fields_ = [("status", _i32), ("error", _i32), ("submit_us", _i64), ("admit_us", _i64),
+                ("end_us", _i64)]
+
+
+class psa_server_stats(ctypes.Structure):
+    _fields_ = [("waiting", _i32), ("resident", _i32), ("completed", _i64), ("failed", _i64),
+                ("canceled", _i64), ("quanta", _i64), ("used_bytes", _i64),
+                ("budget_bytes", _i64)]
 
 
 # (name, restype, argtypes) of every exported entry point in include/psa.h
@@ -78,6 +102,18 @@ _SIGNATURES = [
     ("psa_job_energy_cut", _i32, [_P, _P, _P, _u32]),
     ("psa_job_destroy", None, [_P]),
     ("psa_anneal", _i32, [_P, _P, ctypes.POINTER(psa_run_desc), _P, _P, _P, _u32]),
+    ("psa_jobs_step_batch", _i32, [_P, _i32, ctypes.POINTER(_P), _i32]),
+    ("psa_anneal_batch", _i32, [_P, _i32, ctypes.POINTER(psa_batch_item), _u32]),
+    ("psa_server_create", _i32, [_P, ctypes.POINTER(psa_server_opts), ctypes.POINTER(_P)]),
+    ("psa_server_submit", _i32, [_P, _i32, _i64, _P, _P, _P, _P, _u32,
+                                 ctypes.POINTER(psa_run_desc), _P, _P, _P,
+                                 ctypes.POINTER(_u64)]),
+    ("psa_server_poll", _i32, [_P, _u64, ctypes.POINTER(psa_result)]),
+    ("psa_server_wait", _i32, [_P, _u64, _i64, ctypes.POINTER(psa_result)]),
+    ("psa_server_cancel", _i32, [_P, _u64]),
+    ("psa_server_release", _i32, [_P, _u64]),
+    ("psa_server_stats_get", _i32, [_P, ctypes.POINTER(psa_server_stats)]),
+    ("psa_server_destroy", None, [_P]),
 ]
 
 
@@ -360,3 +396,106 @@ def anneal(ctx, graph, steps, trials, seed=0, spins=True, **kw):
                            _ptr(C), PSA_OUT_HOST), "psa_anneal")
     del keep
     return S, E, C
+
+
+def jobs_step_batch(ctx, jobs, k):
+    """Advance several jobs by up to k steps each in one batched launch."""
+    arr = (_P * len(jobs))(*[j.handle for j in jobs])
+    _check(_lib.psa_jobs_step_batch(ctx.handle, len(jobs), arr, int(k)), "psa_jobs_step_batch")
+
+
+def anneal_batch(ctx, items, sequential=False, spins=False):
+    """items: list of (graph, steps, trials, seed, kwargs for make_desc).
+    Returns a list of (spins or None, energy, cut) host arrays."""
+    keep = []
+    arr = (psa_batch_item * len(items))()
+    outs = []
+    for idx, (graph, steps, trials, seed, kw) in enumerate(items):
+        desc, k = make_desc(steps, trials, seed, **kw)
+        keep.append(k)
+        n = graph.info()["n"]
+        E = np.zeros(trials, np.int64)
+        C = np.zeros(trials, np.int64)
+        S = np.zeros((trials, n), np.int8) if spins else None
+        outs.append((S, E, C))
+        arr[idx].graph = graph.handle
+        arr[idx].desc = desc
+        arr[idx].energy_out = _ptr(E)
+        arr[idx].cut_out = _ptr(C)
+        arr[idx].spins_out = _ptr(S)
+    flags = PSA_OUT_HOST | (PSA_BATCH_SEQUENTIAL if sequential else 0)
+    _check(_lib.psa_anneal_batch(ctx.handle, len(items), arr, flags), "psa_anneal_batch")
+    del keep
+    return outs
+
+
+class Server:
+    """Continuous-batching anneal server on a context (see psa_server_create)."""
+
+    def __init__(self, ctx, hbm_budget_bytes=0, max_resident=0, quantum_steps=0):
+        o = psa_server_opts(int(hbm_budget_bytes), int(max_resident), int(quantum_steps))
+        h = _P()
+        _check(_lib.psa_server_create(ctx.handle, ctypes.byref(o), ctypes.byref(h)),
+               "psa_server_create")
+        self.ctx, self.handle = ctx, h
+        self._pending = {}
+
+    def submit(self, n, u, v, val, steps, trials, seed=0, h=None, maxcut=True, spins=False,
+               **kw):
+        """Queue one anneal; returns a ticket.  The result buffers live in this
+        object until result() hands them out."""
+        u = np.ascontiguousarray(u, dtype=np.int32)
+        v = np.ascontiguousarray(v, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.int32)
+        hh = None if h is None else np.ascontiguousarray(h, dtype=np.int32)
+        desc, keep = make_desc(steps, trials, seed, **kw)
+        E = np.zeros(trials, np.int64)
+        C = np.zeros(trials, np.int64)
+        S = np.zeros((trials, n), np.int8) if spins else None
+        t = _u64()
+        _check(_lib.psa_server_submit(self.handle, n, u.size, _ptr(u), _ptr(v), _ptr(val),
+                                      _ptr(hh), PSA_GRAPH_MAXCUT if maxcut else PSA_GRAPH_ISING,
+                                      ctypes.byref(desc), _ptr(E), _ptr(C), _ptr(S),
+                                      ctypes.byref(t)), "psa_server_submit")
+        del keep
+        self._pending[t.value] = (S, E, C)
+        return t.value
+
+    def poll(self, ticket):
+        r = psa_result()
+        _check(_lib.psa_server_poll(self.handle, ticket, ctypes.byref(r)), "psa_server_poll")
+        return r
+
+    def wait(self, ticket, timeout_s=None):
+        """Block until the job ends; returns the psa_result (status field), or
+        raises PsaError(PSA_ETIMEDOUT) after timeout_s seconds."""
+        r = psa_result()
+        us = -1 if timeout_s is None else int(timeout_s * 1e6)
+        _check(_lib.psa_server_wait(self.handle, ticket, us, ctypes.byref(r)), "psa_server_wait")
+        return r
+
+    def result(self, ticket):
+        """(spins or None, energy, cut) of a finished job; frees its record."""
+        r = self.wait(ticket)
+        out = self._pending.pop(ticket)
+        _check(_lib.psa_server_release(self.handle, ticket), "psa_server_release")
+        return r, out
+
+    def cancel(self, ticket):
+        _check(_lib.psa_server_cancel(self.handle, ticket), "psa_server_cancel")
+
+    def stats(self):
+        st = psa_server_stats()
+        _check(_lib.psa_server_stats_get(self.handle, ctypes.byref(st)), "psa_server_stats_get")
+        return {f: getattr(st, f) for f, _ in psa_server_stats._fields_}
+
+    def close(self):
+        if self.handle:
+            _lib.psa_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,141 @@
+"""GPU parity of the batched launch: many graphs of uneven size and weight
+type in one launch give exactly the results of running each alone, and of
+the oracle; jobs advanced in step quanta, with a job joining mid-way, end
+where a single uninterrupted run ends."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_14476_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def psa():
+    from paper_2601_14476_amd import psa as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(psa):
+    c = psa.Context(0)
+    yield c
+    c.close()
+
+
+def _mix():
+    """(n, u, v, J, h, maxcut_w or None, trials, steps, seed, sigmas) of a mixed batch."""
+    rng = np.random.default_rng(3)
+    out = []
+    for idx, (kind, n, trials, steps) in enumerate([
+            ("er1", 300, 8, 40), ("gnm", 811, 3, 55), ("torus", 0, 10, 30), ("int", 257, 5, 25),
+            ("big", 97, 4, 20), ("gnm", 2000, 33, 12), ("er1", 1203, 1, 35), ("int", 64, 7, 60),
+            ("gnm", 5, 2, 15), ("hub", 400, 6, 18)]):
+        if kind == "er1":
+            n, u, v, w = inputs.erdos_renyi(n, 0.05, 100 + idx)
+            j, h = -w, None
+        elif kind == "gnm":
+            n, u, v, w = inputs.gnm(n, min(3 * n, n * (n - 1) // 2), 100 + idx)
+            j, h = -w, None
+        elif kind == "torus":
+            n, u, v, w = inputs.torus(12, 15, 100 + idx)
+            j, h = -w, None
+        elif kind == "hub":
+            hub = np.arange(1, 301, dtype=np.int32)
+            ring_u = np.arange(1, n, dtype=np.int32)
+            ring_v = np.roll(ring_u, -1)
+            u = np.concatenate([np.zeros(300, np.int32), np.minimum(ring_u, ring_v)])
+            v = np.concatenate([hub, np.maximum(ring_u, ring_v)])
+            j = rng.choice([-1, 1], size=u.size).astype(np.int32)
+            h = None
+        else:
+            _, u, v, _ = inputs.gnm(n, 3 * n, 100 + idx)
+            jmax = 4 if kind == "int" else 3
+            j = (rng.integers(1, jmax + 1, size=u.size) * rng.choice([-1, 1], size=u.size))
+            h = rng.integers(-5, 6, size=n)
+            if kind == "big":
+                j = j * 15000
+                h = h * 2000
+            j = j.astype(np.int32)
+            h = h.astype(np.int32)
+        sig = (0.1, 0.1, 0.1, 0.8) if idx % 2 == 0 else (0.0, 0.0, 0.0, 1.0)
+        out.append((n, u, v, j, h, trials, steps, 1000 + idx, sig))
+    return out
+
+
+def _schedule(kind_big, steps):
+    return oracle.schedule(steps, 1e-5, 1e-4) if kind_big else oracle.schedule(steps, 0.02, 0.8)
+
+
+def test_batch_equals_sequential_and_oracle(psa, ctx):
+    mix = _mix()
+    graphs, items = [], []
+    for n, u, v, j, h, T, S, seed, sig in mix:
+        g = psa.Graph.from_edges(ctx, n, u, v, j, h=h, maxcut=False)
+        graphs.append(g)
+        i0 = _schedule(int(np.abs(j).max()) > 1000, S)
+        items.append((g, S, T, seed, dict(i0=i0, sigma_lambda=sig[0], sigma_delta=sig[1],
+                                          sigma_nu=sig[2], p_mean=sig[3])))
+    batched = psa.anneal_batch(ctx, items, spins=True)
+    seq = psa.anneal_batch(ctx, items, sequential=True, spins=True)
+    for (bs, bE, bC), (ss, sE, sC) in zip(batched, seq):
+        np.testing.assert_array_equal(bs, ss)
+        np.testing.assert_array_equal(bE, sE)
+        np.testing.assert_array_equal(bC, sC)
+    for (n, u, v, j, h, T, S, seed, sig), (bs, bE, bC) in zip(mix, batched):
+        i0 = _schedule(int(np.abs(j).max()) > 1000, S)
+        lam, dl, thr = oracle.variability(n, seed, *sig)
+        k = min(T, 2)
+        ref = oracle.anneal(n, u, v, j, h, i0, lam, dl, thr, seed, 0, k)
+        np.testing.assert_array_equal(bs[:k], ref[0])
+        np.testing.assert_array_equal(bE[:k], ref[1])
+        np.testing.assert_array_equal(bC[:k], ref[2])
+
+
+def test_step_quanta_with_late_joiner(psa, ctx):
+    """Continuous batching semantics: jobs advance together in quanta of 7
+    steps; a job created after three quanta joins the next launches.  Every
+    job ends exactly where an uninterrupted single run ends."""
+    specs = [(inputs.gnm(500, 1500, 7), 5, 40, 11, (0.1, 0.1, 0.1, 0.8)),
+             (inputs.erdos_renyi(350, 0.04, 8), 9, 23, 12, (0.0, 0.0, 0.0, 1.0)),
+             (inputs.torus(10, 20, 9), 4, 31, 13, (0.2, 0.05, 0.2, 0.7))]
+    late = (inputs.gnm(901, 2700, 10), 6, 26, 14, (0.05, 0.05, 0.05, 0.8))
+
+    def make(spec):
+        (n, u, v, w), T, S, seed, sig = spec
+        g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
+        job = psa.Job(ctx, g, S, T, seed, sigma_lambda=sig[0], sigma_delta=sig[1],
+                      sigma_nu=sig[2], p_mean=sig[3])
+        ref = psa.Job(ctx, g, S, T, seed, sigma_lambda=sig[0], sigma_delta=sig[1],
+                      sigma_nu=sig[2], p_mean=sig[3])
+        ref.step(S)
+        return g, job, ref
+
+    live = [make(s) for s in specs]
+    rounds = 0
+    while any(j.position < j.steps for _, j, _ in live):
+        psa.jobs_step_batch(ctx, [j for _, j, _ in live if j.position < j.steps], 7)
+        rounds += 1
+        if rounds == 3:
+            live.append(make(late))
+    for g, job, ref in live:
+        assert job.position == job.steps
+        np.testing.assert_array_equal(job.read_spins(), ref.read_spins())
+        np.testing.assert_array_equal(job.energy_cut()[1], ref.energy_cut()[1])
+    # and one of them against the oracle
+    (n, u, v, w), T, S, seed, sig = specs[2]
+    i0, _, _ = oracle.schedule_paper(n, u, v, -w, S)
+    lam, dl, thr = oracle.variability(n, seed, *sig)
+    ref = oracle.anneal(n, u, v, -w, None, i0, lam, dl, thr, seed, 0, T)
+    np.testing.assert_array_equal(live[2][1].read_spins(), ref[0])
+
+
+def test_batch_rejects_bad_input(psa, ctx):
+    n, u, v, w = inputs.gnm(50, 100, 1)
+    g = psa.Graph.from_edges(ctx, n, u, v, w)
+    job = psa.Job(ctx, g, 10, 2, 0)
+    with pytest.raises(psa.PsaError):
+        psa.jobs_step_batch(ctx, [job, job], 3)        # listed twice
+    with pytest.raises(psa.PsaError):
+        psa.anneal_batch(ctx, [(g, 0, 2, 0, {})])       # steps < 1

@@ -307,3 +307,53 @@ def test_device_outputs(psa, ctx):
     g.close()
     dctx.close()
     torch.cuda.set_stream(torch.cuda.default_stream())
+
+
+def _star_plus_ring(n, hub_degree, seed):
+    """A hub joined to `hub_degree` p-bits plus a ring: one row longer than 255."""
+    rng = np.random.default_rng(seed)
+    u = [0] * hub_degree
+    v = list(range(1, hub_degree + 1))
+    for i in range(1, n):
+        u.append(i)
+        v.append(i % (n - 1) + 1)
+    u, v = np.array(u, np.int32), np.array(v, np.int32)
+    key = np.minimum(u, v).astype(np.int64) * n + np.maximum(u, v)
+    _, first = np.unique(key, return_index=True)
+    keep = np.sort(first)
+    u, v = u[keep], v[keep]
+    keep = u != v
+    u, v = u[keep], v[keep]
+    w = rng.choice([-1, 1], size=u.size).astype(np.int32)
+    return n, u, v, w
+
+
+@pytest.mark.parametrize("kind", ["unit", "int", "big", "hub"])
+@pytest.mark.parametrize("tpw,lpt", [(1, 1), (1, 2), (1, 4), (4, 0)])
+def test_edge_encodings_match_oracle(psa, ctx, kind, tpw, lpt):
+    """Every edge encoding of the anneal kernel (0/1-byte mirror, SWAR words,
+    packed 32-bit, separate col/val) against the oracle, 30 steps."""
+    if kind == "unit":
+        n, u, v, w = inputs.gnm(603, 2500, 11)
+        j, h = -w, None
+    elif kind == "int":
+        n, u, v, j, h = _random_ising(603, 2500, 12)
+    elif kind == "big":                       # |J| >= 2^15: col/val pairs
+        n, u, v, j, h = _random_ising(211, 700, 13, jmax=3)
+        j = (j * 20000).astype(np.int32)
+        h = (h * 1000).astype(np.int32)
+    else:                                     # a row of degree 300 (> 255)
+        n, u, v, w = _star_plus_ring(500, 300, 14)
+        j, h = -w, None
+    g = psa.Graph.from_edges(ctx, n, u, v, j, h=h, maxcut=False)
+    T, S = 9, 30
+    lam, dl, thr = oracle.variability(n, 21, 0.2, 0.3, 0.2, 0.7)
+    i0 = oracle.schedule(S, 0.02, 0.5) if kind != "big" else oracle.schedule(S, 1e-5, 1e-4)
+    job = psa.Job(ctx, g, S, T, seed=21, i0=i0, sigma_lambda=0.2, sigma_delta=0.3,
+                  sigma_nu=0.2, p_mean=0.7, trials_per_group=tpw, lanes_per_task=lpt)
+    job.step(S)
+    ref = oracle.anneal(n, u, v, j, h, i0, lam, dl, thr, 21, 0, T)
+    np.testing.assert_array_equal(job.read_spins(), ref[0])
+    E, C = job.energy_cut()
+    np.testing.assert_array_equal(E, ref[1])
+    np.testing.assert_array_equal(C, ref[2])

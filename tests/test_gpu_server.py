@@ -1,0 +1,124 @@
+"""GPU tests of the serving loop: results served in a mix equal the same runs
+alone; admission respects the HBM budget and slot cap; cancel, time-outs and
+a failing request are handled without disturbing the other jobs.  Failure
+conditions are forced from the host (tiny budgets, bad graphs, cancels)."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_14476_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def psa():
+    from paper_2601_14476_amd import psa as mod
+    return mod
+
+
+def _alone(psa, ctx, spec):
+    (n, u, v, w), T, S, seed, sig = spec
+    g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
+    out = psa.anneal(ctx, g, S, T, seed, sigma_lambda=sig[0], sigma_delta=sig[1],
+                     sigma_nu=sig[2], p_mean=sig[3])
+    g.close()
+    return out
+
+
+def _specs():
+    return [
+        (inputs.gnm(700, 2100, 1), 6, 90, 31, (0.1, 0.1, 0.1, 0.8)),
+        (inputs.erdos_renyi(300, 0.05, 2), 3, 40, 32, (0.0, 0.0, 0.0, 1.0)),
+        (inputs.torus(10, 30, 3), 12, 120, 33, (0.2, 0.05, 0.1, 0.8)),
+        (inputs.gnm(1500, 6000, 4), 2, 65, 34, (0.05, 0.05, 0.05, 0.8)),
+        (inputs.gnm(64, 300, 5), 40, 33, 35, (0.0, 0.0, 0.0, 1.0)),
+        (inputs.gnm(2500, 9000, 6), 5, 150, 36, (0.1, 0.1, 0.1, 0.8)),
+    ]
+
+
+def _submit(srv, spec, spins=True):
+    (n, u, v, w), T, S, seed, sig = spec
+    return srv.submit(n, u, v, w, S, T, seed, spins=spins, sigma_lambda=sig[0],
+                      sigma_delta=sig[1], sigma_nu=sig[2], p_mean=sig[3])
+
+
+def test_served_results_equal_alone(psa):
+    """Staggered arrivals, quantum 17 steps, at most 3 resident: jobs overlap
+    on the device and join as slots free up; every result equals its run
+    alone, and one equals the oracle."""
+    ctx = psa.Context(0)
+    specs = _specs()
+    ref = [_alone(psa, ctx, sp) for sp in specs]
+    srv = psa.Server(ctx, max_resident=3, quantum_steps=17)
+    tickets = []
+    for sp in specs:
+        tickets.append(_submit(srv, sp))
+        time.sleep(0.002)
+    results = [srv.result(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(specs) and st["failed"] == 0
+    for (r, (S, E, C)), (rS, rE, rC) in zip(results, ref):
+        assert r.status == psa.PSA_JOB_DONE
+        np.testing.assert_array_equal(S, rS)
+        np.testing.assert_array_equal(E, rE)
+        np.testing.assert_array_equal(C, rC)
+        assert r.submit_us <= r.admit_us <= r.end_us
+    (n, u, v, w), T, S_, seed, sig = specs[2]
+    i0, _, _ = oracle.schedule_paper(n, u, v, -w, S_)
+    lam, dl, thr = oracle.variability(n, seed, *sig)
+    o = oracle.anneal(n, u, v, -w, None, i0, lam, dl, thr, seed, 0, T)
+    np.testing.assert_array_equal(results[2][1][0], o[0])
+    ctx.close()
+
+
+def test_budget_serialises_and_rejects(psa):
+    ctx = psa.Context(0)
+    specs = _specs()[:3]
+    # a budget of about one of these jobs: they queue for memory
+    budget = 150_000
+    srv = psa.Server(ctx, hbm_budget_bytes=budget, quantum_steps=25)
+    tickets = [_submit(srv, sp, spins=False) for sp in specs]
+    big = srv.submit(*inputs.gnm(20000, 60000, 9), 10, 200, 1)      # alone above budget
+    seen_resident, seen_used = 0, 0
+    while True:
+        st = srv.stats()
+        seen_resident = max(seen_resident, st["resident"])
+        seen_used = max(seen_used, st["used_bytes"])
+        if st["completed"] + st["failed"] >= 4:
+            break
+        time.sleep(0.001)
+    for t, sp in zip(tickets, specs):
+        r, (_, E, C) = srv.result(t)
+        assert r.status == psa.PSA_JOB_DONE
+        np.testing.assert_array_equal(C, _alone(psa, ctx, sp)[2])
+    r = srv.wait(big)
+    assert r.status == psa.PSA_JOB_ERROR and r.error == psa.PSA_ENOMEM
+    assert 1 <= seen_resident < 3 and seen_used <= budget
+    srv.close()
+    ctx.close()
+
+
+def test_cancel_timeout_and_bad_request(psa):
+    ctx = psa.Context(0)
+    srv = psa.Server(ctx, quantum_steps=50)
+    n, u, v, w = inputs.gnm(3000, 12000, 7)
+    long_job = srv.submit(n, u, v, w, 100000, 64, 3)
+    bad = srv.submit(3, np.array([0, 1]), np.array([0, 2]), np.array([1, 1]), 10, 2, 0)
+    ok_spec = _specs()[1]
+    ok = _submit(srv, ok_spec)
+    with pytest.raises(psa.PsaError) as e:
+        srv.wait(long_job, timeout_s=0.05)
+    assert e.value.status == psa.PSA_ETIMEDOUT
+    srv.cancel(long_job)
+    assert srv.wait(long_job).status == psa.PSA_JOB_CANCELED
+    r = srv.wait(bad)
+    assert r.status == psa.PSA_JOB_ERROR and r.error == psa.PSA_EINVAL
+    r, (S, E, C) = srv.result(ok)
+    assert r.status == psa.PSA_JOB_DONE
+    np.testing.assert_array_equal(S, _alone(psa, ctx, ok_spec)[0])
+    srv.close()
+    ctx.close()
