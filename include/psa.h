@@ -78,7 +78,10 @@ psa_status psa_ctx_create(int32_t device, void *hip_stream, psa_ctx **out);
 /* Wait for all work queued on the context's stream. */
 psa_status psa_ctx_synchronize(psa_ctx *ctx);
 
-/* Destroy the context (after its graphs and jobs).  NULL is ignored. */
+/* Drop the creator's reference to the context.  Graphs and jobs made from
+ * it hold references of their own, so they may be destroyed before or after
+ * the context; its streams and staging are released with the last
+ * reference.  NULL is ignored. */
 void psa_ctx_destroy(psa_ctx *ctx);
 
 /* ------------------------------------------------------------------ */
@@ -119,6 +122,9 @@ psa_status psa_graph_from_csr(psa_ctx *ctx, int32_t n, const int64_t *row_ptr,
                               psa_graph **out);
 
 psa_status psa_graph_info_get(const psa_graph *g, psa_graph_info *out);
+
+/* Drop the creator's reference; jobs on the graph keep it alive until they
+ * are destroyed.  NULL is ignored. */
 void psa_graph_destroy(psa_graph *g);
 
 /* ------------------------------------------------------------------ */
@@ -183,8 +189,18 @@ typedef struct psa_run_desc {
     int32_t block;
     int32_t trials_per_group;
     int32_t lanes_per_task;
-    uint32_t flags; /* reserved, 0 */
+    uint32_t flags; /* PSA_PATH_* */
 } psa_run_desc;
+
+/* Field-computation path of a run (psa_run_desc.flags).  AUTO picks by a
+ * cost model (long rows -> dense); CSR walks the sparse rows from LDS /
+ * L2; DENSE multiplies the dense int8 coupling matrix with the spins of all
+ * trials on the matrix cores (every |J_ij| <= 127; EUNSUPPORTED otherwise).
+ * Results are identical on every path. */
+#define PSA_PATH_AUTO 0u
+#define PSA_PATH_CSR 1u
+#define PSA_PATH_DENSE 2u
+#define PSA_PATH_MASK 3u
 
 /* Fill *d with the defaults: steps 1000, trials 1, seed 0, the paper's I0
  * endpoints (i0_min = i0_max = -1), no variability (sigmas 0, p_mean 1),
@@ -306,6 +322,8 @@ typedef struct psa_server_stats {
     int32_t waiting, resident;
     int64_t completed, failed, canceled, quanta;
     int64_t used_bytes, budget_bytes;
+    int32_t peak_resident;   /* most jobs resident at once so far       */
+    int64_t peak_used_bytes; /* most device bytes held at once so far   */
 } psa_server_stats;
 
 /* Start a server on ctx.  Its scheduler thread issues all device work on the

@@ -20,7 +20,7 @@ OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libpsa.so")
 
 SOURCES = [
-    "anneal.hip", "kernels.hip", "abi.cpp", "graph.cpp", "batch.cpp", "server.cpp",
+    "anneal.hip", "dense.hip", "kernels.hip", "abi.cpp", "graph.cpp", "batch.cpp", "server.cpp",
     "host_params.cpp",
 ]
 

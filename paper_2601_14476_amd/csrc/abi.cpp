@@ -77,9 +77,14 @@ void job_free(psa_job *j) {
     dev_free(j->d_delta);
     dev_free(j->d_thr24);
     dev_free(j->d_order);
+    dev_free(j->d_m);
     dev_free(j->d_spins);
     dev_free(j->d_scratch);
+    psa_ctx *ctx = j->retained ? j->ctx : nullptr;
+    psa_graph *g = j->graph_ref;
     delete j;
+    if (g) psa::graph_unref(g);
+    if (ctx) psa::ctx_release(ctx);
 }
 
 psa_status ensure_scratch(psa_job *j, size_t bytes) {
@@ -131,6 +136,9 @@ psa_status psa_ctx_create(int32_t device, void *hip_stream, psa_ctx **out) {
         PSA_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "hipStreamCreate");
         c->own_stream = true;
     }
+    PSA_HIP(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking), "hipStreamCreate");
+    PSA_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "hipEventCreate");
+    PSA_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "hipEventCreate");
     *out = c.release();
     return PSA_OK;
 }
@@ -147,13 +155,34 @@ psa_status psa_ctx_synchronize(psa_ctx *ctx) {
 
 void psa_ctx_destroy(psa_ctx *ctx) {
     if (!ctx) return;
+    psa::ctx_release(ctx);
+}
+
+}  // extern "C"
+
+namespace psa {
+
+void ctx_retain(psa_ctx *ctx) { ctx->refs.fetch_add(1); }
+
+void ctx_release(psa_ctx *ctx) {
+    if (ctx->refs.fetch_sub(1) != 1) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->stream2) (void)hipStreamSynchronize(ctx->stream2);
     if (ctx->d_batch_table) (void)hipFree(ctx->d_batch_table);
     if (ctx->d_batch_work) (void)hipFree(ctx->d_batch_work);
+    if (ctx->d_dense_table) (void)hipFree(ctx->d_dense_table);
+    if (ctx->d_dense_work) (void)hipFree(ctx->d_dense_work);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->stream2) (void)hipStreamDestroy(ctx->stream2);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
+
+}  // namespace psa
+
+extern "C" {
 
 psa_status psa_graph_from_edges(psa_ctx *ctx, int32_t n, int64_t m, const int32_t *u,
                                 const int32_t *v, const int32_t *val, const int32_t *h,
@@ -190,13 +219,7 @@ psa_status psa_graph_info_get(const psa_graph *g, psa_graph_info *out) {
     return PSA_OK;
 }
 
-void psa_graph_destroy(psa_graph *g) {
-    if (g && g->ctx) {
-        (void)hipSetDevice(g->ctx->device);
-        (void)hipStreamSynchronize(g->ctx->stream);
-    }
-    psa::graph_release(g);
-}
+void psa_graph_destroy(psa_graph *g) { psa::graph_unref(g); }
 
 psa_status psa_schedule_paper(const psa_graph *g, double *i0_min, double *i0_max) {
     if (!g || !i0_min || !i0_max) {
@@ -262,6 +285,10 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
         set_error("psa_job_create: lanes_per_task must be 0, 1, 2 or 4");
         return PSA_EINVAL;
     }
+    if ((desc->flags & ~PSA_PATH_MASK) != 0 || (desc->flags & PSA_PATH_MASK) == PSA_PATH_MASK) {
+        set_error("psa_job_create: unknown flags");
+        return PSA_EINVAL;
+    }
     const int32_t S = desc->steps;
     std::vector<float> i0(static_cast<size_t>(S));
     if (desc->i0) {
@@ -301,17 +328,32 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
     PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     std::unique_ptr<psa_job, void (*)(psa_job *)> j(new psa_job(), job_free);
     j->ctx = ctx;
+    psa::ctx_retain(ctx);
+    j->retained = true;
+    const_cast<psa_graph *>(g)->refs.fetch_add(1);
+    j->graph_ref = const_cast<psa_graph *>(g);
     j->g = g;
     j->run.trials = desc->trials;
     j->run.t4 = (desc->trials + 3) / 4 * 4;
     j->run.steps = S;
-    {
+    const uint32_t path = desc->flags & PSA_PATH_MASK;
+    if (path != PSA_PATH_DENSE) {
         std::string why;
         if (!psa::plan_anneal(g->dev, j->run, desc->trials_per_group, desc->lanes_per_task,
                               desc->block, ctx->max_lds, ctx->num_cu, &j->plan, &why)) {
-            set_error("psa_job_create: " + why);
-            return PSA_EUNSUPPORTED;
+            if (path == PSA_PATH_CSR) {
+                set_error("psa_job_create: " + why);
+                return PSA_EUNSUPPORTED;
+            }
+            j->plan.dense = 1;  // too large for the LDS-resident sweep
         }
+    }
+    if (path == PSA_PATH_DENSE || (path == PSA_PATH_AUTO && psa::prefer_dense(g->dev, j->run)))
+        j->plan.dense = 1;
+    if (j->plan.dense) {
+        psa_status st = psa::ensure_dense_matrix(const_cast<psa_graph *>(g));
+        if (st != PSA_OK) return st;
+        j->plan.nb = desc->trials >= 64 ? 4 : (desc->trials >= 32 ? 2 : 1);
     }
     j->run.key0 = static_cast<uint32_t>(desc->seed);
     j->run.key1 = static_cast<uint32_t>(desc->seed >> 32);
@@ -330,6 +372,11 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
     if ((st = dev_upload(&j->d_order, order.data(), order.size(), "job upload")) != PSA_OK) return st;
     const size_t spin_bytes = static_cast<size_t>(n) * static_cast<size_t>(j->run.t4);
     if ((st = dev_upload<int8_t>(&j->d_spins, nullptr, spin_bytes, "job spins")) != PSA_OK) return st;
+    if (j->plan.dense) {
+        j->tp = (j->run.t4 + 16 * j->plan.nb - 1) / (16 * j->plan.nb) * (16 * j->plan.nb);
+        const size_t mb = 2 * static_cast<size_t>(j->tp) * static_cast<size_t>(g->np);
+        if ((st = dev_upload<int8_t>(&j->d_m, nullptr, mb, "job dense spins")) != PSA_OK) return st;
+    }
     j->run.i0 = j->d_i0;
     j->run.lambda = j->d_lambda;
     j->run.delta = j->d_delta;
@@ -360,6 +407,16 @@ psa_status psa_job_step(psa_job *job, int32_t k) {
     const int32_t t_end = static_cast<int32_t>(std::min<int64_t>(int64_t{job->t} + k, job->run.steps));
     if (t_end <= job->t) return PSA_OK;
     PSA_HIP(hipSetDevice(job->ctx->device), "hipSetDevice");
+    if (job->plan.dense) {
+        psa_ctx *ctx = job->ctx;
+        PSA_HIP(hipEventRecord(ctx->ev_fork, ctx->stream), "hipEventRecord");
+        PSA_HIP(hipStreamWaitEvent(ctx->stream2, ctx->ev_fork, 0), "hipStreamWaitEvent");
+        psa_job *one[1] = {job};
+        psa_status st = psa::dense_step_jobs(ctx, one, 1, k);
+        PSA_HIP(hipEventRecord(ctx->ev_join, ctx->stream2), "hipEventRecord");
+        PSA_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "hipStreamWaitEvent");
+        return st;
+    }
     PSA_HIP(psa::launch_anneal(job->ctx->stream, job->g->dev, job->run, job->plan, job->d_order,
                                job->t, t_end),
             "anneal launch");

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <memory>
 #include <numeric>
 #include <string>
@@ -86,6 +87,102 @@ void build_work_list(const std::vector<int32_t> &trials, const std::vector<doubl
         for (size_t s = 0; s < queue[x].size(); ++s) (*work)[s * kXcds + x] = queue[x][s];
 }
 
+// Automatic path choice.  Whole-device estimates per step: the CSR walk
+// issues ~60 + 3 d lane-operations per update (d = mean degree) at 39.3 T
+// lane-ops/s; the dense product costs 2 np^2 tp int8 MACs at ~2.5 P ops/s
+// effective, or np^2 bytes of J per trial tile at ~4 TB/s, whichever is
+// larger, plus ~60 lane-operations of epilogue per update.
+bool prefer_dense(const DevGraph &g, const DevRun &run) {
+    if (g.n < 256) return false;
+    const double n = g.n, T = run.t4, d = g.nnz / static_cast<double>(g.n);
+    const double np = (g.n + 63) / 64 * 64;
+    const int32_t nb = run.t4 >= 64 ? 4 : (run.t4 >= 32 ? 2 : 1);
+    const double tp = std::ceil(T / (16.0 * nb)) * 16.0 * nb;
+    const double csr = n * T * (60.0 + 3.0 * d) / 39.3e12;
+    const double mfma = 2.0 * np * np * tp / 2.5e15;
+    const double bytes = np * np * (tp / (16.0 * nb)) / 4.0e12;
+    const double dense = std::max(mfma, bytes) + n * T * 60.0 / 39.3e12;
+    return dense < 0.7 * csr;
+}
+
+psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, int32_t k) {
+    std::vector<psa::DenseJob> table;
+    std::vector<int4> work;
+    std::vector<psa_job *> live;
+    int32_t max_steps = 0, nb = 4;
+    for (int32_t j = 0; j < count; ++j) {
+        psa_job *job = jobs[j];
+        const int32_t te = static_cast<int32_t>(std::min<int64_t>(int64_t{job->t} + k, job->run.steps));
+        if (te <= job->t) continue;
+        nb = std::min(nb, job->plan.nb);
+        live.push_back(job);
+    }
+    if (live.empty()) return PSA_OK;
+    for (size_t j = 0; j < live.size(); ++j) {
+        psa_job *job = live[j];
+        const psa_graph *g = job->g;
+        const int32_t te = static_cast<int32_t>(std::min<int64_t>(int64_t{job->t} + k, job->run.steps));
+        const int32_t tile = 16 * nb;
+        psa::DenseJob d;
+        d.n = g->info.n;
+        d.n4 = g->dev.n4;
+        d.np = g->np;
+        d.t4 = job->run.t4;
+        d.tp = job->tp;
+        d.t = job->t;
+        d.t_end = te;
+        d.J = g->d_dense;
+        d.m0 = job->d_m;
+        d.m1 = job->d_m + static_cast<size_t>(job->tp) * g->np;
+        d.h = g->dev.h;
+        d.i0 = job->run.i0;
+        d.lam = job->run.lambda;
+        d.dlt = job->run.delta;
+        d.thr = job->run.thr24;
+        d.k0 = job->run.key0;
+        d.k1 = job->run.key1;
+        table.push_back(d);
+        for (int32_t tt = 0; tt < job->tp / tile; ++tt)
+            for (int32_t rt = 0; rt < g->np / 64; ++rt)
+                work.push_back(make_int4(static_cast<int32_t>(j), rt, tt, 0));
+        max_steps = std::max(max_steps, te - job->t);
+    }
+    PSA_HIP(hipStreamSynchronize(ctx->stream2), "hipStreamSynchronize");
+    psa_status st;
+    if ((st = ensure(&ctx->d_dense_table, &ctx->dense_table_cap, table.size() * sizeof(psa::DenseJob))) != PSA_OK)
+        return st;
+    if ((st = ensure(&ctx->d_dense_work, &ctx->dense_work_cap, work.size() * sizeof(int4))) != PSA_OK)
+        return st;
+    ctx->h_dense_table = table;
+    ctx->h_dense_work = work;
+    for (psa_job *job : live)
+        for (int half = 0; half < 2; ++half)  // both buffers: a fully defined state
+            PSA_HIP(psa::launch_to_dense(ctx->stream2, job->g->info.n, job->run.t4, job->g->np,
+                                         job->tp, job->d_spins,
+                                         job->d_m + static_cast<size_t>(half) * job->tp * job->g->np),
+                    "dense layout");
+    PSA_HIP(hipMemcpyAsync(ctx->d_dense_table, ctx->h_dense_table.data(),
+                           table.size() * sizeof(psa::DenseJob), hipMemcpyHostToDevice, ctx->stream2),
+            "dense table upload");
+    PSA_HIP(hipMemcpyAsync(ctx->d_dense_work, ctx->h_dense_work.data(), work.size() * sizeof(int4),
+                           hipMemcpyHostToDevice, ctx->stream2),
+            "dense work upload");
+    PSA_HIP(psa::launch_dense_steps(ctx->stream2, static_cast<const psa::DenseJob *>(ctx->d_dense_table),
+                                    static_cast<const int4 *>(ctx->d_dense_work),
+                                    static_cast<int32_t>(work.size()), nb, max_steps),
+            "dense step launch");
+    for (size_t j = 0; j < live.size(); ++j) {
+        psa_job *job = live[j];
+        const psa::DenseJob &d = table[j];
+        const int8_t *fin = ((d.t_end - d.t) & 1) ? d.m1 : d.m0;
+        PSA_HIP(psa::launch_from_dense(ctx->stream2, job->g->info.n, job->run.t4, job->g->np, fin,
+                                       job->d_spins),
+                "dense layout");
+        job->t = d.t_end;
+    }
+    return PSA_OK;
+}
+
 }  // namespace psa
 
 extern "C" {
@@ -99,6 +196,7 @@ psa_status psa_jobs_step_batch(psa_ctx *ctx, int32_t count, psa_job *const *jobs
     std::vector<int32_t> trials;
     std::vector<double> cost;
     std::vector<int32_t> t_end;
+    std::vector<psa_job *> dense_jobs;
     size_t lds = 0;
     int32_t max_lanes = 0;
     for (int32_t j = 0; j < count; ++j) {
@@ -117,6 +215,10 @@ psa_status psa_jobs_step_batch(psa_ctx *ctx, int32_t count, psa_job *const *jobs
             std::min<int64_t>(int64_t{job->t} + k, job->run.steps));
         t_end.push_back(te);
         if (te <= job->t) continue;
+        if (job->plan.dense) {
+            dense_jobs.push_back(job);
+            continue;
+        }
         psa::AnnealPlan plan;
         int32_t variant = 0;
         std::string why;
@@ -134,10 +236,23 @@ psa_status psa_jobs_step_batch(psa_ctx *ctx, int32_t count, psa_job *const *jobs
         lds = std::max(lds, plan.lds_bytes);
         max_lanes = std::max(max_lanes, job->g->dev.n4 / 4 * plan.lpt);
     }
-    if (table.empty()) return PSA_OK;
+    PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    if (!dense_jobs.empty()) {
+        // dense runs on the second stream, concurrently with the CSR launch
+        PSA_HIP(hipEventRecord(ctx->ev_fork, ctx->stream), "hipEventRecord");
+        PSA_HIP(hipStreamWaitEvent(ctx->stream2, ctx->ev_fork, 0), "hipStreamWaitEvent");
+        psa_status st = psa::dense_step_jobs(ctx, dense_jobs.data(),
+                                             static_cast<int32_t>(dense_jobs.size()), k);
+        if (st != PSA_OK) return st;
+        PSA_HIP(hipEventRecord(ctx->ev_join, ctx->stream2), "hipEventRecord");
+    }
+    if (table.empty()) {
+        if (!dense_jobs.empty())
+            PSA_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "hipStreamWaitEvent");
+        return PSA_OK;
+    }
     std::vector<int2> work;
     psa::build_work_list(trials, cost, &work);
-    PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     // the staging buffers are reused: the previous batched launch must be done
     PSA_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     psa_status st;
@@ -160,6 +275,8 @@ psa_status psa_jobs_step_batch(psa_ctx *ctx, int32_t count, psa_job *const *jobs
                                      static_cast<int32_t>(work.size()), block, lds),
             "batch anneal launch");
     for (int32_t j = 0; j < count; ++j) jobs[j]->t = std::max(jobs[j]->t, t_end[j]);
+    if (!dense_jobs.empty())
+        PSA_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "hipStreamWaitEvent");
     return PSA_OK;
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -61,6 +62,8 @@ struct DevRun {
 // How the persistent anneal kernel is launched for one run.
 enum CsrKind : int32_t { kCsrPair = 0, kCsrPack32 = 1, kCsrPack16 = 2, kCsrUnit = 3 };
 struct AnnealPlan {
+    int32_t dense = 0;        // 1: dense int8 matrix-core path (nb below)
+    int32_t nb = 4;           // dense path: 16-trial blocks per workgroup
     int32_t tpw = 1;          // trials per workgroup: 1 or 4
     int32_t lpt = 1;          // lanes per 4-p-bit task (tpw == 1): 1, 2 or 4
     int32_t csr = kCsrPair;   // edge encoding read by the kernel
@@ -106,11 +109,36 @@ struct BatchJob {
     int32_t variant;
 };
 
+// One run of the dense int8 matrix-core path (dense.hip), as the step kernel
+// reads it.  J is [np][np] int8; m0 / m1 are the two [tp][np] spin buffers
+// (trial-major); steps t .. t_end-1 of the launch sequence.
+struct DenseJob {
+    int32_t n, n4, np, t4, tp, t, t_end;
+    const int8_t *J;
+    int8_t *m0, *m1;
+    const int32_t *h;
+    const float *i0;
+    const float *lam;
+    const float *dlt;
+    const uint32_t *thr;
+    uint32_t k0, k1;
+};
+
 // Choose tpw / lanes per task / CSR placement / block for a run
 // (tpw_req, lpt_req, block_req: 0 = automatic).  Returns false with a reason if n does not fit in LDS.
 bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t lpt_req,
                  int32_t block_req, size_t max_lds, int32_t num_cu, AnnealPlan *plan,
                  std::string *why);
+
+// Dense path launchers (dense.hip).  launch_dense_steps issues `steps`
+// launches; launch s advances every run of the work list (job, 64-row tile,
+// trial tile of 16 nb) by its step t + s.
+hipError_t launch_dense_steps(hipStream_t stream, const DenseJob *jobs, const int4 *work,
+                              int32_t nwork, int32_t nb, int32_t steps);
+hipError_t launch_to_dense(hipStream_t stream, int32_t n, int32_t t4, int32_t np, int32_t tp,
+                           const int8_t *spins, int8_t *m);
+hipError_t launch_from_dense(hipStream_t stream, int32_t n, int32_t t4, int32_t np,
+                             const int8_t *m, int8_t *spins);
 
 // Kernel launchers (kernels.hip).  All are asynchronous on `stream`.
 hipError_t launch_init_spins(hipStream_t stream, int32_t n, const DevRun &run);
@@ -166,7 +194,21 @@ psa_status host_graph_from_csr(int32_t n, const int64_t *row_ptr, const int32_t 
                                const int32_t *val, const int32_t *h, uint32_t flags,
                                HostGraph *out);
 psa_status upload_graph(psa_ctx *ctx, HostGraph &&hg, psa_graph **out);
-void graph_release(psa_graph *g);
+void graph_release(psa_graph *g);   // free now (creation failures)
+void graph_unref(psa_graph *g);     // drop one reference, free at zero
+// Cost model of the automatic path choice: dense when the rows are long
+// enough that the matrix-core product beats the CSR walk.
+bool prefer_dense(const DevGraph &g, const DevRun &run);
+// Build and upload the dense int8 coupling matrix of g (once); EUNSUPPORTED
+// if a coupling does not fit int8.
+psa_status ensure_dense_matrix(psa_graph *g);
+// Advance the dense-planned jobs of `jobs` by up to k steps (each clipped to
+// its schedule) on the context's second stream; the caller joins it.
+psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, int32_t k);
+
+// Context references (abi.cpp).
+void ctx_retain(psa_ctx *ctx);
+void ctx_release(psa_ctx *ctx);
 
 // XCD-aware work list of a batched launch (batch.cpp).
 void build_work_list(const std::vector<int32_t> &trials, const std::vector<double> &cost,
@@ -175,6 +217,10 @@ void build_work_list(const std::vector<int32_t> &trials, const std::vector<doubl
 }  // namespace psa
 
 struct psa_ctx {
+    // references: the creator's plus one per live graph and job; the context
+    // is freed when the last one is dropped (psa_ctx_destroy drops the
+    // creator's), so objects may be destroyed in any order
+    std::atomic<int32_t> refs{1};
     int32_t device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -185,10 +231,20 @@ struct psa_ctx {
     size_t batch_table_cap = 0, batch_work_cap = 0;
     std::vector<psa::BatchJob> h_batch_table;
     std::vector<int2> h_batch_work;
+    // dense-path launches run on a second stream, joined with events
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    void *d_dense_table = nullptr, *d_dense_work = nullptr;
+    size_t dense_table_cap = 0, dense_work_cap = 0;
+    std::vector<psa::DenseJob> h_dense_table;
+    std::vector<int4> h_dense_work;
 };
 
 struct psa_graph {
     psa_ctx *ctx = nullptr;
+    bool retained = false;  // holds a reference on ctx
+    // references: the creator's plus one per live job on this graph
+    std::atomic<int32_t> refs{1};
     psa_graph_info info{};
     psa::DevGraph dev;
     // owning device pointers
@@ -196,15 +252,22 @@ struct psa_graph {
     uint32_t *d_pk32 = nullptr;
     uint16_t *d_pk16 = nullptr, *d_ux16 = nullptr;
     std::vector<int32_t> row_ptr_host;  // [n4+4]
+    std::vector<int32_t> col_host, val_host;  // for the dense matrix, on demand
+    int8_t *d_dense = nullptr;          // [np][np] int8, built on first use
+    int32_t np = 0;
 };
 
 struct psa_job {
     psa_ctx *ctx = nullptr;
+    bool retained = false;         // holds a reference on ctx
+    psa_graph *graph_ref = nullptr;  // holds a reference on its graph
     const psa_graph *g = nullptr;
     psa::DevRun run;
     int32_t t = 0;       // steps applied so far
     psa::AnnealPlan plan;
     int32_t *d_order = nullptr;  // [n4/4] task visiting order
+    int8_t *d_m = nullptr;       // dense path: two [tp][np] buffers
+    int32_t tp = 0;
     // owning device pointers
     float *d_i0 = nullptr, *d_lambda = nullptr, *d_delta = nullptr;
     uint32_t *d_thr24 = nullptr;

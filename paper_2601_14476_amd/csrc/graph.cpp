@@ -159,9 +159,41 @@ void graph_release(psa_graph *g) {
     for (void *p : {static_cast<void *>(g->d_row_ptr), static_cast<void *>(g->d_col),
                     static_cast<void *>(g->d_val), static_cast<void *>(g->d_h),
                     static_cast<void *>(g->d_pk32), static_cast<void *>(g->d_pk16),
-                    static_cast<void *>(g->d_ux16)})
+                    static_cast<void *>(g->d_ux16), static_cast<void *>(g->d_dense)})
         if (p) (void)hipFree(p);
+    psa_ctx *ctx = g->retained ? g->ctx : nullptr;
     delete g;
+    if (ctx) ctx_release(ctx);
+}
+
+void graph_unref(psa_graph *g) {
+    if (!g) return;
+    if (g->refs.fetch_sub(1) != 1) return;
+    if (g->ctx) {
+        (void)hipSetDevice(g->ctx->device);
+        (void)hipStreamSynchronize(g->ctx->stream);
+        if (g->ctx->stream2) (void)hipStreamSynchronize(g->ctx->stream2);
+    }
+    graph_release(g);
+}
+
+psa_status ensure_dense_matrix(psa_graph *g) {
+    if (g->d_dense) return PSA_OK;
+    const int32_t n = g->info.n;
+    const int32_t np = (n + 63) / 64 * 64;
+    for (int32_t v : g->val_host)
+        if (v < -127 || v > 127) {
+            set_error("dense path: a coupling does not fit int8");
+            return PSA_EUNSUPPORTED;
+        }
+    std::vector<int8_t> dense(static_cast<size_t>(np) * np, 0);
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t p = g->row_ptr_host[i]; p < g->row_ptr_host[i + 1]; ++p)
+            dense[static_cast<size_t>(i) * np + g->col_host[p]] = static_cast<int8_t>(g->val_host[p]);
+    psa_status st = upload(&g->d_dense, dense);
+    if (st != PSA_OK) return st;
+    g->np = np;
+    return PSA_OK;
 }
 
 psa_status host_graph_from_edges(int32_t n, int64_t m, const int32_t *u, const int32_t *v,
@@ -261,6 +293,8 @@ psa_status upload_graph(psa_ctx *ctx, HostGraph &&hg, psa_graph **out) {
     }
     std::unique_ptr<psa_graph, void (*)(psa_graph *)> g(new psa_graph(), graph_release);
     g->ctx = ctx;
+    ctx_retain(ctx);
+    g->retained = true;
     g->info = hg.info;
     psa_status st;
     if ((st = upload(&g->d_row_ptr, hg.rp32)) != PSA_OK) return st;
@@ -283,6 +317,8 @@ psa_status upload_graph(psa_ctx *ctx, HostGraph &&hg, psa_graph **out) {
     g->dev.ux16 = g->d_ux16;
     g->dev.w2 = hg.w2;
     g->row_ptr_host = std::move(hg.rp32);
+    g->col_host = std::move(hg.col);
+    g->val_host = std::move(hg.val);
     *out = g.release();
     return PSA_OK;
 }

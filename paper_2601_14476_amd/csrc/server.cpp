@@ -91,7 +91,8 @@ struct psa_server {
     std::vector<ServerJob *> resident;
     std::unordered_map<uint64_t, std::unique_ptr<ServerJob>> jobs;
     uint64_t next_ticket = 1;
-    size_t used_bytes = 0;
+    size_t used_bytes = 0, peak_used = 0;
+    int32_t peak_resident = 0;
     int64_t completed = 0, failed = 0, canceled = 0, quanta = 0;
     bool stop = false;
     std::thread worker;
@@ -217,6 +218,8 @@ void scheduler(psa_server *s) {
             }
             j->status = PSA_JOB_RUNNING;
             s->resident.push_back(j);
+            s->peak_resident = std::max(s->peak_resident, static_cast<int32_t>(s->resident.size()));
+            s->peak_used = std::max(s->peak_used, s->used_bytes);
         }
         if (s->resident.empty()) {
             if (s->stop) break;
@@ -456,6 +459,8 @@ psa_status psa_server_stats_get(psa_server *s, psa_server_stats *out) {
     out->quanta = s->quanta;
     out->used_bytes = static_cast<int64_t>(s->used_bytes);
     out->budget_bytes = s->opts.hbm_budget_bytes;
+    out->peak_resident = s->peak_resident;
+    out->peak_used_bytes = static_cast<int64_t>(s->peak_used);
     return PSA_OK;
 }
 

@@ -34,6 +34,7 @@ PSA_GRAPH_MAXCUT = 1
 PSA_OUT_HOST = 0
 PSA_OUT_DEVICE = 1
 PSA_BATCH_SEQUENTIAL = 2
+PSA_PATH_AUTO, PSA_PATH_CSR, PSA_PATH_DENSE = 0, 1, 2
 
 _P = ctypes.c_void_p
 _i32, _i64, _u32, _u64, _f64 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
@@ -72,7 +73,7 @@ class psa_result(ctypes.Structure):
 class psa_server_stats(ctypes.Structure):
     _fields_ = [("waiting", _i32), ("resident", _i32), ("completed", _i64), ("failed", _i64),
                 ("canceled", _i64), ("quanta", _i64), ("used_bytes", _i64),
-                ("budget_bytes", _i64)]
+                ("budget_bytes", _i64), ("peak_resident", _i32), ("peak_used_bytes", _i64)]
 
 
 # (name, restype, argtypes) of every exported entry point in include/psa.h
@@ -295,7 +296,7 @@ def variability_draw(n, seed, sigma_lambda=0.0, sigma_delta=0.0, sigma_nu=0.0, p
 def make_desc(steps, trials, seed=0, i0=None, i0_min=None, i0_max=None,
               sigma_lambda=0.0, sigma_delta=0.0, sigma_nu=0.0, p_mean=1.0,
               lam=None, delta=None, thr24=None, block=0, trials_per_group=0,
-              lanes_per_task=0):
+              lanes_per_task=0, path=PSA_PATH_AUTO):
     """Build a psa_run_desc; returns (desc, keepalive arrays)."""
     d = psa_run_desc()
     _lib.psa_run_desc_default(ctypes.byref(d))
@@ -318,6 +319,7 @@ def make_desc(steps, trials, seed=0, i0=None, i0_min=None, i0_max=None,
     d.block = int(block)
     d.trials_per_group = int(trials_per_group)
     d.lanes_per_task = int(lanes_per_task)
+    d.flags = int(path)
     return d, keep
 
 

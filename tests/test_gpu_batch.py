@@ -139,3 +139,24 @@ def test_batch_rejects_bad_input(psa, ctx):
         psa.jobs_step_batch(ctx, [job, job], 3)        # listed twice
     with pytest.raises(psa.PsaError):
         psa.anneal_batch(ctx, [(g, 0, 2, 0, {})])       # steps < 1
+
+
+def test_batch_mixes_dense_and_csr_jobs(psa, ctx):
+    """Dense-path and CSR-path jobs advanced together give the results of
+    each alone."""
+    specs = [(inputs.erdos_renyi(700, 0.2, 51), psa.PSA_PATH_DENSE, 64, 30),
+             (inputs.gnm(900, 2700, 52), psa.PSA_PATH_CSR, 10, 45),
+             (inputs.erdos_renyi(200, 0.5, 53), psa.PSA_PATH_DENSE, 20, 38),
+             (inputs.torus(8, 9, 54), psa.PSA_PATH_AUTO, 3, 12)]
+    jobs, refs = [], []
+    for (n, u, v, w), path, T, S in specs:
+        g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
+        jobs.append(psa.Job(ctx, g, S, T, 5, path=path, sigma_nu=0.1, p_mean=0.8))
+        ref = psa.Job(ctx, g, S, T, 5, path=psa.PSA_PATH_CSR, sigma_nu=0.1, p_mean=0.8)
+        ref.step(S)
+        refs.append(ref)
+    while any(j.position < j.steps for j in jobs):
+        psa.jobs_step_batch(ctx, [j for j in jobs if j.position < j.steps], 11)
+    for j, r in zip(jobs, refs):
+        np.testing.assert_array_equal(j.read_spins(), r.read_spins())
+        np.testing.assert_array_equal(j.energy_cut()[0], r.energy_cut()[0])

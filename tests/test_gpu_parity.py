@@ -357,3 +357,63 @@ def test_edge_encodings_match_oracle(psa, ctx, kind, tpw, lpt):
     E, C = job.energy_cut()
     np.testing.assert_array_equal(E, ref[1])
     np.testing.assert_array_equal(C, ref[2])
+
+
+@pytest.mark.parametrize("n,trials,kind", [(1, 3, "unit"), (63, 7, "int"), (64, 16, "unit"),
+                                           (65, 33, "int"), (300, 64, "unit"), (1000, 100, "int"),
+                                           (257, 1, "unit")])
+def test_dense_path_matches_oracle(psa, ctx, n, trials, kind):
+    """Dense int8 matrix-core path against the oracle and against the CSR
+    path: identical spins, energies and cuts."""
+    if kind == "unit":
+        if n > 1:
+            _, u, v, w = inputs.erdos_renyi(n, 0.3, 40 + n, weights="pm1")
+        else:
+            u = v = w = np.zeros(0, np.int32)
+        j, h = -w, None
+    else:
+        n, u, v, j, h = _random_ising(n, 4 * n, 41 + n, jmax=5)
+    g = psa.Graph.from_edges(ctx, n, u, v, j, h=h, maxcut=False)
+    S = 20
+    i0 = oracle.schedule(S, 0.01, 0.4)
+    kw = dict(i0=i0, sigma_lambda=0.1, sigma_delta=0.2, sigma_nu=0.1, p_mean=0.8)
+    dense = psa.Job(ctx, g, S, trials, 7, path=psa.PSA_PATH_DENSE, **kw)
+    csr = psa.Job(ctx, g, S, trials, 7, path=psa.PSA_PATH_CSR, **kw)
+    dense.step(7)
+    dense.step(13)
+    csr.step(S)
+    np.testing.assert_array_equal(dense.read_spins(), csr.read_spins())
+    lam, dl, thr = oracle.variability(n, 7, 0.1, 0.2, 0.1, 0.8)
+    k = min(trials, 3)
+    ref = oracle.anneal(n, u, v, j, h, i0, lam, dl, thr, 7, 0, k)
+    np.testing.assert_array_equal(dense.read_spins()[:k], ref[0])
+    E, C = dense.energy_cut()
+    np.testing.assert_array_equal(E[:k], ref[1])
+    np.testing.assert_array_equal(C[:k], ref[2])
+
+
+def test_dense_path_rejects_wide_couplings(psa, ctx):
+    u = np.array([0], np.int32)
+    v = np.array([1], np.int32)
+    g = psa.Graph.from_edges(ctx, 2, u, v, np.array([300], np.int32), maxcut=False)
+    with pytest.raises(psa.PsaError) as e:
+        psa.Job(ctx, g, 5, 2, 0, i0_min=0.001, i0_max=0.01, path=psa.PSA_PATH_DENSE)
+    assert e.value.status == psa.PSA_EUNSUPPORTED
+
+
+def test_objects_outlive_their_creators_handles(psa):
+    """The context and graph stay alive while a job needs them: dropping the
+    creator's handles first must neither crash nor change results."""
+    n, u, v, w = inputs.gnm(300, 900, 3)
+    c = psa.Context(0)
+    g = psa.Graph.from_edges(c, n, u, v, w)
+    job = psa.Job(c, g, 20, 5, 1)
+    ref = psa.Job(c, g, 20, 5, 1)
+    ref.step(20)
+    expect = ref.read_spins()
+    ref.close()
+    g.close()
+    c.close()                 # job still holds both
+    job.step(20)
+    np.testing.assert_array_equal(job.read_spins(), expect)
+    job.close()

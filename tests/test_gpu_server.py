@@ -83,11 +83,8 @@ def test_budget_serialises_and_rejects(psa):
     srv = psa.Server(ctx, hbm_budget_bytes=budget, quantum_steps=25)
     tickets = [_submit(srv, sp, spins=False) for sp in specs]
     big = srv.submit(*inputs.gnm(20000, 60000, 9), 10, 200, 1)      # alone above budget
-    seen_resident, seen_used = 0, 0
     while True:
         st = srv.stats()
-        seen_resident = max(seen_resident, st["resident"])
-        seen_used = max(seen_used, st["used_bytes"])
         if st["completed"] + st["failed"] >= 4:
             break
         time.sleep(0.001)
@@ -97,7 +94,7 @@ def test_budget_serialises_and_rejects(psa):
         np.testing.assert_array_equal(C, _alone(psa, ctx, sp)[2])
     r = srv.wait(big)
     assert r.status == psa.PSA_JOB_ERROR and r.error == psa.PSA_ENOMEM
-    assert 1 <= seen_resident < 3 and seen_used <= budget
+    assert 1 <= st["peak_resident"] < 3 and 0 < st["peak_used_bytes"] <= budget
     srv.close()
     ctx.close()
 
