@@ -47,6 +47,7 @@ OPS_DECIDE = 2         # compare with r, select
 # MI355X: 256 CUs x 4 SIMD x 16 lanes, one 32-bit VALU op per lane per clock
 # at 2.4 GHz (the 157.3 TFLOP/s FP32 figure counts an FMA as 2 and dual issue).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+MFMA_I8_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak, TOP/s
 
 
 def ops_per_update(mean_degree: float, timing: bool) -> float:
@@ -100,6 +101,8 @@ def main():
     ap.add_argument("--duration", type=float, default=20.0, help="c5: seconds of arrivals")
     ap.add_argument("--quantum", type=int, default=250, help="c5: steps per scheduling quantum")
     ap.add_argument("--max-resident", type=int, default=128, help="c5: resident job slots")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="c5: cost-model path choice instead of the autotuner")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--tpw", type=int, default=0, help="trials per workgroup (0 = auto)")
     ap.add_argument("--lpt", type=int, default=0, help="lanes per 4-p-bit task (0 = auto)")
@@ -219,8 +222,11 @@ def main():
 def bench_batch(args):
     """256 graphs of uneven size (n in [800, 5000]; half G(n, p) with +1
     weights, p in [0.02, 0.1]; half random degree 4-8 with +-1 weights), 64
-    trials, 1,000 sweeps each, all resident: one batched launch per step
-    versus the same jobs one graph at a time on the same stream."""
+    trials, 1,000 sweeps each, all resident.  Path and launch shape of every
+    job come from the autotuner (batched mode, per shape class; tuning time
+    is reported apart, as set-up).  One batched launch per step sequence
+    versus the same anneals one graph at a time (each tuned for running
+    alone) on the same stream."""
     import torch
     from paper_2601_14476_amd import inputs, psa
     specs = inputs.batch_jobs()
@@ -228,21 +234,36 @@ def bench_batch(args):
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     ctx = psa.Context(0, stream)
-    graphs, jobs, outs = [], [], []
+    graphs, jobs, alone, outs = [], [], [], []
     updates = 0
-    ops = 0.0
+    valu_ops = 0.0
+    mfma_ops = 0.0
+    dense_jobs = 0
+    t_tune = 0.0
     for sp in specs:
         n, u, v, w = inputs.make_graph(sp["graph"])
         g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
         info = g.info()
-        job = psa.Job(ctx, g, sp["steps"], sp["trials"], sp["seed"], trials_per_group=1)
+        t0 = time.perf_counter()
+        rb = psa.tune_get(ctx, g, sp["steps"], sp["trials"], sp["seed"], batch=True)
+        ra = psa.tune_get(ctx, g, sp["steps"], sp["trials"], sp["seed"], batch=False)
+        t_tune += time.perf_counter() - t0
+        kb = psa.tune_kwargs(rb)
+        if kb["trials_per_group"] == 0:
+            kb["trials_per_group"] = 1
+        jobs.append(psa.Job(ctx, g, sp["steps"], sp["trials"], sp["seed"], **kb))
+        alone.append(psa.Job(ctx, g, sp["steps"], sp["trials"], sp["seed"], **psa.tune_kwargs(ra)))
         graphs.append(g)
-        jobs.append(job)
         outs.append((torch.empty(sp["trials"], dtype=torch.int64, device="cuda"),
                      torch.empty(sp["trials"], dtype=torch.int64, device="cuda")))
         upd = n * sp["trials"] * sp["steps"]
         updates += upd
-        ops += ops_per_update(info["nnz"] / n, False) * upd
+        if rb["path"] == psa.PSA_PATH_DENSE:
+            dense_jobs += 1
+            valu_ops += ops_per_update(0.0, False) * upd
+            mfma_ops += 2.0 * n * n * sp["trials"] * sp["steps"]
+        else:
+            valu_ops += ops_per_update(info["nnz"] / n, False) * upd
     S = max(sp["steps"] for sp in specs)
 
     def batched(ev=None):
@@ -257,7 +278,7 @@ def bench_batch(args):
             j.energy_cut(E, C)
 
     def sequential():
-        for j, (E, C) in zip(jobs, outs):
+        for j, (E, C) in zip(alone, outs):
             j.reset()
             j.step(S)
             j.energy_cut(E, C)
@@ -282,7 +303,7 @@ def bench_batch(args):
     wall_seq = time.perf_counter() - t0
     same = all(np.array_equal(a, c.cpu().numpy()) for a, (_, c) in zip(cuts_batched, outs))
     value = updates * args.steps / wall
-    achieved = ops / (kernel_ms * 1e-3) / 1e12
+    achieved = valu_ops / (kernel_ms * 1e-3) / 1e12
     line = {
         "metric": "p-bit updates/s (n x trials x steps / s), 1 GPU",
         "value": value,
@@ -298,15 +319,18 @@ def bench_batch(args):
         "data": "synthetic",
         "config": {
             "workload": "c4", "graphs": len(specs), "trials": 64, "sweeps": S,
-            "updates_per_batch": updates,
+            "updates_per_batch": updates, "dense_path_jobs": dense_jobs,
+            "tune_classes": psa.tune_cache_size(ctx), "tune_s": t_tune,
             "one_graph_at_a_time_updates_per_s": updates / wall_seq,
             "batched_over_one_at_a_time": wall_seq / (wall / args.steps),
             "identical_cuts": same,
         },
         "roofline": {
-            "bound": "alu", "kernel": "anneal_batch_kernel", "achieved": achieved,
-            "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
-            "traffic": None, "kernel_ms": kernel_ms,
+            "bound": "alu", "kernel": "anneal_batch_kernel + dense_step_kernel",
+            "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+            "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel_ms": kernel_ms,
+            "mfma_int8_achieved_tops": mfma_ops / (kernel_ms * 1e-3) / 1e12,
+            "mfma_int8_peak_tops": MFMA_I8_PEAK_TOPS,
         },
     }
     print(json.dumps(line), flush=True)
@@ -351,13 +375,30 @@ def bench_serve(args):
             n, u, v, w = pick(spec)
             tk = srv.submit(n, u, v, w, spec["steps"], spec["trials"], spec["seed"],
                             sigma_lambda=spec["sigma_lambda"], sigma_delta=spec["sigma_delta"],
-                            sigma_nu=spec["sigma_nu"], p_mean=spec["p_mean"])
+                            sigma_nu=spec["sigma_nu"], p_mean=spec["p_mean"],
+                            tune=not args.no_tune)
             tickets.append(tk)
             updates.append(n * spec["trials"] * spec["steps"])
 
     th = threading.Thread(target=client)
     th.start()
     th.join()
+    # progress while the queue drains (one line every ~20 s)
+    last = time.perf_counter()
+    for i, tk in enumerate(tickets):
+        while True:
+            try:
+                srv.wait(tk, timeout_s=5.0)
+                break
+            except psa.PsaError as e:
+                if e.status != psa.PSA_ETIMEDOUT:
+                    raise
+            if time.perf_counter() - last > 20.0:
+                st = srv.stats()
+                print(f"[c5] {time.perf_counter() - t0:.0f}s completed {st['completed']}/"
+                      f"{len(tickets)} resident {st['resident']} waiting {st['waiting']}",
+                      file=sys.stderr, flush=True)
+                last = time.perf_counter()
     lat = []
     first_submit, last_end = None, 0
     done = 0
@@ -395,6 +436,7 @@ def bench_serve(args):
             "served_updates_per_s": float(sum(updates) / makespan),
             "offered_updates_per_s": float(sum(updates) / args.duration),
             "makespan_s": makespan, "quanta": stats["quanta"],
+            "autotuned": not args.no_tune,
         },
     }
     print(json.dumps(line), flush=True)

@@ -194,13 +194,20 @@ typedef struct psa_run_desc {
 
 /* Field-computation path of a run (psa_run_desc.flags).  AUTO picks by a
  * cost model (long rows -> dense); CSR walks the sparse rows from LDS /
- * L2; DENSE multiplies the dense int8 coupling matrix with the spins of all
- * trials on the matrix cores (every |J_ij| <= 127; EUNSUPPORTED otherwise).
- * Results are identical on every path. */
+ * L2; DENSE multiplies the dense coupling matrix with the spins of all
+ * trials on the int8 matrix cores.  The dense matrix is stored as 2-bit
+ * fields times one scale when every stored coupling has the same magnitude
+ * (unit and +-1 weights), else as int8 (every |J_ij| <= 127; EUNSUPPORTED
+ * otherwise).  Results are identical on every path. */
 #define PSA_PATH_AUTO 0u
 #define PSA_PATH_CSR 1u
 #define PSA_PATH_DENSE 2u
 #define PSA_PATH_MASK 3u
+/* With PSA_PATH_AUTO: take path and launch shape from the context's tuning
+ * cache, measuring them with psa_autotune on a miss (alone for
+ * psa_job_create / psa_anneal, batched inside psa_anneal_batch and the
+ * server).  Launch shape never changes results. */
+#define PSA_TUNE 4u
 
 /* Fill *d with the defaults: steps 1000, trials 1, seed 0, the paper's I0
  * endpoints (i0_min = i0_max = -1), no variability (sigmas 0, p_mean 1),
@@ -263,9 +270,11 @@ psa_status psa_anneal(psa_ctx *ctx, const psa_graph *g,
 
 /* Advance every job of `jobs` (all created on ctx, each listed once) by up
  * to k steps, clipped to each job's schedule, with one launch of the batch
- * kernel on the context's stream: one work item per (job, trial), each
- * workgroup dispatching to the kernel variant its job needs.  The results
- * are identical to stepping each job alone. */
+ * kernel on the context's stream: one work item per (job, trial) -- or per
+ * (job, group of four trials) for jobs created with trials_per_group 4 --
+ * each workgroup dispatching to the kernel variant its job needs.  Jobs on
+ * the dense path advance on a second stream, joined before return.  The
+ * results are identical to stepping each job alone. */
 psa_status psa_jobs_step_batch(psa_ctx *ctx, int32_t count, psa_job *const *jobs,
                                int32_t k);
 
@@ -288,6 +297,54 @@ typedef struct psa_batch_item {
  * Blocks until the results are written. */
 psa_status psa_anneal_batch(psa_ctx *ctx, int32_t count,
                             const psa_batch_item *items, uint32_t flags);
+
+/* ------------------------------------------------------------------ */
+/* Autotuning (measured choice of path and launch shape)                 */
+/* ------------------------------------------------------------------ */
+
+/* What to tune for: one run alone (latency of its steps), or a run inside
+ * batched launches (device time per run and step while other runs fill the
+ * chip; timed on enough copies of the run to fill it). */
+#define PSA_TUNE_ALONE 0u
+#define PSA_TUNE_BATCH 1u
+
+typedef struct psa_tune_result {
+    uint32_t path;             /* PSA_PATH_CSR or PSA_PATH_DENSE            */
+    int32_t trials_per_group;  /* CSR alone: 1 or 4; 0 = automatic          */
+    int32_t lanes_per_task;    /* CSR: 1, 2 or 4; 0 = automatic              */
+    int32_t candidates;        /* configurations timed                      */
+    double us_per_step;        /* best measured, microseconds per run-step  */
+    double csr_us_per_step;    /* best CSR configuration (< 0: none ran)    */
+    double dense_us_per_step;  /* dense path (< 0: not applicable)          */
+    double model_csr_us;       /* the cost model's estimates, for reference */
+    double model_dense_us;     /* (< 0: not applicable)                     */
+} psa_tune_result;
+
+/* Time every applicable configuration -- CSR with one trial per workgroup
+ * at 1, 2 or 4 lanes per task (2 or 4 when batched), CSR with four trials
+ * per workgroup, and the dense path when the couplings have a dense
+ * encoding -- on
+ * scratch runs of `desc` (same graph, trials, schedule and factors) over
+ * `probe_steps` steps (>= 1, clipped to the schedule) after one warm-up
+ * step, and return the fastest.  The result is also stored in the
+ * context's tuning cache, keyed by mode, trials and the graph's shape class
+ * (n and mean degree within about 9 % and 19 %, coupling encoding, rows of
+ * at most 255 entries), for PSA_TUNE.  Queues and waits on the context's
+ * stream; the caller's jobs are not touched. */
+psa_status psa_autotune(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *desc,
+                        int32_t probe_steps, uint32_t mode, psa_tune_result *out);
+
+/* The tuning cache's entry for (g, desc->trials, mode); on a miss,
+ * psa_autotune with 8 probe steps (which stores it). */
+psa_status psa_tune_get(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *desc,
+                        uint32_t mode, psa_tune_result *out);
+
+/* Copy a tuning result's path and launch shape into a run description. */
+void psa_tune_apply(const psa_tune_result *r, psa_run_desc *desc);
+
+/* Entries in the context's tuning cache; psa_tune_clear empties it. */
+int32_t psa_tune_cache_size(psa_ctx *ctx);
+void psa_tune_clear(psa_ctx *ctx);
 
 /* ------------------------------------------------------------------ */
 /* Serving with continuous batching                                     */

@@ -31,16 +31,6 @@ using psa::set_error;
 
 namespace {
 
-psa_status hip_fail(hipError_t err, const char *what) {
-    set_error(std::string(what) + ": " + hipGetErrorString(err));
-    return PSA_EHIP;
-}
-
-#define PSA_HIP(expr, what)                          \
-    do {                                             \
-        hipError_t _e = (expr);                      \
-        if (_e != hipSuccess) return hip_fail(_e, what); \
-    } while (0)
 
 template <typename T>
 psa_status dev_upload(T **dst, const T *src, size_t count, const char *what) {
@@ -54,7 +44,7 @@ psa_status dev_upload(T **dst, const T *src, size_t count, const char *what) {
     }
     if (src) {
         e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
-        if (e != hipSuccess) return hip_fail(e, what);
+        if (e != hipSuccess) return psa::hip_fail(e, what);
     }
     return PSA_OK;
 }
@@ -285,9 +275,16 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
         set_error("psa_job_create: lanes_per_task must be 0, 1, 2 or 4");
         return PSA_EINVAL;
     }
-    if ((desc->flags & ~PSA_PATH_MASK) != 0 || (desc->flags & PSA_PATH_MASK) == PSA_PATH_MASK) {
+    if ((desc->flags & ~(PSA_PATH_MASK | PSA_TUNE)) != 0 ||
+        (desc->flags & PSA_PATH_MASK) == PSA_PATH_MASK) {
         set_error("psa_job_create: unknown flags");
         return PSA_EINVAL;
+    }
+    if (desc->flags & PSA_TUNE) {
+        psa_run_desc tuned = *desc;
+        psa_status st = psa::tuned_desc(ctx, g, &tuned, PSA_TUNE_ALONE);
+        if (st != PSA_OK) return st;
+        return psa_job_create(ctx, g, &tuned, out);
     }
     const int32_t S = desc->steps;
     std::vector<float> i0(static_cast<size_t>(S));
@@ -348,7 +345,7 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
             j->plan.dense = 1;  // too large for the LDS-resident sweep
         }
     }
-    if (path == PSA_PATH_DENSE || (path == PSA_PATH_AUTO && psa::prefer_dense(g->dev, j->run)))
+    if (path == PSA_PATH_DENSE || (path == PSA_PATH_AUTO && psa::prefer_dense(g, j->run, j->plan)))
         j->plan.dense = 1;
     if (j->plan.dense) {
         psa_status st = psa::ensure_dense_matrix(const_cast<psa_graph *>(g));

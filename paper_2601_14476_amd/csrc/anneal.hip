@@ -504,6 +504,11 @@ __global__ __launch_bounds__(BLOCK) void anneal_batch_kernel(const BatchJob *__r
         case kBatchP32Lds2: anneal_body<1, 2, kCsrPack32, true, BLOCK>(a, w.y, smem); break;
         case kBatchP32Glb2: anneal_body<1, 2, kCsrPack32, false, BLOCK>(a, w.y, smem); break;
         case kBatchPairGlb2: anneal_body<1, 2, kCsrPair, false, BLOCK>(a, w.y, smem); break;
+        case kBatchP16Lds4T: anneal_body<4, 1, kCsrPack16, true, BLOCK>(a, w.y, smem); break;
+        case kBatchP16Glb4T: anneal_body<4, 1, kCsrPack16, false, BLOCK>(a, w.y, smem); break;
+        case kBatchP32Lds4T: anneal_body<4, 1, kCsrPack32, true, BLOCK>(a, w.y, smem); break;
+        case kBatchP32Glb4T: anneal_body<4, 1, kCsrPack32, false, BLOCK>(a, w.y, smem); break;
+        case kBatchPairGlb4T: anneal_body<4, 1, kCsrPair, false, BLOCK>(a, w.y, smem); break;
         default: break;
     }
 }
@@ -661,9 +666,23 @@ void fill_anneal_args(AnnealArgs *a, const DevGraph &g, const DevRun &run, const
     a->spins = run.spins;
 }
 
-bool plan_batch_item(const DevGraph &g, const DevRun &run, int32_t lpt_req, size_t max_lds,
-                     AnnealPlan *plan, int32_t *variant, std::string *why) {
+bool plan_batch_item(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t lpt_req,
+                     size_t max_lds, AnnealPlan *plan, int32_t *variant, std::string *why) {
     AnnealPlan p;
+    if (tpw_req == 4) {
+        if (!plan_anneal(g, run, 4, 1, 0, max_lds, 1 << 30, &p, why)) return false;
+        if (p.csr == kCsrPack16) {
+            *variant = p.csr_lds ? kBatchP16Lds4T : kBatchP16Glb4T;
+        } else if (p.csr == kCsrPack32) {
+            *variant = p.csr_lds ? kBatchP32Lds4T : kBatchP32Glb4T;
+        } else {
+            *variant = kBatchPairGlb4T;
+            p.csr_lds = 0;
+            p.lds_bytes = 2 * spin_buf_bytes(g.n4, 4, kCsrPair);
+        }
+        *plan = p;
+        return true;
+    }
     if (!plan_anneal(g, run, 1, lpt_req == 4 ? 4 : 2, 0, max_lds, 1 << 30, &p, why)) return false;
     if (p.csr == kCsrUnit) {
         *variant = p.lpt == 4 ? (p.csr_lds ? kBatchUnitLds4 : kBatchUnitGlb4)

@@ -26,16 +26,6 @@ namespace {
 constexpr int kXcds = 8;
 constexpr int kChunk = 16;  // work items placed on one XCD together
 
-psa_status hip_fail(hipError_t err, const char *what) {
-    set_error(std::string(what) + ": " + hipGetErrorString(err));
-    return PSA_EHIP;
-}
-
-#define PSA_HIP(expr, what)                               \
-    do {                                                  \
-        hipError_t _e = (expr);                           \
-        if (_e != hipSuccess) return hip_fail(_e, what);  \
-    } while (0)
 
 // Grow-only device buffer kept by the context between batched launches.
 psa_status ensure(void **buf, size_t *cap, size_t bytes) {
@@ -92,37 +82,87 @@ void build_work_list(const std::vector<int32_t> &trials, const std::vector<doubl
 // lane-ops/s; the dense product costs 2 np^2 tp int8 MACs at ~2.5 P ops/s
 // effective, or np^2 bytes of J per trial tile at ~4 TB/s, whichever is
 // larger, plus ~60 lane-operations of epilogue per update.
-bool prefer_dense(const DevGraph &g, const DevRun &run) {
-    if (g.n < 256) return false;
-    const double n = g.n, T = run.t4, d = g.nnz / static_cast<double>(g.n);
-    const double np = (g.n + 63) / 64 * 64;
-    const int32_t nb = run.t4 >= 64 ? 4 : (run.t4 >= 32 ? 2 : 1);
-    const double tp = std::ceil(T / (16.0 * nb)) * 16.0 * nb;
-    const double csr = n * T * (60.0 + 3.0 * d) / 39.3e12;
-    const double mfma = 2.0 * np * np * tp / 2.5e15;
-    const double bytes = np * np * (tp / (16.0 * nb)) / 4.0e12;
-    const double dense = std::max(mfma, bytes) + n * T * 60.0 / 39.3e12;
-    return dense < 0.7 * csr;
+double csr_step_seconds(const DevGraph &g, const DevRun &run, const AnnealPlan &plan) {
+    // lane-ops per update: RNG, activation and decision (about 60), plus a
+    // gather per edge: a few ops from LDS, tens when the rows stream from
+    // memory (latency-bound gathers of one trial per workgroup)
+    const double d = g.nnz / static_cast<double>(std::max(g.n, 1));
+    const double per_edge = plan.csr_lds ? 3.0 : 40.0;
+    return static_cast<double>(g.n) * run.t4 * (60.0 + per_edge * d) / kValuOpsPerSecond;
+}
+
+double dense_step_seconds(int32_t n, int32_t t4, bool two_bit) {
+    const double np = (n + 127) / 128 * 128;
+    const int32_t nb = t4 >= 64 ? 4 : (t4 >= 32 ? 2 : 1);
+    const double tp = std::ceil(t4 / (16.0 * nb)) * 16.0 * nb;
+    const double mfma = 2.0 * np * np * tp / (0.5 * kMfmaI8OpsPerSecond);
+    const double bytes = np * np * (two_bit ? 0.25 : 1.0) * (tp / (16.0 * nb)) / kHbmBytesPerSecond;
+    return std::max(mfma, bytes) + static_cast<double>(n) * t4 * 60.0 / kValuOpsPerSecond;
+}
+
+bool dense_two_bit(const psa_graph *g) {
+    int32_t mag = 0;
+    for (int32_t v : g->val_host) {
+        const int32_t a = v < 0 ? -v : v;
+        if (mag == 0) mag = a;
+        if (a != mag) return false;
+    }
+    return true;
+}
+
+bool prefer_dense(const psa_graph *g, const DevRun &run, const AnnealPlan &plan) {
+    if (g->info.n < 256) return false;
+    const bool two_bit = dense_two_bit(g);
+    if (!two_bit && std::any_of(g->val_host.begin(), g->val_host.end(),
+                                [](int32_t v) { return v < -127 || v > 127; }))
+        return false;
+    return dense_step_seconds(g->info.n, run.t4, two_bit) < 0.7 * csr_step_seconds(g->dev, run, plan);
+}
+
+// Work list of the dense runs `idx` of `table` (one encoding): items (job,
+// 256-row group, trial tile) in chunks of up to 16 consecutive row groups of
+// one trial tile, each chunk given whole to the least loaded of the 8 XCDs,
+// heaviest runs first.  Workgroup b of a launch runs on XCD b % 8, so slot b
+// takes item b / 8 of that XCD's queue (or an empty slot): a run's chunk
+// shares its spin tile in one L2.
+static void dense_work_list(const std::vector<DenseJob> &table, const std::vector<int32_t> &idx,
+                            int32_t nb, std::vector<int4> *out) {
+    constexpr int32_t kXcd = 8, kChunk = 16;
+    std::vector<int32_t> order(idx);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const DenseJob &x = table[a], &y = table[b];
+        return static_cast<double>(x.np) * x.np * x.tp > static_cast<double>(y.np) * y.np * y.tp;
+    });
+    std::vector<std::vector<int4>> bins(kXcd);
+    std::vector<double> load(kXcd, 0.0);
+    for (int32_t j : order) {
+        const DenseJob &d = table[j];
+        const int32_t groups = (d.np + 255) / 256, tiles = d.tp / (16 * nb);
+        for (int32_t tt = 0; tt < tiles; ++tt)
+            for (int32_t g0 = 0; g0 < groups; g0 += kChunk) {
+                const int32_t g1 = std::min(groups, g0 + kChunk);
+                const int32_t x = static_cast<int32_t>(std::min_element(load.begin(), load.end()) - load.begin());
+                for (int32_t g = g0; g < g1; ++g) bins[x].push_back(make_int4(j, g, tt, 0));
+                load[x] += static_cast<double>(g1 - g0) * d.np;
+            }
+    }
+    size_t len = 0;
+    for (const auto &b : bins) len = std::max(len, b.size());
+    out->assign(len * kXcd, make_int4(-1, 0, 0, 0));
+    for (int32_t x = 0; x < kXcd; ++x)
+        for (size_t q = 0; q < bins[x].size(); ++q) (*out)[q * kXcd + x] = bins[x][q];
 }
 
 psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, int32_t k) {
     std::vector<psa::DenseJob> table;
-    std::vector<int4> work;
     std::vector<psa_job *> live;
-    int32_t max_steps = 0, nb = 4;
+    std::vector<int32_t> by_enc[2];
+    int32_t max_steps = 0, nb[2] = {4, 4};
     for (int32_t j = 0; j < count; ++j) {
         psa_job *job = jobs[j];
-        const int32_t te = static_cast<int32_t>(std::min<int64_t>(int64_t{job->t} + k, job->run.steps));
-        if (te <= job->t) continue;
-        nb = std::min(nb, job->plan.nb);
-        live.push_back(job);
-    }
-    if (live.empty()) return PSA_OK;
-    for (size_t j = 0; j < live.size(); ++j) {
-        psa_job *job = live[j];
         const psa_graph *g = job->g;
         const int32_t te = static_cast<int32_t>(std::min<int64_t>(int64_t{job->t} + k, job->run.steps));
-        const int32_t tile = 16 * nb;
+        if (te <= job->t) continue;
         psa::DenseJob d;
         d.n = g->info.n;
         d.n4 = g->dev.n4;
@@ -131,6 +171,7 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
         d.tp = job->tp;
         d.t = job->t;
         d.t_end = te;
+        d.scale = g->dense_scale;
         d.J = g->d_dense;
         d.m0 = job->d_m;
         d.m1 = job->d_m + static_cast<size_t>(job->tp) * g->np;
@@ -141,11 +182,22 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
         d.thr = job->run.thr24;
         d.k0 = job->run.key0;
         d.k1 = job->run.key1;
+        const int32_t e = g->dense_enc == kDenseT2 ? 1 : 0;
+        by_enc[e].push_back(static_cast<int32_t>(table.size()));
+        nb[e] = std::min(nb[e], job->plan.nb);
         table.push_back(d);
-        for (int32_t tt = 0; tt < job->tp / tile; ++tt)
-            for (int32_t rt = 0; rt < g->np / 64; ++rt)
-                work.push_back(make_int4(static_cast<int32_t>(j), rt, tt, 0));
+        live.push_back(job);
         max_steps = std::max(max_steps, te - job->t);
+    }
+    if (live.empty()) return PSA_OK;
+    std::vector<int4> work, part;
+    size_t off[2] = {0, 0}, len[2] = {0, 0};
+    for (int e = 0; e < 2; ++e) {
+        if (by_enc[e].empty()) continue;
+        dense_work_list(table, by_enc[e], nb[e], &part);
+        off[e] = work.size();
+        len[e] = part.size();
+        work.insert(work.end(), part.begin(), part.end());
     }
     PSA_HIP(hipStreamSynchronize(ctx->stream2), "hipStreamSynchronize");
     psa_status st;
@@ -167,10 +219,14 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
     PSA_HIP(hipMemcpyAsync(ctx->d_dense_work, ctx->h_dense_work.data(), work.size() * sizeof(int4),
                            hipMemcpyHostToDevice, ctx->stream2),
             "dense work upload");
-    PSA_HIP(psa::launch_dense_steps(ctx->stream2, static_cast<const psa::DenseJob *>(ctx->d_dense_table),
-                                    static_cast<const int4 *>(ctx->d_dense_work),
-                                    static_cast<int32_t>(work.size()), nb, max_steps),
-            "dense step launch");
+    const int4 *dwork = static_cast<const int4 *>(ctx->d_dense_work);
+    for (int e = 0; e < 2; ++e) {
+        if (len[e] == 0) continue;
+        PSA_HIP(psa::launch_dense_steps(ctx->stream2, static_cast<const psa::DenseJob *>(ctx->d_dense_table),
+                                        dwork + off[e], static_cast<int32_t>(len[e]), nb[e],
+                                        e == 1 ? kDenseT2 : kDenseI8, max_steps),
+                "dense step launch");
+    }
     for (size_t j = 0; j < live.size(); ++j) {
         psa_job *job = live[j];
         const psa::DenseJob &d = table[j];
@@ -222,8 +278,9 @@ psa_status psa_jobs_step_batch(psa_ctx *ctx, int32_t count, psa_job *const *jobs
         psa::AnnealPlan plan;
         int32_t variant = 0;
         std::string why;
-        if (!psa::plan_batch_item(job->g->dev, job->run, job->plan.tpw == 1 ? job->plan.lpt : 0,
-                                  ctx->max_lds, &plan, &variant, &why)) {
+        if (!psa::plan_batch_item(job->g->dev, job->run, job->plan.tpw,
+                                  job->plan.tpw == 1 ? job->plan.lpt : 0, ctx->max_lds, &plan,
+                                  &variant, &why)) {
             set_error("psa_jobs_step_batch: " + why);
             return PSA_EUNSUPPORTED;
         }
@@ -231,7 +288,7 @@ psa_status psa_jobs_step_batch(psa_ctx *ctx, int32_t count, psa_job *const *jobs
         psa::fill_anneal_args(&bj.a, job->g->dev, job->run, job->d_order, job->t, te);
         bj.variant = variant;
         table.push_back(bj);
-        trials.push_back(job->run.trials);
+        trials.push_back(plan.tpw == 4 ? job->run.t4 / 4 : job->run.trials);  // work items
         cost.push_back(static_cast<double>(job->run.trials) * job->g->dev.n4 * (te - job->t));
         lds = std::max(lds, plan.lds_bytes);
         max_lanes = std::max(max_lanes, job->g->dev.n4 / 4 * plan.lpt);
@@ -298,7 +355,16 @@ psa_status psa_anneal_batch(psa_ctx *ctx, int32_t count, const psa_batch_item *i
     int32_t max_steps = 0;
     for (int32_t j = 0; j < count; ++j) {
         psa_run_desc d = items[j].desc;
-        if (!(flags & PSA_BATCH_SEQUENTIAL)) d.trials_per_group = 1;
+        if (!(flags & PSA_BATCH_SEQUENTIAL)) {
+            if (d.flags & PSA_TUNE) {
+                psa_status st = psa::tuned_desc(ctx, items[j].graph, &d, PSA_TUNE_BATCH);
+                if (st != PSA_OK) {
+                    set_error("psa_anneal_batch: item " + std::to_string(j) + ": " + psa_last_error());
+                    return st;
+                }
+            }
+            if (d.trials_per_group == 0) d.trials_per_group = 1;
+        }
         psa_job *job = nullptr;
         psa_status st = psa_job_create(ctx, items[j].graph, &d, &job);
         if (st != PSA_OK) {

@@ -1,24 +1,38 @@
-// dense.hip -- dense int8 matrix-core path of the local field (gfx950).
+// dense.hip -- dense matrix-core path of the local field (gfx950).
 //
 // For graphs whose rows are long, one synchronous step is a product of the
 // dense coupling matrix with the spins of all trials,
 //     L[i][k] = h_i + sum_j J_ij m_j,k      (int8 x int8 -> int32, exact),
 // computed with v_mfma_i32_16x16x64_i8, followed by the p-bit update of
 // Eq. 6 in the same kernel.  One launch advances one step of every dense run
-// in a work list (run, 64-row tile, trial tile); the step loop is on the
-// host (or in a captured graph of launches), because a step needs the whole
-// previous state of its run.
+// in a work list (run, 256-row group, trial tile); the step loop is on the
+// host, because a step needs the whole previous state of its run.
 //
-// Layouts (per run):
-//   J    int8 [np][np], np = n rounded up to 64, zero padding;
-//   M    int8 [tp][np] per buffer (trial-major, p-bit index contiguous),
-//        tp = trials rounded up to the trial tile; two buffers by step parity.
+// Coupling encodings (per graph, chosen at build time):
+//   kDenseI8  int8 [np][np], row-major, zero padding (any |J| <= 127);
+//   kDenseT2  2-bit fields f in {0, +1, -1} with J = scale * f, for graphs
+//             whose couplings share one magnitude (unit and +-1 weights).
+//             Four times fewer bytes than int8; unpacked to int8 in
+//             registers with v_perm_b32 just before the matrix instruction.
+//   T2 layout: one uint32 per (row i, k-tile c of 64 columns, lane group g of
+//   16 columns), at index (i * np/64 + c) * 4 + g.  Column 64c + 16g + 4d + b
+//   sits in bits 8b + 2d .. 8b + 2d + 1 (d = dword of the operand, b = byte),
+//   so that (word >> 2d) & 0x03030303 is a byte selector for dword d.
+//
+// Spins M: int8 [tp][np] per buffer (trial-major, p-bit index contiguous), tp
+// = trials rounded up to the trial tile; two buffers by step parity.
+//
 // MFMA operand layout (16x16x64, int8): lane l supplies A[row l%16][k (l/16)*16
 // .. +15] and B[k (l/16)*16 .. +15][col l%16] as 16 bytes each, and receives
 // D[row (l/16)*4 + r][col l%16] in its four accumulators r = 0..3.  The four
 // rows of a lane are four consecutive p-bits 4m..4m+3 of one trial: exactly
 // the p-bits one Philox block serves, so the epilogue draws one r block (and
-// one gate block) per lane and trial column.
+// one gate block) per lane, row block and trial column.
+//
+// Workgroup: 4 waves x 64 rows (four 16-row blocks per wave) against one trial
+// tile of 16 NB trials.  The trial tile's spins stream through LDS in chunks
+// of 128 columns (double-buffered, one barrier per chunk); each wave reads its
+// own coupling rows straight from memory, one chunk ahead of the matrix work.
 #include <hip/hip_runtime.h>
 
 #include "device_math.hpp"
@@ -29,106 +43,195 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-constexpr int kRows = 64;            // rows per workgroup (4 waves x 16)
-constexpr int kK = 64;               // K per MFMA
-constexpr int kLdsStride = kK + 16;  // padded LDS row of the B tile (bytes)
+constexpr int kKC = 128;             // columns per LDS chunk (two k-tiles)
+constexpr int kLdsStride = kKC + 16; // padded LDS row of the spin tile (bytes)
+constexpr int kWaveRows = 64;        // four 16-row blocks per wave
+constexpr int kGroupRows = 256;      // rows per workgroup
 
-__device__ __forceinline__ Words4 block_of(uint32_t t, uint32_t m, uint32_t k, uint32_t tag,
-                                           uint32_t k0, uint32_t k1) {
-    return philox4x32_10(t, m, k, tag, k0, k1);
+// byte selector s in {0, 1, 2} -> {0x00, 0x01, 0xFF}, four bytes at once
+__device__ __forceinline__ int32_t t2_dword(uint32_t word, int d) {
+    const uint32_t sel = (word >> (2 * d)) & 0x03030303u;
+    return static_cast<int32_t>(__builtin_amdgcn_perm(0u, 0x00FF0100u, sel));
 }
 
+__device__ __forceinline__ v4i t2_unpack(uint32_t word) {
+    return v4i{t2_dword(word, 0), t2_dword(word, 1), t2_dword(word, 2), t2_dword(word, 3)};
+}
+
+template <int ENC>
+struct AFrag;
+template <>
+struct AFrag<kDenseI8> {
+    v4i v[2][4];
+};
+template <>
+struct AFrag<kDenseT2> {
+    uint32_t v[2][4];
+};
+
 // NB = 16-trial blocks per workgroup (trial tile = 16 NB).
-template <int NB>
+template <int NB, int ENC>
 __global__ __launch_bounds__(256) void dense_step_kernel(const DenseJob *__restrict__ jobs,
                                                          const int4 *__restrict__ work, int32_t t_off) {
-    __shared__ __align__(16) int8_t bt[2][16 * NB * kLdsStride];
-    const int4 w = work[blockIdx.x];  // (job, row tile, trial tile, -)
+    constexpr int kTrials = 16 * NB;
+    constexpr int kBVec = kTrials * (kKC / 16);        // 16-byte pieces of one spin chunk
+    constexpr int kBPer = (kBVec + 255) / 256;
+    __shared__ __align__(16) int8_t bt[2][kTrials * kLdsStride];
+    const int4 w = work[blockIdx.x];  // (job, row group, trial tile, -); job < 0: empty slot
+    if (w.x < 0) return;
     const DenseJob &jb = jobs[w.x];
     const int32_t t = jb.t + t_off;
     if (t >= jb.t_end) return;
     const int32_t np = jb.np;
-    const int32_t row0 = w.y * kRows;
-    const int32_t trial0 = w.z * (16 * NB);
-    const int8_t *__restrict__ J = jb.J;
+    const int32_t trial0 = w.z * kTrials;
     const int8_t *__restrict__ cur = ((t - jb.t) & 1) ? jb.m1 : jb.m0;
     int8_t *__restrict__ nxt = ((t - jb.t) & 1) ? jb.m0 : jb.m1;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int arow = row0 + wave * 16 + (lane & 15);
+    const int lr = lane & 15;
     const int kgrp = (lane >> 4) * 16;
+    const int32_t wrow0 = w.y * kGroupRows + wave * kWaveRows;
+    const bool active = wrow0 < np;  // np is a multiple of 128: a wave is all in or all out
+    const int32_t ktiles = np / 64;
 
-    v4i acc[NB];
+    int4 breg[kBPer];
+    auto fetch_b = [&](int kc) {
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[nb] = v4i{0, 0, 0, 0};
-
-    // cooperative B-tile load: 16*NB trial rows x 64 bytes, 16 bytes a thread
-    auto load_b = [&](int buf, int k0) {
-        for (int c = threadIdx.x; c < 16 * NB * 4; c += 256) {
-            const int tr = c >> 2, part = (c & 3) * 16;
-            const int4 v = *reinterpret_cast<const int4 *>(cur + static_cast<size_t>(trial0 + tr) * np + k0 + part);
-            *reinterpret_cast<int4 *>(&bt[buf][tr * kLdsStride + part]) = v;
+        for (int q = 0; q < kBPer; ++q) {
+            const int c = static_cast<int>(threadIdx.x) + q * 256;
+            if (kBVec % 256 == 0 || c < kBVec) {
+                const int tr = c >> 3, part = (c & 7) * 16;
+                breg[q] = *reinterpret_cast<const int4 *>(cur + static_cast<size_t>(trial0 + tr) * np +
+                                                          kc * kKC + part);
+            }
         }
     };
-    load_b(0, 0);
+    auto store_b = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < kBPer; ++q) {
+            const int c = static_cast<int>(threadIdx.x) + q * 256;
+            if (kBVec % 256 == 0 || c < kBVec) {
+                const int tr = c >> 3, part = (c & 7) * 16;
+                *reinterpret_cast<int4 *>(&bt[buf][tr * kLdsStride + part]) = breg[q];
+            }
+        }
+    };
+    auto fetch_a = [&](int kc, AFrag<ENC> &dst) {
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const size_t row = static_cast<size_t>(wrow0 + rb * 16 + lr);
+                if constexpr (ENC == kDenseI8) {
+                    const int8_t *J = static_cast<const int8_t *>(jb.J);
+                    dst.v[kt][rb] = *reinterpret_cast<const v4i *>(J + row * np + kc * kKC + kt * 64 + kgrp);
+                } else {
+                    const uint32_t *J = static_cast<const uint32_t *>(jb.J);
+                    dst.v[kt][rb] = J[(row * ktiles + kc * 2 + kt) * 4 + (lane >> 4)];
+                }
+            }
+    };
+
+    v4i acc[4][NB];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[rb][nb] = v4i{0, 0, 0, 0};
+
+    auto compute = [&](int buf, const AFrag<ENC> &af) {
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) {
+            v4i b[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                b[nb] = *reinterpret_cast<const v4i *>(&bt[buf][(nb * 16 + lr) * kLdsStride + kt * 64 + kgrp]);
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                v4i a;
+                if constexpr (ENC == kDenseI8)
+                    a = af.v[kt][rb];
+                else
+                    a = t2_unpack(af.v[kt][rb]);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[rb][nb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b[nb], acc[rb][nb], 0, 0, 0);
+            }
+        }
+    };
+    const int nkc = np / kKC;
+    // one chunk: prefetch chunk kc+1 (spins into registers, couplings into
+    // `pre`), multiply chunk kc, then publish the prefetched spins
+    auto chunk = [&](int kc, const AFrag<ENC> &use, AFrag<ENC> &pre) {
+        const bool more = kc + 1 < nkc;
+        if (more) {
+            fetch_b(kc + 1);
+            if (active) fetch_a(kc + 1, pre);
+        }
+        if (active) compute(kc & 1, use);
+        if (more) store_b((kc + 1) & 1);
+        __syncthreads();
+    };
+
+    AFrag<ENC> fa, fb;
+    fetch_b(0);
+    store_b(0);
+    if (active) fetch_a(0, fa);
     __syncthreads();
-    const int nk = np / kK;
-    for (int kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < nk) load_b(buf ^ 1, (kt + 1) * kK);
-        const v4i a = *reinterpret_cast<const v4i *>(J + static_cast<size_t>(arow) * np + kt * kK + kgrp);
+    for (int kc = 0; kc < nkc; kc += 2) {
+        chunk(kc, fa, fb);
+        if (kc + 1 < nkc) chunk(kc + 1, fb, fa);
+    }
+    if (!active) return;
+
+    // epilogue: lane owns p-bits 4m..4m+3 of each row block for trial columns nb
+    const float i0t = jb.i0[t];
+    const int32_t scale = jb.scale;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        const int32_t i0 = wrow0 + rb * 16 + (lane >> 4) * 4;
+        if (i0 >= jb.n4) continue;
+        const int32_t m = i0 >> 2;
+        const int4 hh = *reinterpret_cast<const int4 *>(jb.h + i0);
+        const uint4 th = *reinterpret_cast<const uint4 *>(jb.thr + i0);
+        const float4 lm = *reinterpret_cast<const float4 *>(jb.lam + i0);
+        const float4 dl = *reinterpret_cast<const float4 *>(jb.dlt + i0);
+        const int32_t hv[4] = {hh.x, hh.y, hh.z, hh.w};
+        const uint32_t tv[4] = {th.x, th.y, th.z, th.w};
+        const float av[4] = {i0t * lm.x, i0t * lm.y, i0t * lm.z, i0t * lm.w};
+        const float dv[4] = {dl.x, dl.y, dl.z, dl.w};
+        const bool need_gate = (tv[0] < kGateOne) | (tv[1] < kGateOne) | (tv[2] < kGateOne) |
+                               (tv[3] < kGateOne);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            const v4i b = *reinterpret_cast<const v4i *>(&bt[buf][(nb * 16 + (lane & 15)) * kLdsStride + kgrp]);
-            acc[nb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[nb], 0, 0, 0);
-        }
-        __syncthreads();
-    }
-
-    // epilogue: lane owns p-bits 4m..4m+3 (m = task) for trial columns nb
-    const int32_t i0 = row0 + wave * 16 + (lane >> 4) * 4;
-    const int32_t m = i0 >> 2;
-    if (i0 >= jb.n4) return;
-    const float i0t = jb.i0[t];
-    const int4 hh = *reinterpret_cast<const int4 *>(jb.h + i0);
-    const uint4 th = *reinterpret_cast<const uint4 *>(jb.thr + i0);
-    const float4 lm = *reinterpret_cast<const float4 *>(jb.lam + i0);
-    const float4 dl = *reinterpret_cast<const float4 *>(jb.dlt + i0);
-    const int32_t hv[4] = {hh.x, hh.y, hh.z, hh.w};
-    const uint32_t tv[4] = {th.x, th.y, th.z, th.w};
-    const float av[4] = {i0t * lm.x, i0t * lm.y, i0t * lm.z, i0t * lm.w};
-    const float dv[4] = {dl.x, dl.y, dl.z, dl.w};
-    const bool need_gate = (tv[0] < kGateOne) | (tv[1] < kGateOne) | (tv[2] < kGateOne) |
-                           (tv[3] < kGateOne);
+            const int32_t k = trial0 + nb * 16 + lr;
+            if (k >= jb.t4) continue;
+            uint32_t old = 0u;
+            uint32_t gw[4] = {0u, 0u, 0u, 0u};
+            if (need_gate) {
+                old = *reinterpret_cast<const uint32_t *>(cur + static_cast<size_t>(k) * np + i0);
+                const Words4 g = philox4x32_10(static_cast<uint32_t>(t), static_cast<uint32_t>(m),
+                                               static_cast<uint32_t>(k), kTagGate, jb.k0, jb.k1);
+                gw[0] = g.x;
+                gw[1] = g.y;
+                gw[2] = g.z;
+                gw[3] = g.w;
+            }
+            const Words4 r = philox4x32_10(static_cast<uint32_t>(t), static_cast<uint32_t>(m),
+                                           static_cast<uint32_t>(k), kTagR, jb.k0, jb.k1);
+            const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+            uint32_t out = 0u;
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        const int32_t k = trial0 + nb * 16 + (lane & 15);
-        if (k >= jb.t4) continue;
-        const uint32_t old = *reinterpret_cast<const uint32_t *>(cur + static_cast<size_t>(k) * np + i0);
-        uint32_t gw[4] = {0u, 0u, 0u, 0u};
-        if (need_gate) {
-            const Words4 g = block_of(static_cast<uint32_t>(t), static_cast<uint32_t>(m),
-                                      static_cast<uint32_t>(k), kTagGate, jb.k0, jb.k1);
-            gw[0] = g.x;
-            gw[1] = g.y;
-            gw[2] = g.z;
-            gw[3] = g.w;
+            for (int p = 0; p < 4; ++p) {
+                const int32_t L = hv[p] + scale * acc[rb][nb][p];
+                const float b = static_cast<float>(L) + dv[p];
+                const float x = av[p] * b;
+                const bool up = tanh_f32(x) > r_of(rw[p]);
+                const bool fire = tv[p] >= kGateOne || fires(gw[p], tv[p]);
+                const uint32_t ob = (old >> (8 * p)) & 0xFFu;
+                out |= (fire ? (up ? 0x01u : 0xFFu) : ob) << (8 * p);
+            }
+            *reinterpret_cast<uint32_t *>(nxt + static_cast<size_t>(k) * np + i0) = out;
         }
-        const Words4 r = block_of(static_cast<uint32_t>(t), static_cast<uint32_t>(m),
-                                  static_cast<uint32_t>(k), kTagR, jb.k0, jb.k1);
-        const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
-        uint32_t out = 0u;
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int32_t L = hv[p] + acc[nb][p];
-            const float b = static_cast<float>(L) + dv[p];
-            const float x = av[p] * b;
-            const bool up = tanh_f32(x) > r_of(rw[p]);
-            const bool fire = tv[p] >= kGateOne || fires(gw[p], tv[p]);
-            const uint32_t ob = (old >> (8 * p)) & 0xFFu;
-            out |= (fire ? (up ? 0x01u : 0xFFu) : ob) << (8 * p);
-        }
-        *reinterpret_cast<uint32_t *>(nxt + static_cast<size_t>(k) * np + i0) = out;
     }
 }
 
@@ -152,18 +255,26 @@ __global__ void from_dense_kernel(int32_t n, int32_t t4, int32_t np, const int8_
     spins[idx] = m[static_cast<size_t>(k) * np + i];
 }
 
+template <int ENC>
+hipError_t launch_dense_enc(hipStream_t stream, const DenseJob *jobs, const int4 *work, int32_t nwork,
+                            int32_t nb, int32_t s) {
+    switch (nb) {
+        case 1: hipLaunchKernelGGL((dense_step_kernel<1, ENC>), dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
+        case 2: hipLaunchKernelGGL((dense_step_kernel<2, ENC>), dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
+        case 4: hipLaunchKernelGGL((dense_step_kernel<4, ENC>), dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_dense_steps(hipStream_t stream, const DenseJob *jobs, const int4 *work,
-                              int32_t nwork, int32_t nb, int32_t steps) {
+                              int32_t nwork, int32_t nb, int32_t enc, int32_t steps) {
+    if (nwork <= 0) return hipSuccess;
     for (int32_t s = 0; s < steps; ++s) {
-        switch (nb) {
-            case 1: hipLaunchKernelGGL(dense_step_kernel<1>, dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
-            case 2: hipLaunchKernelGGL(dense_step_kernel<2>, dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
-            case 4: hipLaunchKernelGGL(dense_step_kernel<4>, dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
-            default: return hipErrorInvalidValue;
-        }
-        const hipError_t e = hipGetLastError();
+        const hipError_t e = enc == kDenseT2 ? launch_dense_enc<kDenseT2>(stream, jobs, work, nwork, nb, s)
+                                             : launch_dense_enc<kDenseI8>(stream, jobs, work, nwork, nb, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <array>
 #include <atomic>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,6 +24,21 @@ constexpr uint32_t kGateOneHost = 1u << 24;
 // Thread-local error text behind psa_last_error().
 void set_error(const std::string &msg);
 void clear_error();
+
+// Record a failed HIP call as the last error.
+inline psa_status hip_fail(hipError_t err, const char *what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(err));
+    return PSA_EHIP;
+}
+
+#define PSA_HIP(expr, what)                                    \
+    do {                                                       \
+        const hipError_t psa_hip_e_ = (expr);                  \
+        if (psa_hip_e_ != hipSuccess) return psa::hip_fail(psa_hip_e_, what); \
+    } while (0)
+
+// Shape class of a tuning problem (tune.cpp).
+using TuneKey = std::array<int64_t, 6>;
 
 // Device copy of a graph in CSR form.  Row i holds its neighbours j in
 // increasing order with their couplings J_ij.  Per-p-bit arrays are padded to
@@ -101,6 +119,12 @@ enum BatchVariant : int32_t {
     kBatchP32Lds2 = 4,
     kBatchP32Glb2 = 5,
     kBatchPairGlb2 = 6,
+    // four trials per workgroup (work item = group of four trials)
+    kBatchP16Lds4T = 7,
+    kBatchP16Glb4T = 8,
+    kBatchP32Lds4T = 9,
+    kBatchP32Glb4T = 10,
+    kBatchPairGlb4T = 11,
 };
 
 // One run of a batched launch, as stored in the device job table.
@@ -109,12 +133,18 @@ struct BatchJob {
     int32_t variant;
 };
 
-// One run of the dense int8 matrix-core path (dense.hip), as the step kernel
-// reads it.  J is [np][np] int8; m0 / m1 are the two [tp][np] spin buffers
-// (trial-major); steps t .. t_end-1 of the launch sequence.
+// Encodings of the dense coupling matrix (dense.hip): int8 entries, or 2-bit
+// fields f in {0, +1, -1} with J = scale * f.
+enum : int32_t { kDenseI8 = 0, kDenseT2 = 1 };
+
+// One run of the dense matrix-core path (dense.hip), as the step kernel reads
+// it.  J is the encoded [np][np] coupling matrix (np a multiple of 128); m0 /
+// m1 are the two [tp][np] spin buffers (trial-major); steps t .. t_end-1 of
+// the launch sequence.
 struct DenseJob {
     int32_t n, n4, np, t4, tp, t, t_end;
-    const int8_t *J;
+    int32_t scale;  // J = scale * entry (1 for int8)
+    const void *J;
     int8_t *m0, *m1;
     const int32_t *h;
     const float *i0;
@@ -131,10 +161,11 @@ bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t 
                  std::string *why);
 
 // Dense path launchers (dense.hip).  launch_dense_steps issues `steps`
-// launches; launch s advances every run of the work list (job, 64-row tile,
-// trial tile of 16 nb) by its step t + s.
+// launches; launch s advances every run of the work list (job, 256-row group,
+// trial tile of 16 nb; job -1 = empty slot) by its step t + s.  All runs of
+// one work list share the encoding `enc`.
 hipError_t launch_dense_steps(hipStream_t stream, const DenseJob *jobs, const int4 *work,
-                              int32_t nwork, int32_t nb, int32_t steps);
+                              int32_t nwork, int32_t nb, int32_t enc, int32_t steps);
 hipError_t launch_to_dense(hipStream_t stream, int32_t n, int32_t t4, int32_t np, int32_t tp,
                            const int8_t *spins, int8_t *m);
 hipError_t launch_from_dense(hipStream_t stream, int32_t n, int32_t t4, int32_t np,
@@ -151,10 +182,11 @@ hipError_t launch_anneal(hipStream_t stream, const DevGraph &g, const DevRun &ru
                          int32_t t_end);
 void fill_anneal_args(AnnealArgs *a, const DevGraph &g, const DevRun &run, const int32_t *order,
                       int32_t t_begin, int32_t t_end);
-// Plan of one run inside a batched launch (one trial per workgroup); sets
-// the variant the batch kernel dispatches to.
-bool plan_batch_item(const DevGraph &g, const DevRun &run, int32_t lpt_req, size_t max_lds,
-                     AnnealPlan *plan, int32_t *variant, std::string *why);
+// Plan of one run inside a batched launch (tpw_req 4: four trials per
+// workgroup; otherwise one, with lpt_req 4 or 2 lanes per task); sets the
+// variant the batch kernel dispatches to.
+bool plan_batch_item(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t lpt_req,
+                     size_t max_lds, AnnealPlan *plan, int32_t *variant, std::string *why);
 // One launch over a work list: work[b] = (index into jobs, trial), or
 // (-1, 0) for an empty slot.
 hipError_t launch_anneal_batch(hipStream_t stream, const BatchJob *jobs, const int2 *work,
@@ -196,15 +228,30 @@ psa_status host_graph_from_csr(int32_t n, const int64_t *row_ptr, const int32_t 
 psa_status upload_graph(psa_ctx *ctx, HostGraph &&hg, psa_graph **out);
 void graph_release(psa_graph *g);   // free now (creation failures)
 void graph_unref(psa_graph *g);     // drop one reference, free at zero
+// Chip figures of the cost model (MI355X: 256 CUs at 2.4 GHz).
+constexpr double kValuOpsPerSecond = 256.0 * 4 * 16 * 2.4e9;  // 32-bit lane-ops
+constexpr double kMfmaI8OpsPerSecond = 5.0e15;                // dense int8
+constexpr double kHbmBytesPerSecond = 8.0e12;
+// Modelled seconds per step of the CSR sweep (with the given plan) and of the
+// dense matrix-core step (2-bit or int8 couplings).
+double csr_step_seconds(const DevGraph &g, const DevRun &run, const AnnealPlan &plan);
+double dense_step_seconds(int32_t n, int32_t t4, bool two_bit);
+// True when every stored coupling has one magnitude (the 2-bit encoding).
+bool dense_two_bit(const psa_graph *g);
 // Cost model of the automatic path choice: dense when the rows are long
-// enough that the matrix-core product beats the CSR walk.
-bool prefer_dense(const DevGraph &g, const DevRun &run);
+// enough that the matrix-core product beats the CSR walk, and the couplings
+// have a dense encoding.
+bool prefer_dense(const psa_graph *g, const DevRun &run, const AnnealPlan &plan);
 // Build and upload the dense int8 coupling matrix of g (once); EUNSUPPORTED
 // if a coupling does not fit int8.
 psa_status ensure_dense_matrix(psa_graph *g);
 // Advance the dense-planned jobs of `jobs` by up to k steps (each clipped to
 // its schedule) on the context's second stream; the caller joins it.
 psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, int32_t k);
+
+// Path and launch shape of d from the context's tuning cache, measured on a
+// miss (mode PSA_TUNE_ALONE or PSA_TUNE_BATCH); clears PSA_TUNE (tune.cpp).
+psa_status tuned_desc(psa_ctx *ctx, const psa_graph *g, psa_run_desc *d, uint32_t mode);
 
 // Context references (abi.cpp).
 void ctx_retain(psa_ctx *ctx);
@@ -238,6 +285,9 @@ struct psa_ctx {
     size_t dense_table_cap = 0, dense_work_cap = 0;
     std::vector<psa::DenseJob> h_dense_table;
     std::vector<int4> h_dense_work;
+    // measured path / launch shape per shape class (psa_autotune)
+    std::mutex tune_mu;
+    std::map<psa::TuneKey, psa_tune_result> tune_cache;
 };
 
 struct psa_graph {
@@ -253,8 +303,10 @@ struct psa_graph {
     uint16_t *d_pk16 = nullptr, *d_ux16 = nullptr;
     std::vector<int32_t> row_ptr_host;  // [n4+4]
     std::vector<int32_t> col_host, val_host;  // for the dense matrix, on demand
-    int8_t *d_dense = nullptr;          // [np][np] int8, built on first use
-    int32_t np = 0;
+    void *d_dense = nullptr;            // encoded [np][np] couplings, built on first use
+    int32_t np = 0;                     // n rounded up to 128
+    int32_t dense_enc = 0;              // kDenseI8 or kDenseT2
+    int32_t dense_scale = 1;            // J = dense_scale * entry
 };
 
 struct psa_job {

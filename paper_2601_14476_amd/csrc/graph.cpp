@@ -180,18 +180,47 @@ void graph_unref(psa_graph *g) {
 psa_status ensure_dense_matrix(psa_graph *g) {
     if (g->d_dense) return PSA_OK;
     const int32_t n = g->info.n;
-    const int32_t np = (n + 63) / 64 * 64;
-    for (int32_t v : g->val_host)
-        if (v < -127 || v > 127) {
+    const int32_t np = (n + 127) / 128 * 128;
+    // one shared magnitude -> 2-bit fields; otherwise int8 entries
+    int32_t mag = 0;
+    bool one_mag = true;
+    for (int32_t v : g->val_host) {
+        const int32_t a = v < 0 ? -v : v;
+        if (mag == 0) mag = a;
+        one_mag = one_mag && a == mag;
+    }
+    psa_status st;
+    if (one_mag) {
+        const int32_t ktiles = np / 64;
+        std::vector<uint32_t> words(static_cast<size_t>(np) * ktiles * 4, 0u);
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t p = g->row_ptr_host[i]; p < g->row_ptr_host[i + 1]; ++p) {
+                const int32_t k = g->col_host[p];
+                const int32_t c = k >> 6, grp = (k >> 4) & 3, e = k & 15, d = e >> 2, b = e & 3;
+                const uint32_t f = g->val_host[p] > 0 ? 1u : 2u;
+                words[(static_cast<size_t>(i) * ktiles + c) * 4 + grp] |= f << (8 * b + 2 * d);
+            }
+        uint32_t *dev = nullptr;
+        if ((st = upload(&dev, words)) != PSA_OK) return st;
+        g->d_dense = dev;
+        g->dense_enc = kDenseT2;
+        g->dense_scale = mag == 0 ? 1 : mag;
+    } else {
+        if (mag > 127 || std::any_of(g->val_host.begin(), g->val_host.end(),
+                                     [](int32_t v) { return v < -127 || v > 127; })) {
             set_error("dense path: a coupling does not fit int8");
             return PSA_EUNSUPPORTED;
         }
-    std::vector<int8_t> dense(static_cast<size_t>(np) * np, 0);
-    for (int32_t i = 0; i < n; ++i)
-        for (int32_t p = g->row_ptr_host[i]; p < g->row_ptr_host[i + 1]; ++p)
-            dense[static_cast<size_t>(i) * np + g->col_host[p]] = static_cast<int8_t>(g->val_host[p]);
-    psa_status st = upload(&g->d_dense, dense);
-    if (st != PSA_OK) return st;
+        std::vector<int8_t> dense(static_cast<size_t>(np) * np, 0);
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t p = g->row_ptr_host[i]; p < g->row_ptr_host[i + 1]; ++p)
+                dense[static_cast<size_t>(i) * np + g->col_host[p]] = static_cast<int8_t>(g->val_host[p]);
+        int8_t *dev = nullptr;
+        if ((st = upload(&dev, dense)) != PSA_OK) return st;
+        g->d_dense = dev;
+        g->dense_enc = kDenseI8;
+        g->dense_scale = 1;
+    }
     g->np = np;
     return PSA_OK;
 }

@@ -146,7 +146,11 @@ psa_status admit_job(psa_server *s, ServerJob *j) {
     d.lambda = j->lambda.empty() ? nullptr : j->lambda.data();
     d.delta = j->delta.empty() ? nullptr : j->delta.data();
     d.thr24 = j->thr24.empty() ? nullptr : j->thr24.data();
-    d.trials_per_group = 1;
+    if (d.flags & PSA_TUNE) {
+        st = psa::tuned_desc(s->ctx, j->graph, &d, PSA_TUNE_BATCH);
+        if (st != PSA_OK) return st;
+    }
+    if (d.trials_per_group == 0) d.trials_per_group = 1;
     return psa_job_create(s->ctx, j->graph, &d, &j->job);
 }
 

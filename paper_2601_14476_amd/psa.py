@@ -35,6 +35,8 @@ PSA_OUT_HOST = 0
 PSA_OUT_DEVICE = 1
 PSA_BATCH_SEQUENTIAL = 2
 PSA_PATH_AUTO, PSA_PATH_CSR, PSA_PATH_DENSE = 0, 1, 2
+PSA_TUNE = 4
+PSA_TUNE_ALONE, PSA_TUNE_BATCH = 0, 1
 
 _P = ctypes.c_void_p
 _i32, _i64, _u32, _u64, _f64 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
@@ -54,6 +56,12 @@ class psa_run_desc(ctypes.Structure):
                 ("sigma_nu", _f64), ("p_mean", _f64), ("lambda_", _P),
                 ("delta", _P), ("thr24", _P), ("block", _i32),
                 ("trials_per_group", _i32), ("lanes_per_task", _i32), ("flags", _u32)]
+
+
+class psa_tune_result(ctypes.Structure):
+    _fields_ = [("path", _u32), ("trials_per_group", _i32), ("lanes_per_task", _i32),
+                ("candidates", _i32), ("us_per_step", _f64), ("csr_us_per_step", _f64),
+                ("dense_us_per_step", _f64), ("model_csr_us", _f64), ("model_dense_us", _f64)]
 
 
 class psa_batch_item(ctypes.Structure):
@@ -105,6 +113,13 @@ _SIGNATURES = [
     ("psa_anneal", _i32, [_P, _P, ctypes.POINTER(psa_run_desc), _P, _P, _P, _u32]),
     ("psa_jobs_step_batch", _i32, [_P, _i32, ctypes.POINTER(_P), _i32]),
     ("psa_anneal_batch", _i32, [_P, _i32, ctypes.POINTER(psa_batch_item), _u32]),
+    ("psa_autotune", _i32, [_P, _P, ctypes.POINTER(psa_run_desc), _i32, _u32,
+                            ctypes.POINTER(psa_tune_result)]),
+    ("psa_tune_get", _i32, [_P, _P, ctypes.POINTER(psa_run_desc), _u32,
+                            ctypes.POINTER(psa_tune_result)]),
+    ("psa_tune_apply", None, [ctypes.POINTER(psa_tune_result), ctypes.POINTER(psa_run_desc)]),
+    ("psa_tune_cache_size", _i32, [_P]),
+    ("psa_tune_clear", None, [_P]),
     ("psa_server_create", _i32, [_P, ctypes.POINTER(psa_server_opts), ctypes.POINTER(_P)]),
     ("psa_server_submit", _i32, [_P, _i32, _i64, _P, _P, _P, _P, _u32,
                                  ctypes.POINTER(psa_run_desc), _P, _P, _P,
@@ -296,8 +311,9 @@ def variability_draw(n, seed, sigma_lambda=0.0, sigma_delta=0.0, sigma_nu=0.0, p
 def make_desc(steps, trials, seed=0, i0=None, i0_min=None, i0_max=None,
               sigma_lambda=0.0, sigma_delta=0.0, sigma_nu=0.0, p_mean=1.0,
               lam=None, delta=None, thr24=None, block=0, trials_per_group=0,
-              lanes_per_task=0, path=PSA_PATH_AUTO):
-    """Build a psa_run_desc; returns (desc, keepalive arrays)."""
+              lanes_per_task=0, path=PSA_PATH_AUTO, tune=False):
+    """Build a psa_run_desc; returns (desc, keepalive arrays).  tune=True sets
+    PSA_TUNE (path and launch shape from the context's tuning cache)."""
     d = psa_run_desc()
     _lib.psa_run_desc_default(ctypes.byref(d))
     d.steps, d.trials, d.seed = int(steps), int(trials), int(seed)
@@ -319,8 +335,46 @@ def make_desc(steps, trials, seed=0, i0=None, i0_min=None, i0_max=None,
     d.block = int(block)
     d.trials_per_group = int(trials_per_group)
     d.lanes_per_task = int(lanes_per_task)
-    d.flags = int(path)
+    d.flags = int(path) | (PSA_TUNE if tune else 0)
     return d, keep
+
+
+def autotune(ctx, graph, steps, trials, seed=0, probe_steps=8, batch=False, **kw):
+    """Time the applicable paths and launch shapes (psa_autotune); returns a
+    dict of the psa_tune_result fields."""
+    desc, keep = make_desc(steps, trials, seed, **kw)
+    r = psa_tune_result()
+    _check(_lib.psa_autotune(ctx.handle, graph.handle, ctypes.byref(desc), int(probe_steps),
+                             PSA_TUNE_BATCH if batch else PSA_TUNE_ALONE, ctypes.byref(r)),
+           "psa_autotune")
+    del keep
+    return {f: getattr(r, f) for f, _ in psa_tune_result._fields_}
+
+
+def tune_get(ctx, graph, steps, trials, seed=0, batch=False, **kw):
+    """The tuning cache's entry for this graph's shape class (measured on a
+    miss, psa_tune_get); returns a dict of the psa_tune_result fields."""
+    desc, keep = make_desc(steps, trials, seed, **kw)
+    r = psa_tune_result()
+    _check(_lib.psa_tune_get(ctx.handle, graph.handle, ctypes.byref(desc),
+                             PSA_TUNE_BATCH if batch else PSA_TUNE_ALONE, ctypes.byref(r)),
+           "psa_tune_get")
+    del keep
+    return {f: getattr(r, f) for f, _ in psa_tune_result._fields_}
+
+
+def tune_kwargs(r):
+    """make_desc keyword arguments that apply a tuning result."""
+    return dict(path=r["path"], trials_per_group=r["trials_per_group"],
+                lanes_per_task=r["lanes_per_task"])
+
+
+def tune_cache_size(ctx):
+    return int(_lib.psa_tune_cache_size(ctx.handle))
+
+
+def tune_clear(ctx):
+    _lib.psa_tune_clear(ctx.handle)
 
 
 class Job:

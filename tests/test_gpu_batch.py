@@ -148,6 +148,11 @@ def test_batch_mixes_dense_and_csr_jobs(psa, ctx):
              (inputs.gnm(900, 2700, 52), psa.PSA_PATH_CSR, 10, 45),
              (inputs.erdos_renyi(200, 0.5, 53), psa.PSA_PATH_DENSE, 20, 38),
              (inputs.torus(8, 9, 54), psa.PSA_PATH_AUTO, 3, 12)]
+    # integer couplings |J| <= 4: the int8 encoding, in the same batch as 2-bit ones
+    rng = np.random.default_rng(55)
+    _, iu, iv, _ = inputs.gnm(450, 20000, 55)
+    iw = (rng.integers(1, 5, size=iu.size) * rng.choice([-1, 1], size=iu.size)).astype(np.int32)
+    specs.append(((450, iu, iv, iw), psa.PSA_PATH_DENSE, 17, 26))
     jobs, refs = [], []
     for (n, u, v, w), path, T, S in specs:
         g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
@@ -160,3 +165,38 @@ def test_batch_mixes_dense_and_csr_jobs(psa, ctx):
     for j, r in zip(jobs, refs):
         np.testing.assert_array_equal(j.read_spins(), r.read_spins())
         np.testing.assert_array_equal(j.energy_cut()[0], r.energy_cut()[0])
+
+
+def test_batch_four_trial_groups(psa, ctx):
+    """Jobs with four trials per workgroup inside a batched launch (16-bit
+    and 32-bit packed edges, column/value pairs, edges in LDS and in global
+    memory), mixed with one-trial jobs: each ends where it ends alone."""
+    rng = np.random.default_rng(71)
+    specs = []
+    n, u, v, w = inputs.gnm(700, 2100, 71)                       # +-1, LDS
+    specs.append((n, u, v, -w, None, 4, 13, 40))
+    n, u, v, w = inputs.gnm(6000, 60000, 72)                     # +-1, edges beyond LDS
+    specs.append((n, u, v, -w, None, 4, 9, 25))
+    n, u, v, _ = inputs.gnm(500, 2000, 73)                       # |J| <= 4: 32-bit packing
+    j = (rng.integers(1, 5, size=u.size) * rng.choice([-1, 1], size=u.size)).astype(np.int32)
+    specs.append((n, u, v, j, rng.integers(-3, 4, size=n).astype(np.int32), 4, 6, 33))
+    n, u, v, _ = inputs.gnm(300, 900, 74)                        # |J| >= 2^15: pairs
+    j = (rng.choice([-1, 1], size=u.size) * 40000).astype(np.int32)
+    specs.append((n, u, v, j, None, 4, 5, 21))
+    n, u, v, w = inputs.gnm(800, 2400, 75)                       # one-trial job in the mix
+    specs.append((n, u, v, -w, None, 1, 7, 30))
+    jobs, refs = [], []
+    for n, u, v, j, h, tpw, T, S in specs:
+        g = psa.Graph.from_edges(ctx, n, u, v, j, h=h, maxcut=False)
+        big = int(np.abs(j).max()) > 1000
+        i0 = oracle.schedule(S, 1e-5, 1e-4) if big else oracle.schedule(S, 0.02, 0.8)
+        kw = dict(i0=i0, sigma_lambda=0.1, sigma_delta=0.1, sigma_nu=0.1, p_mean=0.8)
+        jobs.append(psa.Job(ctx, g, S, T, 9, trials_per_group=tpw, path=psa.PSA_PATH_CSR, **kw))
+        ref = psa.Job(ctx, g, S, T, 9, trials_per_group=1, path=psa.PSA_PATH_CSR, **kw)
+        ref.step(S)
+        refs.append(ref)
+    while any(jb.position < jb.steps for jb in jobs):
+        psa.jobs_step_batch(ctx, [jb for jb in jobs if jb.position < jb.steps], 8)
+    for jb, r in zip(jobs, refs):
+        np.testing.assert_array_equal(jb.read_spins(), r.read_spins())
+        np.testing.assert_array_equal(jb.energy_cut()[0], r.energy_cut()[0])

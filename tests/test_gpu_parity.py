@@ -361,15 +361,22 @@ def test_edge_encodings_match_oracle(psa, ctx, kind, tpw, lpt):
 
 @pytest.mark.parametrize("n,trials,kind", [(1, 3, "unit"), (63, 7, "int"), (64, 16, "unit"),
                                            (65, 33, "int"), (300, 64, "unit"), (1000, 100, "int"),
-                                           (257, 1, "unit")])
+                                           (257, 1, "unit"), (129, 5, "scaled"), (700, 40, "one"),
+                                           (1300, 130, "one"), (385, 64, "scaled")])
 def test_dense_path_matches_oracle(psa, ctx, n, trials, kind):
-    """Dense int8 matrix-core path against the oracle and against the CSR
-    path: identical spins, energies and cuts."""
-    if kind == "unit":
+    """Dense matrix-core path against the oracle and against the CSR path:
+    identical spins, energies and cuts.  "unit" (+-1), "one" (all +1) and
+    "scaled" (+-3) couplings take the 2-bit encoding, "int" (|J| <= 5) the
+    int8 one; sizes span several 256-row groups, 128-column chunks and trial
+    tiles with ragged tails."""
+    if kind in ("unit", "one", "scaled"):
         if n > 1:
-            _, u, v, w = inputs.erdos_renyi(n, 0.3, 40 + n, weights="pm1")
+            p = 0.3 if kind != "one" else 0.08
+            _, u, v, w = inputs.erdos_renyi(n, p, 40 + n, weights="one" if kind == "one" else "pm1")
         else:
             u = v = w = np.zeros(0, np.int32)
+        if kind == "scaled":
+            w = 3 * w
         j, h = -w, None
     else:
         n, u, v, j, h = _random_ising(n, 4 * n, 41 + n, jmax=5)
@@ -393,9 +400,10 @@ def test_dense_path_matches_oracle(psa, ctx, n, trials, kind):
 
 
 def test_dense_path_rejects_wide_couplings(psa, ctx):
-    u = np.array([0], np.int32)
-    v = np.array([1], np.int32)
-    g = psa.Graph.from_edges(ctx, 2, u, v, np.array([300], np.int32), maxcut=False)
+    """Couplings of several magnitudes, one above int8, have no dense encoding
+    (a single magnitude, however large, takes the 2-bit one)."""
+    g = psa.Graph.from_edges(ctx, 3, np.array([0, 1], np.int32), np.array([1, 2], np.int32),
+                             np.array([300, 1], np.int32), maxcut=False)
     with pytest.raises(psa.PsaError) as e:
         psa.Job(ctx, g, 5, 2, 0, i0_min=0.001, i0_max=0.01, path=psa.PSA_PATH_DENSE)
     assert e.value.status == psa.PSA_EUNSUPPORTED
