@@ -44,6 +44,7 @@
 #define TAG_R 1u
 #define TAG_GATE 2u
 #define TAG_VAR 3u
+#define TAG_STALL 4u
 
 #define GATE_ONE (1u << 24)
 
@@ -435,6 +436,72 @@ int psa_ref_run(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
                 float x = a_i * b_i;
                 float y = psa_ref_tanh(x);
                 next[i] = (y > r) ? (int8_t)1 : (int8_t)-1;
+            }
+            memcpy(mk, next, (size_t)n);
+        }
+    }
+    free(L);
+    free(next);
+    adj_free(&a);
+    return 0;
+}
+
+/* SpSA (Eq. 5).  Per step and trial: every p-bit first decides whether its
+ * input I_i is stalled (kept from the previous step, with probability
+ * stall24 / 2^24) or formed anew, I_i = I0 (h_i + sum_j J_ij m_j(t)), here
+ * with the device-variability pre-activation x = (I0 lambda_i)(L_i +
+ * delta_i); then the p-bit output follows Eq. 1 / Eq. 6 with the held or
+ * fresh input, under the same timing gate as pSA. */
+int psa_ref_run_spsa(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+                     const int32_t *ej, const int32_t *h, const float *i0,
+                     const float *lambda, const float *offset,
+                     const uint32_t *thr24, uint32_t stall24, uint64_t seed,
+                     int32_t trial_begin, int32_t trial_end, int32_t t_begin,
+                     int32_t t_end, int8_t *spins, float *x_state)
+{
+    if (!i0 || !lambda || !offset || !thr24 || !spins || !x_state ||
+        trial_begin < 0 || trial_end < trial_begin || t_begin < 0 ||
+        t_end < t_begin || stall24 > GATE_ONE)
+        return -1;
+    ref_adj a;
+    int rc = adj_build(n, m, eu, ev, ej, h, &a);
+    if (rc != 0)
+        return rc;
+    int32_t *L = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int8_t *next = (int8_t *)malloc((size_t)n);
+    if (!L || !next) {
+        free(L);
+        free(next);
+        adj_free(&a);
+        return -2;
+    }
+    for (int32_t k = trial_begin; k < trial_end; k++) {
+        int8_t *mk = spins + (int64_t)(k - trial_begin) * n;
+        float *xk = x_state + (int64_t)(k - trial_begin) * n;
+        for (int32_t t = t_begin; t < t_end; t++) {
+            for (int32_t i = 0; i < n; i++)
+                L[i] = field_of(&a, h, i, mk);
+            for (int32_t i = 0; i < n; i++) {
+                /* input stage: held with probability p, else fresh */
+                uint32_t us = psa_ref_word(seed, (uint32_t)t, (uint32_t)i,
+                                           (uint32_t)k, TAG_STALL);
+                int stalled = t > 0 && (us >> 8) < stall24;
+                if (!stalled) {
+                    float a_i = i0[t] * lambda[i];
+                    float b_i = (float)L[i] + offset[i];
+                    xk[i] = a_i * b_i;
+                }
+                /* output stage: as pSA, on the held or fresh input */
+                uint32_t ug = psa_ref_word(seed, (uint32_t)t, (uint32_t)i,
+                                           (uint32_t)k, TAG_GATE);
+                if (!psa_ref_gate(ug, thr24[i])) {
+                    next[i] = mk[i];
+                    continue;
+                }
+                uint32_t ur = psa_ref_word(seed, (uint32_t)t, (uint32_t)i,
+                                           (uint32_t)k, TAG_R);
+                float r = psa_ref_r_from_word(ur);
+                next[i] = (psa_ref_tanh(xk[i]) > r) ? (int8_t)1 : (int8_t)-1;
             }
             memcpy(mk, next, (size_t)n);
         }

@@ -87,6 +87,22 @@ int psa_ref_run(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
                 int32_t trial_end, int32_t t_begin, int32_t t_end,
                 int8_t *spins);
 
+/* Stalled-input variant (SpSA, Eq. 5): the input of a p-bit keeps its
+ * previous value with probability stall24 / 2^24, else it is formed anew
+ * from the spins of step t; the output rule (gate, r, tanh) is the pSA one.
+ * The held input is the whole pre-activation x_i of the last refresh (I0
+ * and the variability factors of that step included).  Step 0 always
+ * refreshes.  x_state ([trials][n] floats, same rows as spins) carries the
+ * inputs between calls: read when t_begin > 0, written on return.
+ * Randomness: the stall word is Philox word i mod 4 of counter
+ * (t, i/4, k, 4); the input stalls iff (word >> 8) < stall24. */
+int psa_ref_run_spsa(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+                     const int32_t *ej, const int32_t *h, const float *i0,
+                     const float *lambda, const float *offset,
+                     const uint32_t *thr24, uint32_t stall24, uint64_t seed,
+                     int32_t trial_begin, int32_t trial_end, int32_t t_begin,
+                     int32_t t_end, int8_t *spins, float *x_state);
+
 /* Ising energy (Eq. 2) and cut weight with w = -J of each trial row. */
 int psa_ref_energy_cut(int32_t n, int64_t m, const int32_t *eu,
                        const int32_t *ev, const int32_t *ej, const int32_t *h,

@@ -368,6 +368,86 @@ def test_isolated_pbit_marginals_per_step():
         assert np.all(np.abs(f - p) <= tol), (t, f, p)
 
 
+def test_spsa_without_stall_is_psa():
+    """Eq. 5 with stall probability 0 is Eq. 3: the same trajectories."""
+    n, u, v, j, h = _random_ising(60, 200, 81)
+    i0 = oracle.schedule(25, 0.02, 1.5)
+    lam, off, thr = oracle.variability(n, 5, 0.2, 0.3, 0.2, 0.7)
+    a = oracle.anneal(n, u, v, j, h, i0, lam, off, thr, 5, 0, 6)
+    b = oracle.anneal_spsa(n, u, v, j, h, i0, lam, off, thr, 0, 5, 0, 6)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("stall", [1 << 22, 1 << 23, ONE24])
+def test_spsa_constant_input_is_psa(stall):
+    """Without couplings and with a constant I0 a fresh input equals the held
+    one, so stalling changes nothing: the stall draws must not disturb the
+    r and gate streams.  With couplings the trajectories do differ."""
+    n, S, T = 30, 20, 5
+    rng = np.random.default_rng(82)
+    h = rng.integers(-3, 4, size=n).astype(np.int32)
+    i0 = np.full(S, 0.4, np.float32)
+    lam, off, thr = oracle.variability(n, 6, 0.2, 0.3, 0.2, 0.7)
+    e = np.zeros(0, np.int32)
+    a = oracle.anneal(n, e, e, e, h, i0, lam, off, thr, 6, 0, T)
+    b = oracle.anneal_spsa(n, e, e, e, h, i0, lam, off, thr, stall, 6, 0, T)
+    np.testing.assert_array_equal(a[0], b[0])
+    n2, u, v, j, h2 = _random_ising(n, 90, 83)
+    a = oracle.anneal(n2, u, v, j, h2, i0, lam, off, thr, 6, 0, T)
+    b = oracle.anneal_spsa(n2, u, v, j, h2, i0, lam, off, thr, stall, 6, 0, T)
+    assert not np.array_equal(a[0], b[0])
+
+
+@pytest.mark.parametrize("p_stall", [0.5, 1.0])
+def test_spsa_isolated_pbit_marginals(p_stall):
+    """No couplings: the held input of step t was formed at step t - J, J
+    truncated-geometric (P(J = j) = (1-p) p^j for j < t, p^t for j = t, as
+    step 0 always refreshes), independently of the output chain, so
+      P(m(t+1)=+1) = g E_J[q(I0[t-J])] + (1-g) P(m(t)=+1).
+    Using I0[t] (no stall) or a stale-by-one index fails at these sizes."""
+    n, T, S = 12, 8000, 7
+    h = np.array([-3, -2, -1, 0, 1, 2, 3, 1, -1, 2, 0, 1], np.int32)
+    lam = np.array([1, 1, 1, 1, 1, 1, 1, .6, 1.4, .8, 1, 1.2], np.float32)
+    off = np.array([0, 0, 0, 0, 0, 0, 0, .3, -.5, .2, .7, -.9], np.float32)
+    g = np.array([1, 1, 1, 1, 1, 1, .5, 1, .7, .25, 1, 0])
+    thr = np.round(g * ONE24).astype(np.uint32)
+    stall24 = int(round(p_stall * ONE24))
+    i0 = oracle.schedule(S, 0.05, 2.0)
+    e = np.zeros(0, np.int32)
+    spins = oracle.init_spins(n, 78, 0, T)
+    x = None
+    p = (spins == 1).mean(axis=0).astype(np.float64)
+    p_psa = p.copy()
+    separated = False
+    for t in range(S):
+        spins, x = oracle.run_spsa(n, e, e, e, h, i0, lam, off, thr, stall24, 78, 0, T, t,
+                                   t + 1, spins, x)
+        w = [(1 - p_stall) * p_stall ** jj for jj in range(t)] + [p_stall ** t]
+        eq = sum(wj * _p_plus(i0[t - jj], lam, h, off) for jj, wj in enumerate(w))
+        p = g * eq + (1 - g) * p
+        p_psa = g * _p_plus(i0[t], lam, h, off) + (1 - g) * p_psa
+        f = (spins == 1).mean(axis=0)
+        tol = 5 * np.sqrt(np.maximum(p * (1 - p), 1e-4) / T) + 1e-9
+        assert np.all(np.abs(f - p) <= tol), (t, f, p)
+        separated |= bool(np.any(np.abs(p - p_psa) > 2 * tol))
+    assert separated   # the test can tell SpSA from pSA
+
+
+def test_spsa_resume_composes():
+    """Steps 0..k then k..S with the held inputs carried over equal 0..S."""
+    n, u, v, j, h = _random_ising(40, 120, 84)
+    S, T, k = 18, 5, 7
+    i0 = oracle.schedule(S, 0.02, 1.5)
+    lam, off, thr = oracle.variability(n, 8, 0.1, 0.1, 0.1, 0.8)
+    s0 = oracle.init_spins(n, 8, 0, T)
+    full, xf = oracle.run_spsa(n, u, v, j, h, i0, lam, off, thr, 1 << 23, 8, 0, T, 0, S, s0)
+    s1, x1 = oracle.run_spsa(n, u, v, j, h, i0, lam, off, thr, 1 << 23, 8, 0, T, 0, k, s0)
+    s2, x2 = oracle.run_spsa(n, u, v, j, h, i0, lam, off, thr, 1 << 23, 8, 0, T, k, S, s1, x1)
+    np.testing.assert_array_equal(full, s2)
+    np.testing.assert_array_equal(xf, x2)
+
+
 def _two_spin_transition(i0, J, h, lam, off):
     states = [(1, 1), (1, -1), (-1, 1), (-1, -1)]
     P = np.zeros((4, 4))
