@@ -47,18 +47,24 @@ OPS_DECIDE = 2         # compare with r, select
 # MI355X: 256 CUs x 4 SIMD x 16 lanes, one 32-bit VALU op per lane per clock
 # at 2.4 GHz (the 157.3 TFLOP/s FP32 figure counts an FMA as 2 and dual issue).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+OPS_STALL = 3  # shift-compare of the stall word, select / memory op of the held input
 MFMA_I8_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak, TOP/s
+HBM_PEAK_GBS = 8000.0
 
 
-def ops_per_update(mean_degree: float, timing: bool) -> float:
-    philox = PHILOX_BLOCK_OPS / 4 * (2 if timing else 1)
+def ops_per_update(mean_degree: float, timing: bool, spsa: bool = False) -> float:
+    """Algorithmic 32-bit lane-operations of one p-bit update.  SpSA adds a
+    quarter Philox block for the stall word, its compare and the load or
+    store of the held input."""
+    philox = PHILOX_BLOCK_OPS / 4 * ((2 if timing else 1) + (1 if spsa else 0))
     return (philox + OPS_R_MAP + (OPS_GATE_MAP if timing else 0) + mean_degree
-            + OPS_PREACT + OPS_TANH + OPS_DECIDE)
+            + OPS_PREACT + OPS_TANH + OPS_DECIDE + (OPS_STALL if spsa else 0))
 
 
-def cpu_baseline(spec, budget_s: float = 15.0):
+def cpu_baseline(spec, budget_s: float = 15.0, stall24=None):
     """Time the oracle on a bounded sample: the first `k` trials over the
-    full schedule, k chosen so the single-thread work is about budget_s."""
+    full schedule, k chosen so the single-thread work is about budget_s.
+    stall24: time the SpSA oracle with that stall threshold instead."""
     import oracle
     from concurrent.futures import ThreadPoolExecutor
     oracle.build(force=False)
@@ -71,8 +77,12 @@ def cpu_baseline(spec, budget_s: float = 15.0):
     # calibrate: one trial, a few steps
     cal_steps = max(1, min(S, 50))
     t0 = time.perf_counter()
-    oracle.run(n, u, v, -w, None, i0, lam, dlt, thr, spec["seed"], 0, 1, 0, cal_steps,
-               oracle.init_spins(n, spec["seed"], 0, 1))
+    if stall24 is None:
+        oracle.run(n, u, v, -w, None, i0, lam, dlt, thr, spec["seed"], 0, 1, 0, cal_steps,
+                   oracle.init_spins(n, spec["seed"], 0, 1))
+    else:
+        oracle.run_spsa(n, u, v, -w, None, i0, lam, dlt, thr, stall24, spec["seed"], 0, 1, 0,
+                        cal_steps, oracle.init_spins(n, spec["seed"], 0, 1))
     per_update = (time.perf_counter() - t0) / (n * cal_steps)
     cores = min(os.cpu_count() or 1, 16)
     trials = max(1, min(spec["trials"], int(budget_s / (per_update * n * S))))
@@ -81,8 +91,13 @@ def cpu_baseline(spec, budget_s: float = 15.0):
     parts = [(int(a), int(b)) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
     t0 = time.perf_counter()
     with ThreadPoolExecutor(len(parts)) as ex:
-        list(ex.map(lambda ab: oracle.anneal(n, u, v, -w, None, i0, lam, dlt, thr,
-                                             spec["seed"], ab[0], ab[1]), parts))
+        if stall24 is None:
+            list(ex.map(lambda ab: oracle.anneal(n, u, v, -w, None, i0, lam, dlt, thr,
+                                                 spec["seed"], ab[0], ab[1]), parts))
+        else:
+            list(ex.map(lambda ab: oracle.anneal_spsa(n, u, v, -w, None, i0, lam, dlt, thr,
+                                                      stall24, spec["seed"], ab[0], ab[1]),
+                        parts))
     dt = time.perf_counter() - t0
     updates = n * trials * S
     return {"value": updates / dt, "unit": "p-bit updates/s", "cores": len(parts),
@@ -101,8 +116,15 @@ def main():
     ap.add_argument("--duration", type=float, default=20.0, help="c5: seconds of arrivals")
     ap.add_argument("--quantum", type=int, default=250, help="c5: steps per scheduling quantum")
     ap.add_argument("--max-resident", type=int, default=128, help="c5: resident job slots")
+    ap.add_argument("--graphs", type=int, default=256,
+                    help="c4: graphs in the batch (256 = the workload; fewer for profiling)")
     ap.add_argument("--no-tune", action="store_true",
                     help="c5: cost-model path choice instead of the autotuner")
+    ap.add_argument("--algorithm", default="psa", choices=["psa", "spsa"],
+                    help="c1-c3: update rule (pSA, Eq. 3, or stalled p-bits, Eq. 5)")
+    ap.add_argument("--p-stall", type=float, default=0.5, help="SpSA stall probability")
+    ap.add_argument("--path", default="auto", choices=["auto", "csr", "dense"],
+                    help="c1-c3: field path")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--tpw", type=int, default=0, help="trials per workgroup (0 = auto)")
     ap.add_argument("--lpt", type=int, default=0, help="lanes per 4-p-bit task (0 = auto)")
@@ -143,10 +165,13 @@ def main():
     ctx = psa.Context(0, stream)
     g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
     info = g.info()
+    spsa = args.algorithm == "spsa"
     job = psa.Job(ctx, g, S, T, spec["seed"], sigma_lambda=spec["sigma_lambda"],
                   sigma_delta=spec["sigma_delta"], sigma_nu=spec["sigma_nu"],
                   p_mean=spec["p_mean"], block=args.block, trials_per_group=args.tpw,
-                  lanes_per_task=args.lpt)
+                  lanes_per_task=args.lpt, path={"auto": psa.PSA_PATH_AUTO, "csr": psa.PSA_PATH_CSR,
+                                                 "dense": psa.PSA_PATH_DENSE}[args.path],
+                  algorithm=psa.PSA_ALG_SPSA if spsa else psa.PSA_ALG_PSA, p_stall=args.p_stall)
     E = torch.empty(T, dtype=torch.int64, device="cuda")
     C = torch.empty(T, dtype=torch.int64, device="cuda")
 
@@ -176,7 +201,7 @@ def main():
     value = updates * args.steps / wall
     timing = spec["sigma_nu"] > 0 or spec["p_mean"] < 1.0
     mean_deg = info["nnz"] / n
-    opu = ops_per_update(mean_deg, timing)
+    opu = ops_per_update(mean_deg, timing, spsa)
     achieved = opu * updates / (kernel_ms * 1e-3) / 1e12
     line = {
         "metric": "p-bit updates/s (n x trials x steps / s), 1 GPU",
@@ -198,10 +223,12 @@ def main():
             "sigma_lambda": spec["sigma_lambda"], "sigma_delta": spec["sigma_delta"],
             "sigma_nu": spec["sigma_nu"], "p_mean": spec["p_mean"],
             "updates_per_anneal": updates,
+            "algorithm": args.algorithm, "p_stall": args.p_stall if spsa else None,
+            "path": "dense" if job.dense else "csr",
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "anneal_lds_kernel",
+            "kernel": "dense_step_kernel" if job.dense else "anneal_kernel",
             "achieved": achieved,
             "peak": VALU_PEAK_TOPS,
             "unit": "TOP/s",
@@ -212,7 +239,8 @@ def main():
         },
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(spec)
+        line["cpu_baseline"] = cpu_baseline(
+            spec, stall24=int(args.p_stall * 2 ** 24) if spsa else None)
     print(json.dumps(line), flush=True)
     job.close()
     g.close()
@@ -229,14 +257,16 @@ def bench_batch(args):
     alone) on the same stream."""
     import torch
     from paper_2601_14476_amd import inputs, psa
-    specs = inputs.batch_jobs()
+    specs = inputs.batch_jobs(count=args.graphs)
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     ctx = psa.Context(0, stream)
     graphs, jobs, alone, outs = [], [], [], []
     updates = 0
-    valu_ops = 0.0
+    valu_ops = 0.0       # CSR jobs
+    dense_valu = 0.0     # dense jobs' epilogue
+    dense_bytes = 0.0
     mfma_ops = 0.0
     dense_jobs = 0
     t_tune = 0.0
@@ -260,8 +290,15 @@ def bench_batch(args):
         updates += upd
         if rb["path"] == psa.PSA_PATH_DENSE:
             dense_jobs += 1
-            valu_ops += ops_per_update(0.0, False) * upd
+            dense_valu += ops_per_update(0.0, False) * upd
             mfma_ops += 2.0 * n * n * sp["trials"] * sp["steps"]
+            # algorithmic bytes per step: the encoded couplings once per
+            # 64-trial tile, the spins read and written once
+            np_ = (n + 127) // 128 * 128
+            enc = jobs[-1].info()["dense_encoding"]
+            tiles = (sp["trials"] + 63) // 64
+            dense_bytes += (np_ * np_ * (0.25 if enc == 2 else 1.0) * tiles
+                            + 2 * n * sp["trials"]) * sp["steps"]
         else:
             valu_ops += ops_per_update(info["nnz"] / n, False) * upd
     S = max(sp["steps"] for sp in specs)
@@ -288,11 +325,15 @@ def bench_batch(args):
     torch.cuda.synchronize()
     events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(args.steps)]
+    ctx.timing()                     # clear
+    ctx.set_timing(True)
     t0 = time.perf_counter()
     for k in range(args.steps):
         batched(events[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ctx.set_timing(False)
+    fam = ctx.timing()
     kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
     cuts_batched = [c.cpu().numpy().copy() for _, c in outs]
     sequential()
@@ -303,7 +344,33 @@ def bench_batch(args):
     wall_seq = time.perf_counter() - t0
     same = all(np.array_equal(a, c.cpu().numpy()) for a, (_, c) in zip(cuts_batched, outs))
     value = updates * args.steps / wall
-    achieved = valu_ops / (kernel_ms * 1e-3) / 1e12
+    # per-family device time per batch (each measured on its own stream)
+    dense_ms = fam["dense_ms"] / args.steps
+    batch_ms = fam["batch_ms"] / args.steps
+    dense_frac = {
+        "mfma": (mfma_ops / (dense_ms * 1e-3) / 1e12 / MFMA_I8_PEAK_TOPS) if dense_ms else 0.0,
+        "alu": (dense_valu / (dense_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS) if dense_ms else 0.0,
+        "hbm": (dense_bytes / (dense_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if dense_ms else 0.0,
+    }
+    if dense_ms >= batch_ms:
+        bound = max(dense_frac, key=dense_frac.get)
+        achieved = {"mfma": mfma_ops / (dense_ms * 1e-3) / 1e12,
+                    "alu": dense_valu / (dense_ms * 1e-3) / 1e12,
+                    "hbm": dense_bytes / (dense_ms * 1e-3) / 1e9}[bound]
+        peak = {"mfma": MFMA_I8_PEAK_TOPS, "alu": VALU_PEAK_TOPS, "hbm": HBM_PEAK_GBS}[bound]
+        roof = {"bound": bound, "kernel": "dense_step_kernel", "achieved": achieved,
+                "peak": peak, "unit": "GB/s" if bound == "hbm" else "TOP/s",
+                "frac": achieved / peak, "traffic": None,
+                "kernel_ms": dense_ms / max(fam["dense_launches"] / args.steps, 1),
+                "launches_per_batch": fam["dense_launches"] / args.steps,
+                "dense_fracs": dense_frac}
+    else:
+        achieved = valu_ops / (batch_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": "anneal_batch_kernel", "achieved": achieved,
+                "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
+                "traffic": None, "kernel_ms": batch_ms, "dense_fracs": dense_frac}
+    roof.update({"dense_ms_per_batch": dense_ms, "csr_batch_ms_per_batch": batch_ms,
+                 "batch_span_ms": kernel_ms})
     line = {
         "metric": "p-bit updates/s (n x trials x steps / s), 1 GPU",
         "value": value,
@@ -325,13 +392,7 @@ def bench_batch(args):
             "batched_over_one_at_a_time": wall_seq / (wall / args.steps),
             "identical_cuts": same,
         },
-        "roofline": {
-            "bound": "alu", "kernel": "anneal_batch_kernel + dense_step_kernel",
-            "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-            "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel_ms": kernel_ms,
-            "mfma_int8_achieved_tops": mfma_ops / (kernel_ms * 1e-3) / 1e12,
-            "mfma_int8_peak_tops": MFMA_I8_PEAK_TOPS,
-        },
+        "roofline": roof,
     }
     print(json.dumps(line), flush=True)
 

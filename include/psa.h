@@ -84,6 +84,24 @@ psa_status psa_ctx_synchronize(psa_ctx *ctx);
  * reference.  NULL is ignored. */
 void psa_ctx_destroy(psa_ctx *ctx);
 
+/* Device time per kernel family, measured with HIP events on the stream
+ * each family is launched on (the context's stream for the CSR sweep and
+ * batch kernels, its second stream for the dense step kernels).  Off by
+ * default; psa_ctx_set_timing(ctx, 1) starts recording, and
+ * psa_ctx_timing_read waits for the recorded work, fills *out with the
+ * totals since the last read and clears them. */
+typedef struct psa_timing {
+    double anneal_ms;        /* CSR sweep launches (one job stepped alone) */
+    double batch_ms;         /* CSR batch kernel launches                  */
+    double dense_ms;         /* dense step sequences (launch gaps included) */
+    int64_t anneal_launches;
+    int64_t batch_launches;
+    int64_t dense_launches;  /* one per step of a dense work list           */
+} psa_timing;
+
+psa_status psa_ctx_set_timing(psa_ctx *ctx, int32_t on);
+psa_status psa_ctx_timing_read(psa_ctx *ctx, psa_timing *out);
+
 /* ------------------------------------------------------------------ */
 /* Graphs (Eq. 2-3: couplings J and biases h)                           */
 /* ------------------------------------------------------------------ */
@@ -189,8 +207,25 @@ typedef struct psa_run_desc {
     int32_t block;
     int32_t trials_per_group;
     int32_t lanes_per_task;
-    uint32_t flags; /* PSA_PATH_* */
+    uint32_t flags; /* PSA_PATH_*, PSA_TUNE */
+    uint32_t algorithm; /* PSA_ALG_PSA or PSA_ALG_SPSA */
+    double p_stall;     /* SpSA: probability that an input is held (0..1) */
 } psa_run_desc;
+
+/* Update rule (psa_run_desc.algorithm).
+ *   PSA_ALG_PSA   plain pSA (Eq. 3): every step forms the input of each
+ *                 p-bit from the spins of the previous step.
+ *   PSA_ALG_SPSA  stalled p-bits (Eq. 5): at each step t > 0 the input of a
+ *                 p-bit (its whole pre-activation x = (I0 lambda)(L + delta)
+ *                 of the step it was last formed) is held with probability
+ *                 p_stall, else formed anew; step 0 always forms it.  The
+ *                 stall of p-bit i, trial k at step t is decided by Philox
+ *                 word i mod 4 of counter (t, i/4, k, 4): held iff
+ *                 (word >> 8) < floor(p_stall 2^24).  The output rule
+ *                 (timing gate, r, tanh) is unchanged.  A job keeps the held
+ *                 inputs on the device (4 bytes per p-bit and trial). */
+#define PSA_ALG_PSA 0u
+#define PSA_ALG_SPSA 1u
 
 /* Field-computation path of a run (psa_run_desc.flags).  AUTO picks by a
  * cost model (long rows -> dense); CSR walks the sparse rows from LDS /
@@ -211,7 +246,8 @@ typedef struct psa_run_desc {
 
 /* Fill *d with the defaults: steps 1000, trials 1, seed 0, the paper's I0
  * endpoints (i0_min = i0_max = -1), no variability (sigmas 0, p_mean 1),
- * no explicit arrays, automatic block size. */
+ * no explicit arrays, automatic block size, plain pSA (p_stall 0.5, the
+ * paper's value, used only with PSA_ALG_SPSA). */
 void psa_run_desc_default(psa_run_desc *d);
 
 /* Output placement flags of the read calls and psa_anneal. */
@@ -235,6 +271,18 @@ psa_status psa_job_reset(psa_job *job);
  * context's stream; returns once they are queued. */
 psa_status psa_job_step(psa_job *job, int32_t k);
 
+/* How a job runs (chosen at creation). */
+typedef struct psa_job_info {
+    uint32_t path;             /* PSA_PATH_CSR or PSA_PATH_DENSE              */
+    int32_t trials_per_group;  /* CSR: trials per workgroup (1 or 4)          */
+    int32_t lanes_per_task;    /* CSR, one trial per workgroup: 1, 2 or 4     */
+    int32_t block;             /* CSR: threads per workgroup                  */
+    int32_t dense_encoding;    /* dense: 1 = int8 entries, 2 = 2-bit fields   */
+    uint32_t algorithm;        /* PSA_ALG_*                                   */
+} psa_job_info;
+
+psa_status psa_job_get_info(const psa_job *job, psa_job_info *out);
+
 /* Current step index t (the number of steps applied so far). */
 psa_status psa_job_position(const psa_job *job, int32_t *t);
 
@@ -243,7 +291,9 @@ psa_status psa_job_position(const psa_job *job, int32_t *t);
 psa_status psa_job_read_spins(psa_job *job, int8_t *out, uint32_t flags);
 
 /* Replace the spins of all trials by in[trials][n] (+1/-1 only; host or
- * device per flags) and set the step index to t (checkpoint / resume). */
+ * device per flags) and set the step index to t (checkpoint / resume).
+ * EUNSUPPORTED for an SpSA job with t > 0 (its held inputs are not part of
+ * the spins). */
 psa_status psa_job_write_spins(psa_job *job, const int8_t *in, int32_t t,
                                uint32_t flags);
 
@@ -327,9 +377,9 @@ typedef struct psa_tune_result {
  * scratch runs of `desc` (same graph, trials, schedule and factors) over
  * `probe_steps` steps (>= 1, clipped to the schedule) after one warm-up
  * step, and return the fastest.  The result is also stored in the
- * context's tuning cache, keyed by mode, trials and the graph's shape class
- * (n and mean degree within about 9 % and 19 %, coupling encoding, rows of
- * at most 255 entries), for PSA_TUNE.  Queues and waits on the context's
+ * context's tuning cache, keyed by mode, trials, update rule and the
+ * graph's shape class (n and mean degree within about 9 % and 19 %,
+ * coupling encoding, rows of at most 255 entries), for PSA_TUNE.  Queues and waits on the context's
  * stream; the caller's jobs are not touched. */
 psa_status psa_autotune(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *desc,
                         int32_t probe_steps, uint32_t mode, psa_tune_result *out);

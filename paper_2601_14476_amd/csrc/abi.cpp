@@ -69,6 +69,7 @@ void job_free(psa_job *j) {
     dev_free(j->d_order);
     dev_free(j->d_m);
     dev_free(j->d_spins);
+    dev_free(j->d_xs);
     dev_free(j->d_scratch);
     psa_ctx *ctx = j->retained ? j->ctx : nullptr;
     psa_graph *g = j->graph_ref;
@@ -148,9 +149,75 @@ void psa_ctx_destroy(psa_ctx *ctx) {
     psa::ctx_release(ctx);
 }
 
+psa_status psa_ctx_set_timing(psa_ctx *ctx, int32_t on) {
+    if (!ctx) {
+        set_error("psa_ctx_set_timing: ctx is NULL");
+        return PSA_EINVAL;
+    }
+    ctx->timing = on != 0;
+    return PSA_OK;
+}
+
+psa_status psa_ctx_timing_read(psa_ctx *ctx, psa_timing *out) {
+    if (!ctx || !out) {
+        set_error("psa_ctx_timing_read: NULL argument");
+        return PSA_EINVAL;
+    }
+    PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    for (const auto &sp : ctx->spans) {
+        PSA_HIP(hipEventSynchronize(sp.end), "hipEventSynchronize");
+        float ms = 0.0f;
+        PSA_HIP(hipEventElapsedTime(&ms, sp.begin, sp.end), "hipEventElapsedTime");
+        ctx->timed_ms[sp.family] += ms;
+        ctx->timed_launches[sp.family] += sp.launches;
+        ctx->event_pool.push_back(sp.begin);
+        ctx->event_pool.push_back(sp.end);
+    }
+    ctx->spans.clear();
+    out->anneal_ms = ctx->timed_ms[psa::kTimeAnneal];
+    out->batch_ms = ctx->timed_ms[psa::kTimeBatch];
+    out->dense_ms = ctx->timed_ms[psa::kTimeDense];
+    out->anneal_launches = ctx->timed_launches[psa::kTimeAnneal];
+    out->batch_launches = ctx->timed_launches[psa::kTimeBatch];
+    out->dense_launches = ctx->timed_launches[psa::kTimeDense];
+    for (int f = 0; f < 3; ++f) {
+        ctx->timed_ms[f] = 0.0;
+        ctx->timed_launches[f] = 0;
+    }
+    return PSA_OK;
+}
+
 }  // extern "C"
 
 namespace psa {
+
+psa_status time_begin(psa_ctx *ctx, hipStream_t stream, hipEvent_t *ev) {
+    *ev = nullptr;
+    if (!ctx->timing) return PSA_OK;
+    if (ctx->event_pool.empty()) {
+        PSA_HIP(hipEventCreate(ev), "hipEventCreate");
+    } else {
+        *ev = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+    }
+    PSA_HIP(hipEventRecord(*ev, stream), "hipEventRecord");
+    return PSA_OK;
+}
+
+psa_status time_end(psa_ctx *ctx, hipStream_t stream, int family, hipEvent_t begin,
+                    int64_t launches) {
+    if (!begin) return PSA_OK;
+    hipEvent_t end = nullptr;
+    if (ctx->event_pool.empty()) {
+        PSA_HIP(hipEventCreate(&end), "hipEventCreate");
+    } else {
+        end = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+    }
+    PSA_HIP(hipEventRecord(end, stream), "hipEventRecord");
+    ctx->spans.push_back({family, begin, end, launches});
+    return PSA_OK;
+}
 
 void ctx_retain(psa_ctx *ctx) { ctx->refs.fetch_add(1); }
 
@@ -163,6 +230,11 @@ void ctx_release(psa_ctx *ctx) {
     if (ctx->d_batch_work) (void)hipFree(ctx->d_batch_work);
     if (ctx->d_dense_table) (void)hipFree(ctx->d_dense_table);
     if (ctx->d_dense_work) (void)hipFree(ctx->d_dense_work);
+    for (const auto &sp : ctx->spans) {
+        (void)hipEventDestroy(sp.begin);
+        (void)hipEventDestroy(sp.end);
+    }
+    for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->stream2) (void)hipStreamDestroy(ctx->stream2);
@@ -244,6 +316,8 @@ void psa_run_desc_default(psa_run_desc *d) {
     d->i0_min = -1.0;
     d->i0_max = -1.0;
     d->p_mean = 1.0;
+    d->algorithm = PSA_ALG_PSA;
+    d->p_stall = 0.5;
 }
 
 psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *desc,
@@ -278,6 +352,14 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
     if ((desc->flags & ~(PSA_PATH_MASK | PSA_TUNE)) != 0 ||
         (desc->flags & PSA_PATH_MASK) == PSA_PATH_MASK) {
         set_error("psa_job_create: unknown flags");
+        return PSA_EINVAL;
+    }
+    if (desc->algorithm != PSA_ALG_PSA && desc->algorithm != PSA_ALG_SPSA) {
+        set_error("psa_job_create: unknown algorithm");
+        return PSA_EINVAL;
+    }
+    if (desc->algorithm == PSA_ALG_SPSA && !(desc->p_stall >= 0.0 && desc->p_stall <= 1.0)) {
+        set_error("psa_job_create: p_stall must be in [0, 1]");
         return PSA_EINVAL;
     }
     if (desc->flags & PSA_TUNE) {
@@ -374,6 +456,13 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
         const size_t mb = 2 * static_cast<size_t>(j->tp) * static_cast<size_t>(g->np);
         if ((st = dev_upload<int8_t>(&j->d_m, nullptr, mb, "job dense spins")) != PSA_OK) return st;
     }
+    if (desc->algorithm == PSA_ALG_SPSA) {
+        // held inputs: [t4/4][n4][4] floats, formed at step 0 before any read
+        const size_t xb = static_cast<size_t>(n4) * static_cast<size_t>(j->run.t4);
+        if ((st = dev_upload<float>(&j->d_xs, nullptr, xb, "job held inputs")) != PSA_OK) return st;
+        j->run.xs = j->d_xs;
+        j->run.stall24 = static_cast<uint32_t>(std::floor(desc->p_stall * 16777216.0));
+    }
     j->run.i0 = j->d_i0;
     j->run.lambda = j->d_lambda;
     j->run.delta = j->d_delta;
@@ -414,10 +503,28 @@ psa_status psa_job_step(psa_job *job, int32_t k) {
         PSA_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "hipStreamWaitEvent");
         return st;
     }
+    hipEvent_t ev = nullptr;
+    psa_status st = psa::time_begin(job->ctx, job->ctx->stream, &ev);
+    if (st != PSA_OK) return st;
     PSA_HIP(psa::launch_anneal(job->ctx->stream, job->g->dev, job->run, job->plan, job->d_order,
                                job->t, t_end),
             "anneal launch");
+    if ((st = psa::time_end(job->ctx, job->ctx->stream, psa::kTimeAnneal, ev, 1)) != PSA_OK) return st;
     job->t = t_end;
+    return PSA_OK;
+}
+
+psa_status psa_job_get_info(const psa_job *job, psa_job_info *out) {
+    if (!job || !out) {
+        set_error("psa_job_get_info: NULL argument");
+        return PSA_EINVAL;
+    }
+    out->path = job->plan.dense ? PSA_PATH_DENSE : PSA_PATH_CSR;
+    out->trials_per_group = job->plan.dense ? 0 : job->plan.tpw;
+    out->lanes_per_task = job->plan.dense ? 0 : job->plan.lpt;
+    out->block = job->plan.dense ? 256 : job->plan.block;
+    out->dense_encoding = job->plan.dense ? (job->g->dense_enc == psa::kDenseT2 ? 2 : 1) : 0;
+    out->algorithm = job->run.xs ? PSA_ALG_SPSA : PSA_ALG_PSA;
     return PSA_OK;
 }
 
@@ -455,6 +562,11 @@ psa_status psa_job_write_spins(psa_job *job, const int8_t *in, int32_t t, uint32
     if (!job || !in || (flags & ~PSA_OUT_DEVICE) != 0 || t < 0 || t > job->run.steps) {
         set_error("psa_job_write_spins: invalid arguments");
         return PSA_EINVAL;
+    }
+    if (job->run.xs != nullptr && t > 0) {
+        set_error("psa_job_write_spins: an SpSA job resumes only at step 0 (held inputs are not "
+                  "part of the spins)");
+        return PSA_EUNSUPPORTED;
     }
     PSA_HIP(hipSetDevice(job->ctx->device), "hipSetDevice");
     const int32_t n = job->g->info.n;

@@ -48,12 +48,9 @@ __device__ __forceinline__ Words4 block_of(uint32_t t, uint32_t m, uint32_t k, u
     return philox4x32_10(t, m, k, tag, k0, k1);
 }
 
-// Eq. 6 decision for one p-bit and trial: +1 iff tanh((I0 lambda)(L + delta)) > r.
-__device__ __forceinline__ bool goes_up(float a, float d, int32_t L, uint32_t rword) {
-    const float b = static_cast<float>(L) + d;
-    const float x = a * b;
-    return tanh_f32(x) > r_of(rword);
-}
+// Eq. 6 decision for one p-bit and trial: +1 iff tanh(x) > r, x the
+// (fresh or held) pre-activation (I0 lambda)(L + delta).
+__device__ __forceinline__ bool goes_up(float x, uint32_t rword) { return tanh_f32(x) > r_of(rword); }
 
 template <int TPW, int CSR>
 struct Enc {
@@ -222,12 +219,19 @@ template <int CSR, int LPT>
 __device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, uint32_t sub,
                                                    uint32_t k, uint32_t t, float i0t,
                                                    const unsigned char *cur, uint32_t k0,
-                                                   uint32_t k1) {
+                                                   uint32_t k1, const Stall &st) {
     constexpr int P = 4 / LPT;
     constexpr bool kU = Enc<1, CSR>::kU;
     const bool need_gate = any_gate(v.thr, m);
-    uint32_t rw[P], gw[P];
+    uint32_t rw[P], gw[P], sw[P];
     task_words<LPT>(t, static_cast<uint32_t>(m), k, sub, need_gate, k0, k1, rw, gw);
+#pragma unroll
+    for (int j = 0; j < P; ++j) sw[j] = 0u;
+    if (st.xs != nullptr && t > 0) {
+        const Words4 b = block_of(t, static_cast<uint32_t>(m), k, kTagStall, k0, k1);
+#pragma unroll
+        for (int j = 0; j < P; ++j) sw[j] = word_of(b, sub * P + j);
+    }
     const int32_t base = 4 * m + static_cast<int32_t>(sub) * P;
     int32_t L[P];
     if constexpr (CSR == kCsrUnit) {
@@ -249,7 +253,8 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, ui
         const uint32_t old = cur[i];
         const uint32_t th = v.thr[i];
         const bool fire = th >= kGateOne || fires(gw[j], th);
-        const bool up = goes_up(i0t * v.lam[i], v.dlt[i], L[j], rw[j]);
+        const float x = input_of(i0t * v.lam[i], v.dlt[i], L[j], st, i, k, t, sw[j]);
+        const bool up = goes_up(x, rw[j]);
         const uint32_t nb = kU ? (up ? 1u : 0u) : (up ? 0x01u : 0xFFu);
         out |= (fire ? nb : old) << (8 * j);
     }
@@ -263,7 +268,7 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, ui
 template <int CSR>
 __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int32_t q, uint32_t t,
                                                  float i0t, const uint32_t *cur, uint32_t *nxt,
-                                                 uint32_t k0, uint32_t k1) {
+                                                 uint32_t k0, uint32_t k1, const Stall &st) {
     constexpr bool kU = Enc<4, CSR>::kU;
     int32_t L[4][4];
     uint32_t word[4], th[4];
@@ -295,10 +300,19 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
         }
         const Words4 r = block_of(t, static_cast<uint32_t>(m), k, kTagR, k0, k1);
         const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+        uint32_t sw[4] = {0u, 0u, 0u, 0u};
+        if (st.xs != nullptr && t > 0) {
+            const Words4 b = block_of(t, static_cast<uint32_t>(m), k, kTagStall, k0, k1);
+            sw[0] = b.x;
+            sw[1] = b.y;
+            sw[2] = b.z;
+            sw[3] = b.w;
+        }
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             const bool fire = th[p] >= kGateOne || fires(gw[p], th[p]);
-            const bool up = goes_up(a[p], d[p], L[p][kk], rw[p]);
+            const float x = input_of(a[p], d[p], L[p][kk], st, 4 * m + p, k, t, sw[p]);
+            const bool up = goes_up(x, rw[p]);
             const uint32_t nb = kU ? (up ? 1u : 0u) : (up ? 0x01u : 0xFFu);
             if (fire) word[p] = (word[p] & ~(0xFFu << (8 * kk))) | (nb << (8 * kk));
         }
@@ -419,6 +433,7 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
 
     unsigned char *cur = buf0;
     unsigned char *nxt = buf1;
+    const Stall st{a.xs, a.stall24, n4};
     for (int32_t t = a.t_begin; t < a.t_end; ++t) {
         const float i0t = a.i0[t];
         if constexpr (TPW == 1) {
@@ -428,7 +443,7 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
                 const int32_t m = v.order[slot];
                 const uint32_t b = task_one_trial<CSR, LPT>(v, m, sub, static_cast<uint32_t>(q),
                                                             static_cast<uint32_t>(t), i0t, cur,
-                                                            a.k0, a.k1);
+                                                            a.k0, a.k1, st);
                 constexpr int P = 4 / LPT;
                 const int32_t at = 4 * m + static_cast<int32_t>(sub) * P;
                 if constexpr (P == 4) {
@@ -449,7 +464,7 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
             for (int32_t slot = threadIdx.x; slot < tasks; slot += BLOCK)
                 task_four_trials<CSR>(v, v.order[slot], q, static_cast<uint32_t>(t), i0t,
                                       reinterpret_cast<const uint32_t *>(cur),
-                                      reinterpret_cast<uint32_t *>(nxt), a.k0, a.k1);
+                                      reinterpret_cast<uint32_t *>(nxt), a.k0, a.k1, st);
         }
         __syncthreads();
         unsigned char *tmp = cur;
@@ -664,6 +679,8 @@ void fill_anneal_args(AnnealArgs *a, const DevGraph &g, const DevRun &run, const
     a->k0 = run.key0;
     a->k1 = run.key1;
     a->spins = run.spins;
+    a->xs = run.xs;
+    a->stall24 = run.stall24;
 }
 
 bool plan_batch_item(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t lpt_req,

@@ -182,6 +182,8 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
         d.thr = job->run.thr24;
         d.k0 = job->run.key0;
         d.k1 = job->run.key1;
+        d.xs = job->run.xs;
+        d.stall24 = job->run.stall24;
         const int32_t e = g->dense_enc == kDenseT2 ? 1 : 0;
         by_enc[e].push_back(static_cast<int32_t>(table.size()));
         nb[e] = std::min(nb[e], job->plan.nb);
@@ -220,13 +222,18 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
                            hipMemcpyHostToDevice, ctx->stream2),
             "dense work upload");
     const int4 *dwork = static_cast<const int4 *>(ctx->d_dense_work);
+    hipEvent_t ev = nullptr;
+    if ((st = time_begin(ctx, ctx->stream2, &ev)) != PSA_OK) return st;
+    int64_t launches = 0;
     for (int e = 0; e < 2; ++e) {
         if (len[e] == 0) continue;
         PSA_HIP(psa::launch_dense_steps(ctx->stream2, static_cast<const psa::DenseJob *>(ctx->d_dense_table),
                                         dwork + off[e], static_cast<int32_t>(len[e]), nb[e],
                                         e == 1 ? kDenseT2 : kDenseI8, max_steps),
                 "dense step launch");
+        launches += max_steps;
     }
+    if ((st = time_end(ctx, ctx->stream2, kTimeDense, ev, launches)) != PSA_OK) return st;
     for (size_t j = 0; j < live.size(); ++j) {
         psa_job *job = live[j];
         const psa::DenseJob &d = table[j];
@@ -327,10 +334,13 @@ psa_status psa_jobs_step_batch(psa_ctx *ctx, int32_t count, psa_job *const *jobs
                            hipMemcpyHostToDevice, ctx->stream),
             "batch work upload");
     const int32_t block = max_lanes > 1024 ? 1024 : (max_lanes > 256 ? 512 : 256);
+    hipEvent_t ev = nullptr;
+    if ((st = psa::time_begin(ctx, ctx->stream, &ev)) != PSA_OK) return st;
     PSA_HIP(psa::launch_anneal_batch(ctx->stream, static_cast<const psa::BatchJob *>(ctx->d_batch_table),
                                      static_cast<const int2 *>(ctx->d_batch_work),
                                      static_cast<int32_t>(work.size()), block, lds),
             "batch anneal launch");
+    if ((st = psa::time_end(ctx, ctx->stream, psa::kTimeBatch, ev, 1)) != PSA_OK) return st;
     for (int32_t j = 0; j < count; ++j) jobs[j]->t = std::max(jobs[j]->t, t_end[j]);
     if (!dense_jobs.empty())
         PSA_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "hipStreamWaitEvent");

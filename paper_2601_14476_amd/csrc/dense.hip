@@ -58,6 +58,15 @@ __device__ __forceinline__ v4i t2_unpack(uint32_t word) {
     return v4i{t2_dword(word, 0), t2_dword(word, 1), t2_dword(word, 2), t2_dword(word, 3)};
 }
 
+// Device-global views of pointers read from the job table (so that loads
+// are global, not flat, and do not wait on LDS traffic).
+template <typename T>
+using gptr = const T __attribute__((address_space(1))) *;
+template <typename T, typename P>
+__device__ __forceinline__ gptr<T> as_global(P p) {
+    return (gptr<T>)(p);
+}
+
 template <int ENC>
 struct AFrag;
 template <>
@@ -75,7 +84,7 @@ __global__ __launch_bounds__(256) void dense_step_kernel(const DenseJob *__restr
                                                          const int4 *__restrict__ work, int32_t t_off) {
     constexpr int kTrials = 16 * NB;
     constexpr int kBVec = kTrials * (kKC / 16);        // 16-byte pieces of one spin chunk
-    constexpr int kBPer = (kBVec + 255) / 256;
+    constexpr int kBPer = (kBVec + 255) / 256;  // 1 or 2
     __shared__ __align__(16) int8_t bt[2][kTrials * kLdsStride];
     const int4 w = work[blockIdx.x];  // (job, row group, trial tile, -); job < 0: empty slot
     if (w.x < 0) return;
@@ -91,29 +100,32 @@ __global__ __launch_bounds__(256) void dense_step_kernel(const DenseJob *__restr
     const int lr = lane & 15;
     const int kgrp = (lane >> 4) * 16;
     const int32_t wrow0 = w.y * kGroupRows + wave * kWaveRows;
-    const bool active = wrow0 < np;  // np is a multiple of 128: a wave is all in or all out
+    // np is a multiple of 128: a wave's 64 rows are all in or all out.  A
+    // wave past the end multiplies the last 64 rows again (no branches in the
+    // main loop) and skips the epilogue.
+    const bool active = wrow0 < np;
+    const int32_t arow0 = active ? wrow0 : np - kWaveRows;
     const int32_t ktiles = np / 64;
 
-    int4 breg[kBPer];
+    static_assert(kBVec == 128 || kBVec % 256 == 0, "spin chunk split");
+    // spin chunk kc+1 staged in registers while chunk kc is multiplied; with
+    // a 128-piece chunk the upper half of the threads repeat the lower half
+    // (same bytes to the same LDS place), keeping the loop free of branches
+    v4i breg0, breg1;
+    const int c0 = static_cast<int>(threadIdx.x) % kBVec;
+    const gptr<int8_t> gcur = as_global<int8_t>(cur);
     auto fetch_b = [&](int kc) {
-#pragma unroll
-        for (int q = 0; q < kBPer; ++q) {
-            const int c = static_cast<int>(threadIdx.x) + q * 256;
-            if (kBVec % 256 == 0 || c < kBVec) {
-                const int tr = c >> 3, part = (c & 7) * 16;
-                breg[q] = *reinterpret_cast<const int4 *>(cur + static_cast<size_t>(trial0 + tr) * np +
-                                                          kc * kKC + part);
-            }
+        breg0 = *as_global<v4i>(gcur + static_cast<size_t>(trial0 + (c0 >> 3)) * np + kc * kKC + (c0 & 7) * 16);
+        if constexpr (kBPer == 2) {
+            const int c = c0 + 256;
+            breg1 = *as_global<v4i>(gcur + static_cast<size_t>(trial0 + (c >> 3)) * np + kc * kKC + (c & 7) * 16);
         }
     };
     auto store_b = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < kBPer; ++q) {
-            const int c = static_cast<int>(threadIdx.x) + q * 256;
-            if (kBVec % 256 == 0 || c < kBVec) {
-                const int tr = c >> 3, part = (c & 7) * 16;
-                *reinterpret_cast<int4 *>(&bt[buf][tr * kLdsStride + part]) = breg[q];
-            }
+        *reinterpret_cast<v4i *>(&bt[buf][(c0 >> 3) * kLdsStride + (c0 & 7) * 16]) = breg0;
+        if constexpr (kBPer == 2) {
+            const int c = c0 + 256;
+            *reinterpret_cast<v4i *>(&bt[buf][(c >> 3) * kLdsStride + (c & 7) * 16]) = breg1;
         }
     };
     auto fetch_a = [&](int kc, AFrag<ENC> &dst) {
@@ -121,12 +133,12 @@ __global__ __launch_bounds__(256) void dense_step_kernel(const DenseJob *__restr
         for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb) {
-                const size_t row = static_cast<size_t>(wrow0 + rb * 16 + lr);
+                const size_t row = static_cast<size_t>(arow0 + rb * 16 + lr);
                 if constexpr (ENC == kDenseI8) {
-                    const int8_t *J = static_cast<const int8_t *>(jb.J);
-                    dst.v[kt][rb] = *reinterpret_cast<const v4i *>(J + row * np + kc * kKC + kt * 64 + kgrp);
+                    const gptr<int8_t> J = as_global<int8_t>(jb.J);
+                    dst.v[kt][rb] = *as_global<v4i>(J + row * np + kc * kKC + kt * 64 + kgrp);
                 } else {
-                    const uint32_t *J = static_cast<const uint32_t *>(jb.J);
+                    const gptr<uint32_t> J = as_global<uint32_t>(jb.J);
                     dst.v[kt][rb] = J[(row * ktiles + kc * 2 + kt) * 4 + (lane >> 4)];
                 }
             }
@@ -159,23 +171,26 @@ __global__ __launch_bounds__(256) void dense_step_kernel(const DenseJob *__restr
         }
     };
     const int nkc = np / kKC;
-    // one chunk: prefetch chunk kc+1 (spins into registers, couplings into
-    // `pre`), multiply chunk kc, then publish the prefetched spins
+    // one chunk: prefetch chunk kc+1 (the last chunk fetches itself again)
+    // -- spins into registers, couplings into `pre` --, multiply chunk kc,
+    // then publish the prefetched spins into the other LDS buffer
     auto chunk = [&](int kc, const AFrag<ENC> &use, AFrag<ENC> &pre) {
-        const bool more = kc + 1 < nkc;
-        if (more) {
-            fetch_b(kc + 1);
-            if (active) fetch_a(kc + 1, pre);
-        }
-        if (active) compute(kc & 1, use);
-        if (more) store_b((kc + 1) & 1);
+        const int kn = kc + 1 < nkc ? kc + 1 : kc;
+        fetch_b(kn);
+        fetch_a(kn, pre);
+        // keep the prefetch ahead of the matrix work (the scheduler would
+        // otherwise sink the loads next to their first use)
+        __builtin_amdgcn_sched_barrier(0);
+        compute(kc & 1, use);
+        __builtin_amdgcn_sched_barrier(0);
+        store_b((kc + 1) & 1);
         __syncthreads();
     };
 
     AFrag<ENC> fa, fb;
     fetch_b(0);
     store_b(0);
-    if (active) fetch_a(0, fa);
+    fetch_a(0, fa);
     __syncthreads();
     for (int kc = 0; kc < nkc; kc += 2) {
         chunk(kc, fa, fb);
@@ -183,11 +198,24 @@ __global__ __launch_bounds__(256) void dense_step_kernel(const DenseJob *__restr
     }
     if (!active) return;
 
-    // epilogue: lane owns p-bits 4m..4m+3 of each row block for trial columns nb
+    // epilogue: lane owns p-bits 4m..4m+3 of each row block for trial columns
+    // nb.  Row blocks run as a loop with a uniform index; each pass picks its
+    // accumulators with constant indices, so the accumulator array stays in
+    // registers while the body (Philox blocks and activations, unrolled over
+    // the trial blocks) is emitted NB times rather than 4 NB times.
     const float i0t = jb.i0[t];
     const int32_t scale = jb.scale;
-#pragma unroll
+    const Stall st{jb.xs, jb.stall24, jb.n4};
+#pragma unroll 1
     for (int rb = 0; rb < 4; ++rb) {
+        v4i arow[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            arow[nb] = acc[0][nb];
+#pragma unroll
+            for (int q = 1; q < 4; ++q)
+                if (rb == q) arow[nb] = acc[q][nb];
+        }
         const int32_t i0 = wrow0 + rb * 16 + (lane >> 4) * 4;
         if (i0 >= jb.n4) continue;
         const int32_t m = i0 >> 2;
@@ -219,12 +247,21 @@ __global__ __launch_bounds__(256) void dense_step_kernel(const DenseJob *__restr
             const Words4 r = philox4x32_10(static_cast<uint32_t>(t), static_cast<uint32_t>(m),
                                            static_cast<uint32_t>(k), kTagR, jb.k0, jb.k1);
             const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+            uint32_t sw[4] = {0u, 0u, 0u, 0u};
+            if (st.xs != nullptr && t > 0) {
+                const Words4 b = philox4x32_10(static_cast<uint32_t>(t), static_cast<uint32_t>(m),
+                                               static_cast<uint32_t>(k), kTagStall, jb.k0, jb.k1);
+                sw[0] = b.x;
+                sw[1] = b.y;
+                sw[2] = b.z;
+                sw[3] = b.w;
+            }
             uint32_t out = 0u;
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
-                const int32_t L = hv[p] + scale * acc[rb][nb][p];
-                const float b = static_cast<float>(L) + dv[p];
-                const float x = av[p] * b;
+                const int32_t L = hv[p] + scale * arow[nb][p];
+                const float x = input_of(av[p], dv[p], L, st, i0 + p, static_cast<uint32_t>(k),
+                                         static_cast<uint32_t>(t), sw[p]);
                 const bool up = tanh_f32(x) > r_of(rw[p]);
                 const bool fire = tv[p] >= kGateOne || fires(gw[p], tv[p]);
                 const uint32_t ob = (old >> (8 * p)) & 0xFFu;

@@ -13,7 +13,7 @@
 namespace psa {
 
 // Purposes of the random words; part of the Philox counter.
-enum : uint32_t { kTagInit = 0, kTagR = 1, kTagGate = 2, kTagVar = 3 };
+enum : uint32_t { kTagInit = 0, kTagR = 1, kTagGate = 2, kTagVar = 3, kTagStall = 4 };
 
 constexpr uint32_t kGateOne = 1u << 24;
 
@@ -87,6 +87,28 @@ __device__ __forceinline__ float tanh_f32(float x) {
     float y = 1.0f - 2.0f / (e + 1.0f);
     y = (a >= 9.0f) ? 1.0f : y;
     return copysignf(y, x);
+}
+
+// SpSA held-input state of one run: pre-activations [t4/4][n4][4] (trial
+// group, p-bit, trial in group); xs == nullptr for plain pSA.
+struct Stall {
+    float *xs;
+    uint32_t s24;
+    int32_t n4;
+};
+
+// Input stage of p-bit i, trial k at step t (Eq. 5 on the pre-activation
+// x = a (L + d), a = I0 lambda_i, d = delta_i): with SpSA the input is held
+// from the last refresh iff t > 0 and (stall word >> 8) < stall24, else it is
+// formed anew and stored.  Plain pSA: always fresh.
+__device__ __forceinline__ float input_of(float a, float d, int32_t L, const Stall &st, int32_t i,
+                                          uint32_t k, uint32_t t, uint32_t sword) {
+    const float x = a * (static_cast<float>(L) + d);
+    if (st.xs == nullptr) return x;
+    float *slot = st.xs + ((static_cast<size_t>(k >> 2) * st.n4 + i) * 4 + (k & 3u));
+    if (t > 0 && (sword >> 8) < st.s24) return *slot;
+    *slot = x;
+    return x;
 }
 
 // Sign-extend byte k of a packed word of four int8 spins.

@@ -38,7 +38,7 @@ inline psa_status hip_fail(hipError_t err, const char *what) {
     } while (0)
 
 // Shape class of a tuning problem (tune.cpp).
-using TuneKey = std::array<int64_t, 6>;
+using TuneKey = std::array<int64_t, 7>;
 
 // Device copy of a graph in CSR form.  Row i holds its neighbours j in
 // increasing order with their couplings J_ij.  Per-p-bit arrays are padded to
@@ -75,6 +75,8 @@ struct DevRun {
     const float *delta = nullptr;         // [n4]
     const uint32_t *thr24 = nullptr;      // [n4] (padding p-bits: 0, never fire)
     int8_t *spins = nullptr;              // [n][t4]
+    float *xs = nullptr;                  // SpSA held inputs [t4/4][n4][4], else nullptr
+    uint32_t stall24 = 0;                 // SpSA stall threshold
 };
 
 // How the persistent anneal kernel is launched for one run.
@@ -108,6 +110,10 @@ struct AnnealArgs {
     const int32_t *order;
     uint32_t k0, k1;
     int8_t *spins;
+    // SpSA (Eq. 5): held pre-activations [t4/4][n4][4] (nullptr = pSA) and the
+    // stall threshold (an input is held iff (stall word >> 8) < stall24)
+    float *xs;
+    uint32_t stall24;
 };
 
 // Kernel variants a batched launch can mix (one trial per workgroup).
@@ -152,6 +158,8 @@ struct DenseJob {
     const float *dlt;
     const uint32_t *thr;
     uint32_t k0, k1;
+    float *xs;         // SpSA held inputs [t4/4][n4][4], else nullptr
+    uint32_t stall24;  // SpSA stall threshold
 };
 
 // Choose tpw / lanes per task / CSR placement / block for a run
@@ -253,6 +261,13 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
 // miss (mode PSA_TUNE_ALONE or PSA_TUNE_BATCH); clears PSA_TUNE (tune.cpp).
 psa_status tuned_desc(psa_ctx *ctx, const psa_graph *g, psa_run_desc *d, uint32_t mode);
 
+// Per-family timing (abi.cpp): begin/end a span on `stream` when the
+// context records timing (no-ops otherwise).
+enum : int { kTimeAnneal = 0, kTimeBatch = 1, kTimeDense = 2 };
+psa_status time_begin(psa_ctx *ctx, hipStream_t stream, hipEvent_t *ev);
+psa_status time_end(psa_ctx *ctx, hipStream_t stream, int family, hipEvent_t begin,
+                    int64_t launches);
+
 // Context references (abi.cpp).
 void ctx_retain(psa_ctx *ctx);
 void ctx_release(psa_ctx *ctx);
@@ -285,6 +300,18 @@ struct psa_ctx {
     size_t dense_table_cap = 0, dense_work_cap = 0;
     std::vector<psa::DenseJob> h_dense_table;
     std::vector<int4> h_dense_work;
+    // per-family device timing (psa_ctx_set_timing): event pairs awaiting
+    // resolution, by family 0 anneal, 1 batch, 2 dense
+    bool timing = false;
+    struct TimedSpan {
+        int family;
+        hipEvent_t begin, end;
+        int64_t launches;
+    };
+    std::vector<TimedSpan> spans;
+    std::vector<hipEvent_t> event_pool;
+    double timed_ms[3] = {0.0, 0.0, 0.0};
+    int64_t timed_launches[3] = {0, 0, 0};
     // measured path / launch shape per shape class (psa_autotune)
     std::mutex tune_mu;
     std::map<psa::TuneKey, psa_tune_result> tune_cache;
@@ -324,6 +351,7 @@ struct psa_job {
     float *d_i0 = nullptr, *d_lambda = nullptr, *d_delta = nullptr;
     uint32_t *d_thr24 = nullptr;
     int8_t *d_spins = nullptr;
+    float *d_xs = nullptr;       // SpSA held inputs
     void *d_scratch = nullptr;   // read-out staging
     size_t scratch_bytes = 0;
 };

@@ -38,14 +38,14 @@ bool dense_encodable(const psa_graph *g) {
 
 // Shape class of a tuning problem: mode, trials, n within 1/8 octave, mean
 // degree within 1/4 octave, dense encoding, rows short enough for 16-bit
-// packing.
-TuneKey tune_key(const psa_graph *g, int32_t trials, uint32_t mode) {
+// packing, update rule.
+TuneKey tune_key(const psa_graph *g, int32_t trials, uint32_t mode, uint32_t algorithm) {
     const double n = std::max(g->info.n, 1);
     const double d = static_cast<double>(g->info.nnz) / n;
     const int64_t enc = dense_two_bit(g) ? 2 : (dense_encodable(g) ? 1 : 0);
     return TuneKey{static_cast<int64_t>(mode), trials, static_cast<int64_t>(std::ceil(std::log2(n) * 8.0)),
                    static_cast<int64_t>(std::floor(std::log2(1.0 + d) * 4.0)), enc,
-                   g->dev.max_degree <= 255 ? 1 : 0};
+                   g->dev.max_degree <= 255 ? 1 : 0, static_cast<int64_t>(algorithm)};
 }
 
 // Time one candidate: `copies` scratch runs of desc with the candidate's
@@ -175,7 +175,7 @@ psa_status psa_autotune(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *de
     r.model_dense_us = dense_ok ? 1e6 * psa::dense_step_seconds(g->info.n, run.t4, psa::dense_two_bit(g)) : -1.0;
     {
         std::lock_guard<std::mutex> lock(ctx->tune_mu);
-        ctx->tune_cache[psa::tune_key(g, base.trials, mode)] = r;
+        ctx->tune_cache[psa::tune_key(g, base.trials, mode, base.algorithm)] = r;
     }
     *out = r;
     return PSA_OK;
@@ -190,7 +190,7 @@ psa_status psa_tune_get(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *de
     }
     {
         std::lock_guard<std::mutex> lock(ctx->tune_mu);
-        auto it = ctx->tune_cache.find(psa::tune_key(g, desc->trials, mode));
+        auto it = ctx->tune_cache.find(psa::tune_key(g, desc->trials, mode, desc->algorithm));
         if (it != ctx->tune_cache.end()) {
             *out = it->second;
             return PSA_OK;

@@ -36,6 +36,7 @@ PSA_OUT_DEVICE = 1
 PSA_BATCH_SEQUENTIAL = 2
 PSA_PATH_AUTO, PSA_PATH_CSR, PSA_PATH_DENSE = 0, 1, 2
 PSA_TUNE = 4
+PSA_ALG_PSA, PSA_ALG_SPSA = 0, 1
 PSA_TUNE_ALONE, PSA_TUNE_BATCH = 0, 1
 
 _P = ctypes.c_void_p
@@ -55,13 +56,24 @@ class psa_run_desc(ctypes.Structure):
                 ("sigma_lambda", _f64), ("sigma_delta", _f64),
                 ("sigma_nu", _f64), ("p_mean", _f64), ("lambda_", _P),
                 ("delta", _P), ("thr24", _P), ("block", _i32),
-                ("trials_per_group", _i32), ("lanes_per_task", _i32), ("flags", _u32)]
+                ("trials_per_group", _i32), ("lanes_per_task", _i32), ("flags", _u32),
+                ("algorithm", _u32), ("p_stall", _f64)]
 
 
 class psa_tune_result(ctypes.Structure):
     _fields_ = [("path", _u32), ("trials_per_group", _i32), ("lanes_per_task", _i32),
                 ("candidates", _i32), ("us_per_step", _f64), ("csr_us_per_step", _f64),
                 ("dense_us_per_step", _f64), ("model_csr_us", _f64), ("model_dense_us", _f64)]
+
+
+class psa_job_info(ctypes.Structure):
+    _fields_ = [("path", _u32), ("trials_per_group", _i32), ("lanes_per_task", _i32),
+                ("block", _i32), ("dense_encoding", _i32), ("algorithm", _u32)]
+
+
+class psa_timing(ctypes.Structure):
+    _fields_ = [("anneal_ms", _f64), ("batch_ms", _f64), ("dense_ms", _f64),
+                ("anneal_launches", _i64), ("batch_launches", _i64), ("dense_launches", _i64)]
 
 
 class psa_batch_item(ctypes.Structure):
@@ -91,6 +103,8 @@ _SIGNATURES = [
     ("psa_ctx_create", _i32, [_i32, _P, ctypes.POINTER(_P)]),
     ("psa_ctx_synchronize", _i32, [_P]),
     ("psa_ctx_destroy", None, [_P]),
+    ("psa_ctx_set_timing", _i32, [_P, _i32]),
+    ("psa_ctx_timing_read", _i32, [_P, ctypes.POINTER(psa_timing)]),
     ("psa_graph_from_edges", _i32, [_P, _i32, _i64, _P, _P, _P, _P, _u32,
                                     ctypes.POINTER(_P)]),
     ("psa_graph_from_csr", _i32, [_P, _i32, _P, _P, _P, _P, _u32,
@@ -105,6 +119,7 @@ _SIGNATURES = [
     ("psa_job_reset", _i32, [_P]),
     ("psa_job_step", _i32, [_P, _i32]),
     ("psa_job_position", _i32, [_P, ctypes.POINTER(_i32)]),
+    ("psa_job_get_info", _i32, [_P, ctypes.POINTER(psa_job_info)]),
     ("psa_job_read_spins", _i32, [_P, _P, _u32]),
     ("psa_job_write_spins", _i32, [_P, _P, _i32, _u32]),
     ("psa_job_local_field", _i32, [_P, _P, _u32]),
@@ -221,6 +236,16 @@ class Context:
         self.handle = h
         self.device = device
 
+    def set_timing(self, on=True):
+        """Record device time per kernel family (psa_ctx_set_timing)."""
+        _check(_lib.psa_ctx_set_timing(self.handle, 1 if on else 0), "psa_ctx_set_timing")
+
+    def timing(self):
+        """Totals since the last call (psa_ctx_timing_read), as a dict."""
+        r = psa_timing()
+        _check(_lib.psa_ctx_timing_read(self.handle, ctypes.byref(r)), "psa_ctx_timing_read")
+        return {f: getattr(r, f) for f, _ in psa_timing._fields_}
+
     def synchronize(self):
         _check(_lib.psa_ctx_synchronize(self.handle), "psa_ctx_synchronize")
 
@@ -311,7 +336,8 @@ def variability_draw(n, seed, sigma_lambda=0.0, sigma_delta=0.0, sigma_nu=0.0, p
 def make_desc(steps, trials, seed=0, i0=None, i0_min=None, i0_max=None,
               sigma_lambda=0.0, sigma_delta=0.0, sigma_nu=0.0, p_mean=1.0,
               lam=None, delta=None, thr24=None, block=0, trials_per_group=0,
-              lanes_per_task=0, path=PSA_PATH_AUTO, tune=False):
+              lanes_per_task=0, path=PSA_PATH_AUTO, tune=False, algorithm=PSA_ALG_PSA,
+              p_stall=0.5):
     """Build a psa_run_desc; returns (desc, keepalive arrays).  tune=True sets
     PSA_TUNE (path and launch shape from the context's tuning cache)."""
     d = psa_run_desc()
@@ -336,6 +362,8 @@ def make_desc(steps, trials, seed=0, i0=None, i0_min=None, i0_max=None,
     d.trials_per_group = int(trials_per_group)
     d.lanes_per_task = int(lanes_per_task)
     d.flags = int(path) | (PSA_TUNE if tune else 0)
+    d.algorithm = int(algorithm)
+    d.p_stall = float(p_stall)
     return d, keep
 
 
@@ -388,6 +416,15 @@ class Job:
                                    ctypes.byref(out)), "psa_job_create")
         del keep
         self.handle = out
+
+    def info(self):
+        r = psa_job_info()
+        _check(_lib.psa_job_get_info(self.handle, ctypes.byref(r)), "psa_job_get_info")
+        return {f: getattr(r, f) for f, _ in psa_job_info._fields_}
+
+    @property
+    def dense(self):
+        return self.info()["path"] == PSA_PATH_DENSE
 
     def reset(self):
         _check(_lib.psa_job_reset(self.handle), "psa_job_reset")

@@ -200,3 +200,24 @@ def test_batch_four_trial_groups(psa, ctx):
     for jb, r in zip(jobs, refs):
         np.testing.assert_array_equal(jb.read_spins(), r.read_spins())
         np.testing.assert_array_equal(jb.energy_cut()[0], r.energy_cut()[0])
+
+
+def test_batch_mixes_spsa_and_psa(psa, ctx):
+    """SpSA and pSA jobs on CSR (one and four trials per workgroup) and dense
+    paths advance together in quanta and end where each ends alone."""
+    specs = [(inputs.gnm(600, 1800, 95), psa.PSA_ALG_SPSA, psa.PSA_PATH_CSR, 1, 9, 33),
+             (inputs.gnm(900, 2700, 96), psa.PSA_ALG_SPSA, psa.PSA_PATH_CSR, 4, 12, 27),
+             (inputs.erdos_renyi(500, 0.2, 97), psa.PSA_ALG_SPSA, psa.PSA_PATH_DENSE, 0, 20, 31),
+             (inputs.gnm(700, 2100, 98), psa.PSA_ALG_PSA, psa.PSA_PATH_CSR, 1, 5, 29)]
+    kw = dict(sigma_lambda=0.1, sigma_delta=0.1, sigma_nu=0.1, p_mean=0.8, p_stall=0.5)
+    jobs, refs = [], []
+    for (n, u, v, w), alg, path, tpw, T, S in specs:
+        g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
+        jobs.append(psa.Job(ctx, g, S, T, 3, algorithm=alg, path=path, trials_per_group=tpw, **kw))
+        ref = psa.Job(ctx, g, S, T, 3, algorithm=alg, path=psa.PSA_PATH_CSR, **kw)
+        ref.step(S)
+        refs.append(ref)
+    while any(j.position < j.steps for j in jobs):
+        psa.jobs_step_batch(ctx, [j for j in jobs if j.position < j.steps], 7)
+    for j, r in zip(jobs, refs):
+        np.testing.assert_array_equal(j.read_spins(), r.read_spins())

@@ -425,3 +425,65 @@ def test_objects_outlive_their_creators_handles(psa):
     job.step(20)
     np.testing.assert_array_equal(job.read_spins(), expect)
     job.close()
+
+
+@pytest.mark.parametrize("kind,tpw,lpt,path", [
+    ("unit", 1, 1, "csr"), ("unit", 1, 2, "csr"), ("unit", 1, 4, "csr"), ("unit", 4, 0, "csr"),
+    ("int", 1, 2, "csr"), ("int", 4, 0, "csr"), ("unit", 0, 0, "dense"), ("int", 0, 0, "dense")])
+def test_spsa_trajectories_match_oracle(psa, ctx, kind, tpw, lpt, path):
+    """Stalled p-bits (Eq. 5): spins after every chunk of steps equal the
+    oracle's on every path and launch shape (held inputs carried between
+    launches on the device)."""
+    if kind == "unit":
+        n, u, v, w = inputs.gnm(333, 1400, 91)
+        j, h = -w, None
+    else:
+        n, u, v, j, h = _random_ising(301, 1300, 92, jmax=4)
+    g = psa.Graph.from_edges(ctx, n, u, v, j, h=h, maxcut=False)
+    S, T = 24, 11
+    i0 = oracle.schedule(S, 0.02, 0.9)
+    sig = (0.1, 0.2, 0.1, 0.8)
+    lam, dl, thr = oracle.variability(n, 13, *sig)
+    job = psa.Job(ctx, g, S, T, seed=13, i0=i0, sigma_lambda=sig[0], sigma_delta=sig[1],
+                  sigma_nu=sig[2], p_mean=sig[3], trials_per_group=tpw, lanes_per_task=lpt,
+                  path=psa.PSA_PATH_DENSE if path == "dense" else psa.PSA_PATH_CSR,
+                  algorithm=psa.PSA_ALG_SPSA, p_stall=0.5)
+    ref = oracle.init_spins(n, 13, 0, T)
+    x = None
+    t = 0
+    for k in (1, 6, 9, 8):
+        job.step(k)
+        ref, x = oracle.run_spsa(n, u, v, j, h, i0, lam, dl, thr, 1 << 23, 13, 0, T, t, t + k,
+                                 ref, x)
+        t += k
+        np.testing.assert_array_equal(job.read_spins(), ref, err_msg=f"after step {t}")
+    E, C = job.energy_cut()
+    rE, rC = oracle.energy_cut(n, u, v, j, h, ref)
+    np.testing.assert_array_equal(E, rE)
+    np.testing.assert_array_equal(C, rC)
+
+
+def test_spsa_edge_cases(psa, ctx):
+    """p_stall 0 is pSA; p_stall 1 freezes every input at step 0 (matches the
+    oracle); a reset re-forms the inputs; resuming an SpSA job mid-run from
+    spins alone is refused."""
+    n, u, v, w = inputs.gnm(200, 700, 93)
+    g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
+    kw = dict(sigma_lambda=0.1, sigma_delta=0.1, sigma_nu=0.1, p_mean=0.8)
+    a = psa.anneal(ctx, g, 30, 7, 4, **kw)
+    b = psa.anneal(ctx, g, 30, 7, 4, algorithm=psa.PSA_ALG_SPSA, p_stall=0.0, **kw)
+    np.testing.assert_array_equal(a[0], b[0])
+    job = psa.Job(ctx, g, 30, 7, 4, algorithm=psa.PSA_ALG_SPSA, p_stall=1.0, **kw)
+    job.step(30)
+    i0, _, _ = oracle.schedule_paper(n, u, v, -w, 30)
+    lam, dl, thr = oracle.variability(n, 4, 0.1, 0.1, 0.1, 0.8)
+    ref = oracle.anneal_spsa(n, u, v, -w, None, i0, lam, dl, thr, 1 << 24, 4, 0, 7)
+    np.testing.assert_array_equal(job.read_spins(), ref[0])
+    job.reset()
+    job.step(30)
+    np.testing.assert_array_equal(job.read_spins(), ref[0])
+    with pytest.raises(psa.PsaError) as e:
+        job.write_spins(job.read_spins(), 5)
+    assert e.value.status == psa.PSA_EUNSUPPORTED
+    with pytest.raises(psa.PsaError):
+        psa.Job(ctx, g, 30, 7, 4, algorithm=psa.PSA_ALG_SPSA, p_stall=1.5)
