@@ -77,6 +77,9 @@ def _load():
     lib.psa_ref_run_spsa.argtypes = [i32, i64, P, P, P, P, P, P, P, P, u32, u64, i32,
                                      i32, i32, i32, P, P]
     lib.psa_ref_run_spsa.restype = ctypes.c_int
+    lib.psa_ref_run_tapsa.argtypes = [i32, i64, P, P, P, P, P, P, P, P, i32, u64, i32,
+                                      i32, i32, i32, P, P]
+    lib.psa_ref_run_tapsa.restype = ctypes.c_int
     lib.psa_ref_energy_cut.argtypes = [i32, i64, P, P, P, P, i32, P, P, P]
     lib.psa_ref_energy_cut.restype = ctypes.c_int
     lib.psa_ref_anneal.argtypes = [i32, i64, P, P, P, P, i32, P, P, P, P, u64,
@@ -258,6 +261,44 @@ def run_spsa(n, eu, ev, ej, h, i0, lam, off, thr, stall24, seed, trial_begin, tr
                                     _ptr(x)),
            "psa_ref_run_spsa")
     return s, x
+
+
+def run_tapsa(n, eu, ev, ej, h, i0, lam, off, thr, alpha, seed, trial_begin, trial_end,
+              t_begin, t_end, spins, ring=None):
+    """TApSA sweeps t_begin..t_end-1 (Eq. 4) on copies of `spins` and of the
+    field windows `ring` ([trials][n][alpha] int32; needed when t_begin > 0).
+    Returns (spins, ring)."""
+    eu, ev, ej = _edges(eu, ev, ej)
+    h = _opt_h(h, n)
+    i0 = np.ascontiguousarray(i0, dtype=np.float32)
+    lam = np.ascontiguousarray(lam, dtype=np.float32)
+    off = np.ascontiguousarray(off, dtype=np.float32)
+    thr = np.ascontiguousarray(thr, dtype=np.uint32)
+    if i0.size < t_end or lam.size != n or off.size != n or thr.size != n:
+        raise ValueError("schedule or per-p-bit arrays have the wrong size")
+    rows = trial_end - trial_begin
+    s = np.ascontiguousarray(np.array(spins, dtype=np.int8, copy=True).reshape(rows, n))
+    if ring is None:
+        if t_begin > 0:
+            raise ValueError("ring is needed to resume at t_begin > 0")
+        rg = np.zeros((rows, n, alpha), np.int32)
+    else:
+        rg = np.ascontiguousarray(np.array(ring, dtype=np.int32, copy=True).reshape(rows, n, alpha))
+    _check(_load().psa_ref_run_tapsa(n, eu.size, _ptr(eu), _ptr(ev), _ptr(ej), _ptr(h),
+                                     _ptr(i0), _ptr(lam), _ptr(off), _ptr(thr), int(alpha),
+                                     seed, trial_begin, trial_end, t_begin, t_end, _ptr(s),
+                                     _ptr(rg)),
+           "psa_ref_run_tapsa")
+    return s, rg
+
+
+def anneal_tapsa(n, eu, ev, ej, h, i0, lam, off, thr, alpha, seed, trial_begin, trial_end):
+    """TApSA anneal: initial spins, len(i0) sweeps, energy and cut per trial."""
+    s0 = init_spins(n, seed, trial_begin, trial_end)
+    s, _ = run_tapsa(n, eu, ev, ej, h, i0, lam, off, thr, alpha, seed, trial_begin,
+                     trial_end, 0, len(i0), s0)
+    E, C = energy_cut(n, eu, ev, ej, h, s)
+    return s, E, C
 
 
 def anneal_spsa(n, eu, ev, ej, h, i0, lam, off, thr, stall24, seed, trial_begin, trial_end):

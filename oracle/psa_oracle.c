@@ -512,6 +512,70 @@ int psa_ref_run_spsa(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
     return 0;
 }
 
+/* TApSA (Eq. 4).  Per step and trial: every p-bit forms its temporary field
+ * TI_i(t) (Eq. 4a, the integer field of the spins of step t) and records it
+ * in its window; its input is I0 times the mean of the window (Eq. 4b, the
+ * fields of steps t, t-1, .., t-alpha+1, fewer at the start), with the
+ * variability pre-activation of Eq. 6; the output follows Eq. 1 / Eq. 6. */
+int psa_ref_run_tapsa(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+                      const int32_t *ej, const int32_t *h, const float *i0,
+                      const float *lambda, const float *offset,
+                      const uint32_t *thr24, int32_t alpha, uint64_t seed,
+                      int32_t trial_begin, int32_t trial_end, int32_t t_begin,
+                      int32_t t_end, int8_t *spins, int32_t *ring)
+{
+    if (!i0 || !lambda || !offset || !thr24 || !spins || !ring || alpha < 1 ||
+        trial_begin < 0 || trial_end < trial_begin || t_begin < 0 || t_end < t_begin)
+        return -1;
+    ref_adj a;
+    int rc = adj_build(n, m, eu, ev, ej, h, &a);
+    if (rc != 0)
+        return rc;
+    int32_t *L = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int8_t *next = (int8_t *)malloc((size_t)n);
+    if (!L || !next) {
+        free(L);
+        free(next);
+        adj_free(&a);
+        return -2;
+    }
+    for (int32_t k = trial_begin; k < trial_end; k++) {
+        int8_t *mk = spins + (int64_t)(k - trial_begin) * n;
+        int32_t *rk = ring + (int64_t)(k - trial_begin) * n * alpha;
+        for (int32_t t = t_begin; t < t_end; t++) {
+            for (int32_t i = 0; i < n; i++)
+                L[i] = field_of(&a, h, i, mk);          /* Eq. 4a */
+            int32_t count = t + 1 < alpha ? t + 1 : alpha;
+            for (int32_t i = 0; i < n; i++) {
+                int32_t *w = rk + (int64_t)i * alpha;
+                w[t % alpha] = L[i];
+                int64_t sum = 0;
+                for (int32_t q = 0; q < count; q++)
+                    sum += w[(t - q) % alpha];
+                float mean = (float)sum / (float)count;  /* Eq. 4b */
+                uint32_t ug = psa_ref_word(seed, (uint32_t)t, (uint32_t)i,
+                                           (uint32_t)k, TAG_GATE);
+                if (!psa_ref_gate(ug, thr24[i])) {
+                    next[i] = mk[i];
+                    continue;
+                }
+                uint32_t ur = psa_ref_word(seed, (uint32_t)t, (uint32_t)i,
+                                           (uint32_t)k, TAG_R);
+                float r = psa_ref_r_from_word(ur);
+                float a_i = i0[t] * lambda[i];
+                float b_i = mean + offset[i];
+                float x = a_i * b_i;
+                next[i] = (psa_ref_tanh(x) > r) ? (int8_t)1 : (int8_t)-1;
+            }
+            memcpy(mk, next, (size_t)n);
+        }
+    }
+    free(L);
+    free(next);
+    adj_free(&a);
+    return 0;
+}
+
 /* Eq. 2: H = -sum_i h_i m_i - sum_{i<j} J_ij m_i m_j.  Cut of the
  * bipartition {m = +1} / {m = -1} with edge weights w = -J (the MAX-CUT
  * objective): sum over edges of w_ij [m_i != m_j]. */

@@ -103,6 +103,20 @@ int psa_ref_run_spsa(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
                      int32_t trial_begin, int32_t trial_end, int32_t t_begin,
                      int32_t t_end, int8_t *spins, float *x_state);
 
+/* Time-averaged variant (TApSA, Eq. 4): the input of a p-bit is I0 times
+ * the mean of its last alpha fields TI(t) = h + sum_j J m_j(t) (the
+ * available ones while t < alpha - 1), here with the device-variability
+ * pre-activation x = (I0 lambda_i)(mean + delta_i), the mean computed as
+ * (float)sum / (float)count, each rounded once.  ring ([trials][n][alpha]
+ * int32, same rows as spins) holds the window: field of step t in slot
+ * t mod alpha; read when t_begin > 0, written on return. */
+int psa_ref_run_tapsa(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+                      const int32_t *ej, const int32_t *h, const float *i0,
+                      const float *lambda, const float *offset,
+                      const uint32_t *thr24, int32_t alpha, uint64_t seed,
+                      int32_t trial_begin, int32_t trial_end, int32_t t_begin,
+                      int32_t t_end, int8_t *spins, int32_t *ring);
+
 /* Ising energy (Eq. 2) and cut weight with w = -J of each trial row. */
 int psa_ref_energy_cut(int32_t n, int64_t m, const int32_t *eu,
                        const int32_t *ev, const int32_t *ej, const int32_t *h,

@@ -448,6 +448,79 @@ def test_spsa_resume_composes():
     np.testing.assert_array_equal(xf, x2)
 
 
+def test_tapsa_window_one_is_psa():
+    """Eq. 4 with a window of one step is Eq. 3."""
+    n, u, v, j, h = _random_ising(60, 200, 85)
+    i0 = oracle.schedule(25, 0.02, 1.5)
+    lam, off, thr = oracle.variability(n, 9, 0.2, 0.3, 0.2, 0.7)
+    a = oracle.anneal(n, u, v, j, h, i0, lam, off, thr, 9, 0, 6)
+    b = oracle.anneal_tapsa(n, u, v, j, h, i0, lam, off, thr, 1, 9, 0, 6)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_tapsa_constant_field_is_psa():
+    """Without couplings the field never changes, so its mean over any window
+    is the field itself: TApSA gives the pSA trajectories for any window and
+    schedule.  With couplings they differ."""
+    n, S, T = 30, 20, 5
+    rng = np.random.default_rng(86)
+    h = rng.integers(-3, 4, size=n).astype(np.int32)
+    i0 = oracle.schedule(S, 0.02, 2.0)
+    lam, off, thr = oracle.variability(n, 10, 0.2, 0.3, 0.2, 0.7)
+    e = np.zeros(0, np.int32)
+    a = oracle.anneal(n, e, e, e, h, i0, lam, off, thr, 10, 0, T)
+    b = oracle.anneal_tapsa(n, e, e, e, h, i0, lam, off, thr, 4, 10, 0, T)
+    np.testing.assert_array_equal(a[0], b[0])
+    n2, u, v, j, h2 = _random_ising(n, 90, 87)
+    a = oracle.anneal(n2, u, v, j, h2, i0, lam, off, thr, 10, 0, T)
+    b = oracle.anneal_tapsa(n2, u, v, j, h2, i0, lam, off, thr, 4, 10, 0, T)
+    assert not np.array_equal(a[0], b[0])
+
+
+@pytest.mark.parametrize("alpha", [2, 3, 4])
+def test_tapsa_deterministic_limit_matches_window_recurrence(alpha):
+    """With an I0 so large that tanh saturates, each update is the sign of
+    (window mean of the fields + delta): a deterministic recurrence written
+    here with numpy over a small coupled graph, start-up windows included.
+    Offsets in {+-0.3, +-0.1, -0.45, +-0.7, 0.55} are no multiple of 1/12,
+    so no mean + delta is 0, and they span the scales at which a wrong
+    window length or start-up divisor flips signs (unit couplings keep the
+    fields small)."""
+    n, u, v, j, h = _random_ising(16, 30, 88, jmax=1)
+    S, T = 12, 32
+    i0 = np.full(S, 1e30, np.float32)
+    lam = np.ones(n, np.float32)
+    off = np.resize(np.array([0.3, -0.3, 0.1, -0.1, -0.45, 0.7, -0.7, 0.55], np.float32), n)
+    thr = np.full(n, ONE24, np.uint32)
+    Jd = _dense(n, u, v, j)
+    s0 = oracle.init_spins(n, 12, 0, T)
+    got, ring = s0, None
+    m = s0.astype(np.int64)
+    hist = []
+    for t in range(S):
+        got, ring = oracle.run_tapsa(n, u, v, j, h, i0, lam, off, thr, alpha, 12, 0, T, t,
+                                     t + 1, got, ring)
+        hist.append(m @ Jd + h)                  # [trials][n] fields of step t
+        win = hist[-alpha:]
+        mean = np.sum(win, axis=0) / len(win)
+        m = np.where(mean + off > 0, 1, -1)
+        np.testing.assert_array_equal(got, m, err_msg=f"step {t}")
+
+
+def test_tapsa_resume_composes():
+    n, u, v, j, h = _random_ising(40, 120, 89)
+    S, T, k = 18, 5, 7
+    i0 = oracle.schedule(S, 0.02, 1.5)
+    lam, off, thr = oracle.variability(n, 11, 0.1, 0.1, 0.1, 0.8)
+    s0 = oracle.init_spins(n, 11, 0, T)
+    full, rf = oracle.run_tapsa(n, u, v, j, h, i0, lam, off, thr, 4, 11, 0, T, 0, S, s0)
+    s1, r1 = oracle.run_tapsa(n, u, v, j, h, i0, lam, off, thr, 4, 11, 0, T, 0, k, s0)
+    s2, r2 = oracle.run_tapsa(n, u, v, j, h, i0, lam, off, thr, 4, 11, 0, T, k, S, s1, r1)
+    np.testing.assert_array_equal(full, s2)
+    np.testing.assert_array_equal(rf, r2)
+
+
 def _two_spin_transition(i0, J, h, lam, off):
     states = [(1, 1), (1, -1), (-1, 1), (-1, -1)]
     P = np.zeros((4, 4))
