@@ -14,10 +14,15 @@
 //             whose couplings share one magnitude (unit and +-1 weights).
 //             Four times fewer bytes than int8; unpacked to int8 in
 //             registers with v_perm_b32 just before the matrix instruction.
-//   T2 layout: one uint32 per (row i, k-tile c of 64 columns, lane group g of
-//   16 columns), at index (i * np/64 + c) * 4 + g.  Column 64c + 16g + 4d + b
-//   sits in bits 8b + 2d .. 8b + 2d + 1 (d = dword of the operand, b = byte),
-//   so that (word >> 2d) & 0x03030303 is a byte selector for dword d.
+//   T2 words: one uint32 per (row i, 64-column k-tile, 16-column lane group
+//   g); column 64 ktile + 16 g + 4d + b sits in bits 8b + 2d .. 8b + 2d + 1
+//   (d = dword of the operand, b = byte), so that (word >> 2d) & 0x03030303
+//   is a byte selector for dword d.  The words are tiled in the order a
+//   wave loads them: per 64-row tile and 128-column chunk, 2 KB as two
+//   1 KB halves of [64 lanes][4 words]; word j of lane l in half h is row
+//   16 (2h + j/2) + l % 16 of the tile, k-tile j % 2 of the chunk, group
+//   l / 16.  A lane's fragments for a chunk are two 16-byte loads, and each
+//   load instruction of the wave reads 1 KB contiguous.
 //
 // Spins M: int8 [tp][np] per buffer (trial-major, p-bit index contiguous), tp
 // = trials rounded up to the trial tile; two buffers by step parity.
@@ -75,12 +80,12 @@ struct AFrag<kDenseI8> {
 };
 template <>
 struct AFrag<kDenseT2> {
-    uint32_t v[2][4];
+    v4i h[2];  // half h, word j: row block 2h + j/2, k-tile j % 2
 };
 
 // NB = 16-trial blocks per workgroup (trial tile = 16 NB).
 template <int NB, int ENC>
-__global__ __launch_bounds__(256) void dense_step_kernel(const DenseJob *__restrict__ jobs,
+__global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kernel(const DenseJob *__restrict__ jobs,
                                                          const int4 *__restrict__ work, int32_t t_off) {
     constexpr int kTrials = 16 * NB;
     constexpr int kBVec = kTrials * (kKC / 16);        // 16-byte pieces of one spin chunk
@@ -105,7 +110,6 @@ __global__ __launch_bounds__(256) void dense_step_kernel(const DenseJob *__restr
     // main loop) and skips the epilogue.
     const bool active = wrow0 < np;
     const int32_t arow0 = active ? wrow0 : np - kWaveRows;
-    const int32_t ktiles = np / 64;
 
     static_assert(kBVec == 128 || kBVec % 256 == 0, "spin chunk split");
     // spin chunk kc+1 staged in registers while chunk kc is multiplied; with
@@ -129,19 +133,21 @@ __global__ __launch_bounds__(256) void dense_step_kernel(const DenseJob *__restr
         }
     };
     auto fetch_a = [&](int kc, AFrag<ENC> &dst) {
+        if constexpr (ENC == kDenseI8) {
+            const gptr<int8_t> J = as_global<int8_t>(jb.J);
 #pragma unroll
-        for (int kt = 0; kt < 2; ++kt)
+            for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) {
-                const size_t row = static_cast<size_t>(arow0 + rb * 16 + lr);
-                if constexpr (ENC == kDenseI8) {
-                    const gptr<int8_t> J = as_global<int8_t>(jb.J);
+                for (int rb = 0; rb < 4; ++rb) {
+                    const size_t row = static_cast<size_t>(arow0 + rb * 16 + lr);
                     dst.v[kt][rb] = *as_global<v4i>(J + row * np + kc * kKC + kt * 64 + kgrp);
-                } else {
-                    const gptr<uint32_t> J = as_global<uint32_t>(jb.J);
-                    dst.v[kt][rb] = J[(row * ktiles + kc * 2 + kt) * 4 + (lane >> 4)];
                 }
-            }
+        } else {
+            const gptr<v4i> J = as_global<v4i>(jb.J);
+            const size_t tile = (static_cast<size_t>(arow0 / kWaveRows) * (np / kKC) + kc) * 2;
+            dst.h[0] = J[tile * 64 + lane];
+            dst.h[1] = J[(tile + 1) * 64 + lane];
+        }
     };
 
     v4i acc[4][NB];
@@ -163,7 +169,7 @@ __global__ __launch_bounds__(256) void dense_step_kernel(const DenseJob *__restr
                 if constexpr (ENC == kDenseI8)
                     a = af.v[kt][rb];
                 else
-                    a = t2_unpack(af.v[kt][rb]);
+                    a = t2_unpack(static_cast<uint32_t>(af.h[rb >> 1][(rb & 1) * 2 + kt]));
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
                     acc[rb][nb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b[nb], acc[rb][nb], 0, 0, 0);
@@ -199,76 +205,82 @@ __global__ __launch_bounds__(256) void dense_step_kernel(const DenseJob *__restr
     if (!active) return;
 
     // epilogue: lane owns p-bits 4m..4m+3 of each row block for trial columns
-    // nb.  Row blocks run as a loop with a uniform index; each pass picks its
-    // accumulators with constant indices, so the accumulator array stays in
-    // registers while the body (Philox blocks and activations, unrolled over
-    // the trial blocks) is emitted NB times rather than 4 NB times.
+    // nb.  The (row block, trial block) pairs run as a loop with a uniform
+    // index, so the body -- Philox blocks and four activations -- is emitted
+    // once per pass, keeping few registers live.
     const float i0t = jb.i0[t];
     const int32_t scale = jb.scale;
     const Stall st{jb.xs, jb.stall24, jb.n4};
-#pragma unroll 1
-    for (int rb = 0; rb < 4; ++rb) {
-        v4i arow[NB];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            arow[nb] = acc[0][nb];
-#pragma unroll
-            for (int q = 1; q < 4; ++q)
-                if (rb == q) arow[nb] = acc[q][nb];
-        }
+    auto update = [&](int e, const v4i a4) __attribute__((always_inline)) {
+        const int rb = e / NB, nb = e % NB;
         const int32_t i0 = wrow0 + rb * 16 + (lane >> 4) * 4;
-        if (i0 >= jb.n4) continue;
+        const int32_t k = trial0 + nb * 16 + lr;
+        // lanes past the padded p-bits or trials compute on clamped inputs
+        // and store nothing (straight-line code, so that two passes interleave)
+        const bool valid = i0 < jb.n4 && k < jb.t4;
+        const int32_t ic = valid ? i0 : 0;
         const int32_t m = i0 >> 2;
-        const int4 hh = *reinterpret_cast<const int4 *>(jb.h + i0);
-        const uint4 th = *reinterpret_cast<const uint4 *>(jb.thr + i0);
-        const float4 lm = *reinterpret_cast<const float4 *>(jb.lam + i0);
-        const float4 dl = *reinterpret_cast<const float4 *>(jb.dlt + i0);
+        const int4 hh = *reinterpret_cast<const int4 *>(jb.h + ic);
+        const uint4 th = *reinterpret_cast<const uint4 *>(jb.thr + ic);
+        const float4 lm = *reinterpret_cast<const float4 *>(jb.lam + ic);
+        const float4 dl = *reinterpret_cast<const float4 *>(jb.dlt + ic);
+        const Stall sv{valid ? st.xs : nullptr, st.s24, st.n4};
         const int32_t hv[4] = {hh.x, hh.y, hh.z, hh.w};
         const uint32_t tv[4] = {th.x, th.y, th.z, th.w};
         const float av[4] = {i0t * lm.x, i0t * lm.y, i0t * lm.z, i0t * lm.w};
         const float dv[4] = {dl.x, dl.y, dl.z, dl.w};
         const bool need_gate = (tv[0] < kGateOne) | (tv[1] < kGateOne) | (tv[2] < kGateOne) |
                                (tv[3] < kGateOne);
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const int32_t k = trial0 + nb * 16 + lr;
-            if (k >= jb.t4) continue;
-            uint32_t old = 0u;
-            uint32_t gw[4] = {0u, 0u, 0u, 0u};
-            if (need_gate) {
-                old = *reinterpret_cast<const uint32_t *>(cur + static_cast<size_t>(k) * np + i0);
-                const Words4 g = philox4x32_10(static_cast<uint32_t>(t), static_cast<uint32_t>(m),
-                                               static_cast<uint32_t>(k), kTagGate, jb.k0, jb.k1);
-                gw[0] = g.x;
-                gw[1] = g.y;
-                gw[2] = g.z;
-                gw[3] = g.w;
-            }
-            const Words4 r = philox4x32_10(static_cast<uint32_t>(t), static_cast<uint32_t>(m),
-                                           static_cast<uint32_t>(k), kTagR, jb.k0, jb.k1);
-            const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
-            uint32_t sw[4] = {0u, 0u, 0u, 0u};
-            if (st.xs != nullptr && t > 0) {
-                const Words4 b = philox4x32_10(static_cast<uint32_t>(t), static_cast<uint32_t>(m),
-                                               static_cast<uint32_t>(k), kTagStall, jb.k0, jb.k1);
-                sw[0] = b.x;
-                sw[1] = b.y;
-                sw[2] = b.z;
-                sw[3] = b.w;
-            }
-            uint32_t out = 0u;
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                const int32_t L = hv[p] + scale * arow[nb][p];
-                const float x = input_of(av[p], dv[p], L, st, i0 + p, static_cast<uint32_t>(k),
-                                         static_cast<uint32_t>(t), sw[p]);
-                const bool up = tanh_f32(x) > r_of(rw[p]);
-                const bool fire = tv[p] >= kGateOne || fires(gw[p], tv[p]);
-                const uint32_t ob = (old >> (8 * p)) & 0xFFu;
-                out |= (fire ? (up ? 0x01u : 0xFFu) : ob) << (8 * p);
-            }
-            *reinterpret_cast<uint32_t *>(nxt + static_cast<size_t>(k) * np + i0) = out;
+        uint32_t old = 0u;
+        uint32_t gw[4] = {0u, 0u, 0u, 0u};
+        if (need_gate) {
+            old = *reinterpret_cast<const uint32_t *>(cur + static_cast<size_t>(k) * np + i0);
+            const Words4 g = philox4x32_10(static_cast<uint32_t>(t), static_cast<uint32_t>(m),
+                                           static_cast<uint32_t>(k), kTagGate, jb.k0, jb.k1);
+            gw[0] = g.x;
+            gw[1] = g.y;
+            gw[2] = g.z;
+            gw[3] = g.w;
         }
+        const Words4 r = philox4x32_10(static_cast<uint32_t>(t), static_cast<uint32_t>(m),
+                                       static_cast<uint32_t>(k), kTagR, jb.k0, jb.k1);
+        const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+        uint32_t sw[4] = {0u, 0u, 0u, 0u};
+        if (sv.xs != nullptr && t > 0) {
+            const Words4 b = philox4x32_10(static_cast<uint32_t>(t), static_cast<uint32_t>(m),
+                                           static_cast<uint32_t>(k), kTagStall, jb.k0, jb.k1);
+            sw[0] = b.x;
+            sw[1] = b.y;
+            sw[2] = b.z;
+            sw[3] = b.w;
+        }
+        uint32_t out = 0u;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int32_t L = hv[p] + scale * a4[p];
+            const float x = input_of(av[p], dv[p], L, sv, i0 + p, static_cast<uint32_t>(k),
+                                     static_cast<uint32_t>(t), sw[p]);
+            const bool up = tanh_f32(x) > r_of(rw[p]);
+            const bool fire = tv[p] >= kGateOne || fires(gw[p], tv[p]);
+            const uint32_t ob = (old >> (8 * p)) & 0xFFu;
+            out |= (fire ? (up ? 0x01u : 0xFFu) : ob) << (8 * p);
+        }
+        if (valid) *reinterpret_cast<uint32_t *>(nxt + static_cast<size_t>(k) * np + i0) = out;
+    };
+    // The accumulators move through a queue read only at its head (constant
+    // register indices; a loop index into the array would force it into
+    // scratch memory).  Two (row block, trial block) pairs per pass: their
+    // Philox chains are independent, which doubles the instruction-level
+    // parallelism.
+    v4i q[4 * NB];
+#pragma unroll
+    for (int e = 0; e < 4 * NB; ++e) q[e] = acc[e / NB][e % NB];
+#pragma unroll 1
+    for (int e = 0; e < 4 * NB; e += 2) {
+        update(e, q[0]);
+        update(e + 1, q[1]);
+#pragma unroll
+        for (int j = 0; j + 2 < 4 * NB; ++j) q[j] = q[j + 2];
     }
 }
 

@@ -191,14 +191,24 @@ psa_status ensure_dense_matrix(psa_graph *g) {
     }
     psa_status st;
     if (one_mag) {
-        const int32_t ktiles = np / 64;
-        std::vector<uint32_t> words(static_cast<size_t>(np) * ktiles * 4, 0u);
+        // 2-bit fields, tiled for the step kernel: for each 64-row tile and
+        // 128-column chunk, 2 KB in the order the 64 lanes of a wave load
+        // them (two 16-byte loads per lane, each load 1 KB contiguous).
+        // Lane l, load `half`, word j holds row 64 rt + 16 (2 half + j/2) +
+        // l % 16, k-tile 2 c + j % 2, lane group l / 16; within the word,
+        // column 64 ktile + 16 g + 4 d + b sits in bits 8b + 2d.
+        const int32_t nchunks = np / 128;
+        std::vector<uint32_t> words(static_cast<size_t>(np) * np / 16, 0u);
         for (int32_t i = 0; i < n; ++i)
             for (int32_t p = g->row_ptr_host[i]; p < g->row_ptr_host[i + 1]; ++p) {
                 const int32_t k = g->col_host[p];
-                const int32_t c = k >> 6, grp = (k >> 4) & 3, e = k & 15, d = e >> 2, b = e & 3;
+                const int32_t rt = i >> 6, rb = (i >> 4) & 3, lr = i & 15;
+                const int32_t c = k >> 7, kt = (k >> 6) & 1, grp = (k >> 4) & 3;
+                const int32_t e = k & 15, d = e >> 2, b = e & 3;
+                const int32_t half = rb >> 1, j = (rb & 1) * 2 + kt, lane = grp * 16 + lr;
+                const size_t at = ((((static_cast<size_t>(rt) * nchunks + c) * 2 + half) * 64 + lane) * 4) + j;
                 const uint32_t f = g->val_host[p] > 0 ? 1u : 2u;
-                words[(static_cast<size_t>(i) * ktiles + c) * 4 + grp] |= f << (8 * b + 2 * d);
+                words[at] |= f << (8 * b + 2 * d);
             }
         uint32_t *dev = nullptr;
         if ((st = upload(&dev, words)) != PSA_OK) return st;
