@@ -22,6 +22,8 @@
 // no edges and never fire), row_ptr to n4 + 4 entries.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_math.hpp"
 #include "engine.hpp"
 
@@ -83,10 +85,31 @@ __device__ __forceinline__ int32_t field_pm1(const Views &v, int32_t i, const in
 
 // One trial, unit weights, mirrored 0/1 bytes: the rows of p-bits
 // base, base+1 (P = 2) or base (P = 1) walked as one contiguous edge range.
-template <int P>
+template <int P, bool BLK>
 __device__ __forceinline__ void field_unit(const Views &v, int32_t base, const uint8_t *cur,
                                            int32_t L[P]) {
     const int32_t e0 = v.row_ptr[base];
+    if constexpr (BLK) {
+        // rows in global memory: aligned blocks of 8 entries (one 16-byte
+        // load), entries outside the rows masked out
+        const int32_t split = v.row_ptr[base + 1];
+        const int32_t e2 = P == 2 ? v.row_ptr[base + 2] : split;
+        int32_t acc0 = 0, acc1 = 0;
+        for (int32_t eb = e0 & ~7; eb < e2; eb += 8) {
+            const u32x4 qv = load_global_x4(v.ux16 + eb);
+            const uint32_t wv[4] = {qv.x, qv.y, qv.z, qv.w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int32_t e = eb + j;
+                const int32_t x = cur[(wv[j >> 1] >> (16 * (j & 1))) & 0xFFFFu];
+                acc0 += (e >= e0 && e < split) ? x : 0;
+                if constexpr (P == 2) acc1 += (e >= split && e < e2) ? x : 0;
+            }
+        }
+        L[0] = v.h[base] + 2 * acc0 - (split - e0);
+        if constexpr (P == 2) L[1] = v.h[base + 1] + 2 * acc1 - (e2 - split);
+        return;
+    }
     if constexpr (P == 1) {
         const int32_t e1 = v.row_ptr[base + 1];
         int32_t acc = 0;
@@ -108,14 +131,31 @@ __device__ __forceinline__ void field_unit(const Views &v, int32_t base, const u
 }
 
 // Four trials, unit weights, 0/1 bytes packed per word (SWAR); degree <= 255.
+template <bool BLK>
 __device__ __forceinline__ void field_swar(const Views &v, int32_t i, const uint32_t *cur,
                                            int32_t L[4]) {
     const int32_t e0 = v.row_ptr[i], e1 = v.row_ptr[i + 1];
     uint32_t acc = 0u;
+    if constexpr (BLK) {
+        // row in global memory: aligned blocks of 8 entries (one 16-byte
+        // load), entries outside the row masked out
+        for (int32_t eb = e0 & ~7; eb < e1; eb += 8) {
+            const u32x4 qv = load_global_x4(v.pk16 + eb);
+            const uint32_t wv[4] = {qv.x, qv.y, qv.z, qv.w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int32_t e = eb + j;
+                const uint32_t w = (wv[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+                const uint32_t x = cur[w >> 1] ^ ((w & 1u) * 0x01010101u);
+                acc += (e >= e0 && e < e1) ? x : 0u;
+            }
+        }
+    } else {
 #pragma unroll 2
-    for (int32_t e = e0; e < e1; ++e) {
-        const uint32_t w = v.pk16[e];
-        acc += cur[w >> 1] ^ ((w & 1u) * 0x01010101u);
+        for (int32_t e = e0; e < e1; ++e) {
+            const uint32_t w = v.pk16[e];
+            acc += cur[w >> 1] ^ ((w & 1u) * 0x01010101u);
+        }
     }
     const int32_t base = v.h[i] - (e1 - e0);
     L[0] = base + 2 * static_cast<int32_t>(acc & 0xFFu);
@@ -215,7 +255,7 @@ __device__ __forceinline__ bool any_gate(const uint32_t *thr, int32_t m) {
 // One trial per workgroup: lane `sub` of task m updates its P p-bits and
 // returns their new bytes (in the LDS encoding) in the low 8P bits.
 // ---------------------------------------------------------------------------
-template <int CSR, int LPT>
+template <int CSR, int LPT, bool SPSA, bool BLK>
 __device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, uint32_t sub,
                                                    uint32_t k, uint32_t t, float i0t,
                                                    const unsigned char *cur, uint32_t k0,
@@ -227,7 +267,7 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, ui
     task_words<LPT>(t, static_cast<uint32_t>(m), k, sub, need_gate, k0, k1, rw, gw);
 #pragma unroll
     for (int j = 0; j < P; ++j) sw[j] = 0u;
-    if (st.xs != nullptr && t > 0) {
+    if (SPSA && t > 0) {
         const Words4 b = block_of(t, static_cast<uint32_t>(m), k, kTagStall, k0, k1);
 #pragma unroll
         for (int j = 0; j < P; ++j) sw[j] = word_of(b, sub * P + j);
@@ -236,10 +276,10 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, ui
     int32_t L[P];
     if constexpr (CSR == kCsrUnit) {
         if constexpr (P == 4) {
-            field_unit<2>(v, base, cur, L);
-            field_unit<2>(v, base + 2, cur, L + 2);
+            field_unit<2, BLK>(v, base, cur, L);
+            field_unit<2, BLK>(v, base + 2, cur, L + 2);
         } else {
-            field_unit<P>(v, base, cur, L);
+            field_unit<P, BLK>(v, base, cur, L);
         }
     } else {
 #pragma unroll
@@ -253,7 +293,7 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, ui
         const uint32_t old = cur[i];
         const uint32_t th = v.thr[i];
         const bool fire = th >= kGateOne || fires(gw[j], th);
-        const float x = input_of(i0t * v.lam[i], v.dlt[i], L[j], st, i, k, t, sw[j]);
+        const float x = input_of<SPSA>(i0t * v.lam[i], v.dlt[i], L[j], st, i, k, t, sw[j]);
         const bool up = goes_up(x, rw[j]);
         const uint32_t nb = kU ? (up ? 1u : 0u) : (up ? 0x01u : 0xFFu);
         out |= (fire ? nb : old) << (8 * j);
@@ -265,7 +305,7 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, ui
 // Four trials per workgroup: one lane per task updates 4 p-bits x 4 trials and
 // writes the four packed words of the next step.
 // ---------------------------------------------------------------------------
-template <int CSR>
+template <int CSR, bool SPSA, bool BLK>
 __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int32_t q, uint32_t t,
                                                  float i0t, const uint32_t *cur, uint32_t *nxt,
                                                  uint32_t k0, uint32_t k1, const Stall &st) {
@@ -281,7 +321,7 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
         a[p] = i0t * v.lam[i];
         d[p] = v.dlt[i];
         if constexpr (CSR == kCsrPack16)
-            field_swar(v, i, cur, L[p]);
+            field_swar<BLK>(v, i, cur, L[p]);
         else
             field_words<CSR>(v, i, cur, L[p]);
     }
@@ -301,7 +341,7 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
         const Words4 r = block_of(t, static_cast<uint32_t>(m), k, kTagR, k0, k1);
         const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
         uint32_t sw[4] = {0u, 0u, 0u, 0u};
-        if (st.xs != nullptr && t > 0) {
+        if (SPSA && t > 0) {
             const Words4 b = block_of(t, static_cast<uint32_t>(m), k, kTagStall, k0, k1);
             sw[0] = b.x;
             sw[1] = b.y;
@@ -311,7 +351,7 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             const bool fire = th[p] >= kGateOne || fires(gw[p], th[p]);
-            const float x = input_of(a[p], d[p], L[p][kk], st, 4 * m + p, k, t, sw[p]);
+            const float x = input_of<SPSA>(a[p], d[p], L[p][kk], st, 4 * m + p, k, t, sw[p]);
             const bool up = goes_up(x, rw[p]);
             const uint32_t nb = kU ? (up ? 1u : 0u) : (up ? 0x01u : 0xFFu);
             if (fire) word[p] = (word[p] & ~(0xFFu << (8 * kk))) | (nb << (8 * kk));
@@ -434,6 +474,10 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
     unsigned char *cur = buf0;
     unsigned char *nxt = buf1;
     const Stall st{a.xs, a.stall24, n4};
+    // the step loop, instantiated with and without the SpSA input stage so
+    // that plain pSA carries no per-update test for it
+    auto sweep = [&](auto spsa_tag) {
+    constexpr bool SPSA = decltype(spsa_tag)::value;
     for (int32_t t = a.t_begin; t < a.t_end; ++t) {
         const float i0t = a.i0[t];
         if constexpr (TPW == 1) {
@@ -441,7 +485,7 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
             const uint32_t sub = threadIdx.x % LPT;
             for (int32_t slot = threadIdx.x / LPT; slot < tasks; slot += BLOCK / LPT) {
                 const int32_t m = v.order[slot];
-                const uint32_t b = task_one_trial<CSR, LPT>(v, m, sub, static_cast<uint32_t>(q),
+                const uint32_t b = task_one_trial<CSR, LPT, SPSA, !CSR_LDS>(v, m, sub, static_cast<uint32_t>(q),
                                                             static_cast<uint32_t>(t), i0t, cur,
                                                             a.k0, a.k1, st);
                 constexpr int P = 4 / LPT;
@@ -462,7 +506,7 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
             }
         } else {
             for (int32_t slot = threadIdx.x; slot < tasks; slot += BLOCK)
-                task_four_trials<CSR>(v, v.order[slot], q, static_cast<uint32_t>(t), i0t,
+                task_four_trials<CSR, SPSA, !CSR_LDS>(v, v.order[slot], q, static_cast<uint32_t>(t), i0t,
                                       reinterpret_cast<const uint32_t *>(cur),
                                       reinterpret_cast<uint32_t *>(nxt), a.k0, a.k1, st);
         }
@@ -471,6 +515,11 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
         cur = nxt;
         nxt = tmp;
     }
+    };
+    if (a.xs != nullptr)
+        sweep(std::true_type{});
+    else
+        sweep(std::false_type{});
 
     if constexpr (TPW == 1) {
         for (int32_t i = threadIdx.x; i < n; i += BLOCK) {

@@ -258,8 +258,8 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             const int32_t L = hv[p] + scale * a4[p];
-            const float x = input_of(av[p], dv[p], L, sv, i0 + p, static_cast<uint32_t>(k),
-                                     static_cast<uint32_t>(t), sw[p]);
+            const float x = input_of<true>(av[p], dv[p], L, sv, i0 + p, static_cast<uint32_t>(k),
+                                           static_cast<uint32_t>(t), sw[p]);
             const bool up = tanh_f32(x) > r_of(rw[p]);
             const bool fire = tv[p] >= kGateOne || fires(gw[p], tv[p]);
             const uint32_t ob = (old >> (8 * p)) & 0xFFu;

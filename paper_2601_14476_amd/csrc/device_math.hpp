@@ -89,6 +89,14 @@ __device__ __forceinline__ float tanh_f32(float x) {
     return copysignf(y, x);
 }
 
+// 16-byte load from device-global memory through an address-space cast, so
+// that it is issued as a global (not flat) load and does not wait on LDS
+// traffic.  p must be 16-byte aligned.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ u32x4 load_global_x4(const void *p) {
+    return *(const u32x4 __attribute__((address_space(1))) *)(p);
+}
+
 // SpSA held-input state of one run: pre-activations [t4/4][n4][4] (trial
 // group, p-bit, trial in group); xs == nullptr for plain pSA.
 struct Stall {
@@ -100,11 +108,13 @@ struct Stall {
 // Input stage of p-bit i, trial k at step t (Eq. 5 on the pre-activation
 // x = a (L + d), a = I0 lambda_i, d = delta_i): with SpSA the input is held
 // from the last refresh iff t > 0 and (stall word >> 8) < stall24, else it is
-// formed anew and stored.  Plain pSA: always fresh.
+// formed anew and stored.  Plain pSA (SPSA false, or no state): always
+// fresh.
+template <bool SPSA>
 __device__ __forceinline__ float input_of(float a, float d, int32_t L, const Stall &st, int32_t i,
                                           uint32_t k, uint32_t t, uint32_t sword) {
     const float x = a * (static_cast<float>(L) + d);
-    if (st.xs == nullptr) return x;
+    if (!SPSA || st.xs == nullptr) return x;
     float *slot = st.xs + ((static_cast<size_t>(k >> 2) * st.n4 + i) * 4 + (k & 3u));
     if (t > 0 && (sword >> 8) < st.s24) return *slot;
     *slot = x;

@@ -118,14 +118,17 @@ psa_status finish_host_graph(int32_t n, const std::vector<int64_t> &row_ptr,
         for (int64_t p = 0; p < nnz; ++p)
             g.pk32[p] = static_cast<uint32_t>(col[p]) | (static_cast<uint32_t>(val[p]) << 16);
     }
+    // 16-bit edge arrays are padded with zeros to a multiple of 8 entries:
+    // kernels that stream rows from global memory load them 8 at a time
+    const size_t nnz8 = static_cast<size_t>((nnz + 7) / 8 * 8);
     if (n <= 32768 && info.unit_weights) {
-        g.pk16.resize(static_cast<size_t>(nnz));
+        g.pk16.assign(nnz8, 0);
         for (int64_t p = 0; p < nnz; ++p)
             g.pk16[p] = static_cast<uint16_t>((static_cast<uint32_t>(col[p]) << 1) |
                                               (val[p] < 0 ? 1u : 0u));
     }
     if (2 * static_cast<int64_t>(g.n4) <= 65536 && info.unit_weights) {
-        g.ux16.resize(static_cast<size_t>(nnz));
+        g.ux16.assign(nnz8, 0);
         for (int64_t p = 0; p < nnz; ++p)
             g.ux16[p] = static_cast<uint16_t>(col[p] + (val[p] < 0 ? g.n4 : 0));
     }
