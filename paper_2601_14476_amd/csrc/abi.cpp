@@ -621,16 +621,19 @@ psa_status psa_job_energy_cut(psa_job *job, int64_t *energy, int64_t *cut, uint3
         return PSA_EINVAL;
     }
     PSA_HIP(hipSetDevice(job->ctx->device), "hipSetDevice");
+    // scratch: [energy, cut staging (host outputs)][per-block partial sums]
+    const size_t bytes = static_cast<size_t>(job->run.trials) * sizeof(int64_t);
+    const size_t part_bytes = psa::energy_partial_bytes(job->g->info.n, job->run.t4);
+    psa_status st = ensure_scratch(job, 2 * bytes + part_bytes);
+    if (st != PSA_OK) return st;
+    int64_t *tmp = static_cast<int64_t *>(job->d_scratch);
+    int64_t *part = tmp + 2 * job->run.trials;
     if (flags & PSA_OUT_DEVICE) {
-        PSA_HIP(psa::launch_energy_cut(job->ctx->stream, job->g->dev, job->run, energy, cut),
+        PSA_HIP(psa::launch_energy_cut(job->ctx->stream, job->g->dev, job->run, part, energy, cut),
                 "energy/cut");
         return PSA_OK;
     }
-    const size_t bytes = static_cast<size_t>(job->run.trials) * sizeof(int64_t);
-    psa_status st = ensure_scratch(job, 2 * bytes);
-    if (st != PSA_OK) return st;
-    int64_t *tmp = static_cast<int64_t *>(job->d_scratch);
-    PSA_HIP(psa::launch_energy_cut(job->ctx->stream, job->g->dev, job->run, tmp,
+    PSA_HIP(psa::launch_energy_cut(job->ctx->stream, job->g->dev, job->run, part, tmp,
                                    tmp + job->run.trials),
             "energy/cut");
     PSA_HIP(hipMemcpyAsync(energy, tmp, bytes, hipMemcpyDeviceToHost, job->ctx->stream), "copy-out");

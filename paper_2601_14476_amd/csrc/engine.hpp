@@ -201,8 +201,10 @@ hipError_t launch_anneal_batch(hipStream_t stream, const BatchJob *jobs, const i
                                int32_t nwork, int32_t block, size_t lds_bytes);
 hipError_t launch_local_field(hipStream_t stream, const DevGraph &g,
                               const DevRun &run, int32_t *out_tn);
-hipError_t launch_energy_cut(hipStream_t stream, const DevGraph &g,
-                             const DevRun &run, int64_t *energy, int64_t *cut);
+// Bytes of the per-block partial sums launch_energy_cut needs.
+size_t energy_partial_bytes(int32_t n, int32_t t4);
+hipError_t launch_energy_cut(hipStream_t stream, const DevGraph &g, const DevRun &run,
+                             int64_t *part, int64_t *energy, int64_t *cut);
 hipError_t launch_spins_to_tn(hipStream_t stream, int32_t n, const DevRun &run,
                               int8_t *out_tn);
 hipError_t launch_spins_from_tn(hipStream_t stream, int32_t n, const DevRun &run,

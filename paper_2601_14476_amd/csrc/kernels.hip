@@ -2,7 +2,7 @@
 //
 //   init_spins_kernel   initial state: m = +1 iff bit 31 of the INIT word
 //   local_field_kernel  L = h + J m (Eq. 3 without I0), for tests
-//   energy_cut_kernel   Eq. 2 energy and MAX-CUT value per trial
+//   energy_partial_kernel, energy_finish_kernel   Eq. 2 energy and MAX-CUT value per trial
 //   spins_{to,from}_tn  layout conversion [n][t4] <-> [trials][n]
 //
 // (The persistent sweep kernel is in anneal.hip.)  Random words: Philox4x32-10
@@ -86,27 +86,34 @@ __global__ void local_field_kernel(int32_t n, int32_t quads, int32_t t4, int32_t
 // ---------------------------------------------------------------------------
 constexpr int kEnergyBlock = 256;
 
-__global__ __launch_bounds__(kEnergyBlock) void energy_cut_kernel(
-    int32_t n, int32_t t4, int32_t trials, const int32_t *__restrict__ row_ptr,
-    const int32_t *__restrict__ col, const int32_t *__restrict__ val,
-    const int32_t *__restrict__ h, int64_t w2, const int8_t *__restrict__ spins,
-    int64_t *__restrict__ energy, int64_t *__restrict__ cut) {
-    const int32_t q = blockIdx.x;
+// Pass 1: workgroup (row block, trial group q) sums, over its 256 rows, the
+// row terms m_i sum_j J_ij m_j and h_i m_i of the four trials of q; thread
+// per row.  part[(block * groups + q) * 8 + c]: c < 4 the S terms of trial
+// 4q + c, c >= 4 the h terms.
+__global__ __launch_bounds__(kEnergyBlock) void energy_partial_kernel(
+    int32_t n, int32_t t4, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const int32_t *__restrict__ val, const int32_t *__restrict__ h,
+    const int8_t *__restrict__ spins, int64_t *__restrict__ part) {
+    const int32_t q = blockIdx.y;
+    const int32_t i = blockIdx.x * kEnergyBlock + threadIdx.x;
     int64_t s[4] = {0, 0, 0, 0};
     int64_t hm[4] = {0, 0, 0, 0};
-    for (int32_t i = threadIdx.x; i < n; i += kEnergyBlock) {
+    if (i < n) {
         const uint32_t wi = load_word(spins, t4, i, q);
         int32_t L[4] = {0, 0, 0, 0};
-        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+        const int32_t e1 = row_ptr[i + 1];
+#pragma unroll 4
+        for (int32_t e = row_ptr[i]; e < e1; ++e) {
             const uint32_t wj = load_word(spins, t4, col[e], q);
+            const int32_t J = val[e];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) L[k] += val[e] * spin_of(wj, k);
+            for (int k = 0; k < 4; ++k) L[k] += J * spin_of(wj, k);
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int32_t mi = spin_of(wi, k);
-            s[k] += static_cast<int64_t>(mi * L[k]);
-            hm[k] += static_cast<int64_t>(mi * h[i]);
+            s[k] = static_cast<int64_t>(mi * L[k]);
+            hm[k] = static_cast<int64_t>(mi * h[i]);
         }
     }
     __shared__ int64_t red[kEnergyBlock / 64][8];
@@ -127,19 +134,29 @@ __global__ __launch_bounds__(kEnergyBlock) void energy_cut_kernel(
         }
     }
     __syncthreads();
-    if (threadIdx.x < 4) {
-        const int k = threadIdx.x;
-        int64_t S = 0, H = 0;
-        for (int w = 0; w < kEnergyBlock / 64; ++w) {
-            S += red[w][k];
-            H += red[w][4 + k];
-        }
-        const int32_t trial = 4 * q + k;
-        if (trial < trials) {
-            energy[trial] = -H - S / 2;
-            cut[trial] = (S - w2) / 4;
-        }
+    if (threadIdx.x < 8) {
+        int64_t v = 0;
+        for (int w = 0; w < kEnergyBlock / 64; ++w) v += red[w][threadIdx.x];
+        part[(static_cast<size_t>(blockIdx.x) * gridDim.y + q) * 8 + threadIdx.x] = v;
     }
+}
+
+// Pass 2: thread per trial k sums the row blocks' terms:
+//   E_k   = -sum_i h_i m_i - S_k / 2
+//   cut_k = sum_{i<j} w_ij [m_i != m_j] = (S_k - W2) / 4     (w = -J)
+__global__ void energy_finish_kernel(int32_t blocks, int32_t groups, int32_t trials, int64_t w2,
+                                     const int64_t *__restrict__ part, int64_t *__restrict__ energy,
+                                     int64_t *__restrict__ cut) {
+    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= trials) return;
+    const int32_t q = k >> 2, c = k & 3;
+    int64_t S = 0, H = 0;
+    for (int32_t b = 0; b < blocks; ++b) {
+        S += part[(static_cast<size_t>(b) * groups + q) * 8 + c];
+        H += part[(static_cast<size_t>(b) * groups + q) * 8 + 4 + c];
+    }
+    energy[k] = -H - S / 2;
+    cut[k] = (S - w2) / 4;
 }
 
 // [n][t4] -> [trials][n]
@@ -186,11 +203,20 @@ hipError_t launch_local_field(hipStream_t stream, const DevGraph &g, const DevRu
     return hipGetLastError();
 }
 
+size_t energy_partial_bytes(int32_t n, int32_t t4) {
+    return static_cast<size_t>((n + kEnergyBlock - 1) / kEnergyBlock) * (t4 / 4) * 8 * sizeof(int64_t);
+}
+
 hipError_t launch_energy_cut(hipStream_t stream, const DevGraph &g, const DevRun &run,
-                             int64_t *energy, int64_t *cut) {
-    hipLaunchKernelGGL(energy_cut_kernel, dim3(run.t4 / 4), dim3(kEnergyBlock), 0, stream, g.n,
-                       run.t4, run.trials, g.row_ptr, g.col, g.val, g.h, g.w2, run.spins, energy,
-                       cut);
+                             int64_t *part, int64_t *energy, int64_t *cut) {
+    const int32_t blocks = (g.n + kEnergyBlock - 1) / kEnergyBlock;
+    const int32_t groups = run.t4 / 4;
+    hipLaunchKernelGGL(energy_partial_kernel, dim3(blocks, groups), dim3(kEnergyBlock), 0, stream,
+                       g.n, run.t4, g.row_ptr, g.col, g.val, g.h, run.spins, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(energy_finish_kernel, dim3(grid_for(run.trials, 256)), dim3(256), 0, stream,
+                       blocks, groups, run.trials, g.w2, part, energy, cut);
     return hipGetLastError();
 }
 
