@@ -48,23 +48,28 @@ OPS_DECIDE = 2         # compare with r, select
 # at 2.4 GHz (the 157.3 TFLOP/s FP32 figure counts an FMA as 2 and dual issue).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 OPS_STALL = 3  # shift-compare of the stall word, select / memory op of the held input
+OPS_MEAN = 10  # window mean: convert, correctly rounded divide
 MFMA_I8_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak, TOP/s
 HBM_PEAK_GBS = 8000.0
 
 
-def ops_per_update(mean_degree: float, timing: bool, spsa: bool = False) -> float:
+def ops_per_update(mean_degree: float, timing: bool, algorithm: str = "psa",
+                   window: int = 4) -> float:
     """Algorithmic 32-bit lane-operations of one p-bit update.  SpSA adds a
     quarter Philox block for the stall word, its compare and the load or
-    store of the held input."""
+    store of the held input; TApSA the window store, window - 1 loads and
+    adds, and the mean (convert, divide)."""
+    spsa = algorithm == "spsa"
     philox = PHILOX_BLOCK_OPS / 4 * ((2 if timing else 1) + (1 if spsa else 0))
+    extra = OPS_STALL if spsa else (2 * window + OPS_MEAN if algorithm == "tapsa" else 0)
     return (philox + OPS_R_MAP + (OPS_GATE_MAP if timing else 0) + mean_degree
-            + OPS_PREACT + OPS_TANH + OPS_DECIDE + (OPS_STALL if spsa else 0))
+            + OPS_PREACT + OPS_TANH + OPS_DECIDE + extra)
 
 
-def cpu_baseline(spec, budget_s: float = 15.0, stall24=None):
+def cpu_baseline(spec, budget_s: float = 15.0, stall24=None, window=None):
     """Time the oracle on a bounded sample: the first `k` trials over the
     full schedule, k chosen so the single-thread work is about budget_s.
-    stall24: time the SpSA oracle with that stall threshold instead."""
+    stall24 / window: time the SpSA / TApSA oracle instead."""
     import oracle
     from concurrent.futures import ThreadPoolExecutor
     oracle.build(force=False)
@@ -77,7 +82,10 @@ def cpu_baseline(spec, budget_s: float = 15.0, stall24=None):
     # calibrate: one trial, a few steps
     cal_steps = max(1, min(S, 50))
     t0 = time.perf_counter()
-    if stall24 is None:
+    if window is not None:
+        oracle.run_tapsa(n, u, v, -w, None, i0, lam, dlt, thr, window, spec["seed"], 0, 1, 0,
+                         cal_steps, oracle.init_spins(n, spec["seed"], 0, 1))
+    elif stall24 is None:
         oracle.run(n, u, v, -w, None, i0, lam, dlt, thr, spec["seed"], 0, 1, 0, cal_steps,
                    oracle.init_spins(n, spec["seed"], 0, 1))
     else:
@@ -91,7 +99,11 @@ def cpu_baseline(spec, budget_s: float = 15.0, stall24=None):
     parts = [(int(a), int(b)) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
     t0 = time.perf_counter()
     with ThreadPoolExecutor(len(parts)) as ex:
-        if stall24 is None:
+        if window is not None:
+            list(ex.map(lambda ab: oracle.anneal_tapsa(n, u, v, -w, None, i0, lam, dlt, thr,
+                                                       window, spec["seed"], ab[0], ab[1]),
+                        parts))
+        elif stall24 is None:
             list(ex.map(lambda ab: oracle.anneal(n, u, v, -w, None, i0, lam, dlt, thr,
                                                  spec["seed"], ab[0], ab[1]), parts))
         else:
@@ -120,9 +132,11 @@ def main():
                     help="c4: graphs in the batch (256 = the workload; fewer for profiling)")
     ap.add_argument("--no-tune", action="store_true",
                     help="c5: cost-model path choice instead of the autotuner")
-    ap.add_argument("--algorithm", default="psa", choices=["psa", "spsa"],
-                    help="c1-c3: update rule (pSA, Eq. 3, or stalled p-bits, Eq. 5)")
+    ap.add_argument("--algorithm", default="psa", choices=["psa", "spsa", "tapsa"],
+                    help="c1-c3: update rule (pSA, Eq. 3; stalled p-bits, Eq. 5; "
+                         "time-averaged p-bits, Eq. 4)")
     ap.add_argument("--p-stall", type=float, default=0.5, help="SpSA stall probability")
+    ap.add_argument("--window", type=int, default=4, help="TApSA window (alpha)")
     ap.add_argument("--path", default="auto", choices=["auto", "csr", "dense"],
                     help="c1-c3: field path")
     ap.add_argument("--block", type=int, default=0)
@@ -166,12 +180,13 @@ def main():
     g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
     info = g.info()
     spsa = args.algorithm == "spsa"
+    alg = {"psa": psa.PSA_ALG_PSA, "spsa": psa.PSA_ALG_SPSA, "tapsa": psa.PSA_ALG_TAPSA}[args.algorithm]
     job = psa.Job(ctx, g, S, T, spec["seed"], sigma_lambda=spec["sigma_lambda"],
                   sigma_delta=spec["sigma_delta"], sigma_nu=spec["sigma_nu"],
                   p_mean=spec["p_mean"], block=args.block, trials_per_group=args.tpw,
                   lanes_per_task=args.lpt, path={"auto": psa.PSA_PATH_AUTO, "csr": psa.PSA_PATH_CSR,
                                                  "dense": psa.PSA_PATH_DENSE}[args.path],
-                  algorithm=psa.PSA_ALG_SPSA if spsa else psa.PSA_ALG_PSA, p_stall=args.p_stall)
+                  algorithm=alg, p_stall=args.p_stall, window=args.window)
     E = torch.empty(T, dtype=torch.int64, device="cuda")
     C = torch.empty(T, dtype=torch.int64, device="cuda")
 
@@ -201,7 +216,7 @@ def main():
     value = updates * args.steps / wall
     timing = spec["sigma_nu"] > 0 or spec["p_mean"] < 1.0
     mean_deg = info["nnz"] / n
-    opu = ops_per_update(mean_deg, timing, spsa)
+    opu = ops_per_update(mean_deg, timing, args.algorithm, args.window)
     achieved = opu * updates / (kernel_ms * 1e-3) / 1e12
     line = {
         "metric": "p-bit updates/s (n x trials x steps / s), 1 GPU",
@@ -224,6 +239,7 @@ def main():
             "sigma_nu": spec["sigma_nu"], "p_mean": spec["p_mean"],
             "updates_per_anneal": updates,
             "algorithm": args.algorithm, "p_stall": args.p_stall if spsa else None,
+            "window": args.window if args.algorithm == "tapsa" else None,
             "path": "dense" if job.dense else "csr",
         },
         "roofline": {
@@ -240,7 +256,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(
-            spec, stall24=int(args.p_stall * 2 ** 24) if spsa else None)
+            spec, stall24=int(args.p_stall * 2 ** 24) if spsa else None,
+            window=args.window if args.algorithm == "tapsa" else None)
     print(json.dumps(line), flush=True)
     job.close()
     g.close()

@@ -208,8 +208,9 @@ typedef struct psa_run_desc {
     int32_t trials_per_group;
     int32_t lanes_per_task;
     uint32_t flags; /* PSA_PATH_*, PSA_TUNE */
-    uint32_t algorithm; /* PSA_ALG_PSA or PSA_ALG_SPSA */
+    uint32_t algorithm; /* PSA_ALG_PSA, PSA_ALG_SPSA or PSA_ALG_TAPSA */
     double p_stall;     /* SpSA: probability that an input is held (0..1) */
+    int32_t window;     /* TApSA: steps averaged, alpha (1..64) */
 } psa_run_desc;
 
 /* Update rule (psa_run_desc.algorithm).
@@ -223,9 +224,18 @@ typedef struct psa_run_desc {
  *                 word i mod 4 of counter (t, i/4, k, 4): held iff
  *                 (word >> 8) < floor(p_stall 2^24).  The output rule
  *                 (timing gate, r, tanh) is unchanged.  A job keeps the held
- *                 inputs on the device (4 bytes per p-bit and trial). */
+ *                 inputs on the device (4 bytes per p-bit and trial).
+ *   PSA_ALG_TAPSA time-averaged p-bits (Eq. 4): the input of a p-bit is I0
+ *                 times the mean of its last `window` integer fields
+ *                 TI(t) = h + sum_j J m_j(t) (of the steps so far while
+ *                 t < window - 1), with the variability pre-activation
+ *                 x = (I0 lambda)(mean + delta); the mean is
+ *                 (float)sum / (float)count, each rounded once.  A job keeps
+ *                 the window on the device (4 window bytes per p-bit and
+ *                 trial). */
 #define PSA_ALG_PSA 0u
 #define PSA_ALG_SPSA 1u
+#define PSA_ALG_TAPSA 2u
 
 /* Field-computation path of a run (psa_run_desc.flags).  AUTO picks by a
  * cost model (long rows -> dense); CSR walks the sparse rows from LDS /
@@ -246,8 +256,8 @@ typedef struct psa_run_desc {
 
 /* Fill *d with the defaults: steps 1000, trials 1, seed 0, the paper's I0
  * endpoints (i0_min = i0_max = -1), no variability (sigmas 0, p_mean 1),
- * no explicit arrays, automatic block size, plain pSA (p_stall 0.5, the
- * paper's value, used only with PSA_ALG_SPSA). */
+ * no explicit arrays, automatic block size, plain pSA (p_stall 0.5 and
+ * window 4, the paper's values, used only by SpSA and TApSA). */
 void psa_run_desc_default(psa_run_desc *d);
 
 /* Output placement flags of the read calls and psa_anneal. */
@@ -292,8 +302,8 @@ psa_status psa_job_read_spins(psa_job *job, int8_t *out, uint32_t flags);
 
 /* Replace the spins of all trials by in[trials][n] (+1/-1 only; host or
  * device per flags) and set the step index to t (checkpoint / resume).
- * EUNSUPPORTED for an SpSA job with t > 0 (its held inputs are not part of
- * the spins). */
+ * EUNSUPPORTED for an SpSA or TApSA job with t > 0 (its held inputs or field
+ * window are not part of the spins). */
 psa_status psa_job_write_spins(psa_job *job, const int8_t *in, int32_t t,
                                uint32_t flags);
 

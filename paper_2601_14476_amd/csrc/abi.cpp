@@ -70,6 +70,7 @@ void job_free(psa_job *j) {
     dev_free(j->d_m);
     dev_free(j->d_spins);
     dev_free(j->d_xs);
+    dev_free(j->d_ring);
     dev_free(j->d_scratch);
     psa_ctx *ctx = j->retained ? j->ctx : nullptr;
     psa_graph *g = j->graph_ref;
@@ -318,6 +319,7 @@ void psa_run_desc_default(psa_run_desc *d) {
     d->p_mean = 1.0;
     d->algorithm = PSA_ALG_PSA;
     d->p_stall = 0.5;
+    d->window = 4;
 }
 
 psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *desc,
@@ -354,8 +356,13 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
         set_error("psa_job_create: unknown flags");
         return PSA_EINVAL;
     }
-    if (desc->algorithm != PSA_ALG_PSA && desc->algorithm != PSA_ALG_SPSA) {
+    if (desc->algorithm != PSA_ALG_PSA && desc->algorithm != PSA_ALG_SPSA &&
+        desc->algorithm != PSA_ALG_TAPSA) {
         set_error("psa_job_create: unknown algorithm");
+        return PSA_EINVAL;
+    }
+    if (desc->algorithm == PSA_ALG_TAPSA && (desc->window < 1 || desc->window > 64)) {
+        set_error("psa_job_create: window must be in [1, 64]");
         return PSA_EINVAL;
     }
     if (desc->algorithm == PSA_ALG_SPSA && !(desc->p_stall >= 0.0 && desc->p_stall <= 1.0)) {
@@ -463,6 +470,16 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
         j->run.xs = j->d_xs;
         j->run.stall24 = static_cast<uint32_t>(std::floor(desc->p_stall * 16777216.0));
     }
+    if (desc->algorithm == PSA_ALG_TAPSA) {
+        // field windows: [t4/4][n4][window][4] int32, slot t mod window written
+        // at step t before any read of it
+        const size_t rb = static_cast<size_t>(n4) * static_cast<size_t>(j->run.t4) *
+                          static_cast<size_t>(desc->window);
+        if ((st = dev_upload<int32_t>(&j->d_ring, nullptr, rb, "job field windows")) != PSA_OK)
+            return st;
+        j->run.ring = j->d_ring;
+        j->run.alpha = desc->window;
+    }
     j->run.i0 = j->d_i0;
     j->run.lambda = j->d_lambda;
     j->run.delta = j->d_delta;
@@ -524,7 +541,7 @@ psa_status psa_job_get_info(const psa_job *job, psa_job_info *out) {
     out->lanes_per_task = job->plan.dense ? 0 : job->plan.lpt;
     out->block = job->plan.dense ? 256 : job->plan.block;
     out->dense_encoding = job->plan.dense ? (job->g->dense_enc == psa::kDenseT2 ? 2 : 1) : 0;
-    out->algorithm = job->run.xs ? PSA_ALG_SPSA : PSA_ALG_PSA;
+    out->algorithm = job->run.ring ? PSA_ALG_TAPSA : (job->run.xs ? PSA_ALG_SPSA : PSA_ALG_PSA);
     return PSA_OK;
 }
 
@@ -563,9 +580,9 @@ psa_status psa_job_write_spins(psa_job *job, const int8_t *in, int32_t t, uint32
         set_error("psa_job_write_spins: invalid arguments");
         return PSA_EINVAL;
     }
-    if (job->run.xs != nullptr && t > 0) {
-        set_error("psa_job_write_spins: an SpSA job resumes only at step 0 (held inputs are not "
-                  "part of the spins)");
+    if ((job->run.xs != nullptr || job->run.ring != nullptr) && t > 0) {
+        set_error("psa_job_write_spins: an SpSA or TApSA job resumes only at step 0 (held inputs "
+                  "and field windows are not part of the spins)");
         return PSA_EUNSUPPORTED;
     }
     PSA_HIP(hipSetDevice(job->ctx->device), "hipSetDevice");

@@ -255,11 +255,11 @@ __device__ __forceinline__ bool any_gate(const uint32_t *thr, int32_t m) {
 // One trial per workgroup: lane `sub` of task m updates its P p-bits and
 // returns their new bytes (in the LDS encoding) in the low 8P bits.
 // ---------------------------------------------------------------------------
-template <int CSR, int LPT, bool SPSA, bool BLK>
+template <int CSR, int LPT, int ALG, bool BLK>
 __device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, uint32_t sub,
                                                    uint32_t k, uint32_t t, float i0t,
                                                    const unsigned char *cur, uint32_t k0,
-                                                   uint32_t k1, const Stall &st) {
+                                                   uint32_t k1, const InputState &st) {
     constexpr int P = 4 / LPT;
     constexpr bool kU = Enc<1, CSR>::kU;
     const bool need_gate = any_gate(v.thr, m);
@@ -267,7 +267,7 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, ui
     task_words<LPT>(t, static_cast<uint32_t>(m), k, sub, need_gate, k0, k1, rw, gw);
 #pragma unroll
     for (int j = 0; j < P; ++j) sw[j] = 0u;
-    if (SPSA && t > 0) {
+    if (ALG == kAlgSpsa && t > 0) {
         const Words4 b = block_of(t, static_cast<uint32_t>(m), k, kTagStall, k0, k1);
 #pragma unroll
         for (int j = 0; j < P; ++j) sw[j] = word_of(b, sub * P + j);
@@ -293,7 +293,7 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, ui
         const uint32_t old = cur[i];
         const uint32_t th = v.thr[i];
         const bool fire = th >= kGateOne || fires(gw[j], th);
-        const float x = input_of<SPSA>(i0t * v.lam[i], v.dlt[i], L[j], st, i, k, t, sw[j]);
+        const float x = input_of<ALG>(i0t * v.lam[i], v.dlt[i], L[j], st, i, k, t, sw[j]);
         const bool up = goes_up(x, rw[j]);
         const uint32_t nb = kU ? (up ? 1u : 0u) : (up ? 0x01u : 0xFFu);
         out |= (fire ? nb : old) << (8 * j);
@@ -305,10 +305,10 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, ui
 // Four trials per workgroup: one lane per task updates 4 p-bits x 4 trials and
 // writes the four packed words of the next step.
 // ---------------------------------------------------------------------------
-template <int CSR, bool SPSA, bool BLK>
+template <int CSR, int ALG, bool BLK>
 __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int32_t q, uint32_t t,
                                                  float i0t, const uint32_t *cur, uint32_t *nxt,
-                                                 uint32_t k0, uint32_t k1, const Stall &st) {
+                                                 uint32_t k0, uint32_t k1, const InputState &st) {
     constexpr bool kU = Enc<4, CSR>::kU;
     int32_t L[4][4];
     uint32_t word[4], th[4];
@@ -341,7 +341,7 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
         const Words4 r = block_of(t, static_cast<uint32_t>(m), k, kTagR, k0, k1);
         const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
         uint32_t sw[4] = {0u, 0u, 0u, 0u};
-        if (SPSA && t > 0) {
+        if (ALG == kAlgSpsa && t > 0) {
             const Words4 b = block_of(t, static_cast<uint32_t>(m), k, kTagStall, k0, k1);
             sw[0] = b.x;
             sw[1] = b.y;
@@ -351,7 +351,7 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             const bool fire = th[p] >= kGateOne || fires(gw[p], th[p]);
-            const float x = input_of<SPSA>(a[p], d[p], L[p][kk], st, 4 * m + p, k, t, sw[p]);
+            const float x = input_of<ALG>(a[p], d[p], L[p][kk], st, 4 * m + p, k, t, sw[p]);
             const bool up = goes_up(x, rw[p]);
             const uint32_t nb = kU ? (up ? 1u : 0u) : (up ? 0x01u : 0xFFu);
             if (fire) word[p] = (word[p] & ~(0xFFu << (8 * kk))) | (nb << (8 * kk));
@@ -473,11 +473,11 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
 
     unsigned char *cur = buf0;
     unsigned char *nxt = buf1;
-    const Stall st{a.xs, a.stall24, n4};
-    // the step loop, instantiated with and without the SpSA input stage so
-    // that plain pSA carries no per-update test for it
-    auto sweep = [&](auto spsa_tag) {
-    constexpr bool SPSA = decltype(spsa_tag)::value;
+    const InputState st{a.xs, a.stall24, a.ring, a.alpha, n4};
+    // the step loop, instantiated per input stage (pSA, SpSA, TApSA) so that
+    // plain pSA carries no per-update test for the others
+    auto sweep = [&](auto alg_tag) {
+    constexpr int ALG = decltype(alg_tag)::value;
     for (int32_t t = a.t_begin; t < a.t_end; ++t) {
         const float i0t = a.i0[t];
         if constexpr (TPW == 1) {
@@ -485,7 +485,7 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
             const uint32_t sub = threadIdx.x % LPT;
             for (int32_t slot = threadIdx.x / LPT; slot < tasks; slot += BLOCK / LPT) {
                 const int32_t m = v.order[slot];
-                const uint32_t b = task_one_trial<CSR, LPT, SPSA, !CSR_LDS>(v, m, sub, static_cast<uint32_t>(q),
+                const uint32_t b = task_one_trial<CSR, LPT, ALG, !CSR_LDS>(v, m, sub, static_cast<uint32_t>(q),
                                                             static_cast<uint32_t>(t), i0t, cur,
                                                             a.k0, a.k1, st);
                 constexpr int P = 4 / LPT;
@@ -506,7 +506,7 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
             }
         } else {
             for (int32_t slot = threadIdx.x; slot < tasks; slot += BLOCK)
-                task_four_trials<CSR, SPSA, !CSR_LDS>(v, v.order[slot], q, static_cast<uint32_t>(t), i0t,
+                task_four_trials<CSR, ALG, !CSR_LDS>(v, v.order[slot], q, static_cast<uint32_t>(t), i0t,
                                       reinterpret_cast<const uint32_t *>(cur),
                                       reinterpret_cast<uint32_t *>(nxt), a.k0, a.k1, st);
         }
@@ -516,10 +516,12 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
         nxt = tmp;
     }
     };
-    if (a.xs != nullptr)
-        sweep(std::true_type{});
+    if (a.ring != nullptr)
+        sweep(std::integral_constant<int, kAlgTapsa>{});
+    else if (a.xs != nullptr)
+        sweep(std::integral_constant<int, kAlgSpsa>{});
     else
-        sweep(std::false_type{});
+        sweep(std::integral_constant<int, kAlgPsa>{});
 
     if constexpr (TPW == 1) {
         for (int32_t i = threadIdx.x; i < n; i += BLOCK) {
@@ -730,6 +732,8 @@ void fill_anneal_args(AnnealArgs *a, const DevGraph &g, const DevRun &run, const
     a->spins = run.spins;
     a->xs = run.xs;
     a->stall24 = run.stall24;
+    a->ring = run.ring;
+    a->alpha = run.alpha;
 }
 
 bool plan_batch_item(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t lpt_req,

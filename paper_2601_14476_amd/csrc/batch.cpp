@@ -184,6 +184,8 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
         d.k1 = job->run.key1;
         d.xs = job->run.xs;
         d.stall24 = job->run.stall24;
+        d.ring = job->run.ring;
+        d.alpha = job->run.alpha;
         const int32_t e = g->dense_enc == kDenseT2 ? 1 : 0;
         by_enc[e].push_back(static_cast<int32_t>(table.size()));
         nb[e] = std::min(nb[e], job->plan.nb);

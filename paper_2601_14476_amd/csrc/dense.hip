@@ -210,7 +210,7 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
     // once per pass, keeping few registers live.
     const float i0t = jb.i0[t];
     const int32_t scale = jb.scale;
-    const Stall st{jb.xs, jb.stall24, jb.n4};
+    const InputState st{jb.xs, jb.stall24, jb.ring, jb.alpha, jb.n4};
     auto update = [&](int e, const v4i a4) __attribute__((always_inline)) {
         const int rb = e / NB, nb = e % NB;
         const int32_t i0 = wrow0 + rb * 16 + (lane >> 4) * 4;
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
         const uint4 th = *reinterpret_cast<const uint4 *>(jb.thr + ic);
         const float4 lm = *reinterpret_cast<const float4 *>(jb.lam + ic);
         const float4 dl = *reinterpret_cast<const float4 *>(jb.dlt + ic);
-        const Stall sv{valid ? st.xs : nullptr, st.s24, st.n4};
+        const InputState sv{valid ? st.xs : nullptr, st.s24, valid ? st.ring : nullptr, st.alpha, st.n4};
         const int32_t hv[4] = {hh.x, hh.y, hh.z, hh.w};
         const uint32_t tv[4] = {th.x, th.y, th.z, th.w};
         const float av[4] = {i0t * lm.x, i0t * lm.y, i0t * lm.z, i0t * lm.w};
@@ -258,8 +258,8 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             const int32_t L = hv[p] + scale * a4[p];
-            const float x = input_of<true>(av[p], dv[p], L, sv, i0 + p, static_cast<uint32_t>(k),
-                                           static_cast<uint32_t>(t), sw[p]);
+            const float x = input_any(av[p], dv[p], L, sv, i0 + p, static_cast<uint32_t>(k),
+                                      static_cast<uint32_t>(t), sw[p]);
             const bool up = tanh_f32(x) > r_of(rw[p]);
             const bool fire = tv[p] >= kGateOne || fires(gw[p], tv[p]);
             const uint32_t ob = (old >> (8 * p)) & 0xFFu;

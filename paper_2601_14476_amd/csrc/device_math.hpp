@@ -97,28 +97,58 @@ __device__ __forceinline__ u32x4 load_global_x4(const void *p) {
     return *(const u32x4 __attribute__((address_space(1))) *)(p);
 }
 
-// SpSA held-input state of one run: pre-activations [t4/4][n4][4] (trial
-// group, p-bit, trial in group); xs == nullptr for plain pSA.
-struct Stall {
+// Input-stage state of one run (Eq. 4 / Eq. 5 variants), both laid out as
+// [t4/4][n4] x (trial in group innermost):
+//   xs    SpSA held pre-activations, [t4/4][n4][4] floats (else nullptr);
+//   ring  TApSA field windows, [t4/4][n4][alpha][4] int32 (else nullptr).
+struct InputState {
     float *xs;
     uint32_t s24;
+    int32_t *ring;
+    int32_t alpha;
     int32_t n4;
 };
 
-// Input stage of p-bit i, trial k at step t (Eq. 5 on the pre-activation
-// x = a (L + d), a = I0 lambda_i, d = delta_i): with SpSA the input is held
-// from the last refresh iff t > 0 and (stall word >> 8) < stall24, else it is
-// formed anew and stored.  Plain pSA (SPSA false, or no state): always
-// fresh.
-template <bool SPSA>
-__device__ __forceinline__ float input_of(float a, float d, int32_t L, const Stall &st, int32_t i,
-                                          uint32_t k, uint32_t t, uint32_t sword) {
-    const float x = a * (static_cast<float>(L) + d);
-    if (!SPSA || st.xs == nullptr) return x;
-    float *slot = st.xs + ((static_cast<size_t>(k >> 2) * st.n4 + i) * 4 + (k & 3u));
-    if (t > 0 && (sword >> 8) < st.s24) return *slot;
-    *slot = x;
-    return x;
+enum : int { kAlgPsa = 0, kAlgSpsa = 1, kAlgTapsa = 2 };
+
+// Input stage of p-bit i, trial k at step t, on the field L of step t; a =
+// I0 lambda_i, d = delta_i.
+//   pSA   (Eq. 3): x = a (L + d).
+//   SpSA  (Eq. 5): the input is held from the last refresh iff t > 0 and
+//         (stall word >> 8) < stall24, else formed anew as above and stored.
+//   TApSA (Eq. 4): L enters the window slot t mod alpha; x = a (mean + d),
+//         mean = (float)sum / (float)count over the last min(t+1, alpha)
+//         fields.
+template <int ALG>
+__device__ __forceinline__ float input_of(float a, float d, int32_t L, const InputState &st,
+                                          int32_t i, uint32_t k, uint32_t t, uint32_t sword) {
+    if constexpr (ALG == kAlgSpsa) {
+        const float x = a * (static_cast<float>(L) + d);
+        float *slot = st.xs + ((static_cast<size_t>(k >> 2) * st.n4 + i) * 4 + (k & 3u));
+        if (t > 0 && (sword >> 8) < st.s24) return *slot;
+        *slot = x;
+        return x;
+    } else if constexpr (ALG == kAlgTapsa) {
+        const uint32_t al = static_cast<uint32_t>(st.alpha);
+        int32_t *w = st.ring + (static_cast<size_t>(k >> 2) * st.n4 + i) * al * 4 + (k & 3u);
+        w[(t % al) * 4] = L;
+        const uint32_t count = t + 1 < al ? t + 1 : al;
+        int32_t sum = L;
+        for (uint32_t q = 1; q < count; ++q) sum += w[((t - q) % al) * 4];
+        const float mean = static_cast<float>(sum) / static_cast<float>(count);
+        return a * (mean + d);
+    } else {
+        (void)st, (void)i, (void)k, (void)t, (void)sword;
+        return a * (static_cast<float>(L) + d);
+    }
+}
+
+// The same with the variant chosen at run time from the state pointers.
+__device__ __forceinline__ float input_any(float a, float d, int32_t L, const InputState &st,
+                                           int32_t i, uint32_t k, uint32_t t, uint32_t sword) {
+    if (st.ring != nullptr) return input_of<kAlgTapsa>(a, d, L, st, i, k, t, sword);
+    if (st.xs != nullptr) return input_of<kAlgSpsa>(a, d, L, st, i, k, t, sword);
+    return input_of<kAlgPsa>(a, d, L, st, i, k, t, sword);
 }
 
 // Sign-extend byte k of a packed word of four int8 spins.

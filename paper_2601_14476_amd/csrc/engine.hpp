@@ -77,6 +77,8 @@ struct DevRun {
     int8_t *spins = nullptr;              // [n][t4]
     float *xs = nullptr;                  // SpSA held inputs [t4/4][n4][4], else nullptr
     uint32_t stall24 = 0;                 // SpSA stall threshold
+    int32_t *ring = nullptr;              // TApSA windows [t4/4][n4][alpha][4], else nullptr
+    int32_t alpha = 1;                    // TApSA window
 };
 
 // How the persistent anneal kernel is launched for one run.
@@ -110,10 +112,13 @@ struct AnnealArgs {
     const int32_t *order;
     uint32_t k0, k1;
     int8_t *spins;
-    // SpSA (Eq. 5): held pre-activations [t4/4][n4][4] (nullptr = pSA) and the
+    // SpSA (Eq. 5): held pre-activations [t4/4][n4][4] (nullptr = off) and the
     // stall threshold (an input is held iff (stall word >> 8) < stall24)
     float *xs;
     uint32_t stall24;
+    // TApSA (Eq. 4): field windows [t4/4][n4][alpha][4] (nullptr = off)
+    int32_t *ring;
+    int32_t alpha;
 };
 
 // Kernel variants a batched launch can mix (one trial per workgroup).
@@ -160,6 +165,8 @@ struct DenseJob {
     uint32_t k0, k1;
     float *xs;         // SpSA held inputs [t4/4][n4][4], else nullptr
     uint32_t stall24;  // SpSA stall threshold
+    int32_t *ring;     // TApSA windows [t4/4][n4][alpha][4], else nullptr
+    int32_t alpha;     // TApSA window
 };
 
 // Choose tpw / lanes per task / CSR placement / block for a run
@@ -354,6 +361,7 @@ struct psa_job {
     uint32_t *d_thr24 = nullptr;
     int8_t *d_spins = nullptr;
     float *d_xs = nullptr;       // SpSA held inputs
+    int32_t *d_ring = nullptr;   // TApSA field windows
     void *d_scratch = nullptr;   // read-out staging
     size_t scratch_bytes = 0;
 };

@@ -65,13 +65,15 @@ struct ServerJob {
 
 // Device bytes a job holds while resident (graph in all encodings, run
 // arrays, spins, read-out staging).
-size_t footprint_of(int32_t n, int64_t m, int32_t trials, int32_t steps, bool spsa) {
+size_t footprint_of(int32_t n, int64_t m, int32_t trials, int32_t steps, const psa_run_desc &d) {
+    const bool spsa = d.algorithm == PSA_ALG_SPSA;
+    const size_t window = d.algorithm == PSA_ALG_TAPSA ? static_cast<size_t>(std::max(d.window, 1)) : 0;
     const size_t n4 = static_cast<size_t>((n + 3) / 4 * 4);
     const size_t nnz = static_cast<size_t>(2 * m);
     const size_t t4 = static_cast<size_t>((trials + 3) / 4 * 4);
     const size_t graph = (n4 + 4) * 4 + nnz * (4 + 4 + 4 + 2 + 2) + n4 * 4;
     const size_t run = static_cast<size_t>(steps) * 4 + n4 * 12 + n4 + n4 * t4 +
-                       (spsa ? n4 * t4 * 4 : 0);
+                       (spsa ? n4 * t4 * 4 : 0) + n4 * t4 * 4 * window;
     const size_t staging = std::max(static_cast<size_t>(n) * trials * 4, static_cast<size_t>(trials) * 16);
     return graph + run + staging + 8 * 256;  // allocation granularity slack
 }
@@ -362,7 +364,7 @@ psa_status psa_server_submit(psa_server *s, int32_t n, int64_t m, const int32_t 
     j->energy_out = energy_out;
     j->cut_out = cut_out;
     j->spins_out = spins_out;
-    j->footprint = footprint_of(n, m, desc->trials, desc->steps, desc->algorithm == PSA_ALG_SPSA);
+    j->footprint = footprint_of(n, m, desc->trials, desc->steps, *desc);
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) {
         set_error("psa_server_submit: server is shutting down");

@@ -36,7 +36,7 @@ PSA_OUT_DEVICE = 1
 PSA_BATCH_SEQUENTIAL = 2
 PSA_PATH_AUTO, PSA_PATH_CSR, PSA_PATH_DENSE = 0, 1, 2
 PSA_TUNE = 4
-PSA_ALG_PSA, PSA_ALG_SPSA = 0, 1
+PSA_ALG_PSA, PSA_ALG_SPSA, PSA_ALG_TAPSA = 0, 1, 2
 PSA_TUNE_ALONE, PSA_TUNE_BATCH = 0, 1
 
 _P = ctypes.c_void_p
@@ -57,7 +57,7 @@ class psa_run_desc(ctypes.Structure):
                 ("sigma_nu", _f64), ("p_mean", _f64), ("lambda_", _P),
                 ("delta", _P), ("thr24", _P), ("block", _i32),
                 ("trials_per_group", _i32), ("lanes_per_task", _i32), ("flags", _u32),
-                ("algorithm", _u32), ("p_stall", _f64)]
+                ("algorithm", _u32), ("p_stall", _f64), ("window", _i32)]
 
 
 class psa_tune_result(ctypes.Structure):
@@ -337,7 +337,7 @@ def make_desc(steps, trials, seed=0, i0=None, i0_min=None, i0_max=None,
               sigma_lambda=0.0, sigma_delta=0.0, sigma_nu=0.0, p_mean=1.0,
               lam=None, delta=None, thr24=None, block=0, trials_per_group=0,
               lanes_per_task=0, path=PSA_PATH_AUTO, tune=False, algorithm=PSA_ALG_PSA,
-              p_stall=0.5):
+              p_stall=0.5, window=4):
     """Build a psa_run_desc; returns (desc, keepalive arrays).  tune=True sets
     PSA_TUNE (path and launch shape from the context's tuning cache)."""
     d = psa_run_desc()
@@ -364,6 +364,7 @@ def make_desc(steps, trials, seed=0, i0=None, i0_min=None, i0_max=None,
     d.flags = int(path) | (PSA_TUNE if tune else 0)
     d.algorithm = int(algorithm)
     d.p_stall = float(p_stall)
+    d.window = int(window)
     return d, keep
 
 

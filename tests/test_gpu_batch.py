@@ -203,13 +203,16 @@ def test_batch_four_trial_groups(psa, ctx):
 
 
 def test_batch_mixes_spsa_and_psa(psa, ctx):
-    """SpSA and pSA jobs on CSR (one and four trials per workgroup) and dense
-    paths advance together in quanta and end where each ends alone."""
+    """SpSA, TApSA and pSA jobs on CSR (one and four trials per workgroup) and
+    dense paths advance together in quanta and end where each ends alone."""
     specs = [(inputs.gnm(600, 1800, 95), psa.PSA_ALG_SPSA, psa.PSA_PATH_CSR, 1, 9, 33),
              (inputs.gnm(900, 2700, 96), psa.PSA_ALG_SPSA, psa.PSA_PATH_CSR, 4, 12, 27),
              (inputs.erdos_renyi(500, 0.2, 97), psa.PSA_ALG_SPSA, psa.PSA_PATH_DENSE, 0, 20, 31),
-             (inputs.gnm(700, 2100, 98), psa.PSA_ALG_PSA, psa.PSA_PATH_CSR, 1, 5, 29)]
-    kw = dict(sigma_lambda=0.1, sigma_delta=0.1, sigma_nu=0.1, p_mean=0.8, p_stall=0.5)
+             (inputs.gnm(700, 2100, 98), psa.PSA_ALG_PSA, psa.PSA_PATH_CSR, 1, 5, 29),
+             (inputs.gnm(650, 1950, 99), psa.PSA_ALG_TAPSA, psa.PSA_PATH_CSR, 1, 6, 25),
+             (inputs.gnm(800, 2400, 100), psa.PSA_ALG_TAPSA, psa.PSA_PATH_CSR, 4, 10, 27),
+             (inputs.erdos_renyi(450, 0.2, 101), psa.PSA_ALG_TAPSA, psa.PSA_PATH_DENSE, 0, 18, 22)]
+    kw = dict(sigma_lambda=0.1, sigma_delta=0.1, sigma_nu=0.1, p_mean=0.8, p_stall=0.5, window=4)
     jobs, refs = [], []
     for (n, u, v, w), alg, path, tpw, T, S in specs:
         g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)

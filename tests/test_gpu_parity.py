@@ -487,3 +487,59 @@ def test_spsa_edge_cases(psa, ctx):
     assert e.value.status == psa.PSA_EUNSUPPORTED
     with pytest.raises(psa.PsaError):
         psa.Job(ctx, g, 30, 7, 4, algorithm=psa.PSA_ALG_SPSA, p_stall=1.5)
+
+
+@pytest.mark.parametrize("kind,tpw,lpt,path,window", [
+    ("unit", 1, 1, "csr", 4), ("unit", 1, 2, "csr", 4), ("unit", 1, 4, "csr", 3),
+    ("unit", 4, 0, "csr", 4), ("int", 1, 2, "csr", 4), ("int", 4, 0, "csr", 2),
+    ("unit", 0, 0, "dense", 4), ("int", 0, 0, "dense", 3)])
+def test_tapsa_trajectories_match_oracle(psa, ctx, kind, tpw, lpt, path, window):
+    """Time-averaged p-bits (Eq. 4): spins after every chunk of steps equal
+    the oracle's on every path and launch shape (field windows carried
+    between launches on the device, start-up averages included)."""
+    if kind == "unit":
+        n, u, v, w = inputs.gnm(333, 1400, 94)
+        j, h = -w, None
+    else:
+        n, u, v, j, h = _random_ising(301, 1300, 95, jmax=4)
+    g = psa.Graph.from_edges(ctx, n, u, v, j, h=h, maxcut=False)
+    S, T = 24, 11
+    i0 = oracle.schedule(S, 0.02, 0.9)
+    sig = (0.1, 0.2, 0.1, 0.8)
+    lam, dl, thr = oracle.variability(n, 17, *sig)
+    job = psa.Job(ctx, g, S, T, seed=17, i0=i0, sigma_lambda=sig[0], sigma_delta=sig[1],
+                  sigma_nu=sig[2], p_mean=sig[3], trials_per_group=tpw, lanes_per_task=lpt,
+                  path=psa.PSA_PATH_DENSE if path == "dense" else psa.PSA_PATH_CSR,
+                  algorithm=psa.PSA_ALG_TAPSA, window=window)
+    ref = oracle.init_spins(n, 17, 0, T)
+    ring = None
+    t = 0
+    for k in (1, 2, 6, 7, 8):
+        job.step(k)
+        ref, ring = oracle.run_tapsa(n, u, v, j, h, i0, lam, dl, thr, window, 17, 0, T, t,
+                                     t + k, ref, ring)
+        t += k
+        np.testing.assert_array_equal(job.read_spins(), ref, err_msg=f"after step {t}")
+    E, C = job.energy_cut()
+    rE, rC = oracle.energy_cut(n, u, v, j, h, ref)
+    np.testing.assert_array_equal(E, rE)
+    np.testing.assert_array_equal(C, rC)
+
+
+def test_tapsa_edge_cases(psa, ctx):
+    """A window of one is pSA; resuming a TApSA job mid-run from spins alone
+    is refused; windows outside [1, 64] are rejected."""
+    n, u, v, w = inputs.gnm(200, 700, 96)
+    g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
+    kw = dict(sigma_lambda=0.1, sigma_delta=0.1, sigma_nu=0.1, p_mean=0.8)
+    a = psa.anneal(ctx, g, 30, 7, 4, **kw)
+    b = psa.anneal(ctx, g, 30, 7, 4, algorithm=psa.PSA_ALG_TAPSA, window=1, **kw)
+    np.testing.assert_array_equal(a[0], b[0])
+    job = psa.Job(ctx, g, 30, 7, 4, algorithm=psa.PSA_ALG_TAPSA, window=4, **kw)
+    job.step(10)
+    with pytest.raises(psa.PsaError) as e:
+        job.write_spins(job.read_spins(), 5)
+    assert e.value.status == psa.PSA_EUNSUPPORTED
+    for bad in (0, 65):
+        with pytest.raises(psa.PsaError):
+            psa.Job(ctx, g, 30, 7, 4, algorithm=psa.PSA_ALG_TAPSA, window=bad)
