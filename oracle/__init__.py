@@ -80,6 +80,11 @@ def _load():
     lib.psa_ref_run_tapsa.argtypes = [i32, i64, P, P, P, P, P, P, P, P, i32, u64, i32,
                                       i32, i32, i32, P, P]
     lib.psa_ref_run_tapsa.restype = ctypes.c_int
+    lib.psa_ref_periods.argtypes = [i32, u64, f64, i32, P]
+    lib.psa_ref_periods.restype = ctypes.c_int
+    lib.psa_ref_run_period.argtypes = [i32, i64, P, P, P, P, P, P, P, P, i32, u64, i32, i32,
+                                       i32, i32, P]
+    lib.psa_ref_run_period.restype = ctypes.c_int
     lib.psa_ref_energy_cut.argtypes = [i32, i64, P, P, P, P, i32, P, P, P]
     lib.psa_ref_energy_cut.restype = ctypes.c_int
     lib.psa_ref_anneal.argtypes = [i32, i64, P, P, P, P, i32, P, P, P, P, u64,
@@ -261,6 +266,43 @@ def run_spsa(n, eu, ev, ej, h, i0, lam, off, thr, stall24, seed, trial_begin, tr
                                     _ptr(x)),
            "psa_ref_run_spsa")
     return s, x
+
+
+def periods(n, seed, sigma_nu, t_res):
+    """Integer timing periods in sub-steps (psa_ref_periods)."""
+    out = np.zeros(n, np.uint32)
+    _check(_load().psa_ref_periods(n, seed, float(sigma_nu), int(t_res), _ptr(out)),
+           "psa_ref_periods")
+    return out
+
+
+def run_period(n, eu, ev, ej, h, i0, lam, off, period, t_res, seed, trial_begin, trial_end,
+               t_begin, t_end, spins):
+    """Period-mode cycles t_begin..t_end-1 on a copy of `spins`."""
+    eu, ev, ej = _edges(eu, ev, ej)
+    h = _opt_h(h, n)
+    i0 = np.ascontiguousarray(i0, dtype=np.float32)
+    lam = np.ascontiguousarray(lam, dtype=np.float32)
+    off = np.ascontiguousarray(off, dtype=np.float32)
+    period = np.ascontiguousarray(period, dtype=np.uint32)
+    if i0.size < t_end or lam.size != n or off.size != n or period.size != n:
+        raise ValueError("schedule or per-p-bit arrays have the wrong size")
+    rows = trial_end - trial_begin
+    s = np.ascontiguousarray(np.array(spins, dtype=np.int8, copy=True).reshape(rows, n))
+    _check(_load().psa_ref_run_period(n, eu.size, _ptr(eu), _ptr(ev), _ptr(ej), _ptr(h),
+                                      _ptr(i0), _ptr(lam), _ptr(off), _ptr(period), int(t_res),
+                                      seed, trial_begin, trial_end, t_begin, t_end, _ptr(s)),
+           "psa_ref_run_period")
+    return s
+
+
+def anneal_period(n, eu, ev, ej, h, i0, lam, off, period, t_res, seed, trial_begin, trial_end):
+    """Period-mode anneal: initial spins, len(i0) cycles, energy and cut."""
+    s0 = init_spins(n, seed, trial_begin, trial_end)
+    s = run_period(n, eu, ev, ej, h, i0, lam, off, period, t_res, seed, trial_begin,
+                   trial_end, 0, len(i0), s0)
+    E, C = energy_cut(n, eu, ev, ej, h, s)
+    return s, E, C
 
 
 def run_tapsa(n, eu, ev, ej, h, i0, lam, off, thr, alpha, seed, trial_begin, trial_end,

@@ -354,6 +354,26 @@ int psa_ref_variability(int32_t n, uint64_t seed, double sigma_lambda,
     return 0;
 }
 
+/* Eq. 6's timing factor nu_i as the integer period of the listing's gate
+ * (count mod nu[i]): the nominal period is one cycle of t_res sub-steps
+ * and nu_i stretches or shortens it. */
+int psa_ref_periods(int32_t n, uint64_t seed, double sigma_nu, int32_t t_res,
+                    uint32_t *period_out)
+{
+    if (n < 1 || !period_out || t_res < 1 || !(sigma_nu >= 0.0))
+        return -1;
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int32_t i = 0; i < n; i++) {
+        uint32_t c1[4] = {0u, (uint32_t)i, 1u, TAG_VAR};
+        uint32_t x[4];
+        psa_ref_philox4x32_10(c1, key, x);
+        double nu = sigma_nu * box_muller_cos(x[0], x[1]);
+        double p = rint((double)t_res * (1.0 + nu));
+        period_out[i] = p < 1.0 ? 1u : (uint32_t)p;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* Initial state: uniform +-1 from the top bit of the INIT word.        */
 /* ------------------------------------------------------------------ */
@@ -504,6 +524,63 @@ int psa_ref_run_spsa(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
                 next[i] = (psa_ref_tanh(xk[i]) > r) ? (int8_t)1 : (int8_t)-1;
             }
             memcpy(mk, next, (size_t)n);
+        }
+    }
+    free(L);
+    free(next);
+    adj_free(&a);
+    return 0;
+}
+
+/* Period-mode timing (Eq. 6, listing): the simulation advances in sub-steps
+ * of 1/t_res cycle; a p-bit fires at the sub-steps that are multiples of its
+ * period and otherwise holds its output. */
+int psa_ref_run_period(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+                       const int32_t *ej, const int32_t *h, const float *i0,
+                       const float *lambda, const float *offset,
+                       const uint32_t *period, int32_t t_res, uint64_t seed,
+                       int32_t trial_begin, int32_t trial_end, int32_t t_begin,
+                       int32_t t_end, int8_t *spins)
+{
+    if (!i0 || !lambda || !offset || !period || !spins || t_res < 1 ||
+        trial_begin < 0 || trial_end < trial_begin || t_begin < 0 || t_end < t_begin)
+        return -1;
+    for (int32_t i = 0; i < n; i++)
+        if (period[i] < 1)
+            return -1;
+    ref_adj a;
+    int rc = adj_build(n, m, eu, ev, ej, h, &a);
+    if (rc != 0)
+        return rc;
+    int32_t *L = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int8_t *next = (int8_t *)malloc((size_t)n);
+    if (!L || !next) {
+        free(L);
+        free(next);
+        adj_free(&a);
+        return -2;
+    }
+    for (int32_t k = trial_begin; k < trial_end; k++) {
+        int8_t *mk = spins + (int64_t)(k - trial_begin) * n;
+        for (int32_t t = t_begin; t < t_end; t++) {
+            for (int32_t s = 0; s < t_res; s++) {
+                uint32_t tau = (uint32_t)t * (uint32_t)t_res + (uint32_t)s;
+                for (int32_t i = 0; i < n; i++)
+                    L[i] = field_of(&a, h, i, mk);
+                for (int32_t i = 0; i < n; i++) {
+                    if (tau % period[i] != 0) {
+                        next[i] = mk[i];
+                        continue;
+                    }
+                    uint32_t ur = psa_ref_word(seed, tau, (uint32_t)i, (uint32_t)k, TAG_R);
+                    float r = psa_ref_r_from_word(ur);
+                    float a_i = i0[t] * lambda[i];
+                    float b_i = (float)L[i] + offset[i];
+                    float x = a_i * b_i;
+                    next[i] = (psa_ref_tanh(x) > r) ? (int8_t)1 : (int8_t)-1;
+                }
+                memcpy(mk, next, (size_t)n);
+            }
         }
     }
     free(L);

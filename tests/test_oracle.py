@@ -521,6 +521,101 @@ def test_tapsa_resume_composes():
     np.testing.assert_array_equal(rf, r2)
 
 
+def test_period_mode_unit_resolution_is_psa():
+    """One sub-step per cycle and no timing spread: every period is 1, every
+    p-bit fires at every step with r from counter t -- plain pSA."""
+    n, u, v, j, h = _random_ising(60, 200, 90)
+    i0 = oracle.schedule(25, 0.02, 1.5)
+    lam, off, _ = oracle.variability(n, 12, 0.2, 0.3, 0.0, 1.0)
+    per = oracle.periods(n, 12, 0.0, 1)
+    assert np.all(per == 1)
+    thr = np.full(n, ONE24, np.uint32)
+    a = oracle.anneal(n, u, v, j, h, i0, lam, off, thr, 12, 0, 6)
+    b = oracle.anneal_period(n, u, v, j, h, i0, lam, off, per, 1, 12, 0, 6)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_period_draw():
+    """period_i = max(1, rint(t_res (1 + sigma_nu z_i))) with the same normal
+    z_i as the update probability of the variability draw; sigma 0 gives
+    t_res exactly; with a wide spread the period is 1 (rounded or clipped)
+    with probability Phi(-0.425)."""
+    n = 20000
+    np.testing.assert_array_equal(oracle.periods(n, 4, 0.0, 10), np.full(n, 10, np.uint32))
+    per = oracle.periods(n, 4, 0.05, 10)
+    _, _, thr = oracle.variability(n, 4, 0.0, 0.0, 0.05, 0.5)
+    z = (thr.astype(np.float64) / ONE24 - 0.5) / 0.05          # no clipping at 0.5 +- 10 sigma
+    expect = np.maximum(1, np.rint(10 * (1 + 0.05 * z)))
+    near_tie = np.abs(10 * (1 + 0.05 * z) - np.floor(10 * (1 + 0.05 * z)) - 0.5) < 1e-5
+    assert np.all((per == expect) | near_tie)
+    wide = oracle.periods(n, 5, 2.0, 10)
+    frac = np.mean(wide == 1)
+    from math import erf, sqrt
+    p1 = 0.5 * (1 + erf(-0.425 / sqrt(2)))     # period 1 <=> 10 (1 + 2 z) < 1.5
+    assert abs(frac - p1) < 5 * np.sqrt(p1 * (1 - p1) / n)
+
+
+def test_period_mode_isolated_marginals():
+    """No couplings: at the end of cycle c a p-bit's output was drawn at its
+    last firing sub-step tau = P floor(((c+1) t_res - 1) / P), with the I0 of
+    that sub-step's cycle, so P(+1) = q(I0[tau // t_res]).  A wrong modulus,
+    sub-step-to-cycle map or I0 index fails it."""
+    t_res, S, T = 10, 6, 6000
+    per = np.array([1, 3, 7, 10, 13, 17, 25, 40, 59, 10, 11, 9], np.uint32)
+    n = per.size
+    h = np.array([2, -1, 1, 3, -2, 1, 2, -3, 1, 0, 2, -1], np.int32)
+    lam = np.ones(n, np.float32)
+    off = np.array([0, 0, 0, 0.25, 0, 0, -0.25, 0, 0, 0.5, 0, 0], np.float32)
+    i0 = oracle.schedule(S, 0.05, 2.0)
+    e = np.zeros(0, np.int32)
+    s = oracle.init_spins(n, 21, 0, T)
+    for c in range(S):
+        s = oracle.run_period(n, e, e, e, h, i0, lam, off, per, t_res, 21, 0, T, c, c + 1, s)
+        last = per * (((c + 1) * t_res - 1) // per)
+        q = _p_plus(i0[last // t_res], lam, h, off)
+        f = (s == 1).mean(axis=0)
+        tol = 5 * np.sqrt(np.maximum(q * (1 - q), 1e-4) / T)
+        assert np.all(np.abs(f - q) <= tol), (c, f, q)
+
+
+def test_period_mode_deterministic_limit_matches_substep_recurrence():
+    """Saturated I0: at every sub-step the p-bits whose period divides it take
+    sign(L + delta) of the spins of that sub-step (synchronously), the others
+    hold -- written here with numpy on a small coupled graph."""
+    n, u, v, j, h = _random_ising(16, 30, 91, jmax=2)
+    t_res, S, T = 10, 5, 8
+    rng = np.random.default_rng(91)
+    per = rng.integers(1, 25, size=n).astype(np.uint32)
+    i0 = np.full(S, 1e30, np.float32)
+    lam = np.ones(n, np.float32)
+    off = np.where(np.arange(n) % 2 == 0, 0.5, -0.5).astype(np.float32)
+    Jd = _dense(n, u, v, j)
+    s = oracle.init_spins(n, 22, 0, T)
+    m = s.astype(np.int64)
+    for c in range(S):
+        s = oracle.run_period(n, u, v, j, h, i0, lam, off, per, t_res, 22, 0, T, c, c + 1, s)
+        for sub in range(t_res):
+            tau = c * t_res + sub
+            L = m @ Jd + h
+            fire = (tau % per) == 0
+            m = np.where(fire, np.where(L + off > 0, 1, -1), m)
+        np.testing.assert_array_equal(s, m, err_msg=f"cycle {c}")
+
+
+def test_period_mode_cycles_compose():
+    n, u, v, j, h = _random_ising(40, 120, 92)
+    S, T, k = 9, 4, 4
+    i0 = oracle.schedule(S, 0.02, 1.5)
+    lam, off, _ = oracle.variability(n, 13, 0.1, 0.1, 0.0, 1.0)
+    per = oracle.periods(n, 13, 0.2, 10)
+    s0 = oracle.init_spins(n, 13, 0, T)
+    full = oracle.run_period(n, u, v, j, h, i0, lam, off, per, 10, 13, 0, T, 0, S, s0)
+    s1 = oracle.run_period(n, u, v, j, h, i0, lam, off, per, 10, 13, 0, T, 0, k, s0)
+    s2 = oracle.run_period(n, u, v, j, h, i0, lam, off, per, 10, 13, 0, T, k, S, s1)
+    np.testing.assert_array_equal(full, s2)
+
+
 def _two_spin_transition(i0, J, h, lam, off):
     states = [(1, 1), (1, -1), (-1, 1), (-1, -1)]
     P = np.zeros((4, 4))
