@@ -49,6 +49,7 @@ OPS_DECIDE = 2         # compare with r, select
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 OPS_STALL = 3  # shift-compare of the stall word, select / memory op of the held input
 OPS_MEAN = 10  # window mean: convert, correctly rounded divide
+OPS_PERIOD = 6  # period test: convert, reciprocal, multiply, truncate, multiply-subtract, compare
 MFMA_I8_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak, TOP/s
 HBM_PEAK_GBS = 8000.0
 
@@ -66,7 +67,7 @@ def ops_per_update(mean_degree: float, timing: bool, algorithm: str = "psa",
             + OPS_PREACT + OPS_TANH + OPS_DECIDE + extra)
 
 
-def cpu_baseline(spec, budget_s: float = 15.0, stall24=None, window=None):
+def cpu_baseline(spec, budget_s: float = 15.0, stall24=None, window=None, t_res=None):
     """Time the oracle on a bounded sample: the first `k` trials over the
     full schedule, k chosen so the single-thread work is about budget_s.
     stall24 / window: time the SpSA / TApSA oracle instead."""
@@ -82,7 +83,11 @@ def cpu_baseline(spec, budget_s: float = 15.0, stall24=None, window=None):
     # calibrate: one trial, a few steps
     cal_steps = max(1, min(S, 50))
     t0 = time.perf_counter()
-    if window is not None:
+    per = oracle.periods(n, spec["seed"], spec["sigma_nu"], t_res) if t_res else None
+    if t_res:
+        oracle.run_period(n, u, v, -w, None, i0, lam, dlt, per, t_res, spec["seed"], 0, 1, 0,
+                          cal_steps, oracle.init_spins(n, spec["seed"], 0, 1))
+    elif window is not None:
         oracle.run_tapsa(n, u, v, -w, None, i0, lam, dlt, thr, window, spec["seed"], 0, 1, 0,
                          cal_steps, oracle.init_spins(n, spec["seed"], 0, 1))
     elif stall24 is None:
@@ -99,7 +104,11 @@ def cpu_baseline(spec, budget_s: float = 15.0, stall24=None, window=None):
     parts = [(int(a), int(b)) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
     t0 = time.perf_counter()
     with ThreadPoolExecutor(len(parts)) as ex:
-        if window is not None:
+        if t_res:
+            list(ex.map(lambda ab: oracle.anneal_period(n, u, v, -w, None, i0, lam, dlt, per,
+                                                        t_res, spec["seed"], ab[0], ab[1]),
+                        parts))
+        elif window is not None:
             list(ex.map(lambda ab: oracle.anneal_tapsa(n, u, v, -w, None, i0, lam, dlt, thr,
                                                        window, spec["seed"], ab[0], ab[1]),
                         parts))
@@ -137,6 +146,9 @@ def main():
                          "time-averaged p-bits, Eq. 4)")
     ap.add_argument("--p-stall", type=float, default=0.5, help="SpSA stall probability")
     ap.add_argument("--window", type=int, default=4, help="TApSA window (alpha)")
+    ap.add_argument("--t-res", type=int, default=0,
+                    help="c1-c3: period-mode timing with this many sub-steps per cycle "
+                         "(0 = update-probability timing)")
     ap.add_argument("--path", default="auto", choices=["auto", "csr", "dense"],
                     help="c1-c3: field path")
     ap.add_argument("--block", type=int, default=0)
@@ -186,7 +198,7 @@ def main():
                   p_mean=spec["p_mean"], block=args.block, trials_per_group=args.tpw,
                   lanes_per_task=args.lpt, path={"auto": psa.PSA_PATH_AUTO, "csr": psa.PSA_PATH_CSR,
                                                  "dense": psa.PSA_PATH_DENSE}[args.path],
-                  algorithm=alg, p_stall=args.p_stall, window=args.window)
+                  algorithm=alg, p_stall=args.p_stall, window=args.window, t_res=args.t_res)
     E = torch.empty(T, dtype=torch.int64, device="cuda")
     C = torch.empty(T, dtype=torch.int64, device="cuda")
 
@@ -217,6 +229,12 @@ def main():
     timing = spec["sigma_nu"] > 0 or spec["p_mean"] < 1.0
     mean_deg = info["nnz"] / n
     opu = ops_per_update(mean_deg, timing, args.algorithm, args.window)
+    if args.t_res > 0:
+        # period mode: per cycle and p-bit, t_res period checks plus the
+        # expected number of firings (t_res / period) of an ungated update
+        per = psa.periods_draw(n, spec["seed"], spec["sigma_nu"], args.t_res)
+        fires = float(np.mean(args.t_res / per.astype(np.float64)))
+        opu = args.t_res * OPS_PERIOD + fires * ops_per_update(mean_deg, False)
     achieved = opu * updates / (kernel_ms * 1e-3) / 1e12
     line = {
         "metric": "p-bit updates/s (n x trials x steps / s), 1 GPU",
@@ -240,6 +258,7 @@ def main():
             "updates_per_anneal": updates,
             "algorithm": args.algorithm, "p_stall": args.p_stall if spsa else None,
             "window": args.window if args.algorithm == "tapsa" else None,
+            "t_res": args.t_res or None,
             "path": "dense" if job.dense else "csr",
         },
         "roofline": {
@@ -257,7 +276,8 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(
             spec, stall24=int(args.p_stall * 2 ** 24) if spsa else None,
-            window=args.window if args.algorithm == "tapsa" else None)
+            window=args.window if args.algorithm == "tapsa" else None,
+            t_res=args.t_res or None)
     print(json.dumps(line), flush=True)
     job.close()
     g.close()

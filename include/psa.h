@@ -177,6 +177,13 @@ psa_status psa_variability_draw(int32_t n, uint64_t seed, double sigma_lambda,
                                 double p_mean, float *lambda_out,
                                 float *delta_out, uint32_t *thr24_out);
 
+/* Integer timing periods of the period mode: period_i = max(1,
+ * rint(t_res (1 + sigma_nu z3))) with the same standard normal z3 as the
+ * update probability of psa_variability_draw.  EINVAL on t_res < 1 or a
+ * negative sigma. */
+psa_status psa_periods_draw(int32_t n, uint64_t seed, double sigma_nu, int32_t t_res,
+                            uint32_t *period_out);
+
 /* ------------------------------------------------------------------ */
 /* Runs                                                                  */
 /* ------------------------------------------------------------------ */
@@ -211,7 +218,21 @@ typedef struct psa_run_desc {
     uint32_t algorithm; /* PSA_ALG_PSA, PSA_ALG_SPSA or PSA_ALG_TAPSA */
     double p_stall;     /* SpSA: probability that an input is held (0..1) */
     int32_t window;     /* TApSA: steps averaged, alpha (1..64) */
+    int32_t t_res;      /* 0: timing as an update probability; >= 1: timing
+                           as integer periods of t_res sub-steps per cycle */
+    const uint32_t *period; /* period mode, optional [n] periods (>= 1) */
 } psa_run_desc;
+
+/* Timing modes of the variability model (Eq. 6, nu_i):
+ *   t_res = 0 (default): probability mode -- each step a p-bit fires with its
+ *            probability thr24_i / 2^24 (gate word), else holds its output.
+ *   t_res >= 1: period mode, the listing's count mod nu[i] gate -- a cycle
+ *            (one step of the schedule) has t_res sub-steps tau = t t_res + s;
+ *            at sub-step tau every p-bit whose period divides tau updates
+ *            (synchronously, I0 of cycle t, r from Philox counter
+ *            (tau, i/4, k, 1)); periods are max(1, rint(t_res (1 + nu_i))),
+ *            nu_i ~ N(0, sigma_nu^2) (psa_periods_draw), unless given.
+ *            Plain pSA only; steps * t_res must stay below 2^22. */
 
 /* Update rule (psa_run_desc.algorithm).
  *   PSA_ALG_PSA   plain pSA (Eq. 3): every step forms the input of each

@@ -302,6 +302,11 @@ psa_status psa_schedule_fill(int32_t steps, double i0_min, double i0_max, float 
     return psa::fill_schedule(steps, i0_min, i0_max, i0_out);
 }
 
+psa_status psa_periods_draw(int32_t n, uint64_t seed, double sigma_nu, int32_t t_res,
+                            uint32_t *period_out) {
+    return psa::draw_periods(n, seed, sigma_nu, t_res, period_out);
+}
+
 psa_status psa_variability_draw(int32_t n, uint64_t seed, double sigma_lambda,
                                 double sigma_delta, double sigma_nu, double p_mean,
                                 float *lambda_out, float *delta_out, uint32_t *thr24_out) {
@@ -365,6 +370,15 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
         set_error("psa_job_create: window must be in [1, 64]");
         return PSA_EINVAL;
     }
+    if (desc->t_res < 0 ||
+        (desc->t_res > 0 && static_cast<int64_t>(desc->steps) * desc->t_res >= (int64_t{1} << 22))) {
+        set_error("psa_job_create: t_res must be >= 0 with steps * t_res < 2^22");
+        return PSA_EINVAL;
+    }
+    if (desc->t_res > 0 && desc->algorithm != PSA_ALG_PSA) {
+        set_error("psa_job_create: period-mode timing is built for plain pSA only");
+        return PSA_EUNSUPPORTED;
+    }
     if (desc->algorithm == PSA_ALG_SPSA && !(desc->p_stall >= 0.0 && desc->p_stall <= 1.0)) {
         set_error("psa_job_create: p_stall must be in [0, 1]");
         return PSA_EINVAL;
@@ -410,6 +424,20 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
             set_error("psa_job_create: lambda/delta must be finite and thr24 <= 2^24");
             return PSA_EINVAL;
         }
+    }
+    if (desc->t_res > 0) {
+        // period mode: the per-p-bit timing array holds integer periods
+        if (desc->period) {
+            for (int32_t i = 0; i < n; ++i) thr[i] = desc->period[i];
+        } else {
+            psa_status st = psa::draw_periods(n, desc->seed, desc->sigma_nu, desc->t_res, thr.data());
+            if (st != PSA_OK) return st;
+        }
+        for (int32_t i = 0; i < n; ++i)
+            if (thr[i] < 1u) {
+                set_error("psa_job_create: periods must be >= 1");
+                return PSA_EINVAL;
+            }
     }
     PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     std::unique_ptr<psa_job, void (*)(psa_job *)> j(new psa_job(), job_free);
@@ -480,6 +508,7 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
         j->run.ring = j->d_ring;
         j->run.alpha = desc->window;
     }
+    j->run.t_res = desc->t_res;
     j->run.i0 = j->d_i0;
     j->run.lambda = j->d_lambda;
     j->run.delta = j->d_delta;

@@ -262,7 +262,20 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, ui
                                                    uint32_t k1, const InputState &st) {
     constexpr int P = 4 / LPT;
     constexpr bool kU = Enc<1, CSR>::kU;
-    const bool need_gate = any_gate(v.thr, m);
+    const int32_t base = 4 * m + static_cast<int32_t>(sub) * P;
+    if constexpr (ALG == kAlgPeriod) {
+        // t is the sub-step; p-bits whose period does not divide it hold
+        bool anyf = false;
+#pragma unroll
+        for (int j = 0; j < P; ++j) anyf |= period_fires(t, v.thr[base + j]);
+        if (!anyf) {
+            uint32_t out = 0u;
+#pragma unroll
+            for (int j = 0; j < P; ++j) out |= static_cast<uint32_t>(cur[base + j]) << (8 * j);
+            return out;
+        }
+    }
+    const bool need_gate = ALG != kAlgPeriod && any_gate(v.thr, m);
     uint32_t rw[P], gw[P], sw[P];
     task_words<LPT>(t, static_cast<uint32_t>(m), k, sub, need_gate, k0, k1, rw, gw);
 #pragma unroll
@@ -272,7 +285,6 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, ui
 #pragma unroll
         for (int j = 0; j < P; ++j) sw[j] = word_of(b, sub * P + j);
     }
-    const int32_t base = 4 * m + static_cast<int32_t>(sub) * P;
     int32_t L[P];
     if constexpr (CSR == kCsrUnit) {
         if constexpr (P == 4) {
@@ -292,7 +304,7 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, ui
         const int32_t i = base + j;
         const uint32_t old = cur[i];
         const uint32_t th = v.thr[i];
-        const bool fire = th >= kGateOne || fires(gw[j], th);
+        const bool fire = ALG == kAlgPeriod ? period_fires(t, th) : (th >= kGateOne || fires(gw[j], th));
         const float x = input_of<ALG>(i0t * v.lam[i], v.dlt[i], L[j], st, i, k, t, sw[j]);
         const bool up = goes_up(x, rw[j]);
         const uint32_t nb = kU ? (up ? 1u : 0u) : (up ? 0x01u : 0xFFu);
@@ -318,6 +330,19 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
         const int32_t i = 4 * m + p;
         word[p] = cur[i];
         th[p] = v.thr[i];
+    }
+    if constexpr (ALG == kAlgPeriod) {
+        // t is the sub-step; p-bits whose period does not divide it hold
+        if (!(period_fires(t, th[0]) | period_fires(t, th[1]) | period_fires(t, th[2]) |
+              period_fires(t, th[3]))) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) nxt[4 * m + p] = word[p];
+            return;
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int32_t i = 4 * m + p;
         a[p] = i0t * v.lam[i];
         d[p] = v.dlt[i];
         if constexpr (CSR == kCsrPack16)
@@ -325,8 +350,8 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
         else
             field_words<CSR>(v, i, cur, L[p]);
     }
-    const bool need_gate = (th[0] < kGateOne) | (th[1] < kGateOne) | (th[2] < kGateOne) |
-                           (th[3] < kGateOne);
+    const bool need_gate = ALG != kAlgPeriod && ((th[0] < kGateOne) | (th[1] < kGateOne) |
+                                                 (th[2] < kGateOne) | (th[3] < kGateOne));
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
         const uint32_t k = static_cast<uint32_t>(4 * q + kk);
@@ -350,7 +375,8 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
         }
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-            const bool fire = th[p] >= kGateOne || fires(gw[p], th[p]);
+            const bool fire = ALG == kAlgPeriod ? period_fires(t, th[p])
+                                                : (th[p] >= kGateOne || fires(gw[p], th[p]));
             const float x = input_of<ALG>(a[p], d[p], L[p][kk], st, 4 * m + p, k, t, sw[p]);
             const bool up = goes_up(x, rw[p]);
             const uint32_t nb = kU ? (up ? 1u : 0u) : (up ? 0x01u : 0xFFu);
@@ -478,16 +504,20 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
     // plain pSA carries no per-update test for the others
     auto sweep = [&](auto alg_tag) {
     constexpr int ALG = decltype(alg_tag)::value;
+    // period mode: t_res sub-steps per step (the counter of the random words
+    // and of the period gate is the sub-step); otherwise one
+    const int32_t nsub = ALG == kAlgPeriod ? a.t_res : 1;
     for (int32_t t = a.t_begin; t < a.t_end; ++t) {
         const float i0t = a.i0[t];
+        for (int32_t s = 0; s < nsub; ++s) {
+        const uint32_t tau = static_cast<uint32_t>(t) * static_cast<uint32_t>(nsub) + static_cast<uint32_t>(s);
         if constexpr (TPW == 1) {
             // the LPT lanes of a task share its slot, so they enter and leave together
             const uint32_t sub = threadIdx.x % LPT;
             for (int32_t slot = threadIdx.x / LPT; slot < tasks; slot += BLOCK / LPT) {
                 const int32_t m = v.order[slot];
                 const uint32_t b = task_one_trial<CSR, LPT, ALG, !CSR_LDS>(v, m, sub, static_cast<uint32_t>(q),
-                                                            static_cast<uint32_t>(t), i0t, cur,
-                                                            a.k0, a.k1, st);
+                                                            tau, i0t, cur, a.k0, a.k1, st);
                 constexpr int P = 4 / LPT;
                 const int32_t at = 4 * m + static_cast<int32_t>(sub) * P;
                 if constexpr (P == 4) {
@@ -506,7 +536,7 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
             }
         } else {
             for (int32_t slot = threadIdx.x; slot < tasks; slot += BLOCK)
-                task_four_trials<CSR, ALG, !CSR_LDS>(v, v.order[slot], q, static_cast<uint32_t>(t), i0t,
+                task_four_trials<CSR, ALG, !CSR_LDS>(v, v.order[slot], q, tau, i0t,
                                       reinterpret_cast<const uint32_t *>(cur),
                                       reinterpret_cast<uint32_t *>(nxt), a.k0, a.k1, st);
         }
@@ -514,9 +544,12 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
         unsigned char *tmp = cur;
         cur = nxt;
         nxt = tmp;
+        }
     }
     };
-    if (a.ring != nullptr)
+    if (a.t_res > 0)
+        sweep(std::integral_constant<int, kAlgPeriod>{});
+    else if (a.ring != nullptr)
         sweep(std::integral_constant<int, kAlgTapsa>{});
     else if (a.xs != nullptr)
         sweep(std::integral_constant<int, kAlgSpsa>{});
@@ -734,6 +767,7 @@ void fill_anneal_args(AnnealArgs *a, const DevGraph &g, const DevRun &run, const
     a->stall24 = run.stall24;
     a->ring = run.ring;
     a->alpha = run.alpha;
+    a->t_res = run.t_res;
 }
 
 bool plan_batch_item(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t lpt_req,

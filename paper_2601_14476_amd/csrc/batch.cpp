@@ -186,12 +186,13 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
         d.stall24 = job->run.stall24;
         d.ring = job->run.ring;
         d.alpha = job->run.alpha;
+        d.t_res = job->run.t_res;
         const int32_t e = g->dense_enc == kDenseT2 ? 1 : 0;
         by_enc[e].push_back(static_cast<int32_t>(table.size()));
         nb[e] = std::min(nb[e], job->plan.nb);
         table.push_back(d);
         live.push_back(job);
-        max_steps = std::max(max_steps, te - job->t);
+        max_steps = std::max(max_steps, (te - job->t) * std::max(job->run.t_res, 1));
     }
     if (live.empty()) return PSA_OK;
     std::vector<int4> work, part;
@@ -239,7 +240,7 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
     for (size_t j = 0; j < live.size(); ++j) {
         psa_job *job = live[j];
         const psa::DenseJob &d = table[j];
-        const int8_t *fin = ((d.t_end - d.t) & 1) ? d.m1 : d.m0;
+        const int8_t *fin = (((d.t_end - d.t) * std::max(d.t_res, 1)) & 1) ? d.m1 : d.m0;
         PSA_HIP(psa::launch_from_dense(ctx->stream2, job->g->info.n, job->run.t4, job->g->np, fin,
                                        job->d_spins),
                 "dense layout");

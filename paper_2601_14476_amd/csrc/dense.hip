@@ -94,12 +94,18 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
     const int4 w = work[blockIdx.x];  // (job, row group, trial tile, -); job < 0: empty slot
     if (w.x < 0) return;
     const DenseJob &jb = jobs[w.x];
-    const int32_t t = jb.t + t_off;
-    if (t >= jb.t_end) return;
+    // launch t_off advances sub-step t_off of this run's sequence: one
+    // sub-step per step, or t_res of them in period mode; tau counts
+    // sub-steps from the start of the anneal, t is the step (cycle) of tau
+    const int32_t u = jb.t_res > 0 ? jb.t_res : 1;
+    if (t_off >= (jb.t_end - jb.t) * u) return;
+    const uint32_t tau = static_cast<uint32_t>(jb.t * u + t_off);
+    const int32_t t = static_cast<int32_t>(tau / static_cast<uint32_t>(u));
+    const bool period_mode = jb.t_res > 0;
     const int32_t np = jb.np;
     const int32_t trial0 = w.z * kTrials;
-    const int8_t *__restrict__ cur = ((t - jb.t) & 1) ? jb.m1 : jb.m0;
-    int8_t *__restrict__ nxt = ((t - jb.t) & 1) ? jb.m0 : jb.m1;
+    const int8_t *__restrict__ cur = (t_off & 1) ? jb.m1 : jb.m0;
+    int8_t *__restrict__ nxt = (t_off & 1) ? jb.m0 : jb.m1;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int lr = lane & 15;
@@ -229,20 +235,21 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
         const uint32_t tv[4] = {th.x, th.y, th.z, th.w};
         const float av[4] = {i0t * lm.x, i0t * lm.y, i0t * lm.z, i0t * lm.w};
         const float dv[4] = {dl.x, dl.y, dl.z, dl.w};
-        const bool need_gate = (tv[0] < kGateOne) | (tv[1] < kGateOne) | (tv[2] < kGateOne) |
-                               (tv[3] < kGateOne);
+        const bool need_gate = !period_mode && ((tv[0] < kGateOne) | (tv[1] < kGateOne) |
+                                                (tv[2] < kGateOne) | (tv[3] < kGateOne));
         uint32_t old = 0u;
         uint32_t gw[4] = {0u, 0u, 0u, 0u};
-        if (need_gate) {
+        if (need_gate || period_mode)  // p-bits that do not fire keep these
             old = *reinterpret_cast<const uint32_t *>(cur + static_cast<size_t>(k) * np + i0);
-            const Words4 g = philox4x32_10(static_cast<uint32_t>(t), static_cast<uint32_t>(m),
+        if (need_gate) {
+            const Words4 g = philox4x32_10(tau, static_cast<uint32_t>(m),
                                            static_cast<uint32_t>(k), kTagGate, jb.k0, jb.k1);
             gw[0] = g.x;
             gw[1] = g.y;
             gw[2] = g.z;
             gw[3] = g.w;
         }
-        const Words4 r = philox4x32_10(static_cast<uint32_t>(t), static_cast<uint32_t>(m),
+        const Words4 r = philox4x32_10(tau, static_cast<uint32_t>(m),
                                        static_cast<uint32_t>(k), kTagR, jb.k0, jb.k1);
         const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
         uint32_t sw[4] = {0u, 0u, 0u, 0u};
@@ -261,7 +268,8 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
             const float x = input_any(av[p], dv[p], L, sv, i0 + p, static_cast<uint32_t>(k),
                                       static_cast<uint32_t>(t), sw[p]);
             const bool up = tanh_f32(x) > r_of(rw[p]);
-            const bool fire = tv[p] >= kGateOne || fires(gw[p], tv[p]);
+            const bool fire = period_mode ? period_fires(tau, tv[p])
+                                          : (tv[p] >= kGateOne || fires(gw[p], tv[p]));
             const uint32_t ob = (old >> (8 * p)) & 0xFFu;
             out |= (fire ? (up ? 0x01u : 0xFFu) : ob) << (8 * p);
         }

@@ -109,7 +109,21 @@ struct InputState {
     int32_t n4;
 };
 
-enum : int { kAlgPsa = 0, kAlgSpsa = 1, kAlgTapsa = 2 };
+// Input / timing variants of the sweep: plain pSA, SpSA, TApSA, and plain pSA
+// with period-mode timing.
+enum : int { kAlgPsa = 0, kAlgSpsa = 1, kAlgTapsa = 2, kAlgPeriod = 3 };
+
+// Period mode: does a p-bit of period P (0 = never) fire at sub-step tau?
+// tau < 2^22, so the quotient from a float reciprocal is within one of
+// tau / P and one correction each way gives the exact remainder.
+__device__ __forceinline__ bool period_fires(uint32_t tau, uint32_t P) {
+    if (P == 0u) return false;
+    const float fq = static_cast<float>(tau) * __builtin_amdgcn_rcpf(static_cast<float>(P));
+    int32_t r = static_cast<int32_t>(tau) - static_cast<int32_t>(fq) * static_cast<int32_t>(P);
+    if (r < 0) r += static_cast<int32_t>(P);
+    if (r >= static_cast<int32_t>(P)) r -= static_cast<int32_t>(P);
+    return r == 0;
+}
 
 // Input stage of p-bit i, trial k at step t, on the field L of step t; a =
 // I0 lambda_i, d = delta_i.

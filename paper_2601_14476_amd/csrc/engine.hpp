@@ -79,6 +79,7 @@ struct DevRun {
     uint32_t stall24 = 0;                 // SpSA stall threshold
     int32_t *ring = nullptr;              // TApSA windows [t4/4][n4][alpha][4], else nullptr
     int32_t alpha = 1;                    // TApSA window
+    int32_t t_res = 0;                    // period mode: sub-steps per cycle (thr24 holds periods)
 };
 
 // How the persistent anneal kernel is launched for one run.
@@ -119,6 +120,8 @@ struct AnnealArgs {
     // TApSA (Eq. 4): field windows [t4/4][n4][alpha][4] (nullptr = off)
     int32_t *ring;
     int32_t alpha;
+    // period mode (t_res >= 1): thr holds integer periods, t_res sub-steps per step
+    int32_t t_res;
 };
 
 // Kernel variants a batched launch can mix (one trial per workgroup).
@@ -167,6 +170,7 @@ struct DenseJob {
     uint32_t stall24;  // SpSA stall threshold
     int32_t *ring;     // TApSA windows [t4/4][n4][alpha][4], else nullptr
     int32_t alpha;     // TApSA window
+    int32_t t_res;     // period mode: sub-steps per step (thr holds periods); 0 otherwise
 };
 
 // Choose tpw / lanes per task / CSR placement / block for a run
@@ -224,6 +228,9 @@ psa_status fill_schedule(int32_t steps, double i0_min, double i0_max, float *out
 psa_status draw_variability(int32_t n, uint64_t seed, double sigma_lambda,
                             double sigma_delta, double sigma_nu, double p_mean,
                             float *lambda, float *delta, uint32_t *thr24);
+// Integer timing periods of the period mode (psa_periods_draw).
+psa_status draw_periods(int32_t n, uint64_t seed, double sigma_nu, int32_t t_res,
+                        uint32_t *period);
 
 // Graph ingestion (graph.cpp): CPU phase, then device upload.
 struct HostGraph {

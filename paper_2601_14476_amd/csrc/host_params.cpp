@@ -91,4 +91,23 @@ psa_status draw_variability(int32_t n, uint64_t seed, double sigma_lambda, doubl
     return PSA_OK;
 }
 
+psa_status draw_periods(int32_t n, uint64_t seed, double sigma_nu, int32_t t_res,
+                        uint32_t *period) {
+    if (n < 1 || !period || t_res < 1 || !(sigma_nu >= 0.0)) {
+        set_error("periods: need n >= 1, t_res >= 1, sigma_nu >= 0 and an output");
+        return PSA_EINVAL;
+    }
+    const uint32_t k0 = static_cast<uint32_t>(seed);
+    const uint32_t k1 = static_cast<uint32_t>(seed >> 32);
+    for (int32_t i = 0; i < n; ++i) {
+        const uint32_t cb[4] = {0u, static_cast<uint32_t>(i), 1u, kTagVarHost};
+        uint32_t b[4];
+        philox4x32_10_host(cb, k0, k1, b);
+        const double nu = sigma_nu * normal_from(b[0], b[1]);
+        const double p = rint(static_cast<double>(t_res) * (1.0 + nu));
+        period[i] = p < 1.0 ? 1u : static_cast<uint32_t>(p);
+    }
+    return PSA_OK;
+}
+
 }  // namespace psa

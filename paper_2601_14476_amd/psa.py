@@ -57,7 +57,8 @@ class psa_run_desc(ctypes.Structure):
                 ("sigma_nu", _f64), ("p_mean", _f64), ("lambda_", _P),
                 ("delta", _P), ("thr24", _P), ("block", _i32),
                 ("trials_per_group", _i32), ("lanes_per_task", _i32), ("flags", _u32),
-                ("algorithm", _u32), ("p_stall", _f64), ("window", _i32)]
+                ("algorithm", _u32), ("p_stall", _f64), ("window", _i32), ("t_res", _i32),
+                ("period", _P)]
 
 
 class psa_tune_result(ctypes.Structure):
@@ -113,6 +114,7 @@ _SIGNATURES = [
     ("psa_graph_destroy", None, [_P]),
     ("psa_schedule_paper", _i32, [_P, ctypes.POINTER(_f64), ctypes.POINTER(_f64)]),
     ("psa_schedule_fill", _i32, [_i32, _f64, _f64, _P]),
+    ("psa_periods_draw", _i32, [_i32, _u64, _f64, _i32, _P]),
     ("psa_variability_draw", _i32, [_i32, _u64, _f64, _f64, _f64, _f64, _P, _P, _P]),
     ("psa_run_desc_default", None, [ctypes.POINTER(psa_run_desc)]),
     ("psa_job_create", _i32, [_P, _P, ctypes.POINTER(psa_run_desc), ctypes.POINTER(_P)]),
@@ -324,6 +326,14 @@ def schedule_fill(steps, i0_min, i0_max):
     return out[:steps]
 
 
+def periods_draw(n, seed, sigma_nu, t_res):
+    """Integer timing periods of the period mode (psa_periods_draw)."""
+    out = np.zeros(n, np.uint32)
+    _check(_lib.psa_periods_draw(int(n), int(seed), float(sigma_nu), int(t_res), _ptr(out)),
+           "psa_periods_draw")
+    return out
+
+
 def variability_draw(n, seed, sigma_lambda=0.0, sigma_delta=0.0, sigma_nu=0.0, p_mean=1.0):
     lam = np.zeros(n, np.float32)
     dlt = np.zeros(n, np.float32)
@@ -337,7 +347,7 @@ def make_desc(steps, trials, seed=0, i0=None, i0_min=None, i0_max=None,
               sigma_lambda=0.0, sigma_delta=0.0, sigma_nu=0.0, p_mean=1.0,
               lam=None, delta=None, thr24=None, block=0, trials_per_group=0,
               lanes_per_task=0, path=PSA_PATH_AUTO, tune=False, algorithm=PSA_ALG_PSA,
-              p_stall=0.5, window=4):
+              p_stall=0.5, window=4, t_res=0, period=None):
     """Build a psa_run_desc; returns (desc, keepalive arrays).  tune=True sets
     PSA_TUNE (path and launch shape from the context's tuning cache)."""
     d = psa_run_desc()
@@ -365,6 +375,11 @@ def make_desc(steps, trials, seed=0, i0=None, i0_min=None, i0_max=None,
     d.algorithm = int(algorithm)
     d.p_stall = float(p_stall)
     d.window = int(window)
+    d.t_res = int(t_res)
+    if period is not None:
+        a = np.ascontiguousarray(period, dtype=np.uint32)
+        keep.append(a)
+        d.period = _ptr(a)
     return d, keep
 
 

@@ -68,6 +68,15 @@ def test_variability_draw_matches_oracle(psa, sig):
             np.testing.assert_array_equal(a, b)
 
 
+@pytest.mark.parametrize("sig,t_res", [(0.0, 10), (0.1, 10), (0.3, 7), (2.0, 10), (0.2, 1)])
+def test_periods_draw_matches_oracle(psa, sig, t_res):
+    for seed in (0, 5, 2**63 + 7):
+        np.testing.assert_array_equal(psa.periods_draw(5000, seed, sig, t_res),
+                                      oracle.periods(5000, seed, sig, t_res))
+    with pytest.raises(psa.PsaError):
+        psa.periods_draw(10, 0, sig, 0)
+
+
 def test_variability_rejects_bad_parameters(psa):
     with pytest.raises(psa.PsaError):
         psa.variability_draw(10, 0, -0.1, 0, 0, 1)

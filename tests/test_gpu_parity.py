@@ -543,3 +543,68 @@ def test_tapsa_edge_cases(psa, ctx):
     for bad in (0, 65):
         with pytest.raises(psa.PsaError):
             psa.Job(ctx, g, 30, 7, 4, algorithm=psa.PSA_ALG_TAPSA, window=bad)
+
+
+@pytest.mark.parametrize("kind,tpw,lpt,path,t_res", [
+    ("unit", 1, 2, "csr", 10), ("unit", 1, 4, "csr", 10), ("unit", 1, 1, "csr", 7),
+    ("unit", 4, 0, "csr", 10), ("int", 1, 2, "csr", 10), ("int", 4, 0, "csr", 3),
+    ("unit", 0, 0, "dense", 10), ("int", 0, 0, "dense", 5)])
+def test_period_mode_matches_oracle(psa, ctx, kind, tpw, lpt, path, t_res):
+    """Period-mode timing (the listing's count mod nu gate at t_res sub-steps
+    per cycle): spins after every chunk of cycles equal the oracle's on every
+    path and launch shape."""
+    if kind == "unit":
+        n, u, v, w = inputs.gnm(333, 1400, 97)
+        j, h = -w, None
+    else:
+        n, u, v, j, h = _random_ising(301, 1300, 98, jmax=4)
+    g = psa.Graph.from_edges(ctx, n, u, v, j, h=h, maxcut=False)
+    S, T = 12, 11
+    i0 = oracle.schedule(S, 0.02, 0.9)
+    lam, dl, _ = oracle.variability(n, 19, 0.1, 0.2, 0.3, 1.0)
+    per = oracle.periods(n, 19, 0.3, t_res)
+    job = psa.Job(ctx, g, S, T, seed=19, i0=i0, sigma_lambda=0.1, sigma_delta=0.2, sigma_nu=0.3,
+                  trials_per_group=tpw, lanes_per_task=lpt, t_res=t_res,
+                  path=psa.PSA_PATH_DENSE if path == "dense" else psa.PSA_PATH_CSR)
+    ref = oracle.init_spins(n, 19, 0, T)
+    t = 0
+    for k in (1, 4, 7):
+        job.step(k)
+        ref = oracle.run_period(n, u, v, j, h, i0, lam, dl, per, t_res, 19, 0, T, t, t + k, ref)
+        t += k
+        np.testing.assert_array_equal(job.read_spins(), ref, err_msg=f"after cycle {t}")
+    E, C = job.energy_cut()
+    rE, rC = oracle.energy_cut(n, u, v, j, h, ref)
+    np.testing.assert_array_equal(E, rE)
+    np.testing.assert_array_equal(C, rC)
+
+
+def test_period_mode_edge_cases(psa, ctx):
+    """t_res 1 with no timing spread is pSA; explicit periods are used as
+    given; period mode with SpSA, zero periods and too many sub-steps are
+    refused; a period-mode job resumes from its spins (no other state)."""
+    n, u, v, w = inputs.gnm(200, 700, 99)
+    g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
+    a = psa.anneal(ctx, g, 30, 7, 4, sigma_lambda=0.1, sigma_delta=0.1)
+    b = psa.anneal(ctx, g, 30, 7, 4, sigma_lambda=0.1, sigma_delta=0.1, t_res=1)
+    np.testing.assert_array_equal(a[0], b[0])
+    per = np.arange(n, dtype=np.uint32) % 13 + 1
+    job = psa.Job(ctx, g, 20, 5, 6, t_res=10, period=per)
+    job.step(20)
+    i0, _, _ = oracle.schedule_paper(n, u, v, -w, 20)
+    lam, dl, _ = oracle.variability(n, 6, 0.0, 0.0, 0.0, 1.0)
+    ref = oracle.anneal_period(n, u, v, -w, None, i0, lam, dl, per, 10, 6, 0, 5)
+    np.testing.assert_array_equal(job.read_spins(), ref[0])
+    mid = psa.Job(ctx, g, 20, 5, 6, t_res=10, period=per)
+    mid.step(8)
+    resumed = psa.Job(ctx, g, 20, 5, 6, t_res=10, period=per)
+    resumed.write_spins(mid.read_spins(), 8)
+    resumed.step(12)
+    np.testing.assert_array_equal(resumed.read_spins(), ref[0])
+    with pytest.raises(psa.PsaError) as e:
+        psa.Job(ctx, g, 20, 5, 6, t_res=10, algorithm=psa.PSA_ALG_SPSA)
+    assert e.value.status == psa.PSA_EUNSUPPORTED
+    with pytest.raises(psa.PsaError):
+        psa.Job(ctx, g, 20, 5, 6, t_res=10, period=np.zeros(n, np.uint32))
+    with pytest.raises(psa.PsaError):
+        psa.Job(ctx, g, 1 << 20, 5, 6, t_res=10)
