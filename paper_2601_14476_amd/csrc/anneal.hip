@@ -66,13 +66,14 @@ struct Enc {
 // Field sums.
 // ---------------------------------------------------------------------------
 
-// One trial, +-1 bytes, general weights: L = h_i + sum_j J_ij m_j.
+// One trial, +-1 bytes, general weights: L = h + sum_j J_ij m_j over the
+// row's edges e0 .. e1-1.
 template <int CSR>
-__device__ __forceinline__ int32_t field_pm1(const Views &v, int32_t i, const int8_t *cur) {
-    int32_t L = v.h[i];
-    const int32_t e1 = v.row_ptr[i + 1];
+__device__ __forceinline__ int32_t field_pm1(const Views &v, int32_t e0, int32_t e1, int32_t h,
+                                             const int8_t *cur) {
+    int32_t L = h;
 #pragma unroll 2
-    for (int32_t e = v.row_ptr[i]; e < e1; ++e) {
+    for (int32_t e = e0; e < e1; ++e) {
         if constexpr (CSR == kCsrPack32) {
             const uint32_t w = v.pk32[e];
             L += (static_cast<int32_t>(w) >> 16) * static_cast<int32_t>(cur[w & 0xFFFFu]);
@@ -83,17 +84,18 @@ __device__ __forceinline__ int32_t field_pm1(const Views &v, int32_t i, const in
     return L;
 }
 
-// One trial, unit weights, mirrored 0/1 bytes: the rows of p-bits
-// base, base+1 (P = 2) or base (P = 1) walked as one contiguous edge range.
+// One trial, unit weights, mirrored 0/1 bytes: P = 2 rows (or one) with row
+// boundaries rp[0..P] and biases h[0..P-1], walked as one contiguous edge
+// range.
 template <int P, bool BLK>
-__device__ __forceinline__ void field_unit(const Views &v, int32_t base, const uint8_t *cur,
-                                           int32_t L[P]) {
-    const int32_t e0 = v.row_ptr[base];
+__device__ __forceinline__ void field_unit(const Views &v, const int32_t *rp, const int32_t *h,
+                                           const uint8_t *cur, int32_t L[P]) {
+    const int32_t e0 = rp[0];
     if constexpr (BLK) {
         // rows in global memory: aligned blocks of 8 entries (one 16-byte
         // load), entries outside the rows masked out
-        const int32_t split = v.row_ptr[base + 1];
-        const int32_t e2 = P == 2 ? v.row_ptr[base + 2] : split;
+        const int32_t split = rp[1];
+        const int32_t e2 = P == 2 ? rp[2] : split;
         int32_t acc0 = 0, acc1 = 0;
         for (int32_t eb = e0 & ~7; eb < e2; eb += 8) {
             const u32x4 qv = load_global_x4(v.ux16 + eb);
@@ -106,27 +108,27 @@ __device__ __forceinline__ void field_unit(const Views &v, int32_t base, const u
                 if constexpr (P == 2) acc1 += (e >= split && e < e2) ? x : 0;
             }
         }
-        L[0] = v.h[base] + 2 * acc0 - (split - e0);
-        if constexpr (P == 2) L[1] = v.h[base + 1] + 2 * acc1 - (e2 - split);
+        L[0] = h[0] + 2 * acc0 - (split - e0);
+        if constexpr (P == 2) L[1] = h[1] + 2 * acc1 - (e2 - split);
         return;
     }
     if constexpr (P == 1) {
-        const int32_t e1 = v.row_ptr[base + 1];
+        const int32_t e1 = rp[1];
         int32_t acc = 0;
 #pragma unroll 4
         for (int32_t e = e0; e < e1; ++e) acc += cur[v.ux16[e]];
-        L[0] = v.h[base] + 2 * acc - (e1 - e0);
+        L[0] = h[0] + 2 * acc - (e1 - e0);
     } else {
-        const int32_t split = v.row_ptr[base + 1];
-        const int32_t e2 = v.row_ptr[base + 2];
+        const int32_t split = rp[1];
+        const int32_t e2 = rp[2];
         int32_t acc = 0, acc0 = 0;
 #pragma unroll 4
         for (int32_t e = e0; e < e2; ++e) {
             acc += cur[v.ux16[e]];
             acc0 = (e == split - 1) ? acc : acc0;
         }
-        L[0] = v.h[base] + 2 * acc0 - (split - e0);
-        L[1] = v.h[base + 1] + 2 * (acc - acc0) - (e2 - split);
+        L[0] = h[0] + 2 * acc0 - (split - e0);
+        L[1] = h[1] + 2 * (acc - acc0) - (e2 - split);
     }
 }
 
@@ -252,22 +254,55 @@ __device__ __forceinline__ bool any_gate(const uint32_t *thr, int32_t m) {
 }
 
 // ---------------------------------------------------------------------------
-// One trial per workgroup: lane `sub` of task m updates its P p-bits and
-// returns their new bytes (in the LDS encoding) in the low 8P bits.
+// One trial per workgroup.  TaskConst holds what lane `sub` of task m reads
+// of the graph and factors for its P = 4/LPT p-bits base .. base+P-1: the same
+// at every step, so a lane that owns one task for the whole launch loads it
+// once and keeps it in registers.
 // ---------------------------------------------------------------------------
+template <int P>
+struct TaskConst {
+    int32_t m, base;
+    int32_t rp[P + 1];  // row_ptr[base .. base+P]
+    int32_t h[P];
+    float lam[P], dlt[P];
+    uint32_t thr[P];
+    bool need_gate;     // some p-bit of the task (all four) has a timing gate
+};
+
+template <int LPT>
+__device__ __forceinline__ TaskConst<4 / LPT> load_task(const Views &v, int32_t m, uint32_t sub) {
+    constexpr int P = 4 / LPT;
+    TaskConst<P> c;
+    c.m = m;
+    c.base = 4 * m + static_cast<int32_t>(sub) * P;
+#pragma unroll
+    for (int j = 0; j <= P; ++j) c.rp[j] = v.row_ptr[c.base + j];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        c.h[j] = v.h[c.base + j];
+        c.lam[j] = v.lam[c.base + j];
+        c.dlt[j] = v.dlt[c.base + j];
+        c.thr[j] = v.thr[c.base + j];
+    }
+    c.need_gate = any_gate(v.thr, m);
+    return c;
+}
+
+// Lane `sub` of task c.m updates its P p-bits at step t and returns their new
+// bytes (in the LDS encoding) in the low 8P bits.
 template <int CSR, int LPT, int ALG, bool BLK>
-__device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, uint32_t sub,
-                                                   uint32_t k, uint32_t t, float i0t,
+__device__ __forceinline__ uint32_t task_one_trial(const Views &v, const TaskConst<4 / LPT> &c,
+                                                   uint32_t sub, uint32_t k, uint32_t t, float i0t,
                                                    const unsigned char *cur, uint32_t k0,
                                                    uint32_t k1, const InputState &st) {
     constexpr int P = 4 / LPT;
     constexpr bool kU = Enc<1, CSR>::kU;
-    const int32_t base = 4 * m + static_cast<int32_t>(sub) * P;
+    const int32_t base = c.base;
     if constexpr (ALG == kAlgPeriod) {
         // t is the sub-step; p-bits whose period does not divide it hold
         bool anyf = false;
 #pragma unroll
-        for (int j = 0; j < P; ++j) anyf |= period_fires(t, v.thr[base + j]);
+        for (int j = 0; j < P; ++j) anyf |= period_fires(t, c.thr[j]);
         if (!anyf) {
             uint32_t out = 0u;
 #pragma unroll
@@ -275,37 +310,37 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, int32_t m, ui
             return out;
         }
     }
-    const bool need_gate = ALG != kAlgPeriod && any_gate(v.thr, m);
+    const bool need_gate = ALG != kAlgPeriod && c.need_gate;
     uint32_t rw[P], gw[P], sw[P];
-    task_words<LPT>(t, static_cast<uint32_t>(m), k, sub, need_gate, k0, k1, rw, gw);
+    task_words<LPT>(t, static_cast<uint32_t>(c.m), k, sub, need_gate, k0, k1, rw, gw);
 #pragma unroll
     for (int j = 0; j < P; ++j) sw[j] = 0u;
     if (ALG == kAlgSpsa && t > 0) {
-        const Words4 b = block_of(t, static_cast<uint32_t>(m), k, kTagStall, k0, k1);
+        const Words4 b = block_of(t, static_cast<uint32_t>(c.m), k, kTagStall, k0, k1);
 #pragma unroll
         for (int j = 0; j < P; ++j) sw[j] = word_of(b, sub * P + j);
     }
     int32_t L[P];
     if constexpr (CSR == kCsrUnit) {
         if constexpr (P == 4) {
-            field_unit<2, BLK>(v, base, cur, L);
-            field_unit<2, BLK>(v, base + 2, cur, L + 2);
+            field_unit<2, BLK>(v, c.rp, c.h, cur, L);
+            field_unit<2, BLK>(v, c.rp + 2, c.h + 2, cur, L + 2);
         } else {
-            field_unit<P, BLK>(v, base, cur, L);
+            field_unit<P, BLK>(v, c.rp, c.h, cur, L);
         }
     } else {
 #pragma unroll
         for (int j = 0; j < P; ++j)
-            L[j] = field_pm1<CSR>(v, base + j, reinterpret_cast<const int8_t *>(cur));
+            L[j] = field_pm1<CSR>(v, c.rp[j], c.rp[j + 1], c.h[j], reinterpret_cast<const int8_t *>(cur));
     }
     uint32_t out = 0u;
 #pragma unroll
     for (int j = 0; j < P; ++j) {
         const int32_t i = base + j;
         const uint32_t old = cur[i];
-        const uint32_t th = v.thr[i];
+        const uint32_t th = c.thr[j];
         const bool fire = ALG == kAlgPeriod ? period_fires(t, th) : (th >= kGateOne || fires(gw[j], th));
-        const float x = input_of<ALG>(i0t * v.lam[i], v.dlt[i], L[j], st, i, k, t, sw[j]);
+        const float x = input_of<ALG>(i0t * c.lam[j], c.dlt[j], L[j], st, i, k, t, sw[j]);
         const bool up = goes_up(x, rw[j]);
         const uint32_t nb = kU ? (up ? 1u : 0u) : (up ? 0x01u : 0xFFu);
         out |= (fire ? nb : old) << (8 * j);
@@ -500,6 +535,36 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
     unsigned char *cur = buf0;
     unsigned char *nxt = buf1;
     const InputState st{a.xs, a.stall24, a.ring, a.alpha, n4};
+
+    // One trial per workgroup: update the P p-bits of one task and store them
+    // (and the complemented copy) into the next buffer.
+    constexpr int P = 4 / LPT;
+    const uint32_t sub = threadIdx.x % LPT;
+    auto one_trial_step = [&](auto alg_tag, const TaskConst<P> &c, uint32_t tau, float i0t,
+                              const unsigned char *from, unsigned char *to)
+                              __attribute__((always_inline)) {
+        constexpr int ALG = decltype(alg_tag)::value;
+        const uint32_t b = task_one_trial<CSR, LPT, ALG, !CSR_LDS>(v, c, sub, static_cast<uint32_t>(q),
+                                                                   tau, i0t, from, a.k0, a.k1, st);
+        const int32_t at = c.base;
+        if constexpr (P == 4) {
+            *reinterpret_cast<uint32_t *>(to + at) = b;
+            if constexpr (E::kMirror) *reinterpret_cast<uint32_t *>(to + n4 + at) = b ^ 0x01010101u;
+        } else if constexpr (P == 2) {
+            *reinterpret_cast<uint16_t *>(to + at) = static_cast<uint16_t>(b);
+            if constexpr (E::kMirror)
+                *reinterpret_cast<uint16_t *>(to + n4 + at) = static_cast<uint16_t>(b ^ 0x0101u);
+        } else {
+            to[at] = static_cast<unsigned char>(b);
+            if constexpr (E::kMirror) to[n4 + at] = static_cast<unsigned char>(b ^ 1u);
+        }
+    };
+    // When every task has a slot of its own (tasks x LPT <= BLOCK), a lane
+    // keeps its task's constants in registers for the whole launch.
+    const bool resident = TPW == 1 && tasks * LPT <= BLOCK;
+    const bool owns = resident && static_cast<int32_t>(threadIdx.x) / LPT < tasks;
+    TaskConst<P> own{};
+    if (owns) own = load_task<LPT>(v, v.order[threadIdx.x / LPT], sub);
     // the step loop, instantiated per input stage (pSA, SpSA, TApSA) so that
     // plain pSA carries no per-update test for the others
     auto sweep = [&](auto alg_tag) {
@@ -512,27 +577,12 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
         for (int32_t s = 0; s < nsub; ++s) {
         const uint32_t tau = static_cast<uint32_t>(t) * static_cast<uint32_t>(nsub) + static_cast<uint32_t>(s);
         if constexpr (TPW == 1) {
-            // the LPT lanes of a task share its slot, so they enter and leave together
-            const uint32_t sub = threadIdx.x % LPT;
-            for (int32_t slot = threadIdx.x / LPT; slot < tasks; slot += BLOCK / LPT) {
-                const int32_t m = v.order[slot];
-                const uint32_t b = task_one_trial<CSR, LPT, ALG, !CSR_LDS>(v, m, sub, static_cast<uint32_t>(q),
-                                                            tau, i0t, cur, a.k0, a.k1, st);
-                constexpr int P = 4 / LPT;
-                const int32_t at = 4 * m + static_cast<int32_t>(sub) * P;
-                if constexpr (P == 4) {
-                    *reinterpret_cast<uint32_t *>(nxt + at) = b;
-                    if constexpr (E::kMirror)
-                        *reinterpret_cast<uint32_t *>(nxt + n4 + at) = b ^ 0x01010101u;
-                } else if constexpr (P == 2) {
-                    *reinterpret_cast<uint16_t *>(nxt + at) = static_cast<uint16_t>(b);
-                    if constexpr (E::kMirror)
-                        *reinterpret_cast<uint16_t *>(nxt + n4 + at) =
-                            static_cast<uint16_t>(b ^ 0x0101u);
-                } else {
-                    nxt[at] = static_cast<unsigned char>(b);
-                    if constexpr (E::kMirror) nxt[n4 + at] = static_cast<unsigned char>(b ^ 1u);
-                }
+            if (resident) {
+                if (owns) one_trial_step(alg_tag, own, tau, i0t, cur, nxt);
+            } else {
+                // the LPT lanes of a task share its slot, so they enter and leave together
+                for (int32_t slot = threadIdx.x / LPT; slot < tasks; slot += BLOCK / LPT)
+                    one_trial_step(alg_tag, load_task<LPT>(v, v.order[slot], sub), tau, i0t, cur, nxt);
             }
         } else {
             for (int32_t slot = threadIdx.x; slot < tasks; slot += BLOCK)
