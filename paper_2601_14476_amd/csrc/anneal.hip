@@ -132,6 +132,55 @@ __device__ __forceinline__ void field_unit(const Views &v, const int32_t *rp, co
     }
 }
 
+// Unit weights, one trial: the first kCacheEdges edge indices of a lane's
+// pair of rows, two 16-bit indices per register, kept across the steps of a
+// launch by a lane that owns its task throughout (entries past the rows hold
+// index 0, a valid byte that is masked out).
+constexpr int kCacheEdges = 16;
+struct EdgeCache {
+    uint32_t w[kCacheEdges / 2];
+};
+
+__device__ __forceinline__ EdgeCache load_edge_cache(const Views &v, int32_t e0, int32_t e2) {
+    EdgeCache c;
+#pragma unroll
+    for (int j = 0; j < kCacheEdges / 2; ++j) {
+        const int32_t e = e0 + 2 * j;
+        const uint32_t lo = e < e2 ? v.ux16[e] : 0u;
+        const uint32_t hi = e + 1 < e2 ? v.ux16[e + 1] : 0u;
+        c.w[j] = lo | (hi << 16);
+    }
+    return c;
+}
+
+// field_unit with the first kCacheEdges indices from registers: every cached
+// byte load is issued at once; longer rows finish from the edge array.
+template <int P, bool BLK>
+__device__ __forceinline__ void field_unit_cached(const Views &v, const int32_t *rp, const int32_t *h,
+                                                  const EdgeCache &c, const uint8_t *cur,
+                                                  int32_t L[P]) {
+    const int32_t e0 = rp[0];
+    const int32_t split = rp[1];
+    const int32_t e2 = P == 2 ? rp[2] : split;
+    int32_t acc0 = 0, acc1 = 0;
+#pragma unroll
+    for (int j = 0; j < kCacheEdges; ++j) {
+        const int32_t e = e0 + j;
+        const int32_t x = cur[(c.w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu];
+        acc0 += e < split ? x : 0;
+        if constexpr (P == 2) acc1 += (e >= split && e < e2) ? x : 0;
+    }
+    for (int32_t e = e0 + kCacheEdges; e < e2; ++e) {
+        const uint32_t idx = BLK ? *(const uint16_t __attribute__((address_space(1))) *)(v.ux16 + e)
+                                 : v.ux16[e];
+        const int32_t x = cur[idx];
+        acc0 += e < split ? x : 0;
+        if constexpr (P == 2) acc1 += e >= split ? x : 0;
+    }
+    L[0] = h[0] + 2 * acc0 - (split - e0);
+    if constexpr (P == 2) L[1] = h[1] + 2 * acc1 - (e2 - split);
+}
+
 // Four trials, unit weights, 0/1 bytes packed per word (SWAR); degree <= 255.
 template <bool BLK>
 __device__ __forceinline__ void field_swar(const Views &v, int32_t i, const uint32_t *cur,
@@ -290,11 +339,11 @@ __device__ __forceinline__ TaskConst<4 / LPT> load_task(const Views &v, int32_t 
 
 // Lane `sub` of task c.m updates its P p-bits at step t and returns their new
 // bytes (in the LDS encoding) in the low 8P bits.
-template <int CSR, int LPT, int ALG, bool BLK>
+template <int CSR, int LPT, int ALG, bool BLK, bool CACHED>
 __device__ __forceinline__ uint32_t task_one_trial(const Views &v, const TaskConst<4 / LPT> &c,
-                                                   uint32_t sub, uint32_t k, uint32_t t, float i0t,
-                                                   const unsigned char *cur, uint32_t k0,
-                                                   uint32_t k1, const InputState &st) {
+                                                   const EdgeCache *ec, uint32_t sub, uint32_t k,
+                                                   uint32_t t, float i0t, const unsigned char *cur,
+                                                   uint32_t k0, uint32_t k1, const InputState &st) {
     constexpr int P = 4 / LPT;
     constexpr bool kU = Enc<1, CSR>::kU;
     const int32_t base = c.base;
@@ -321,7 +370,15 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, const TaskCon
         for (int j = 0; j < P; ++j) sw[j] = word_of(b, sub * P + j);
     }
     int32_t L[P];
-    if constexpr (CSR == kCsrUnit) {
+    if constexpr (CSR == kCsrUnit && CACHED) {
+        if constexpr (P == 4) {
+            field_unit_cached<2, BLK>(v, c.rp, c.h, ec[0], cur, L);
+            field_unit_cached<2, BLK>(v, c.rp + 2, c.h + 2, ec[1], cur, L + 2);
+        } else {
+            field_unit_cached<P, BLK>(v, c.rp, c.h, ec[0], cur, L);
+        }
+    } else if constexpr (CSR == kCsrUnit) {
+        (void)ec;
         if constexpr (P == 4) {
             field_unit<2, BLK>(v, c.rp, c.h, cur, L);
             field_unit<2, BLK>(v, c.rp + 2, c.h + 2, cur, L + 2);
@@ -329,6 +386,7 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, const TaskCon
             field_unit<P, BLK>(v, c.rp, c.h, cur, L);
         }
     } else {
+        (void)ec;
 #pragma unroll
         for (int j = 0; j < P; ++j)
             L[j] = field_pm1<CSR>(v, c.rp[j], c.rp[j + 1], c.h[j], reinterpret_cast<const int8_t *>(cur));
@@ -540,12 +598,14 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
     // (and the complemented copy) into the next buffer.
     constexpr int P = 4 / LPT;
     const uint32_t sub = threadIdx.x % LPT;
-    auto one_trial_step = [&](auto alg_tag, const TaskConst<P> &c, uint32_t tau, float i0t,
+    auto one_trial_step = [&](auto alg_tag, auto cached_tag, const TaskConst<P> &c,
+                              const EdgeCache *ec, uint32_t tau, float i0t,
                               const unsigned char *from, unsigned char *to)
                               __attribute__((always_inline)) {
         constexpr int ALG = decltype(alg_tag)::value;
-        const uint32_t b = task_one_trial<CSR, LPT, ALG, !CSR_LDS>(v, c, sub, static_cast<uint32_t>(q),
-                                                                   tau, i0t, from, a.k0, a.k1, st);
+        constexpr bool CACHED = decltype(cached_tag)::value;
+        const uint32_t b = task_one_trial<CSR, LPT, ALG, !CSR_LDS, CACHED>(
+            v, c, ec, sub, static_cast<uint32_t>(q), tau, i0t, from, a.k0, a.k1, st);
         const int32_t at = c.base;
         if constexpr (P == 4) {
             *reinterpret_cast<uint32_t *>(to + at) = b;
@@ -564,7 +624,14 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
     const bool resident = TPW == 1 && tasks * LPT <= BLOCK;
     const bool owns = resident && static_cast<int32_t>(threadIdx.x) / LPT < tasks;
     TaskConst<P> own{};
-    if (owns) own = load_task<LPT>(v, v.order[threadIdx.x / LPT], sub);
+    EdgeCache own_edges[P == 4 ? 2 : 1] = {};
+    if (owns) {
+        own = load_task<LPT>(v, v.order[threadIdx.x / LPT], sub);
+        if constexpr (CSR == kCsrUnit) {
+            own_edges[0] = load_edge_cache(v, own.rp[0], own.rp[P == 4 ? 2 : P]);
+            if constexpr (P == 4) own_edges[1] = load_edge_cache(v, own.rp[2], own.rp[4]);
+        }
+    }
     // the step loop, instantiated per input stage (pSA, SpSA, TApSA) so that
     // plain pSA carries no per-update test for the others
     auto sweep = [&](auto alg_tag) {
@@ -578,11 +645,13 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
         const uint32_t tau = static_cast<uint32_t>(t) * static_cast<uint32_t>(nsub) + static_cast<uint32_t>(s);
         if constexpr (TPW == 1) {
             if (resident) {
-                if (owns) one_trial_step(alg_tag, own, tau, i0t, cur, nxt);
+                if (owns)
+                    one_trial_step(alg_tag, std::true_type{}, own, own_edges, tau, i0t, cur, nxt);
             } else {
                 // the LPT lanes of a task share its slot, so they enter and leave together
                 for (int32_t slot = threadIdx.x / LPT; slot < tasks; slot += BLOCK / LPT)
-                    one_trial_step(alg_tag, load_task<LPT>(v, v.order[slot], sub), tau, i0t, cur, nxt);
+                    one_trial_step(alg_tag, std::false_type{}, load_task<LPT>(v, v.order[slot], sub),
+                                   nullptr, tau, i0t, cur, nxt);
             }
         } else {
             for (int32_t slot = threadIdx.x; slot < tasks; slot += BLOCK)
