@@ -133,15 +133,18 @@ __device__ __forceinline__ void field_unit(const Views &v, const int32_t *rp, co
 }
 
 // Unit weights, one trial: the first kCacheEdges edge indices of a lane's
-// pair of rows, two 16-bit indices per register, kept across the steps of a
-// launch by a lane that owns its task throughout (entries past the rows hold
-// index 0, a valid byte that is masked out).
+// pair of rows (or one row), two 16-bit indices per register, kept across the
+// steps of a launch by a lane that owns its task throughout.  Entries past the
+// rows hold index 0 (a valid byte); bit j of sel[r] says entry j belongs to
+// row r.
 constexpr int kCacheEdges = 16;
 struct EdgeCache {
     uint32_t w[kCacheEdges / 2];
+    uint32_t sel[2];
 };
 
-__device__ __forceinline__ EdgeCache load_edge_cache(const Views &v, int32_t e0, int32_t e2) {
+__device__ __forceinline__ EdgeCache load_edge_cache(const Views &v, int32_t e0, int32_t split,
+                                                     int32_t e2) {
     EdgeCache c;
 #pragma unroll
     for (int j = 0; j < kCacheEdges / 2; ++j) {
@@ -150,11 +153,18 @@ __device__ __forceinline__ EdgeCache load_edge_cache(const Views &v, int32_t e0,
         const uint32_t hi = e + 1 < e2 ? v.ux16[e + 1] : 0u;
         c.w[j] = lo | (hi << 16);
     }
+    auto below = [](int32_t cnt) -> uint32_t {
+        return cnt >= kCacheEdges ? (1u << kCacheEdges) - 1u : (1u << cnt) - 1u;
+    };
+    c.sel[0] = below(split - e0);
+    c.sel[1] = below(e2 - e0) & ~c.sel[0];
     return c;
 }
 
 // field_unit with the first kCacheEdges indices from registers: every cached
-// byte load is issued at once; longer rows finish from the edge array.
+// byte load is issued at once, the 0/1 bytes are gathered into a bit pattern
+// and each row's share counted with one popcount; longer rows finish from the
+// edge array.
 template <int P, bool BLK>
 __device__ __forceinline__ void field_unit_cached(const Views &v, const int32_t *rp, const int32_t *h,
                                                   const EdgeCache &c, const uint8_t *cur,
@@ -162,14 +172,12 @@ __device__ __forceinline__ void field_unit_cached(const Views &v, const int32_t 
     const int32_t e0 = rp[0];
     const int32_t split = rp[1];
     const int32_t e2 = P == 2 ? rp[2] : split;
-    int32_t acc0 = 0, acc1 = 0;
+    uint32_t bits = 0u;
 #pragma unroll
-    for (int j = 0; j < kCacheEdges; ++j) {
-        const int32_t e = e0 + j;
-        const int32_t x = cur[(c.w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu];
-        acc0 += e < split ? x : 0;
-        if constexpr (P == 2) acc1 += (e >= split && e < e2) ? x : 0;
-    }
+    for (int j = 0; j < kCacheEdges; ++j)
+        bits |= static_cast<uint32_t>(cur[(c.w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu]) << j;
+    int32_t acc0 = __builtin_popcount(bits & c.sel[0]);
+    int32_t acc1 = P == 2 ? __builtin_popcount(bits & c.sel[1]) : 0;
     for (int32_t e = e0 + kCacheEdges; e < e2; ++e) {
         const uint32_t idx = BLK ? *(const uint16_t __attribute__((address_space(1))) *)(v.ux16 + e)
                                  : v.ux16[e];
@@ -599,13 +607,13 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
     constexpr int P = 4 / LPT;
     const uint32_t sub = threadIdx.x % LPT;
     auto one_trial_step = [&](auto alg_tag, auto cached_tag, const TaskConst<P> &c,
-                              const EdgeCache *ec, uint32_t tau, float i0t,
-                              const unsigned char *from, unsigned char *to)
+                              const EdgeCache *ec, uint32_t tau, float i0t, uint32_t k0,
+                              uint32_t k1, const unsigned char *from, unsigned char *to)
                               __attribute__((always_inline)) {
         constexpr int ALG = decltype(alg_tag)::value;
         constexpr bool CACHED = decltype(cached_tag)::value;
         const uint32_t b = task_one_trial<CSR, LPT, ALG, !CSR_LDS, CACHED>(
-            v, c, ec, sub, static_cast<uint32_t>(q), tau, i0t, from, a.k0, a.k1, st);
+            v, c, ec, sub, static_cast<uint32_t>(q), tau, i0t, from, k0, k1, st);
         const int32_t at = c.base;
         if constexpr (P == 4) {
             *reinterpret_cast<uint32_t *>(to + at) = b;
@@ -628,8 +636,8 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
     if (owns) {
         own = load_task<LPT>(v, v.order[threadIdx.x / LPT], sub);
         if constexpr (CSR == kCsrUnit) {
-            own_edges[0] = load_edge_cache(v, own.rp[0], own.rp[P == 4 ? 2 : P]);
-            if constexpr (P == 4) own_edges[1] = load_edge_cache(v, own.rp[2], own.rp[4]);
+            own_edges[0] = load_edge_cache(v, own.rp[0], own.rp[1], own.rp[P == 1 ? 1 : 2]);
+            if constexpr (P == 4) own_edges[1] = load_edge_cache(v, own.rp[2], own.rp[3], own.rp[4]);
         }
     }
     // the step loop, instantiated per input stage (pSA, SpSA, TApSA) so that
@@ -641,23 +649,28 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
     const int32_t nsub = ALG == kAlgPeriod ? a.t_res : 1;
     for (int32_t t = a.t_begin; t < a.t_end; ++t) {
         const float i0t = a.i0[t];
+        // the key, opaque to the optimiser at every step: the Philox key
+        // schedule is then formed on the scalar unit where it is used rather
+        // than hoisted out of the loop into registers that spill
+        uint32_t k0 = a.k0, k1 = a.k1;
+        asm volatile("" : "+s"(k0), "+s"(k1));
         for (int32_t s = 0; s < nsub; ++s) {
         const uint32_t tau = static_cast<uint32_t>(t) * static_cast<uint32_t>(nsub) + static_cast<uint32_t>(s);
         if constexpr (TPW == 1) {
             if (resident) {
                 if (owns)
-                    one_trial_step(alg_tag, std::true_type{}, own, own_edges, tau, i0t, cur, nxt);
+                    one_trial_step(alg_tag, std::true_type{}, own, own_edges, tau, i0t, k0, k1, cur, nxt);
             } else {
                 // the LPT lanes of a task share its slot, so they enter and leave together
                 for (int32_t slot = threadIdx.x / LPT; slot < tasks; slot += BLOCK / LPT)
                     one_trial_step(alg_tag, std::false_type{}, load_task<LPT>(v, v.order[slot], sub),
-                                   nullptr, tau, i0t, cur, nxt);
+                                   nullptr, tau, i0t, k0, k1, cur, nxt);
             }
         } else {
             for (int32_t slot = threadIdx.x; slot < tasks; slot += BLOCK)
                 task_four_trials<CSR, ALG, !CSR_LDS>(v, v.order[slot], q, tau, i0t,
                                       reinterpret_cast<const uint32_t *>(cur),
-                                      reinterpret_cast<uint32_t *>(nxt), a.k0, a.k1, st);
+                                      reinterpret_cast<uint32_t *>(nxt), k0, k1, st);
         }
         __syncthreads();
         unsigned char *tmp = cur;

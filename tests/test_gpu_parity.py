@@ -328,13 +328,18 @@ def _star_plus_ring(n, hub_degree, seed):
     return n, u, v, w
 
 
-@pytest.mark.parametrize("kind", ["unit", "int", "big", "hub"])
+@pytest.mark.parametrize("kind", ["unit", "int", "big", "hub", "wide"])
 @pytest.mark.parametrize("tpw,lpt", [(1, 1), (1, 2), (1, 4), (4, 0)])
 def test_edge_encodings_match_oracle(psa, ctx, kind, tpw, lpt):
     """Every edge encoding of the anneal kernel (0/1-byte mirror, SWAR words,
-    packed 32-bit, separate col/val) against the oracle, 30 steps."""
+    packed 32-bit, separate col/val), with the edges in LDS and (kind "wide":
+    200 KB of edges, rows of ~50) in global memory, against the oracle, 30
+    steps."""
     if kind == "unit":
         n, u, v, w = inputs.gnm(603, 2500, 11)
+        j, h = -w, None
+    elif kind == "wide":
+        n, u, v, w = inputs.gnm(2000, 50000, 15)
         j, h = -w, None
     elif kind == "int":
         n, u, v, j, h = _random_ising(603, 2500, 12)
