@@ -63,6 +63,36 @@ struct Enc {
 };
 
 // ---------------------------------------------------------------------------
+// Fast layout of the one-trial sweep (unit weights, LPT = 2 or 4, at most
+// 1,024 lanes of tasks): the two spin buffers lie kFastStride bytes apart and
+// each holds four copies of the n4 spins, u, 1 - u, 32 u and 32 (1 - u), then
+// a zero byte at 4 n4.  A lane that owns its task for the whole launch keeps
+// the LDS addresses of its rows' first kFastSlots edges in registers (edges
+// of its second row point into the 32x copies, unused slots at the zero
+// byte), so one sum of those bytes holds both rows' counts: the low five bits
+// and the rest.  With the buffer distance a constant, the step loop unrolled
+// by two reads either buffer through the load's immediate offset.
+// ---------------------------------------------------------------------------
+constexpr int32_t kFastStride = 8256;  // >= 4 n4 + 1 for every n4 the layout admits
+constexpr int kFastSlots = 24;
+
+__host__ __device__ constexpr bool fast_layout(int32_t tpw, int32_t lpt, int32_t csr, int32_t n4) {
+    return tpw == 1 && csr == kCsrUnit && (lpt == 2 || lpt == 4) && (n4 / 4) * lpt <= 1024;
+}
+
+typedef const uint8_t __attribute__((address_space(3))) lds_u8;
+
+// LDS byte address of a pointer into the workgroup's LDS.
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+    return static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_u8 *)(p)));
+}
+
+template <uint32_t OFF>
+__device__ __forceinline__ uint32_t lds_byte(uint32_t addr) {
+    return *((lds_u8 *)(uintptr_t)(addr) + OFF);
+}
+
+// ---------------------------------------------------------------------------
 // Field sums.
 // ---------------------------------------------------------------------------
 
@@ -187,6 +217,48 @@ __device__ __forceinline__ void field_unit_cached(const Views &v, const int32_t 
     }
     L[0] = h[0] + 2 * acc0 - (split - e0);
     if constexpr (P == 2) L[1] = h[1] + 2 * acc1 - (e2 - split);
+}
+
+// Fast layout: the lane's slot addresses (into buffer 0) for rows rp[0..P],
+// P = 1 or 2.
+struct FastCache {
+    uint32_t a[kFastSlots];
+};
+
+template <int P>
+__device__ __forceinline__ FastCache load_fast_cache(const Views &v, const int32_t *rp, uint32_t base0,
+                                                     int32_t n4) {
+    FastCache c;
+    const int32_t e0 = rp[0], split = rp[1], e2 = rp[P];
+#pragma unroll
+    for (int j = 0; j < kFastSlots; ++j) {
+        const int32_t e = e0 + j;
+        uint32_t x = 4u * static_cast<uint32_t>(n4);  // the zero byte
+        if (e < e2) x = v.ux16[e] + (e >= split ? 2u * static_cast<uint32_t>(n4) : 0u);
+        c.a[j] = base0 + x;
+    }
+    return c;
+}
+
+// Fields of the lane's P rows from the buffer at LDS offset OFF (cur points
+// there): the cached slots in one sum, then the edges past kFastSlots.
+template <int P, uint32_t OFF, bool BLK>
+__device__ __forceinline__ void field_fast(const Views &v, const int32_t *rp, const int32_t *h,
+                                           const FastCache &c, const uint8_t *cur, int32_t L[P]) {
+    uint32_t acc = 0u;
+#pragma unroll
+    for (int j = 0; j < kFastSlots; ++j) acc += lds_byte<OFF>(c.a[j]);
+    const int32_t e0 = rp[0], split = rp[1], e2 = rp[P];
+    int32_t c0 = static_cast<int32_t>(acc & 31u), c1 = static_cast<int32_t>(acc >> 5);
+    for (int32_t e = e0 + kFastSlots; e < e2; ++e) {
+        const uint32_t idx = BLK ? *(const uint16_t __attribute__((address_space(1))) *)(v.ux16 + e)
+                                 : v.ux16[e];
+        const int32_t x = cur[idx];
+        c0 += e < split ? x : 0;
+        c1 += e < split ? 0 : x;
+    }
+    L[0] = h[0] + 2 * c0 - (split - e0);
+    if constexpr (P == 2) L[1] = h[1] + 2 * c1 - (e2 - split);
 }
 
 // Four trials, unit weights, 0/1 bytes packed per word (SWAR); degree <= 255.
@@ -347,11 +419,15 @@ __device__ __forceinline__ TaskConst<4 / LPT> load_task(const Views &v, int32_t 
 
 // Lane `sub` of task c.m updates its P p-bits at step t and returns their new
 // bytes (in the LDS encoding) in the low 8P bits.
-template <int CSR, int LPT, int ALG, bool BLK, bool CACHED>
+// Field sources of the one-trial update.
+enum : int { kFieldPlain = 0, kFieldEdgeCache = 1, kFieldFast0 = 2, kFieldFast1 = 3 };
+
+template <int CSR, int LPT, int ALG, bool BLK, int FIELD>
 __device__ __forceinline__ uint32_t task_one_trial(const Views &v, const TaskConst<4 / LPT> &c,
-                                                   const EdgeCache *ec, uint32_t sub, uint32_t k,
-                                                   uint32_t t, float i0t, const unsigned char *cur,
-                                                   uint32_t k0, uint32_t k1, const InputState &st) {
+                                                   const EdgeCache *ec, const FastCache *fc,
+                                                   uint32_t sub, uint32_t k, uint32_t t, float i0t,
+                                                   const unsigned char *cur, uint32_t k0,
+                                                   uint32_t k1, const InputState &st) {
     constexpr int P = 4 / LPT;
     constexpr bool kU = Enc<1, CSR>::kU;
     const int32_t base = c.base;
@@ -378,7 +454,12 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, const TaskCon
         for (int j = 0; j < P; ++j) sw[j] = word_of(b, sub * P + j);
     }
     int32_t L[P];
-    if constexpr (CSR == kCsrUnit && CACHED) {
+    if constexpr (CSR == kCsrUnit && (FIELD == kFieldFast0 || FIELD == kFieldFast1) && P <= 2) {
+        (void)ec;
+        field_fast<P, FIELD == kFieldFast0 ? 0u : static_cast<uint32_t>(kFastStride), BLK>(
+            v, c.rp, c.h, *fc, cur, L);
+    } else if constexpr (CSR == kCsrUnit && FIELD == kFieldEdgeCache) {
+        (void)fc;
         if constexpr (P == 4) {
             field_unit_cached<2, BLK>(v, c.rp, c.h, ec[0], cur, L);
             field_unit_cached<2, BLK>(v, c.rp + 2, c.h + 2, ec[1], cur, L + 2);
@@ -386,7 +467,7 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, const TaskCon
             field_unit_cached<P, BLK>(v, c.rp, c.h, ec[0], cur, L);
         }
     } else if constexpr (CSR == kCsrUnit) {
-        (void)ec;
+        (void)ec, (void)fc;
         if constexpr (P == 4) {
             field_unit<2, BLK>(v, c.rp, c.h, cur, L);
             field_unit<2, BLK>(v, c.rp + 2, c.h + 2, cur, L + 2);
@@ -394,7 +475,7 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, const TaskCon
             field_unit<P, BLK>(v, c.rp, c.h, cur, L);
         }
     } else {
-        (void)ec;
+        (void)ec, (void)fc;
 #pragma unroll
         for (int j = 0; j < P; ++j)
             L[j] = field_pm1<CSR>(v, c.rp[j], c.rp[j + 1], c.h[j], reinterpret_cast<const int8_t *>(cur));
@@ -490,7 +571,7 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
 
 // ---------------------------------------------------------------------------
 // LDS carve-up (also used by the host planner):
-//   [buffer 0][buffer 1]                       2 * spin_buf_bytes
+//   [buffer 0][buffer 1]                       2 * spin_stride
 //   [row_ptr n4+4][h n4][lam n4][dlt n4][thr n4][order tasks rounded to 4]  (csr_lds)
 //   [edges: nnz * edge_bytes]                                               (csr_lds)
 // ---------------------------------------------------------------------------
@@ -498,6 +579,11 @@ __host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~size
 
 __host__ __device__ constexpr size_t spin_buf_bytes(int32_t n4, int32_t tpw, int32_t csr) {
     return align16(static_cast<size_t>(n4) * tpw * (csr == kCsrUnit ? 2 : 1));
+}
+
+// Distance between the two spin buffers.
+__host__ __device__ constexpr size_t spin_stride(int32_t n4, int32_t tpw, int32_t lpt, int32_t csr) {
+    return fast_layout(tpw, lpt, csr, n4) ? static_cast<size_t>(kFastStride) : spin_buf_bytes(n4, tpw, csr);
 }
 
 __host__ __device__ constexpr size_t params_bytes(int32_t n4) {
@@ -514,7 +600,9 @@ template <int TPW, int LPT, int CSR, bool CSR_LDS, int BLOCK>
 __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsigned char *smem) {
     using E = Enc<TPW, CSR>;
     const int32_t n = a.n, n4 = a.n4, tasks = a.tasks;
-    const size_t sb = spin_buf_bytes(n4, TPW, CSR);
+    constexpr bool kFastKind = TPW == 1 && CSR == kCsrUnit && (LPT == 2 || LPT == 4);
+    const bool fast_lay = kFastKind && fast_layout(TPW, LPT, CSR, n4);
+    const size_t sb = spin_stride(n4, TPW, LPT, CSR);
     unsigned char *buf0 = smem;
     unsigned char *buf1 = smem + sb;
 
@@ -583,9 +671,17 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
                 const unsigned char u = s > 0 ? 1 : 0;
                 buf0[i] = u;
                 if constexpr (E::kMirror) buf0[n4 + i] = u ^ 1u;
+                if (fast_lay) {
+                    buf0[2 * n4 + i] = static_cast<unsigned char>(u << 5);
+                    buf0[3 * n4 + i] = static_cast<unsigned char>((u ^ 1u) << 5);
+                }
             } else {
                 buf0[i] = static_cast<unsigned char>(s);
             }
+        }
+        if (fast_lay && threadIdx.x == 0) {
+            buf0[4 * n4] = 0;
+            buf1[4 * n4] = 0;
         }
     } else {
         uint32_t *s0 = reinterpret_cast<uint32_t *>(buf0);
@@ -612,8 +708,8 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
                               __attribute__((always_inline)) {
         constexpr int ALG = decltype(alg_tag)::value;
         constexpr bool CACHED = decltype(cached_tag)::value;
-        const uint32_t b = task_one_trial<CSR, LPT, ALG, !CSR_LDS, CACHED>(
-            v, c, ec, sub, static_cast<uint32_t>(q), tau, i0t, from, k0, k1, st);
+        const uint32_t b = task_one_trial<CSR, LPT, ALG, !CSR_LDS, CACHED ? kFieldEdgeCache : kFieldPlain>(
+            v, c, ec, nullptr, sub, static_cast<uint32_t>(q), tau, i0t, from, k0, k1, st);
         const int32_t at = c.base;
         if constexpr (P == 4) {
             *reinterpret_cast<uint32_t *>(to + at) = b;
@@ -631,15 +727,49 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
     // keeps its task's constants in registers for the whole launch.
     const bool resident = TPW == 1 && tasks * LPT <= BLOCK;
     const bool owns = resident && static_cast<int32_t>(threadIdx.x) / LPT < tasks;
+    // resident lanes in the fast layout (LPT 2 or 4) sum cached slots; other
+    // resident lanes (LPT 1) walk cached edge indices
+    const bool fast = fast_lay && resident;
     TaskConst<P> own{};
     EdgeCache own_edges[P == 4 ? 2 : 1] = {};
+    FastCache own_fast = {};
     if (owns) {
         own = load_task<LPT>(v, v.order[threadIdx.x / LPT], sub);
+        if constexpr (kFastKind) {
+            if (fast) own_fast = load_fast_cache<P>(v, own.rp, lds_addr(smem), n4);
+        }
         if constexpr (CSR == kCsrUnit) {
-            own_edges[0] = load_edge_cache(v, own.rp[0], own.rp[1], own.rp[P == 1 ? 1 : 2]);
-            if constexpr (P == 4) own_edges[1] = load_edge_cache(v, own.rp[2], own.rp[3], own.rp[4]);
+            if (!fast) {
+                own_edges[0] = load_edge_cache(v, own.rp[0], own.rp[1], own.rp[P == 1 ? 1 : 2]);
+                if constexpr (P == 4) own_edges[1] = load_edge_cache(v, own.rp[2], own.rp[3], own.rp[4]);
+            }
         }
     }
+    // Fast layout, one step: read the buffer at offset RO, write all four
+    // copies into the other.
+    auto fast_step = [&](auto alg_tag, auto par_tag, uint32_t tau, float i0t, uint32_t k0, uint32_t k1)
+                         __attribute__((always_inline)) {
+        constexpr int ALG = decltype(alg_tag)::value;
+        constexpr int PAR = decltype(par_tag)::value;
+        constexpr uint32_t RO = PAR ? static_cast<uint32_t>(kFastStride) : 0u;
+        constexpr uint32_t WO = PAR ? 0u : static_cast<uint32_t>(kFastStride);
+        const uint32_t b = task_one_trial<CSR, LPT, ALG, !CSR_LDS, PAR ? kFieldFast1 : kFieldFast0>(
+            v, own, nullptr, &own_fast, sub, static_cast<uint32_t>(q), tau, i0t, smem + RO, k0, k1, st);
+        unsigned char *to = smem + WO + own.base;
+        if constexpr (P == 2) {
+            const uint32_t m = b ^ 0x0101u;
+            *reinterpret_cast<uint16_t *>(to) = static_cast<uint16_t>(b);
+            *reinterpret_cast<uint16_t *>(to + n4) = static_cast<uint16_t>(m);
+            *reinterpret_cast<uint16_t *>(to + 2 * n4) = static_cast<uint16_t>(b << 5);
+            *reinterpret_cast<uint16_t *>(to + 3 * n4) = static_cast<uint16_t>(m << 5);
+        } else {
+            const uint32_t m = b ^ 1u;
+            to[0] = static_cast<unsigned char>(b);
+            to[n4] = static_cast<unsigned char>(m);
+            to[2 * n4] = static_cast<unsigned char>(b << 5);
+            to[3 * n4] = static_cast<unsigned char>(m << 5);
+        }
+    };
     // the step loop, instantiated per input stage (pSA, SpSA, TApSA) so that
     // plain pSA carries no per-update test for the others
     auto sweep = [&](auto alg_tag) {
@@ -647,6 +777,38 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
     // period mode: t_res sub-steps per step (the counter of the random words
     // and of the period gate is the sub-step); otherwise one
     const int32_t nsub = ALG == kAlgPeriod ? a.t_res : 1;
+    if constexpr (kFastKind) {
+        if (fast) {
+            // two steps per iteration: buffer 0 -> 1, then 1 -> 0
+            int32_t t = a.t_begin, s = 0, left = (a.t_end - a.t_begin) * nsub;
+            auto half = [&](auto par_tag) __attribute__((always_inline)) {
+                const float i0t = a.i0[t];
+                uint32_t k0 = a.k0, k1 = a.k1;
+                asm volatile("" : "+s"(k0), "+s"(k1));
+                const uint32_t tau = static_cast<uint32_t>(t) * static_cast<uint32_t>(nsub) +
+                                     static_cast<uint32_t>(s);
+                if (owns) fast_step(alg_tag, par_tag, tau, i0t, k0, k1);
+                __syncthreads();
+                if (++s == nsub) {
+                    s = 0;
+                    ++t;
+                }
+                --left;
+            };
+            bool in1 = false;
+            while (left > 0) {
+                half(std::integral_constant<int, 0>{});
+                if (left == 0) {
+                    in1 = true;
+                    break;
+                }
+                half(std::integral_constant<int, 1>{});
+            }
+            cur = in1 ? buf1 : buf0;
+            nxt = in1 ? buf0 : buf1;
+            return;
+        }
+    }
     for (int32_t t = a.t_begin; t < a.t_end; ++t) {
         const float i0t = a.i0[t];
         // the key, opaque to the optimiser at every step: the Philox key
@@ -816,7 +978,7 @@ bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t 
         else  // spread tasks over more lanes while the workgroup has lanes to spare
             p.lpt = tasks * 4 <= 1024 ? 4 : (tasks * 2 <= 1024 ? 2 : 1);
     }
-    const size_t sp = 2 * spin_buf_bytes(n4, p.tpw, p.csr);
+    const size_t sp = 2 * spin_stride(n4, p.tpw, p.lpt, p.csr);
     if (sp > max_lds) {
         if (why)
             *why = "n = " + std::to_string(g.n) + " does not fit the LDS-resident spin state (" +
