@@ -65,16 +65,18 @@ struct Enc {
 // ---------------------------------------------------------------------------
 // Fast layout of the one-trial sweep (unit weights, LPT = 2 or 4, at most
 // 1,024 lanes of tasks): the two spin buffers lie kFastStride bytes apart and
-// each holds four copies of the n4 spins, u, 1 - u, 32 u and 32 (1 - u), then
+// each holds four copies of the n4 spins, u, 1 - u, 64 u and 64 (1 - u), then
 // a zero byte at 4 n4.  A lane that owns its task for the whole launch keeps
 // the LDS addresses of its rows' first kFastSlots edges in registers (edges
-// of its second row point into the 32x copies, unused slots at the zero
-// byte), so one sum of those bytes holds both rows' counts: the low five bits
+// of its second row point into the 64x copies, unused slots at the zero
+// byte), so one sum of those bytes holds both rows' counts: the low six bits
 // and the rest.  With the buffer distance a constant, the step loop unrolled
 // by two reads either buffer through the load's immediate offset.
 // ---------------------------------------------------------------------------
 constexpr int32_t kFastStride = 8256;  // >= 4 n4 + 1 for every n4 the layout admits
-constexpr int kFastSlots = 24;
+constexpr int kFastSlots = 32;
+constexpr int kFastChunk = 8;  // slots per wave-uniform skip test
+static_assert(kFastSlots < 64, "the first row's count must fit the low six bits");
 
 __host__ __device__ constexpr bool fast_layout(int32_t tpw, int32_t lpt, int32_t csr, int32_t n4) {
     return tpw == 1 && csr == kCsrUnit && (lpt == 2 || lpt == 4) && (n4 / 4) * lpt <= 1024;
@@ -220,9 +222,12 @@ __device__ __forceinline__ void field_unit_cached(const Views &v, const int32_t 
 }
 
 // Fast layout: the lane's slot addresses (into buffer 0) for rows rp[0..P],
-// P = 1 or 2.
+// P = 1 or 2, and the number of kFastChunk-slot chunks that some lane of the
+// wavefront uses (uniform; tasks are ordered heaviest first, so the lanes of a
+// wavefront have rows of similar length).
 struct FastCache {
     uint32_t a[kFastSlots];
+    uint32_t chunks;
 };
 
 template <int P>
@@ -247,9 +252,14 @@ __device__ __forceinline__ void field_fast(const Views &v, const int32_t *rp, co
                                            const FastCache &c, const uint8_t *cur, int32_t L[P]) {
     uint32_t acc = 0u;
 #pragma unroll
-    for (int j = 0; j < kFastSlots; ++j) acc += lds_byte<OFF>(c.a[j]);
+    for (int g = 0; g < kFastSlots / kFastChunk; ++g) {
+        if (static_cast<uint32_t>(g) < c.chunks) {
+#pragma unroll
+            for (int j = 0; j < kFastChunk; ++j) acc += lds_byte<OFF>(c.a[kFastChunk * g + j]);
+        }
+    }
     const int32_t e0 = rp[0], split = rp[1], e2 = rp[P];
-    int32_t c0 = static_cast<int32_t>(acc & 31u), c1 = static_cast<int32_t>(acc >> 5);
+    int32_t c0 = static_cast<int32_t>(acc & 63u), c1 = static_cast<int32_t>(acc >> 6);
     for (int32_t e = e0 + kFastSlots; e < e2; ++e) {
         const uint32_t idx = BLK ? *(const uint16_t __attribute__((address_space(1))) *)(v.ux16 + e)
                                  : v.ux16[e];
@@ -672,8 +682,8 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
                 buf0[i] = u;
                 if constexpr (E::kMirror) buf0[n4 + i] = u ^ 1u;
                 if (fast_lay) {
-                    buf0[2 * n4 + i] = static_cast<unsigned char>(u << 5);
-                    buf0[3 * n4 + i] = static_cast<unsigned char>((u ^ 1u) << 5);
+                    buf0[2 * n4 + i] = static_cast<unsigned char>(u << 6);
+                    buf0[3 * n4 + i] = static_cast<unsigned char>((u ^ 1u) << 6);
                 }
             } else {
                 buf0[i] = static_cast<unsigned char>(s);
@@ -745,6 +755,17 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
             }
         }
     }
+    if constexpr (kFastKind) {
+        if (fast) {
+            // slot chunks the wavefront needs: the largest row-pair length of
+            // its lanes (every lane of the wavefront takes part)
+            int32_t cnt = owns ? min(own.rp[P] - own.rp[0], kFastSlots) : 0;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) cnt = max(cnt, __shfl_xor(cnt, off));
+            own_fast.chunks = static_cast<uint32_t>(
+                __builtin_amdgcn_readfirstlane((cnt + kFastChunk - 1) / kFastChunk));
+        }
+    }
     // Fast layout, one step: read the buffer at offset RO, write all four
     // copies into the other.
     auto fast_step = [&](auto alg_tag, auto par_tag, uint32_t tau, float i0t, uint32_t k0, uint32_t k1)
@@ -760,14 +781,14 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
             const uint32_t m = b ^ 0x0101u;
             *reinterpret_cast<uint16_t *>(to) = static_cast<uint16_t>(b);
             *reinterpret_cast<uint16_t *>(to + n4) = static_cast<uint16_t>(m);
-            *reinterpret_cast<uint16_t *>(to + 2 * n4) = static_cast<uint16_t>(b << 5);
-            *reinterpret_cast<uint16_t *>(to + 3 * n4) = static_cast<uint16_t>(m << 5);
+            *reinterpret_cast<uint16_t *>(to + 2 * n4) = static_cast<uint16_t>(b << 6);
+            *reinterpret_cast<uint16_t *>(to + 3 * n4) = static_cast<uint16_t>(m << 6);
         } else {
             const uint32_t m = b ^ 1u;
             to[0] = static_cast<unsigned char>(b);
             to[n4] = static_cast<unsigned char>(m);
-            to[2 * n4] = static_cast<unsigned char>(b << 5);
-            to[3 * n4] = static_cast<unsigned char>(m << 5);
+            to[2 * n4] = static_cast<unsigned char>(b << 6);
+            to[3 * n4] = static_cast<unsigned char>(m << 6);
         }
     };
     // the step loop, instantiated per input stage (pSA, SpSA, TApSA) so that
