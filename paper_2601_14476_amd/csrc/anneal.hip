@@ -52,7 +52,7 @@ __device__ __forceinline__ Words4 block_of(uint32_t t, uint32_t m, uint32_t k, u
 
 // Eq. 6 decision for one p-bit and trial: +1 iff tanh(x) > r, x the
 // (fresh or held) pre-activation (I0 lambda)(L + delta).
-__device__ __forceinline__ bool goes_up(float x, uint32_t rword) { return tanh_f32(x) > r_of(rword); }
+__device__ __forceinline__ bool goes_up(float x, uint32_t rword) { return pbit_up(x, rword); }
 
 template <int TPW, int CSR>
 struct Enc {

@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
             const int32_t L = hv[p] + scale * a4[p];
             const float x = input_any(av[p], dv[p], L, sv, i0 + p, static_cast<uint32_t>(k),
                                       static_cast<uint32_t>(t), sw[p]);
-            const bool up = tanh_f32(x) > r_of(rw[p]);
+            const bool up = pbit_up(x, rw[p]);
             const bool fire = period_mode ? period_fires(tau, tv[p])
                                           : (tv[p] >= kGateOne || fires(gw[p], tv[p]));
             const uint32_t ob = (old >> (8 * p)) & 0xFFu;

@@ -1,10 +1,11 @@
 // device_math.hpp -- per-update arithmetic of the p-bit (gfx950 device code).
 //
 // Counter-based randomness, the uniform r of Eq. 1, the timing gate, and a
-// single-precision tanh with a fixed operation order.  Everything here is
+// single-precision tanh with a fixed operation order.  Every value here is
 // evaluated with IEEE single-precision operations that round exactly once
 // (explicit fmaf, correctly rounded division, no contraction), so that the
-// result does not depend on how the compiler schedules it.
+// result does not depend on how the compiler schedules it; the decision
+// pbit_up takes hardware approximations only where they cannot change it.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -88,6 +89,24 @@ __device__ __forceinline__ float tanh_f32(float x) {
     float y = 1.0f - 2.0f / (e + 1.0f);
     y = (a >= 9.0f) ? 1.0f : y;
     return copysignf(y, x);
+}
+
+// Eq. 1 decision: +1 iff tanh_f32(x) > r.  A cheap estimate of tanh (the
+// hardware 2^v and reciprocal, each within about one ulp, in place of the
+// polynomial and the correctly rounded division) decides whenever it lies
+// more than 2^-16 from r.  The estimate is within 2^-20 of tanh_f32(x): a
+// relative error of about 2^-21 in 2^v moves 1 - 2/(e+1) by at most half
+// that, the reciprocal adds 2^-23 and the roundings a few 2^-24; so every
+// such decision is the one tanh_f32 gives.  The rest (about 2^-16 of the
+// updates) evaluate tanh_f32 itself.
+__device__ __forceinline__ bool pbit_up(float x, uint32_t rword) {
+    const float r = r_of(rword);
+    const float a = fminf(fabsf(x), 9.0f);
+    const float e = __builtin_amdgcn_exp2f(a * 0x1.715476p+1f);
+    const float y = fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
+    const float diff = copysignf(y, x) - r;
+    if (fabsf(diff) > 0x1p-16f) return diff > 0.0f;
+    return tanh_f32(x) > r;
 }
 
 // 16-byte load from device-global memory through an address-space cast, so
