@@ -450,6 +450,26 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
     j->run.trials = desc->trials;
     j->run.t4 = (desc->trials + 3) / 4 * 4;
     j->run.steps = S;
+    psa_status st;
+    const int32_t n4 = g->dev.n4;
+    // input-stage state first: the launch plan depends on it (LDS windows)
+    if (desc->algorithm == PSA_ALG_SPSA) {
+        // held inputs: [t4/4][n4][4] floats, formed at step 0 before any read
+        const size_t xb = static_cast<size_t>(n4) * static_cast<size_t>(j->run.t4);
+        if ((st = dev_upload<float>(&j->d_xs, nullptr, xb, "job held inputs")) != PSA_OK) return st;
+        j->run.xs = j->d_xs;
+        j->run.stall24 = static_cast<uint32_t>(std::floor(desc->p_stall * 16777216.0));
+    }
+    if (desc->algorithm == PSA_ALG_TAPSA) {
+        // field windows: [t4/4][n4][window][4] int32, slot t mod window written
+        // at step t before any read of it
+        const size_t rb = static_cast<size_t>(n4) * static_cast<size_t>(j->run.t4) *
+                          static_cast<size_t>(desc->window);
+        if ((st = dev_upload<int32_t>(&j->d_ring, nullptr, rb, "job field windows")) != PSA_OK)
+            return st;
+        j->run.ring = j->d_ring;
+        j->run.alpha = desc->window;
+    }
     const uint32_t path = desc->flags & PSA_PATH_MASK;
     if (path != PSA_PATH_DENSE) {
         std::string why;
@@ -471,9 +491,7 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
     }
     j->run.key0 = static_cast<uint32_t>(desc->seed);
     j->run.key1 = static_cast<uint32_t>(desc->seed >> 32);
-    psa_status st;
     // per-p-bit arrays padded to n4: padding p-bits never fire
-    const int32_t n4 = g->dev.n4;
     lam.resize(static_cast<size_t>(n4), 1.0f);
     dlt.resize(static_cast<size_t>(n4), 0.0f);
     thr.resize(static_cast<size_t>(n4), 0u);
@@ -490,23 +508,6 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
         j->tp = (j->run.t4 + 16 * j->plan.nb - 1) / (16 * j->plan.nb) * (16 * j->plan.nb);
         const size_t mb = 2 * static_cast<size_t>(j->tp) * static_cast<size_t>(g->np);
         if ((st = dev_upload<int8_t>(&j->d_m, nullptr, mb, "job dense spins")) != PSA_OK) return st;
-    }
-    if (desc->algorithm == PSA_ALG_SPSA) {
-        // held inputs: [t4/4][n4][4] floats, formed at step 0 before any read
-        const size_t xb = static_cast<size_t>(n4) * static_cast<size_t>(j->run.t4);
-        if ((st = dev_upload<float>(&j->d_xs, nullptr, xb, "job held inputs")) != PSA_OK) return st;
-        j->run.xs = j->d_xs;
-        j->run.stall24 = static_cast<uint32_t>(std::floor(desc->p_stall * 16777216.0));
-    }
-    if (desc->algorithm == PSA_ALG_TAPSA) {
-        // field windows: [t4/4][n4][window][4] int32, slot t mod window written
-        // at step t before any read of it
-        const size_t rb = static_cast<size_t>(n4) * static_cast<size_t>(j->run.t4) *
-                          static_cast<size_t>(desc->window);
-        if ((st = dev_upload<int32_t>(&j->d_ring, nullptr, rb, "job field windows")) != PSA_OK)
-            return st;
-        j->run.ring = j->d_ring;
-        j->run.alpha = desc->window;
     }
     j->run.t_res = desc->t_res;
     j->run.i0 = j->d_i0;

@@ -429,17 +429,28 @@ __device__ __forceinline__ TaskConst<4 / LPT> load_task(const Views &v, int32_t 
 
 // Lane `sub` of task c.m updates its P p-bits at step t and returns their new
 // bytes (in the LDS encoding) in the low 8P bits.
+// Input-stage state a resident lane keeps in registers for its P p-bits:
+// TApSA window sums (the fields of the last min(t+1, alpha) steps, the
+// current one included) and SpSA held pre-activations.
+template <int P>
+struct LaneInput {
+    int32_t wsum[P];
+    float held[P];
+};
+
 // Field sources of the one-trial update.
 enum : int { kFieldPlain = 0, kFieldEdgeCache = 1, kFieldFast0 = 2, kFieldFast1 = 3 };
 
-template <int CSR, int LPT, int ALG, bool BLK, int FIELD>
+template <int CSR, int LPT, int ALG, bool BLK, int FIELD, bool LRING = false>
 __device__ __forceinline__ uint32_t task_one_trial(const Views &v, const TaskConst<4 / LPT> &c,
                                                    const EdgeCache *ec, const FastCache *fc,
-                                                   uint32_t sub, uint32_t k, uint32_t t, float i0t,
-                                                   const unsigned char *cur, uint32_t k0,
-                                                   uint32_t k1, const InputState &st) {
+                                                   LaneInput<4 / LPT> *li, int32_t *lring, uint32_t sub, uint32_t k,
+                                                   uint32_t t, float i0t, const unsigned char *cur,
+                                                   uint32_t k0, uint32_t k1, const InputState &st) {
     constexpr int P = 4 / LPT;
     constexpr bool kU = Enc<1, CSR>::kU;
+    // resident lanes carry the input stage in registers (li)
+    constexpr bool RES = FIELD != kFieldPlain;
     const int32_t base = c.base;
     if constexpr (ALG == kAlgPeriod) {
         // t is the sub-step; p-bits whose period does not divide it hold
@@ -452,6 +463,24 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, const TaskCon
             for (int j = 0; j < P; ++j) out |= static_cast<uint32_t>(cur[base + j]) << (8 * j);
             return out;
         }
+    }
+    // TApSA, resident: the field that leaves the window (step t - alpha) sits
+    // in the slot this step's field takes; its load is issued first
+    int32_t tap_old[P];
+    int32_t *tap_w[P];
+    if constexpr (ALG == kAlgTapsa && RES) {
+        const uint32_t al = static_cast<uint32_t>(st.alpha);
+        const uint32_t slot = t % al;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            if constexpr (LRING)
+                tap_w[j] = lring + static_cast<size_t>(base + j) * al + slot;
+            else
+                tap_w[j] = st.ring + ((static_cast<size_t>(k >> 2) * st.n4 + base + j) * al + slot) * 4 + (k & 3u);
+            tap_old[j] = t >= al ? *tap_w[j] : 0;
+        }
+    } else {
+        (void)lring;
     }
     const bool need_gate = ALG != kAlgPeriod && c.need_gate;
     uint32_t rw[P], gw[P], sw[P];
@@ -497,7 +526,23 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, const TaskCon
         const uint32_t old = cur[i];
         const uint32_t th = c.thr[j];
         const bool fire = ALG == kAlgPeriod ? period_fires(t, th) : (th >= kGateOne || fires(gw[j], th));
-        const float x = input_of<ALG>(i0t * c.lam[j], c.dlt[j], L[j], st, i, k, t, sw[j]);
+        float x;
+        if constexpr (ALG == kAlgTapsa && RES) {
+            // the window sum advanced by the entering and the leaving field
+            li->wsum[j] += L[j] - tap_old[j];
+            *tap_w[j] = L[j];
+            const uint32_t al = static_cast<uint32_t>(st.alpha);
+            const uint32_t count = t + 1 < al ? t + 1 : al;
+            const float mean = static_cast<float>(li->wsum[j]) / static_cast<float>(count);
+            x = (i0t * c.lam[j]) * (mean + c.dlt[j]);
+        } else if constexpr (ALG == kAlgSpsa && RES) {
+            const float fresh = (i0t * c.lam[j]) * (static_cast<float>(L[j]) + c.dlt[j]);
+            x = (t > 0 && (sw[j] >> 8) < st.s24) ? li->held[j] : fresh;
+            li->held[j] = x;
+        } else {
+            (void)li;
+            x = input_of<ALG>(i0t * c.lam[j], c.dlt[j], L[j], st, i, k, t, sw[j]);
+        }
         const bool up = goes_up(x, rw[j]);
         const uint32_t nb = kU ? (up ? 1u : 0u) : (up ? 0x01u : 0xFFu);
         out |= (fire ? nb : old) << (8 * j);
@@ -582,6 +627,7 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
 // ---------------------------------------------------------------------------
 // LDS carve-up (also used by the host planner):
 //   [buffer 0][buffer 1]                       2 * spin_stride
+//   [TApSA windows]                            ring_lds_bytes
 //   [row_ptr n4+4][h n4][lam n4][dlt n4][thr n4][order tasks rounded to 4]  (csr_lds)
 //   [edges: nnz * edge_bytes]                                               (csr_lds)
 // ---------------------------------------------------------------------------
@@ -594,6 +640,17 @@ __host__ __device__ constexpr size_t spin_buf_bytes(int32_t n4, int32_t tpw, int
 // Distance between the two spin buffers.
 __host__ __device__ constexpr size_t spin_stride(int32_t n4, int32_t tpw, int32_t lpt, int32_t csr) {
     return fast_layout(tpw, lpt, csr, n4) ? static_cast<size_t>(kFastStride) : spin_buf_bytes(n4, tpw, csr);
+}
+
+// TApSA windows of a fast-layout run in LDS ([n4][alpha] int32 of the
+// workgroup's trial, behind the spin buffers) when they take at most 64 KB;
+// else they stay in device memory.
+__host__ __device__ constexpr size_t ring_lds_bytes(int32_t n4, int32_t tpw, int32_t lpt, int32_t csr,
+                                                    bool has_ring, int32_t alpha) {
+    return (has_ring && fast_layout(tpw, lpt, csr, n4) &&
+            static_cast<size_t>(n4) * static_cast<size_t>(alpha) * 4 <= 65536)
+               ? align16(static_cast<size_t>(n4) * static_cast<size_t>(alpha) * 4)
+               : 0;
 }
 
 __host__ __device__ constexpr size_t params_bytes(int32_t n4) {
@@ -613,12 +670,14 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
     constexpr bool kFastKind = TPW == 1 && CSR == kCsrUnit && (LPT == 2 || LPT == 4);
     const bool fast_lay = kFastKind && fast_layout(TPW, LPT, CSR, n4);
     const size_t sb = spin_stride(n4, TPW, LPT, CSR);
+    const size_t ring_res = ring_lds_bytes(n4, TPW, LPT, CSR, a.ring != nullptr, a.alpha);
     unsigned char *buf0 = smem;
     unsigned char *buf1 = smem + sb;
+    int32_t *lring = reinterpret_cast<int32_t *>(smem + 2 * sb);
 
     Views v;
     if constexpr (CSR_LDS) {
-        int32_t *l_rp = reinterpret_cast<int32_t *>(smem + 2 * sb);
+        int32_t *l_rp = reinterpret_cast<int32_t *>(smem + 2 * sb + ring_res);
         int32_t *l_h = l_rp + n4 + 4;
         float *l_lam = reinterpret_cast<float *>(l_h + n4);
         float *l_dlt = l_lam + n4;
@@ -713,13 +772,13 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
     constexpr int P = 4 / LPT;
     const uint32_t sub = threadIdx.x % LPT;
     auto one_trial_step = [&](auto alg_tag, auto cached_tag, const TaskConst<P> &c,
-                              const EdgeCache *ec, uint32_t tau, float i0t, uint32_t k0,
-                              uint32_t k1, const unsigned char *from, unsigned char *to)
+                              const EdgeCache *ec, LaneInput<P> *li, uint32_t tau, float i0t,
+                              uint32_t k0, uint32_t k1, const unsigned char *from, unsigned char *to)
                               __attribute__((always_inline)) {
         constexpr int ALG = decltype(alg_tag)::value;
         constexpr bool CACHED = decltype(cached_tag)::value;
         const uint32_t b = task_one_trial<CSR, LPT, ALG, !CSR_LDS, CACHED ? kFieldEdgeCache : kFieldPlain>(
-            v, c, ec, nullptr, sub, static_cast<uint32_t>(q), tau, i0t, from, k0, k1, st);
+            v, c, ec, nullptr, li, nullptr, sub, static_cast<uint32_t>(q), tau, i0t, from, k0, k1, st);
         const int32_t at = c.base;
         if constexpr (P == 4) {
             *reinterpret_cast<uint32_t *>(to + at) = b;
@@ -743,8 +802,27 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
     TaskConst<P> own{};
     EdgeCache own_edges[P == 4 ? 2 : 1] = {};
     FastCache own_fast = {};
+    LaneInput<P> own_in = {};
     if (owns) {
         own = load_task<LPT>(v, v.order[threadIdx.x / LPT], sub);
+        // input-stage state of the lane's p-bits: the TApSA window sums up to
+        // step t_begin - 1 from the ring, the SpSA held inputs
+        const size_t row0 = static_cast<size_t>(q >> 2) * n4 + own.base;
+        if (a.ring != nullptr) {
+            const int32_t al = a.alpha;
+            const int32_t cnt = a.t_begin < al ? a.t_begin : al;
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                int32_t sum = 0;
+                for (int32_t i = 0; i < cnt; ++i)
+                    sum += a.ring[((row0 + j) * al + (a.t_begin - 1 - i) % al) * 4 + (q & 3)];
+                own_in.wsum[j] = sum;
+            }
+        }
+        if (a.xs != nullptr) {
+#pragma unroll
+            for (int j = 0; j < P; ++j) own_in.held[j] = a.xs[(row0 + j) * 4 + (q & 3)];
+        }
         if constexpr (kFastKind) {
             if (fast) own_fast = load_fast_cache<P>(v, own.rp, lds_addr(smem), n4);
         }
@@ -754,6 +832,14 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
                 if constexpr (P == 4) own_edges[1] = load_edge_cache(v, own.rp[2], own.rp[3], own.rp[4]);
             }
         }
+    }
+    // TApSA windows of a fast run in LDS: in at the start, out at the end
+    const bool lds_ring = fast && ring_res > 0;
+    if (lds_ring) {
+        const int32_t al = a.alpha;
+        const size_t g0 = static_cast<size_t>(q >> 2) * n4 * al;
+        for (int32_t x = threadIdx.x; x < n4 * al; x += BLOCK) lring[x] = a.ring[(g0 + x) * 4 + (q & 3)];
+        __syncthreads();
     }
     if constexpr (kFastKind) {
         if (fast) {
@@ -768,14 +854,16 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
     }
     // Fast layout, one step: read the buffer at offset RO, write all four
     // copies into the other.
-    auto fast_step = [&](auto alg_tag, auto par_tag, uint32_t tau, float i0t, uint32_t k0, uint32_t k1)
-                         __attribute__((always_inline)) {
+    auto fast_step = [&](auto alg_tag, auto par_tag, auto lring_tag, uint32_t tau, float i0t, uint32_t k0,
+                         uint32_t k1) __attribute__((always_inline)) {
         constexpr int ALG = decltype(alg_tag)::value;
         constexpr int PAR = decltype(par_tag)::value;
+        constexpr bool LR = decltype(lring_tag)::value;
         constexpr uint32_t RO = PAR ? static_cast<uint32_t>(kFastStride) : 0u;
         constexpr uint32_t WO = PAR ? 0u : static_cast<uint32_t>(kFastStride);
-        const uint32_t b = task_one_trial<CSR, LPT, ALG, !CSR_LDS, PAR ? kFieldFast1 : kFieldFast0>(
-            v, own, nullptr, &own_fast, sub, static_cast<uint32_t>(q), tau, i0t, smem + RO, k0, k1, st);
+        const uint32_t b = task_one_trial<CSR, LPT, ALG, !CSR_LDS, PAR ? kFieldFast1 : kFieldFast0, LR>(
+            v, own, nullptr, &own_fast, &own_in, lring, sub, static_cast<uint32_t>(q), tau, i0t, smem + RO,
+            k0, k1, st);
         unsigned char *to = smem + WO + own.base;
         if constexpr (P == 2) {
             const uint32_t m = b ^ 0x0101u;
@@ -801,32 +889,38 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
     if constexpr (kFastKind) {
         if (fast) {
             // two steps per iteration: buffer 0 -> 1, then 1 -> 0
-            int32_t t = a.t_begin, s = 0, left = (a.t_end - a.t_begin) * nsub;
-            auto half = [&](auto par_tag) __attribute__((always_inline)) {
-                const float i0t = a.i0[t];
-                uint32_t k0 = a.k0, k1 = a.k1;
-                asm volatile("" : "+s"(k0), "+s"(k1));
-                const uint32_t tau = static_cast<uint32_t>(t) * static_cast<uint32_t>(nsub) +
-                                     static_cast<uint32_t>(s);
-                if (owns) fast_step(alg_tag, par_tag, tau, i0t, k0, k1);
-                __syncthreads();
-                if (++s == nsub) {
-                    s = 0;
-                    ++t;
+            auto run_fast = [&](auto lring_tag) __attribute__((always_inline)) {
+                int32_t t = a.t_begin, s = 0, left = (a.t_end - a.t_begin) * nsub;
+                auto half = [&](auto par_tag) __attribute__((always_inline)) {
+                    const float i0t = a.i0[t];
+                    uint32_t k0 = a.k0, k1 = a.k1;
+                    asm volatile("" : "+s"(k0), "+s"(k1));
+                    const uint32_t tau = static_cast<uint32_t>(t) * static_cast<uint32_t>(nsub) +
+                                         static_cast<uint32_t>(s);
+                    if (owns) fast_step(alg_tag, par_tag, lring_tag, tau, i0t, k0, k1);
+                    __syncthreads();
+                    if (++s == nsub) {
+                        s = 0;
+                        ++t;
+                    }
+                    --left;
+                };
+                bool in1 = false;
+                while (left > 0) {
+                    half(std::integral_constant<int, 0>{});
+                    if (left == 0) {
+                        in1 = true;
+                        break;
+                    }
+                    half(std::integral_constant<int, 1>{});
                 }
-                --left;
+                cur = in1 ? buf1 : buf0;
+                nxt = in1 ? buf0 : buf1;
             };
-            bool in1 = false;
-            while (left > 0) {
-                half(std::integral_constant<int, 0>{});
-                if (left == 0) {
-                    in1 = true;
-                    break;
-                }
-                half(std::integral_constant<int, 1>{});
-            }
-            cur = in1 ? buf1 : buf0;
-            nxt = in1 ? buf0 : buf1;
+            if (ALG == kAlgTapsa && lds_ring)
+                run_fast(std::true_type{});
+            else
+                run_fast(std::false_type{});
             return;
         }
     }
@@ -842,12 +936,12 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
         if constexpr (TPW == 1) {
             if (resident) {
                 if (owns)
-                    one_trial_step(alg_tag, std::true_type{}, own, own_edges, tau, i0t, k0, k1, cur, nxt);
+                    one_trial_step(alg_tag, std::true_type{}, own, own_edges, &own_in, tau, i0t, k0, k1, cur, nxt);
             } else {
                 // the LPT lanes of a task share its slot, so they enter and leave together
                 for (int32_t slot = threadIdx.x / LPT; slot < tasks; slot += BLOCK / LPT)
                     one_trial_step(alg_tag, std::false_type{}, load_task<LPT>(v, v.order[slot], sub),
-                                   nullptr, tau, i0t, k0, k1, cur, nxt);
+                                   nullptr, nullptr, tau, i0t, k0, k1, cur, nxt);
             }
         } else {
             for (int32_t slot = threadIdx.x; slot < tasks; slot += BLOCK)
@@ -872,6 +966,16 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
         sweep(std::integral_constant<int, kAlgPsa>{});
 
     if constexpr (TPW == 1) {
+        if (lds_ring) {
+            const int32_t al = a.alpha;
+            const size_t g0 = static_cast<size_t>(q >> 2) * n4 * al;
+            for (int32_t x = threadIdx.x; x < n4 * al; x += BLOCK) a.ring[(g0 + x) * 4 + (q & 3)] = lring[x];
+        }
+        if (owns && a.xs != nullptr) {
+            const size_t row0 = static_cast<size_t>(q >> 2) * n4 + own.base;
+#pragma unroll
+            for (int j = 0; j < P; ++j) a.xs[(row0 + j) * 4 + (q & 3)] = own_in.held[j];
+        }
         for (int32_t i = threadIdx.x; i < n; i += BLOCK) {
             int8_t s;
             if constexpr (E::kU)
@@ -999,7 +1103,8 @@ bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t 
         else  // spread tasks over more lanes while the workgroup has lanes to spare
             p.lpt = tasks * 4 <= 1024 ? 4 : (tasks * 2 <= 1024 ? 2 : 1);
     }
-    const size_t sp = 2 * spin_stride(n4, p.tpw, p.lpt, p.csr);
+    const size_t sp = 2 * spin_stride(n4, p.tpw, p.lpt, p.csr) +
+                      ring_lds_bytes(n4, p.tpw, p.lpt, p.csr, run.ring != nullptr, run.alpha);
     if (sp > max_lds) {
         if (why)
             *why = "n = " + std::to_string(g.n) + " does not fit the LDS-resident spin state (" +
@@ -1039,10 +1144,21 @@ void task_order(const DevGraph &g, const std::vector<int32_t> &row_ptr_host, con
                      [&](int32_t x, int32_t y) { return key[x] > key[y]; });
 }
 
+// LDS the kernel carves for a run under a plan (the layout above).
+size_t lds_need(const DevGraph &g, const DevRun &run, const AnnealPlan &p) {
+    size_t b = 2 * spin_stride(g.n4, p.tpw, p.lpt, p.csr) +
+               ring_lds_bytes(g.n4, p.tpw, p.lpt, p.csr, run.ring != nullptr, run.alpha);
+    if (p.csr_lds) b += params_bytes(g.n4) + align16(static_cast<size_t>(g.nnz) * edge_bytes(p.csr));
+    return b;
+}
+
 hipError_t launch_anneal(hipStream_t stream, const DevGraph &g, const DevRun &run,
                          const AnnealPlan &plan, const int32_t *order, int32_t t_begin,
                          int32_t t_end) {
     if (t_end <= t_begin) return hipSuccess;
+    // a plan made for another input stage would leave the kernel's LDS
+    // layout outside the allocation
+    if (lds_need(g, run, plan) > plan.lds_bytes) return hipErrorInvalidValue;
     AnnealArgs a;
     fill_anneal_args(&a, g, run, order, t_begin, t_end);
     if (plan.tpw == 4) return launch_four_trials(stream, a, plan);
