@@ -613,3 +613,49 @@ def test_period_mode_edge_cases(psa, ctx):
         psa.Job(ctx, g, 20, 5, 6, t_res=10, period=np.zeros(n, np.uint32))
     with pytest.raises(psa.PsaError):
         psa.Job(ctx, g, 1 << 20, 5, 6, t_res=10)
+
+
+@pytest.mark.parametrize("n,lpt", [(2048, 2), (2049, 0), (1024, 4), (1025, 4)])
+def test_fast_layout_boundaries(psa, ctx, n, lpt):
+    """Sizes at the edge of the one-trial fast layout (every task a lane pair
+    or quad of its own, at most 1,024 lanes): n = 2,048 with two lanes per
+    task is the largest that takes it; n = 2,049 falls back to one lane per
+    task with cached edge indices; n = 1,025 with four lanes per task cannot
+    hold every task and walks slots.  Each against the oracle, 25 steps."""
+    m = 3 * n
+    nn, u, v, w = inputs.gnm(n, m, 120 + n)
+    g = psa.Graph.from_edges(ctx, nn, u, v, w, maxcut=True)
+    S, T = 25, 5
+    i0 = oracle.schedule(S, 0.02, 0.9)
+    lam, dl, thr = oracle.variability(nn, 31, 0.1, 0.2, 0.2, 0.7)
+    job = psa.Job(ctx, g, S, T, seed=31, i0=i0, sigma_lambda=0.1, sigma_delta=0.2,
+                  sigma_nu=0.2, p_mean=0.7, trials_per_group=1, lanes_per_task=lpt,
+                  path=psa.PSA_PATH_CSR)
+    job.step(11)
+    job.step(S - 11)
+    ref = oracle.anneal(nn, u, v, -w, None, i0, lam, dl, thr, 31, 0, T)
+    np.testing.assert_array_equal(job.read_spins(), ref[0])
+
+
+@pytest.mark.parametrize("window", [4, 40])
+def test_tapsa_windows_in_lds_and_device_memory(psa, ctx, window):
+    """TApSA on the fast layout: a window of 4 on n = 1,500 keeps the windows
+    in LDS (24 KB), 40 keeps them in device memory (240 KB); both resume
+    across launches and equal the oracle."""
+    n, u, v, w = inputs.gnm(1500, 4500, 97)
+    g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
+    S, T = 30, 6
+    i0 = oracle.schedule(S, 0.02, 0.9)
+    lam, dl, thr = oracle.variability(n, 23, 0.1, 0.1, 0.1, 0.8)
+    job = psa.Job(ctx, g, S, T, seed=23, i0=i0, sigma_lambda=0.1, sigma_delta=0.1,
+                  sigma_nu=0.1, p_mean=0.8, trials_per_group=1, lanes_per_task=2,
+                  path=psa.PSA_PATH_CSR, algorithm=psa.PSA_ALG_TAPSA, window=window)
+    ref = oracle.init_spins(n, 23, 0, T)
+    ring = None
+    t = 0
+    for k in (3, 9, 18):
+        job.step(k)
+        ref, ring = oracle.run_tapsa(n, u, v, -w, None, i0, lam, dl, thr, window, 23, 0, T,
+                                     t, t + k, ref, ring)
+        t += k
+        np.testing.assert_array_equal(job.read_spins(), ref, err_msg=f"after step {t}")
