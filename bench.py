@@ -34,37 +34,48 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic 32-bit lane-operations per p-bit update:
-# one Philox4x32-10 block = 10 rounds x (2 32x32->64 multiplies + 4 xor) = 60,
-# shared by the 4 p-bits of a task; the timing gate needs a second block.
-PHILOX_BLOCK_OPS = 60
+# Algorithmic 32-bit lane-operations per p-bit update: the fewest VALU
+# instructions the method's arithmetic takes on gfx950 (a lower bound on what
+# a kernel issues).  One Philox4x32-10 block = 10 rounds x (2 32x32->64
+# multiplies, one instruction each, + 2 three-input XOR) = 40, shared by the
+# 4 p-bits of a task; the timing gate needs a second block.
+PHILOX_BLOCK_OPS = 40
 OPS_R_MAP = 4          # shift-or, subtract, convert, scale
 OPS_GATE_MAP = 2       # shift, compare
 OPS_PREACT = 3.25      # int->float, + delta, * a  (a = I0*lambda once per quad)
-OPS_TANH = 17          # |x|, scale, round, sub, 7 fma, ldexp, add, div, sub, sign
-OPS_DECIDE = 2         # compare with r, select
+OPS_DECIDE = 11        # tanh estimate (clamp, scale, 2^v, +1, reciprocal, fma,
+                       # sign), distance to r, two compares, select
+# neighbour term per edge: a three-input add takes two neighbour bytes of one
+# trial; one add of a packed word takes a neighbour of four trials
+OPS_EDGE_ONE_TRIAL = 0.5
+OPS_EDGE_FOUR_TRIALS = 0.25
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes, one 32-bit VALU op per lane per clock
 # at 2.4 GHz (the 157.3 TFLOP/s FP32 figure counts an FMA as 2 and dual issue).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-OPS_STALL = 3  # shift-compare of the stall word, select / memory op of the held input
+OPS_STALL = 3  # shift-compare of the stall word, select of the held input
+OPS_WINDOW = 2  # window sum: add the entering field, subtract the leaving one
 OPS_MEAN = 10  # window mean: convert, correctly rounded divide
 OPS_PERIOD = 6  # period test: convert, reciprocal, multiply, truncate, multiply-subtract, compare
 MFMA_I8_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak, TOP/s
 HBM_PEAK_GBS = 8000.0
 
 
-def ops_per_update(mean_degree: float, timing: bool, algorithm: str = "psa",
-                   window: int = 4) -> float:
-    """Algorithmic 32-bit lane-operations of one p-bit update.  SpSA adds a
-    quarter Philox block for the stall word, its compare and the load or
-    store of the held input; TApSA the window store, window - 1 loads and
-    adds, and the mean (convert, divide)."""
+def ops_per_update(field_ops: float, timing: bool, algorithm: str = "psa") -> float:
+    """Algorithmic 32-bit lane-operations of one p-bit update; field_ops is
+    the neighbour term (mean degree x the per-edge cost of the sweep).  SpSA
+    adds a quarter Philox block for the stall word and its compare and
+    select; TApSA the window-sum update and the mean (convert, divide)."""
     spsa = algorithm == "spsa"
     philox = PHILOX_BLOCK_OPS / 4 * ((2 if timing else 1) + (1 if spsa else 0))
-    extra = OPS_STALL if spsa else (2 * window + OPS_MEAN if algorithm == "tapsa" else 0)
-    return (philox + OPS_R_MAP + (OPS_GATE_MAP if timing else 0) + mean_degree
-            + OPS_PREACT + OPS_TANH + OPS_DECIDE + extra)
+    extra = OPS_STALL if spsa else (OPS_WINDOW + OPS_MEAN if algorithm == "tapsa" else 0)
+    return (philox + OPS_R_MAP + (OPS_GATE_MAP if timing else 0) + field_ops
+            + OPS_PREACT + OPS_DECIDE + extra)
+
+
+def edge_ops(job_info) -> float:
+    """Per-edge cost of the neighbour term for the sweep a job runs."""
+    return OPS_EDGE_FOUR_TRIALS if job_info["trials_per_group"] == 4 else OPS_EDGE_ONE_TRIAL
 
 
 def cpu_baseline(spec, budget_s: float = 15.0, stall24=None, window=None, t_res=None):
@@ -227,14 +238,15 @@ def main():
     updates = n * T * S
     value = updates * args.steps / wall
     timing = spec["sigma_nu"] > 0 or spec["p_mean"] < 1.0
-    mean_deg = info["nnz"] / n
-    opu = ops_per_update(mean_deg, timing, args.algorithm, args.window)
+    jinfo = job.info()
+    field_ops = 0.0 if jinfo["path"] == psa.PSA_PATH_DENSE else info["nnz"] / n * edge_ops(jinfo)
+    opu = ops_per_update(field_ops, timing, args.algorithm)
     if args.t_res > 0:
         # period mode: per cycle and p-bit, t_res period checks plus the
         # expected number of firings (t_res / period) of an ungated update
         per = psa.periods_draw(n, spec["seed"], spec["sigma_nu"], args.t_res)
         fires = float(np.mean(args.t_res / per.astype(np.float64)))
-        opu = args.t_res * OPS_PERIOD + fires * ops_per_update(mean_deg, False)
+        opu = args.t_res * OPS_PERIOD + fires * ops_per_update(field_ops, False)
     achieved = opu * updates / (kernel_ms * 1e-3) / 1e12
     line = {
         "metric": "p-bit updates/s (n x trials x steps / s), 1 GPU",
@@ -337,7 +349,7 @@ def bench_batch(args):
             dense_bytes += (np_ * np_ * (0.25 if enc == 2 else 1.0) * tiles
                             + 2 * n * sp["trials"]) * sp["steps"]
         else:
-            valu_ops += ops_per_update(info["nnz"] / n, False) * upd
+            valu_ops += ops_per_update(info["nnz"] / n * edge_ops(jobs[-1].info()), False) * upd
     S = max(sp["steps"] for sp in specs)
 
     def batched(ev=None):

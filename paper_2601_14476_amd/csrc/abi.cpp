@@ -71,6 +71,7 @@ void job_free(psa_job *j) {
     dev_free(j->d_spins);
     dev_free(j->d_xs);
     dev_free(j->d_ring);
+    dev_free(j->d_pp);
     dev_free(j->d_scratch);
     psa_ctx *ctx = j->retained ? j->ctx : nullptr;
     psa_graph *g = j->graph_ref;
@@ -502,6 +503,18 @@ psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *
     if ((st = dev_upload(&j->d_delta, dlt.data(), dlt.size(), "job upload")) != PSA_OK) return st;
     if ((st = dev_upload(&j->d_thr24, thr.data(), thr.size(), "job upload")) != PSA_OK) return st;
     if ((st = dev_upload(&j->d_order, order.data(), order.size(), "job upload")) != PSA_OK) return st;
+    if (g->dev.ell) {
+        // per-p-bit constants of the ELL four-trial sweep, one 16-byte load each
+        std::vector<int32_t> pp(4 * static_cast<size_t>(n4));
+        for (int32_t i = 0; i < n4; ++i) {
+            pp[4 * i] = g->h_host[i] - (g->row_ptr_host[i + 1] - g->row_ptr_host[i]);
+            memcpy(&pp[4 * i + 1], &lam[i], 4);
+            memcpy(&pp[4 * i + 2], &dlt[i], 4);
+            pp[4 * i + 3] = static_cast<int32_t>(thr[i]);
+        }
+        if ((st = dev_upload(&j->d_pp, pp.data(), pp.size(), "job upload")) != PSA_OK) return st;
+        j->run.pp = j->d_pp;
+    }
     const size_t spin_bytes = static_cast<size_t>(n) * static_cast<size_t>(j->run.t4);
     if ((st = dev_upload<int8_t>(&j->d_spins, nullptr, spin_bytes, "job spins")) != PSA_OK) return st;
     if (j->plan.dense) {

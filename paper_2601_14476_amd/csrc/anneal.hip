@@ -43,6 +43,9 @@ struct Views {
     const uint32_t *pk32;
     const uint16_t *pk16;
     const uint16_t *ux16;
+    const uint32_t *ell;
+    const int32_t *eptr;
+    const int32_t *pp;
 };
 
 __device__ __forceinline__ Words4 block_of(uint32_t t, uint32_t m, uint32_t k, uint32_t tag,
@@ -305,6 +308,26 @@ __device__ __forceinline__ void field_swar(const Views &v, int32_t i, const uint
     L[3] = base + 2 * static_cast<int32_t>(acc >> 24);
 }
 
+// Four trials, unit weights, the task's rows from the per-task ELL array in
+// device memory (16 bytes per group: entry j of the four rows, 4 col | (J <
+// 0), the zero word past a row's end): no masks, one 16-byte load per group.
+__device__ __forceinline__ void field_ell(const Views &v, int32_t m, const uint32_t *cur,
+                                          uint32_t acc[4]) {
+    const unsigned char *cb = reinterpret_cast<const unsigned char *>(cur);
+    const int32_t g0 = v.eptr[m], g1 = v.eptr[m + 1];
+#pragma unroll 2
+    for (int32_t gi = g0; gi < g1; ++gi) {
+        const u32x4 q = load_global_x4(v.ell + 4 * static_cast<size_t>(gi));
+        const uint32_t ev[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const uint32_t w = *reinterpret_cast<const uint32_t *>(cb + (ev[p] & ~3u));
+            const uint32_t neg = 0u - (ev[p] & 1u);
+            acc[p] += w ^ (neg & 0x01010101u);
+        }
+    }
+}
+
 // Four trials, +-1 bytes packed per word, general weights.
 template <int CSR>
 __device__ __forceinline__ void field_words(const Views &v, int32_t i, const uint32_t *cur,
@@ -559,14 +582,26 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
                                                  float i0t, const uint32_t *cur, uint32_t *nxt,
                                                  uint32_t k0, uint32_t k1, const InputState &st) {
     constexpr bool kU = Enc<4, CSR>::kU;
+    // unit weights with the rows in device memory: the ELL rows and the
+    // packed per-p-bit constants (h - deg, lambda, delta, thr24)
+    constexpr bool kEll = CSR == kCsrPack16 && BLK;
     int32_t L[4][4];
     uint32_t word[4], th[4];
     float a[4], d[4];
+    int32_t hd[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const int32_t i = 4 * m + p;
         word[p] = cur[i];
-        th[p] = v.thr[i];
+        if constexpr (kEll) {
+            const u32x4 c = load_global_x4(v.pp + 4 * static_cast<size_t>(i));
+            hd[p] = static_cast<int32_t>(c.x);
+            a[p] = i0t * __uint_as_float(c.y);
+            d[p] = __uint_as_float(c.z);
+            th[p] = c.w;
+        } else {
+            th[p] = v.thr[i];
+        }
     }
     if constexpr (ALG == kAlgPeriod) {
         // t is the sub-step; p-bits whose period does not divide it hold
@@ -577,15 +612,25 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
             return;
         }
     }
+    if constexpr (kEll) {
+        uint32_t acc[4] = {0u, 0u, 0u, 0u};
+        field_ell(v, m, cur, acc);
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const int32_t i = 4 * m + p;
-        a[p] = i0t * v.lam[i];
-        d[p] = v.dlt[i];
-        if constexpr (CSR == kCsrPack16)
-            field_swar<BLK>(v, i, cur, L[p]);
-        else
-            field_words<CSR>(v, i, cur, L[p]);
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                L[p][kk] = hd[p] + 2 * static_cast<int32_t>((acc[p] >> (8 * kk)) & 0xFFu);
+    } else {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int32_t i = 4 * m + p;
+            a[p] = i0t * v.lam[i];
+            d[p] = v.dlt[i];
+            if constexpr (CSR == kCsrPack16)
+                field_swar<BLK>(v, i, cur, L[p]);
+            else
+                field_words<CSR>(v, i, cur, L[p]);
+        }
     }
     const bool need_gate = ALG != kAlgPeriod && ((th[0] < kGateOne) | (th[1] < kGateOne) |
                                                  (th[2] < kGateOne) | (th[3] < kGateOne));
@@ -634,7 +679,8 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
 __host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 __host__ __device__ constexpr size_t spin_buf_bytes(int32_t n4, int32_t tpw, int32_t csr) {
-    return align16(static_cast<size_t>(n4) * tpw * (csr == kCsrUnit ? 2 : 1));
+    // four trials per workgroup: one more word, kept zero (ELL padding entries)
+    return align16(static_cast<size_t>(n4) * tpw * (csr == kCsrUnit ? 2 : 1) + (tpw == 4 ? 4 : 0));
 }
 
 // Distance between the two spin buffers.
@@ -731,6 +777,9 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
         v.pk16 = a.pk16;
         v.ux16 = a.ux16;
     }
+    v.ell = a.ell;
+    v.eptr = a.eptr;
+    v.pp = a.pp;
 
     // spins of this workgroup's trials -> LDS (padding p-bits = +1)
     if constexpr (TPW == 1) {
@@ -759,6 +808,10 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
                                            a.spins + static_cast<size_t>(i) * a.t4 + 4 * q)
                                      : 0x01010101u;
             s0[i] = E::kU ? ((~w >> 7) & 0x01010101u) : w;
+        }
+        if (threadIdx.x == 0) {
+            s0[n4] = 0u;
+            reinterpret_cast<uint32_t *>(buf1)[n4] = 0u;
         }
     }
     __syncthreads();
@@ -1159,6 +1212,9 @@ hipError_t launch_anneal(hipStream_t stream, const DevGraph &g, const DevRun &ru
     // a plan made for another input stage would leave the kernel's LDS
     // layout outside the allocation
     if (lds_need(g, run, plan) > plan.lds_bytes) return hipErrorInvalidValue;
+    // the four-trial sweep over rows in device memory reads the ELL rows
+    if (plan.tpw == 4 && plan.csr == kCsrPack16 && !plan.csr_lds && (!g.ell || !run.pp))
+        return hipErrorInvalidValue;
     AnnealArgs a;
     fill_anneal_args(&a, g, run, order, t_begin, t_end);
     if (plan.tpw == 4) return launch_four_trials(stream, a, plan);
@@ -1185,6 +1241,9 @@ void fill_anneal_args(AnnealArgs *a, const DevGraph &g, const DevRun &run, const
     a->pk32 = g.pk32;
     a->pk16 = g.pk16;
     a->ux16 = g.ux16;
+    a->ell = g.ell;
+    a->eptr = g.eptr;
+    a->pp = run.pp;
     a->h = g.h;
     a->i0 = run.i0;
     a->lam = run.lambda;
@@ -1207,6 +1266,10 @@ bool plan_batch_item(const DevGraph &g, const DevRun &run, int32_t tpw_req, int3
     if (tpw_req == 4) {
         if (!plan_anneal(g, run, 4, 1, 0, max_lds, 1 << 30, &p, why)) return false;
         if (p.csr == kCsrPack16) {
+            if (!p.csr_lds && (!g.ell || !run.pp)) {
+                if (why) *why = "four-trial run without its ELL rows";
+                return false;
+            }
             *variant = p.csr_lds ? kBatchP16Lds4T : kBatchP16Glb4T;
         } else if (p.csr == kCsrPack32) {
             *variant = p.csr_lds ? kBatchP32Lds4T : kBatchP32Glb4T;

@@ -29,6 +29,10 @@ struct Words4 {
 __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1,
                                                 uint32_t c2, uint32_t c3,
                                                 uint32_t k0, uint32_t k1) {
+    // The key is uniform (one per run) and lives in scalar registers; kept
+    // opaque here, so that its schedule is formed on the scalar unit at each
+    // use rather than hoisted out of the loops into spilled registers.
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
         // one 32x32->64 multiply-add instruction per product on gfx950

@@ -58,6 +58,12 @@ struct DevGraph {
     const uint32_t *pk32 = nullptr;    // [nnz] or null
     const uint16_t *pk16 = nullptr;    // [nnz] or null
     const uint16_t *ux16 = nullptr;    // [nnz] or null
+    // unit weights, degree <= 255: per-task ELL rows for the four-trial sweep
+    // streaming edges from device memory; group g = eptr[m] .. eptr[m+1]-1 of
+    // task m holds entry j of rows 4m..4m+3 as 4 col | (J < 0), past a row's
+    // end the zero word 4 n4
+    const uint32_t *ell = nullptr;     // [4 * groups] or null
+    const int32_t *eptr = nullptr;     // [n4/4 + 1] or null
     const int32_t *h = nullptr;        // [n4]
     int64_t w2 = 0;                    // sum_i sum_j J_ij = 2 sum_{i<j} J_ij
 };
@@ -80,6 +86,9 @@ struct DevRun {
     int32_t *ring = nullptr;              // TApSA windows [t4/4][n4][alpha][4], else nullptr
     int32_t alpha = 1;                    // TApSA window
     int32_t t_res = 0;                    // period mode: sub-steps per cycle (thr24 holds periods)
+    // per-p-bit constants [n4][4] of the ELL four-trial sweep: h_i - deg_i,
+    // lambda_i and delta_i (float bits), thr24_i
+    const int32_t *pp = nullptr;
 };
 
 // How the persistent anneal kernel is launched for one run.
@@ -105,6 +114,9 @@ struct AnnealArgs {
     const uint32_t *pk32;
     const uint16_t *pk16;
     const uint16_t *ux16;
+    const uint32_t *ell;
+    const int32_t *eptr;
+    const int32_t *pp;
     const int32_t *h;
     const float *i0;
     const float *lam;
@@ -242,6 +254,8 @@ struct HostGraph {
     std::vector<int32_t> h;     // [n4]
     std::vector<uint32_t> pk32;
     std::vector<uint16_t> pk16, ux16;
+    std::vector<uint32_t> ell;
+    std::vector<int32_t> eptr;
 };
 psa_status host_graph_from_edges(int32_t n, int64_t m, const int32_t *u, const int32_t *v,
                                  const int32_t *val, const int32_t *h, uint32_t flags,
@@ -344,7 +358,10 @@ struct psa_graph {
     int32_t *d_row_ptr = nullptr, *d_col = nullptr, *d_val = nullptr, *d_h = nullptr;
     uint32_t *d_pk32 = nullptr;
     uint16_t *d_pk16 = nullptr, *d_ux16 = nullptr;
+    uint32_t *d_ell = nullptr;
+    int32_t *d_eptr = nullptr;
     std::vector<int32_t> row_ptr_host;  // [n4+4]
+    std::vector<int32_t> h_host;        // [n4]
     std::vector<int32_t> col_host, val_host;  // for the dense matrix, on demand
     void *d_dense = nullptr;            // encoded [np][np] couplings, built on first use
     int32_t np = 0;                     // n rounded up to 128
@@ -369,6 +386,7 @@ struct psa_job {
     int8_t *d_spins = nullptr;
     float *d_xs = nullptr;       // SpSA held inputs
     int32_t *d_ring = nullptr;   // TApSA field windows
+    int32_t *d_pp = nullptr;     // per-p-bit constants of the ELL sweep
     void *d_scratch = nullptr;   // read-out staging
     size_t scratch_bytes = 0;
 };

@@ -132,6 +132,25 @@ psa_status finish_host_graph(int32_t n, const std::vector<int64_t> &row_ptr,
         for (int64_t p = 0; p < nnz; ++p)
             g.ux16[p] = static_cast<uint16_t>(col[p] + (val[p] < 0 ? g.n4 : 0));
     }
+    if (n <= 32768 && info.unit_weights && max_deg <= 255) {
+        // per-task ELL: task m pads its four rows to the longest of them
+        const int32_t tasks = g.n4 / 4;
+        g.eptr.assign(static_cast<size_t>(tasks) + 1, 0);
+        for (int32_t m = 0; m < tasks; ++m) {
+            int32_t d = 0;
+            for (int32_t p = 0; p < 4; ++p) d = std::max(d, g.rp32[4 * m + p + 1] - g.rp32[4 * m + p]);
+            g.eptr[m + 1] = g.eptr[m] + d;
+        }
+        const uint32_t zero = 4u * static_cast<uint32_t>(g.n4);
+        g.ell.assign(4 * static_cast<size_t>(g.eptr[tasks]), zero);
+        for (int32_t m = 0; m < tasks; ++m)
+            for (int32_t p = 0; p < 4; ++p) {
+                const int32_t i = 4 * m + p;
+                for (int32_t e = g.rp32[i]; e < g.rp32[i + 1]; ++e)
+                    g.ell[4 * (static_cast<size_t>(g.eptr[m]) + (e - g.rp32[i])) + p] =
+                        4u * static_cast<uint32_t>(col[e]) | (val[e] < 0 ? 1u : 0u);
+            }
+    }
     g.col = std::move(col);
     g.val = std::move(val);
     *out = std::move(g);
@@ -162,7 +181,8 @@ void graph_release(psa_graph *g) {
     for (void *p : {static_cast<void *>(g->d_row_ptr), static_cast<void *>(g->d_col),
                     static_cast<void *>(g->d_val), static_cast<void *>(g->d_h),
                     static_cast<void *>(g->d_pk32), static_cast<void *>(g->d_pk16),
-                    static_cast<void *>(g->d_ux16), static_cast<void *>(g->d_dense)})
+                    static_cast<void *>(g->d_ux16), static_cast<void *>(g->d_dense),
+                    static_cast<void *>(g->d_ell), static_cast<void *>(g->d_eptr)})
         if (p) (void)hipFree(p);
     psa_ctx *ctx = g->retained ? g->ctx : nullptr;
     delete g;
@@ -346,6 +366,8 @@ psa_status upload_graph(psa_ctx *ctx, HostGraph &&hg, psa_graph **out) {
     if ((st = upload(&g->d_pk32, hg.pk32)) != PSA_OK) return st;
     if ((st = upload(&g->d_pk16, hg.pk16)) != PSA_OK) return st;
     if ((st = upload(&g->d_ux16, hg.ux16)) != PSA_OK) return st;
+    if ((st = upload(&g->d_ell, hg.ell)) != PSA_OK) return st;
+    if ((st = upload(&g->d_eptr, hg.eptr)) != PSA_OK) return st;
     g->dev.n = hg.n;
     g->dev.n4 = hg.n4;
     g->dev.nnz = hg.nnz;
@@ -357,8 +379,11 @@ psa_status upload_graph(psa_ctx *ctx, HostGraph &&hg, psa_graph **out) {
     g->dev.pk32 = g->d_pk32;
     g->dev.pk16 = g->d_pk16;
     g->dev.ux16 = g->d_ux16;
+    g->dev.ell = g->d_ell;
+    g->dev.eptr = g->d_eptr;
     g->dev.w2 = hg.w2;
     g->row_ptr_host = std::move(hg.rp32);
+    g->h_host = std::move(hg.h);
     g->col_host = std::move(hg.col);
     g->val_host = std::move(hg.val);
     *out = g.release();

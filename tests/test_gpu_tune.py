@@ -1,8 +1,8 @@
 """GPU tests of the autotuner: every configuration it can pick gives the
 results of the plain run (launch shape and path never change results), the
 tuning cache is keyed by shape class, and the measured choice follows the
-structure of the graph where the gap is large (long dense rows -> matrix
-cores, short sparse rows -> CSR)."""
+structure of the graph where the gap is large (rows of ~600 entries ->
+matrix cores, short sparse rows -> CSR)."""
 import numpy as np
 import pytest
 
@@ -57,7 +57,7 @@ def test_autotune_alone_and_tuned_job_exact(psa, ctx):
 
 
 def test_autotune_batch_follows_row_length(psa, ctx):
-    n, u, v, w = inputs.erdos_renyi(2000, 0.08, 63)          # ~160 entries a row
+    n, u, v, w = inputs.erdos_renyi(2000, 0.3, 63)           # ~600 entries a row
     dense_g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
     r = psa.autotune(ctx, dense_g, 200, 64, 1, probe_steps=8, batch=True)
     assert r["path"] == psa.PSA_PATH_DENSE, r
