@@ -61,10 +61,12 @@ __device__ __forceinline__ uint32_t swap_pair(uint32_t v) {
     return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(v), 0xB1, 0xF, 0xF, false));
 }
 
-// r in (-1, 1): odd multiple of 2^-24 from the top 25 bits of a word.
+// r in (-1, 1): the odd multiple of 2^-24 given by the top 25 bits of a word
+// with the lowest forced to one, ((u >> 7) | 1) 2^-24 - 1 = (u >> 8) 2^-23 +
+// 2^-24 - 1: the 24-bit integer converts exactly and the single fma rounds
+// nothing (its result is representable).
 __device__ __forceinline__ float r_of(uint32_t u) {
-    const int32_t j = static_cast<int32_t>((u >> 7) | 1u) - static_cast<int32_t>(kGateOne);
-    return static_cast<float>(j) * 0x1p-24f;
+    return fmaf(static_cast<float>(u >> 8), 0x1p-23f, 0x1p-24f - 1.0f);
 }
 
 // Timing gate for a p-bit whose update probability is thr24 / 2^24 (< 1).
