@@ -1159,6 +1159,10 @@ bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t 
     const size_t sp = 2 * spin_stride(n4, p.tpw, p.lpt, p.csr) +
                       ring_lds_bytes(n4, p.tpw, p.lpt, p.csr, run.ring != nullptr, run.alpha);
     if (sp > max_lds) {
+        // four trials' spin state too large: one trial per workgroup if the
+        // choice was the planner's
+        if (p.tpw == 4 && tpw_req != 4)
+            return plan_anneal(g, run, 1, lpt_req, block_req, max_lds, num_cu, plan, why);
         if (why)
             *why = "n = " + std::to_string(g.n) + " does not fit the LDS-resident spin state (" +
                    std::to_string(sp) + " > " + std::to_string(max_lds) + " bytes)";

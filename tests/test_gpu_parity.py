@@ -659,3 +659,22 @@ def test_tapsa_windows_in_lds_and_device_memory(psa, ctx, window):
                                      t, t + k, ref, ring)
         t += k
         np.testing.assert_array_equal(job.read_spins(), ref, err_msg=f"after step {t}")
+
+
+def test_four_trial_state_beyond_lds_falls_back(psa, ctx):
+    """With 1,024 trials the planner takes four trials per workgroup, whose
+    spin state (2 x 4 bytes per p-bit) does not fit LDS at n = 21,000; it
+    then runs one trial per workgroup instead.  Sampled trials against the
+    oracle."""
+    n, u, v, w = inputs.gnm(21000, 42000, 131)
+    g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
+    S, T = 6, 1024
+    job = psa.Job(ctx, g, S, T, 5, sigma_lambda=0.1, sigma_delta=0.1, sigma_nu=0.1, p_mean=0.8,
+                  path=psa.PSA_PATH_CSR)
+    assert job.info()["trials_per_group"] == 1
+    job.step(S)
+    spins = job.read_spins()
+    i0, lam, dl, thr = _oracle_params(n, u, v, w, S, 5, 0.1, 0.1, 0.1, 0.8)
+    for k in (0, 511, 1023):
+        ref = oracle.anneal(n, u, v, -w, None, i0, lam, dl, thr, 5, k, k + 1)
+        np.testing.assert_array_equal(spins[k], ref[0][0], err_msg=f"trial {k}")
