@@ -16,10 +16,17 @@
 //   kCsrPack16 (TPW 4, every |J| = 1, degree <= 255): four trials' 0/1 bytes
 //              per word; pk16[e] = j << 1 | (J < 0); x_e = word_j XOR
 //              (J < 0 ? 0x01010101 : 0), summed four trials per 32-bit add.
+//              With the rows in device memory the sweep reads the per-task
+//              ELL groups instead (entry j of a task's four rows in 16 bytes).
 //   kCsrPack32 pk32[e] = j | J << 16; spins as +-1 bytes; general weights.
 //   kCsrPair   separate col / val arrays; spins as +-1 bytes; general weights.
 // Per-p-bit arrays are padded to n4 = 4 ceil(n/4) entries (padding p-bits have
 // no edges and never fire), row_ptr to n4 + 4 entries.
+//
+// One trial per workgroup with every task on lanes of its own (tasks x LPT <=
+// BLOCK) runs "resident": a lane keeps its task's constants, the input-stage
+// state and (unit weights, LPT 2 or 4: the fast layout below) the LDS
+// addresses of its rows' neighbours in registers for the whole launch.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
