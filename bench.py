@@ -138,6 +138,53 @@ def cpu_baseline(spec, budget_s: float = 15.0, stall24=None, window=None, t_res=
                       f"({updates:.3g} updates, {dt:.2f} s wall on {len(parts)} threads)"}
 
 
+def cpu_baseline_batch(graphs, steps, trials, budget_s: float = 15.0):
+    """Time the oracle on a bounded sample of the batched mix: the first
+    trials of the first graphs (alternately G(n, p) and degree 4-8) over the
+    full schedule, about budget_s of single-thread work, spread over up to 16
+    threads.  graphs: [(n, u, v, w, seed)]."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    oracle.build(force=False)
+    cores = min(os.cpu_count() or 1, 16)
+    units = []   # (graph index, trial)
+    prepared = []
+    est = 0.0
+    for gi, (n, u, v, w, seed) in enumerate(graphs):
+        i0, _, _ = oracle.schedule_paper(n, u, v, -w, steps)
+        lam, dlt, thr = oracle.variability(n, seed, 0.0, 0.0, 0.0, 1.0)
+        prepared.append((n, u, v, w, seed, i0, lam, dlt, thr))
+        # calibrate on this graph: one trial, a few steps
+        cal = min(steps, 20)
+        t0 = time.perf_counter()
+        oracle.run(n, u, v, -w, None, i0, lam, dlt, thr, seed, 0, 1, 0, cal,
+                   oracle.init_spins(n, seed, 0, 1))
+        per_trial = (time.perf_counter() - t0) / cal * steps
+        k = 0
+        while k < min(trials, 4) and est < budget_s:
+            units.append((gi, k))
+            est += per_trial
+            k += 1
+        if est >= budget_s:
+            break
+
+    def run(unit):
+        gi, k = unit
+        n, u, v, w, seed, i0, lam, dlt, thr = prepared[gi]
+        oracle.anneal(n, u, v, -w, None, i0, lam, dlt, thr, seed, k, k + 1)
+        return n * steps
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(min(cores, len(units))) as ex:
+        updates = sum(ex.map(run, units))
+    dt = time.perf_counter() - t0
+    used = sorted({gi for gi, _ in units})
+    return {"value": updates / dt, "unit": "p-bit updates/s", "cores": min(cores, len(units)),
+            "kind": "oracle",
+            "sample": f"{len(units)} trials of graphs {used[0]}..{used[-1]} of the mix x all "
+                      f"{steps} steps ({updates:.3g} updates, {dt:.2f} s wall)"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -443,6 +490,12 @@ def bench_batch(args):
         },
         "roofline": roof,
     }
+    if not args.no_cpu_baseline:
+        sample = []
+        for sp in specs[:16]:
+            n, u, v, w = inputs.make_graph(sp["graph"])
+            sample.append((n, u, v, w, sp["seed"]))
+        line["cpu_baseline"] = cpu_baseline_batch(sample, S, specs[0]["trials"])
     print(json.dumps(line), flush=True)
 
 
