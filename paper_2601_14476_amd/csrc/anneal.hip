@@ -77,16 +77,19 @@ struct Enc {
 // 1,024 lanes of tasks): the two spin buffers lie kFastStride bytes apart and
 // each holds four copies of the n4 spins, u, 1 - u, 64 u and 64 (1 - u), then
 // a zero byte at 4 n4.  A lane that owns its task for the whole launch keeps
-// the LDS addresses of its rows' first kFastSlots edges in registers (edges
-// of its second row point into the 64x copies, unused slots at the zero
-// byte), so one sum of those bytes holds both rows' counts: the low six bits
-// and the rest.  With the buffer distance a constant, the step loop unrolled
+// the LDS addresses of its rows' first fast_slots<P>() edges in registers
+// (edges of its second row point into the 64x copies, unused slots at the
+// zero byte), so one sum of those bytes holds both rows' counts: the low six
+// bits and the rest; a lane with one row caches twice as many.  With the buffer distance a constant, the step loop unrolled
 // by two reads either buffer through the load's immediate offset.
 // ---------------------------------------------------------------------------
 constexpr int32_t kFastStride = 8256;  // >= 4 n4 + 1 for every n4 the layout admits
-constexpr int kFastSlots = 32;
-constexpr int kFastChunk = 8;  // slots per wave-uniform skip test
+constexpr int kFastSlots = 32;   // two rows per lane (LPT 2)
+constexpr int kFastSlots1 = 64;  // one row per lane (LPT 4)
+constexpr int kFastChunk = 8;    // slots per wave-uniform skip test
 static_assert(kFastSlots < 64, "the first row's count must fit the low six bits");
+template <int P>
+constexpr int fast_slots() { return P == 1 ? kFastSlots1 : kFastSlots; }
 
 __host__ __device__ constexpr bool fast_layout(int32_t tpw, int32_t lpt, int32_t csr, int32_t n4) {
     return tpw == 1 && csr == kCsrUnit && (lpt == 2 || lpt == 4) && (n4 / 4) * lpt <= 1024;
@@ -235,18 +238,19 @@ __device__ __forceinline__ void field_unit_cached(const Views &v, const int32_t 
 // P = 1 or 2, and the number of kFastChunk-slot chunks that some lane of the
 // wavefront uses (uniform; tasks are ordered heaviest first, so the lanes of a
 // wavefront have rows of similar length).
+template <int P>
 struct FastCache {
-    uint32_t a[kFastSlots];
+    uint32_t a[fast_slots<P>()];
     uint32_t chunks;
 };
 
 template <int P>
-__device__ __forceinline__ FastCache load_fast_cache(const Views &v, const int32_t *rp, uint32_t base0,
+__device__ __forceinline__ FastCache<P> load_fast_cache(const Views &v, const int32_t *rp, uint32_t base0,
                                                      int32_t n4) {
-    FastCache c;
+    FastCache<P> c;
     const int32_t e0 = rp[0], split = rp[1], e2 = rp[P];
 #pragma unroll
-    for (int j = 0; j < kFastSlots; ++j) {
+    for (int j = 0; j < fast_slots<P>(); ++j) {
         const int32_t e = e0 + j;
         uint32_t x = 4u * static_cast<uint32_t>(n4);  // the zero byte
         if (e < e2) x = v.ux16[e] + (e >= split ? 2u * static_cast<uint32_t>(n4) : 0u);
@@ -256,21 +260,24 @@ __device__ __forceinline__ FastCache load_fast_cache(const Views &v, const int32
 }
 
 // Fields of the lane's P rows from the buffer at LDS offset OFF (cur points
-// there): the cached slots in one sum, then the edges past kFastSlots.
+// there): the cached slots in one sum, then the edges past them.
 template <int P, uint32_t OFF, bool BLK>
 __device__ __forceinline__ void field_fast(const Views &v, const int32_t *rp, const int32_t *h,
-                                           const FastCache &c, const uint8_t *cur, int32_t L[P]) {
+                                           const FastCache<P> &c, const uint8_t *cur, int32_t L[P]) {
     uint32_t acc = 0u;
+    constexpr int K = fast_slots<P>();
 #pragma unroll
-    for (int g = 0; g < kFastSlots / kFastChunk; ++g) {
+    for (int g = 0; g < K / kFastChunk; ++g) {
         if (static_cast<uint32_t>(g) < c.chunks) {
 #pragma unroll
             for (int j = 0; j < kFastChunk; ++j) acc += lds_byte<OFF>(c.a[kFastChunk * g + j]);
         }
     }
     const int32_t e0 = rp[0], split = rp[1], e2 = rp[P];
-    int32_t c0 = static_cast<int32_t>(acc & 63u), c1 = static_cast<int32_t>(acc >> 6);
-    for (int32_t e = e0 + kFastSlots; e < e2; ++e) {
+    // one row: the whole sum; two rows: the low six bits and the rest
+    int32_t c0 = static_cast<int32_t>(P == 1 ? acc : (acc & 63u));
+    int32_t c1 = static_cast<int32_t>(P == 1 ? 0u : (acc >> 6));
+    for (int32_t e = e0 + K; e < e2; ++e) {
         const uint32_t idx = BLK ? *(const uint16_t __attribute__((address_space(1))) *)(v.ux16 + e)
                                  : v.ux16[e];
         const int32_t x = cur[idx];
@@ -473,7 +480,7 @@ enum : int { kFieldPlain = 0, kFieldEdgeCache = 1, kFieldFast0 = 2, kFieldFast1 
 
 template <int CSR, int LPT, int ALG, bool BLK, int FIELD, bool LRING = false>
 __device__ __forceinline__ uint32_t task_one_trial(const Views &v, const TaskConst<4 / LPT> &c,
-                                                   const EdgeCache *ec, const FastCache *fc,
+                                                   const EdgeCache *ec, const FastCache<4 / LPT> *fc,
                                                    LaneInput<4 / LPT> *li, int32_t *lring, uint32_t sub, uint32_t k,
                                                    uint32_t t, float i0t, const unsigned char *cur,
                                                    uint32_t k0, uint32_t k1, const InputState &st) {
@@ -861,7 +868,7 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
     const bool fast = fast_lay && resident;
     TaskConst<P> own{};
     EdgeCache own_edges[P == 4 ? 2 : 1] = {};
-    FastCache own_fast = {};
+    FastCache<P> own_fast = {};
     LaneInput<P> own_in = {};
     if (owns) {
         own = load_task<LPT>(v, v.order[threadIdx.x / LPT], sub);
@@ -905,7 +912,7 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
         if (fast) {
             // slot chunks the wavefront needs: the largest row-pair length of
             // its lanes (every lane of the wavefront takes part)
-            int32_t cnt = owns ? min(own.rp[P] - own.rp[0], kFastSlots) : 0;
+            int32_t cnt = owns ? min(own.rp[P] - own.rp[0], fast_slots<P>()) : 0;
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) cnt = max(cnt, __shfl_xor(cnt, off));
             own_fast.chunks = static_cast<uint32_t>(

@@ -637,6 +637,28 @@ def test_fast_layout_boundaries(psa, ctx, n, lpt):
     np.testing.assert_array_equal(job.read_spins(), ref[0])
 
 
+@pytest.mark.parametrize("p", [0.12, 0.3])
+def test_one_row_lanes_past_cached_slots(psa, ctx, p):
+    """Four lanes per task (one row per lane) on the fast layout cache 64 slot
+    addresses per lane; G(400, p) rows of about 48 (p = 0.12) and 120 edges
+    (p = 0.3) end before and after the cached slots, and wavefronts mix both
+    near 64.  Against the oracle, 20 steps."""
+    nn, u, v, w = inputs.erdos_renyi(400, p, 71, weights="pm1")
+    g = psa.Graph.from_edges(ctx, nn, u, v, w, maxcut=True)
+    deg = np.bincount(np.concatenate([u, v]), minlength=nn)
+    S, T = 20, 4
+    i0 = oracle.schedule(S, 0.02, 0.9)
+    lam, dl, thr = oracle.variability(nn, 19, 0.1, 0.2, 0.2, 0.7)
+    job = psa.Job(ctx, g, S, T, seed=19, i0=i0, sigma_lambda=0.1, sigma_delta=0.2,
+                  sigma_nu=0.2, p_mean=0.7, trials_per_group=1, lanes_per_task=4,
+                  path=psa.PSA_PATH_CSR)
+    _say(f"n=400 p={p} degree {deg.min()}..{deg.max()}")
+    job.step(7)
+    job.step(S - 7)
+    ref = oracle.anneal(nn, u, v, -w, None, i0, lam, dl, thr, 19, 0, T)
+    np.testing.assert_array_equal(job.read_spins(), ref[0])
+
+
 @pytest.mark.parametrize("window", [4, 40])
 def test_tapsa_windows_in_lds_and_device_memory(psa, ctx, window):
     """TApSA on the fast layout: a window of 4 on n = 1,500 keeps the windows
