@@ -16,8 +16,8 @@
 //             registers with v_perm_b32 just before the matrix instruction.
 //   T2 words: one uint32 per (row i, 64-column k-tile, 16-column lane group
 //   g); column 64 ktile + 16 g + 4d + b sits in bits 8b + 2d .. 8b + 2d + 1
-//   (d = dword of the operand, b = byte), so that (word >> 2d) & 0x03030303
-//   is a byte selector for dword d.  The words are tiled in the order a
+//   (d = dword of the operand, b = byte): fields of even dwords in bits 0-1
+//   of a byte (of word >> 4 for d = 2), of odd dwords in bits 2-3.  The words are tiled in the order a
 //   wave loads them: per 64-row tile and 128-column chunk, 2 KB as two
 //   1 KB halves of [64 lanes][4 words]; word j of lane l in half h is row
 //   16 (2h + j/2) + l % 16 of the tile, k-tile j % 2 of the chunk, group
@@ -53,14 +53,22 @@ constexpr int kLdsStride = kKC + 16; // padded LDS row of the spin tile (bytes)
 constexpr int kWaveRows = 64;        // four 16-row blocks per wave
 constexpr int kGroupRows = 256;      // rows per workgroup
 
-// byte selector s in {0, 1, 2} -> {0x00, 0x01, 0xFF}, four bytes at once
-__device__ __forceinline__ int32_t t2_dword(uint32_t word, int d) {
-    const uint32_t sel = (word >> (2 * d)) & 0x03030303u;
-    return static_cast<int32_t>(__builtin_amdgcn_perm(0u, 0x00FF0100u, sel));
+// Field f in {0, 1, 2} -> byte {0x00, 0x01, 0xFF}, four bytes at once.
+// Even dwords: the field in bits 0-1 of each byte is a selector of the low
+// source's bytes 0x00, 0x01, 0xFF.  Odd dwords: the field in bits 2-3, masked
+// in place, is the selector 0, 4 or 8: the low source's byte 0 (0x00), the
+// high source's byte 0 (0x01), or the sign of the low source's byte 1 (0xFF).
+// So one mask per dword and one shift per pair, no shift per dword.
+__device__ __forceinline__ int32_t t2_even(uint32_t w) {
+    return static_cast<int32_t>(__builtin_amdgcn_perm(0u, 0x00FF0100u, w & 0x03030303u));
+}
+__device__ __forceinline__ int32_t t2_odd(uint32_t w) {
+    return static_cast<int32_t>(__builtin_amdgcn_perm(0x00000001u, 0x0000FF00u, w & 0x0C0C0C0Cu));
 }
 
 __device__ __forceinline__ v4i t2_unpack(uint32_t word) {
-    return v4i{t2_dword(word, 0), t2_dword(word, 1), t2_dword(word, 2), t2_dword(word, 3)};
+    const uint32_t hi = word >> 4;
+    return v4i{t2_even(word), t2_odd(word), t2_even(hi), t2_odd(hi)};
 }
 
 // Device-global views of pointers read from the job table (so that loads
