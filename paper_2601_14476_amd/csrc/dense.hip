@@ -17,9 +17,10 @@
 //   T2 words: one uint32 per (row i, 64-column k-tile, 16-column lane group
 //   g); column 64 ktile + 16 g + 4d + b sits in bits 8b + 2d .. 8b + 2d + 1
 //   (d = dword of the operand, b = byte): fields of even dwords in bits 0-1
-//   of a byte (of word >> 4 for d = 2), of odd dwords in bits 2-3.  The words are tiled in the order a
-//   wave loads them: per 64-row tile and 128-column chunk, 2 KB as two
-//   1 KB halves of [64 lanes][4 words]; word j of lane l in half h is row
+//   of a byte (of word >> 4 for d = 2), of odd dwords in bits 2-3.  The
+//   words are tiled in the order a wave loads them: per 64-row tile and
+//   128-column chunk, 2 KB as two 1 KB halves of [64 lanes][4 words]; word
+//   j of lane l in half h is row
 //   16 (2h + j/2) + l % 16 of the tile, k-tile j % 2 of the chunk, group
 //   l / 16.  A lane's fragments for a chunk are two 16-byte loads, and each
 //   load instruction of the wave reads 1 KB contiguous.
