@@ -23,6 +23,7 @@ Besides the contract fields the JSON line carries:
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -59,6 +60,42 @@ OPS_MEAN = 10  # window mean: convert, correctly rounded divide
 OPS_PERIOD = 6  # period test: convert, reciprocal, multiply, truncate, multiply-subtract, compare
 MFMA_I8_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak, TOP/s
 HBM_PEAK_GBS = 8000.0
+
+
+TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "hbm_traffic_by_workload.md")
+
+
+def source_digest() -> str:
+    """sha256 (first 16 hex digits) over the library's sources: the C header
+    and every file under csrc/, names and bytes, in name order."""
+    h = hashlib.sha256()
+    files = [os.path.join(ROOT, "include", "psa.h")]
+    csrc = os.path.join(ROOT, "paper_2601_14476_amd", "csrc")
+    files += [os.path.join(csrc, f) for f in sorted(os.listdir(csrc))
+              if f.endswith((".hip", ".hpp", ".cpp", ".h"))]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` on `workload`, from the rocprofv3
+    FETCH_SIZE / WRITE_SIZE table under profiles/ (already scaled by the
+    copy-kernel calibration), or None when no row matches or the library's
+    sources differ from those the counters were taken on."""
+    try:
+        with open(TRAFFIC_TABLE) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    digest = source_digest()
+    for ln in lines:
+        cells = [c.strip().strip("`") for c in ln.strip().strip("|").split("|")]
+        if len(cells) == 6 and cells[0] == workload and cells[1] == kernel and cells[5] == digest:
+            return int(cells[4].replace(",", ""))
+    return None
 
 
 def ops_per_update(field_ops: float, timing: bool, algorithm: str = "psa") -> float:
@@ -216,7 +253,13 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times); "
                          "used to scale the HBM traffic counters")
+    ap.add_argument("--source-digest", action="store_true",
+                    help="only print the digest of the library's sources that the HBM "
+                         "traffic table is keyed on")
     args = ap.parse_args()
+    if args.source_digest:
+        print(source_digest())
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
               "trials and jobs shard across GPUs without communication, but no "
@@ -329,7 +372,10 @@ def main():
             "peak": VALU_PEAK_TOPS,
             "unit": "TOP/s",
             "frac": achieved / VALU_PEAK_TOPS,
-            "traffic": None,
+            # counters were taken in the default launch of each workload only
+            "traffic": (measured_traffic(args.workload, "dense_step_kernel" if job.dense else "anneal_kernel")
+                        if args.algorithm == "psa" and not args.t_res and args.path == "auto"
+                        and not (args.block or args.tpw or args.lpt) else None),
             "ops_per_update": opu,
             "kernel_ms": kernel_ms,
         },
@@ -551,7 +597,8 @@ def bench_dense(args):
         "roofline": {"bound": bound, "kernel": "dense_step_kernel",
                      "achieved": {"mfma": mfma, "alu": valu, "hbm": hbm}[bound],
                      "peak": {"mfma": MFMA_I8_PEAK_TOPS, "alu": VALU_PEAK_TOPS, "hbm": HBM_PEAK_GBS}[bound],
-                     "unit": "GB/s" if bound == "hbm" else "TOP/s", "frac": fr[bound], "traffic": None,
+                     "unit": "GB/s" if bound == "hbm" else "TOP/s", "frac": fr[bound],
+                     "traffic": measured_traffic("c4-dense", "dense_step_kernel"),
                      "kernel_us_per_step": per_us, "dense_fracs": fr},
     }
     print(json.dumps(line), flush=True)
