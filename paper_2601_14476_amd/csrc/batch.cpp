@@ -158,6 +158,7 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
     std::vector<psa_job *> live;
     std::vector<int32_t> by_enc[2];
     int32_t max_steps = 0, nb[2] = {4, 4};
+    bool plain[2] = {true, true};  // every run of the encoding is plain pSA
     for (int32_t j = 0; j < count; ++j) {
         psa_job *job = jobs[j];
         const psa_graph *g = job->g;
@@ -188,6 +189,7 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
         d.alpha = job->run.alpha;
         d.t_res = job->run.t_res;
         const int32_t e = g->dense_enc == kDenseT2 ? 1 : 0;
+        plain[e] = plain[e] && d.xs == nullptr && d.ring == nullptr && d.t_res == 0;
         by_enc[e].push_back(static_cast<int32_t>(table.size()));
         nb[e] = std::min(nb[e], job->plan.nb);
         table.push_back(d);
@@ -232,7 +234,7 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
         if (len[e] == 0) continue;
         PSA_HIP(psa::launch_dense_steps(ctx->stream2, static_cast<const psa::DenseJob *>(ctx->d_dense_table),
                                         dwork + off[e], static_cast<int32_t>(len[e]), nb[e],
-                                        e == 1 ? kDenseT2 : kDenseI8, max_steps),
+                                        e == 1 ? kDenseT2 : kDenseI8, plain[e], max_steps),
                 "dense step launch");
         launches += max_steps;
     }

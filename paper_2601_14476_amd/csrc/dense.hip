@@ -92,8 +92,10 @@ struct AFrag<kDenseT2> {
     v4i h[2];  // half h, word j: row block 2h + j/2, k-tile j % 2
 };
 
-// NB = 16-trial blocks per workgroup (trial tile = 16 NB).
-template <int NB, int ENC>
+// NB = 16-trial blocks per workgroup (trial tile = 16 NB).  PLAIN: every run
+// of the launch is pSA with one sub-step per step (no held inputs, windows or
+// periods), so the epilogue carries no run-time mode tests.
+template <int NB, int ENC, bool PLAIN>
 __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kernel(const DenseJob *__restrict__ jobs,
                                                          const int4 *__restrict__ work, int32_t t_off) {
     constexpr int kTrials = 16 * NB;
@@ -106,11 +108,11 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
     // launch t_off advances sub-step t_off of this run's sequence: one
     // sub-step per step, or t_res of them in period mode; tau counts
     // sub-steps from the start of the anneal, t is the step (cycle) of tau
-    const int32_t u = jb.t_res > 0 ? jb.t_res : 1;
+    const bool period_mode = !PLAIN && jb.t_res > 0;
+    const int32_t u = period_mode ? jb.t_res : 1;
     if (t_off >= (jb.t_end - jb.t) * u) return;
     const uint32_t tau = static_cast<uint32_t>(jb.t * u + t_off);
-    const int32_t t = static_cast<int32_t>(tau / static_cast<uint32_t>(u));
-    const bool period_mode = jb.t_res > 0;
+    const int32_t t = PLAIN ? static_cast<int32_t>(tau) : static_cast<int32_t>(tau / static_cast<uint32_t>(u));
     const int32_t np = jb.np;
     const int32_t trial0 = w.z * kTrials;
     const int8_t *__restrict__ cur = (t_off & 1) ? jb.m1 : jb.m0;
@@ -262,7 +264,7 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
                                        static_cast<uint32_t>(k), kTagR, jb.k0, jb.k1);
         const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
         uint32_t sw[4] = {0u, 0u, 0u, 0u};
-        if (sv.xs != nullptr && t > 0) {
+        if (!PLAIN && sv.xs != nullptr && t > 0) {
             const Words4 b = philox4x32_10(static_cast<uint32_t>(t), static_cast<uint32_t>(m),
                                            static_cast<uint32_t>(k), kTagStall, jb.k0, jb.k1);
             sw[0] = b.x;
@@ -274,7 +276,9 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             const int32_t L = hv[p] + scale * a4[p];
-            const float x = input_any(av[p], dv[p], L, sv, i0 + p, static_cast<uint32_t>(k),
+            const float x = PLAIN ? input_of<kAlgPsa>(av[p], dv[p], L, sv, i0 + p, static_cast<uint32_t>(k),
+                                                      static_cast<uint32_t>(t), sw[p])
+                                  : input_any(av[p], dv[p], L, sv, i0 + p, static_cast<uint32_t>(k),
                                       static_cast<uint32_t>(t), sw[p]);
             const bool up = pbit_up(x, rw[p]);
             const bool fire = period_mode ? period_fires(tau, tv[p])
@@ -321,13 +325,13 @@ __global__ void from_dense_kernel(int32_t n, int32_t t4, int32_t np, const int8_
     spins[idx] = m[static_cast<size_t>(k) * np + i];
 }
 
-template <int ENC>
+template <int ENC, bool PLAIN>
 hipError_t launch_dense_enc(hipStream_t stream, const DenseJob *jobs, const int4 *work, int32_t nwork,
                             int32_t nb, int32_t s) {
     switch (nb) {
-        case 1: hipLaunchKernelGGL((dense_step_kernel<1, ENC>), dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
-        case 2: hipLaunchKernelGGL((dense_step_kernel<2, ENC>), dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
-        case 4: hipLaunchKernelGGL((dense_step_kernel<4, ENC>), dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
+        case 1: hipLaunchKernelGGL((dense_step_kernel<1, ENC, PLAIN>), dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
+        case 2: hipLaunchKernelGGL((dense_step_kernel<2, ENC, PLAIN>), dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
+        case 4: hipLaunchKernelGGL((dense_step_kernel<4, ENC, PLAIN>), dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -336,11 +340,16 @@ hipError_t launch_dense_enc(hipStream_t stream, const DenseJob *jobs, const int4
 }  // namespace
 
 hipError_t launch_dense_steps(hipStream_t stream, const DenseJob *jobs, const int4 *work,
-                              int32_t nwork, int32_t nb, int32_t enc, int32_t steps) {
+                              int32_t nwork, int32_t nb, int32_t enc, bool plain, int32_t steps) {
     if (nwork <= 0) return hipSuccess;
     for (int32_t s = 0; s < steps; ++s) {
-        const hipError_t e = enc == kDenseT2 ? launch_dense_enc<kDenseT2>(stream, jobs, work, nwork, nb, s)
-                                             : launch_dense_enc<kDenseI8>(stream, jobs, work, nwork, nb, s);
+        hipError_t e;
+        if (enc == kDenseT2)
+            e = plain ? launch_dense_enc<kDenseT2, true>(stream, jobs, work, nwork, nb, s)
+                      : launch_dense_enc<kDenseT2, false>(stream, jobs, work, nwork, nb, s);
+        else
+            e = plain ? launch_dense_enc<kDenseI8, true>(stream, jobs, work, nwork, nb, s)
+                      : launch_dense_enc<kDenseI8, false>(stream, jobs, work, nwork, nb, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -211,7 +211,9 @@ def test_batch_mixes_spsa_and_psa(psa, ctx):
              (inputs.gnm(700, 2100, 98), psa.PSA_ALG_PSA, psa.PSA_PATH_CSR, 1, 5, 29),
              (inputs.gnm(650, 1950, 99), psa.PSA_ALG_TAPSA, psa.PSA_PATH_CSR, 1, 6, 25),
              (inputs.gnm(800, 2400, 100), psa.PSA_ALG_TAPSA, psa.PSA_PATH_CSR, 4, 10, 27),
-             (inputs.erdos_renyi(450, 0.2, 101), psa.PSA_ALG_TAPSA, psa.PSA_PATH_DENSE, 0, 18, 22)]
+             (inputs.erdos_renyi(450, 0.2, 101), psa.PSA_ALG_TAPSA, psa.PSA_PATH_DENSE, 0, 18, 22),
+             # a pSA run in a dense list with other modes takes the general step
+             (inputs.erdos_renyi(420, 0.2, 102), psa.PSA_ALG_PSA, psa.PSA_PATH_DENSE, 0, 13, 24)]
     kw = dict(sigma_lambda=0.1, sigma_delta=0.1, sigma_nu=0.1, p_mean=0.8, p_stall=0.5, window=4)
     jobs, refs = [], []
     for (n, u, v, w), alg, path, tpw, T, S in specs:
@@ -224,3 +226,27 @@ def test_batch_mixes_spsa_and_psa(psa, ctx):
         psa.jobs_step_batch(ctx, [j for j in jobs if j.position < j.steps], 7)
     for j, r in zip(jobs, refs):
         np.testing.assert_array_equal(j.read_spins(), r.read_spins())
+
+
+def test_dense_psa_list_with_a_period_run(psa, ctx):
+    """Dense pSA runs alone use the step without mode tests; with a period-mode
+    run in the same list, all of them take the general step.  Both end where
+    each run ends alone on the CSR path."""
+    kw = dict(sigma_lambda=0.1, sigma_delta=0.1, sigma_nu=0.1, p_mean=0.8)
+    graphs = [psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
+              for n, u, v, w in (inputs.erdos_renyi(380, 0.25, 111), inputs.erdos_renyi(300, 0.3, 112))]
+    for with_period in (False, True):
+        jobs = [psa.Job(ctx, graphs[0], 21, 16, 5, path=psa.PSA_PATH_DENSE, **kw),
+                psa.Job(ctx, graphs[1], 17, 9, 6, path=psa.PSA_PATH_DENSE, **kw)]
+        refs = [psa.Job(ctx, graphs[0], 21, 16, 5, path=psa.PSA_PATH_CSR, **kw),
+                psa.Job(ctx, graphs[1], 17, 9, 6, path=psa.PSA_PATH_CSR, **kw)]
+        if with_period:
+            jobs.append(psa.Job(ctx, graphs[1], 9, 5, 7, path=psa.PSA_PATH_DENSE, t_res=10, **kw))
+            refs.append(psa.Job(ctx, graphs[1], 9, 5, 7, path=psa.PSA_PATH_CSR, t_res=10, **kw))
+        for r in refs:
+            r.step(r.steps)
+        while any(j.position < j.steps for j in jobs):
+            psa.jobs_step_batch(ctx, [j for j in jobs if j.position < j.steps], 6)
+        for j, r in zip(jobs, refs):
+            np.testing.assert_array_equal(j.read_spins(), r.read_spins())
+            np.testing.assert_array_equal(j.energy_cut()[1], r.energy_cut()[1])
