@@ -250,3 +250,47 @@ def test_dense_psa_list_with_a_period_run(psa, ctx):
         for j, r in zip(jobs, refs):
             np.testing.assert_array_equal(j.read_spins(), r.read_spins())
             np.testing.assert_array_equal(j.energy_cut()[1], r.energy_cut()[1])
+
+
+def test_dense_step_at_bench_size_sampled_trials(psa, ctx):
+    """The dense matrix-core step at the size and in the launch the dense-step
+    benchmark times: G(n, p) graphs with n in [2000, 4000] (one not a multiple
+    of 128) and p in [0.04, 0.1], +1 weights (2-bit couplings), 64 trials, the
+    paper's schedule over 1,000 steps, all runs in one dense list advanced in
+    quanta.  Without variability the synchronous update of these dense
+    antiferromagnetic couplings ends in the two uniform states (cut 0): the
+    oscillation that the paper's variability breaks, and a full-size check of
+    the same trajectory on both sides.  Sampled trials (first, middle, last of the trial tile) against
+    the oracle; energy and cut of every trial against the oracle's evaluation
+    of the device spins."""
+    from concurrent.futures import ThreadPoolExecutor
+    S, T = 1000, 64
+    specs = [inputs.erdos_renyi(3968, 0.1, 700), inputs.erdos_renyi(2000, 0.04, 701),
+             inputs.erdos_renyi(2777, 0.07, 702)]
+    graphs = [psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True) for n, u, v, w in specs]
+    # the second run also draws the three variability factors (gated updates)
+    var = [(0.0, 0.0, 0.0, 1.0), (0.1, 0.1, 0.1, 0.8), (0.0, 0.0, 0.0, 1.0)]
+    jobs = [psa.Job(ctx, g, S, T, 40 + i, path=psa.PSA_PATH_DENSE, sigma_lambda=var[i][0],
+                    sigma_delta=var[i][1], sigma_nu=var[i][2], p_mean=var[i][3])
+            for i, g in enumerate(graphs)]
+    assert all(j.dense for j in jobs)
+    for _ in range(4):
+        psa.jobs_step_batch(ctx, jobs, S // 4)
+    sample = [0, 31, 63]
+    work = []
+    for i, (n, u, v, w) in enumerate(specs):
+        i0, _, _ = oracle.schedule_paper(n, u, v, -w, S)
+        lam, dlt, thr = oracle.variability(n, 40 + i, *var[i])
+        work += [(i, k, n, u, v, w, i0, lam, dlt, thr) for k in sample]
+    with ThreadPoolExecutor(len(work)) as ex:
+        res = list(ex.map(lambda a: oracle.anneal(a[2], a[3], a[4], -a[5], None, a[6], a[7], a[8], a[9],
+                                                  40 + a[0], a[1], a[1] + 1), work))
+    spins = [j.read_spins() for j in jobs]
+    ec = [j.energy_cut() for j in jobs]
+    for (i, k, *_), (os_, oE, oC) in zip(work, res):
+        np.testing.assert_array_equal(spins[i][k], os_[0], err_msg=f"graph {i} trial {k}")
+        assert ec[i][0][k] == oE[0] and ec[i][1][k] == oC[0]
+    for i, (n, u, v, w) in enumerate(specs):
+        E, C = oracle.energy_cut(n, u, v, -w, None, spins[i])
+        np.testing.assert_array_equal(ec[i][0], E)
+        np.testing.assert_array_equal(ec[i][1], C)
