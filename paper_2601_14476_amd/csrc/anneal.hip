@@ -86,7 +86,8 @@ struct Enc {
 constexpr int32_t kFastStride = 8256;  // >= 4 n4 + 1 for every n4 the layout admits
 constexpr int kFastSlots = 32;   // two rows per lane (LPT 2)
 constexpr int kFastSlots1 = 64;  // one row per lane (LPT 4)
-constexpr int kFastChunk = 8;    // slots per wave-uniform skip test
+template <int P>
+constexpr int fast_chunk() { return P == 1 ? 8 : 4; }  // slots per wave-uniform skip test
 static_assert(kFastSlots < 64, "the first row's count must fit the low six bits");
 template <int P>
 constexpr int fast_slots() { return P == 1 ? kFastSlots1 : kFastSlots; }
@@ -235,7 +236,7 @@ __device__ __forceinline__ void field_unit_cached(const Views &v, const int32_t 
 }
 
 // Fast layout: the lane's slot addresses (into buffer 0) for rows rp[0..P],
-// P = 1 or 2, and the number of kFastChunk-slot chunks that some lane of the
+// P = 1 or 2, and the number of fast_chunk<P>()-slot chunks that some lane of the
 // wavefront uses (uniform; tasks are ordered heaviest first, so the lanes of a
 // wavefront have rows of similar length).
 template <int P>
@@ -266,11 +267,12 @@ __device__ __forceinline__ void field_fast(const Views &v, const int32_t *rp, co
                                            const FastCache<P> &c, const uint8_t *cur, int32_t L[P]) {
     uint32_t acc = 0u;
     constexpr int K = fast_slots<P>();
+    constexpr int C = fast_chunk<P>();
 #pragma unroll
-    for (int g = 0; g < K / kFastChunk; ++g) {
+    for (int g = 0; g < K / C; ++g) {
         if (static_cast<uint32_t>(g) < c.chunks) {
 #pragma unroll
-            for (int j = 0; j < kFastChunk; ++j) acc += lds_byte<OFF>(c.a[kFastChunk * g + j]);
+            for (int j = 0; j < C; ++j) acc += lds_byte<OFF>(c.a[C * g + j]);
         }
     }
     const int32_t e0 = rp[0], split = rp[1], e2 = rp[P];
@@ -916,7 +918,7 @@ __device__ __forceinline__ void anneal_body(const AnnealArgs &a, int32_t q, unsi
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) cnt = max(cnt, __shfl_xor(cnt, off));
             own_fast.chunks = static_cast<uint32_t>(
-                __builtin_amdgcn_readfirstlane((cnt + kFastChunk - 1) / kFastChunk));
+                __builtin_amdgcn_readfirstlane((cnt + fast_chunk<P>() - 1) / fast_chunk<P>()));
         }
     }
     // Fast layout, one step: read the buffer at offset RO, write all four
