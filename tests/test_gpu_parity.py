@@ -434,13 +434,17 @@ def test_objects_outlive_their_creators_handles(psa):
 
 @pytest.mark.parametrize("kind,tpw,lpt,path", [
     ("unit", 1, 1, "csr"), ("unit", 1, 2, "csr"), ("unit", 1, 4, "csr"), ("unit", 4, 0, "csr"),
-    ("int", 1, 2, "csr"), ("int", 4, 0, "csr"), ("unit", 0, 0, "dense"), ("int", 0, 0, "dense")])
+    ("int", 1, 2, "csr"), ("int", 4, 0, "csr"), ("unit", 0, 0, "dense"), ("int", 0, 0, "dense"),
+    ("long", 1, 4, "csr")])
 def test_spsa_trajectories_match_oracle(psa, ctx, kind, tpw, lpt, path):
     """Stalled p-bits (Eq. 5): spins after every chunk of steps equal the
     oracle's on every path and launch shape (held inputs carried between
     launches on the device)."""
     if kind == "unit":
         n, u, v, w = inputs.gnm(333, 1400, 91)
+        j, h = -w, None
+    elif kind == "long":  # rows of ~90 edges: one-row lanes past their cached slots
+        n, u, v, w = inputs.erdos_renyi(300, 0.3, 91, weights="pm1")
         j, h = -w, None
     else:
         n, u, v, j, h = _random_ising(301, 1300, 92, jmax=4)
@@ -497,13 +501,16 @@ def test_spsa_edge_cases(psa, ctx):
 @pytest.mark.parametrize("kind,tpw,lpt,path,window", [
     ("unit", 1, 1, "csr", 4), ("unit", 1, 2, "csr", 4), ("unit", 1, 4, "csr", 3),
     ("unit", 4, 0, "csr", 4), ("int", 1, 2, "csr", 4), ("int", 4, 0, "csr", 2),
-    ("unit", 0, 0, "dense", 4), ("int", 0, 0, "dense", 3)])
+    ("unit", 0, 0, "dense", 4), ("int", 0, 0, "dense", 3), ("long", 1, 4, "csr", 4)])
 def test_tapsa_trajectories_match_oracle(psa, ctx, kind, tpw, lpt, path, window):
     """Time-averaged p-bits (Eq. 4): spins after every chunk of steps equal
     the oracle's on every path and launch shape (field windows carried
     between launches on the device, start-up averages included)."""
     if kind == "unit":
         n, u, v, w = inputs.gnm(333, 1400, 94)
+        j, h = -w, None
+    elif kind == "long":  # rows of ~90 edges: one-row lanes past their cached slots
+        n, u, v, w = inputs.erdos_renyi(300, 0.3, 94, weights="pm1")
         j, h = -w, None
     else:
         n, u, v, j, h = _random_ising(301, 1300, 95, jmax=4)
@@ -553,13 +560,16 @@ def test_tapsa_edge_cases(psa, ctx):
 @pytest.mark.parametrize("kind,tpw,lpt,path,t_res", [
     ("unit", 1, 2, "csr", 10), ("unit", 1, 4, "csr", 10), ("unit", 1, 1, "csr", 7),
     ("unit", 4, 0, "csr", 10), ("int", 1, 2, "csr", 10), ("int", 4, 0, "csr", 3),
-    ("unit", 0, 0, "dense", 10), ("int", 0, 0, "dense", 5)])
+    ("unit", 0, 0, "dense", 10), ("int", 0, 0, "dense", 5), ("long", 1, 4, "csr", 10)])
 def test_period_mode_matches_oracle(psa, ctx, kind, tpw, lpt, path, t_res):
     """Period-mode timing (the listing's count mod nu gate at t_res sub-steps
     per cycle): spins after every chunk of cycles equal the oracle's on every
     path and launch shape."""
     if kind == "unit":
         n, u, v, w = inputs.gnm(333, 1400, 97)
+        j, h = -w, None
+    elif kind == "long":  # rows of ~90 edges: one-row lanes past their cached slots
+        n, u, v, w = inputs.erdos_renyi(300, 0.3, 97, weights="pm1")
         j, h = -w, None
     else:
         n, u, v, j, h = _random_ising(301, 1300, 98, jmax=4)
