@@ -7,16 +7,22 @@ kernel), run all sweeps (the persistent anneal kernel), and reduce energy
 and cut per trial into device buffers.  The metric is p-bit updates per
 second, n * trials * steps per anneal / wall time of the timed steps.
 
-Default workload: random sparse graph n=2,000 (6,000 edges, +-1 weights),
-timing/intensity/offset variability sigma 0.1 (update probability mean 0.8),
-2,000 sweeps, 100 trials.  Other workloads: --workload c1 (G1-shaped ER,
-n=800, 1,000 sweeps, 10 trials) or c3 (G81-shaped 100x200 torus, 5,000 sweeps,
-1,024 trials).
+Default workload: the G81-shaped 100 x 200 torus (n=20,000, 40,000 edges,
++-1 weights), timing/intensity/offset variability sigma 0.1 (update
+probability mean 0.8), 5,000 sweeps, 1,024 trials -- the largest single-GPU
+configuration.  Other workloads: --workload c1 (G1-shaped ER, n=800, 1,000
+sweeps, 10 trials), c2 (random sparse n=2,000, 6,000 edges, 2,000 sweeps,
+100 trials), c4 (batched mix of 256 graphs), c4-dense (the dense step alone)
+and c5 (serving trace).
 
 Besides the contract fields the JSON line carries:
   roofline     -- the anneal kernel's algorithmic VALU lane-operations per
                   launch over its average duration (HIP events on the
-                  library's stream) against the chip's VALU issue rate;
+                  library's stream) against the chip's VALU issue rate, with
+                  three operation counts side by side: the gfx950 lower bound
+                  (the headline fraction), the workload table's estimate, and
+                  the lane-instructions the kernel issued (rocprofv3 counters
+                  under profiles/, while the sources are unchanged);
   cpu_baseline -- the oracle timed on this host's cores on a bounded sample
                   of the same workload (trials spread over threads).
 """
@@ -61,8 +67,22 @@ OPS_PERIOD = 6  # period test: convert, reciprocal, multiply, truncate, multiply
 MFMA_I8_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak, TOP/s
 HBM_PEAK_GBS = 8000.0
 
+# The workload table's own estimate of the VALU work per update (written
+# before any kernel, for a generic 32-bit ISA): about 100 lane-operations per
+# Philox4x32-10 block, of which an update takes a quarter (r) or a half (r and
+# the timing gate), about 20 FP32 operations for the pre-activation and tanh,
+# and one add per neighbour.  gfx950 forms each 32x32->64 product in one
+# instruction and each three-way XOR in another, so a block takes 40, which is
+# why the lower bound above is the headline count.
+SURVEY_PHILOX_BLOCK_OPS = 100
+SURVEY_FP32_OPS = 20
+
+# Host threads the oracle may use: the CPU share of one GPU on the GPU hosts
+# (16), whatever the machine's core count.
+CPU_SHARE_THREADS = 16
 
 TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "hbm_traffic_by_workload.md")
+ISSUE_TABLE = os.path.join(ROOT, "profiles", "valu_issue_by_workload.md")
 
 
 def source_digest() -> str:
@@ -96,6 +116,42 @@ def measured_traffic(workload: str, kernel: str):
         if len(cells) == 6 and cells[0] == workload and cells[1] == kernel and cells[5] == digest:
             return int(cells[4].replace(",", ""))
     return None
+
+
+def measured_issue(workload: str, kernel: str):
+    """(issued VALU lane-instructions per update, VALU busy fraction) of
+    `kernel` on `workload` from the rocprofv3 SQ_INSTS_VALU table under
+    profiles/, or None when no row matches the library's current sources."""
+    try:
+        with open(ISSUE_TABLE) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    digest = source_digest()
+    for ln in lines:
+        cells = [c.strip().strip("`") for c in ln.strip().strip("|").split("|")]
+        if len(cells) == 7 and cells[0] == workload and cells[1] == kernel and cells[6] == digest:
+            return float(cells[4]), float(cells[5])
+    return None
+
+
+def survey_ops_per_update(degree: float, timing: bool) -> float:
+    """The workload table's estimate of VALU lane-operations per update."""
+    return SURVEY_PHILOX_BLOCK_OPS * (0.5 if timing else 0.25) + SURVEY_FP32_OPS + degree
+
+
+def host_cpu():
+    """(logical cores of this host, CPU model name)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
 
 
 def ops_per_update(field_ops: float, timing: bool, algorithm: str = "psa") -> float:
@@ -145,7 +201,8 @@ def cpu_baseline(spec, budget_s: float = 15.0, stall24=None, window=None, t_res=
         oracle.run_spsa(n, u, v, -w, None, i0, lam, dlt, thr, stall24, spec["seed"], 0, 1, 0,
                         cal_steps, oracle.init_spins(n, spec["seed"], 0, 1))
     per_update = (time.perf_counter() - t0) / (n * cal_steps)
-    cores = min(os.cpu_count() or 1, 16)
+    host_cores, model = host_cpu()
+    cores = min(host_cores, CPU_SHARE_THREADS)
     trials = max(1, min(spec["trials"], int(budget_s / (per_update * n * S))))
     trials = max(min(cores, spec["trials"]), trials)
     bounds = np.linspace(0, trials, min(cores, trials) + 1).astype(int)
@@ -172,7 +229,9 @@ def cpu_baseline(spec, budget_s: float = 15.0, stall24=None, window=None, t_res=
     return {"value": updates / dt, "unit": "p-bit updates/s", "cores": len(parts),
             "kind": "oracle",
             "sample": f"{trials} of {spec['trials']} trials x all {S} steps x n={n} "
-                      f"({updates:.3g} updates, {dt:.2f} s wall on {len(parts)} threads)"}
+                      f"({updates:.3g} updates, {dt:.2f} s wall on {len(parts)} threads)",
+            "host_cores": host_cores, "cpu_model": model,
+            "single_thread_updates_per_s": 1.0 / per_update}
 
 
 def cpu_baseline_batch(graphs, steps, trials, budget_s: float = 15.0):
@@ -183,7 +242,8 @@ def cpu_baseline_batch(graphs, steps, trials, budget_s: float = 15.0):
     import oracle
     from concurrent.futures import ThreadPoolExecutor
     oracle.build(force=False)
-    cores = min(os.cpu_count() or 1, 16)
+    host_cores, model = host_cpu()
+    cores = min(host_cores, CPU_SHARE_THREADS)
     units = []   # (graph index, trial)
     prepared = []
     est = 0.0
@@ -219,7 +279,8 @@ def cpu_baseline_batch(graphs, steps, trials, budget_s: float = 15.0):
     return {"value": updates / dt, "unit": "p-bit updates/s", "cores": min(cores, len(units)),
             "kind": "oracle",
             "sample": f"{len(units)} trials of graphs {used[0]}..{used[-1]} of the mix x all "
-                      f"{steps} steps ({updates:.3g} updates, {dt:.2f} s wall)"}
+                      f"{steps} steps ({updates:.3g} updates, {dt:.2f} s wall)",
+            "host_cores": host_cores, "cpu_model": model}
 
 
 def main():
@@ -227,7 +288,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4-dense", "c5"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c4-dense", "c5"])
     ap.add_argument("--rate", type=float, default=50.0, help="c5: arrivals per second")
     ap.add_argument("--duration", type=float, default=20.0, help="c5: seconds of arrivals")
     ap.add_argument("--quantum", type=int, default=250, help="c5: steps per scheduling quantum")
@@ -340,6 +401,18 @@ def main():
         fires = float(np.mean(args.t_res / per.astype(np.float64)))
         opu = args.t_res * OPS_PERIOD + fires * ops_per_update(field_ops, False)
     achieved = opu * updates / (kernel_ms * 1e-3) / 1e12
+    kname = "dense_step_kernel" if job.dense else "anneal_kernel"
+    default_launch = (args.algorithm == "psa" and not args.t_res and args.path == "auto"
+                      and not (args.block or args.tpw or args.lpt))
+    # the three operation counts side by side (plain pSA in probability mode)
+    op_counts = {"gfx950_lower_bound": opu}
+    if args.algorithm == "psa" and not args.t_res and not job.dense:
+        op_counts["survey_estimate"] = survey_ops_per_update(info["nnz"] / n, timing)
+    issue = measured_issue(args.workload, kname) if default_launch else None
+    if issue is not None:
+        op_counts["issued_measured"] = issue[0]
+    fracs = {k: v * updates / (kernel_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS
+             for k, v in op_counts.items()}
     line = {
         "metric": "p-bit updates/s (n x trials x steps / s), 1 GPU",
         "value": value,
@@ -367,16 +440,17 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "dense_step_kernel" if job.dense else "anneal_kernel",
+            "kernel": kname,
             "achieved": achieved,
             "peak": VALU_PEAK_TOPS,
             "unit": "TOP/s",
             "frac": achieved / VALU_PEAK_TOPS,
             # counters were taken in the default launch of each workload only
-            "traffic": (measured_traffic(args.workload, "dense_step_kernel" if job.dense else "anneal_kernel")
-                        if args.algorithm == "psa" and not args.t_res and args.path == "auto"
-                        and not (args.block or args.tpw or args.lpt) else None),
+            "traffic": measured_traffic(args.workload, kname) if default_launch else None,
             "ops_per_update": opu,
+            "op_counts_per_update": op_counts,
+            "fracs_by_op_count": fracs,
+            "valu_busy_measured": issue[1] if issue is not None else None,
             "kernel_ms": kernel_ms,
         },
     }

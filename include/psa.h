@@ -27,7 +27,9 @@
  * Conventions
  *   - Every call returns a psa_status; on failure the outputs are left
  *     untouched and psa_last_error() describes the failure (thread-local).
- *   - Nothing throws across the ABI.  No call keeps a pointer it was given:
+ *   - Nothing throws across the ABI: every call catches what its C++ body
+ *     throws (a failed host allocation becomes PSA_ENOMEM, any other
+ *     exception PSA_EINTERNAL).  No call keeps a pointer it was given:
  *     host arrays are copied before the call returns.
  *   - "device pointer" arguments are HIP device addresses on the context's
  *     device (for instance torch.Tensor.data_ptr() of a cuda tensor); work
@@ -52,8 +54,12 @@ typedef int32_t psa_status;
 #define PSA_ENOMEM (-2)       /* host or device allocation failed        */
 #define PSA_EHIP (-3)         /* a HIP runtime call failed               */
 #define PSA_EUNSUPPORTED (-4) /* valid request this build cannot serve   */
+#define PSA_EAGAIN (-5)       /* server queue full: submit again later   */
 #define PSA_ECANCELED (-6)    /* the job was canceled                    */
 #define PSA_ETIMEDOUT (-7)    /* a wait ended before the job finished    */
+#define PSA_EINTERNAL (-8)    /* an unexpected failure inside the library
+                                 (an exception of the host runtime, e.g.
+                                 a thread that could not be started)     */
 
 typedef struct psa_ctx psa_ctx;
 typedef struct psa_graph psa_graph;
@@ -118,6 +124,10 @@ typedef struct psa_graph_info {
     int32_t max_degree;    /* largest row length                          */
     int32_t unit_weights;  /* 1 if every |J_ij| == 1                      */
     double mean_s;         /* mean_i sqrt((n-1) Var(J_i,:)), dense rows   */
+    int64_t device_bytes;  /* device memory the graph holds now: CSR,
+                              packed encodings and, once a dense-path job
+                              has built it, the dense coupling matrix
+                              (0 from psa_graph_check_edges)              */
 } psa_graph_info;
 
 /* Build a graph from an undirected edge list on the host: edge e joins
@@ -140,6 +150,16 @@ psa_status psa_graph_from_csr(psa_ctx *ctx, int32_t n, const int64_t *row_ptr,
                               psa_graph **out);
 
 psa_status psa_graph_info_get(const psa_graph *g, psa_graph_info *out);
+
+/* The host half of psa_graph_from_edges without a context or device:
+ * validate the edge list exactly as psa_graph_from_edges does (same EINVAL
+ * cases) and return the graph's statistics (n, edges, W_total, mean(s_i),
+ * bounds; device_bytes = 0).  PSA_ENOMEM if the host cannot hold the CSR
+ * being built (about 24 bytes per edge).  Usable on a machine without a
+ * GPU, e.g. to check requests before submitting them to a server. */
+psa_status psa_graph_check_edges(int32_t n, int64_t m, const int32_t *u, const int32_t *v,
+                                 const int32_t *val, const int32_t *h, uint32_t flags,
+                                 psa_graph_info *out);
 
 /* Drop the creator's reference; jobs on the graph keep it alive until they
  * are destroyed.  NULL is ignored. */
@@ -310,6 +330,9 @@ typedef struct psa_job_info {
     int32_t block;             /* CSR: threads per workgroup                  */
     int32_t dense_encoding;    /* dense: 1 = int8 entries, 2 = 2-bit fields   */
     uint32_t algorithm;        /* PSA_ALG_*                                   */
+    int64_t device_bytes;      /* device memory the job holds (run arrays,
+                                  spin state, input-stage state, staging);
+                                  its graph's is counted by the graph       */
 } psa_job_info;
 
 psa_status psa_job_get_info(const psa_job *job, psa_job_info *out);
@@ -434,11 +457,14 @@ void psa_tune_clear(psa_ctx *ctx);
 typedef struct psa_server psa_server;
 
 /* Admission limits.  hbm_budget_bytes <= 0: half of the device memory free
- * at creation; max_resident <= 0: 64 jobs; quantum_steps <= 0: 250. */
+ * at creation; max_resident <= 0: 64 jobs; quantum_steps <= 0: 250;
+ * max_waiting <= 0: no limit on jobs queued but not yet resident (else
+ * psa_server_submit returns PSA_EAGAIN while that many wait). */
 typedef struct psa_server_opts {
     int64_t hbm_budget_bytes; /* device bytes resident jobs may hold       */
     int32_t max_resident;     /* jobs advanced together in one launch      */
     int32_t quantum_steps;    /* steps per launch between scheduling points */
+    int32_t max_waiting;      /* queued jobs accepted before PSA_EAGAIN    */
 } psa_server_opts;
 
 /* Job states. */
@@ -452,7 +478,8 @@ typedef struct psa_result {
     int32_t status;    /* PSA_JOB_*                                      */
     int32_t error;     /* psa_status of a failed job (PSA_OK otherwise)  */
     int64_t submit_us; /* times in microseconds since server creation   */
-    int64_t admit_us;  /* -1 until admitted                              */
+    int64_t admit_us;  /* -1 until admitted (device memory reserved)     */
+    int64_t start_us;  /* -1 until its first step quantum is launched    */
     int64_t end_us;    /* -1 until done, failed or canceled              */
 } psa_result;
 
@@ -470,7 +497,14 @@ typedef struct psa_server_stats {
  * waiting jobs first come first served while their device footprint fits
  * the budget and a slot is free, and advances every resident job by one
  * quantum in a single batched launch (psa_jobs_step_batch).  A job's results
- * are identical to running it alone. */
+ * are identical to running it alone.
+ * Footprint: admission reserves an estimate of what the job will hold (its
+ * graph in every encoding, the dense coupling matrix and dense spin buffers
+ * when the dense path may be chosen, the run state, read-out staging, and
+ * the scratch runs the autotuner times with PSA_TUNE); once the job is
+ * created the reservation is replaced by the device bytes it actually holds
+ * (graph and job, psa_graph_info.device_bytes + psa_job_info.device_bytes),
+ * and a dense matrix the chosen path does not read is freed. */
 psa_status psa_server_create(psa_ctx *ctx, const psa_server_opts *opts,
                              psa_server **out);
 
@@ -479,7 +513,9 @@ psa_status psa_server_create(psa_ctx *ctx, const psa_server_opts *opts,
  * copied).  energy_out / cut_out ([trials]) and spins_out ([trials][n] or
  * NULL) are host buffers the server fills when the job is done; they must
  * stay valid until the job reports DONE, ERROR or CANCELED.  A job whose
- * footprint alone exceeds the budget ends in ERROR with PSA_ENOMEM. */
+ * footprint alone exceeds the budget ends in ERROR with PSA_ENOMEM.
+ * PSA_EAGAIN (nothing queued, *ticket untouched) while max_waiting jobs
+ * wait for admission. */
 psa_status psa_server_submit(psa_server *s, int32_t n, int64_t m,
                              const int32_t *u, const int32_t *v,
                              const int32_t *val, const int32_t *h,
@@ -507,6 +543,27 @@ psa_status psa_server_stats_get(psa_server *s, psa_server_stats *out);
 /* Stop the server: queued jobs are canceled, resident jobs are canceled
  * after the current quantum, the scheduler thread is joined. */
 void psa_server_destroy(psa_server *s);
+
+/* ------------------------------------------------------------------ */
+/* Value-level checks of the per-update arithmetic (tests)              */
+/* ------------------------------------------------------------------ */
+
+/* y[i] = the device's single-precision tanh of x[i] (Eq. 1's activation;
+ * the operation order is fixed: tanh(x) = sign(x) (1 - 2/(2^v + 1)) with
+ * v = |x| RN(2 log2 e), 2^v from a degree-7 Taylor polynomial of 2^f and an
+ * exact scaling, a correctly rounded division, |x| >= 9 giving +-1).
+ * x and y are device pointers to count floats; asynchronous on the
+ * context's stream. */
+psa_status psa_debug_tanh(psa_ctx *ctx, int64_t count, const float *x, float *y);
+
+/* out[i] = the decision the kernels take for an input x[i] and the random
+ * word rword[i] of the r stream (Eq. 1: +1 iff tanh(x) > r, r the odd
+ * multiple of 2^-24 given by the top 24 bits of the word): bit 0 is set for
+ * +1; bit 1 is set when the hardware estimate of tanh lay within 2^-16 of r,
+ * so that the exact tanh of psa_debug_tanh decided.  Device pointers to
+ * count elements; asynchronous on the context's stream. */
+psa_status psa_debug_decide(psa_ctx *ctx, int64_t count, const float *x, const uint32_t *rword,
+                            uint8_t *out);
 
 #ifdef __cplusplus
 }

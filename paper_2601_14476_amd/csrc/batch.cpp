@@ -256,157 +256,161 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
 extern "C" {
 
 psa_status psa_jobs_step_batch(psa_ctx *ctx, int32_t count, psa_job *const *jobs, int32_t k) {
-    if (!ctx || count < 0 || (count > 0 && !jobs) || k < 0) {
-        set_error("psa_jobs_step_batch: invalid arguments");
-        return PSA_EINVAL;
-    }
-    std::vector<psa::BatchJob> table;
-    std::vector<int32_t> trials;
-    std::vector<double> cost;
-    std::vector<int32_t> t_end;
-    std::vector<psa_job *> dense_jobs;
-    size_t lds = 0;
-    int32_t max_lanes = 0;
-    for (int32_t j = 0; j < count; ++j) {
-        psa_job *job = jobs[j];
-        if (!job || job->ctx != ctx) {
-            set_error("psa_jobs_step_batch: job " + std::to_string(j) + " is NULL or belongs to "
-                      "another context");
+    return psa::guarded("psa_jobs_step_batch", [&]() -> psa_status {
+        if (!ctx || count < 0 || (count > 0 && !jobs) || k < 0) {
+            set_error("psa_jobs_step_batch: invalid arguments");
             return PSA_EINVAL;
         }
-        for (int32_t i = 0; i < j; ++i)
-            if (jobs[i] == job) {
-                set_error("psa_jobs_step_batch: job listed twice");
+        std::vector<psa::BatchJob> table;
+        std::vector<int32_t> trials;
+        std::vector<double> cost;
+        std::vector<int32_t> t_end;
+        std::vector<psa_job *> dense_jobs;
+        size_t lds = 0;
+        int32_t max_lanes = 0;
+        for (int32_t j = 0; j < count; ++j) {
+            psa_job *job = jobs[j];
+            if (!job || job->ctx != ctx) {
+                set_error("psa_jobs_step_batch: job " + std::to_string(j) + " is NULL or belongs to "
+                          "another context");
                 return PSA_EINVAL;
             }
-        const int32_t te = static_cast<int32_t>(
-            std::min<int64_t>(int64_t{job->t} + k, job->run.steps));
-        t_end.push_back(te);
-        if (te <= job->t) continue;
-        if (job->plan.dense) {
-            dense_jobs.push_back(job);
-            continue;
+            for (int32_t i = 0; i < j; ++i)
+                if (jobs[i] == job) {
+                    set_error("psa_jobs_step_batch: job listed twice");
+                    return PSA_EINVAL;
+                }
+            const int32_t te = static_cast<int32_t>(
+                std::min<int64_t>(int64_t{job->t} + k, job->run.steps));
+            t_end.push_back(te);
+            if (te <= job->t) continue;
+            if (job->plan.dense) {
+                dense_jobs.push_back(job);
+                continue;
+            }
+            psa::AnnealPlan plan;
+            int32_t variant = 0;
+            std::string why;
+            if (!psa::plan_batch_item(job->g->dev, job->run, job->plan.tpw,
+                                      job->plan.tpw == 1 ? job->plan.lpt : 0, ctx->max_lds, &plan,
+                                      &variant, &why)) {
+                set_error("psa_jobs_step_batch: " + why);
+                return PSA_EUNSUPPORTED;
+            }
+            psa::BatchJob bj;
+            psa::fill_anneal_args(&bj.a, job->g->dev, job->run, job->d_order, job->t, te);
+            bj.variant = variant;
+            table.push_back(bj);
+            trials.push_back(plan.tpw == 4 ? job->run.t4 / 4 : job->run.trials);  // work items
+            cost.push_back(static_cast<double>(job->run.trials) * job->g->dev.n4 * (te - job->t));
+            lds = std::max(lds, plan.lds_bytes);
+            max_lanes = std::max(max_lanes, job->g->dev.n4 / 4 * plan.lpt);
         }
-        psa::AnnealPlan plan;
-        int32_t variant = 0;
-        std::string why;
-        if (!psa::plan_batch_item(job->g->dev, job->run, job->plan.tpw,
-                                  job->plan.tpw == 1 ? job->plan.lpt : 0, ctx->max_lds, &plan,
-                                  &variant, &why)) {
-            set_error("psa_jobs_step_batch: " + why);
-            return PSA_EUNSUPPORTED;
+        PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+        if (!dense_jobs.empty()) {
+            // dense runs on the second stream, concurrently with the CSR launch
+            PSA_HIP(hipEventRecord(ctx->ev_fork, ctx->stream), "hipEventRecord");
+            PSA_HIP(hipStreamWaitEvent(ctx->stream2, ctx->ev_fork, 0), "hipStreamWaitEvent");
+            psa_status st = psa::dense_step_jobs(ctx, dense_jobs.data(),
+                                                 static_cast<int32_t>(dense_jobs.size()), k);
+            if (st != PSA_OK) return st;
+            PSA_HIP(hipEventRecord(ctx->ev_join, ctx->stream2), "hipEventRecord");
         }
-        psa::BatchJob bj;
-        psa::fill_anneal_args(&bj.a, job->g->dev, job->run, job->d_order, job->t, te);
-        bj.variant = variant;
-        table.push_back(bj);
-        trials.push_back(plan.tpw == 4 ? job->run.t4 / 4 : job->run.trials);  // work items
-        cost.push_back(static_cast<double>(job->run.trials) * job->g->dev.n4 * (te - job->t));
-        lds = std::max(lds, plan.lds_bytes);
-        max_lanes = std::max(max_lanes, job->g->dev.n4 / 4 * plan.lpt);
-    }
-    PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-    if (!dense_jobs.empty()) {
-        // dense runs on the second stream, concurrently with the CSR launch
-        PSA_HIP(hipEventRecord(ctx->ev_fork, ctx->stream), "hipEventRecord");
-        PSA_HIP(hipStreamWaitEvent(ctx->stream2, ctx->ev_fork, 0), "hipStreamWaitEvent");
-        psa_status st = psa::dense_step_jobs(ctx, dense_jobs.data(),
-                                             static_cast<int32_t>(dense_jobs.size()), k);
-        if (st != PSA_OK) return st;
-        PSA_HIP(hipEventRecord(ctx->ev_join, ctx->stream2), "hipEventRecord");
-    }
-    if (table.empty()) {
+        if (table.empty()) {
+            if (!dense_jobs.empty())
+                PSA_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "hipStreamWaitEvent");
+            return PSA_OK;
+        }
+        std::vector<int2> work;
+        psa::build_work_list(trials, cost, &work);
+        // the staging buffers are reused: the previous batched launch must be done
+        PSA_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        psa_status st;
+        if ((st = ensure(&ctx->d_batch_table, &ctx->batch_table_cap,
+                         table.size() * sizeof(psa::BatchJob))) != PSA_OK)
+            return st;
+        if ((st = ensure(&ctx->d_batch_work, &ctx->batch_work_cap, work.size() * sizeof(int2))) != PSA_OK)
+            return st;
+        ctx->h_batch_table = table;
+        ctx->h_batch_work = work;
+        PSA_HIP(hipMemcpyAsync(ctx->d_batch_table, ctx->h_batch_table.data(),
+                               table.size() * sizeof(psa::BatchJob), hipMemcpyHostToDevice, ctx->stream),
+                "batch table upload");
+        PSA_HIP(hipMemcpyAsync(ctx->d_batch_work, ctx->h_batch_work.data(), work.size() * sizeof(int2),
+                               hipMemcpyHostToDevice, ctx->stream),
+                "batch work upload");
+        const int32_t block = max_lanes > 1024 ? 1024 : (max_lanes > 256 ? 512 : 256);
+        hipEvent_t ev = nullptr;
+        if ((st = psa::time_begin(ctx, ctx->stream, &ev)) != PSA_OK) return st;
+        PSA_HIP(psa::launch_anneal_batch(ctx->stream, static_cast<const psa::BatchJob *>(ctx->d_batch_table),
+                                         static_cast<const int2 *>(ctx->d_batch_work),
+                                         static_cast<int32_t>(work.size()), block, lds),
+                "batch anneal launch");
+        if ((st = psa::time_end(ctx, ctx->stream, psa::kTimeBatch, ev, 1)) != PSA_OK) return st;
+        for (int32_t j = 0; j < count; ++j) jobs[j]->t = std::max(jobs[j]->t, t_end[j]);
         if (!dense_jobs.empty())
             PSA_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "hipStreamWaitEvent");
         return PSA_OK;
-    }
-    std::vector<int2> work;
-    psa::build_work_list(trials, cost, &work);
-    // the staging buffers are reused: the previous batched launch must be done
-    PSA_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    psa_status st;
-    if ((st = ensure(&ctx->d_batch_table, &ctx->batch_table_cap,
-                     table.size() * sizeof(psa::BatchJob))) != PSA_OK)
-        return st;
-    if ((st = ensure(&ctx->d_batch_work, &ctx->batch_work_cap, work.size() * sizeof(int2))) != PSA_OK)
-        return st;
-    ctx->h_batch_table = table;
-    ctx->h_batch_work = work;
-    PSA_HIP(hipMemcpyAsync(ctx->d_batch_table, ctx->h_batch_table.data(),
-                           table.size() * sizeof(psa::BatchJob), hipMemcpyHostToDevice, ctx->stream),
-            "batch table upload");
-    PSA_HIP(hipMemcpyAsync(ctx->d_batch_work, ctx->h_batch_work.data(), work.size() * sizeof(int2),
-                           hipMemcpyHostToDevice, ctx->stream),
-            "batch work upload");
-    const int32_t block = max_lanes > 1024 ? 1024 : (max_lanes > 256 ? 512 : 256);
-    hipEvent_t ev = nullptr;
-    if ((st = psa::time_begin(ctx, ctx->stream, &ev)) != PSA_OK) return st;
-    PSA_HIP(psa::launch_anneal_batch(ctx->stream, static_cast<const psa::BatchJob *>(ctx->d_batch_table),
-                                     static_cast<const int2 *>(ctx->d_batch_work),
-                                     static_cast<int32_t>(work.size()), block, lds),
-            "batch anneal launch");
-    if ((st = psa::time_end(ctx, ctx->stream, psa::kTimeBatch, ev, 1)) != PSA_OK) return st;
-    for (int32_t j = 0; j < count; ++j) jobs[j]->t = std::max(jobs[j]->t, t_end[j]);
-    if (!dense_jobs.empty())
-        PSA_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "hipStreamWaitEvent");
-    return PSA_OK;
+    });
 }
 
 psa_status psa_anneal_batch(psa_ctx *ctx, int32_t count, const psa_batch_item *items,
                             uint32_t flags) {
-    if (!ctx || count < 0 || (count > 0 && !items) ||
-        (flags & ~(PSA_OUT_DEVICE | PSA_BATCH_SEQUENTIAL)) != 0) {
-        set_error("psa_anneal_batch: invalid arguments");
-        return PSA_EINVAL;
-    }
-    for (int32_t j = 0; j < count; ++j)
-        if (!items[j].graph || !items[j].energy_out || !items[j].cut_out) {
-            set_error("psa_anneal_batch: item " + std::to_string(j) +
-                      " needs a graph, energy_out and cut_out");
+    return psa::guarded("psa_anneal_batch", [&]() -> psa_status {
+        if (!ctx || count < 0 || (count > 0 && !items) ||
+            (flags & ~(PSA_OUT_DEVICE | PSA_BATCH_SEQUENTIAL)) != 0) {
+            set_error("psa_anneal_batch: invalid arguments");
             return PSA_EINVAL;
         }
-    std::vector<std::unique_ptr<psa_job, void (*)(psa_job *)>> owned;
-    std::vector<psa_job *> jobs;
-    int32_t max_steps = 0;
-    for (int32_t j = 0; j < count; ++j) {
-        psa_run_desc d = items[j].desc;
-        if (!(flags & PSA_BATCH_SEQUENTIAL)) {
-            if (d.flags & PSA_TUNE) {
-                psa_status st = psa::tuned_desc(ctx, items[j].graph, &d, PSA_TUNE_BATCH);
-                if (st != PSA_OK) {
-                    set_error("psa_anneal_batch: item " + std::to_string(j) + ": " + psa_last_error());
-                    return st;
-                }
+        for (int32_t j = 0; j < count; ++j)
+            if (!items[j].graph || !items[j].energy_out || !items[j].cut_out) {
+                set_error("psa_anneal_batch: item " + std::to_string(j) +
+                          " needs a graph, energy_out and cut_out");
+                return PSA_EINVAL;
             }
-            if (d.trials_per_group == 0) d.trials_per_group = 1;
+        std::vector<std::unique_ptr<psa_job, void (*)(psa_job *)>> owned;
+        std::vector<psa_job *> jobs;
+        int32_t max_steps = 0;
+        for (int32_t j = 0; j < count; ++j) {
+            psa_run_desc d = items[j].desc;
+            if (!(flags & PSA_BATCH_SEQUENTIAL)) {
+                if (d.flags & PSA_TUNE) {
+                    psa_status st = psa::tuned_desc(ctx, items[j].graph, &d, PSA_TUNE_BATCH);
+                    if (st != PSA_OK) {
+                        set_error("psa_anneal_batch: item " + std::to_string(j) + ": " + psa_last_error());
+                        return st;
+                    }
+                }
+                if (d.trials_per_group == 0) d.trials_per_group = 1;
+            }
+            psa_job *job = nullptr;
+            psa_status st = psa_job_create(ctx, items[j].graph, &d, &job);
+            if (st != PSA_OK) {
+                set_error("psa_anneal_batch: item " + std::to_string(j) + ": " + psa_last_error());
+                return st;
+            }
+            owned.emplace_back(job, psa_job_destroy);
+            jobs.push_back(job);
+            max_steps = std::max(max_steps, d.steps);
         }
-        psa_job *job = nullptr;
-        psa_status st = psa_job_create(ctx, items[j].graph, &d, &job);
-        if (st != PSA_OK) {
-            set_error("psa_anneal_batch: item " + std::to_string(j) + ": " + psa_last_error());
-            return st;
+        psa_status st;
+        if (flags & PSA_BATCH_SEQUENTIAL) {
+            for (psa_job *job : jobs)
+                if ((st = psa_job_step(job, job->run.steps)) != PSA_OK) return st;
+        } else {
+            if ((st = psa_jobs_step_batch(ctx, count, jobs.data(), max_steps)) != PSA_OK) return st;
         }
-        owned.emplace_back(job, psa_job_destroy);
-        jobs.push_back(job);
-        max_steps = std::max(max_steps, d.steps);
-    }
-    psa_status st;
-    if (flags & PSA_BATCH_SEQUENTIAL) {
-        for (psa_job *job : jobs)
-            if ((st = psa_job_step(job, job->run.steps)) != PSA_OK) return st;
-    } else {
-        if ((st = psa_jobs_step_batch(ctx, count, jobs.data(), max_steps)) != PSA_OK) return st;
-    }
-    const uint32_t out = flags & PSA_OUT_DEVICE;
-    for (int32_t j = 0; j < count; ++j) {
-        if ((st = psa_job_energy_cut(jobs[j], items[j].energy_out, items[j].cut_out, out)) != PSA_OK)
-            return st;
-        if (items[j].spins_out &&
-            (st = psa_job_read_spins(jobs[j], items[j].spins_out, out)) != PSA_OK)
-            return st;
-    }
-    PSA_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    return PSA_OK;
+        const uint32_t out = flags & PSA_OUT_DEVICE;
+        for (int32_t j = 0; j < count; ++j) {
+            if ((st = psa_job_energy_cut(jobs[j], items[j].energy_out, items[j].cut_out, out)) != PSA_OK)
+                return st;
+            if (items[j].spins_out &&
+                (st = psa_job_read_spins(jobs[j], items[j].spins_out, out)) != PSA_OK)
+                return st;
+        }
+        PSA_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        return PSA_OK;
+    });
 }
 
 }  // extern "C"

@@ -105,13 +105,20 @@ __device__ __forceinline__ float tanh_f32(float x) {
 // that, the reciprocal adds 2^-23 and the roundings a few 2^-24; so every
 // such decision is the one tanh_f32 gives.  The rest (about 2^-16 of the
 // updates) evaluate tanh_f32 itself.
-__device__ __forceinline__ bool pbit_up(float x, uint32_t rword) {
-    const float r = r_of(rword);
+__device__ __forceinline__ float tanh_estimate_minus(float x, float r) {
     const float a = fminf(fabsf(x), 9.0f);
     const float e = __builtin_amdgcn_exp2f(a * 0x1.715476p+1f);
     const float y = fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
-    const float diff = copysignf(y, x) - r;
-    if (fabsf(diff) > 0x1p-16f) return diff > 0.0f;
+    return copysignf(y, x) - r;
+}
+
+// True when the estimate's distance to r decides (else tanh_f32 is evaluated).
+__device__ __forceinline__ bool estimate_decides(float diff) { return fabsf(diff) > 0x1p-16f; }
+
+__device__ __forceinline__ bool pbit_up(float x, uint32_t rword) {
+    const float r = r_of(rword);
+    const float diff = tanh_estimate_minus(x, r);
+    if (estimate_decides(diff)) return diff > 0.0f;
     return tanh_f32(x) > r;
 }
 

@@ -8,6 +8,8 @@
 #include <atomic>
 #include <map>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -24,6 +26,38 @@ constexpr uint32_t kGateOneHost = 1u << 24;
 // Thread-local error text behind psa_last_error().
 void set_error(const std::string &msg);
 void clear_error();
+// Set the error text without allocating (a string literal, kept by address):
+// the fallback when building the message itself fails.
+void set_error_static(const char *msg) noexcept;
+
+// Run the body of an exported call so that no exception unwinds across the C
+// ABI: std::bad_alloc and std::length_error become PSA_ENOMEM, any other
+// exception PSA_EINTERNAL, each with the error text set.
+template <typename F>
+psa_status guarded(const char *call, F &&body) noexcept {
+    const char *what = nullptr;
+    psa_status st = PSA_EINTERNAL;
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        st = PSA_ENOMEM;
+        what = "host memory allocation failed";
+    } catch (const std::length_error &) {
+        st = PSA_ENOMEM;
+        what = "host memory allocation failed (size too large)";
+    } catch (const std::exception &e) {
+        what = e.what();
+    } catch (...) {
+        what = "unknown exception";
+    }
+    try {
+        set_error(std::string(call) + ": " + what);
+    } catch (...) {
+        set_error_static(st == PSA_ENOMEM ? "host memory allocation failed"
+                                          : "internal error (exception in the host runtime)");
+    }
+    return st;
+}
 
 // Record a failed HIP call as the last error.
 inline psa_status hip_fail(hipError_t err, const char *what) {
@@ -233,6 +267,11 @@ hipError_t launch_spins_to_tn(hipStream_t stream, int32_t n, const DevRun &run,
                               int8_t *out_tn);
 hipError_t launch_spins_from_tn(hipStream_t stream, int32_t n, const DevRun &run,
                                 const int8_t *in_tn);
+// Test entry points: device tanh_f32 of count values; pbit_up decisions of
+// count (x, word) pairs with the branch taken (bit 0 up, bit 1 tanh_f32).
+hipError_t launch_debug_tanh(hipStream_t stream, int64_t count, const float *x, float *y);
+hipError_t launch_debug_decide(hipStream_t stream, int64_t count, const float *x,
+                               const uint32_t *word, uint8_t *out);
 
 // Host-side helpers (host_params.cpp).
 void philox4x32_10_host(const uint32_t ctr[4], uint32_t key0, uint32_t key1,
@@ -284,6 +323,9 @@ bool prefer_dense(const psa_graph *g, const DevRun &run, const AnnealPlan &plan)
 // Build and upload the dense int8 coupling matrix of g (once); EUNSUPPORTED
 // if a coupling does not fit int8.
 psa_status ensure_dense_matrix(psa_graph *g);
+// Free the dense coupling matrix of g (after the work queued on the context's
+// streams), for a graph that no live job reads it through.
+void release_dense_matrix(psa_graph *g);
 // Advance the dense-planned jobs of `jobs` by up to k steps (each clipped to
 // its schedule) on the context's second stream; the caller joins it.
 psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, int32_t k);
@@ -368,6 +410,8 @@ struct psa_graph {
     int32_t np = 0;                     // n rounded up to 128
     int32_t dense_enc = 0;              // kDenseI8 or kDenseT2
     int32_t dense_scale = 1;            // J = dense_scale * entry
+    size_t dev_bytes = 0;               // device bytes of the CSR and its encodings
+    size_t dense_bytes = 0;             // device bytes of d_dense
 };
 
 struct psa_job {
@@ -390,4 +434,5 @@ struct psa_job {
     int32_t *d_pp = nullptr;     // per-p-bit constants of the ELL sweep
     void *d_scratch = nullptr;   // read-out staging
     size_t scratch_bytes = 0;
+    size_t dev_bytes = 0;        // device bytes of every allocation above
 };

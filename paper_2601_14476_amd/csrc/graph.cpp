@@ -157,8 +157,9 @@ psa_status finish_host_graph(int32_t n, const std::vector<int64_t> &row_ptr,
     return PSA_OK;
 }
 
+// Allocate and fill a device copy of src; the bytes are added to *acct.
 template <typename T>
-psa_status upload(T **dst, const std::vector<T> &src) {
+psa_status upload(T **dst, const std::vector<T> &src, size_t *acct) {
     *dst = nullptr;
     if (src.empty()) return PSA_OK;
     if (hipMalloc(reinterpret_cast<void **>(dst), src.size() * sizeof(T)) != hipSuccess) {
@@ -166,6 +167,7 @@ psa_status upload(T **dst, const std::vector<T> &src) {
         set_error("graph upload: device allocation failed");
         return PSA_ENOMEM;
     }
+    *acct += src.size() * sizeof(T);
     const hipError_t e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         set_error(std::string("graph upload: ") + hipGetErrorString(e));
@@ -234,7 +236,7 @@ psa_status ensure_dense_matrix(psa_graph *g) {
                 words[at] |= f << (8 * b + 2 * d);
             }
         uint32_t *dev = nullptr;
-        if ((st = upload(&dev, words)) != PSA_OK) return st;
+        if ((st = upload(&dev, words, &g->dense_bytes)) != PSA_OK) return st;
         g->d_dense = dev;
         g->dense_enc = kDenseT2;
         g->dense_scale = mag == 0 ? 1 : mag;
@@ -249,13 +251,25 @@ psa_status ensure_dense_matrix(psa_graph *g) {
             for (int32_t p = g->row_ptr_host[i]; p < g->row_ptr_host[i + 1]; ++p)
                 dense[static_cast<size_t>(i) * np + g->col_host[p]] = static_cast<int8_t>(g->val_host[p]);
         int8_t *dev = nullptr;
-        if ((st = upload(&dev, dense)) != PSA_OK) return st;
+        if ((st = upload(&dev, dense, &g->dense_bytes)) != PSA_OK) return st;
         g->d_dense = dev;
         g->dense_enc = kDenseI8;
         g->dense_scale = 1;
     }
     g->np = np;
     return PSA_OK;
+}
+
+void release_dense_matrix(psa_graph *g) {
+    if (!g->d_dense) return;
+    if (g->ctx) {
+        (void)hipSetDevice(g->ctx->device);
+        (void)hipStreamSynchronize(g->ctx->stream);
+        if (g->ctx->stream2) (void)hipStreamSynchronize(g->ctx->stream2);
+    }
+    (void)hipFree(g->d_dense);
+    g->d_dense = nullptr;
+    g->dense_bytes = 0;
 }
 
 psa_status host_graph_from_edges(int32_t n, int64_t m, const int32_t *u, const int32_t *v,
@@ -359,15 +373,15 @@ psa_status upload_graph(psa_ctx *ctx, HostGraph &&hg, psa_graph **out) {
     g->retained = true;
     g->info = hg.info;
     psa_status st;
-    if ((st = upload(&g->d_row_ptr, hg.rp32)) != PSA_OK) return st;
-    if ((st = upload(&g->d_col, hg.col)) != PSA_OK) return st;
-    if ((st = upload(&g->d_val, hg.val)) != PSA_OK) return st;
-    if ((st = upload(&g->d_h, hg.h)) != PSA_OK) return st;
-    if ((st = upload(&g->d_pk32, hg.pk32)) != PSA_OK) return st;
-    if ((st = upload(&g->d_pk16, hg.pk16)) != PSA_OK) return st;
-    if ((st = upload(&g->d_ux16, hg.ux16)) != PSA_OK) return st;
-    if ((st = upload(&g->d_ell, hg.ell)) != PSA_OK) return st;
-    if ((st = upload(&g->d_eptr, hg.eptr)) != PSA_OK) return st;
+    if ((st = upload(&g->d_row_ptr, hg.rp32, &g->dev_bytes)) != PSA_OK) return st;
+    if ((st = upload(&g->d_col, hg.col, &g->dev_bytes)) != PSA_OK) return st;
+    if ((st = upload(&g->d_val, hg.val, &g->dev_bytes)) != PSA_OK) return st;
+    if ((st = upload(&g->d_h, hg.h, &g->dev_bytes)) != PSA_OK) return st;
+    if ((st = upload(&g->d_pk32, hg.pk32, &g->dev_bytes)) != PSA_OK) return st;
+    if ((st = upload(&g->d_pk16, hg.pk16, &g->dev_bytes)) != PSA_OK) return st;
+    if ((st = upload(&g->d_ux16, hg.ux16, &g->dev_bytes)) != PSA_OK) return st;
+    if ((st = upload(&g->d_ell, hg.ell, &g->dev_bytes)) != PSA_OK) return st;
+    if ((st = upload(&g->d_eptr, hg.eptr, &g->dev_bytes)) != PSA_OK) return st;
     g->dev.n = hg.n;
     g->dev.n4 = hg.n4;
     g->dev.nnz = hg.nnz;

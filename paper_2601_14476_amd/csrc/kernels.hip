@@ -10,6 +10,8 @@
 // (m = i/4) of trial k; word i mod 4.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_math.hpp"
 #include "engine.hpp"
 
@@ -183,6 +185,31 @@ inline unsigned grid_for(int64_t items, int block) {
     return static_cast<unsigned>((items + block - 1) / block);
 }
 
+// ---------------------------------------------------------------------------
+// Value-level checks of the per-update arithmetic (test entry points): the
+// device tanh_f32 of every x, and the decision pbit_up of every (x, word)
+// with the branch it took (bit 0: +1, bit 1: the estimate was within 2^-16
+// of r, so tanh_f32 decided).  Grid-stride over count elements.
+// ---------------------------------------------------------------------------
+__global__ void debug_tanh_kernel(int64_t count, const float *__restrict__ x,
+                                  float *__restrict__ y) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += stride)
+        y[i] = tanh_f32(x[i]);
+}
+
+__global__ void debug_decide_kernel(int64_t count, const float *__restrict__ x,
+                                    const uint32_t *__restrict__ word, uint8_t *__restrict__ out) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += stride) {
+        const float diff = tanh_estimate_minus(x[i], r_of(word[i]));
+        out[i] = static_cast<uint8_t>((pbit_up(x[i], word[i]) ? 1u : 0u) |
+                                      (estimate_decides(diff) ? 0u : 2u));
+    }
+}
+
 }  // namespace
 
 hipError_t launch_init_spins(hipStream_t stream, int32_t n, const DevRun &run) {
@@ -234,6 +261,23 @@ hipError_t launch_spins_from_tn(hipStream_t stream, int32_t n, const DevRun &run
     hipLaunchKernelGGL(spins_from_tn_kernel,
                        dim3(grid_for(static_cast<int64_t>(n) * run.trials, block)), dim3(block), 0,
                        stream, n, run.t4, run.trials, in_tn, run.spins);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_tanh(hipStream_t stream, int64_t count, const float *x, float *y) {
+    const int block = 256;
+    const int64_t grid = std::min<int64_t>((count + block - 1) / block, 8192);
+    hipLaunchKernelGGL(debug_tanh_kernel, dim3(static_cast<uint32_t>(grid)), dim3(block), 0, stream,
+                       count, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_decide(hipStream_t stream, int64_t count, const float *x,
+                               const uint32_t *word, uint8_t *out) {
+    const int block = 256;
+    const int64_t grid = std::min<int64_t>((count + block - 1) / block, 8192);
+    hipLaunchKernelGGL(debug_decide_kernel, dim3(static_cast<uint32_t>(grid)), dim3(block), 0,
+                       stream, count, x, word, out);
     return hipGetLastError();
 }
 

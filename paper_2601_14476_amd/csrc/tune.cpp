@@ -119,84 +119,88 @@ extern "C" {
 
 psa_status psa_autotune(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *desc,
                         int32_t probe_steps, uint32_t mode, psa_tune_result *out) {
-    if (!ctx || !g || !desc || !out || probe_steps < 1 ||
-        (mode != PSA_TUNE_ALONE && mode != PSA_TUNE_BATCH)) {
-        psa::set_error("psa_autotune: invalid arguments");
-        return PSA_EINVAL;
-    }
-    if (g->ctx != ctx || desc->steps < 1 || desc->trials < 1) {
-        psa::set_error("psa_autotune: graph of another context, or steps / trials < 1");
-        return PSA_EINVAL;
-    }
-    psa_run_desc base = *desc;
-    base.flags = PSA_PATH_AUTO;
-    const int32_t probe = std::min(probe_steps, base.steps);
-    std::vector<psa::Candidate> cands;
-    cands.push_back({PSA_PATH_CSR, 4, 0});
-    for (int32_t lpt : {1, 2, 4}) {
-        // inside a batch a one-trial run uses 2 or 4 lanes per task
-        if (mode == PSA_TUNE_BATCH && lpt == 1) continue;
-        cands.push_back({PSA_PATH_CSR, 1, lpt});
-    }
-    const bool dense_ok = psa::dense_encodable(g) && g->info.n <= 32768;
-    if (dense_ok) cands.push_back({PSA_PATH_DENSE, 0, 0});
-
-    psa_tune_result r{};
-    r.csr_us_per_step = -1.0;
-    r.dense_us_per_step = -1.0;
-    r.us_per_step = -1.0;
-    for (const psa::Candidate &c : cands) {
-        double us = 0.0;
-        const psa_status st = psa::time_candidate(ctx, g, base, c, probe, mode, &us);
-        if (st == PSA_EUNSUPPORTED) continue;  // e.g. spin state beyond LDS
-        if (st != PSA_OK) return st;
-        ++r.candidates;
-        double &best_of_path = c.path == PSA_PATH_DENSE ? r.dense_us_per_step : r.csr_us_per_step;
-        if (best_of_path < 0.0 || us < best_of_path) best_of_path = us;
-        if (r.us_per_step < 0.0 || us < r.us_per_step) {
-            r.us_per_step = us;
-            r.path = c.path;
-            r.trials_per_group = c.tpw;
-            r.lanes_per_task = c.lpt;
+    return psa::guarded("psa_autotune", [&]() -> psa_status {
+        if (!ctx || !g || !desc || !out || probe_steps < 1 ||
+            (mode != PSA_TUNE_ALONE && mode != PSA_TUNE_BATCH)) {
+            psa::set_error("psa_autotune: invalid arguments");
+            return PSA_EINVAL;
         }
-    }
-    if (r.candidates == 0) {
-        psa::set_error("psa_autotune: no configuration applies to this graph");
-        return PSA_EUNSUPPORTED;
-    }
-    psa::DevRun run;
-    run.trials = base.trials;
-    run.t4 = (base.trials + 3) / 4 * 4;
-    psa::AnnealPlan plan;
-    std::string why;
-    r.model_csr_us = psa::plan_anneal(g->dev, run, 0, 0, 0, ctx->max_lds, ctx->num_cu, &plan, &why)
-                         ? 1e6 * psa::csr_step_seconds(g->dev, run, plan)
-                         : -1.0;
-    r.model_dense_us = dense_ok ? 1e6 * psa::dense_step_seconds(g->info.n, run.t4, psa::dense_two_bit(g)) : -1.0;
-    {
-        std::lock_guard<std::mutex> lock(ctx->tune_mu);
-        ctx->tune_cache[psa::tune_key(g, base.trials, mode, base.algorithm)] = r;
-    }
-    *out = r;
-    return PSA_OK;
+        if (g->ctx != ctx || desc->steps < 1 || desc->trials < 1) {
+            psa::set_error("psa_autotune: graph of another context, or steps / trials < 1");
+            return PSA_EINVAL;
+        }
+        psa_run_desc base = *desc;
+        base.flags = PSA_PATH_AUTO;
+        const int32_t probe = std::min(probe_steps, base.steps);
+        std::vector<psa::Candidate> cands;
+        cands.push_back({PSA_PATH_CSR, 4, 0});
+        for (int32_t lpt : {1, 2, 4}) {
+            // inside a batch a one-trial run uses 2 or 4 lanes per task
+            if (mode == PSA_TUNE_BATCH && lpt == 1) continue;
+            cands.push_back({PSA_PATH_CSR, 1, lpt});
+        }
+        const bool dense_ok = psa::dense_encodable(g) && g->info.n <= 32768;
+        if (dense_ok) cands.push_back({PSA_PATH_DENSE, 0, 0});
+
+        psa_tune_result r{};
+        r.csr_us_per_step = -1.0;
+        r.dense_us_per_step = -1.0;
+        r.us_per_step = -1.0;
+        for (const psa::Candidate &c : cands) {
+            double us = 0.0;
+            const psa_status st = psa::time_candidate(ctx, g, base, c, probe, mode, &us);
+            if (st == PSA_EUNSUPPORTED) continue;  // e.g. spin state beyond LDS
+            if (st != PSA_OK) return st;
+            ++r.candidates;
+            double &best_of_path = c.path == PSA_PATH_DENSE ? r.dense_us_per_step : r.csr_us_per_step;
+            if (best_of_path < 0.0 || us < best_of_path) best_of_path = us;
+            if (r.us_per_step < 0.0 || us < r.us_per_step) {
+                r.us_per_step = us;
+                r.path = c.path;
+                r.trials_per_group = c.tpw;
+                r.lanes_per_task = c.lpt;
+            }
+        }
+        if (r.candidates == 0) {
+            psa::set_error("psa_autotune: no configuration applies to this graph");
+            return PSA_EUNSUPPORTED;
+        }
+        psa::DevRun run;
+        run.trials = base.trials;
+        run.t4 = (base.trials + 3) / 4 * 4;
+        psa::AnnealPlan plan;
+        std::string why;
+        r.model_csr_us = psa::plan_anneal(g->dev, run, 0, 0, 0, ctx->max_lds, ctx->num_cu, &plan, &why)
+                             ? 1e6 * psa::csr_step_seconds(g->dev, run, plan)
+                             : -1.0;
+        r.model_dense_us = dense_ok ? 1e6 * psa::dense_step_seconds(g->info.n, run.t4, psa::dense_two_bit(g)) : -1.0;
+        {
+            std::lock_guard<std::mutex> lock(ctx->tune_mu);
+            ctx->tune_cache[psa::tune_key(g, base.trials, mode, base.algorithm)] = r;
+        }
+        *out = r;
+        return PSA_OK;
+    });
 }
 
 psa_status psa_tune_get(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *desc, uint32_t mode,
                         psa_tune_result *out) {
-    if (!ctx || !g || !desc || !out || (mode != PSA_TUNE_ALONE && mode != PSA_TUNE_BATCH) ||
-        desc->trials < 1) {
-        psa::set_error("psa_tune_get: invalid arguments");
-        return PSA_EINVAL;
-    }
-    {
-        std::lock_guard<std::mutex> lock(ctx->tune_mu);
-        auto it = ctx->tune_cache.find(psa::tune_key(g, desc->trials, mode, desc->algorithm));
-        if (it != ctx->tune_cache.end()) {
-            *out = it->second;
-            return PSA_OK;
+    return psa::guarded("psa_tune_get", [&]() -> psa_status {
+        if (!ctx || !g || !desc || !out || (mode != PSA_TUNE_ALONE && mode != PSA_TUNE_BATCH) ||
+            desc->trials < 1) {
+            psa::set_error("psa_tune_get: invalid arguments");
+            return PSA_EINVAL;
         }
-    }
-    return psa_autotune(ctx, g, desc, 8, mode, out);
+        {
+            std::lock_guard<std::mutex> lock(ctx->tune_mu);
+            auto it = ctx->tune_cache.find(psa::tune_key(g, desc->trials, mode, desc->algorithm));
+            if (it != ctx->tune_cache.end()) {
+                *out = it->second;
+                return PSA_OK;
+            }
+        }
+        return psa_autotune(ctx, g, desc, 8, mode, out);
+    });
 }
 
 void psa_tune_apply(const psa_tune_result *r, psa_run_desc *desc) {
@@ -208,14 +212,23 @@ void psa_tune_apply(const psa_tune_result *r, psa_run_desc *desc) {
 
 int32_t psa_tune_cache_size(psa_ctx *ctx) {
     if (!ctx) return 0;
-    std::lock_guard<std::mutex> lock(ctx->tune_mu);
-    return static_cast<int32_t>(ctx->tune_cache.size());
+    try {
+        std::lock_guard<std::mutex> lock(ctx->tune_mu);
+        return static_cast<int32_t>(ctx->tune_cache.size());
+    } catch (...) {
+        psa::set_error_static("psa_tune_cache_size: could not lock the tuning cache");
+        return -1;
+    }
 }
 
 void psa_tune_clear(psa_ctx *ctx) {
     if (!ctx) return;
-    std::lock_guard<std::mutex> lock(ctx->tune_mu);
-    ctx->tune_cache.clear();
+    try {
+        std::lock_guard<std::mutex> lock(ctx->tune_mu);
+        ctx->tune_cache.clear();
+    } catch (...) {
+        psa::set_error_static("psa_tune_clear: could not lock the tuning cache");
+    }
 }
 
 }  // extern "C"

@@ -25,8 +25,10 @@ PSA_EINVAL = -1
 PSA_ENOMEM = -2
 PSA_EHIP = -3
 PSA_EUNSUPPORTED = -4
+PSA_EAGAIN = -5
 PSA_ECANCELED = -6
 PSA_ETIMEDOUT = -7
+PSA_EINTERNAL = -8
 PSA_JOB_QUEUED, PSA_JOB_RUNNING, PSA_JOB_DONE, PSA_JOB_ERROR, PSA_JOB_CANCELED = range(5)
 
 PSA_GRAPH_ISING = 0
@@ -47,7 +49,7 @@ _i32, _i64, _u32, _u64, _f64 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
 class psa_graph_info(ctypes.Structure):
     _fields_ = [("n", _i32), ("edges", _i64), ("nnz", _i64), ("w_total", _i64),
                 ("max_abs_field", _i32), ("max_degree", _i32),
-                ("unit_weights", _i32), ("mean_s", _f64)]
+                ("unit_weights", _i32), ("mean_s", _f64), ("device_bytes", _i64)]
 
 
 class psa_run_desc(ctypes.Structure):
@@ -69,7 +71,8 @@ class psa_tune_result(ctypes.Structure):
 
 class psa_job_info(ctypes.Structure):
     _fields_ = [("path", _u32), ("trials_per_group", _i32), ("lanes_per_task", _i32),
-                ("block", _i32), ("dense_encoding", _i32), ("algorithm", _u32)]
+                ("block", _i32), ("dense_encoding", _i32), ("algorithm", _u32),
+                ("device_bytes", _i64)]
 
 
 class psa_timing(ctypes.Structure):
@@ -83,12 +86,13 @@ class psa_batch_item(ctypes.Structure):
 
 
 class psa_server_opts(ctypes.Structure):
-    _fields_ = [("hbm_budget_bytes", _i64), ("max_resident", _i32), ("quantum_steps", _i32)]
+    _fields_ = [("hbm_budget_bytes", _i64), ("max_resident", _i32), ("quantum_steps", _i32),
+                ("max_waiting", _i32)]
 
 
 class psa_result(ctypes.Structure):
     _fields_ = [("status", _i32), ("error", _i32), ("submit_us", _i64), ("admit_us", _i64),
-                ("end_us", _i64)]
+                ("start_us", _i64), ("end_us", _i64)]
 
 
 class psa_server_stats(ctypes.Structure):
@@ -111,6 +115,8 @@ _SIGNATURES = [
     ("psa_graph_from_csr", _i32, [_P, _i32, _P, _P, _P, _P, _u32,
                                   ctypes.POINTER(_P)]),
     ("psa_graph_info_get", _i32, [_P, ctypes.POINTER(psa_graph_info)]),
+    ("psa_graph_check_edges", _i32, [_i32, _i64, _P, _P, _P, _P, _u32,
+                                     ctypes.POINTER(psa_graph_info)]),
     ("psa_graph_destroy", None, [_P]),
     ("psa_schedule_paper", _i32, [_P, ctypes.POINTER(_f64), ctypes.POINTER(_f64)]),
     ("psa_schedule_fill", _i32, [_i32, _f64, _f64, _P]),
@@ -147,6 +153,8 @@ _SIGNATURES = [
     ("psa_server_release", _i32, [_P, _u64]),
     ("psa_server_stats_get", _i32, [_P, ctypes.POINTER(psa_server_stats)]),
     ("psa_server_destroy", None, [_P]),
+    ("psa_debug_tanh", _i32, [_P, _i64, _P, _P]),
+    ("psa_debug_decide", _i32, [_P, _i64, _P, _P, _P]),
 ]
 
 
@@ -317,6 +325,22 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def graph_check_edges(n, u, v, val, h=None, maxcut=True):
+    """Validate an edge list on the host and return its statistics
+    (psa_graph_check_edges; no context or device needed)."""
+    u = np.ascontiguousarray(u, dtype=np.int32)
+    v = np.ascontiguousarray(v, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.int32)
+    hh = None if h is None else np.ascontiguousarray(h, dtype=np.int32)
+    if not (u.shape == v.shape == val.shape) or (hh is not None and hh.shape != (n,)):
+        raise ValueError("edge arrays must have equal length and h shape (n,)")
+    i = psa_graph_info()
+    _check(_lib.psa_graph_check_edges(n, u.size, _ptr(u), _ptr(v), _ptr(val), _ptr(hh),
+                                      PSA_GRAPH_MAXCUT if maxcut else PSA_GRAPH_ISING,
+                                      ctypes.byref(i)), "psa_graph_check_edges")
+    return {f: getattr(i, f) for f, _ in psa_graph_info._fields_}
 
 
 def schedule_fill(steps, i0_min, i0_max):
@@ -541,8 +565,9 @@ def anneal_batch(ctx, items, sequential=False, spins=False):
 class Server:
     """Continuous-batching anneal server on a context (see psa_server_create)."""
 
-    def __init__(self, ctx, hbm_budget_bytes=0, max_resident=0, quantum_steps=0):
-        o = psa_server_opts(int(hbm_budget_bytes), int(max_resident), int(quantum_steps))
+    def __init__(self, ctx, hbm_budget_bytes=0, max_resident=0, quantum_steps=0, max_waiting=0):
+        o = psa_server_opts(int(hbm_budget_bytes), int(max_resident), int(quantum_steps),
+                            int(max_waiting))
         h = _P()
         _check(_lib.psa_server_create(ctx.handle, ctypes.byref(o), ctypes.byref(h)),
                "psa_server_create")

@@ -90,3 +90,83 @@ def test_binding_has_no_cpu_path():
     for word in ("philox", "0xd2511f53", "import oracle", "from oracle", "np.tanh",
                  "math.tanh", "torch.tanh"):
         assert word not in src.lower(), word
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+def test_graph_check_edges_matches_oracle(psa, name):
+    """Host-side ingestion statistics (no device): counts, W_total and the
+    paper's mean(s_i) against the oracle, degree bound from the edge list."""
+    from paper_2601_14476_amd import inputs
+    spec = inputs.workload(name)
+    n, u, v, w = spec["n"], spec["u"], spec["v"], spec["w"]
+    info = psa.graph_check_edges(n, u, v, w)
+    deg = np.bincount(np.concatenate([u, v]), minlength=n)
+    assert info["n"] == n and info["edges"] == u.size and info["nnz"] == 2 * u.size
+    assert info["w_total"] == int(w.sum())
+    assert info["max_degree"] == int(deg.max())
+    assert info["max_abs_field"] == int(deg.max())
+    assert info["unit_weights"] == 1 and info["device_bytes"] == 0
+    assert info["mean_s"] == oracle.mean_s(n, u, v, -w)
+
+
+def test_graph_check_edges_rejects_invalid_graphs(psa):
+    z = np.array([0], np.int32)
+    o = np.array([1], np.int32)
+    cases = [(2, z, z, o),                                        # self loop
+             (2, np.array([0, 1], np.int32), np.array([1, 0], np.int32),
+              np.array([1, 1], np.int32)),                        # repeated pair
+             (2, z, np.array([5], np.int32), o),                  # out of range
+             (2, z, o, np.array([1 << 24], np.int32))]            # field bound 2^24
+    for n, u, v, w in cases:
+        with pytest.raises(psa.PsaError) as e:
+            psa.graph_check_edges(n, u, v, w)
+        assert e.value.status == psa.PSA_EINVAL
+
+
+_ENOMEM_CHILD = r"""
+import ctypes, resource, sys
+import numpy as np
+
+class Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("edges", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("w_total", ctypes.c_int64), ("max_abs_field", ctypes.c_int32),
+                ("max_degree", ctypes.c_int32), ("unit_weights", ctypes.c_int32),
+                ("mean_s", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+
+lib = ctypes.CDLL(sys.argv[1])
+lib.psa_last_error.restype = ctypes.c_char_p
+ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+# a valid circulant graph: p-bit i joined to i+1 .. i+15 (mod n), 30 M edges
+n, K = 2_000_000, 15
+u = np.repeat(np.arange(n, dtype=np.int32), K)
+v = ((u.astype(np.int64) + np.tile(np.arange(1, K + 1), n)) % n).astype(np.int32)
+w = np.ones(u.size, np.int32)
+info = Info()
+# room for the library's first arrays but not for the CSR (240 MB per array)
+vm = int(open("/proc/self/status").read().split("VmSize:")[1].split()[0]) * 1024
+soft, hard = resource.getrlimit(resource.RLIMIT_AS)
+resource.setrlimit(resource.RLIMIT_AS, (vm + (64 << 20), hard))
+st = lib.psa_graph_check_edges(n, u.size, ptr(u), ptr(v), ptr(w), None, 1, ctypes.byref(info))
+msg = lib.psa_last_error().decode()
+resource.setrlimit(resource.RLIMIT_AS, (soft, hard))
+# the library is still usable afterwards
+u2, v2, w2 = np.array([0, 1], np.int32), np.array([1, 2], np.int32), np.ones(2, np.int32)
+st2 = lib.psa_graph_check_edges(3, 2, ptr(u2), ptr(v2), ptr(w2), None, 1, ctypes.byref(info))
+print(st, st2, info.edges, msg)
+"""
+
+
+def test_host_allocation_failure_is_a_status_not_a_crash(psa):
+    """A failed host allocation inside an exported call returns PSA_ENOMEM
+    with an error text, instead of an exception unwinding through the C ABI
+    (which would abort the process).  Forced in a child process by capping
+    its address space just above what it has mapped."""
+    import subprocess
+    import sys
+    res = subprocess.run([sys.executable, "-c", _ENOMEM_CHILD, psa.LIB_PATH],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 0, res.stderr[-2000:]
+    st, st2, edges, *msg = res.stdout.split()
+    assert int(st) == psa.PSA_ENOMEM, res.stdout
+    assert "psa_graph_check_edges" in " ".join(msg) and "allocation" in " ".join(msg)
+    assert int(st2) == psa.PSA_OK and int(edges) == 2

@@ -42,3 +42,31 @@ def test_missing_table_gives_none(monkeypatch):
 def test_committed_table_has_the_workloads(w):
     with open(os.path.join(ROOT, "profiles", "hbm_traffic_by_workload.md")) as fh:
         assert f"| {w} | anneal_kernel |" in fh.read()
+
+
+def test_issue_row_matches_only_its_digest(tmp_path, monkeypatch):
+    p = tmp_path / "i.md"
+    d = bench.source_digest()
+    p.write_text("| Workload | Kernel | I | W | Per update | Busy | Sources |\n|---|---|---|---|---|---|---|\n"
+                 f"| c3 | anneal_kernel | 9.0e10 | 4,096 | 56.2 | 0.88 | `{d}` |\n")
+    monkeypatch.setattr(bench, "ISSUE_TABLE", str(p))
+    assert bench.measured_issue("c3", "anneal_kernel") == (56.2, 0.88)
+    assert bench.measured_issue("c2", "anneal_kernel") is None
+    p.write_text(p.read_text().replace(d, "0123456789abcdef"))
+    assert bench.measured_issue("c3", "anneal_kernel") is None
+
+
+def test_survey_op_count_reproduces_the_workload_table():
+    """The workload table's estimates: 74 lane-operations per update on the
+    torus (degree 4, timing on), 76 on the n = 2,000 graph (degree 6)."""
+    assert bench.survey_ops_per_update(4.0, True) == 74.0
+    assert bench.survey_ops_per_update(6.0, True) == 76.0
+    # the gfx950 lower bound of the same updates
+    assert bench.ops_per_update(4 * bench.OPS_EDGE_FOUR_TRIALS, True) == 41.25
+    assert bench.ops_per_update(6 * bench.OPS_EDGE_ONE_TRIAL, True) == 43.25
+
+
+def test_default_workload_is_the_torus():
+    import argparse
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    assert 'ap.add_argument("--workload", default="c3"' in src

@@ -1,0 +1,164 @@
+"""GPU value-level pins of the per-update arithmetic: the device tanh and the
+device decision (Eq. 1), evaluated through the C ABI's test entry points and
+compared value by value with the oracle.
+
+* Every float32 in [0, 9] and its negation: the device tanh equals the
+  oracle's psa_ref_tanh bit for bit (the kernels evaluate the same fixed
+  operation order; |x| >= 9 gives exactly +-1, checked on a grid above 9).
+* The decision: for inputs x and random words placed so that r lies within
+  2^-16 of tanh(x) -- where the kernels abandon the hardware estimate and
+  evaluate tanh itself -- and further away, the device's +-1 equals the
+  oracle's tanh(x) > r; both branches are taken, and exact ties (r equal to
+  tanh(x)) give -1.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+CHUNK = 1 << 26          # floats per device call
+NINE = np.float32(9.0).view(np.uint32)
+
+
+@pytest.fixture(scope="module")
+def psa():
+    from paper_2601_14476_amd import psa as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(psa, torch):
+    stream = torch.cuda.Stream()
+    c = psa.Context(0, stream)
+    yield c
+    c.close()
+
+
+def _oracle_tanh(x):
+    """psa_ref_tanh over a large array, split over threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    parts = np.array_split(x, 16)
+    with ThreadPoolExecutor(16) as ex:
+        return np.concatenate(list(ex.map(oracle.tanh_array, parts)))
+
+
+def _device_tanh(psa, ctx, torch, bits_lo, bits_hi, negate):
+    xb = torch.arange(bits_lo, bits_hi, dtype=torch.int64, device="cuda")
+    if negate:
+        xb = xb - (1 << 31)   # the sign bit set, as a signed 32-bit pattern
+    x = xb.to(torch.int32).view(torch.float32).contiguous()
+    y = torch.empty_like(x)
+    psa._check(psa.psa_debug_tanh(ctx.handle, x.numel(), psa._ptr(x), psa._ptr(y)),
+               "psa_debug_tanh")
+    ctx.synchronize()
+    return x.cpu().numpy(), y.cpu().numpy()
+
+
+@pytest.mark.parametrize("negate", [False, True])
+def test_device_tanh_every_float_in_0_9(psa, ctx, torch, negate):
+    """All 1,091,567,617 float32 values of [0, 9] (bit patterns 0 .. 9.0f),
+    or their negations, in chunks of 2^26."""
+    top = int(NINE) + 1
+    bad_total = 0
+    for lo in range(0, top, CHUNK):
+        hi = min(lo + CHUNK, top)
+        x, y = _device_tanh(psa, ctx, torch, lo, hi, negate)
+        ref = _oracle_tanh(x)
+        bad = np.flatnonzero(y.view(np.uint32) != ref.view(np.uint32))
+        if bad.size:
+            k = bad[:5]
+            pytest.fail(f"{bad.size} of [{lo:#x}, {hi:#x}) differ (negate={negate}); first "
+                        f"x={x[k].tolist()} device={y[k].tolist()} oracle={ref[k].tolist()}")
+        bad_total += bad.size
+    assert bad_total == 0
+
+
+def test_device_tanh_saturates_above_nine(psa, ctx, torch):
+    x = np.concatenate([np.linspace(9.0, 1e6, 100001, dtype=np.float32),
+                        np.array([np.inf, np.finfo(np.float32).max, 9.000001], np.float32)])
+    x = np.concatenate([x, -x])
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.empty_like(xd)
+    psa._check(psa.psa_debug_tanh(ctx.handle, xd.numel(), psa._ptr(xd), psa._ptr(yd)), "tanh")
+    ctx.synchronize()
+    y = yd.cpu().numpy()
+    np.testing.assert_array_equal(y, np.sign(x).astype(np.float32))
+    np.testing.assert_array_equal(y.view(np.uint32), oracle.tanh_array(x).view(np.uint32))
+
+
+def _decide(psa, ctx, torch, x, words):
+    xd = torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()
+    wd = torch.from_numpy(np.ascontiguousarray(words, np.uint32).view(np.int32)).cuda()
+    out = torch.empty(x.size, dtype=torch.uint8, device="cuda")
+    psa._check(psa.psa_debug_decide(ctx.handle, x.size, psa._ptr(xd), psa._ptr(wd), psa._ptr(out)),
+               "psa_debug_decide")
+    ctx.synchronize()
+    return out.cpu().numpy()
+
+
+def _words_near(y, offsets, rng):
+    """Words whose r = (2j + 1) 2^-24 - 1 is `offsets` lattice steps from the
+    lattice point nearest y (j = word >> 8; the low byte is random)."""
+    j0 = np.rint((y.astype(np.float64) + 1.0) * 2.0 ** 23 - 0.5).astype(np.int64)
+    j = np.clip(j0 + offsets, 0, (1 << 24) - 1)
+    low = rng.integers(0, 256, size=j.size)
+    return ((j << 8) | low).astype(np.uint32)
+
+
+def test_device_decision_near_and_far_from_r(psa, ctx, torch):
+    rng = np.random.default_rng(11)
+    count = 4_000_000
+    # inputs across the range the kernels see, including tiny and saturated ones
+    x = np.concatenate([rng.uniform(-9.5, 9.5, count // 2),
+                        rng.standard_normal(count // 4) * 0.05,
+                        rng.uniform(-40, 40, count // 4)]).astype(np.float32)
+    y = oracle.tanh_array(x)
+    # r within +-1000 lattice steps (2^-23 each) of tanh(x): |r - tanh| < 2^-16
+    # for the inner 128 steps, so both branches occur
+    off = rng.integers(-1000, 1001, size=x.size)
+    words = _words_near(y, off, rng)
+    r = oracle.r_array(words)
+    want = y > r
+    got = _decide(psa, ctx, torch, x, words)
+    up = (got & 1).astype(bool)
+    bad = np.flatnonzero(up != want)
+    assert bad.size == 0, (f"{bad.size} decisions differ; first x={x[bad[:5]].tolist()} "
+                           f"r={r[bad[:5]].tolist()}")
+    fallback = (got & 2) != 0
+    near = np.abs(y.astype(np.float64) - r.astype(np.float64)) < 2.0 ** -17
+    far = np.abs(y.astype(np.float64) - r.astype(np.float64)) > 2.0 ** -14
+    # the exact recipe decides every close call, the estimate every clear one
+    assert fallback[near].all()
+    assert not fallback[far].any()
+    assert 0.05 < fallback.mean() < 0.95
+    # uniform random words: about 2^-16 of the decisions take the exact recipe
+    w2 = rng.integers(0, 1 << 32, size=x.size, dtype=np.uint64).astype(np.uint32)
+    got2 = _decide(psa, ctx, torch, x, w2)
+    np.testing.assert_array_equal((got2 & 1).astype(bool), y > oracle.r_array(w2))
+
+
+def test_device_decision_ties_give_minus_one(psa, ctx, torch):
+    """r == tanh(x) exactly: tanh values in [0.5, 1) are multiples of 2^-24,
+    and the odd ones lie on the r lattice; the strict comparison gives -1."""
+    rng = np.random.default_rng(12)
+    x = rng.uniform(0.56, 8.0, 2_000_000).astype(np.float32)
+    y = oracle.tanh_array(x)
+    q = np.rint(y.astype(np.float64) * 2.0 ** 24).astype(np.int64)
+    odd = (q % 2 == 1) & (y < 1.0)
+    x, y = x[odd], y[odd]
+    j = ((y.astype(np.float64) + 1.0) * 2.0 ** 23 - 0.5).astype(np.int64)
+    words = ((j << 8) | rng.integers(0, 256, size=j.size)).astype(np.uint32)
+    r = oracle.r_array(words)
+    assert np.array_equal(r, y), "tie construction"
+    got = _decide(psa, ctx, torch, np.concatenate([x, -x]),
+                  np.concatenate([words, _words_near(-y, np.zeros(y.size, np.int64), rng)]))
+    assert not (got & 1).any()
+    assert x.size > 100_000

@@ -1,10 +1,14 @@
 """GPU tests of the solution-quality harness: its traces, sweeps and cycle
-series are the same anneals the library runs directly, aggregated."""
+series are the same anneals the library runs directly, aggregated, and they
+equal the oracle's: every cycle of an energy trace against the oracle
+stepped one cycle at a time, every row of a sweep or cycle series against
+the oracle's anneals of all trials."""
 import json
 
 import numpy as np
 import pytest
 
+import oracle
 from paper_2601_14476_amd import experiments, inputs
 
 pytestmark = pytest.mark.gpu
@@ -23,10 +27,69 @@ def ctx(psa):
     c.close()
 
 
+GRAPH = inputs.gnm(300, 900, 77)
+
+
 @pytest.fixture(scope="module")
 def graph(psa, ctx):
-    n, u, v, w = inputs.gnm(300, 900, 77)
+    n, u, v, w = GRAPH
     return psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
+
+
+def _oracle_cuts(cycles, trials, seed, sig=(0.0, 0.0, 0.0, 1.0), t_res=0):
+    """Final cuts of all trials of one anneal, computed by the oracle."""
+    n, u, v, w = GRAPH
+    i0, _, _ = oracle.schedule_paper(n, u, v, -w, cycles)
+    lam, dlt, thr = oracle.variability(n, seed, *sig)
+    if t_res:
+        per = oracle.periods(n, seed, sig[2], t_res)
+        return oracle.anneal_period(n, u, v, -w, None, i0, lam, dlt, per, t_res, seed, 0,
+                                    trials)[2]
+    return oracle.anneal(n, u, v, -w, None, i0, lam, dlt, thr, seed, 0, trials)[2]
+
+
+def test_energy_trace_every_cycle_matches_oracle(psa, ctx, graph):
+    """pSA, SpSA and TApSA with all three variability factors: the energy of
+    every trial after every cycle equals the oracle advanced one cycle at a
+    time (held inputs and field windows carried between its calls)."""
+    n, u, v, w = GRAPH
+    cycles, trials, seed = 20, 8, 3
+    sig = (0.1, 0.1, 0.1, 0.8)
+    kw = dict(sigma_lambda=sig[0], sigma_delta=sig[1], sigma_nu=sig[2], p_mean=sig[3])
+    i0, _, _ = oracle.schedule_paper(n, u, v, -w, cycles)
+    lam, dlt, thr = oracle.variability(n, seed, *sig)
+    for alg in experiments.ALGORITHMS:
+        e = experiments.energy_trace(psa, ctx, graph, cycles, trials, seed, alg, **kw)
+        s = oracle.init_spins(n, seed, 0, trials)
+        state = None
+        for t in range(cycles):
+            if alg == "psa":
+                s = oracle.run(n, u, v, -w, None, i0, lam, dlt, thr, seed, 0, trials, t, t + 1, s)
+            elif alg == "spsa":
+                s, state = oracle.run_spsa(n, u, v, -w, None, i0, lam, dlt, thr, 1 << 23, seed, 0,
+                                           trials, t, t + 1, s, state)
+            else:
+                s, state = oracle.run_tapsa(n, u, v, -w, None, i0, lam, dlt, thr, 4, seed, 0,
+                                            trials, t, t + 1, s, state)
+            E, _ = oracle.energy_cut(n, u, v, -w, None, s)
+            np.testing.assert_array_equal(e[t], E, err_msg=f"{alg} cycle {t}")
+
+
+def test_sweep_and_cycle_rows_match_oracle(psa, ctx, graph):
+    for factor, values in (("nu", [0.0, 0.2]), ("lambda", [0.5]), ("delta", [0.3])):
+        rows = experiments.sigma_sweep(psa, ctx, graph, factor, values, 30, 6, 1)
+        for r, s in zip(rows, values):
+            sig = {"nu": (0.0, 0.0, s, 0.8 if s > 0 else 1.0), "lambda": (s, 0.0, 0.0, 1.0),
+                   "delta": (0.0, s, 0.0, 1.0)}[factor]
+            cut = _oracle_cuts(30, 6, 1, sig)
+            assert r["mean_cut"] == float(cut.mean()) and r["best_cut"] == int(cut.max())
+            assert r["std_cut"] == float(cut.std())
+    per = experiments.sigma_sweep(psa, ctx, graph, "nu", [0.3], 12, 4, 1, t_res=10)
+    cut = _oracle_cuts(12, 4, 1, (0.0, 0.0, 0.3, 1.0), t_res=10)
+    assert per[0]["mean_cut"] == float(cut.mean()) and per[0]["best_cut"] == int(cut.max())
+    for r in experiments.cut_vs_cycles(psa, ctx, graph, [5, 40], 6, 2):
+        cut = _oracle_cuts(r["cycles"], 6, 2)
+        assert r["mean_cut"] == float(cut.mean()) and r["best_cut"] == int(cut.max())
 
 
 def test_energy_trace_ends_at_the_anneal(psa, ctx, graph):

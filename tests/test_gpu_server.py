@@ -39,10 +39,10 @@ def _specs():
     ]
 
 
-def _submit(srv, spec, spins=True):
+def _submit(srv, spec, spins=True, **kw):
     (n, u, v, w), T, S, seed, sig = spec
     return srv.submit(n, u, v, w, S, T, seed, spins=spins, sigma_lambda=sig[0],
-                      sigma_delta=sig[1], sigma_nu=sig[2], p_mean=sig[3])
+                      sigma_delta=sig[1], sigma_nu=sig[2], p_mean=sig[3], **kw)
 
 
 def test_served_results_equal_alone(psa):
@@ -66,7 +66,7 @@ def test_served_results_equal_alone(psa):
         np.testing.assert_array_equal(S, rS)
         np.testing.assert_array_equal(E, rE)
         np.testing.assert_array_equal(C, rC)
-        assert r.submit_us <= r.admit_us <= r.end_us
+        assert r.submit_us <= r.admit_us <= r.start_us <= r.end_us
     (n, u, v, w), T, S_, seed, sig = specs[2]
     i0, _, _ = oracle.schedule_paper(n, u, v, -w, S_)
     lam, dl, thr = oracle.variability(n, seed, *sig)
@@ -78,10 +78,11 @@ def test_served_results_equal_alone(psa):
 def test_budget_serialises_and_rejects(psa):
     ctx = psa.Context(0)
     specs = _specs()[:3]
-    # a budget of about one of these jobs: they queue for memory
+    # a budget of about one of these jobs: they queue for memory (the CSR path
+    # is forced, so that no dense matrix is reserved for them)
     budget = 150_000
     srv = psa.Server(ctx, hbm_budget_bytes=budget, quantum_steps=25)
-    tickets = [_submit(srv, sp, spins=False) for sp in specs]
+    tickets = [_submit(srv, sp, spins=False, path=psa.PSA_PATH_CSR) for sp in specs]
     big = srv.submit(*inputs.gnm(20000, 60000, 9), 10, 200, 1)      # alone above budget
     while True:
         st = srv.stats()
@@ -117,5 +118,64 @@ def test_cancel_timeout_and_bad_request(psa):
     r, (S, E, C) = srv.result(ok)
     assert r.status == psa.PSA_JOB_DONE
     np.testing.assert_array_equal(S, _alone(psa, ctx, ok_spec)[0])
+    srv.close()
+    ctx.close()
+
+
+def _wait_for(cond, what, limit_s=30.0):
+    t0 = time.perf_counter()
+    while not cond():
+        if time.perf_counter() - t0 > limit_s:
+            raise AssertionError(f"timed out waiting for {what}")
+        time.sleep(0.001)
+
+
+def test_queue_limit_returns_eagain(psa):
+    """max_waiting = 2: with one long job resident (one slot), two more wait
+    and the next submission is refused with PSA_EAGAIN until one is admitted."""
+    ctx = psa.Context(0)
+    srv = psa.Server(ctx, max_resident=1, quantum_steps=50, max_waiting=2)
+    n, u, v, w = inputs.gnm(2000, 6000, 21)
+    long_job = srv.submit(n, u, v, w, 1_000_000, 32, 1)
+    _wait_for(lambda: srv.stats()["resident"] == 1, "the long job to be admitted")
+    small = _specs()[4]
+    queued = [_submit(srv, small, spins=False), _submit(srv, small, spins=False)]
+    with pytest.raises(psa.PsaError) as e:
+        _submit(srv, small, spins=False)
+    assert e.value.status == psa.PSA_EAGAIN
+    assert srv.stats()["waiting"] == 2
+    srv.cancel(long_job)
+    assert srv.wait(long_job).status == psa.PSA_JOB_CANCELED
+    for t in queued:                       # admitted once the slot frees up
+        assert srv.wait(t).status == psa.PSA_JOB_DONE
+    later = _submit(srv, small, spins=False)
+    assert srv.wait(later).status == psa.PSA_JOB_DONE
+    srv.close()
+    ctx.close()
+
+
+def test_dense_job_footprint_counts_its_matrix(psa):
+    """A served dense-path job is charged what it holds on the device: its
+    graph with the dense coupling matrix, its dense spin buffers and run state
+    (the same allocations as the job created alone), plus read-out staging."""
+    n, u, v, w = inputs.erdos_renyi(3000, 0.08, 31)
+    T = 64
+    ctx = psa.Context(0)
+    g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
+    alone = psa.Job(ctx, g, 100_000, T, 2, path=psa.PSA_PATH_DENSE)
+    assert alone.dense
+    held = g.info()["device_bytes"] + alone.info()["device_bytes"]
+    np_ = (n + 127) // 128 * 128
+    assert g.info()["device_bytes"] >= np_ * np_ // 4           # the 2-bit matrix
+    alone.close()
+    g.close()
+    srv = psa.Server(ctx, quantum_steps=50)
+    t = srv.submit(n, u, v, w, 100_000, T, 2, path=psa.PSA_PATH_DENSE)
+    _wait_for(lambda: srv.stats()["resident"] == 1, "the dense job to be admitted")
+    used = srv.stats()["used_bytes"]
+    assert held <= used <= held + (1 << 20), (held, used)
+    srv.cancel(t)
+    assert srv.wait(t).status == psa.PSA_JOB_CANCELED
+    assert srv.stats()["used_bytes"] == 0
     srv.close()
     ctx.close()
