@@ -56,6 +56,8 @@ def _device_tanh(psa, ctx, torch, bits_lo, bits_hi, negate):
         xb = xb - (1 << 31)   # the sign bit set, as a signed 32-bit pattern
     x = xb.to(torch.int32).view(torch.float32).contiguous()
     y = torch.empty_like(x)
+    # the inputs are written on torch's stream; the library runs on its own
+    torch.cuda.current_stream().synchronize()
     psa._check(psa.psa_debug_tanh(ctx.handle, x.numel(), psa._ptr(x), psa._ptr(y)),
                "psa_debug_tanh")
     ctx.synchronize()
@@ -87,6 +89,7 @@ def test_device_tanh_saturates_above_nine(psa, ctx, torch):
     x = np.concatenate([x, -x])
     xd = torch.from_numpy(x).cuda()
     yd = torch.empty_like(xd)
+    torch.cuda.current_stream().synchronize()
     psa._check(psa.psa_debug_tanh(ctx.handle, xd.numel(), psa._ptr(xd), psa._ptr(yd)), "tanh")
     ctx.synchronize()
     y = yd.cpu().numpy()
@@ -98,6 +101,7 @@ def _decide(psa, ctx, torch, x, words):
     xd = torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()
     wd = torch.from_numpy(np.ascontiguousarray(words, np.uint32).view(np.int32)).cuda()
     out = torch.empty(x.size, dtype=torch.uint8, device="cuda")
+    torch.cuda.current_stream().synchronize()
     psa._check(psa.psa_debug_decide(ctx.handle, x.size, psa._ptr(xd), psa._ptr(wd), psa._ptr(out)),
                "psa_debug_decide")
     ctx.synchronize()
