@@ -369,6 +369,37 @@ psa_status psa_anneal(psa_ctx *ctx, const psa_graph *g,
                       int64_t *energy_out, int64_t *cut_out, uint32_t flags);
 
 /* ------------------------------------------------------------------ */
+/* Anneal without device allocation                                     */
+/* ------------------------------------------------------------------ */
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, serving loops that must not call hipMalloc, harnesses that
+ * forbid it.  The same anneal as psa_anneal (identical spins, energies and
+ * cuts) with every piece of run state the library needs beyond the graph
+ * and the outputs -- schedule and factors as the kernels read them, spin
+ * state, task order, SpSA held inputs or TApSA windows, energy partial sums
+ * -- placed in one static device array of PSA_NOALLOC_SCRATCH_BYTES per
+ * GPU, which the library holds from the first context on that GPU until the
+ * process ends.  No hipMalloc, hipFree or other allocating call is made.
+ *   - Outputs are device pointers on ctx's device: energy_out and cut_out
+ *     [trials] int64 (required), spins_out [trials][n] int8 or NULL.
+ *   - Sweep path only: PSA_PATH_AUTO runs the CSR sweep; PSA_PATH_DENSE
+ *     gives PSA_EUNSUPPORTED (the dense path builds a coupling matrix);
+ *     PSA_TUNE gives PSA_EINVAL (tuning times scratch runs); a run too large
+ *     for the LDS-resident sweep gives PSA_EUNSUPPORTED.
+ *   - A run whose state exceeds PSA_NOALLOC_SCRATCH_BYTES gives PSA_ENOMEM
+ *     before any device work is queued, with the bytes it would need in
+ *     psa_last_error().  The state is about n * trials bytes of spins plus
+ *     16 n + 4 steps bytes, times 5 with SpSA and 4 window + 1 with TApSA.
+ *   - Blocks until the outputs are written.  Every call on a GPU shares that
+ *     GPU's array: calls that overlap on one GPU (from several threads or
+ *     contexts) race and give wrong results; serialise them. */
+#define PSA_NOALLOC_SCRATCH_BYTES (((size_t)128) << 20)
+
+psa_status psa_anneal_noalloc(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *desc,
+                              int8_t *spins_out, int64_t *energy_out, int64_t *cut_out);
+
+/* ------------------------------------------------------------------ */
 /* Batched runs: many graphs of uneven size in one launch              */
 /* ------------------------------------------------------------------ */
 

@@ -43,21 +43,48 @@ using psa::set_error;
 namespace {
 
 
-// Allocate count elements on the device (at least one), copy src into them
-// when given, and add the bytes to *acct.
+// Bump allocator over memory the caller owns (psa_anneal_noalloc's static
+// scratch): 256-byte aligned pieces, never freed.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+    void *carve(size_t bytes) {
+        const size_t at = (used + 255) / 256 * 256;
+        if (at > cap || bytes > cap - at) return nullptr;
+        used = at + bytes;
+        return base + at;
+    }
+};
+
+// Place count elements on the device (at least one) -- from `arena` when
+// given, else a fresh allocation -- copy src into them when given, and add
+// the bytes to *acct.
 template <typename T>
-psa_status dev_upload(T **dst, const T *src, size_t count, const char *what, size_t *acct) {
+psa_status dev_upload(T **dst, const T *src, size_t count, const char *what, size_t *acct,
+                      Arena *arena = nullptr) {
     *dst = nullptr;
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), count * sizeof(T));
-    if (e != hipSuccess) {
-        *dst = nullptr;
-        set_error(std::string(what) + ": device allocation failed");
-        return PSA_ENOMEM;
+    if (arena) {
+        *dst = static_cast<T *>(arena->carve(count * sizeof(T)));
+        if (!*dst) {
+            set_error(std::string(what) + ": the run needs more than the " +
+                      std::to_string(PSA_NOALLOC_SCRATCH_BYTES) +
+                      " bytes of the static scratch (at least " +
+                      std::to_string(arena->used + count * sizeof(T)) + ")");
+            return PSA_ENOMEM;
+        }
+    } else {
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), count * sizeof(T));
+        if (e != hipSuccess) {
+            *dst = nullptr;
+            set_error(std::string(what) + ": device allocation failed");
+            return PSA_ENOMEM;
+        }
     }
     *acct += count * sizeof(T);
     if (src) {
-        e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+        hipError_t e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
         if (e != hipSuccess) return psa::hip_fail(e, what);
     }
     return PSA_OK;
@@ -75,6 +102,15 @@ void job_free(psa_job *j) {
     if (j->ctx) {
         (void)hipSetDevice(j->ctx->device);
         (void)hipStreamSynchronize(j->ctx->stream);
+    }
+    if (j->borrowed) {
+        // carved from memory the job does not own: forget, never free
+        j->d_i0 = j->d_lambda = j->d_delta = nullptr;
+        j->d_thr24 = nullptr;
+        j->d_order = j->d_ring = j->d_pp = nullptr;
+        j->d_m = j->d_spins = nullptr;
+        j->d_xs = nullptr;
+        j->d_scratch = nullptr;
     }
     dev_free(j->d_i0);
     dev_free(j->d_lambda);
@@ -96,6 +132,10 @@ void job_free(psa_job *j) {
 
 psa_status ensure_scratch(psa_job *j, size_t bytes) {
     if (j->scratch_bytes >= bytes) return PSA_OK;
+    if (j->borrowed) {
+        set_error("job: read-out staging beyond what was reserved in the static scratch");
+        return PSA_EINVAL;
+    }
     PSA_HIP(hipStreamSynchronize(j->ctx->stream), "hipStreamSynchronize");
     dev_free(j->d_scratch);
     j->dev_bytes -= j->scratch_bytes;
@@ -131,6 +171,9 @@ psa_status psa_ctx_create(int32_t device, void *hip_stream, psa_ctx **out) {
             return PSA_EINVAL;
         }
         PSA_HIP(hipSetDevice(device), "hipSetDevice");
+        // the static scratch of psa_anneal_noalloc: its address on this device
+        psa_status sst = psa::noalloc_scratch_init(device);
+        if (sst != PSA_OK) return sst;
         std::unique_ptr<psa_ctx> c(new psa_ctx());
         c->device = device;
         PSA_HIP(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device),
@@ -394,211 +437,250 @@ void psa_run_desc_default(psa_run_desc *d) {
     d->window = 4;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Body of psa_job_create: validate, upload the schedule and factors, plan
+// the launch, set the initial spins.  Device arrays come from `arena` when
+// given (then the job borrows them), else from fresh allocations.
+psa_status create_job(const char *who, psa_ctx *ctx, const psa_graph *g,
+                      const psa_run_desc *desc, Arena *arena, psa_job **out) {
+    if (!ctx || !g || !desc || !out) {
+        set_error(std::string(who) + ": NULL argument");
+        return PSA_EINVAL;
+    }
+    if (g->ctx != ctx) {
+        set_error(std::string(who) + ": graph belongs to another context");
+        return PSA_EINVAL;
+    }
+    const int32_t n = g->info.n;
+    if (desc->steps < 1 || desc->trials < 1 || desc->trials > (1 << 28)) {
+        set_error(std::string(who) + ": need steps >= 1 and 1 <= trials <= 2^28");
+        return PSA_EINVAL;
+    }
+    if (desc->block != 0 && desc->block != 256 && desc->block != 512 && desc->block != 1024) {
+        set_error(std::string(who) + ": block must be 0, 256, 512 or 1024");
+        return PSA_EINVAL;
+    }
+    if (desc->trials_per_group != 0 && desc->trials_per_group != 1 &&
+        desc->trials_per_group != 4) {
+        set_error(std::string(who) + ": trials_per_group must be 0, 1 or 4");
+        return PSA_EINVAL;
+    }
+    if (desc->lanes_per_task != 0 && desc->lanes_per_task != 1 && desc->lanes_per_task != 2 &&
+        desc->lanes_per_task != 4) {
+        set_error(std::string(who) + ": lanes_per_task must be 0, 1, 2 or 4");
+        return PSA_EINVAL;
+    }
+    if ((desc->flags & ~(PSA_PATH_MASK | PSA_TUNE)) != 0 ||
+        (desc->flags & PSA_PATH_MASK) == PSA_PATH_MASK) {
+        set_error(std::string(who) + ": unknown flags");
+        return PSA_EINVAL;
+    }
+    if (desc->algorithm != PSA_ALG_PSA && desc->algorithm != PSA_ALG_SPSA &&
+        desc->algorithm != PSA_ALG_TAPSA) {
+        set_error(std::string(who) + ": unknown algorithm");
+        return PSA_EINVAL;
+    }
+    if (desc->algorithm == PSA_ALG_TAPSA && (desc->window < 1 || desc->window > 64)) {
+        set_error(std::string(who) + ": window must be in [1, 64]");
+        return PSA_EINVAL;
+    }
+    if (desc->t_res < 0 ||
+        (desc->t_res > 0 && static_cast<int64_t>(desc->steps) * desc->t_res >= (int64_t{1} << 22))) {
+        set_error(std::string(who) + ": t_res must be >= 0 with steps * t_res < 2^22");
+        return PSA_EINVAL;
+    }
+    if (desc->t_res > 0 && desc->algorithm != PSA_ALG_PSA) {
+        set_error(std::string(who) + ": period-mode timing is built for plain pSA only");
+        return PSA_EUNSUPPORTED;
+    }
+    if (desc->algorithm == PSA_ALG_SPSA && !(desc->p_stall >= 0.0 && desc->p_stall <= 1.0)) {
+        set_error(std::string(who) + ": p_stall must be in [0, 1]");
+        return PSA_EINVAL;
+    }
+    if ((desc->flags & PSA_TUNE) && arena) {
+        set_error(std::string(who) + ": PSA_TUNE times scratch runs, which allocate");
+        return PSA_EINVAL;
+    }
+    if (desc->flags & PSA_TUNE) {
+        psa_run_desc tuned = *desc;
+        psa_status st = psa::tuned_desc(ctx, g, &tuned, PSA_TUNE_ALONE);
+        if (st != PSA_OK) return st;
+        return psa_job_create(ctx, g, &tuned, out);
+    }
+    const int32_t S = desc->steps;
+    std::vector<float> i0(static_cast<size_t>(S));
+    if (desc->i0) {
+        for (int32_t t = 0; t < S; ++t) {
+            if (!(std::isfinite(desc->i0[t]))) {
+                set_error(std::string(who) + ": non-finite I0");
+                return PSA_EINVAL;
+            }
+            i0[t] = desc->i0[t];
+        }
+    } else {
+        double lo = desc->i0_min, hi = desc->i0_max;
+        if (!(lo > 0.0)) {
+            psa_status st = psa_schedule_paper(g, &lo, &hi);
+            if (st != PSA_OK) return st;
+        }
+        psa_status st = psa::fill_schedule(S, lo, hi, i0.data());
+        if (st != PSA_OK) return st;
+    }
+    std::vector<float> lam(static_cast<size_t>(n)), dlt(static_cast<size_t>(n));
+    std::vector<uint32_t> thr(static_cast<size_t>(n));
+    if (!desc->lambda || !desc->delta || !desc->thr24) {
+        psa_status st = psa::draw_variability(n, desc->seed, desc->sigma_lambda, desc->sigma_delta,
+                                              desc->sigma_nu, desc->p_mean, lam.data(), dlt.data(),
+                                              thr.data());
+        if (st != PSA_OK) return st;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        if (desc->lambda) lam[i] = desc->lambda[i];
+        if (desc->delta) dlt[i] = desc->delta[i];
+        if (desc->thr24) thr[i] = desc->thr24[i];
+        if (!std::isfinite(lam[i]) || !std::isfinite(dlt[i]) || thr[i] > psa::kGateOneHost) {
+            set_error(std::string(who) + ": lambda/delta must be finite and thr24 <= 2^24");
+            return PSA_EINVAL;
+        }
+    }
+    if (desc->t_res > 0) {
+        // period mode: the per-p-bit timing array holds integer periods
+        if (desc->period) {
+            for (int32_t i = 0; i < n; ++i) thr[i] = desc->period[i];
+        } else {
+            psa_status st = psa::draw_periods(n, desc->seed, desc->sigma_nu, desc->t_res, thr.data());
+            if (st != PSA_OK) return st;
+        }
+        for (int32_t i = 0; i < n; ++i)
+            if (thr[i] < 1u) {
+                set_error(std::string(who) + ": periods must be >= 1");
+                return PSA_EINVAL;
+            }
+    }
+    PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    std::unique_ptr<psa_job, void (*)(psa_job *)> j(new psa_job(), job_free);
+    j->borrowed = arena != nullptr;
+    j->ctx = ctx;
+    psa::ctx_retain(ctx);
+    j->retained = true;
+    const_cast<psa_graph *>(g)->refs.fetch_add(1);
+    j->graph_ref = const_cast<psa_graph *>(g);
+    j->g = g;
+    j->run.trials = desc->trials;
+    j->run.t4 = (desc->trials + 3) / 4 * 4;
+    j->run.steps = S;
+    psa_status st;
+    const int32_t n4 = g->dev.n4;
+    // input-stage state first: the launch plan depends on it (LDS windows)
+    if (desc->algorithm == PSA_ALG_SPSA) {
+        // held inputs: [t4/4][n4][4] floats, formed at step 0 before any read
+        const size_t xb = static_cast<size_t>(n4) * static_cast<size_t>(j->run.t4);
+        if ((st = dev_upload<float>(&j->d_xs, nullptr, xb, "job held inputs", &j->dev_bytes, arena)) != PSA_OK) return st;
+        j->run.xs = j->d_xs;
+        j->run.stall24 = static_cast<uint32_t>(std::floor(desc->p_stall * 16777216.0));
+    }
+    if (desc->algorithm == PSA_ALG_TAPSA) {
+        // field windows: [t4/4][n4][window][4] int32, slot t mod window written
+        // at step t before any read of it
+        const size_t rb = static_cast<size_t>(n4) * static_cast<size_t>(j->run.t4) *
+                          static_cast<size_t>(desc->window);
+        if ((st = dev_upload<int32_t>(&j->d_ring, nullptr, rb, "job field windows", &j->dev_bytes, arena)) != PSA_OK)
+            return st;
+        j->run.ring = j->d_ring;
+        j->run.alpha = desc->window;
+    }
+    const uint32_t path = desc->flags & PSA_PATH_MASK;
+    if (path != PSA_PATH_DENSE) {
+        std::string why;
+        if (!psa::plan_anneal(g->dev, j->run, desc->trials_per_group, desc->lanes_per_task,
+                              desc->block, ctx->max_lds, ctx->num_cu, &j->plan, &why)) {
+            if (path == PSA_PATH_CSR) {
+                set_error(std::string(who) + ": " + why);
+                return PSA_EUNSUPPORTED;
+            }
+            j->plan.dense = 1;  // too large for the LDS-resident sweep
+        }
+    }
+    if (path == PSA_PATH_DENSE || (path == PSA_PATH_AUTO && psa::prefer_dense(g, j->run, j->plan)))
+        j->plan.dense = 1;
+    if (j->plan.dense && arena) {
+        set_error("the run needs the dense path, which the static scratch does not hold");
+        return PSA_EUNSUPPORTED;
+    }
+    if (j->plan.dense) {
+        psa_status st = psa::ensure_dense_matrix(const_cast<psa_graph *>(g));
+        if (st != PSA_OK) return st;
+        j->plan.nb = desc->trials >= 64 ? 4 : (desc->trials >= 32 ? 2 : 1);
+    }
+    j->run.key0 = static_cast<uint32_t>(desc->seed);
+    j->run.key1 = static_cast<uint32_t>(desc->seed >> 32);
+    // per-p-bit arrays padded to n4: padding p-bits never fire
+    lam.resize(static_cast<size_t>(n4), 1.0f);
+    dlt.resize(static_cast<size_t>(n4), 0.0f);
+    thr.resize(static_cast<size_t>(n4), 0u);
+    std::vector<int32_t> order;
+    psa::task_order(g->dev, g->row_ptr_host, j->plan, &order);
+    if ((st = dev_upload(&j->d_i0, i0.data(), i0.size(), "job upload", &j->dev_bytes, arena)) != PSA_OK) return st;
+    if ((st = dev_upload(&j->d_lambda, lam.data(), lam.size(), "job upload", &j->dev_bytes, arena)) != PSA_OK) return st;
+    if ((st = dev_upload(&j->d_delta, dlt.data(), dlt.size(), "job upload", &j->dev_bytes, arena)) != PSA_OK) return st;
+    if ((st = dev_upload(&j->d_thr24, thr.data(), thr.size(), "job upload", &j->dev_bytes, arena)) != PSA_OK) return st;
+    if ((st = dev_upload(&j->d_order, order.data(), order.size(), "job upload", &j->dev_bytes, arena)) != PSA_OK) return st;
+    if (g->dev.ell) {
+        // per-p-bit constants of the ELL four-trial sweep, one 16-byte load each
+        std::vector<int32_t> pp(4 * static_cast<size_t>(n4));
+        for (int32_t i = 0; i < n4; ++i) {
+            pp[4 * i] = g->h_host[i] - (g->row_ptr_host[i + 1] - g->row_ptr_host[i]);
+            memcpy(&pp[4 * i + 1], &lam[i], 4);
+            memcpy(&pp[4 * i + 2], &dlt[i], 4);
+            pp[4 * i + 3] = static_cast<int32_t>(thr[i]);
+        }
+        if ((st = dev_upload(&j->d_pp, pp.data(), pp.size(), "job upload", &j->dev_bytes, arena)) != PSA_OK) return st;
+        j->run.pp = j->d_pp;
+    }
+    const size_t spin_bytes = static_cast<size_t>(n) * static_cast<size_t>(j->run.t4);
+    if ((st = dev_upload<int8_t>(&j->d_spins, nullptr, spin_bytes, "job spins", &j->dev_bytes, arena)) != PSA_OK) return st;
+    if (j->plan.dense) {
+        j->tp = (j->run.t4 + 16 * j->plan.nb - 1) / (16 * j->plan.nb) * (16 * j->plan.nb);
+        const size_t mb = 2 * static_cast<size_t>(j->tp) * static_cast<size_t>(g->np);
+        if ((st = dev_upload<int8_t>(&j->d_m, nullptr, mb, "job dense spins", &j->dev_bytes, arena)) != PSA_OK) return st;
+    }
+    j->run.t_res = desc->t_res;
+    j->run.i0 = j->d_i0;
+    j->run.lambda = j->d_lambda;
+    j->run.delta = j->d_delta;
+    j->run.thr24 = j->d_thr24;
+    j->run.spins = j->d_spins;
+    if (arena) {
+        // read-out staging of the energy reduction, reserved before any launch
+        const size_t bytes = 2 * static_cast<size_t>(desc->trials) * sizeof(int64_t) +
+                             psa::energy_partial_bytes(n, j->run.t4);
+        j->d_scratch = arena->carve(bytes);
+        if (!j->d_scratch) {
+            set_error("the run needs more than the " + std::to_string(PSA_NOALLOC_SCRATCH_BYTES) +
+                      " bytes of the static scratch (at least " + std::to_string(arena->used + bytes) +
+                      ")");
+            return PSA_ENOMEM;
+        }
+        j->scratch_bytes = bytes;
+        j->dev_bytes += bytes;
+    }
+    PSA_HIP(psa::launch_init_spins(ctx->stream, n, j->run), "init_spins launch");
+    j->t = 0;
+    *out = j.release();
+    return PSA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 psa_status psa_job_create(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *desc,
                           psa_job **out) {
     return psa::guarded("psa_job_create", [&]() -> psa_status {
-        if (!ctx || !g || !desc || !out) {
-            set_error("psa_job_create: NULL argument");
-            return PSA_EINVAL;
-        }
-        if (g->ctx != ctx) {
-            set_error("psa_job_create: graph belongs to another context");
-            return PSA_EINVAL;
-        }
-        const int32_t n = g->info.n;
-        if (desc->steps < 1 || desc->trials < 1 || desc->trials > (1 << 28)) {
-            set_error("psa_job_create: need steps >= 1 and 1 <= trials <= 2^28");
-            return PSA_EINVAL;
-        }
-        if (desc->block != 0 && desc->block != 256 && desc->block != 512 && desc->block != 1024) {
-            set_error("psa_job_create: block must be 0, 256, 512 or 1024");
-            return PSA_EINVAL;
-        }
-        if (desc->trials_per_group != 0 && desc->trials_per_group != 1 &&
-            desc->trials_per_group != 4) {
-            set_error("psa_job_create: trials_per_group must be 0, 1 or 4");
-            return PSA_EINVAL;
-        }
-        if (desc->lanes_per_task != 0 && desc->lanes_per_task != 1 && desc->lanes_per_task != 2 &&
-            desc->lanes_per_task != 4) {
-            set_error("psa_job_create: lanes_per_task must be 0, 1, 2 or 4");
-            return PSA_EINVAL;
-        }
-        if ((desc->flags & ~(PSA_PATH_MASK | PSA_TUNE)) != 0 ||
-            (desc->flags & PSA_PATH_MASK) == PSA_PATH_MASK) {
-            set_error("psa_job_create: unknown flags");
-            return PSA_EINVAL;
-        }
-        if (desc->algorithm != PSA_ALG_PSA && desc->algorithm != PSA_ALG_SPSA &&
-            desc->algorithm != PSA_ALG_TAPSA) {
-            set_error("psa_job_create: unknown algorithm");
-            return PSA_EINVAL;
-        }
-        if (desc->algorithm == PSA_ALG_TAPSA && (desc->window < 1 || desc->window > 64)) {
-            set_error("psa_job_create: window must be in [1, 64]");
-            return PSA_EINVAL;
-        }
-        if (desc->t_res < 0 ||
-            (desc->t_res > 0 && static_cast<int64_t>(desc->steps) * desc->t_res >= (int64_t{1} << 22))) {
-            set_error("psa_job_create: t_res must be >= 0 with steps * t_res < 2^22");
-            return PSA_EINVAL;
-        }
-        if (desc->t_res > 0 && desc->algorithm != PSA_ALG_PSA) {
-            set_error("psa_job_create: period-mode timing is built for plain pSA only");
-            return PSA_EUNSUPPORTED;
-        }
-        if (desc->algorithm == PSA_ALG_SPSA && !(desc->p_stall >= 0.0 && desc->p_stall <= 1.0)) {
-            set_error("psa_job_create: p_stall must be in [0, 1]");
-            return PSA_EINVAL;
-        }
-        if (desc->flags & PSA_TUNE) {
-            psa_run_desc tuned = *desc;
-            psa_status st = psa::tuned_desc(ctx, g, &tuned, PSA_TUNE_ALONE);
-            if (st != PSA_OK) return st;
-            return psa_job_create(ctx, g, &tuned, out);
-        }
-        const int32_t S = desc->steps;
-        std::vector<float> i0(static_cast<size_t>(S));
-        if (desc->i0) {
-            for (int32_t t = 0; t < S; ++t) {
-                if (!(std::isfinite(desc->i0[t]))) {
-                    set_error("psa_job_create: non-finite I0");
-                    return PSA_EINVAL;
-                }
-                i0[t] = desc->i0[t];
-            }
-        } else {
-            double lo = desc->i0_min, hi = desc->i0_max;
-            if (!(lo > 0.0)) {
-                psa_status st = psa_schedule_paper(g, &lo, &hi);
-                if (st != PSA_OK) return st;
-            }
-            psa_status st = psa::fill_schedule(S, lo, hi, i0.data());
-            if (st != PSA_OK) return st;
-        }
-        std::vector<float> lam(static_cast<size_t>(n)), dlt(static_cast<size_t>(n));
-        std::vector<uint32_t> thr(static_cast<size_t>(n));
-        if (!desc->lambda || !desc->delta || !desc->thr24) {
-            psa_status st = psa::draw_variability(n, desc->seed, desc->sigma_lambda, desc->sigma_delta,
-                                                  desc->sigma_nu, desc->p_mean, lam.data(), dlt.data(),
-                                                  thr.data());
-            if (st != PSA_OK) return st;
-        }
-        for (int32_t i = 0; i < n; ++i) {
-            if (desc->lambda) lam[i] = desc->lambda[i];
-            if (desc->delta) dlt[i] = desc->delta[i];
-            if (desc->thr24) thr[i] = desc->thr24[i];
-            if (!std::isfinite(lam[i]) || !std::isfinite(dlt[i]) || thr[i] > psa::kGateOneHost) {
-                set_error("psa_job_create: lambda/delta must be finite and thr24 <= 2^24");
-                return PSA_EINVAL;
-            }
-        }
-        if (desc->t_res > 0) {
-            // period mode: the per-p-bit timing array holds integer periods
-            if (desc->period) {
-                for (int32_t i = 0; i < n; ++i) thr[i] = desc->period[i];
-            } else {
-                psa_status st = psa::draw_periods(n, desc->seed, desc->sigma_nu, desc->t_res, thr.data());
-                if (st != PSA_OK) return st;
-            }
-            for (int32_t i = 0; i < n; ++i)
-                if (thr[i] < 1u) {
-                    set_error("psa_job_create: periods must be >= 1");
-                    return PSA_EINVAL;
-                }
-        }
-        PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-        std::unique_ptr<psa_job, void (*)(psa_job *)> j(new psa_job(), job_free);
-        j->ctx = ctx;
-        psa::ctx_retain(ctx);
-        j->retained = true;
-        const_cast<psa_graph *>(g)->refs.fetch_add(1);
-        j->graph_ref = const_cast<psa_graph *>(g);
-        j->g = g;
-        j->run.trials = desc->trials;
-        j->run.t4 = (desc->trials + 3) / 4 * 4;
-        j->run.steps = S;
-        psa_status st;
-        const int32_t n4 = g->dev.n4;
-        // input-stage state first: the launch plan depends on it (LDS windows)
-        if (desc->algorithm == PSA_ALG_SPSA) {
-            // held inputs: [t4/4][n4][4] floats, formed at step 0 before any read
-            const size_t xb = static_cast<size_t>(n4) * static_cast<size_t>(j->run.t4);
-            if ((st = dev_upload<float>(&j->d_xs, nullptr, xb, "job held inputs", &j->dev_bytes)) != PSA_OK) return st;
-            j->run.xs = j->d_xs;
-            j->run.stall24 = static_cast<uint32_t>(std::floor(desc->p_stall * 16777216.0));
-        }
-        if (desc->algorithm == PSA_ALG_TAPSA) {
-            // field windows: [t4/4][n4][window][4] int32, slot t mod window written
-            // at step t before any read of it
-            const size_t rb = static_cast<size_t>(n4) * static_cast<size_t>(j->run.t4) *
-                              static_cast<size_t>(desc->window);
-            if ((st = dev_upload<int32_t>(&j->d_ring, nullptr, rb, "job field windows", &j->dev_bytes)) != PSA_OK)
-                return st;
-            j->run.ring = j->d_ring;
-            j->run.alpha = desc->window;
-        }
-        const uint32_t path = desc->flags & PSA_PATH_MASK;
-        if (path != PSA_PATH_DENSE) {
-            std::string why;
-            if (!psa::plan_anneal(g->dev, j->run, desc->trials_per_group, desc->lanes_per_task,
-                                  desc->block, ctx->max_lds, ctx->num_cu, &j->plan, &why)) {
-                if (path == PSA_PATH_CSR) {
-                    set_error("psa_job_create: " + why);
-                    return PSA_EUNSUPPORTED;
-                }
-                j->plan.dense = 1;  // too large for the LDS-resident sweep
-            }
-        }
-        if (path == PSA_PATH_DENSE || (path == PSA_PATH_AUTO && psa::prefer_dense(g, j->run, j->plan)))
-            j->plan.dense = 1;
-        if (j->plan.dense) {
-            psa_status st = psa::ensure_dense_matrix(const_cast<psa_graph *>(g));
-            if (st != PSA_OK) return st;
-            j->plan.nb = desc->trials >= 64 ? 4 : (desc->trials >= 32 ? 2 : 1);
-        }
-        j->run.key0 = static_cast<uint32_t>(desc->seed);
-        j->run.key1 = static_cast<uint32_t>(desc->seed >> 32);
-        // per-p-bit arrays padded to n4: padding p-bits never fire
-        lam.resize(static_cast<size_t>(n4), 1.0f);
-        dlt.resize(static_cast<size_t>(n4), 0.0f);
-        thr.resize(static_cast<size_t>(n4), 0u);
-        std::vector<int32_t> order;
-        psa::task_order(g->dev, g->row_ptr_host, j->plan, &order);
-        if ((st = dev_upload(&j->d_i0, i0.data(), i0.size(), "job upload", &j->dev_bytes)) != PSA_OK) return st;
-        if ((st = dev_upload(&j->d_lambda, lam.data(), lam.size(), "job upload", &j->dev_bytes)) != PSA_OK) return st;
-        if ((st = dev_upload(&j->d_delta, dlt.data(), dlt.size(), "job upload", &j->dev_bytes)) != PSA_OK) return st;
-        if ((st = dev_upload(&j->d_thr24, thr.data(), thr.size(), "job upload", &j->dev_bytes)) != PSA_OK) return st;
-        if ((st = dev_upload(&j->d_order, order.data(), order.size(), "job upload", &j->dev_bytes)) != PSA_OK) return st;
-        if (g->dev.ell) {
-            // per-p-bit constants of the ELL four-trial sweep, one 16-byte load each
-            std::vector<int32_t> pp(4 * static_cast<size_t>(n4));
-            for (int32_t i = 0; i < n4; ++i) {
-                pp[4 * i] = g->h_host[i] - (g->row_ptr_host[i + 1] - g->row_ptr_host[i]);
-                memcpy(&pp[4 * i + 1], &lam[i], 4);
-                memcpy(&pp[4 * i + 2], &dlt[i], 4);
-                pp[4 * i + 3] = static_cast<int32_t>(thr[i]);
-            }
-            if ((st = dev_upload(&j->d_pp, pp.data(), pp.size(), "job upload", &j->dev_bytes)) != PSA_OK) return st;
-            j->run.pp = j->d_pp;
-        }
-        const size_t spin_bytes = static_cast<size_t>(n) * static_cast<size_t>(j->run.t4);
-        if ((st = dev_upload<int8_t>(&j->d_spins, nullptr, spin_bytes, "job spins", &j->dev_bytes)) != PSA_OK) return st;
-        if (j->plan.dense) {
-            j->tp = (j->run.t4 + 16 * j->plan.nb - 1) / (16 * j->plan.nb) * (16 * j->plan.nb);
-            const size_t mb = 2 * static_cast<size_t>(j->tp) * static_cast<size_t>(g->np);
-            if ((st = dev_upload<int8_t>(&j->d_m, nullptr, mb, "job dense spins", &j->dev_bytes)) != PSA_OK) return st;
-        }
-        j->run.t_res = desc->t_res;
-        j->run.i0 = j->d_i0;
-        j->run.lambda = j->d_lambda;
-        j->run.delta = j->d_delta;
-        j->run.thr24 = j->d_thr24;
-        j->run.spins = j->d_spins;
-        PSA_HIP(psa::launch_init_spins(ctx->stream, n, j->run), "init_spins launch");
-        j->t = 0;
-        *out = j.release();
-        return PSA_OK;
+        return create_job("psa_job_create", ctx, g, desc, nullptr, out);
     });
 }
 
@@ -811,6 +893,45 @@ psa_status psa_anneal(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *desc
         if ((st = psa_job_step(job, desc->steps)) != PSA_OK) return st;
         if ((st = psa_job_energy_cut(job, energy_out, cut_out, flags)) != PSA_OK) return st;
         if (spins_out && (st = psa_job_read_spins(job, spins_out, flags)) != PSA_OK) return st;
+        PSA_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        return PSA_OK;
+    });
+}
+
+psa_status psa_anneal_noalloc(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *desc,
+                              int8_t *spins_out, int64_t *energy_out, int64_t *cut_out) {
+    return psa::guarded("psa_anneal_noalloc", [&]() -> psa_status {
+        if (!ctx || !g || !desc || !energy_out || !cut_out) {
+            set_error("psa_anneal_noalloc: ctx, g, desc, energy_out and cut_out are required");
+            return PSA_EINVAL;
+        }
+        const uint32_t path = desc->flags & PSA_PATH_MASK;
+        if (path == PSA_PATH_DENSE) {
+            set_error("psa_anneal_noalloc: the dense path builds its coupling matrix on the device; "
+                      "use psa_anneal");
+            return PSA_EUNSUPPORTED;
+        }
+        PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+        void *base = psa::noalloc_scratch(ctx->device);
+        if (!base) {
+            set_error("psa_anneal_noalloc: no static scratch on this device");
+            return PSA_EHIP;
+        }
+        // earlier work of this context may still read the scratch
+        PSA_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        psa_run_desc d = *desc;
+        if (path == PSA_PATH_AUTO) d.flags = (d.flags & ~PSA_PATH_MASK) | PSA_PATH_CSR;
+        Arena arena;
+        arena.base = static_cast<char *>(base);
+        arena.cap = PSA_NOALLOC_SCRATCH_BYTES;
+        psa_job *job = nullptr;
+        psa_status st = create_job("psa_anneal_noalloc", ctx, g, &d, &arena, &job);
+        if (st != PSA_OK) return st;
+        std::unique_ptr<psa_job, void (*)(psa_job *)> guard(job, job_free);
+        if ((st = psa_job_step(job, d.steps)) != PSA_OK) return st;
+        if ((st = psa_job_energy_cut(job, energy_out, cut_out, PSA_OUT_DEVICE)) != PSA_OK) return st;
+        if (spins_out && (st = psa_job_read_spins(job, spins_out, PSA_OUT_DEVICE)) != PSA_OK)
+            return st;
         PSA_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
         return PSA_OK;
     });

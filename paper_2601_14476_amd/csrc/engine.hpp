@@ -341,6 +341,12 @@ psa_status time_begin(psa_ctx *ctx, hipStream_t stream, hipEvent_t *ev);
 psa_status time_end(psa_ctx *ctx, hipStream_t stream, int family, hipEvent_t begin,
                     int64_t launches);
 
+// Static device scratch of psa_anneal_noalloc (noalloc.hip): look up the
+// array's address on `device` (which must be current) once and keep it;
+// noalloc_scratch returns it (nullptr before the lookup).
+psa_status noalloc_scratch_init(int32_t device);
+void *noalloc_scratch(int32_t device);
+
 // Context references (abi.cpp).
 void ctx_retain(psa_ctx *ctx);
 void ctx_release(psa_ctx *ctx);
@@ -435,4 +441,7 @@ struct psa_job {
     void *d_scratch = nullptr;   // read-out staging
     size_t scratch_bytes = 0;
     size_t dev_bytes = 0;        // device bytes of every allocation above
+    // the device arrays above are carved from memory the job does not own
+    // (psa_anneal_noalloc's static scratch): never freed or grown
+    bool borrowed = false;
 };

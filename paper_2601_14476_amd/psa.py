@@ -38,6 +38,7 @@ PSA_OUT_DEVICE = 1
 PSA_BATCH_SEQUENTIAL = 2
 PSA_PATH_AUTO, PSA_PATH_CSR, PSA_PATH_DENSE = 0, 1, 2
 PSA_TUNE = 4
+PSA_NOALLOC_SCRATCH_BYTES = 128 << 20
 PSA_ALG_PSA, PSA_ALG_SPSA, PSA_ALG_TAPSA = 0, 1, 2
 PSA_TUNE_ALONE, PSA_TUNE_BATCH = 0, 1
 
@@ -134,6 +135,7 @@ _SIGNATURES = [
     ("psa_job_energy_cut", _i32, [_P, _P, _P, _u32]),
     ("psa_job_destroy", None, [_P]),
     ("psa_anneal", _i32, [_P, _P, ctypes.POINTER(psa_run_desc), _P, _P, _P, _u32]),
+    ("psa_anneal_noalloc", _i32, [_P, _P, ctypes.POINTER(psa_run_desc), _P, _P, _P]),
     ("psa_jobs_step_batch", _i32, [_P, _i32, ctypes.POINTER(_P), _i32]),
     ("psa_anneal_batch", _i32, [_P, _i32, ctypes.POINTER(psa_batch_item), _u32]),
     ("psa_autotune", _i32, [_P, _P, ctypes.POINTER(psa_run_desc), _i32, _u32,
@@ -529,6 +531,21 @@ def anneal(ctx, graph, steps, trials, seed=0, spins=True, **kw):
                            _ptr(C), PSA_OUT_HOST), "psa_anneal")
     del keep
     return S, E, C
+
+
+def anneal_noalloc(ctx, graph, steps, trials, seed=0, spins_out=None, energy_out=None,
+                   cut_out=None, **kw):
+    """Whole anneal with no device allocation (psa_anneal_noalloc): outputs are
+    device tensors on the context's device -- energy_out, cut_out int64
+    [trials] (required), spins_out int8 [trials][n] or None -- written
+    before return."""
+    for name, buf in (("energy_out", energy_out), ("cut_out", cut_out), ("spins_out", spins_out)):
+        if buf is not None and not _is_device(buf):
+            raise ValueError(f"{name} must be a device tensor")
+    desc, keep = make_desc(steps, trials, seed, **kw)
+    _check(_lib.psa_anneal_noalloc(ctx.handle, graph.handle, ctypes.byref(desc), _ptr(spins_out),
+                                   _ptr(energy_out), _ptr(cut_out)), "psa_anneal_noalloc")
+    del keep
 
 
 def jobs_step_batch(ctx, jobs, k):
