@@ -85,17 +85,25 @@ TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "hbm_traffic_by_workload.md")
 ISSUE_TABLE = os.path.join(ROOT, "profiles", "valu_issue_by_workload.md")
 
 
-def source_digest() -> str:
-    """sha256 (first 16 hex digits) over the library's sources: the C header
-    and every file under csrc/, names and bytes, in name order."""
+# The sources each measured kernel is compiled from: its own file, the
+# per-update arithmetic and the argument structures it reads.
+KERNEL_SOURCES = {
+    "anneal_kernel": ["anneal.hip", "device_math.hpp", "engine.hpp"],
+    "dense_step_kernel": ["dense.hip", "device_math.hpp", "engine.hpp"],
+    "period_kernel": ["period.hip", "device_math.hpp", "engine.hpp"],
+}
+
+
+def source_digest(kernel: str) -> str:
+    """sha256 (first 16 hex digits) over the sources `kernel` is compiled
+    from (names and bytes, in the listed order): the counter tables under
+    profiles/ are keyed on it, so a row stops applying once the kernel's
+    code changes, and only then."""
     h = hashlib.sha256()
-    files = [os.path.join(ROOT, "include", "psa.h")]
     csrc = os.path.join(ROOT, "paper_2601_14476_amd", "csrc")
-    files += [os.path.join(csrc, f) for f in sorted(os.listdir(csrc))
-              if f.endswith((".hip", ".hpp", ".cpp", ".h"))]
-    for f in files:
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for f in KERNEL_SOURCES[kernel]:
+        h.update(f.encode())
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -110,7 +118,7 @@ def measured_traffic(workload: str, kernel: str):
             lines = fh.read().splitlines()
     except OSError:
         return None
-    digest = source_digest()
+    digest = source_digest(kernel)
     for ln in lines:
         cells = [c.strip().strip("`") for c in ln.strip().strip("|").split("|")]
         if len(cells) == 6 and cells[0] == workload and cells[1] == kernel and cells[5] == digest:
@@ -127,7 +135,7 @@ def measured_issue(workload: str, kernel: str):
             lines = fh.read().splitlines()
     except OSError:
         return None
-    digest = source_digest()
+    digest = source_digest(kernel)
     for ln in lines:
         cells = [c.strip().strip("`") for c in ln.strip().strip("|").split("|")]
         if len(cells) == 7 and cells[0] == workload and cells[1] == kernel and cells[6] == digest:
@@ -319,7 +327,8 @@ def main():
                          "traffic table is keyed on")
     args = ap.parse_args()
     if args.source_digest:
-        print(source_digest())
+        for k in KERNEL_SOURCES:
+            print(k, source_digest(k))
         return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "

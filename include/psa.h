@@ -333,6 +333,13 @@ typedef struct psa_job_info {
     int64_t device_bytes;      /* device memory the job holds (run arrays,
                                   spin state, input-stage state, staging);
                                   its graph's is counted by the graph       */
+    int32_t period_classes;    /* period mode on the class sweep: distinct
+                                  periods (1..64; the sub-steps visit only
+                                  the p-bits that fire); 0 otherwise        */
+    int32_t period_resident;   /* with period_classes > 0: p-bits each lane
+                                  keeps resident (1, 2, 4 or 8; graphs of up
+                                  to 2,048 p-bits with |J| < 2^15), 0 if the
+                                  sweep visits them from records            */
 } psa_job_info;
 
 psa_status psa_job_get_info(const psa_job *job, psa_job_info *out);

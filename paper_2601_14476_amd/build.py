@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libpsa.so")
 
 SOURCES = [
     "anneal.hip", "dense.hip", "kernels.hip", "abi.cpp", "graph.cpp", "batch.cpp", "server.cpp",
-    "host_params.cpp", "tune.cpp", "noalloc.hip",
+    "host_params.cpp", "tune.cpp", "noalloc.hip", "period.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -111,6 +111,9 @@ void job_free(psa_job *j) {
         j->d_m = j->d_spins = nullptr;
         j->d_xs = nullptr;
         j->d_scratch = nullptr;
+        j->d_prec = nullptr;
+        j->d_pcls = nullptr;
+        j->d_pcache = nullptr;
     }
     dev_free(j->d_i0);
     dev_free(j->d_lambda);
@@ -122,6 +125,9 @@ void job_free(psa_job *j) {
     dev_free(j->d_xs);
     dev_free(j->d_ring);
     dev_free(j->d_pp);
+    dev_free(j->d_prec);
+    dev_free(j->d_pcls);
+    dev_free(j->d_pcache);
     dev_free(j->d_scratch);
     psa_ctx *ctx = j->retained ? j->ctx : nullptr;
     psa_graph *g = j->graph_ref;
@@ -640,6 +646,24 @@ psa_status create_job(const char *who, psa_ctx *ctx, const psa_graph *g,
         if ((st = dev_upload(&j->d_pp, pp.data(), pp.size(), "job upload", &j->dev_bytes, arena)) != PSA_OK) return st;
         j->run.pp = j->d_pp;
     }
+    if (desc->t_res > 0 && !j->plan.dense && j->plan.tpw == 1) {
+        // period mode, one trial per workgroup: the sweep over period classes
+        std::vector<psa::PeriodRec> recs;
+        std::vector<psa::PeriodClass> classes;
+        std::vector<uint32_t> ecache;
+        j->run.t_res = desc->t_res;
+        if (psa::plan_period(g->dev, j->run, g->row_ptr_host, g->col_host, g->val_host, g->h_host, lam,
+                             dlt, thr, ctx->max_lds,
+                             desc->block, &j->pplan, &recs, &classes, &ecache)) {
+            if ((st = dev_upload(&j->d_prec, recs.data(), recs.size(), "job upload", &j->dev_bytes, arena)) != PSA_OK) return st;
+            if ((st = dev_upload(&j->d_pcls, classes.data(), classes.size(), "job upload", &j->dev_bytes, arena)) != PSA_OK) return st;
+            if (!ecache.empty() &&
+                (st = dev_upload(&j->d_pcache, ecache.data(), ecache.size(), "job upload", &j->dev_bytes, arena)) != PSA_OK)
+                return st;
+        } else {
+            j->pplan = psa::PeriodPlan{};
+        }
+    }
     const size_t spin_bytes = static_cast<size_t>(n) * static_cast<size_t>(j->run.t4);
     if ((st = dev_upload<int8_t>(&j->d_spins, nullptr, spin_bytes, "job spins", &j->dev_bytes, arena)) != PSA_OK) return st;
     if (j->plan.dense) {
@@ -719,9 +743,14 @@ psa_status psa_job_step(psa_job *job, int32_t k) {
         hipEvent_t ev = nullptr;
         psa_status st = psa::time_begin(job->ctx, job->ctx->stream, &ev);
         if (st != PSA_OK) return st;
-        PSA_HIP(psa::launch_anneal(job->ctx->stream, job->g->dev, job->run, job->plan, job->d_order,
-                                   job->t, t_end),
-                "anneal launch");
+        if (job->pplan.nclass > 0)
+            PSA_HIP(psa::launch_period(job->ctx->stream, job->g->dev, job->run, job->pplan, job->d_prec,
+                                       job->d_pcls, job->d_pcache, job->t, t_end),
+                    "period sweep launch");
+        else
+            PSA_HIP(psa::launch_anneal(job->ctx->stream, job->g->dev, job->run, job->plan, job->d_order,
+                                       job->t, t_end),
+                    "anneal launch");
         if ((st = psa::time_end(job->ctx, job->ctx->stream, psa::kTimeAnneal, ev, 1)) != PSA_OK) return st;
         job->t = t_end;
         return PSA_OK;
@@ -741,6 +770,8 @@ psa_status psa_job_get_info(const psa_job *job, psa_job_info *out) {
         out->dense_encoding = job->plan.dense ? (job->g->dense_enc == psa::kDenseT2 ? 2 : 1) : 0;
         out->algorithm = job->run.ring ? PSA_ALG_TAPSA : (job->run.xs ? PSA_ALG_SPSA : PSA_ALG_PSA);
         out->device_bytes = static_cast<int64_t>(job->dev_bytes);
+        out->period_classes = job->pplan.nclass;
+        out->period_resident = job->pplan.resident_k;
         return PSA_OK;
     });
 }

@@ -26,29 +26,48 @@ struct Words4 {
     uint32_t x, y, z, w;
 };
 
+// State of one block between rounds: counter words and the round's key.
+struct PhiloxState {
+    uint32_t c0, c1, c2, c3, k0, k1;
+};
+
+// R more rounds of the block (a caller may split the ten rounds to place
+// them between other work).
+template <int R>
+__device__ __forceinline__ void philox_rounds(PhiloxState &s) {
+#pragma unroll
+    for (int round = 0; round < R; ++round) {
+        // one 32x32->64 multiply-add instruction per product on gfx950
+        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * s.c0;
+        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * s.c2;
+        // three-input XOR in one instruction (truth table 0x96)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p1 >> 32), s.c1, s.k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p0 >> 32), s.c3, s.k1, 0x96);
+        s.c1 = static_cast<uint32_t>(p1);
+        s.c3 = static_cast<uint32_t>(p0);
+        s.c0 = n0;
+        s.c2 = n2;
+        s.k0 += 0x9E3779B9u;
+        s.k1 += 0xBB67AE85u;
+    }
+}
+
+// The block's starting state; the key is uniform (one per run) and lives in
+// scalar registers, kept opaque here so that its schedule is formed on the
+// scalar unit at each use rather than hoisted out of the loops into spilled
+// registers.
+__device__ __forceinline__ PhiloxState philox_start(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                    uint32_t c3, uint32_t k0, uint32_t k1) {
+    asm volatile("" : "+s"(k0), "+s"(k1));
+    return PhiloxState{c0, c1, c2, c3, k0, k1};
+}
+
 __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1,
                                                 uint32_t c2, uint32_t c3,
                                                 uint32_t k0, uint32_t k1) {
-    // The key is uniform (one per run) and lives in scalar registers; kept
-    // opaque here, so that its schedule is formed on the scalar unit at each
-    // use rather than hoisted out of the loops into spilled registers.
-    asm volatile("" : "+s"(k0), "+s"(k1));
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        // one 32x32->64 multiply-add instruction per product on gfx950
-        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
-        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
-        // three-input XOR in one instruction (truth table 0x96)
-        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p1 >> 32), c1, k0, 0x96);
-        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p0 >> 32), c3, k1, 0x96);
-        c1 = static_cast<uint32_t>(p1);
-        c3 = static_cast<uint32_t>(p0);
-        c0 = n0;
-        c2 = n2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return Words4{c0, c1, c2, c3};
+    PhiloxState s = philox_start(c0, c1, c2, c3, k0, k1);
+    philox_rounds<10>(s);
+    return Words4{s.c0, s.c1, s.c2, s.c3};
 }
 
 __device__ __forceinline__ uint32_t word_of(const Words4 &w, uint32_t k) {

@@ -219,6 +219,49 @@ struct DenseJob {
     int32_t t_res;     // period mode: sub-steps per step (thr holds periods); 0 otherwise
 };
 
+// Period-mode sweep (period.hip): p-bits sorted by period into classes.
+// Record of the p-bit at one sorted position (32 bytes, two 16-byte loads):
+// its index, row bounds, bias and factors.
+struct PeriodRec {
+    int32_t i, rp0, rp1, h;
+    float lam, dlt;
+    int32_t cls, pad;  // class index (its period's rank)
+};
+// A class: the p-bits of one period, positions begin .. end-1.
+struct PeriodClass {
+    uint32_t period;
+    int32_t begin, end, pad;
+};
+constexpr int32_t kPeriodMaxClasses = 64;  // one countdown per lane of a wavefront
+struct PeriodPlan {
+    int32_t nclass = 0;      // 0: the run does not take the period sweep
+    int32_t block = 256;
+    int32_t in_lds = 0;      // edges (and for the class sweep, records) in LDS
+    int32_t pk32 = 0;        // edges read as col | J << 16 (else col, val)
+    int32_t sbuf = 0;        // bytes per LDS spin buffer
+    // resident lanes: lane l owns sorted positions l K .. l K + K - 1 with
+    // their first `cache` edge words in registers (K = 0: class sweep)
+    int32_t resident_k = 0;
+    int32_t cache = 0;
+    int32_t unit = 0;        // resident lanes: every |J| == 1 (negated spin copies)
+    size_t lds_bytes = 0;
+};
+// Plan the period sweep of a one-trial-per-workgroup run (false: more than
+// kPeriodMaxClasses distinct periods, no edges, or the spins do not fit in
+// LDS; block_req 256, 512 or 1024 sets the block, else automatic) and
+// build its records and classes from the host copies of the graph and factors.
+bool plan_period(const DevGraph &g, const DevRun &run, const std::vector<int32_t> &row_ptr_host,
+                 const std::vector<int32_t> &col_host, const std::vector<int32_t> &val_host,
+                 const std::vector<int32_t> &h_host, const std::vector<float> &lam,
+                 const std::vector<float> &dlt, const std::vector<uint32_t> &periods, size_t max_lds,
+                 int32_t block_req, PeriodPlan *plan, std::vector<PeriodRec> *recs,
+                 std::vector<PeriodClass> *classes, std::vector<uint32_t> *ecache);
+// Steps t_begin .. t_end-1 (t_res sub-steps each), one workgroup per trial;
+// ecache: the resident lanes' edge words ([n][cache], col | J << 16).
+hipError_t launch_period(hipStream_t stream, const DevGraph &g, const DevRun &run,
+                         const PeriodPlan &plan, const PeriodRec *recs, const PeriodClass *classes,
+                         const uint32_t *ecache, int32_t t_begin, int32_t t_end);
+
 // Choose tpw / lanes per task / CSR placement / block for a run
 // (tpw_req, lpt_req, block_req: 0 = automatic).  Returns false with a reason if n does not fit in LDS.
 bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t lpt_req,
@@ -438,6 +481,11 @@ struct psa_job {
     float *d_xs = nullptr;       // SpSA held inputs
     int32_t *d_ring = nullptr;   // TApSA field windows
     int32_t *d_pp = nullptr;     // per-p-bit constants of the ELL sweep
+    // period-mode sweep (pplan.nclass > 0): records and classes
+    psa::PeriodPlan pplan;
+    psa::PeriodRec *d_prec = nullptr;
+    psa::PeriodClass *d_pcls = nullptr;
+    uint32_t *d_pcache = nullptr;  // resident lanes' edge words
     void *d_scratch = nullptr;   // read-out staging
     size_t scratch_bytes = 0;
     size_t dev_bytes = 0;        // device bytes of every allocation above

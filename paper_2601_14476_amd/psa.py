@@ -73,7 +73,8 @@ class psa_tune_result(ctypes.Structure):
 class psa_job_info(ctypes.Structure):
     _fields_ = [("path", _u32), ("trials_per_group", _i32), ("lanes_per_task", _i32),
                 ("block", _i32), ("dense_encoding", _i32), ("algorithm", _u32),
-                ("device_bytes", _i64)]
+                ("device_bytes", _i64), ("period_classes", _i32),
+                ("period_resident", _i32)]
 
 
 class psa_timing(ctypes.Structure):

@@ -9,21 +9,25 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 
-def _table(tmp_path, digest):
+def _table(tmp_path, da, dd=None):
+    dd = dd or da
     p = tmp_path / "t.md"
     p.write_text("| Workload | Kernel | F | W | Bytes | Sources |\n|---|---|---|---|---|---|\n"
-                 f"| c2 | anneal_kernel | 1.0 | 2.0 | 4,096 | `{digest}` |\n"
-                 f"| c4-dense | dense_step_kernel | 1.0 | 2.0 | 8,192 | `{digest}` |\n")
+                 f"| c2 | anneal_kernel | 1.0 | 2.0 | 4,096 | `{da}` |\n"
+                 f"| c4-dense | dense_step_kernel | 1.0 | 2.0 | 8,192 | `{dd}` |\n")
     return str(p)
 
 
-def test_digest_is_stable_and_short():
-    a, b = bench.source_digest(), bench.source_digest()
+def test_digest_is_stable_short_and_per_kernel():
+    a, b = bench.source_digest("anneal_kernel"), bench.source_digest("anneal_kernel")
     assert a == b and len(a) == 16 and int(a, 16) >= 0
+    digests = {bench.source_digest(k) for k in bench.KERNEL_SOURCES}
+    assert len(digests) == len(bench.KERNEL_SOURCES)
 
 
 def test_traffic_row_matches_only_its_digest(tmp_path, monkeypatch):
-    monkeypatch.setattr(bench, "TRAFFIC_TABLE", _table(tmp_path, bench.source_digest()))
+    monkeypatch.setattr(bench, "TRAFFIC_TABLE", _table(tmp_path, bench.source_digest("anneal_kernel"),
+                                                      bench.source_digest("dense_step_kernel")))
     assert bench.measured_traffic("c2", "anneal_kernel") == 4096
     assert bench.measured_traffic("c4-dense", "dense_step_kernel") == 8192
     assert bench.measured_traffic("c2", "dense_step_kernel") is None
@@ -46,7 +50,7 @@ def test_committed_table_has_the_workloads(w):
 
 def test_issue_row_matches_only_its_digest(tmp_path, monkeypatch):
     p = tmp_path / "i.md"
-    d = bench.source_digest()
+    d = bench.source_digest("anneal_kernel")
     p.write_text("| Workload | Kernel | I | W | Per update | Busy | Sources |\n|---|---|---|---|---|---|---|\n"
                  f"| c3 | anneal_kernel | 9.0e10 | 4,096 | 56.2 | 0.88 | `{d}` |\n")
     monkeypatch.setattr(bench, "ISSUE_TABLE", str(p))

@@ -594,6 +594,85 @@ def test_period_mode_matches_oracle(psa, ctx, kind, tpw, lpt, path, t_res):
     np.testing.assert_array_equal(C, rC)
 
 
+def _resident_k(n, block):
+    """p-bits per lane of the resident period sweep (0: records sweep)."""
+    b = block or 1024
+    if n > 2048:
+        return 0
+    for k in {1024: (1, 2), 512: (1, 2, 4), 256: (1, 2, 4, 8)}[b]:
+        if k * b >= n:
+            return k
+    return 0
+
+
+@pytest.mark.parametrize("block", [0, 256, 512])
+@pytest.mark.parametrize("case", ["classes64", "classes65", "period_one", "pair_edges",
+                                  "rows_in_memory", "n3100", "n5000", "sparse_firing",
+                                  "long_rows", "int_weights", "n2048"])
+def test_period_class_sweep_matches_oracle(psa, ctx, case, block):
+    """The period-mode sweep over period classes (one trial per workgroup):
+    resident lanes (1, 2, 4 or 8 p-bits per lane at 256, 512 or 1,024 lanes;
+    graphs of up to 2,048 p-bits with 16-bit edge words) or the records
+    sweep (larger graphs, couplings too large for the packed edge words, too
+    many p-bits for the block's lanes).  Spins after chunks of cycles equal
+    the oracle's for up to 64 distinct periods (more fall back to the full
+    sweep), a class of period 1 (fires at every sub-step), rows in device
+    memory, periods so long that most sub-steps fire nothing, rows longer
+    than the cached edges, integer couplings with biases, and n = 2,048."""
+    t_res, S, T, seed = 10, 12, 7, 23
+    h = None
+    if case == "pair_edges":
+        n, u, v, j, h = _random_ising(400, 1500, 31, jmax=4)
+        j[::7] *= 9000       # |J| up to 36,000: no 16-bit coupling field
+    elif case == "rows_in_memory":
+        n, u, v, w = inputs.erdos_renyi(1500, 0.4, 32, weights="pm1")
+        j = -w
+    elif case == "n3100":
+        n, u, v, w = inputs.gnm(3100, 9000, 33)
+        j = -w
+    elif case == "n5000":
+        n, u, v, w = inputs.gnm(5000, 15000, 38)
+        j = -w
+    elif case == "long_rows":  # degrees ~20-60: past 12 and 16 cached edges
+        n, u, v, w = inputs.gnm(1800, 36000, 35)
+        j = -w
+    elif case == "int_weights":  # couplings up to 4 and biases: packed words
+        n, u, v, j, h = _random_ising(600, 2400, 36, jmax=4)
+    elif case == "n2048":  # the largest graph on resident lanes
+        n, u, v, w = inputs.gnm(2048, 7000, 37)
+        j = -w
+    else:
+        n, u, v, w = inputs.gnm(700, 2500, 34)
+        j = -w
+    idx = np.arange(n)
+    per = {"classes64": idx % 64 + 1, "classes65": idx % 65 + 1, "period_one": idx % 3 + 1,
+           "sparse_firing": 29 + 8 * (idx % 3)}.get(case)
+    if per is None:
+        per = oracle.periods(n, seed, 0.3, t_res)
+    per = np.ascontiguousarray(per, dtype=np.uint32)
+    g = psa.Graph.from_edges(ctx, n, u, v, j, h=h, maxcut=False)
+    i0 = oracle.schedule(S, 0.02, 0.9)
+    lam, dl, _ = oracle.variability(n, seed, 0.1, 0.2, 0.0, 1.0)
+    job = psa.Job(ctx, g, S, T, seed=seed, i0=i0, sigma_lambda=0.1, sigma_delta=0.2,
+                  t_res=t_res, period=per, trials_per_group=1, path=psa.PSA_PATH_CSR, block=block)
+    classes = len(np.unique(per))
+    info = job.info()
+    assert info["period_classes"] == (classes if classes <= 64 else 0)
+    k = _resident_k(n, block) if classes <= 64 and case != "pair_edges" else 0
+    assert info["period_resident"] == k
+    ref = oracle.init_spins(n, seed, 0, T)
+    t = 0
+    for k in (1, 4, 7):
+        job.step(k)
+        ref = oracle.run_period(n, u, v, j, h, i0, lam, dl, per, t_res, seed, 0, T, t, t + k, ref)
+        t += k
+        np.testing.assert_array_equal(job.read_spins(), ref, err_msg=f"{case} after cycle {t}")
+    E, C = job.energy_cut()
+    rE, rC = oracle.energy_cut(n, u, v, j, h, ref)
+    np.testing.assert_array_equal(E, rE)
+    np.testing.assert_array_equal(C, rC)
+
+
 def test_period_mode_edge_cases(psa, ctx):
     """t_res 1 with no timing spread is pSA; explicit periods are used as
     given; period mode with SpSA, zero periods and too many sub-steps are
