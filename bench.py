@@ -301,6 +301,8 @@ def main():
     ap.add_argument("--duration", type=float, default=20.0, help="c5: seconds of arrivals")
     ap.add_argument("--quantum", type=int, default=250, help="c5: steps per scheduling quantum")
     ap.add_argument("--max-resident", type=int, default=128, help="c5: resident job slots")
+    ap.add_argument("--alone-sample", type=int, default=12,
+                    help="c5: served jobs rerun one at a time for the comparison")
     ap.add_argument("--graphs", type=int, default=256,
                     help="c4: graphs in the batch (256 = the workload; fewer for profiling)")
     ap.add_argument("--no-tune", action="store_true",
@@ -336,6 +338,12 @@ def main():
               "multi-GPU figure is produced here.", file=sys.stderr)
         sys.exit(2)
 
+    pool = None
+    if args.workload == "c5":
+        # the serving benchmark's graph producers, started before anything
+        # in this process touches the GPU
+        import multiprocessing as mp
+        pool = mp.get_context("spawn").Pool(processes=8)
     import torch
     if args.calibrate_copy:
         src = torch.ones(args.calibrate_copy // 4, dtype=torch.int32, device="cuda")
@@ -352,7 +360,7 @@ def main():
     if args.workload == "c4-dense":
         return bench_dense(args)
     if args.workload == "c5":
-        return bench_serve(args)
+        return bench_serve(args, pool)
     spec = inputs.workload(args.workload)
     n, u, v, w = spec["n"], spec["u"], spec["v"], spec["w"]
     T, S = spec["trials"], spec["steps"]
@@ -692,56 +700,75 @@ def bench_dense(args):
     ctx.close()
 
 
-def bench_serve(args):
+def _serve_graph(spec):
+    """Worker of the serving benchmark's graph producer: one job's edge list."""
+    from paper_2601_14476_amd import inputs
+    return inputs.make_graph(spec["graph"])
+
+
+def bench_serve(args, pool):
     """Poisson arrivals at --rate jobs/s for --duration s; per job n in
-    [800, 20000] (random sparse, degree 4-50, +-1), steps in [1000, 10000],
-    trials in [32, 256], sigma in {0, 0.05, 0.1, 0.2}.  Each request carries
-    an edge list that the server ingests; edge lists come from a pool of 40
-    pre-generated graphs (sizes x degrees spanning the ranges), so the client
-    can keep up with the arrival rate.  Reports completed jobs/s, p50/p99
-    latency (submit to result) and served p-bit updates/s."""
+    [800, 20000] (random sparse G(n, m), degree 4-50, +-1 weights, the job's
+    own seeded graph), steps in [1000, 10000], trials in [32, 256], sigma in
+    {0, 0.05, 0.1, 0.2}.  A process pool generates the jobs' edge lists in
+    arrival order ahead of the arrivals (a client submits each at its
+    arrival time; any lag behind the schedule is reported).  Reports
+    completed jobs/s, p50/p99 latency (submit to result), served p-bit
+    updates/s, and -- on a sample of the served jobs rerun one at a time on
+    the same GPU, each tuned for running alone -- the one-at-a-time
+    updates/s, with the cuts of every sampled trial compared (identical)."""
     import threading
     import torch
     from paper_2601_14476_amd import inputs, psa
     trace = inputs.serve_trace(rate=args.rate, duration=args.duration)
-    sizes = [800, 3000, 6000, 10000, 14000, 17000, 20000, 20000]
-    degs = [4, 16, 30, 42, 50]
-    pool = {}
-    for a, n in enumerate(sizes[:7]):
-        for b, d in enumerate(degs):
-            pool[(a, b)] = inputs.gnm(n, n * d // 2, 7000 + 10 * a + b)
-    def pick(spec):
-        _, n, m, _, _ = spec["graph"]
-        d = 2 * m / n
-        a = min(range(7), key=lambda x: abs(sizes[x] - n))
-        b = min(range(5), key=lambda x: abs(degs[x] - d))
-        return pool[(a, b)]
+    # the producers' edge lists in arrival order, the first few seconds' worth
+    # ready before the clock starts
+    produced = pool.imap(_serve_graph, [sp for _, sp in trace], chunksize=1)
+    ahead = []
+    for _ in range(min(len(trace), int(4 * args.rate) + 8)):
+        ahead.append(next(produced))
     torch.cuda.set_device(0)
     ctx = psa.Context(0)
     srv = psa.Server(ctx, max_resident=args.max_resident, quantum_steps=args.quantum)
     tickets = []
     updates = []
+    lag = [0.0]
     t0 = time.perf_counter()
 
     def client():
-        for at, spec in trace:
+        for idx, (at, spec) in enumerate(trace):
+            if idx < len(ahead):
+                n, u, v, w = ahead[idx]
+            else:
+                n, u, v, w = next(produced)
             delay = at - (time.perf_counter() - t0)
             if delay > 0:
                 time.sleep(delay)
-            n, u, v, w = pick(spec)
+            else:
+                lag[0] = max(lag[0], -delay)
             tk = srv.submit(n, u, v, w, spec["steps"], spec["trials"], spec["seed"],
                             sigma_lambda=spec["sigma_lambda"], sigma_delta=spec["sigma_delta"],
                             sigma_nu=spec["sigma_nu"], p_mean=spec["p_mean"],
                             tune=not args.no_tune)
             tickets.append(tk)
             updates.append(n * spec["trials"] * spec["steps"])
+            if idx < len(ahead):
+                ahead[idx] = None
 
     th = threading.Thread(target=client)
     th.start()
-    th.join()
-    # progress while the queue drains (one line every ~20 s)
     last = time.perf_counter()
-    for i, tk in enumerate(tickets):
+    while th.is_alive():
+        th.join(timeout=5.0)
+        if time.perf_counter() - last > 20.0:
+            st = srv.stats()
+            print(f"[c5] {time.perf_counter() - t0:.0f}s submitted {len(tickets)}/{len(trace)} "
+                  f"completed {st['completed']} resident {st['resident']} waiting {st['waiting']}",
+                  file=sys.stderr, flush=True)
+            last = time.perf_counter()
+    pool.close()
+    # progress while the queue drains (one line every ~20 s)
+    for tk in tickets:
         while True:
             try:
                 srv.wait(tk, timeout_s=5.0)
@@ -758,17 +785,39 @@ def bench_serve(args):
     lat = []
     first_submit, last_end = None, 0
     done = 0
-    for tk in tickets:
-        r, _ = srv.result(tk)
+    cuts = {}
+    for j, tk in enumerate(tickets):
+        r, (_, _, C) = srv.result(tk)
         if r.status == psa.PSA_JOB_DONE:
             done += 1
             lat.append((r.end_us - r.submit_us) / 1e6)
             first_submit = r.submit_us if first_submit is None else min(first_submit, r.submit_us)
             last_end = max(last_end, r.end_us)
+            cuts[j] = C
     stats = srv.stats()
     srv.close()
     makespan = (last_end - first_submit) / 1e6
     lat = np.array(lat)
+    served = float(sum(updates) / makespan)
+    # one at a time: a sample across the trace, each alone and tuned alone
+    sample = sorted(cuts)[:: max(1, len(cuts) // max(1, args.alone_sample))][: args.alone_sample]
+    alone_upd, alone_s, same = 0, 0.0, True
+    for j in sample:
+        spec = trace[j][1]
+        n, u, v, w = _serve_graph(spec)
+        g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
+        kw = dict(sigma_lambda=spec["sigma_lambda"], sigma_delta=spec["sigma_delta"],
+                  sigma_nu=spec["sigma_nu"], p_mean=spec["p_mean"])
+        psa.tune_get(ctx, g, spec["steps"], spec["trials"], spec["seed"], **kw)
+        ctx.synchronize()
+        ta = time.perf_counter()
+        _, _, C = psa.anneal(ctx, g, spec["steps"], spec["trials"], spec["seed"], spins=False,
+                             tune=True, **kw)
+        alone_s += time.perf_counter() - ta
+        alone_upd += n * spec["trials"] * spec["steps"]
+        same = same and bool(np.array_equal(C, cuts[j]))
+        g.close()
+    ctx.close()
     line = {
         "metric": "served jobs/s (p50/p99 latency), 1 GPU",
         "value": done / makespan,
@@ -786,13 +835,20 @@ def bench_serve(args):
             "workload": "c5", "arrival_rate": args.rate, "duration_s": args.duration,
             "jobs": len(tickets), "completed": done, "failed": stats["failed"],
             "quantum_steps": args.quantum, "max_resident": args.max_resident,
+            "graphs": "each job's own seeded G(n, m)",
+            "submit_lag_max_s": lag[0],
             "latency_p50_s": float(np.percentile(lat, 50)),
             "latency_p99_s": float(np.percentile(lat, 99)),
             "latency_mean_s": float(lat.mean()),
-            "served_updates_per_s": float(sum(updates) / makespan),
+            "served_updates_per_s": served,
             "offered_updates_per_s": float(sum(updates) / args.duration),
             "makespan_s": makespan, "quanta": stats["quanta"],
+            "peak_resident": stats["peak_resident"],
             "autotuned": not args.no_tune,
+            "alone_sample_jobs": len(sample),
+            "alone_updates_per_s": alone_upd / alone_s if alone_s > 0 else None,
+            "served_vs_alone": served / (alone_upd / alone_s) if alone_s > 0 else None,
+            "alone_cuts_identical": same,
         },
     }
     print(json.dumps(line), flush=True)

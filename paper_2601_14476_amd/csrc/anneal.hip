@@ -331,17 +331,35 @@ __device__ __forceinline__ void field_ell(const Views &v, int32_t m, const uint3
                                           uint32_t acc[4]) {
     const unsigned char *cb = reinterpret_cast<const unsigned char *>(cur);
     const int32_t g0 = v.eptr[m], g1 = v.eptr[m + 1];
-#pragma unroll 2
-    for (int32_t gi = g0; gi < g1; ++gi) {
-        const u32x4 q = load_global_x4(v.ell + 4 * static_cast<size_t>(gi));
-        const uint32_t ev[4] = {q.x, q.y, q.z, q.w};
+    // groups eight (then four) at a time: their 16-byte loads in flight
+    // together, then their neighbour words; a last partial chunk of four
+    // reads its missing groups at the task's last group and adds nothing
+    // for them
+    auto chunk = [&](auto u_tag, int32_t gi, bool tail) __attribute__((always_inline)) {
+        constexpr int U = decltype(u_tag)::value;
+        u32x4 q[U];
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const uint32_t w = *reinterpret_cast<const uint32_t *>(cb + (ev[p] & ~3u));
-            const uint32_t neg = 0u - (ev[p] & 1u);
-            acc[p] += w ^ (neg & 0x01010101u);
+        for (int u = 0; u < U; ++u)
+            q[u] = load_global_x4(v.ell + 4 * static_cast<size_t>(tail ? min(gi + u, g1 - 1) : gi + u));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t ev[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const uint32_t w = *reinterpret_cast<const uint32_t *>(cb + (ev[p] & ~3u));
+                const uint32_t neg = 0u - (ev[p] & 1u);
+                const uint32_t c = w ^ (neg & 0x01010101u);
+                acc[p] += (!tail || gi + u < g1) ? c : 0u;
+            }
         }
+    };
+    int32_t gi = g0;
+    for (; gi + 8 <= g1; gi += 8) chunk(std::integral_constant<int, 8>{}, gi, false);
+    if (gi + 4 <= g1) {
+        chunk(std::integral_constant<int, 4>{}, gi, false);
+        gi += 4;
     }
+    if (gi < g1) chunk(std::integral_constant<int, 4>{}, gi, true);
 }
 
 // Four trials, +-1 bytes packed per word, general weights.
