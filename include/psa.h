@@ -469,10 +469,11 @@ typedef struct psa_tune_result {
  * scratch runs of `desc` (same graph, trials, schedule and factors) over
  * `probe_steps` steps (>= 1, clipped to the schedule) after one warm-up
  * step, and return the fastest.  The result is also stored in the
- * context's tuning cache, keyed by mode, trials, update rule and the
- * graph's shape class (n and mean degree within about 9 % and 19 %,
- * coupling encoding, rows of at most 255 entries), for PSA_TUNE.  Queues and waits on the context's
- * stream; the caller's jobs are not touched. */
+ * context's tuning cache, keyed by mode, trials (in batched mode, trials
+ * within a half octave), update rule and the graph's shape class (n and
+ * mean degree within about 9 % and 19 %, coupling encoding, rows of at most
+ * 255 entries), for PSA_TUNE.  Queues and waits on the context's stream;
+ * the caller's jobs are not touched. */
 psa_status psa_autotune(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *desc,
                         int32_t probe_steps, uint32_t mode, psa_tune_result *out);
 

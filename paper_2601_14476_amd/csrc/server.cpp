@@ -244,53 +244,59 @@ void scheduler_loop(psa_server *s) {
             }
         }
         // admission: first come first served among prepared jobs, by
-        // footprint and slot cap
-        while (!s->stop && static_cast<int32_t>(s->resident.size()) < s->opts.max_resident) {
-            auto it = std::find_if(s->waiting.begin(), s->waiting.end(),
-                                   [](const ServerJob *x) { return x->prepared; });
-            if (it == s->waiting.end()) break;
-            ServerJob *j = *it;
-            if (s->used_bytes + j->footprint > static_cast<size_t>(s->opts.hbm_budget_bytes)) {
-                if (!s->resident.empty()) break;  // wait for memory to free up
-                // alone it cannot fit: reject
+        // footprint and slot cap (called with the lock held; drops it while
+        // a job is uploaded and created)
+        auto admit_waiting = [&]() {
+            while (!s->stop && static_cast<int32_t>(s->resident.size()) < s->opts.max_resident) {
+                auto it = std::find_if(s->waiting.begin(), s->waiting.end(),
+                                       [](const ServerJob *x) { return x->prepared; });
+                if (it == s->waiting.end()) break;
+                ServerJob *j = *it;
+                if (s->used_bytes + j->footprint > static_cast<size_t>(s->opts.hbm_budget_bytes)) {
+                    if (!s->resident.empty()) break;  // wait for memory to free up
+                    // alone it cannot fit: reject
+                    s->waiting.erase(it);
+                    j->status = PSA_JOB_ERROR;
+                    j->error = PSA_ENOMEM;
+                    j->message = "job footprint exceeds the server's HBM budget";
+                    j->end_us = s->now_us();
+                    ++s->failed;
+                    s->cv_done.notify_all();
+                    continue;
+                }
                 s->waiting.erase(it);
-                j->status = PSA_JOB_ERROR;
-                j->error = PSA_ENOMEM;
-                j->message = "job footprint exceeds the server's HBM budget";
-                j->end_us = s->now_us();
-                ++s->failed;
-                s->cv_done.notify_all();
-                continue;
+                s->used_bytes += j->footprint;
+                j->admit_us = s->now_us();
+                lk.unlock();
+                const psa_status st =
+                    psa::guarded("server: admission", [&]() -> psa_status { return admit_job(s, j); });
+                std::string msg = st == PSA_OK ? "" : psa_last_error();
+                // the reservation becomes the bytes the job actually holds
+                const size_t held =
+                    st == PSA_OK ? held_bytes(j->graph, j->job, j->n, j->desc.trials, j->spins_out != nullptr)
+                                 : 0;
+                lk.lock();
+                if (st != PSA_OK) {
+                    release_device(j);
+                    s->used_bytes -= j->footprint;
+                    j->status = PSA_JOB_ERROR;
+                    j->error = st;
+                    j->message = msg;
+                    j->end_us = s->now_us();
+                    ++s->failed;
+                    s->cv_done.notify_all();
+                    continue;
+                }
+                s->used_bytes = s->used_bytes - j->footprint + held;
+                j->footprint = held;
+                j->status = PSA_JOB_RUNNING;
+                s->resident.push_back(j);
+                s->peak_resident = std::max(s->peak_resident, static_cast<int32_t>(s->resident.size()));
+                s->peak_used = std::max(s->peak_used, s->used_bytes);
             }
-            s->waiting.erase(it);
-            s->used_bytes += j->footprint;
-            j->admit_us = s->now_us();
-            lk.unlock();
-            const psa_status st =
-                psa::guarded("server: admission", [&]() -> psa_status { return admit_job(s, j); });
-            std::string msg = st == PSA_OK ? "" : psa_last_error();
-            // the reservation becomes the bytes the job actually holds
-            const size_t held =
-                st == PSA_OK ? held_bytes(j->graph, j->job, j->n, j->desc.trials, j->spins_out != nullptr)
-                             : 0;
-            lk.lock();
-            if (st != PSA_OK) {
-                release_device(j);
-                s->used_bytes -= j->footprint;
-                j->status = PSA_JOB_ERROR;
-                j->error = st;
-                j->message = msg;
-                j->end_us = s->now_us();
-                ++s->failed;
-                s->cv_done.notify_all();
-                continue;
-            }
-            s->used_bytes = s->used_bytes - j->footprint + held;
-            j->footprint = held;
-            j->status = PSA_JOB_RUNNING;
-            s->resident.push_back(j);
-            s->peak_resident = std::max(s->peak_resident, static_cast<int32_t>(s->resident.size()));
-            s->peak_used = std::max(s->peak_used, s->used_bytes);
+        };
+        if (s->resident.empty()) {
+            admit_waiting();
         }
         if (s->resident.empty()) {
             if (s->stop) break;
@@ -314,6 +320,12 @@ void scheduler_loop(psa_server *s) {
         lk.unlock();
         psa_status st = psa_jobs_step_batch(s->ctx, static_cast<int32_t>(handles.size()),
                                             handles.data(), quantum);
+        // while the quantum runs: admit waiting jobs (graph upload, job
+        // creation, tuning probes queued behind the quantum); they join the
+        // next quantum
+        lk.lock();
+        admit_waiting();
+        lk.unlock();
         if (st == PSA_OK) st = psa_ctx_synchronize(s->ctx);
         std::string qmsg = st == PSA_OK ? "" : psa_last_error();
         // retire finished (or failed / canceled) jobs

@@ -43,7 +43,12 @@ TuneKey tune_key(const psa_graph *g, int32_t trials, uint32_t mode, uint32_t alg
     const double n = std::max(g->info.n, 1);
     const double d = static_cast<double>(g->info.nnz) / n;
     const int64_t enc = dense_two_bit(g) ? 2 : (dense_encodable(g) ? 1 : 0);
-    return TuneKey{static_cast<int64_t>(mode), trials, static_cast<int64_t>(std::ceil(std::log2(n) * 8.0)),
+    // batched mode times copies of the run that fill the chip, so the trial
+    // count matters by its magnitude: half-octave classes; alone, exactly
+    const int64_t tkey = mode == PSA_TUNE_BATCH
+                             ? static_cast<int64_t>(std::ceil(std::log2(std::max(trials, 1)) * 2.0))
+                             : trials;
+    return TuneKey{static_cast<int64_t>(mode), tkey, static_cast<int64_t>(std::ceil(std::log2(n) * 8.0)),
                    static_cast<int64_t>(std::floor(std::log2(1.0 + d) * 4.0)), enc,
                    g->dev.max_degree <= 255 ? 1 : 0, static_cast<int64_t>(algorithm)};
 }

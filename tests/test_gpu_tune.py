@@ -68,6 +68,23 @@ def test_autotune_batch_follows_row_length(psa, ctx):
     assert psa.tune_cache_size(ctx) == 2
 
 
+def test_batch_tuning_classes_trials_by_half_octave(psa, ctx):
+    """In batched mode the cache keys trial counts by half octave (40 and 44
+    share a class, 64 does not); alone, by the exact count."""
+    psa.tune_clear(ctx)
+    n, u, v, w = inputs.gnm(1000, 3000, 69)
+    g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
+    psa.tune_get(ctx, g, 50, 40, 1, batch=True)
+    psa.tune_get(ctx, g, 50, 44, 1, batch=True)
+    assert psa.tune_cache_size(ctx) == 1
+    psa.tune_get(ctx, g, 50, 64, 1, batch=True)
+    assert psa.tune_cache_size(ctx) == 2
+    psa.tune_get(ctx, g, 50, 40, 1)
+    psa.tune_get(ctx, g, 50, 44, 1)
+    assert psa.tune_cache_size(ctx) == 4
+    psa.tune_clear(ctx)
+
+
 def test_tuned_batch_equals_untuned(psa, ctx):
     specs = [(inputs.erdos_renyi(1200, 0.1, 65), 64, 40),
              (inputs.gnm(1500, 4500, 66), 64, 35),
