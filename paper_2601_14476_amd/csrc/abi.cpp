@@ -103,6 +103,15 @@ void job_free(psa_job *j) {
         (void)hipSetDevice(j->ctx->device);
         (void)hipStreamSynchronize(j->ctx->stream);
     }
+    if (j->shares) {
+        // the run arrays are the source job's
+        j->d_i0 = j->d_lambda = j->d_delta = nullptr;
+        j->d_thr24 = nullptr;
+        j->d_order = j->d_pp = nullptr;
+        j->d_prec = nullptr;
+        j->d_pcls = nullptr;
+        j->d_pcache = nullptr;
+    }
     if (j->borrowed) {
         // carved from memory the job does not own: forget, never free
         j->d_i0 = j->d_lambda = j->d_delta = nullptr;
@@ -698,6 +707,60 @@ psa_status create_job(const char *who, psa_ctx *ctx, const psa_graph *g,
 }
 
 }  // namespace
+
+namespace psa {
+
+psa_status clone_job_for_timing(psa_job *src, psa_job **out) {
+    psa_ctx *ctx = src->ctx;
+    PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    std::unique_ptr<psa_job, void (*)(psa_job *)> j(new psa_job(), job_free);
+    j->ctx = ctx;
+    ctx_retain(ctx);
+    j->retained = true;
+    src->graph_ref->refs.fetch_add(1);
+    j->graph_ref = src->graph_ref;
+    j->g = src->g;
+    j->run = src->run;
+    j->plan = src->plan;
+    j->pplan = src->pplan;
+    j->tp = src->tp;
+    j->shares = src;
+    j->d_i0 = src->d_i0;
+    j->d_lambda = src->d_lambda;
+    j->d_delta = src->d_delta;
+    j->d_thr24 = src->d_thr24;
+    j->d_order = src->d_order;
+    j->d_pp = src->d_pp;
+    j->d_prec = src->d_prec;
+    j->d_pcls = src->d_pcls;
+    j->d_pcache = src->d_pcache;
+    psa_status st;
+    const int32_t n = src->g->info.n;
+    const size_t spin_bytes = static_cast<size_t>(n) * static_cast<size_t>(j->run.t4);
+    if ((st = dev_upload<int8_t>(&j->d_spins, nullptr, spin_bytes, "clone spins", &j->dev_bytes)) != PSA_OK) return st;
+    j->run.spins = j->d_spins;
+    const size_t n4t4 = static_cast<size_t>(src->g->dev.n4) * static_cast<size_t>(j->run.t4);
+    if (src->d_xs) {
+        if ((st = dev_upload<float>(&j->d_xs, nullptr, n4t4, "clone held inputs", &j->dev_bytes)) != PSA_OK) return st;
+        j->run.xs = j->d_xs;
+    }
+    if (src->d_ring) {
+        if ((st = dev_upload<int32_t>(&j->d_ring, nullptr, n4t4 * static_cast<size_t>(j->run.alpha),
+                                      "clone field windows", &j->dev_bytes)) != PSA_OK)
+            return st;
+        j->run.ring = j->d_ring;
+    }
+    if (src->d_m) {
+        const size_t mb = 2 * static_cast<size_t>(j->tp) * static_cast<size_t>(src->g->np);
+        if ((st = dev_upload<int8_t>(&j->d_m, nullptr, mb, "clone dense spins", &j->dev_bytes)) != PSA_OK) return st;
+    }
+    PSA_HIP(launch_init_spins(ctx->stream, n, j->run), "init_spins launch");
+    j->t = 0;
+    *out = j.release();
+    return PSA_OK;
+}
+
+}  // namespace psa
 
 extern "C" {
 

@@ -390,6 +390,11 @@ psa_status time_end(psa_ctx *ctx, hipStream_t stream, int family, hipEvent_t beg
 psa_status noalloc_scratch_init(int32_t device);
 void *noalloc_scratch(int32_t device);
 
+// A scratch copy of `src` for timing (abi.cpp): the same run and plan, its
+// own spins (initial state), input-stage state and dense spin buffers; the
+// read-only run arrays are shared with src, which must outlive it.
+psa_status clone_job_for_timing(psa_job *src, psa_job **out);
+
 // Context references (abi.cpp).
 void ctx_retain(psa_ctx *ctx);
 void ctx_release(psa_ctx *ctx);
@@ -492,4 +497,8 @@ struct psa_job {
     // the device arrays above are carved from memory the job does not own
     // (psa_anneal_noalloc's static scratch): never freed or grown
     bool borrowed = false;
+    // a timing clone: schedule, factors, task order and period records are
+    // another job's (kept alive by `shares`); only the spin and input-stage
+    // state and the staging are its own
+    psa_job *shares = nullptr;
 };

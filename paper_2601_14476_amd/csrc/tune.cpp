@@ -77,9 +77,12 @@ psa_status time_candidate(psa_ctx *ctx, const psa_graph *g, const psa_run_desc &
     }
     std::vector<JobPtr> owned;
     std::vector<psa_job *> jobs;
+    // one run, then clones sharing its read-only arrays (every job waits for
+    // the stream before it is freed, and none is launched after that)
     for (int32_t i = 0; i < copies; ++i) {
         psa_job *job = nullptr;
-        const psa_status st = psa_job_create(ctx, g, &d, &job);
+        const psa_status st = i == 0 ? psa_job_create(ctx, g, &d, &job)
+                                     : clone_job_for_timing(jobs[0], &job);
         if (st != PSA_OK) return st;
         owned.emplace_back(job, psa_job_destroy);
         jobs.push_back(job);
@@ -145,7 +148,22 @@ psa_status psa_autotune(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *de
             cands.push_back({PSA_PATH_CSR, 1, lpt});
         }
         const bool dense_ok = psa::dense_encodable(g) && g->info.n <= 32768;
-        if (dense_ok) cands.push_back({PSA_PATH_DENSE, 0, 0});
+        // the cost models: they also prune the dense candidate of a large
+        // graph that they put at more than twice the CSR time (its timing
+        // builds an n^2 coupling matrix on the host)
+        psa::DevRun mrun;
+        mrun.trials = base.trials;
+        mrun.t4 = (base.trials + 3) / 4 * 4;
+        psa::AnnealPlan mplan;
+        std::string why;
+        const double model_csr =
+            psa::plan_anneal(g->dev, mrun, 0, 0, 0, ctx->max_lds, ctx->num_cu, &mplan, &why)
+                ? 1e6 * psa::csr_step_seconds(g->dev, mrun, mplan)
+                : -1.0;
+        const double model_dense =
+            dense_ok ? 1e6 * psa::dense_step_seconds(g->info.n, mrun.t4, psa::dense_two_bit(g)) : -1.0;
+        const bool prune_dense = g->info.n > 4096 && model_csr > 0.0 && model_dense > 2.0 * model_csr;
+        if (dense_ok && !prune_dense) cands.push_back({PSA_PATH_DENSE, 0, 0});
 
         psa_tune_result r{};
         r.csr_us_per_step = -1.0;
@@ -170,15 +188,8 @@ psa_status psa_autotune(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *de
             psa::set_error("psa_autotune: no configuration applies to this graph");
             return PSA_EUNSUPPORTED;
         }
-        psa::DevRun run;
-        run.trials = base.trials;
-        run.t4 = (base.trials + 3) / 4 * 4;
-        psa::AnnealPlan plan;
-        std::string why;
-        r.model_csr_us = psa::plan_anneal(g->dev, run, 0, 0, 0, ctx->max_lds, ctx->num_cu, &plan, &why)
-                             ? 1e6 * psa::csr_step_seconds(g->dev, run, plan)
-                             : -1.0;
-        r.model_dense_us = dense_ok ? 1e6 * psa::dense_step_seconds(g->info.n, run.t4, psa::dense_two_bit(g)) : -1.0;
+        r.model_csr_us = model_csr;
+        r.model_dense_us = model_dense;
         {
             std::lock_guard<std::mutex> lock(ctx->tune_mu);
             ctx->tune_cache[psa::tune_key(g, base.trials, mode, base.algorithm)] = r;
