@@ -767,21 +767,27 @@ def bench_serve(args, pool):
                   file=sys.stderr, flush=True)
             last = time.perf_counter()
     pool.close()
-    # progress while the queue drains (one line every ~20 s)
+    # progress while the queue drains (one line every ~20 s, whether or not
+    # the job waited on has ended)
     for tk in tickets:
         while True:
+            ended = True
             try:
                 srv.wait(tk, timeout_s=5.0)
-                break
             except psa.PsaError as e:
                 if e.status != psa.PSA_ETIMEDOUT:
                     raise
+                ended = False
             if time.perf_counter() - last > 20.0:
                 st = srv.stats()
                 print(f"[c5] {time.perf_counter() - t0:.0f}s completed {st['completed']}/"
                       f"{len(tickets)} resident {st['resident']} waiting {st['waiting']}",
                       file=sys.stderr, flush=True)
                 last = time.perf_counter()
+            if ended:
+                break
+    print(f"[c5] drained at {time.perf_counter() - t0:.0f}s; one-at-a-time sample next",
+          file=sys.stderr, flush=True)
     lat = []
     first_submit, last_end = None, 0
     done = 0
@@ -802,7 +808,8 @@ def bench_serve(args, pool):
     # one at a time: a sample across the trace, each alone and tuned alone
     sample = sorted(cuts)[:: max(1, len(cuts) // max(1, args.alone_sample))][: args.alone_sample]
     alone_upd, alone_s, same = 0, 0.0, True
-    for j in sample:
+    for si, j in enumerate(sample):
+        print(f"[c5] alone {si + 1}/{len(sample)}: job {j}", file=sys.stderr, flush=True)
         spec = trace[j][1]
         n, u, v, w = _serve_graph(spec)
         g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
