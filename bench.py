@@ -412,13 +412,19 @@ def main():
     field_ops = 0.0 if jinfo["path"] == psa.PSA_PATH_DENSE else info["nnz"] / n * edge_ops(jinfo)
     opu = ops_per_update(field_ops, timing, args.algorithm)
     if args.t_res > 0:
-        # period mode: per cycle and p-bit, t_res period checks plus the
-        # expected number of firings (t_res / period) of an ungated update
+        # period mode: per cycle and p-bit, the expected number of firings
+        # (t_res / period), each an ungated update that draws a whole Philox
+        # block (the other three words of its counter belong to p-bits that
+        # fire at other sub-steps); the sweep over period classes tests
+        # periods per class, not per p-bit
         per = psa.periods_draw(n, spec["seed"], spec["sigma_nu"], args.t_res)
         fires = float(np.mean(args.t_res / per.astype(np.float64)))
-        opu = args.t_res * OPS_PERIOD + fires * ops_per_update(field_ops, False)
+        opu = fires * (ops_per_update(field_ops, False) + PHILOX_BLOCK_OPS * 3 / 4)
+        if jinfo["period_classes"] == 0:
+            opu += args.t_res * OPS_PERIOD
     achieved = opu * updates / (kernel_ms * 1e-3) / 1e12
-    kname = "dense_step_kernel" if job.dense else "anneal_kernel"
+    kname = ("dense_step_kernel" if job.dense else
+             "period_kernel" if args.t_res > 0 and jinfo["period_classes"] > 0 else "anneal_kernel")
     default_launch = (args.algorithm == "psa" and not args.t_res and args.path == "auto"
                       and not (args.block or args.tpw or args.lpt))
     # the three operation counts side by side (plain pSA in probability mode)
