@@ -632,6 +632,9 @@ psa_status create_job(const char *who, psa_ctx *ctx, const psa_graph *g,
     }
     j->run.key0 = static_cast<uint32_t>(desc->seed);
     j->run.key1 = static_cast<uint32_t>(desc->seed >> 32);
+    j->identity_factors = desc->algorithm == PSA_ALG_PSA && desc->t_res == 0;
+    for (int32_t i = 0; i < n && j->identity_factors; ++i)
+        j->identity_factors = lam[i] == 1.0f && dlt[i] == 0.0f && thr[i] >= psa::kGateOneHost;
     // per-p-bit arrays padded to n4: padding p-bits never fire
     lam.resize(static_cast<size_t>(n4), 1.0f);
     dlt.resize(static_cast<size_t>(n4), 0.0f);
@@ -724,6 +727,7 @@ psa_status clone_job_for_timing(psa_job *src, psa_job **out) {
     j->plan = src->plan;
     j->pplan = src->pplan;
     j->tp = src->tp;
+    j->identity_factors = src->identity_factors;
     j->shares = src;
     j->d_i0 = src->d_i0;
     j->d_lambda = src->d_lambda;

@@ -158,7 +158,8 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
     std::vector<psa_job *> live;
     std::vector<int32_t> by_enc[2];
     int32_t max_steps = 0, nb[2] = {4, 4};
-    bool plain[2] = {true, true};  // every run of the encoding is plain pSA
+    bool plain[2] = {true, true};     // every run of the encoding is plain pSA
+    bool identity[2] = {true, true};  // ... with identity factors and no gate
     for (int32_t j = 0; j < count; ++j) {
         psa_job *job = jobs[j];
         const psa_graph *g = job->g;
@@ -190,6 +191,7 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
         d.t_res = job->run.t_res;
         const int32_t e = g->dense_enc == kDenseT2 ? 1 : 0;
         plain[e] = plain[e] && d.xs == nullptr && d.ring == nullptr && d.t_res == 0;
+        identity[e] = identity[e] && job->identity_factors;
         by_enc[e].push_back(static_cast<int32_t>(table.size()));
         nb[e] = std::min(nb[e], job->plan.nb);
         table.push_back(d);
@@ -234,7 +236,8 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
         if (len[e] == 0) continue;
         PSA_HIP(psa::launch_dense_steps(ctx->stream2, static_cast<const psa::DenseJob *>(ctx->d_dense_table),
                                         dwork + off[e], static_cast<int32_t>(len[e]), nb[e],
-                                        e == 1 ? kDenseT2 : kDenseI8, plain[e], max_steps),
+                                        e == 1 ? kDenseT2 : kDenseI8,
+                                        plain[e] ? (identity[e] ? 2 : 1) : 0, max_steps),
                 "dense step launch");
         launches += max_steps;
     }

@@ -92,12 +92,18 @@ struct AFrag<kDenseT2> {
     v4i h[2];  // half h, word j: row block 2h + j/2, k-tile j % 2
 };
 
-// NB = 16-trial blocks per workgroup (trial tile = 16 NB).  PLAIN: every run
-// of the launch is pSA with one sub-step per step (no held inputs, windows or
-// periods), so the epilogue carries no run-time mode tests.
-template <int NB, int ENC, bool PLAIN>
+// NB = 16-trial blocks per workgroup (trial tile = 16 NB).  MODE: what every
+// run of the launch is -- kDenseAny: tested at run time; kDensePlain: pSA with
+// one sub-step per step (no held inputs, windows or periods), so the epilogue
+// carries no run-time mode tests; kDenseIdentity: that, and every p-bit has
+// lambda = 1, delta = 0 and no timing gate, so the pre-activation is the one
+// product I0 (float)L (exactly the general (I0 lambda)((float)L + delta) at
+// those values) and no gate word is drawn.
+enum : int { kDenseAny = 0, kDensePlain = 1, kDenseIdentity = 2 };
+template <int NB, int ENC, int MODE>
 __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kernel(const DenseJob *__restrict__ jobs,
                                                          const int4 *__restrict__ work, int32_t t_off) {
+    constexpr bool PLAIN = MODE != kDenseAny;
     constexpr int kTrials = 16 * NB;
     constexpr int kBVec = kTrials * (kKC / 16);        // 16-byte pieces of one spin chunk
     constexpr int kBPer = (kBVec + 255) / 256;  // 1 or 2
@@ -222,10 +228,39 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
     if (!active) return;
 
     // epilogue: lane owns p-bits 4m..4m+3 of each row block for trial columns
-    // nb.  The (row block, trial block) pairs run as a loop with a uniform
-    // index, so the body -- Philox blocks and four activations -- is emitted
-    // once per pass, keeping few registers live.
+    // nb.
     const float i0t = jb.i0[t];
+    if constexpr (MODE == kDenseIdentity) {
+        // one r block and four products per (row block, trial block) pair; the
+        // pairs unrolled with constant accumulator indices, a scheduling
+        // barrier between them keeping one pair's temporaries live at a time
+        const int32_t scale = jb.scale;
+        const uint32_t kpos = static_cast<uint32_t>(trial0 + lr);
+#pragma unroll
+        for (int e = 0; e < 4 * NB; ++e) {
+            const int rb = e / NB, nb = e % NB;
+            const int32_t i0 = wrow0 + rb * 16 + (lane >> 4) * 4;
+            const uint32_t k = kpos + static_cast<uint32_t>(nb * 16);
+            const bool valid = i0 < jb.n4 && static_cast<int32_t>(k) < jb.t4;
+            const int4 hh = *reinterpret_cast<const int4 *>(jb.h + (valid ? i0 : 0));
+            const Words4 r = philox4x32_10(tau, static_cast<uint32_t>(i0 >> 2), k, kTagR, jb.k0, jb.k1);
+            const int32_t hv[4] = {hh.x, hh.y, hh.z, hh.w};
+            const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+            uint32_t out = 0u;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int32_t L = hv[p] + scale * acc[rb][nb][p];
+                const float x = i0t * static_cast<float>(L);
+                out |= (pbit_up(x, rw[p]) ? 0x01u : 0xFFu) << (8 * p);
+            }
+            if (valid) *reinterpret_cast<uint32_t *>(nxt + static_cast<size_t>(k) * np + i0) = out;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        return;
+    }
+    // the other modes: the (row block, trial block) pairs run as a loop with a
+    // uniform index, so the body -- Philox blocks and four activations -- is
+    // emitted once per pass, keeping few registers live.
     const int32_t scale = jb.scale;
     const InputState st{jb.xs, jb.stall24, jb.ring, jb.alpha, jb.n4};
     auto update = [&](int e, const v4i a4) __attribute__((always_inline)) {
@@ -325,31 +360,37 @@ __global__ void from_dense_kernel(int32_t n, int32_t t4, int32_t np, const int8_
     spins[idx] = m[static_cast<size_t>(k) * np + i];
 }
 
-template <int ENC, bool PLAIN>
+template <int ENC, int MODE>
 hipError_t launch_dense_enc(hipStream_t stream, const DenseJob *jobs, const int4 *work, int32_t nwork,
                             int32_t nb, int32_t s) {
     switch (nb) {
-        case 1: hipLaunchKernelGGL((dense_step_kernel<1, ENC, PLAIN>), dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
-        case 2: hipLaunchKernelGGL((dense_step_kernel<2, ENC, PLAIN>), dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
-        case 4: hipLaunchKernelGGL((dense_step_kernel<4, ENC, PLAIN>), dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
+        case 1: hipLaunchKernelGGL((dense_step_kernel<1, ENC, MODE>), dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
+        case 2: hipLaunchKernelGGL((dense_step_kernel<2, ENC, MODE>), dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
+        case 4: hipLaunchKernelGGL((dense_step_kernel<4, ENC, MODE>), dim3(nwork), dim3(256), 0, stream, jobs, work, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <int ENC>
+hipError_t launch_dense_mode(hipStream_t stream, const DenseJob *jobs, const int4 *work, int32_t nwork,
+                             int32_t nb, int32_t mode, int32_t s) {
+    switch (mode) {
+        case kDenseAny: return launch_dense_enc<ENC, kDenseAny>(stream, jobs, work, nwork, nb, s);
+        case kDensePlain: return launch_dense_enc<ENC, kDensePlain>(stream, jobs, work, nwork, nb, s);
+        case kDenseIdentity: return launch_dense_enc<ENC, kDenseIdentity>(stream, jobs, work, nwork, nb, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_dense_steps(hipStream_t stream, const DenseJob *jobs, const int4 *work,
-                              int32_t nwork, int32_t nb, int32_t enc, bool plain, int32_t steps) {
+                              int32_t nwork, int32_t nb, int32_t enc, int32_t mode, int32_t steps) {
     if (nwork <= 0) return hipSuccess;
     for (int32_t s = 0; s < steps; ++s) {
-        hipError_t e;
-        if (enc == kDenseT2)
-            e = plain ? launch_dense_enc<kDenseT2, true>(stream, jobs, work, nwork, nb, s)
-                      : launch_dense_enc<kDenseT2, false>(stream, jobs, work, nwork, nb, s);
-        else
-            e = plain ? launch_dense_enc<kDenseI8, true>(stream, jobs, work, nwork, nb, s)
-                      : launch_dense_enc<kDenseI8, false>(stream, jobs, work, nwork, nb, s);
+        const hipError_t e = enc == kDenseT2 ? launch_dense_mode<kDenseT2>(stream, jobs, work, nwork, nb, mode, s)
+                                             : launch_dense_mode<kDenseI8>(stream, jobs, work, nwork, nb, mode, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -271,10 +271,12 @@ bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t 
 // Dense path launchers (dense.hip).  launch_dense_steps issues `steps`
 // launches; launch s advances every run of the work list (job, 256-row group,
 // trial tile of 16 nb; job -1 = empty slot) by its step t + s.  All runs of
-// one work list share the encoding `enc`; `plain` may be set only when every
-// run of the list is pSA without held inputs, windows or periods.
+// one work list share the encoding `enc`; `mode` 1 (plain) may be set only
+// when every run of the list is pSA without held inputs, windows or periods,
+// 2 (identity) only when besides every p-bit has lambda = 1, delta = 0 and
+// thr24 >= 2^24 (no timing gate); 0 tests each run's mode at run time.
 hipError_t launch_dense_steps(hipStream_t stream, const DenseJob *jobs, const int4 *work,
-                              int32_t nwork, int32_t nb, int32_t enc, bool plain, int32_t steps);
+                              int32_t nwork, int32_t nb, int32_t enc, int32_t mode, int32_t steps);
 hipError_t launch_to_dense(hipStream_t stream, int32_t n, int32_t t4, int32_t np, int32_t tp,
                            const int8_t *spins, int8_t *m);
 hipError_t launch_from_dense(hipStream_t stream, int32_t n, int32_t t4, int32_t np,
@@ -497,6 +499,8 @@ struct psa_job {
     // the device arrays above are carved from memory the job does not own
     // (psa_anneal_noalloc's static scratch): never freed or grown
     bool borrowed = false;
+    // every p-bit has lambda = 1, delta = 0 and thr24 >= 2^24 (no timing gate)
+    bool identity_factors = false;
     // a timing clone: schedule, factors, task order and period records are
     // another job's (kept alive by `shares`); only the spin and input-stage
     // state and the staging are its own
