@@ -646,14 +646,19 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
             return;
         }
     }
+    uint32_t acc_ell[4] = {0u, 0u, 0u, 0u};
+    float hdf[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     if constexpr (kEll) {
-        uint32_t acc[4] = {0u, 0u, 0u, 0u};
-        field_ell(v, m, cur, acc);
+        field_ell(v, m, cur, acc_ell);
 #pragma unroll
-        for (int p = 0; p < 4; ++p)
+        for (int p = 0; p < 4; ++p) {
+            hdf[p] = static_cast<float>(hd[p]);
+            if constexpr (ALG != kAlgPsa) {
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-                L[p][kk] = hd[p] + 2 * static_cast<int32_t>((acc[p] >> (8 * kk)) & 0xFFu);
+                for (int kk = 0; kk < 4; ++kk)
+                    L[p][kk] = hd[p] + 2 * static_cast<int32_t>((acc_ell[p] >> (8 * kk)) & 0xFFu);
+            }
+        }
     } else {
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
@@ -693,7 +698,18 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
         for (int p = 0; p < 4; ++p) {
             const bool fire = ALG == kAlgPeriod ? period_fires(t, th[p])
                                                 : (th[p] >= kGateOne || fires(gw[p], th[p]));
-            const float x = input_of<ALG>(a[p], d[p], L[p][kk], st, 4 * m + p, k, t, sw[p]);
+            float x;
+            if constexpr (kEll && ALG == kAlgPsa) {
+                // (float)L from the byte count directly: 2 count + (h - deg) is
+                // an integer below 2^24 in magnitude, so the one fma is exact
+                // and equals the converted field; then the pre-activation as
+                // everywhere, a ((float)L + delta)
+                const float cnt = static_cast<float>((acc_ell[p] >> (8 * kk)) & 0xFFu);
+                const float Lf = fmaf(2.0f, cnt, hdf[p]);
+                x = a[p] * (Lf + d[p]);
+            } else {
+                x = input_of<ALG>(a[p], d[p], L[p][kk], st, 4 * m + p, k, t, sw[p]);
+            }
             const bool up = goes_up(x, rw[p]);
             const uint32_t nb = kU ? (up ? 1u : 0u) : (up ? 0x01u : 0xFFu);
             if (fire) word[p] = (word[p] & ~(0xFFu << (8 * kk))) | (nb << (8 * kk));
