@@ -325,8 +325,8 @@ __device__ __forceinline__ void field_swar(const Views &v, int32_t i, const uint
 }
 
 // Four trials, unit weights, the task's rows from the per-task ELL array in
-// device memory (16 bytes per group: entry j of the four rows, 4 col | (J <
-// 0), the zero word past a row's end): no masks, one 16-byte load per group.
+// device memory (16 bytes per group: entry j of the four rows, col | (J < 0)
+// << 31, the zero word past a row's end): no masks, one 16-byte load per group.
 __device__ __forceinline__ void field_ell(const Views &v, int32_t m, const uint32_t *cur,
                                           uint32_t acc[4]) {
     const unsigned char *cb = reinterpret_cast<const unsigned char *>(cur);
@@ -346,8 +346,10 @@ __device__ __forceinline__ void field_ell(const Views &v, int32_t m, const uint3
             const uint32_t ev[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
-                const uint32_t w = *reinterpret_cast<const uint32_t *>(cb + (ev[p] & ~3u));
-                const uint32_t neg = 0u - (ev[p] & 1u);
+                // word index << 2 drops the sign bit; the sign, spread by an
+                // arithmetic shift, complements the four 0/1 bytes
+                const uint32_t w = *reinterpret_cast<const uint32_t *>(cb + (ev[p] << 2));
+                const uint32_t neg = static_cast<uint32_t>(static_cast<int32_t>(ev[p]) >> 31);
                 const uint32_t c = w ^ (neg & 0x01010101u);
                 acc[p] += (!tail || gi + u < g1) ? c : 0u;
             }

@@ -94,8 +94,8 @@ struct DevGraph {
     const uint16_t *ux16 = nullptr;    // [nnz] or null
     // unit weights, degree <= 255: per-task ELL rows for the four-trial sweep
     // streaming edges from device memory; group g = eptr[m] .. eptr[m+1]-1 of
-    // task m holds entry j of rows 4m..4m+3 as 4 col | (J < 0), past a row's
-    // end the zero word 4 n4
+    // task m holds entry j of rows 4m..4m+3 as col | (J < 0) << 31, past a
+    // row's end the zero word n4
     const uint32_t *ell = nullptr;     // [4 * groups] or null
     const int32_t *eptr = nullptr;     // [n4/4 + 1] or null
     const int32_t *h = nullptr;        // [n4]

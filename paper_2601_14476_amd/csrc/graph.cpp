@@ -141,14 +141,17 @@ psa_status finish_host_graph(int32_t n, const std::vector<int64_t> &row_ptr,
             for (int32_t p = 0; p < 4; ++p) d = std::max(d, g.rp32[4 * m + p + 1] - g.rp32[4 * m + p]);
             g.eptr[m + 1] = g.eptr[m] + d;
         }
-        const uint32_t zero = 4u * static_cast<uint32_t>(g.n4);
+        // an entry is the neighbour's word index with the coupling's sign in
+        // bit 31 (shifted out when the index becomes a byte address); past a
+        // row's end, the zero word n4
+        const uint32_t zero = static_cast<uint32_t>(g.n4);
         g.ell.assign(4 * static_cast<size_t>(g.eptr[tasks]), zero);
         for (int32_t m = 0; m < tasks; ++m)
             for (int32_t p = 0; p < 4; ++p) {
                 const int32_t i = 4 * m + p;
                 for (int32_t e = g.rp32[i]; e < g.rp32[i + 1]; ++e)
                     g.ell[4 * (static_cast<size_t>(g.eptr[m]) + (e - g.rp32[i])) + p] =
-                        4u * static_cast<uint32_t>(col[e]) | (val[e] < 0 ? 1u : 0u);
+                        static_cast<uint32_t>(col[e]) | (val[e] < 0 ? 0x80000000u : 0u);
             }
     }
     g.col = std::move(col);
