@@ -65,6 +65,7 @@ OPS_WINDOW = 2  # window sum: add the entering field, subtract the leaving one
 OPS_MEAN = 10  # window mean: convert, correctly rounded divide
 OPS_PERIOD = 6  # period test: convert, reciprocal, multiply, truncate, multiply-subtract, compare
 MFMA_I8_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak, TOP/s
+MFMA_F4_PEAK_TOPS = 10100.0  # dense fp4 matrix-core peak, TFLOP/s
 HBM_PEAK_GBS = 8000.0
 
 # The workload table's own estimate of the VALU work per update (written
@@ -532,14 +533,16 @@ def bench_batch(args):
         if rb["path"] == psa.PSA_PATH_DENSE:
             dense_jobs += 1
             dense_valu += ops_per_update(0.0, False) * upd
-            mfma_ops += 2.0 * n * n * sp["trials"] * sp["steps"]
-            # algorithmic bytes per step: the encoded couplings once per
-            # 64-trial tile, the spins read and written once
-            np_ = (n + 127) // 128 * 128
             enc = jobs[-1].info()["dense_encoding"]
+            # matrix work in int8-peak equivalents: 2-bit couplings run as
+            # fp4 x fp4 at twice the int8 rate
+            mfma_ops += 2.0 * n * n * sp["trials"] * sp["steps"] * (0.5 if enc == 2 else 1.0)
+            # algorithmic bytes per step: the encoded couplings once per
+            # 64-trial tile, the spins (fp4 or int8) read and written once
+            np_ = (n + 255) // 256 * 256 if enc == 2 else (n + 127) // 128 * 128
             tiles = (sp["trials"] + 63) // 64
             dense_bytes += (np_ * np_ * (0.25 if enc == 2 else 1.0) * tiles
-                            + 2 * n * sp["trials"]) * sp["steps"]
+                            + 2 * n * sp["trials"] * (0.5 if enc == 2 else 1.0)) * sp["steps"]
         else:
             valu_ops += ops_per_update(info["nnz"] / n * edge_ops(jobs[-1].info()), False) * upd
     S = max(sp["steps"] for sp in specs)
@@ -675,25 +678,27 @@ def bench_dense(args):
     tm = ctx.timing()
     per_us = tm["dense_ms"] / steps * 1e3
     n_arr = np.array([sp[0] for sp in specs], float)
-    npad = np.ceil(n_arr / 128) * 128
+    npad = np.ceil(n_arr / 256) * 256
     upd = float(n_arr.sum() * 64)
+    # 2-bit couplings: fp4 x fp4 products against the fp4 matrix peak; bytes:
+    # the couplings once per 64-trial tile, fp4 spins read and written
     mfma = (2 * n_arr ** 2 * 64).sum() / (per_us * 1e-6) / 1e12
-    hbm = (npad ** 2 / 4 + 2 * n_arr * 64).sum() / (per_us * 1e-6) / 1e9
+    hbm = (npad ** 2 / 4 + n_arr * 64).sum() / (per_us * 1e-6) / 1e9
     valu = ops_per_update(0.0, False) * upd / (per_us * 1e-6) / 1e12
-    fr = {"mfma": mfma / MFMA_I8_PEAK_TOPS, "alu": valu / VALU_PEAK_TOPS, "hbm": hbm / HBM_PEAK_GBS}
+    fr = {"mfma": mfma / MFMA_F4_PEAK_TOPS, "alu": valu / VALU_PEAK_TOPS, "hbm": hbm / HBM_PEAK_GBS}
     bound = max(fr, key=fr.get)
     line = {
         "metric": "p-bit updates/s (n x trials x steps / s), 1 GPU",
         "value": upd * steps / wall, "unit": "p-bit updates/s", "n_gpus": 1,
         "steps": steps, "warmup": 20, "ms_per_step": wall / steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "int8 couplings (2-bit encoded) x int8 spins -> int32 field",
+        "dtype": "fp4 couplings (2-bit encoded) x fp4 spins -> f32 field (exact integers)",
         "data": "synthetic",
         "config": {"workload": "c4-dense", "graphs": 48, "trials": 64, "n_range": [2000, 4000],
                    "p_range": [0.04, 0.1]},
         "roofline": {"bound": bound, "kernel": "dense_step_kernel",
                      "achieved": {"mfma": mfma, "alu": valu, "hbm": hbm}[bound],
-                     "peak": {"mfma": MFMA_I8_PEAK_TOPS, "alu": VALU_PEAK_TOPS, "hbm": HBM_PEAK_GBS}[bound],
+                     "peak": {"mfma": MFMA_F4_PEAK_TOPS, "alu": VALU_PEAK_TOPS, "hbm": HBM_PEAK_GBS}[bound],
                      "unit": "GB/s" if bound == "hbm" else "TOP/s", "frac": fr[bound],
                      "traffic": measured_traffic("c4-dense", "dense_step_kernel"),
                      "kernel_us_per_step": per_us, "dense_fracs": fr},

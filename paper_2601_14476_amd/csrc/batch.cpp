@@ -79,9 +79,10 @@ void build_work_list(const std::vector<int32_t> &trials, const std::vector<doubl
 
 // Automatic path choice.  Whole-device estimates per step: the CSR walk
 // issues ~60 + 3 d lane-operations per update (d = mean degree) at 39.3 T
-// lane-ops/s; the dense product costs 2 np^2 tp int8 MACs at ~2.5 P ops/s
-// effective, or np^2 bytes of J per trial tile at ~4 TB/s, whichever is
-// larger, plus ~60 lane-operations of epilogue per update.
+// lane-ops/s; the dense product costs 2 np^2 tp operations at half the int8
+// (or, 2-bit couplings, fp4) matrix peak, or the bytes of J once per trial
+// tile at the HBM peak, whichever is larger, plus ~60 lane-operations of
+// epilogue per update.
 double csr_step_seconds(const DevGraph &g, const DevRun &run, const AnnealPlan &plan) {
     // lane-ops per update: RNG, activation and decision (about 60), plus a
     // gather per edge: a few ops from LDS, tens when the rows stream from
@@ -92,10 +93,10 @@ double csr_step_seconds(const DevGraph &g, const DevRun &run, const AnnealPlan &
 }
 
 double dense_step_seconds(int32_t n, int32_t t4, bool two_bit) {
-    const double np = (n + 127) / 128 * 128;
+    const double np = two_bit ? (n + 255) / 256 * 256 : (n + 127) / 128 * 128;
     const int32_t nb = t4 >= 64 ? 4 : (t4 >= 32 ? 2 : 1);
     const double tp = std::ceil(t4 / (16.0 * nb)) * 16.0 * nb;
-    const double mfma = 2.0 * np * np * tp / (0.5 * kMfmaI8OpsPerSecond);
+    const double mfma = 2.0 * np * np * tp / (0.5 * (two_bit ? kMfmaF4OpsPerSecond : kMfmaI8OpsPerSecond));
     const double bytes = np * np * (two_bit ? 0.25 : 1.0) * (tp / (16.0 * nb)) / kHbmBytesPerSecond;
     return std::max(mfma, bytes) + static_cast<double>(n) * t4 * 60.0 / kValuOpsPerSecond;
 }
@@ -218,7 +219,7 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
     ctx->h_dense_work = work;
     for (psa_job *job : live)
         for (int half = 0; half < 2; ++half)  // both buffers: a fully defined state
-            PSA_HIP(psa::launch_to_dense(ctx->stream2, job->g->info.n, job->run.t4, job->g->np,
+            PSA_HIP(psa::launch_to_dense(ctx->stream2, job->g->dense_enc, job->g->info.n, job->run.t4, job->g->np,
                                          job->tp, job->d_spins,
                                          job->d_m + static_cast<size_t>(half) * job->tp * job->g->np),
                     "dense layout");
@@ -246,7 +247,7 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
         psa_job *job = live[j];
         const psa::DenseJob &d = table[j];
         const int8_t *fin = (((d.t_end - d.t) * std::max(d.t_res, 1)) & 1) ? d.m1 : d.m0;
-        PSA_HIP(psa::launch_from_dense(ctx->stream2, job->g->info.n, job->run.t4, job->g->np, fin,
+        PSA_HIP(psa::launch_from_dense(ctx->stream2, job->g->dense_enc, job->g->info.n, job->run.t4, job->g->np, fin,
                                        job->d_spins),
                 "dense layout");
         job->t = d.t_end;

@@ -2,43 +2,57 @@
 //
 // For graphs whose rows are long, one synchronous step is a product of the
 // dense coupling matrix with the spins of all trials,
-//     L[i][k] = h_i + sum_j J_ij m_j,k      (int8 x int8 -> int32, exact),
-// computed with v_mfma_i32_16x16x64_i8, followed by the p-bit update of
-// Eq. 6 in the same kernel.  One launch advances one step of every dense run
-// in a work list (run, 256-row group, trial tile); the step loop is on the
-// host, because a step needs the whole previous state of its run.
+//     L[i][k] = h_i + sum_j J_ij m_j,k      (exact integer sums),
+// computed on the matrix cores, followed by the p-bit update of Eq. 6 in the
+// same kernel.  One launch advances one step of every dense run in a work
+// list (run, 256-row group, trial tile); the step loop is on the host,
+// because a step needs the whole previous state of its run.
 //
 // Coupling encodings (per graph, chosen at build time):
-//   kDenseI8  int8 [np][np], row-major, zero padding (any |J| <= 127);
+//   kDenseI8  int8 [np][np], row-major, zero padding (any |J| <= 127), with
+//             int8 spins, through v_mfma_i32_16x16x64_i8 (np a multiple of
+//             128);
 //   kDenseT2  2-bit fields f in {0, +1, -1} with J = scale * f, for graphs
-//             whose couplings share one magnitude (unit and +-1 weights).
-//             Four times fewer bytes than int8; unpacked to int8 in
-//             registers with v_perm_b32 just before the matrix instruction.
-//   T2 words: one uint32 per (row i, 64-column k-tile, 16-column lane group
-//   g); column 64 ktile + 16 g + 4d + b sits in bits 8b + 2d .. 8b + 2d + 1
-//   (d = dword of the operand, b = byte): fields of even dwords in bits 0-1
-//   of a byte (of word >> 4 for d = 2), of odd dwords in bits 2-3.  The
-//   words are tiled in the order a wave loads them: per 64-row tile and
-//   128-column chunk, 2 KB as two 1 KB halves of [64 lanes][4 words]; word
-//   j of lane l in half h is row
-//   16 (2h + j/2) + l % 16 of the tile, k-tile j % 2 of the chunk, group
-//   l / 16.  A lane's fragments for a chunk are two 16-byte loads, and each
+//             whose couplings share one magnitude (unit and +-1 weights),
+//             with fp4 (e2m1) spins, through v_mfma_f32_16x16x128_f8f6f4 in
+//             its fp4 x fp4 form (np a multiple of 256).  0, +1 and -1 are
+//             exact fp4 values (codes 0x0, 0x2, 0xA), every product is 0 or
+//             +-1 and every partial sum an integer below 2^24 (the field
+//             bound), so the f32 sums are the exact integers.  Four times
+//             fewer coupling bytes than int8, and twice the depth per matrix
+//             instruction at the int8 instruction's issue cost.
+//   T2 words: the fp4 operand of one lane is four dwords d = 0..3 whose
+//   nibble q is column 32 g + 8 d + q of the 128-column k-step (g = lane /
+//   16); one 32-bit word w holds two of them, dword 2 v in bits 4q + 1 (set:
+//   nonzero) and 4q + 3 (set: negative) of w, dword 2 v + 1 in bits 4q and
+//   4q + 2 of w, so that the dwords are w & 0xAAAAAAAA and (w << 1) &
+//   0xAAAAAAAA: fp4 1.0 = 0b0010, -1.0 = 0b1010.  The words are tiled in the
+//   order a wave loads them: per 64-row tile and 256-column chunk, 4 KB as
+//   four 1 KB quarters of [64 lanes][4 words]; word j of lane l in quarter Q
+//   is row 16 (2 (Q % 2) + j / 2) + l % 16 of the tile, k-step Q / 2 of the
+//   chunk, pair j % 2 (dwords 2 (j % 2) and 2 (j % 2) + 1) of lane group
+//   l / 16.  A lane's operands for a chunk are four 16-byte loads, and each
 //   load instruction of the wave reads 1 KB contiguous.
 //
-// Spins M: int8 [tp][np] per buffer (trial-major, p-bit index contiguous), tp
-// = trials rounded up to the trial tile; two buffers by step parity.
+// Spins M per buffer, trial-major with the p-bit index contiguous, tp =
+// trials rounded up to the trial tile, two buffers by step parity: int8
+// [tp][np] (+1 = 0x01, -1 = 0xFF), or fp4 [tp][np / 2] bytes (p-bit 2b in the
+// low nibble of byte b; +1 = 0x2, -1 = 0xA).  Either way one chunk of a
+// trial's spins is 128 bytes: 128 int8 or 256 fp4 columns.
 //
-// MFMA operand layout (16x16x64, int8): lane l supplies A[row l%16][k (l/16)*16
-// .. +15] and B[k (l/16)*16 .. +15][col l%16] as 16 bytes each, and receives
-// D[row (l/16)*4 + r][col l%16] in its four accumulators r = 0..3.  The four
-// rows of a lane are four consecutive p-bits 4m..4m+3 of one trial: exactly
-// the p-bits one Philox block serves, so the epilogue draws one r block (and
-// one gate block) per lane, row block and trial column.
+// MFMA operand layout: lane l supplies A[row l%16][16 bytes of k at group l/16]
+// and B[the same k][col l%16]; for the 16x16x64 int8 form those are 16 int8,
+// for the fp4 form 32 nibbles.  Lane l receives D[row (l/16)*4 + r][col l%16]
+// in its four accumulators r = 0..3.  The four rows of a lane are four
+// consecutive p-bits 4m..4m+3 of one trial: exactly the p-bits one Philox
+// block serves, so the epilogue draws one r block (and one gate block) per
+// lane, row block and trial column.
 //
 // Workgroup: 4 waves x 64 rows (four 16-row blocks per wave) against one trial
 // tile of 16 NB trials.  The trial tile's spins stream through LDS in chunks
-// of 128 columns (double-buffered, one barrier per chunk); each wave reads its
-// own coupling rows straight from memory, one chunk ahead of the matrix work.
+// of 128 bytes per trial (double-buffered, one barrier per chunk); each wave
+// reads its own coupling rows straight from memory, one chunk ahead of the
+// matrix work.
 #include <hip/hip_runtime.h>
 
 #include "device_math.hpp"
@@ -48,29 +62,39 @@ namespace psa {
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kKC = 128;             // columns per LDS chunk (two k-tiles)
-constexpr int kLdsStride = kKC + 16; // padded LDS row of the spin tile (bytes)
-constexpr int kWaveRows = 64;        // four 16-row blocks per wave
-constexpr int kGroupRows = 256;      // rows per workgroup
+constexpr int kChunkBytes = 128;               // bytes of one trial's spins per LDS chunk
+constexpr int kLdsStride = kChunkBytes + 16;   // padded LDS row of the spin tile (bytes)
+constexpr int kWaveRows = 64;                  // four 16-row blocks per wave
+constexpr int kGroupRows = 256;                // rows per workgroup
 
-// Field f in {0, 1, 2} -> byte {0x00, 0x01, 0xFF}, four bytes at once.
-// Even dwords: the field in bits 0-1 of each byte is a selector of the low
-// source's bytes 0x00, 0x01, 0xFF.  Odd dwords: the field in bits 2-3, masked
-// in place, is the selector 0, 4 or 8: the low source's byte 0 (0x00), the
-// high source's byte 0 (0x01), or the sign of the low source's byte 1 (0xFF).
-// So one mask per dword and one shift per pair, no shift per dword.
-__device__ __forceinline__ int32_t t2_even(uint32_t w) {
-    return static_cast<int32_t>(__builtin_amdgcn_perm(0u, 0x00FF0100u, w & 0x03030303u));
-}
-__device__ __forceinline__ int32_t t2_odd(uint32_t w) {
-    return static_cast<int32_t>(__builtin_amdgcn_perm(0x00000001u, 0x0000FF00u, w & 0x0C0C0C0Cu));
-}
+// Per encoding: columns per chunk, spin bits, spin codes, accumulator type.
+template <int ENC>
+struct Enc;
+template <>
+struct Enc<kDenseI8> {
+    static constexpr int kCols = 128;
+    static constexpr int kBits = 8;
+    static constexpr uint32_t kUp = 0x01u, kDown = 0xFFu;
+    using Acc = v4i;
+};
+template <>
+struct Enc<kDenseT2> {
+    static constexpr int kCols = 256;
+    static constexpr int kBits = 4;
+    static constexpr uint32_t kUp = 0x2u, kDown = 0xAu;
+    using Acc = v4f;
+};
 
-__device__ __forceinline__ v4i t2_unpack(uint32_t word) {
-    const uint32_t hi = word >> 4;
-    return v4i{t2_even(word), t2_odd(word), t2_even(hi), t2_odd(hi)};
+// One pair word of 2-bit fields -> two fp4 dwords (see the T2 layout).
+constexpr uint32_t kF4Mask = 0xAAAAAAAAu;
+__device__ __forceinline__ v8i f4_operand(uint32_t w0, uint32_t w1) {
+    return v8i{static_cast<int>(w0 & kF4Mask), static_cast<int>((w0 << 1) & kF4Mask),
+               static_cast<int>(w1 & kF4Mask), static_cast<int>((w1 << 1) & kF4Mask), 0, 0, 0, 0};
 }
+__device__ __forceinline__ v8i f4_widen(const v4i b) { return v8i{b.x, b.y, b.z, b.w, 0, 0, 0, 0}; }
 
 // Device-global views of pointers read from the job table (so that loads
 // are global, not flat, and do not wait on LDS traffic).
@@ -85,11 +109,11 @@ template <int ENC>
 struct AFrag;
 template <>
 struct AFrag<kDenseI8> {
-    v4i v[2][4];
+    v4i v[2][4];  // k-tile, row block
 };
 template <>
 struct AFrag<kDenseT2> {
-    v4i h[2];  // half h, word j: row block 2h + j/2, k-tile j % 2
+    v4i q[4];  // quarter Q, word j: row block 2 (Q % 2) + j / 2, k-step Q / 2, pair j % 2
 };
 
 // NB = 16-trial blocks per workgroup (trial tile = 16 NB).  MODE: what every
@@ -103,9 +127,11 @@ enum : int { kDenseAny = 0, kDensePlain = 1, kDenseIdentity = 2 };
 template <int NB, int ENC, int MODE>
 __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kernel(const DenseJob *__restrict__ jobs,
                                                          const int4 *__restrict__ work, int32_t t_off) {
+    using E = Enc<ENC>;
+    using Acc = typename E::Acc;
     constexpr bool PLAIN = MODE != kDenseAny;
     constexpr int kTrials = 16 * NB;
-    constexpr int kBVec = kTrials * (kKC / 16);        // 16-byte pieces of one spin chunk
+    constexpr int kBVec = kTrials * (kChunkBytes / 16);  // 16-byte pieces of one spin chunk
     constexpr int kBPer = (kBVec + 255) / 256;  // 1 or 2
     __shared__ __align__(16) int8_t bt[2][kTrials * kLdsStride];
     const int4 w = work[blockIdx.x];  // (job, row group, trial tile, -); job < 0: empty slot
@@ -120,6 +146,7 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
     const uint32_t tau = static_cast<uint32_t>(jb.t * u + t_off);
     const int32_t t = PLAIN ? static_cast<int32_t>(tau) : static_cast<int32_t>(tau / static_cast<uint32_t>(u));
     const int32_t np = jb.np;
+    const int32_t rowb = np * E::kBits / 8;  // bytes per trial row of a spin buffer
     const int32_t trial0 = w.z * kTrials;
     const int8_t *__restrict__ cur = (t_off & 1) ? jb.m1 : jb.m0;
     int8_t *__restrict__ nxt = (t_off & 1) ? jb.m0 : jb.m1;
@@ -142,10 +169,10 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
     const int c0 = static_cast<int>(threadIdx.x) % kBVec;
     const gptr<int8_t> gcur = as_global<int8_t>(cur);
     auto fetch_b = [&](int kc) {
-        breg0 = *as_global<v4i>(gcur + static_cast<size_t>(trial0 + (c0 >> 3)) * np + kc * kKC + (c0 & 7) * 16);
+        breg0 = *as_global<v4i>(gcur + static_cast<size_t>(trial0 + (c0 >> 3)) * rowb + kc * kChunkBytes + (c0 & 7) * 16);
         if constexpr (kBPer == 2) {
             const int c = c0 + 256;
-            breg1 = *as_global<v4i>(gcur + static_cast<size_t>(trial0 + (c >> 3)) * np + kc * kKC + (c & 7) * 16);
+            breg1 = *as_global<v4i>(gcur + static_cast<size_t>(trial0 + (c >> 3)) * rowb + kc * kChunkBytes + (c & 7) * 16);
         }
     };
     auto store_b = [&](int buf) {
@@ -155,6 +182,7 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
             *reinterpret_cast<v4i *>(&bt[buf][(c >> 3) * kLdsStride + (c & 7) * 16]) = breg1;
         }
     };
+    const int nkc = np / E::kCols;
     auto fetch_a = [&](int kc, AFrag<ENC> &dst) {
         if constexpr (ENC == kDenseI8) {
             const gptr<int8_t> J = as_global<int8_t>(jb.J);
@@ -163,22 +191,24 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
 #pragma unroll
                 for (int rb = 0; rb < 4; ++rb) {
                     const size_t row = static_cast<size_t>(arow0 + rb * 16 + lr);
-                    dst.v[kt][rb] = *as_global<v4i>(J + row * np + kc * kKC + kt * 64 + kgrp);
+                    dst.v[kt][rb] = *as_global<v4i>(J + row * np + kc * E::kCols + kt * 64 + kgrp);
                 }
         } else {
             const gptr<v4i> J = as_global<v4i>(jb.J);
-            const size_t tile = (static_cast<size_t>(arow0 / kWaveRows) * (np / kKC) + kc) * 2;
-            dst.h[0] = J[tile * 64 + lane];
-            dst.h[1] = J[(tile + 1) * 64 + lane];
+            const size_t tile = (static_cast<size_t>(arow0 / kWaveRows) * nkc + kc) * 4;
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) dst.q[qq] = J[(tile + qq) * 64 + lane];
         }
     };
 
-    v4i acc[4][NB];
+    Acc acc[4][NB];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[rb][nb] = v4i{0, 0, 0, 0};
+        for (int nb = 0; nb < NB; ++nb) acc[rb][nb] = Acc{0, 0, 0, 0};
 
+    // one chunk: two k-steps of 64 int8 or 128 fp4 columns (64 bytes of each
+    // trial's spins each)
     auto compute = [&](int buf, const AFrag<ENC> &af) {
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt) {
@@ -188,18 +218,22 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
                 b[nb] = *reinterpret_cast<const v4i *>(&bt[buf][(nb * 16 + lr) * kLdsStride + kt * 64 + kgrp]);
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb) {
-                v4i a;
-                if constexpr (ENC == kDenseI8)
-                    a = af.v[kt][rb];
-                else
-                    a = t2_unpack(static_cast<uint32_t>(af.h[rb >> 1][(rb & 1) * 2 + kt]));
+                if constexpr (ENC == kDenseI8) {
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                    acc[rb][nb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b[nb], acc[rb][nb], 0, 0, 0);
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[rb][nb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af.v[kt][rb], b[nb], acc[rb][nb], 0, 0, 0);
+                } else {
+                    const v4i &qw = af.q[kt * 2 + (rb >> 1)];
+                    const v8i a = f4_operand(static_cast<uint32_t>(qw[(rb & 1) * 2]),
+                                             static_cast<uint32_t>(qw[(rb & 1) * 2 + 1]));
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[rb][nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                            a, f4_widen(b[nb]), acc[rb][nb], 4, 4, 0, 0, 0, 0);  // fp4 x fp4, no scaling
+                }
             }
         }
     };
-    const int nkc = np / kKC;
     // one chunk: prefetch chunk kc+1 (the last chunk fetches itself again)
     // -- spins into registers, couplings into `pre` --, multiply chunk kc,
     // then publish the prefetched spins into the other LDS buffer
@@ -228,33 +262,73 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
     if (!active) return;
 
     // epilogue: lane owns p-bits 4m..4m+3 of each row block for trial columns
-    // nb.
+    // nb.  The sum of a p-bit is exact in either accumulator type, and so is
+    // its conversion: L = h + scale * sum as an integer, or (float)L by one
+    // fma (scale * sum and the total are integers below 2^24).
     const float i0t = jb.i0[t];
+    // the spins of p-bits i0..i0+3 of trial k in a buffer, 32 or 16 bits
+    auto spin_at = [&](int8_t *base, uint32_t k, int32_t i0) {
+        return base + static_cast<size_t>(k) * rowb + (i0 * E::kBits >> 3);
+    };
+    auto store4 = [&](uint32_t k, int32_t i0, uint32_t out) {
+        if constexpr (ENC == kDenseT2)
+            *reinterpret_cast<uint16_t *>(spin_at(nxt, k, i0)) = static_cast<uint16_t>(out);
+        else
+            *reinterpret_cast<uint32_t *>(spin_at(nxt, k, i0)) = out;
+    };
     if constexpr (MODE == kDenseIdentity) {
         // one r block and four products per (row block, trial block) pair; the
-        // pairs unrolled with constant accumulator indices, a scheduling
-        // barrier between them keeping one pair's temporaries live at a time
+        // pairs unrolled with constant accumulator indices, two per scheduling
+        // region (their chains are independent), the key schedule formed once.
+        // Each decision is taken from the tanh estimate, its spin code from
+        // the sign of the estimate's distance to r; when some lane of the wave
+        // holds an estimate within 2^-16 of r (about one pair in 250), the
+        // pair's codes are taken from the exact recipe instead -- one uniform
+        // branch per pair, none per p-bit.  Padding p-bits and trials are
+        // written too (their rows and columns of J are zero, and the read-out
+        // skips them).
         const int32_t scale = jb.scale;
+        const float scalef = static_cast<float>(scale);
         const uint32_t kpos = static_cast<uint32_t>(trial0 + lr);
+        const PhiloxKeys keys = philox_keys(jb.k0, jb.k1);
+        const gptr<v4i> hvec = as_global<v4i>(jb.h);
+        // codes of four up spins, and the bits that turn a code into down
+        constexpr uint32_t kUp4 = ENC == kDenseT2 ? 0x2222u : 0x01010101u;
+        constexpr uint32_t kFlip = ENC == kDenseT2 ? 0x8u : 0xFEu;
 #pragma unroll
         for (int e = 0; e < 4 * NB; ++e) {
             const int rb = e / NB, nb = e % NB;
             const int32_t i0 = wrow0 + rb * 16 + (lane >> 4) * 4;
             const uint32_t k = kpos + static_cast<uint32_t>(nb * 16);
-            const bool valid = i0 < jb.n4 && static_cast<int32_t>(k) < jb.t4;
-            const int4 hh = *reinterpret_cast<const int4 *>(jb.h + (valid ? i0 : 0));
-            const Words4 r = philox4x32_10(tau, static_cast<uint32_t>(i0 >> 2), k, kTagR, jb.k0, jb.k1);
-            const int32_t hv[4] = {hh.x, hh.y, hh.z, hh.w};
+            const v4i hh = hvec[(i0 < jb.n4 ? i0 : 0) >> 2];
+            const Words4 r = philox4x32_10(tau, static_cast<uint32_t>(i0 >> 2), k, kTagR, keys);
+            const int32_t hv[4] = {hh[0], hh[1], hh[2], hh[3]};
             const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
-            uint32_t out = 0u;
+            float x[4];
+            uint32_t out = kUp4;
+            bool close = false;
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
-                const int32_t L = hv[p] + scale * acc[rb][nb][p];
-                const float x = i0t * static_cast<float>(L);
-                out |= (pbit_up(x, rw[p]) ? 0x01u : 0xFFu) << (8 * p);
+                float Lf;
+                if constexpr (ENC == kDenseT2)
+                    Lf = fmaf(scalef, acc[rb][nb][p], static_cast<float>(hv[p]));
+                else
+                    Lf = static_cast<float>(hv[p] + scale * acc[rb][nb][p]);
+                x[p] = i0t * Lf;
+                const float diff = tanh_estimate_minus(x[p], r_of(rw[p]));
+                close = close || !estimate_decides(diff);
+                // diff < 0 (sign bit set): down
+                const uint32_t neg = static_cast<uint32_t>(static_cast<int32_t>(__float_as_uint(diff)) >> 31);
+                out ^= (neg & kFlip) << (E::kBits * p);
             }
-            if (valid) *reinterpret_cast<uint32_t *>(nxt + static_cast<size_t>(k) * np + i0) = out;
-            __builtin_amdgcn_sched_barrier(0);
+            if (__ballot(close) != 0u) {
+                out = 0u;
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+                    out |= (tanh_f32(x[p]) > r_of(rw[p]) ? E::kUp : E::kDown) << (E::kBits * p);
+            }
+            store4(k, i0, out);
+            if (e & 1) __builtin_amdgcn_sched_barrier(0);
         }
         return;
     }
@@ -263,7 +337,7 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
     // emitted once per pass, keeping few registers live.
     const int32_t scale = jb.scale;
     const InputState st{jb.xs, jb.stall24, jb.ring, jb.alpha, jb.n4};
-    auto update = [&](int e, const v4i a4) __attribute__((always_inline)) {
+    auto update = [&](int e, const Acc a4) __attribute__((always_inline)) {
         const int rb = e / NB, nb = e % NB;
         const int32_t i0 = wrow0 + rb * 16 + (lane >> 4) * 4;
         const int32_t k = trial0 + nb * 16 + lr;
@@ -285,8 +359,13 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
                                                 (tv[2] < kGateOne) | (tv[3] < kGateOne));
         uint32_t old = 0u;
         uint32_t gw[4] = {0u, 0u, 0u, 0u};
-        if (need_gate || period_mode)  // p-bits that do not fire keep these
-            old = *reinterpret_cast<const uint32_t *>(cur + static_cast<size_t>(k) * np + i0);
+        if (need_gate || period_mode) {  // p-bits that do not fire keep these
+            const int8_t *src = spin_at(const_cast<int8_t *>(cur), static_cast<uint32_t>(k), i0);
+            if constexpr (ENC == kDenseT2)
+                old = *reinterpret_cast<const uint16_t *>(src);
+            else
+                old = *reinterpret_cast<const uint32_t *>(src);
+        }
         if (need_gate) {
             const Words4 g = philox4x32_10(tau, static_cast<uint32_t>(m),
                                            static_cast<uint32_t>(k), kTagGate, jb.k0, jb.k1);
@@ -307,10 +386,11 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
             sw[2] = b.z;
             sw[3] = b.w;
         }
+        constexpr uint32_t kMask = (1u << E::kBits) - 1u;
         uint32_t out = 0u;
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-            const int32_t L = hv[p] + scale * a4[p];
+            const int32_t L = hv[p] + scale * static_cast<int32_t>(a4[p]);
             const float x = PLAIN ? input_of<kAlgPsa>(av[p], dv[p], L, sv, i0 + p, static_cast<uint32_t>(k),
                                                       static_cast<uint32_t>(t), sw[p])
                                   : input_any(av[p], dv[p], L, sv, i0 + p, static_cast<uint32_t>(k),
@@ -318,17 +398,17 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
             const bool up = pbit_up(x, rw[p]);
             const bool fire = period_mode ? period_fires(tau, tv[p])
                                           : (tv[p] >= kGateOne || fires(gw[p], tv[p]));
-            const uint32_t ob = (old >> (8 * p)) & 0xFFu;
-            out |= (fire ? (up ? 0x01u : 0xFFu) : ob) << (8 * p);
+            const uint32_t ob = (old >> (E::kBits * p)) & kMask;
+            out |= (fire ? (up ? E::kUp : E::kDown) : ob) << (E::kBits * p);
         }
-        if (valid) *reinterpret_cast<uint32_t *>(nxt + static_cast<size_t>(k) * np + i0) = out;
+        if (valid) store4(static_cast<uint32_t>(k), i0, out);
     };
     // The accumulators move through a queue read only at its head (constant
     // register indices; a loop index into the array would force it into
     // scratch memory).  Two (row block, trial block) pairs per pass: their
     // Philox chains are independent, which doubles the instruction-level
     // parallelism.
-    v4i q[4 * NB];
+    Acc q[4 * NB];
 #pragma unroll
     for (int e = 0; e < 4 * NB; ++e) q[e] = acc[e / NB][e % NB];
 #pragma unroll 1
@@ -340,8 +420,9 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
     }
 }
 
-// [n][t4] (trials innermost) <-> [tp][np] (p-bits contiguous); padding
-// p-bits and trials of the dense layout are +1.
+// [n][t4] (trials innermost) <-> [tp][np] (p-bits contiguous, int8), or
+// [tp][np / 2] bytes of fp4 nibbles; padding p-bits and trials of the dense
+// layout are +1.
 __global__ void to_dense_kernel(int32_t n, int32_t t4, int32_t np, int32_t tp,
                                 const int8_t *__restrict__ spins, int8_t *__restrict__ m) {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -351,6 +432,19 @@ __global__ void to_dense_kernel(int32_t n, int32_t t4, int32_t np, int32_t tp,
     m[idx] = (i < n && k < t4) ? spins[static_cast<size_t>(i) * t4 + k] : int8_t(1);
 }
 
+__global__ void to_dense_f4_kernel(int32_t n, int32_t t4, int32_t np, int32_t tp,
+                                   const int8_t *__restrict__ spins, uint8_t *__restrict__ m) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int32_t half = np / 2;
+    if (idx >= static_cast<int64_t>(tp) * half) return;
+    const int32_t k = static_cast<int32_t>(idx / half);
+    const int32_t i = 2 * static_cast<int32_t>(idx % half);
+    auto code = [&](int32_t p) -> uint32_t {
+        return (p < n && k < t4 && spins[static_cast<size_t>(p) * t4 + k] < 0) ? 0xAu : 0x2u;
+    };
+    m[idx] = static_cast<uint8_t>(code(i) | code(i + 1) << 4);
+}
+
 __global__ void from_dense_kernel(int32_t n, int32_t t4, int32_t np, const int8_t *__restrict__ m,
                                   int8_t *__restrict__ spins) {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -358,6 +452,16 @@ __global__ void from_dense_kernel(int32_t n, int32_t t4, int32_t np, const int8_
     const int32_t i = static_cast<int32_t>(idx / t4);
     const int32_t k = static_cast<int32_t>(idx % t4);
     spins[idx] = m[static_cast<size_t>(k) * np + i];
+}
+
+__global__ void from_dense_f4_kernel(int32_t n, int32_t t4, int32_t np, const uint8_t *__restrict__ m,
+                                     int8_t *__restrict__ spins) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= static_cast<int64_t>(n) * t4) return;
+    const int32_t i = static_cast<int32_t>(idx / t4);
+    const int32_t k = static_cast<int32_t>(idx % t4);
+    const uint32_t nib = (m[static_cast<size_t>(k) * (np / 2) + i / 2] >> (4 * (i & 1))) & 0xFu;
+    spins[idx] = nib == 0x2u ? int8_t(1) : int8_t(-1);
 }
 
 template <int ENC, int MODE>
@@ -396,19 +500,27 @@ hipError_t launch_dense_steps(hipStream_t stream, const DenseJob *jobs, const in
     return hipSuccess;
 }
 
-hipError_t launch_to_dense(hipStream_t stream, int32_t n, int32_t t4, int32_t np, int32_t tp,
+hipError_t launch_to_dense(hipStream_t stream, int32_t enc, int32_t n, int32_t t4, int32_t np, int32_t tp,
                            const int8_t *spins, int8_t *m) {
-    const int64_t items = static_cast<int64_t>(tp) * np;
-    hipLaunchKernelGGL(to_dense_kernel, dim3(static_cast<unsigned>((items + 255) / 256)), dim3(256), 0,
-                       stream, n, t4, np, tp, spins, m);
+    const int64_t items = static_cast<int64_t>(tp) * (enc == kDenseT2 ? np / 2 : np);
+    const dim3 grid(static_cast<unsigned>((items + 255) / 256));
+    if (enc == kDenseT2)
+        hipLaunchKernelGGL(to_dense_f4_kernel, grid, dim3(256), 0, stream, n, t4, np, tp, spins,
+                           reinterpret_cast<uint8_t *>(m));
+    else
+        hipLaunchKernelGGL(to_dense_kernel, grid, dim3(256), 0, stream, n, t4, np, tp, spins, m);
     return hipGetLastError();
 }
 
-hipError_t launch_from_dense(hipStream_t stream, int32_t n, int32_t t4, int32_t np,
+hipError_t launch_from_dense(hipStream_t stream, int32_t enc, int32_t n, int32_t t4, int32_t np,
                              const int8_t *m, int8_t *spins) {
     const int64_t items = static_cast<int64_t>(n) * t4;
-    hipLaunchKernelGGL(from_dense_kernel, dim3(static_cast<unsigned>((items + 255) / 256)), dim3(256),
-                       0, stream, n, t4, np, m, spins);
+    const dim3 grid(static_cast<unsigned>((items + 255) / 256));
+    if (enc == kDenseT2)
+        hipLaunchKernelGGL(from_dense_f4_kernel, grid, dim3(256), 0, stream, n, t4, np,
+                           reinterpret_cast<const uint8_t *>(m), spins);
+    else
+        hipLaunchKernelGGL(from_dense_kernel, grid, dim3(256), 0, stream, n, t4, np, m, spins);
     return hipGetLastError();
 }
 

@@ -70,6 +70,39 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1,
     return Words4{s.c0, s.c1, s.c2, s.c3};
 }
 
+// The key schedule of one run (the key of each of the ten rounds), formed
+// once by a kernel that draws many blocks under that key.
+struct PhiloxKeys {
+    uint32_t k0[10], k1[10];
+};
+__device__ __forceinline__ PhiloxKeys philox_keys(uint32_t k0, uint32_t k1) {
+    PhiloxKeys K;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        K.k0[round] = k0;
+        K.k1[round] = k1;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return K;
+}
+// The same ten rounds as philox4x32_10, each under its precomputed key.
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                const PhiloxKeys &K) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p1 >> 32), c1, K.k0[round], 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p0 >> 32), c3, K.k1[round], 0x96);
+        c1 = static_cast<uint32_t>(p1);
+        c3 = static_cast<uint32_t>(p0);
+        c0 = n0;
+        c2 = n2;
+    }
+    return Words4{c0, c1, c2, c3};
+}
+
 __device__ __forceinline__ uint32_t word_of(const Words4 &w, uint32_t k) {
     return k == 0 ? w.x : k == 1 ? w.y : k == 2 ? w.z : w.w;
 }

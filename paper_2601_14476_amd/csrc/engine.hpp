@@ -193,14 +193,15 @@ struct BatchJob {
     int32_t variant;
 };
 
-// Encodings of the dense coupling matrix (dense.hip): int8 entries, or 2-bit
-// fields f in {0, +1, -1} with J = scale * f.
+// Encodings of the dense coupling matrix (dense.hip): int8 entries (np a
+// multiple of 128, int8 spins), or 2-bit fields f in {0, +1, -1} with J =
+// scale * f (np a multiple of 256, fp4 spins).
 enum : int32_t { kDenseI8 = 0, kDenseT2 = 1 };
 
 // One run of the dense matrix-core path (dense.hip), as the step kernel reads
-// it.  J is the encoded [np][np] coupling matrix (np a multiple of 128); m0 /
-// m1 are the two [tp][np] spin buffers (trial-major); steps t .. t_end-1 of
-// the launch sequence.
+// it.  J is the encoded [np][np] coupling matrix; m0 / m1 are the two spin
+// buffers (trial-major, [tp][np] int8 or [tp][np / 2] bytes of fp4); steps
+// t .. t_end-1 of the launch sequence.
 struct DenseJob {
     int32_t n, n4, np, t4, tp, t, t_end;
     int32_t scale;  // J = scale * entry (1 for int8)
@@ -277,9 +278,10 @@ bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t 
 // thr24 >= 2^24 (no timing gate); 0 tests each run's mode at run time.
 hipError_t launch_dense_steps(hipStream_t stream, const DenseJob *jobs, const int4 *work,
                               int32_t nwork, int32_t nb, int32_t enc, int32_t mode, int32_t steps);
-hipError_t launch_to_dense(hipStream_t stream, int32_t n, int32_t t4, int32_t np, int32_t tp,
+// [n][t4] spins <-> one dense spin buffer of encoding enc
+hipError_t launch_to_dense(hipStream_t stream, int32_t enc, int32_t n, int32_t t4, int32_t np, int32_t tp,
                            const int8_t *spins, int8_t *m);
-hipError_t launch_from_dense(hipStream_t stream, int32_t n, int32_t t4, int32_t np,
+hipError_t launch_from_dense(hipStream_t stream, int32_t enc, int32_t n, int32_t t4, int32_t np,
                              const int8_t *m, int8_t *spins);
 
 // Kernel launchers (kernels.hip).  All are asynchronous on `stream`.
@@ -354,6 +356,7 @@ void graph_unref(psa_graph *g);     // drop one reference, free at zero
 // Chip figures of the cost model (MI355X: 256 CUs at 2.4 GHz).
 constexpr double kValuOpsPerSecond = 256.0 * 4 * 16 * 2.4e9;  // 32-bit lane-ops
 constexpr double kMfmaI8OpsPerSecond = 5.0e15;                // dense int8
+constexpr double kMfmaF4OpsPerSecond = 10.1e15;               // dense fp4
 constexpr double kHbmBytesPerSecond = 8.0e12;
 // Modelled seconds per step of the CSR sweep (with the given plan) and of the
 // dense matrix-core step (2-bit or int8 couplings).

@@ -208,7 +208,6 @@ void graph_unref(psa_graph *g) {
 psa_status ensure_dense_matrix(psa_graph *g) {
     if (g->d_dense) return PSA_OK;
     const int32_t n = g->info.n;
-    const int32_t np = (n + 127) / 128 * 128;
     // one shared magnitude -> 2-bit fields; otherwise int8 entries
     int32_t mag = 0;
     bool one_mag = true;
@@ -217,26 +216,30 @@ psa_status ensure_dense_matrix(psa_graph *g) {
         if (mag == 0) mag = a;
         one_mag = one_mag && a == mag;
     }
+    const int32_t np = one_mag ? (n + 255) / 256 * 256 : (n + 127) / 128 * 128;
     psa_status st;
     if (one_mag) {
-        // 2-bit fields, tiled for the step kernel: for each 64-row tile and
-        // 128-column chunk, 2 KB in the order the 64 lanes of a wave load
-        // them (two 16-byte loads per lane, each load 1 KB contiguous).
-        // Lane l, load `half`, word j holds row 64 rt + 16 (2 half + j/2) +
-        // l % 16, k-tile 2 c + j % 2, lane group l / 16; within the word,
-        // column 64 ktile + 16 g + 4 d + b sits in bits 8b + 2d.
-        const int32_t nchunks = np / 128;
+        // 2-bit fields that two masks turn into fp4 operands, tiled for the
+        // step kernel: for each 64-row tile and 256-column chunk, 4 KB in the
+        // order the 64 lanes of a wave load them (four 16-byte loads per
+        // lane, each load 1 KB contiguous).  Lane l, quarter Q, word j holds
+        // row 64 rt + 16 (2 (Q % 2) + j / 2) + l % 16 and, of k-step Q / 2
+        // of the chunk, columns 32 (l / 16) + 16 (j % 2) + 0..15: column
+        // 32 g + 8 d + q (d = 0..3, q = 0..7) of the k-step has its nonzero
+        // bit at 4q + 1 (d even) or 4q (d odd) and its sign bit two above.
+        const int32_t nchunks = np / 256;
         std::vector<uint32_t> words(static_cast<size_t>(np) * np / 16, 0u);
         for (int32_t i = 0; i < n; ++i)
             for (int32_t p = g->row_ptr_host[i]; p < g->row_ptr_host[i + 1]; ++p) {
                 const int32_t k = g->col_host[p];
                 const int32_t rt = i >> 6, rb = (i >> 4) & 3, lr = i & 15;
-                const int32_t c = k >> 7, kt = (k >> 6) & 1, grp = (k >> 4) & 3;
-                const int32_t e = k & 15, d = e >> 2, b = e & 3;
-                const int32_t half = rb >> 1, j = (rb & 1) * 2 + kt, lane = grp * 16 + lr;
-                const size_t at = ((((static_cast<size_t>(rt) * nchunks + c) * 2 + half) * 64 + lane) * 4) + j;
-                const uint32_t f = g->val_host[p] > 0 ? 1u : 2u;
-                words[at] |= f << (8 * b + 2 * d);
+                const int32_t c = k >> 8, ks = (k >> 7) & 1, grp = (k >> 5) & 3;
+                const int32_t d = (k >> 3) & 3, q = k & 7;
+                const int32_t quarter = ks * 2 + (rb >> 1), j = (rb & 1) * 2 + (d >> 1), lane = grp * 16 + lr;
+                const size_t at = ((((static_cast<size_t>(rt) * nchunks + c) * 4 + quarter) * 64 + lane) * 4) + j;
+                const int32_t nz = 4 * q + ((d & 1) ? 0 : 1);
+                words[at] |= 1u << nz;
+                if (g->val_host[p] < 0) words[at] |= 1u << (nz + 2);
             }
         uint32_t *dev = nullptr;
         if ((st = upload(&dev, words, &g->dense_bytes)) != PSA_OK) return st;

@@ -102,7 +102,7 @@ size_t reserve_of(const psa::HostGraph &hg, const psa_run_desc &d, bool spins) {
     encodable = encodable || (one_mag && hg.n <= 32768);
     size_t dense = 0;
     if (path != PSA_PATH_CSR && encodable) {
-        const size_t np = static_cast<size_t>((hg.n + 127) / 128 * 128);
+        const size_t np = static_cast<size_t>(one_mag ? (hg.n + 255) / 256 * 256 : (hg.n + 127) / 128 * 128);
         dense = one_mag ? np * np / 4 : np * np;
         run += 2 * ((t4 + 63) / 64 * 64) * np;
     }
