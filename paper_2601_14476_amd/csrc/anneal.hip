@@ -60,10 +60,6 @@ __device__ __forceinline__ Words4 block_of(uint32_t t, uint32_t m, uint32_t k, u
     return philox4x32_10(t, m, k, tag, k0, k1);
 }
 
-// Eq. 6 decision for one p-bit and trial: +1 iff tanh(x) > r, x the
-// (fresh or held) pre-activation (I0 lambda)(L + delta).
-__device__ __forceinline__ bool goes_up(float x, uint32_t rword) { return pbit_up(x, rword); }
-
 template <int TPW, int CSR>
 struct Enc {
     // 0/1 byte encoding in LDS (else +-1 bytes)
@@ -578,13 +574,14 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, const TaskCon
         for (int j = 0; j < P; ++j)
             L[j] = field_pm1<CSR>(v, c.rp[j], c.rp[j + 1], c.h[j], reinterpret_cast<const int8_t *>(cur));
     }
-    uint32_t out = 0u;
+    // pre-activations, then the P decisions from the tanh estimate; when
+    // some lane of the wave holds an estimate within 2^-16 of r, the P are
+    // retaken with the exact recipe -- one uniform branch per task, none per
+    // p-bit (pbit_up's decisions either way)
+    float xv[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) {
         const int32_t i = base + j;
-        const uint32_t old = cur[i];
-        const uint32_t th = c.thr[j];
-        const bool fire = ALG == kAlgPeriod ? period_fires(t, th) : (th >= kGateOne || fires(gw[j], th));
         float x;
         if constexpr (ALG == kAlgTapsa && RES) {
             // the window sum advanced by the entering and the leaving field
@@ -602,8 +599,27 @@ __device__ __forceinline__ uint32_t task_one_trial(const Views &v, const TaskCon
             (void)li;
             x = input_of<ALG>(i0t * c.lam[j], c.dlt[j], L[j], st, i, k, t, sw[j]);
         }
-        const bool up = goes_up(x, rw[j]);
-        const uint32_t nb = kU ? (up ? 1u : 0u) : (up ? 0x01u : 0xFFu);
+        xv[j] = x;
+    }
+    bool up[P];
+    bool close = false;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const float diff = tanh_estimate_minus(xv[j], r_of(rw[j]));
+        close = close || !estimate_decides(diff);
+        up[j] = diff > 0.0f;
+    }
+    if (__ballot(close) != 0u) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) up[j] = tanh_f32(xv[j]) > r_of(rw[j]);
+    }
+    uint32_t out = 0u;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const uint32_t old = cur[base + j];
+        const uint32_t th = c.thr[j];
+        const bool fire = ALG == kAlgPeriod ? period_fires(t, th) : (th >= kGateOne || fires(gw[j], th));
+        const uint32_t nb = kU ? (up[j] ? 1u : 0u) : (up[j] ? 0x01u : 0xFFu);
         out |= (fire ? nb : old) << (8 * j);
     }
     return out;
@@ -696,11 +712,15 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
             sw[2] = b.z;
             sw[3] = b.w;
         }
+        // the four decisions from the tanh estimate; when some lane of the
+        // wave holds an estimate within 2^-16 of r, the four are retaken
+        // with the exact recipe -- one uniform branch per block, none per
+        // p-bit (pbit_up's decisions either way)
+        float x[4];
+        bool up[4];
+        bool close = false;
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-            const bool fire = ALG == kAlgPeriod ? period_fires(t, th[p])
-                                                : (th[p] >= kGateOne || fires(gw[p], th[p]));
-            float x;
             if constexpr (kEll && ALG == kAlgPsa) {
                 // (float)L from the byte count directly: 2 count + (h - deg) is
                 // an integer below 2^24 in magnitude, so the one fma is exact
@@ -708,12 +728,23 @@ __device__ __forceinline__ void task_four_trials(const Views &v, int32_t m, int3
                 // everywhere, a ((float)L + delta)
                 const float cnt = static_cast<float>((acc_ell[p] >> (8 * kk)) & 0xFFu);
                 const float Lf = fmaf(2.0f, cnt, hdf[p]);
-                x = a[p] * (Lf + d[p]);
+                x[p] = a[p] * (Lf + d[p]);
             } else {
-                x = input_of<ALG>(a[p], d[p], L[p][kk], st, 4 * m + p, k, t, sw[p]);
+                x[p] = input_of<ALG>(a[p], d[p], L[p][kk], st, 4 * m + p, k, t, sw[p]);
             }
-            const bool up = goes_up(x, rw[p]);
-            const uint32_t nb = kU ? (up ? 1u : 0u) : (up ? 0x01u : 0xFFu);
+            const float diff = tanh_estimate_minus(x[p], r_of(rw[p]));
+            close = close || !estimate_decides(diff);
+            up[p] = diff > 0.0f;
+        }
+        if (__ballot(close) != 0u) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) up[p] = tanh_f32(x[p]) > r_of(rw[p]);
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const bool fire = ALG == kAlgPeriod ? period_fires(t, th[p])
+                                                : (th[p] >= kGateOne || fires(gw[p], th[p]));
+            const uint32_t nb = kU ? (up[p] ? 1u : 0u) : (up[p] ? 0x01u : 0xFFu);
             if (fire) word[p] = (word[p] & ~(0xFFu << (8 * kk))) | (nb << (8 * kk));
         }
     }
