@@ -322,6 +322,9 @@ def main():
     ap.add_argument("--tpw", type=int, default=0, help="trials per workgroup (0 = auto)")
     ap.add_argument("--lpt", type=int, default=0, help="lanes per 4-p-bit task (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dense-graphs", action="store_true",
+                    help="c4, c4-dense, c5: replay dense step sequences from captured graphs "
+                         "(default: launched one by one, which measured faster)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times); "
                          "used to scale the HBM traffic counters")
@@ -371,6 +374,7 @@ def main():
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     ctx = psa.Context(0, stream)
+    ctx.set_dense_graphs(args.dense_graphs)
     g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
     info = g.info()
     spsa = args.algorithm == "spsa"
@@ -504,6 +508,7 @@ def bench_batch(args):
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     ctx = psa.Context(0, stream)
+    ctx.set_dense_graphs(args.dense_graphs)
     graphs, jobs, alone, outs = [], [], [], []
     updates = 0
     valu_ops = 0.0       # CSR jobs
@@ -663,6 +668,7 @@ def bench_dense(args):
         p = float(rng.uniform(0.04, 0.1))
         specs.append(inputs.erdos_renyi(n, p, 500 + g))
     ctx = psa.Context(0)
+    ctx.set_dense_graphs(args.dense_graphs)
     graphs = [psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True) for n, u, v, w in specs]
     jobs = [psa.Job(ctx, g, 1000, 64, i, path=psa.PSA_PATH_DENSE) for i, g in enumerate(graphs)]
     psa.jobs_step_batch(ctx, jobs, 20)
@@ -740,6 +746,7 @@ def bench_serve(args, pool):
         ahead.append(next(produced))
     torch.cuda.set_device(0)
     ctx = psa.Context(0)
+    ctx.set_dense_graphs(args.dense_graphs)
     srv = psa.Server(ctx, max_resident=args.max_resident, quantum_steps=args.quantum)
     tickets = []
     updates = []

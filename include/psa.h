@@ -103,10 +103,25 @@ typedef struct psa_timing {
     int64_t anneal_launches;
     int64_t batch_launches;
     int64_t dense_launches;  /* one per step of a dense work list           */
+    int64_t dense_graph_launches; /* of dense_launches, those replayed from a
+                                     captured graph (psa_ctx_set_dense_graphs) */
 } psa_timing;
 
 psa_status psa_ctx_set_timing(psa_ctx *ctx, int32_t on);
 psa_status psa_ctx_timing_read(psa_ctx *ctx, psa_timing *out);
+
+/* Dense step sequences as captured HIP graphs (off by default).  A dense
+ * quantum of k steps is k launches that differ only in their step offset;
+ * with graphs on, the context captures such a sequence once per shape (job
+ * table and work list addresses, work items, trial tile, encoding, epilogue
+ * mode, k) and replays it for every later quantum of that shape, whatever
+ * jobs the table holds then (the kernels read the table when they run).  Up
+ * to 8 graphs are kept per context, least recently used evicted.  on = 0
+ * (the default: replays measured slower than launching the steps one by one
+ * on this runtime) launches the steps one by one and frees the kept graphs
+ * (after the dense stream drains).  Results are identical either way.
+ * EINVAL: ctx NULL; EHIP: a HIP call failed. */
+psa_status psa_ctx_set_dense_graphs(psa_ctx *ctx, int32_t on);
 
 /* ------------------------------------------------------------------ */
 /* Graphs (Eq. 2-3: couplings J and biases h)                           */

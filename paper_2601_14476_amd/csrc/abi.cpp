@@ -244,6 +244,23 @@ psa_status psa_ctx_set_timing(psa_ctx *ctx, int32_t on) {
     });
 }
 
+psa_status psa_ctx_set_dense_graphs(psa_ctx *ctx, int32_t on) {
+    return psa::guarded("psa_ctx_set_dense_graphs", [&]() -> psa_status {
+        if (!ctx) {
+            set_error("psa_ctx_set_dense_graphs: ctx is NULL");
+            return PSA_EINVAL;
+        }
+        ctx->dense_graphs = on != 0;
+        if (!ctx->dense_graphs && !ctx->dense_graph_cache.empty()) {
+            PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+            PSA_HIP(hipStreamSynchronize(ctx->stream2), "hipStreamSynchronize");
+            for (const auto &dg : ctx->dense_graph_cache) (void)hipGraphExecDestroy(dg.exec);
+            ctx->dense_graph_cache.clear();
+        }
+        return PSA_OK;
+    });
+}
+
 psa_status psa_ctx_timing_read(psa_ctx *ctx, psa_timing *out) {
     return psa::guarded("psa_ctx_timing_read", [&]() -> psa_status {
         if (!ctx || !out) {
@@ -267,10 +284,12 @@ psa_status psa_ctx_timing_read(psa_ctx *ctx, psa_timing *out) {
         out->anneal_launches = ctx->timed_launches[psa::kTimeAnneal];
         out->batch_launches = ctx->timed_launches[psa::kTimeBatch];
         out->dense_launches = ctx->timed_launches[psa::kTimeDense];
+        out->dense_graph_launches = ctx->timed_graph_launches;
         for (int f = 0; f < 3; ++f) {
             ctx->timed_ms[f] = 0.0;
             ctx->timed_launches[f] = 0;
         }
+        ctx->timed_graph_launches = 0;
         return PSA_OK;
     });
 }
@@ -318,6 +337,7 @@ void ctx_release(psa_ctx *ctx) {
     if (ctx->d_batch_work) (void)hipFree(ctx->d_batch_work);
     if (ctx->d_dense_table) (void)hipFree(ctx->d_dense_table);
     if (ctx->d_dense_work) (void)hipFree(ctx->d_dense_work);
+    for (const auto &dg : ctx->dense_graph_cache) (void)hipGraphExecDestroy(dg.exec);
     for (const auto &sp : ctx->spans) {
         (void)hipEventDestroy(sp.begin);
         (void)hipEventDestroy(sp.end);

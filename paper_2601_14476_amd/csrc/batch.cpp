@@ -154,6 +154,51 @@ static void dense_work_list(const std::vector<DenseJob> &table, const std::vecto
         for (size_t q = 0; q < bins[x].size(); ++q) (*out)[q * kXcd + x] = bins[x][q];
 }
 
+// One dense step sequence on the context's second stream: replayed from a
+// captured graph of the same shape, captured now (evicting the least recently
+// used graph past kDenseGraphCache, after the stream has drained), or -- graphs
+// off, or a single step -- launched one by one.  *graph: it ran as a graph.
+static psa_status dense_sequence(psa_ctx *ctx, const DenseJob *table, const int4 *work, int32_t nwork,
+                                 int32_t nb, int32_t enc, int32_t mode, int32_t steps, bool *graph) {
+    *graph = false;
+    if (!ctx->dense_graphs || steps < kDenseGraphMinSteps) {
+        PSA_HIP(launch_dense_steps(ctx->stream2, table, work, nwork, nb, enc, mode, steps), "dense step launch");
+        return PSA_OK;
+    }
+    auto &cache = ctx->dense_graph_cache;
+    auto it = std::find_if(cache.begin(), cache.end(), [&](const DenseGraph &d) {
+        return d.table == table && d.work == work && d.nwork == nwork && d.nb == nb && d.enc == enc &&
+               d.mode == mode && d.steps == steps;
+    });
+    if (it == cache.end()) {
+        PSA_HIP(hipStreamBeginCapture(ctx->stream2, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+        const hipError_t le = launch_dense_steps(ctx->stream2, table, work, nwork, nb, enc, mode, steps);
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(ctx->stream2, &g);
+        if (le != hipSuccess || ce != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            PSA_HIP(le != hipSuccess ? le : ce, "dense step capture");
+        }
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        PSA_HIP(ie, "hipGraphInstantiate");
+        if (cache.size() >= kDenseGraphCache) {
+            PSA_HIP(hipStreamSynchronize(ctx->stream2), "hipStreamSynchronize");
+            (void)hipGraphExecDestroy(cache.front().exec);
+            cache.erase(cache.begin());
+        }
+        cache.push_back(DenseGraph{table, work, nwork, nb, enc, mode, steps, exec});
+        it = cache.end() - 1;
+    } else {
+        std::rotate(it, it + 1, cache.end());  // most recently used last
+        it = cache.end() - 1;
+    }
+    PSA_HIP(hipGraphLaunch(it->exec, ctx->stream2), "hipGraphLaunch");
+    *graph = true;
+    return PSA_OK;
+}
+
 psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, int32_t k) {
     std::vector<psa::DenseJob> table;
     std::vector<psa_job *> live;
@@ -232,16 +277,18 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
     const int4 *dwork = static_cast<const int4 *>(ctx->d_dense_work);
     hipEvent_t ev = nullptr;
     if ((st = time_begin(ctx, ctx->stream2, &ev)) != PSA_OK) return st;
-    int64_t launches = 0;
+    int64_t launches = 0, replayed = 0;
     for (int e = 0; e < 2; ++e) {
         if (len[e] == 0) continue;
-        PSA_HIP(psa::launch_dense_steps(ctx->stream2, static_cast<const psa::DenseJob *>(ctx->d_dense_table),
-                                        dwork + off[e], static_cast<int32_t>(len[e]), nb[e],
-                                        e == 1 ? kDenseT2 : kDenseI8,
-                                        plain[e] ? (identity[e] ? 2 : 1) : 0, max_steps),
-                "dense step launch");
+        bool graph = false;
+        if ((st = dense_sequence(ctx, static_cast<const psa::DenseJob *>(ctx->d_dense_table), dwork + off[e],
+                                 static_cast<int32_t>(len[e]), nb[e], e == 1 ? kDenseT2 : kDenseI8,
+                                 plain[e] ? (identity[e] ? 2 : 1) : 0, max_steps, &graph)) != PSA_OK)
+            return st;
         launches += max_steps;
+        replayed += graph ? max_steps : 0;
     }
+    if (ev) ctx->timed_graph_launches += replayed;
     if ((st = time_end(ctx, ctx->stream2, kTimeDense, ev, launches)) != PSA_OK) return st;
     for (size_t j = 0; j < live.size(); ++j) {
         psa_job *job = live[j];

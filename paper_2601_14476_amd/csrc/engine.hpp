@@ -269,6 +269,19 @@ bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t 
                  int32_t block_req, size_t max_lds, int32_t num_cu, AnnealPlan *plan,
                  std::string *why);
 
+// A captured dense step sequence: `steps` launches over one work list slice.
+// The launches differ only in their step offset and take device pointers to
+// the job table and work list, which the kernels read when they run; so the
+// graph serves every later call of the same shape whatever the table holds.
+struct DenseGraph {
+    const DenseJob *table;
+    const int4 *work;
+    int32_t nwork, nb, enc, mode, steps;
+    hipGraphExec_t exec;
+};
+constexpr size_t kDenseGraphCache = 8;    // graphs kept per context
+constexpr int32_t kDenseGraphMinSteps = 2;
+
 // Dense path launchers (dense.hip).  launch_dense_steps issues `steps`
 // launches; launch s advances every run of the work list (job, 256-row group,
 // trial tile of 16 nb; job -1 = empty slot) by its step t + s.  All runs of
@@ -432,6 +445,10 @@ struct psa_ctx {
     size_t dense_table_cap = 0, dense_work_cap = 0;
     std::vector<psa::DenseJob> h_dense_table;
     std::vector<int4> h_dense_work;
+    // captured step sequences of the dense path (batch.cpp), most recently
+    // used last; off unless psa_ctx_set_dense_graphs switches them on
+    bool dense_graphs = false;
+    std::vector<psa::DenseGraph> dense_graph_cache;
     // per-family device timing (psa_ctx_set_timing): event pairs awaiting
     // resolution, by family 0 anneal, 1 batch, 2 dense
     bool timing = false;
@@ -444,6 +461,7 @@ struct psa_ctx {
     std::vector<hipEvent_t> event_pool;
     double timed_ms[3] = {0.0, 0.0, 0.0};
     int64_t timed_launches[3] = {0, 0, 0};
+    int64_t timed_graph_launches = 0;  // dense launches replayed from a captured graph
     // measured path / launch shape per shape class (psa_autotune)
     std::mutex tune_mu;
     std::map<psa::TuneKey, psa_tune_result> tune_cache;

@@ -376,6 +376,8 @@ __global__ __launch_bounds__(BLOCK) void period_resident_kernel(PeriodArgs a, co
         bool f[K];
 #pragma unroll
         for (int s = 0; s < K; ++s) f[s] = ocls[s] < kPeriodMaxClasses && ((fire >> ocls[s]) & 1u) != 0u;
+        float xin[K];
+        bool close = false;
         // words of the p-bits that fired at the previous firing sub-step, for
         // their next firing (before the firing p-bits below: a p-bit firing
         // again now takes its word from here)
@@ -408,10 +410,20 @@ __global__ __launch_bounds__(BLOCK) void period_resident_kernel(PeriodArgs a, co
                 }
                 for (int32_t x0 = orp[s]; x0 < oend[s]; x0 += 8)
                     L += chunk_field<true>(x0, oend[s], pk, nullptr, nullptr, spin + RO, []() {}, []() {});
-                const float xin = (i0t * olam[s]) * (static_cast<float>(L) + odlt[s]);
-                cv[s] = pbit_up(xin, nw[s]) ? int8_t(1) : int8_t(-1);
+                xin[s] = (i0t * olam[s]) * (static_cast<float>(L) + odlt[s]);
+                const float diff = tanh_estimate_minus(xin[s], r_of(nw[s]));
+                close = close || !estimate_decides(diff);
+                cv[s] = diff > 0.0f ? int8_t(1) : int8_t(-1);
                 pend[s] = true;
             }
+        }
+        // decisions from the tanh estimate; when some lane of the wave holds
+        // one within 2^-16 of r, the firing slots are retaken with the exact
+        // recipe (one uniform branch per sub-step, none per p-bit)
+        if (__ballot(close) != 0u) {
+#pragma unroll
+            for (int s = 0; s < K; ++s)
+                if (f[s]) cv[s] = tanh_f32(xin[s]) > r_of(nw[s]) ? int8_t(1) : int8_t(-1);
         }
         // the written region lacks this sub-step's and the previous firing
         // sub-step's changes: both are in the lanes' registers

@@ -79,7 +79,8 @@ class psa_job_info(ctypes.Structure):
 
 class psa_timing(ctypes.Structure):
     _fields_ = [("anneal_ms", _f64), ("batch_ms", _f64), ("dense_ms", _f64),
-                ("anneal_launches", _i64), ("batch_launches", _i64), ("dense_launches", _i64)]
+                ("anneal_launches", _i64), ("batch_launches", _i64), ("dense_launches", _i64),
+                ("dense_graph_launches", _i64)]
 
 
 class psa_batch_item(ctypes.Structure):
@@ -112,6 +113,7 @@ _SIGNATURES = [
     ("psa_ctx_destroy", None, [_P]),
     ("psa_ctx_set_timing", _i32, [_P, _i32]),
     ("psa_ctx_timing_read", _i32, [_P, ctypes.POINTER(psa_timing)]),
+    ("psa_ctx_set_dense_graphs", _i32, [_P, _i32]),
     ("psa_graph_from_edges", _i32, [_P, _i32, _i64, _P, _P, _P, _P, _u32,
                                     ctypes.POINTER(_P)]),
     ("psa_graph_from_csr", _i32, [_P, _i32, _P, _P, _P, _P, _u32,
@@ -252,6 +254,10 @@ class Context:
     def set_timing(self, on=True):
         """Record device time per kernel family (psa_ctx_set_timing)."""
         _check(_lib.psa_ctx_set_timing(self.handle, 1 if on else 0), "psa_ctx_set_timing")
+
+    def set_dense_graphs(self, on=True):
+        """Replay dense step sequences from captured graphs (psa_ctx_set_dense_graphs)."""
+        _check(_lib.psa_ctx_set_dense_graphs(self.handle, 1 if on else 0), "psa_ctx_set_dense_graphs")
 
     def timing(self):
         """Totals since the last call (psa_ctx_timing_read), as a dict."""
