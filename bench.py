@@ -66,6 +66,7 @@ OPS_MEAN = 10  # window mean: convert, correctly rounded divide
 OPS_PERIOD = 6  # period test: convert, reciprocal, multiply, truncate, multiply-subtract, compare
 MFMA_I8_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak, TOP/s
 MFMA_F4_PEAK_TOPS = 10100.0  # dense fp4 matrix-core peak, TFLOP/s
+DENSE_LAUNCH = {"steps": 0, "graph": 1, "persistent": 2}
 HBM_PEAK_GBS = 8000.0
 
 # The workload table's own estimate of the VALU work per update (written
@@ -322,9 +323,10 @@ def main():
     ap.add_argument("--tpw", type=int, default=0, help="trials per workgroup (0 = auto)")
     ap.add_argument("--lpt", type=int, default=0, help="lanes per 4-p-bit task (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--dense-graphs", action="store_true",
-                    help="c4, c4-dense, c5: replay dense step sequences from captured graphs "
-                         "(default: launched one by one, which measured faster)")
+    ap.add_argument("--dense-launch", choices=["steps", "persistent", "graph"], default="steps",
+                    help="c4, c4-dense, c5: how a dense quantum is launched (one launch per step, "
+                         "one persistent launch, or per-step launches replayed from a captured "
+                         "graph)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times); "
                          "used to scale the HBM traffic counters")
@@ -374,7 +376,7 @@ def main():
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     ctx = psa.Context(0, stream)
-    ctx.set_dense_graphs(args.dense_graphs)
+    ctx.set_dense_launch(DENSE_LAUNCH[args.dense_launch])
     g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
     info = g.info()
     spsa = args.algorithm == "spsa"
@@ -508,7 +510,7 @@ def bench_batch(args):
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     ctx = psa.Context(0, stream)
-    ctx.set_dense_graphs(args.dense_graphs)
+    ctx.set_dense_launch(DENSE_LAUNCH[args.dense_launch])
     graphs, jobs, alone, outs = [], [], [], []
     updates = 0
     valu_ops = 0.0       # CSR jobs
@@ -668,7 +670,7 @@ def bench_dense(args):
         p = float(rng.uniform(0.04, 0.1))
         specs.append(inputs.erdos_renyi(n, p, 500 + g))
     ctx = psa.Context(0)
-    ctx.set_dense_graphs(args.dense_graphs)
+    ctx.set_dense_launch(DENSE_LAUNCH[args.dense_launch])
     graphs = [psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True) for n, u, v, w in specs]
     jobs = [psa.Job(ctx, g, 1000, 64, i, path=psa.PSA_PATH_DENSE) for i, g in enumerate(graphs)]
     psa.jobs_step_batch(ctx, jobs, 20)
@@ -746,7 +748,7 @@ def bench_serve(args, pool):
         ahead.append(next(produced))
     torch.cuda.set_device(0)
     ctx = psa.Context(0)
-    ctx.set_dense_graphs(args.dense_graphs)
+    ctx.set_dense_launch(DENSE_LAUNCH[args.dense_launch])
     srv = psa.Server(ctx, max_resident=args.max_resident, quantum_steps=args.quantum)
     tickets = []
     updates = []

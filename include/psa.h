@@ -102,26 +102,46 @@ typedef struct psa_timing {
     double dense_ms;         /* dense step sequences (launch gaps included) */
     int64_t anneal_launches;
     int64_t batch_launches;
-    int64_t dense_launches;  /* one per step of a dense work list           */
+    int64_t dense_launches;  /* per dense work list: one per step, or one
+                                for a persistent quantum                    */
     int64_t dense_graph_launches; /* of dense_launches, those replayed from a
-                                     captured graph (psa_ctx_set_dense_graphs) */
+                                     captured graph (psa_ctx_set_dense_launch) */
 } psa_timing;
 
 psa_status psa_ctx_set_timing(psa_ctx *ctx, int32_t on);
 psa_status psa_ctx_timing_read(psa_ctx *ctx, psa_timing *out);
 
-/* Dense step sequences as captured HIP graphs (off by default).  A dense
- * quantum of k steps is k launches that differ only in their step offset;
- * with graphs on, the context captures such a sequence once per shape (job
- * table and work list addresses, work items, trial tile, encoding, epilogue
- * mode, k) and replays it for every later quantum of that shape, whatever
- * jobs the table holds then (the kernels read the table when they run).  Up
- * to 8 graphs are kept per context, least recently used evicted.  on = 0
- * (the default: replays measured slower than launching the steps one by one
- * on this runtime) launches the steps one by one and frees the kept graphs
- * (after the dense stream drains).  Results are identical either way.
- * EINVAL: ctx NULL; EHIP: a HIP call failed. */
-psa_status psa_ctx_set_dense_graphs(psa_ctx *ctx, int32_t on);
+/* How the dense path launches a quantum of k steps (k launches of the step
+ * kernel that differ only in their step offset):
+ *   PSA_DENSE_LAUNCH_STEPS (default)  one launch per step.
+ *   PSA_DENSE_LAUNCH_PERSISTENT  one launch for all k steps.  Whole runs are
+ *     dealt to 8 queues (one per XCD); workgroups take each queue's tasks in
+ *     step order from its ticket counter, and a task waits until every item
+ *     of its run has finished the previous step (a device counter per run;
+ *     spins stored and read at device coherence, since a run's workgroups may
+ *     sit on different XCDs with separate L2s).  A task only waits on tasks
+ *     of its queue taken before it, by running workgroups, so the waits end
+ *     however many workgroups the device keeps resident.  Beside a CSR batch
+ *     (psa_jobs_step_batch) the launch takes the dense family's modelled
+ *     share of the compute units.  Each wait is bounded (about a second); a
+ *     wait past the bound makes the workgroups leave and the next dense
+ *     quantum on the context return PSA_EHIP.  Measured on par with STEPS
+ *     for dense runs alone, and slower beside a CSR batch (whose 1,024-thread
+ *     workgroups need whole compute units that the resident dense
+ *     workgroups keep partly occupied).
+ *   PSA_DENSE_LAUNCH_GRAPH  the k launches captured once per shape (job table
+ *     and work list addresses, work items, trial tile, encoding, epilogue
+ *     mode, k) as a HIP graph and replayed for every later quantum of that
+ *     shape, whatever jobs the table holds then (the kernels read it when
+ *     they run); up to 8 graphs kept per context, least recently used
+ *     evicted.  Measured slower than STEPS on this runtime.
+ * Results are identical in every mode.  Leaving GRAPH frees the kept graphs
+ * (after the dense stream drains).  EINVAL: ctx NULL or an unknown mode;
+ * EHIP: a HIP call failed. */
+#define PSA_DENSE_LAUNCH_STEPS 0
+#define PSA_DENSE_LAUNCH_GRAPH 1
+#define PSA_DENSE_LAUNCH_PERSISTENT 2
+psa_status psa_ctx_set_dense_launch(psa_ctx *ctx, int32_t how);
 
 /* ------------------------------------------------------------------ */
 /* Graphs (Eq. 2-3: couplings J and biases h)                           */
@@ -618,6 +638,14 @@ psa_status psa_debug_tanh(psa_ctx *ctx, int64_t count, const float *x, float *y)
  * count elements; asynchronous on the context's stream. */
 psa_status psa_debug_decide(psa_ctx *ctx, int64_t count, const float *x, const uint32_t *rword,
                             uint8_t *out);
+
+/* The bound of one dependency wait of the persistent dense launch
+ * (PSA_DENSE_LAUNCH_PERSISTENT), in polls of the run's counter: 2^20 by
+ * default (about a second).  A test entry for the failure path: with 0
+ * every wait of a quantum of two or more steps gives up at once, the
+ * workgroups leave normally, and the next dense quantum on the context
+ * returns PSA_EHIP.  EINVAL: ctx NULL. */
+psa_status psa_debug_dense_wait_limit(psa_ctx *ctx, uint32_t max_polls);
 
 #ifdef __cplusplus
 }

@@ -244,14 +244,25 @@ psa_status psa_ctx_set_timing(psa_ctx *ctx, int32_t on) {
     });
 }
 
-psa_status psa_ctx_set_dense_graphs(psa_ctx *ctx, int32_t on) {
-    return psa::guarded("psa_ctx_set_dense_graphs", [&]() -> psa_status {
+psa_status psa_debug_dense_wait_limit(psa_ctx *ctx, uint32_t max_polls) {
+    return psa::guarded("psa_debug_dense_wait_limit", [&]() -> psa_status {
         if (!ctx) {
-            set_error("psa_ctx_set_dense_graphs: ctx is NULL");
+            set_error("psa_debug_dense_wait_limit: ctx is NULL");
             return PSA_EINVAL;
         }
-        ctx->dense_graphs = on != 0;
-        if (!ctx->dense_graphs && !ctx->dense_graph_cache.empty()) {
+        ctx->dense_max_polls = max_polls;
+        return PSA_OK;
+    });
+}
+
+psa_status psa_ctx_set_dense_launch(psa_ctx *ctx, int32_t how) {
+    return psa::guarded("psa_ctx_set_dense_launch", [&]() -> psa_status {
+        if (!ctx || how < PSA_DENSE_LAUNCH_STEPS || how > PSA_DENSE_LAUNCH_PERSISTENT) {
+            set_error("psa_ctx_set_dense_launch: ctx NULL or unknown launch mode");
+            return PSA_EINVAL;
+        }
+        ctx->dense_launch = how;
+        if (how != PSA_DENSE_LAUNCH_GRAPH && !ctx->dense_graph_cache.empty()) {
             PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
             PSA_HIP(hipStreamSynchronize(ctx->stream2), "hipStreamSynchronize");
             for (const auto &dg : ctx->dense_graph_cache) (void)hipGraphExecDestroy(dg.exec);
@@ -338,6 +349,8 @@ void ctx_release(psa_ctx *ctx) {
     if (ctx->d_dense_table) (void)hipFree(ctx->d_dense_table);
     if (ctx->d_dense_work) (void)hipFree(ctx->d_dense_work);
     for (const auto &dg : ctx->dense_graph_cache) (void)hipGraphExecDestroy(dg.exec);
+    if (ctx->d_dense_sync) (void)hipFree(ctx->d_dense_sync);
+    if (ctx->h_dense_err) (void)hipHostFree(ctx->h_dense_err);
     for (const auto &sp : ctx->spans) {
         (void)hipEventDestroy(sp.begin);
         (void)hipEventDestroy(sp.end);

@@ -154,14 +154,16 @@ static void dense_work_list(const std::vector<DenseJob> &table, const std::vecto
         for (size_t q = 0; q < bins[x].size(); ++q) (*out)[q * kXcd + x] = bins[x][q];
 }
 
-// One dense step sequence on the context's second stream: replayed from a
-// captured graph of the same shape, captured now (evicting the least recently
-// used graph past kDenseGraphCache, after the stream has drained), or -- graphs
-// off, or a single step -- launched one by one.  *graph: it ran as a graph.
+// One dense step sequence on the context's second stream, launched step by
+// step: replayed from a captured graph of the same shape, captured now
+// (evicting the least recently used graph past kDenseGraphCache, after the
+// stream has drained), or -- use_graph false, or a single step -- launched one
+// by one.  *graph: it ran as a graph.
 static psa_status dense_sequence(psa_ctx *ctx, const DenseJob *table, const int4 *work, int32_t nwork,
-                                 int32_t nb, int32_t enc, int32_t mode, int32_t steps, bool *graph) {
+                                 int32_t nb, int32_t enc, int32_t mode, int32_t steps, bool use_graph,
+                                 bool *graph) {
     *graph = false;
-    if (!ctx->dense_graphs || steps < kDenseGraphMinSteps) {
+    if (!use_graph || steps < kDenseGraphMinSteps) {
         PSA_HIP(launch_dense_steps(ctx->stream2, table, work, nwork, nb, enc, mode, steps), "dense step launch");
         return PSA_OK;
     }
@@ -199,7 +201,36 @@ static psa_status dense_sequence(psa_ctx *ctx, const DenseJob *table, const int4
     return PSA_OK;
 }
 
-psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, int32_t k) {
+// Task list of the persistent launch: whole runs dealt to kDenseQueues queues
+// (heaviest first, each to the least loaded queue), each queue's items run by
+// run (trial tile, then 256-row group), no empty slots; q->off the queues'
+// bounds in the list.
+static void dense_task_list(const std::vector<DenseJob> &table, const std::vector<int32_t> &idx, int32_t nb,
+                            std::vector<int4> *out, DenseQueues *q) {
+    std::vector<int32_t> order(idx);
+    auto cost = [&](int32_t j) { return static_cast<double>(table[j].np) * table[j].np * table[j].tp; };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+    std::vector<std::vector<int32_t>> queue(kDenseQueues);
+    std::vector<double> load(kDenseQueues, 0.0);
+    for (int32_t j : order) {
+        const int32_t x = static_cast<int32_t>(std::min_element(load.begin(), load.end()) - load.begin());
+        queue[x].push_back(j);
+        load[x] += cost(j);
+    }
+    out->clear();
+    for (int32_t x = 0; x < kDenseQueues; ++x) {
+        q->off[x] = static_cast<int32_t>(out->size());
+        for (int32_t j : queue[x]) {
+            const DenseJob &d = table[j];
+            const int32_t groups = (d.np + 255) / 256, tiles = d.tp / (16 * nb);
+            for (int32_t tt = 0; tt < tiles; ++tt)
+                for (int32_t g = 0; g < groups; ++g) out->push_back(make_int4(j, g, tt, 0));
+        }
+    }
+    q->off[kDenseQueues] = static_cast<int32_t>(out->size());
+}
+
+psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, int32_t k, double share) {
     std::vector<psa::DenseJob> table;
     std::vector<psa_job *> live;
     std::vector<int32_t> by_enc[2];
@@ -220,6 +251,7 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
         d.t = job->t;
         d.t_end = te;
         d.scale = g->dense_scale;
+        d.items = 0;
         d.J = g->d_dense;
         d.m0 = job->d_m;
         d.m1 = job->d_m + static_cast<size_t>(job->tp) * g->np;
@@ -245,21 +277,47 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
         max_steps = std::max(max_steps, (te - job->t) * std::max(job->run.t_res, 1));
     }
     if (live.empty()) return PSA_OK;
+    const int32_t how = max_steps >= kDenseGraphMinSteps ? ctx->dense_launch : kDenseLaunchSteps;
     std::vector<int4> work, part;
     size_t off[2] = {0, 0}, len[2] = {0, 0};
+    DenseQueues queues[2] = {};
     for (int e = 0; e < 2; ++e) {
         if (by_enc[e].empty()) continue;
-        dense_work_list(table, by_enc[e], nb[e], &part);
+        if (how == kDenseLaunchPersistent && plain[e])
+            dense_task_list(table, by_enc[e], nb[e], &part, &queues[e]);
+        else
+            dense_work_list(table, by_enc[e], nb[e], &part);
         off[e] = work.size();
         len[e] = part.size();
         work.insert(work.end(), part.begin(), part.end());
     }
+    for (const int4 &w : work)
+        if (w.x >= 0) ++table[static_cast<size_t>(w.x)].items;
     PSA_HIP(hipStreamSynchronize(ctx->stream2), "hipStreamSynchronize");
+    if (ctx->h_dense_err && (ctx->h_dense_err[0] | ctx->h_dense_err[1])) {
+        ctx->h_dense_err[0] = ctx->h_dense_err[1] = 0u;
+        set_error("dense step sequence: a workgroup waited past its limit for another work item of its run; "
+                  "the spins of that quantum are not valid");
+        return PSA_EHIP;
+    }
     psa_status st;
     if ((st = ensure(&ctx->d_dense_table, &ctx->dense_table_cap, table.size() * sizeof(psa::DenseJob))) != PSA_OK)
         return st;
     if ((st = ensure(&ctx->d_dense_work, &ctx->dense_work_cap, work.size() * sizeof(int4))) != PSA_OK)
         return st;
+    const int32_t sync_words = dense_sync_words(static_cast<int32_t>(table.size()));
+    if (how == kDenseLaunchPersistent) {
+        void *p = ctx->d_dense_sync;
+        if ((st = ensure(&p, &ctx->dense_sync_cap, 2 * static_cast<size_t>(sync_words) * sizeof(uint32_t))) != PSA_OK)
+            return st;
+        ctx->d_dense_sync = static_cast<uint32_t *>(p);
+        if (!ctx->h_dense_err) {
+            void *h = nullptr;
+            PSA_HIP(hipHostMalloc(&h, 2 * sizeof(uint32_t), hipHostMallocDefault), "hipHostMalloc");
+            ctx->h_dense_err = static_cast<uint32_t *>(h);
+            ctx->h_dense_err[0] = ctx->h_dense_err[1] = 0u;
+        }
+    }
     ctx->h_dense_table = table;
     ctx->h_dense_work = work;
     for (psa_job *job : live)
@@ -275,15 +333,30 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
                            hipMemcpyHostToDevice, ctx->stream2),
             "dense work upload");
     const int4 *dwork = static_cast<const int4 *>(ctx->d_dense_work);
+    const psa::DenseJob *dtable = static_cast<const psa::DenseJob *>(ctx->d_dense_table);
     hipEvent_t ev = nullptr;
     if ((st = time_begin(ctx, ctx->stream2, &ev)) != PSA_OK) return st;
     int64_t launches = 0, replayed = 0;
     for (int e = 0; e < 2; ++e) {
         if (len[e] == 0) continue;
+        const int32_t enc = e == 1 ? kDenseT2 : kDenseI8;
+        const int32_t mode = plain[e] ? (identity[e] ? 2 : 1) : 0;
+        if (how == kDenseLaunchPersistent && mode != 0) {
+            uint32_t *sync = ctx->d_dense_sync + static_cast<size_t>(e) * sync_words;
+            const int32_t cus = std::clamp(static_cast<int32_t>(std::lround(share * ctx->num_cu)), kDenseQueues,
+                                           ctx->num_cu);
+            PSA_HIP(psa::launch_dense_persistent(ctx->stream2, dtable, dwork + off[e], queues[e], nb[e], enc, mode,
+                                                 max_steps, sync, sync_words, ctx->dense_max_polls, cus),
+                    "dense step sequence launch");
+            PSA_HIP(hipMemcpyAsync(ctx->h_dense_err + e, sync + 32 * kDenseQueues, sizeof(uint32_t),
+                                   hipMemcpyDeviceToHost, ctx->stream2),
+                    "dense step error flag");
+            launches += 1;
+            continue;
+        }
         bool graph = false;
-        if ((st = dense_sequence(ctx, static_cast<const psa::DenseJob *>(ctx->d_dense_table), dwork + off[e],
-                                 static_cast<int32_t>(len[e]), nb[e], e == 1 ? kDenseT2 : kDenseI8,
-                                 plain[e] ? (identity[e] ? 2 : 1) : 0, max_steps, &graph)) != PSA_OK)
+        if ((st = dense_sequence(ctx, dtable, dwork + off[e], static_cast<int32_t>(len[e]), nb[e], enc, mode,
+                                 max_steps, how == kDenseLaunchGraph, &graph)) != PSA_OK)
             return st;
         launches += max_steps;
         replayed += graph ? max_steps : 0;
@@ -319,6 +392,7 @@ psa_status psa_jobs_step_batch(psa_ctx *ctx, int32_t count, psa_job *const *jobs
         std::vector<psa_job *> dense_jobs;
         size_t lds = 0;
         int32_t max_lanes = 0;
+        double dense_s = 0.0, csr_s = 0.0;  // model estimates of the two families' device time
         for (int32_t j = 0; j < count; ++j) {
             psa_job *job = jobs[j];
             if (!job || job->ctx != ctx) {
@@ -337,6 +411,8 @@ psa_status psa_jobs_step_batch(psa_ctx *ctx, int32_t count, psa_job *const *jobs
             if (te <= job->t) continue;
             if (job->plan.dense) {
                 dense_jobs.push_back(job);
+                dense_s += psa::dense_step_seconds(job->g->info.n, job->run.t4, job->g->dense_enc == psa::kDenseT2) *
+                           (te - job->t);
                 continue;
             }
             psa::AnnealPlan plan;
@@ -348,6 +424,7 @@ psa_status psa_jobs_step_batch(psa_ctx *ctx, int32_t count, psa_job *const *jobs
                 set_error("psa_jobs_step_batch: " + why);
                 return PSA_EUNSUPPORTED;
             }
+            csr_s += psa::csr_step_seconds(job->g->dev, job->run, plan) * (te - job->t);
             psa::BatchJob bj;
             psa::fill_anneal_args(&bj.a, job->g->dev, job->run, job->d_order, job->t, te);
             bj.variant = variant;
@@ -362,8 +439,11 @@ psa_status psa_jobs_step_batch(psa_ctx *ctx, int32_t count, psa_job *const *jobs
             // dense runs on the second stream, concurrently with the CSR launch
             PSA_HIP(hipEventRecord(ctx->ev_fork, ctx->stream), "hipEventRecord");
             PSA_HIP(hipStreamWaitEvent(ctx->stream2, ctx->ev_fork, 0), "hipStreamWaitEvent");
+            // a persistent dense launch keeps its workgroups resident: it gets
+            // the dense family's modelled share of the device
+            const double share = csr_s > 0.0 ? dense_s / (dense_s + csr_s) : 1.0;
             psa_status st = psa::dense_step_jobs(ctx, dense_jobs.data(),
-                                                 static_cast<int32_t>(dense_jobs.size()), k);
+                                                 static_cast<int32_t>(dense_jobs.size()), k, share);
             if (st != PSA_OK) return st;
             PSA_HIP(hipEventRecord(ctx->ev_join, ctx->stream2), "hipEventRecord");
         }

@@ -55,6 +55,9 @@
 // matrix work.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <type_traits>
+
 #include "device_math.hpp"
 #include "engine.hpp"
 
@@ -124,17 +127,25 @@ struct AFrag<kDenseT2> {
 // product I0 (float)L (exactly the general (I0 lambda)((float)L + delta) at
 // those values) and no gate word is drawn.
 enum : int { kDenseAny = 0, kDensePlain = 1, kDenseIdentity = 2 };
-template <int NB, int ENC, int MODE>
-__global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kernel(const DenseJob *__restrict__ jobs,
-                                                         const int4 *__restrict__ work, int32_t t_off) {
+// Spin-buffer accesses of a step that other workgroups' steps read: with
+// COH, buffer loads and stores at device (agent) coherence -- they bypass the
+// per-XCD L2 copies of the lines -- so that the persistent launch needs no
+// cache write-back or invalidation between dependent steps.
+constexpr int kCohAux = 16;                  // cache policy bits: device scope
+constexpr int kRsrcWord3 = 0x00020000;       // raw buffer resource, gfx9 family
+
+// One work item of one step: w = (job, row group, trial tile, -), job < 0 an
+// empty slot; bt the workgroup's two LDS spin chunks.  Every thread of the
+// workgroup calls it (it holds workgroup barriers).
+template <int NB, int ENC, int MODE, bool COH>
+__device__ __forceinline__ void dense_task(const DenseJob *__restrict__ jobs, const int4 w, int32_t t_off,
+                                           int8_t (*__restrict__ bt)[16 * NB * kLdsStride]) {
     using E = Enc<ENC>;
     using Acc = typename E::Acc;
     constexpr bool PLAIN = MODE != kDenseAny;
     constexpr int kTrials = 16 * NB;
     constexpr int kBVec = kTrials * (kChunkBytes / 16);  // 16-byte pieces of one spin chunk
     constexpr int kBPer = (kBVec + 255) / 256;  // 1 or 2
-    __shared__ __align__(16) int8_t bt[2][kTrials * kLdsStride];
-    const int4 w = work[blockIdx.x];  // (job, row group, trial tile, -); job < 0: empty slot
     if (w.x < 0) return;
     const DenseJob &jb = jobs[w.x];
     // launch t_off advances sub-step t_off of this run's sequence: one
@@ -168,11 +179,21 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
     v4i breg0, breg1;
     const int c0 = static_cast<int>(threadIdx.x) % kBVec;
     const gptr<int8_t> gcur = as_global<int8_t>(cur);
+    const int32_t buf_bytes = jb.tp * rowb;
+    const __amdgpu_buffer_rsrc_t rcur =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<int8_t *>(cur), 0, buf_bytes, kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t rnxt = __builtin_amdgcn_make_buffer_rsrc(nxt, 0, buf_bytes, kRsrcWord3);
+    auto load16 = [&](int32_t off) -> v4i {
+        if constexpr (COH)
+            return __builtin_amdgcn_raw_buffer_load_b128(rcur, off, 0, kCohAux);
+        else
+            return *as_global<v4i>(gcur + off);
+    };
     auto fetch_b = [&](int kc) {
-        breg0 = *as_global<v4i>(gcur + static_cast<size_t>(trial0 + (c0 >> 3)) * rowb + kc * kChunkBytes + (c0 & 7) * 16);
+        breg0 = load16((trial0 + (c0 >> 3)) * rowb + kc * kChunkBytes + (c0 & 7) * 16);
         if constexpr (kBPer == 2) {
             const int c = c0 + 256;
-            breg1 = *as_global<v4i>(gcur + static_cast<size_t>(trial0 + (c >> 3)) * rowb + kc * kChunkBytes + (c & 7) * 16);
+            breg1 = load16((trial0 + (c >> 3)) * rowb + kc * kChunkBytes + (c & 7) * 16);
         }
     };
     auto store_b = [&](int buf) {
@@ -267,14 +288,30 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
     // fma (scale * sum and the total are integers below 2^24).
     const float i0t = jb.i0[t];
     // the spins of p-bits i0..i0+3 of trial k in a buffer, 32 or 16 bits
-    auto spin_at = [&](int8_t *base, uint32_t k, int32_t i0) {
-        return base + static_cast<size_t>(k) * rowb + (i0 * E::kBits >> 3);
+    auto spin_off = [&](uint32_t k, int32_t i0) {
+        return static_cast<int32_t>(k) * rowb + (i0 * E::kBits >> 3);
     };
     auto store4 = [&](uint32_t k, int32_t i0, uint32_t out) {
-        if constexpr (ENC == kDenseT2)
-            *reinterpret_cast<uint16_t *>(spin_at(nxt, k, i0)) = static_cast<uint16_t>(out);
+        const int32_t off = spin_off(k, i0);
+        if constexpr (COH && ENC == kDenseT2)
+            __builtin_amdgcn_raw_buffer_store_b16(static_cast<uint16_t>(out), rnxt, off, 0, kCohAux);
+        else if constexpr (COH)
+            __builtin_amdgcn_raw_buffer_store_b32(out, rnxt, off, 0, kCohAux);
+        else if constexpr (ENC == kDenseT2)
+            *reinterpret_cast<uint16_t *>(nxt + off) = static_cast<uint16_t>(out);
         else
-            *reinterpret_cast<uint32_t *>(spin_at(nxt, k, i0)) = out;
+            *reinterpret_cast<uint32_t *>(nxt + off) = out;
+    };
+    auto load4 = [&](uint32_t k, int32_t i0) -> uint32_t {
+        const int32_t off = spin_off(k, i0);
+        if constexpr (COH && ENC == kDenseT2)
+            return __builtin_amdgcn_raw_buffer_load_b16(rcur, off, 0, kCohAux);
+        else if constexpr (COH)
+            return __builtin_amdgcn_raw_buffer_load_b32(rcur, off, 0, kCohAux);
+        else if constexpr (ENC == kDenseT2)
+            return *reinterpret_cast<const uint16_t *>(cur + off);
+        else
+            return *reinterpret_cast<const uint32_t *>(cur + off);
     };
     if constexpr (MODE == kDenseIdentity) {
         // one r block and four products per (row block, trial block) pair; the
@@ -359,13 +396,8 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
                                                 (tv[2] < kGateOne) | (tv[3] < kGateOne));
         uint32_t old = 0u;
         uint32_t gw[4] = {0u, 0u, 0u, 0u};
-        if (need_gate || period_mode) {  // p-bits that do not fire keep these
-            const int8_t *src = spin_at(const_cast<int8_t *>(cur), static_cast<uint32_t>(k), i0);
-            if constexpr (ENC == kDenseT2)
-                old = *reinterpret_cast<const uint16_t *>(src);
-            else
-                old = *reinterpret_cast<const uint32_t *>(src);
-        }
+        if (need_gate || period_mode)  // p-bits that do not fire keep these
+            old = load4(static_cast<uint32_t>(k), i0);
         if (need_gate) {
             const Words4 g = philox4x32_10(tau, static_cast<uint32_t>(m),
                                            static_cast<uint32_t>(k), kTagGate, jb.k0, jb.k1);
@@ -418,6 +450,110 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
 #pragma unroll
         for (int j = 0; j + 2 < 4 * NB; ++j) q[j] = q[j + 2];
     }
+}
+
+template <int NB, int ENC, int MODE>
+__global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kernel(const DenseJob *__restrict__ jobs,
+                                                         const int4 *__restrict__ work, int32_t t_off) {
+    __shared__ __align__(16) int8_t bt[2][16 * NB * kLdsStride];
+    dense_task<NB, ENC, MODE, false>(jobs, work[blockIdx.x], t_off, bt);
+}
+
+// All `steps` steps of a work list in one launch.  The work list is split
+// into kDenseQueues queues, each holding whole runs; queue x's task q = s n_x
+// + i is its item i of step s.  A workgroup takes tasks in that order from
+// its home queue's ticket counter (home: blockIdx mod 8, the XCD it is
+// dispatched to, so a run's spin tiles stay in one L2), then from the other
+// queues in turn; a task of step s > 0 first waits until every item of its
+// run has finished step s - 1 (its run's counter reaches s items).  A task
+// only waits on tasks of its own queue with smaller tickets, which running
+// workgroups hold, so the waits end whatever number of workgroups the device
+// keeps resident; runs, and a run's consecutive steps, overlap (one's
+// epilogue with another's matrix loop).  The workgroups of a run may still
+// sit on different XCDs, each with its own L2: spins are stored and read at
+// device coherence (dense_task's COH accesses, which bypass the L2 copies),
+// and a task's stores have completed before its counter increment; no cache
+// is written back or invalidated (that would also cost kernels running
+// beside it their cached lines).  Runs must be plain pSA (MODE kDensePlain
+// or kDenseIdentity: no held inputs or windows, which other tasks would read).
+//   sync (words, each counter on its own 128-byte line): queue x's ticket
+//   counter at 32 x, the error flag at 32 kDenseQueues, run j's tasks done at
+//   32 (kDenseQueues + 1 + j); zero before the launch.  Each wait polls at most
+//   max_polls times; past that, or once another workgroup has set the error
+//   flag, the workgroup sets the flag and leaves (the host reports it).
+template <int NB, int ENC, int MODE>
+__global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_steps_kernel(
+    const DenseJob *__restrict__ jobs, const int4 *__restrict__ work, DenseQueues queues, int32_t steps,
+    uint32_t *__restrict__ sync, uint32_t max_polls) {
+    __shared__ __align__(16) int8_t bt[2][16 * NB * kLdsStride];
+    __shared__ uint32_t s_ticket, s_fail;
+    uint32_t *const err = sync + 32 * kDenseQueues;
+    uint32_t *const done0 = sync + 32 * (kDenseQueues + 1);
+    const int home = static_cast<int>(blockIdx.x % kDenseQueues);
+    // Control flow below depends only on wavefront-uniform values (read from
+    // LDS with readfirstlane), and the one thread-0 region of an iteration
+    // sits between barriers: a loop exit the compiler must treat as divergent
+    // lets it split a wavefront's lanes across the loop latch, and that
+    // wavefront then meets a different number of barriers than the others.
+    int32_t owed = -1;  // run whose counter this workgroup's last task has not yet advanced
+    for (int a = 0; a < kDenseQueues; ++a) {
+        const int x = (home + a) % kDenseQueues;
+        const int32_t items = queues.off[x + 1] - queues.off[x];
+        const uint32_t total = static_cast<uint32_t>(steps) * static_cast<uint32_t>(items);
+        if (total == 0u) continue;
+        for (;;) {
+            // the previous task's stores completed in every wavefront (the
+            // barrier closing it): publish it, then take the next ticket
+            if (threadIdx.x == 0) {
+                if (owed >= 0)
+                    __hip_atomic_fetch_add(done0 + 32 * owed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t f = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_fail = f;
+                s_ticket = f ? total
+                             : __hip_atomic_fetch_add(sync + 32 * x, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            owed = -1;
+            __syncthreads();
+            const uint32_t ticket = __builtin_amdgcn_readfirstlane(s_ticket);
+            const uint32_t failed = __builtin_amdgcn_readfirstlane(s_fail);
+            __syncthreads();  // read before thread 0 writes them again
+            if (failed) return;
+            if (ticket >= total) break;  // queue drained: the next one
+            const int32_t s = static_cast<int32_t>(ticket / static_cast<uint32_t>(items));
+            const int4 w = work[queues.off[x] + static_cast<int32_t>(ticket % static_cast<uint32_t>(items))];
+            if (s > 0) {
+                if (threadIdx.x == 0) {
+                    const uint32_t need = static_cast<uint32_t>(s) * static_cast<uint32_t>(jobs[w.x].items);
+                    const uint32_t *done = done0 + 32 * w.x;
+                    uint32_t fail = 1u;
+                    for (uint32_t n = 0; n < max_polls; ++n) {
+                        if (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) {
+                            fail = 0u;
+                            break;
+                        }
+                        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+                        __builtin_amdgcn_s_sleep(4);
+                    }
+                    if (fail) __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    s_fail = fail;
+                }
+                __syncthreads();
+                const uint32_t waited_out = __builtin_amdgcn_readfirstlane(s_fail);
+                if (waited_out) return;
+            }
+            dense_task<NB, ENC, MODE, true>(jobs, w, s, bt);
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's spin stores complete
+            __syncthreads();
+            owed = w.x;
+        }
+    }
+    if (threadIdx.x == 0 && owed >= 0)
+        __hip_atomic_fetch_add(done0 + 32 * owed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void zero_words_kernel(uint32_t *__restrict__ p, int32_t count) {
+    const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < count) p[i] = 0u;
 }
 
 // [n][t4] (trials innermost) <-> [tp][np] (p-bits contiguous, int8), or
@@ -498,6 +634,48 @@ hipError_t launch_dense_steps(hipStream_t stream, const DenseJob *jobs, const in
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+template <int ENC, int MODE>
+hipError_t launch_persistent_enc(hipStream_t stream, const DenseJob *jobs, const int4 *work, const DenseQueues &q,
+                                 int32_t nb, int32_t steps, uint32_t *sync, uint32_t max_polls, int32_t num_cu) {
+    void (*fn)(const DenseJob *, const int4 *, DenseQueues, int32_t, uint32_t *, uint32_t);
+    switch (nb) {
+        case 1: fn = dense_steps_kernel<1, ENC, MODE>; break;
+        case 2: fn = dense_steps_kernel<2, ENC, MODE>; break;
+        case 4: fn = dense_steps_kernel<4, ENC, MODE>; break;
+        default: return hipErrorInvalidValue;
+    }
+    int per_cu = 0;
+    const hipError_t oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0);
+    if (oe != hipSuccess) return oe;
+    const int64_t tasks = static_cast<int64_t>(steps) * q.off[kDenseQueues];
+    const int64_t slots = static_cast<int64_t>(std::max(per_cu, 1)) * std::max(num_cu, 1);
+    const int64_t grid = std::max<int64_t>(1, std::min(tasks, slots));
+    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream, jobs, work, q, steps, sync,
+                       max_polls);
+    return hipGetLastError();
+}
+
+int32_t dense_sync_words(int32_t jobs) { return 32 * (kDenseQueues + 1 + jobs); }
+
+hipError_t launch_dense_persistent(hipStream_t stream, const DenseJob *jobs, const int4 *work,
+                                   const DenseQueues &q, int32_t nb, int32_t enc, int32_t mode, int32_t steps,
+                                   uint32_t *sync, int32_t sync_words, uint32_t max_polls, int32_t num_cu) {
+    if (q.off[kDenseQueues] <= 0 || steps <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_words_kernel, dim3(static_cast<unsigned>((sync_words + 255) / 256)), dim3(256), 0,
+                       stream, sync, sync_words);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    auto go = [&](auto enc_tag) -> hipError_t {
+        constexpr int ENC = decltype(enc_tag)::value;
+        switch (mode) {
+            case kDensePlain: return launch_persistent_enc<ENC, kDensePlain>(stream, jobs, work, q, nb, steps, sync, max_polls, num_cu);
+            case kDenseIdentity: return launch_persistent_enc<ENC, kDenseIdentity>(stream, jobs, work, q, nb, steps, sync, max_polls, num_cu);
+            default: return hipErrorInvalidValue;
+        }
+    };
+    return enc == kDenseT2 ? go(std::integral_constant<int, kDenseT2>{}) : go(std::integral_constant<int, kDenseI8>{});
 }
 
 hipError_t launch_to_dense(hipStream_t stream, int32_t enc, int32_t n, int32_t t4, int32_t np, int32_t tp,

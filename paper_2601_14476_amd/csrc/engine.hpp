@@ -205,6 +205,7 @@ enum : int32_t { kDenseI8 = 0, kDenseT2 = 1 };
 struct DenseJob {
     int32_t n, n4, np, t4, tp, t, t_end;
     int32_t scale;  // J = scale * entry (1 for int8)
+    int32_t items;  // work items of the run in its work list (one step)
     const void *J;
     int8_t *m0, *m1;
     const int32_t *h;
@@ -269,6 +270,11 @@ bool plan_anneal(const DevGraph &g, const DevRun &run, int32_t tpw_req, int32_t 
                  int32_t block_req, size_t max_lds, int32_t num_cu, AnnealPlan *plan,
                  std::string *why);
 
+// How a dense quantum is launched (psa_ctx_set_dense_launch, PSA_DENSE_LAUNCH_*).
+enum : int32_t { kDenseLaunchSteps = PSA_DENSE_LAUNCH_STEPS, kDenseLaunchGraph = PSA_DENSE_LAUNCH_GRAPH,
+                 kDenseLaunchPersistent = PSA_DENSE_LAUNCH_PERSISTENT };
+constexpr uint32_t kDenseMaxPolls = 1u << 20;  // bound of one dependency wait (about a second)
+
 // A captured dense step sequence: `steps` launches over one work list slice.
 // The launches differ only in their step offset and take device pointers to
 // the job table and work list, which the kernels read when they run; so the
@@ -291,6 +297,21 @@ constexpr int32_t kDenseGraphMinSteps = 2;
 // thr24 >= 2^24 (no timing gate); 0 tests each run's mode at run time.
 hipError_t launch_dense_steps(hipStream_t stream, const DenseJob *jobs, const int4 *work,
                               int32_t nwork, int32_t nb, int32_t enc, int32_t mode, int32_t steps);
+// The same `steps` steps in one launch (dense_steps_kernel): the work list
+// split into kDenseQueues queues of whole runs (queue x: items off[x] ..
+// off[x+1]-1), tasks taken in step order from each queue's ticket counter,
+// each waiting for its run's previous step (items of a run counted in
+// DenseJob::items).  mode 1 or 2 only (plain pSA runs).  sync:
+// dense_sync_words(table size) words, zeroed here first; its error flag
+// (word 32 kDenseQueues) is left nonzero if a wait passed max_polls.
+constexpr int32_t kDenseQueues = 8;  // one per XCD
+struct DenseQueues {
+    int32_t off[kDenseQueues + 1];
+};
+int32_t dense_sync_words(int32_t jobs);
+hipError_t launch_dense_persistent(hipStream_t stream, const DenseJob *jobs, const int4 *work,
+                                   const DenseQueues &q, int32_t nb, int32_t enc, int32_t mode, int32_t steps,
+                                   uint32_t *sync, int32_t sync_words, uint32_t max_polls, int32_t num_cu);
 // [n][t4] spins <-> one dense spin buffer of encoding enc
 hipError_t launch_to_dense(hipStream_t stream, int32_t enc, int32_t n, int32_t t4, int32_t np, int32_t tp,
                            const int8_t *spins, int8_t *m);
@@ -389,7 +410,9 @@ psa_status ensure_dense_matrix(psa_graph *g);
 void release_dense_matrix(psa_graph *g);
 // Advance the dense-planned jobs of `jobs` by up to k steps (each clipped to
 // its schedule) on the context's second stream; the caller joins it.
-psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, int32_t k);
+// share: the fraction of the device's compute units a persistent dense launch
+// may fill (the rest is left to a CSR batch launched beside it).
+psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, int32_t k, double share = 1.0);
 
 // Path and launch shape of d from the context's tuning cache, measured on a
 // miss (mode PSA_TUNE_ALONE or PSA_TUNE_BATCH); clears PSA_TUNE (tune.cpp).
@@ -445,10 +468,16 @@ struct psa_ctx {
     size_t dense_table_cap = 0, dense_work_cap = 0;
     std::vector<psa::DenseJob> h_dense_table;
     std::vector<int4> h_dense_work;
-    // captured step sequences of the dense path (batch.cpp), most recently
-    // used last; off unless psa_ctx_set_dense_graphs switches them on
-    bool dense_graphs = false;
+    // how dense quanta are launched (psa_ctx_set_dense_launch); captured
+    // step sequences (batch.cpp), most recently used last; the persistent
+    // launch's counters (two regions of 2 + table words) and the pinned copy
+    // of their error flags, checked at the next dense quantum
+    int32_t dense_launch = psa::kDenseLaunchSteps;
+    uint32_t dense_max_polls = psa::kDenseMaxPolls;
     std::vector<psa::DenseGraph> dense_graph_cache;
+    uint32_t *d_dense_sync = nullptr;
+    size_t dense_sync_cap = 0;
+    uint32_t *h_dense_err = nullptr;  // [2], pinned
     // per-family device timing (psa_ctx_set_timing): event pairs awaiting
     // resolution, by family 0 anneal, 1 batch, 2 dense
     bool timing = false;

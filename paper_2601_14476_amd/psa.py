@@ -41,6 +41,7 @@ PSA_TUNE = 4
 PSA_NOALLOC_SCRATCH_BYTES = 128 << 20
 PSA_ALG_PSA, PSA_ALG_SPSA, PSA_ALG_TAPSA = 0, 1, 2
 PSA_TUNE_ALONE, PSA_TUNE_BATCH = 0, 1
+PSA_DENSE_LAUNCH_STEPS, PSA_DENSE_LAUNCH_GRAPH, PSA_DENSE_LAUNCH_PERSISTENT = 0, 1, 2
 
 _P = ctypes.c_void_p
 _i32, _i64, _u32, _u64, _f64 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
@@ -113,7 +114,8 @@ _SIGNATURES = [
     ("psa_ctx_destroy", None, [_P]),
     ("psa_ctx_set_timing", _i32, [_P, _i32]),
     ("psa_ctx_timing_read", _i32, [_P, ctypes.POINTER(psa_timing)]),
-    ("psa_ctx_set_dense_graphs", _i32, [_P, _i32]),
+    ("psa_ctx_set_dense_launch", _i32, [_P, _i32]),
+    ("psa_debug_dense_wait_limit", _i32, [_P, _u32]),
     ("psa_graph_from_edges", _i32, [_P, _i32, _i64, _P, _P, _P, _P, _u32,
                                     ctypes.POINTER(_P)]),
     ("psa_graph_from_csr", _i32, [_P, _i32, _P, _P, _P, _P, _u32,
@@ -255,9 +257,14 @@ class Context:
         """Record device time per kernel family (psa_ctx_set_timing)."""
         _check(_lib.psa_ctx_set_timing(self.handle, 1 if on else 0), "psa_ctx_set_timing")
 
-    def set_dense_graphs(self, on=True):
-        """Replay dense step sequences from captured graphs (psa_ctx_set_dense_graphs)."""
-        _check(_lib.psa_ctx_set_dense_graphs(self.handle, 1 if on else 0), "psa_ctx_set_dense_graphs")
+    def set_dense_launch(self, how):
+        """How dense quanta are launched (psa_ctx_set_dense_launch): one of
+        PSA_DENSE_LAUNCH_STEPS, _GRAPH, _PERSISTENT."""
+        _check(_lib.psa_ctx_set_dense_launch(self.handle, int(how)), "psa_ctx_set_dense_launch")
+
+    def debug_dense_wait_limit(self, max_polls):
+        """Bound of the persistent dense launch's dependency waits (psa_debug_dense_wait_limit)."""
+        _check(_lib.psa_debug_dense_wait_limit(self.handle, int(max_polls)), "psa_debug_dense_wait_limit")
 
     def timing(self):
         """Totals since the last call (psa_ctx_timing_read), as a dict."""
