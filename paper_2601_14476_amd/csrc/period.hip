@@ -378,9 +378,24 @@ __global__ __launch_bounds__(BLOCK) void period_resident_kernel(PeriodArgs a, co
         for (int s = 0; s < K; ++s) f[s] = ocls[s] < kPeriodMaxClasses && ((fire >> ocls[s]) & 1u) != 0u;
         float xin[K];
         bool close = false;
+        // the firing p-bits' cached neighbour loads first, so that their LDS
+        // latency passes under the random blocks below
+        int32_t m[K][C];
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            if (f[s]) {
+#pragma unroll
+                for (int u = 0; u < C; ++u) {
+                    if constexpr (UNIT)
+                        m[s][u] = spin[oc[s][u] + RO];
+                    else
+                        m[s][u] = spin[(oc[s][u] & 0xFFFFu) + RO];
+                }
+            }
+        }
         // words of the p-bits that fired at the previous firing sub-step, for
-        // their next firing (before the firing p-bits below: a p-bit firing
-        // again now takes its word from here)
+        // their next firing (before the decisions below: a p-bit firing again
+        // now takes its word from here)
 #pragma unroll
         for (int s = 0; s < K; ++s) {
             if (pend[s]) {
@@ -392,21 +407,13 @@ __global__ __launch_bounds__(BLOCK) void period_resident_kernel(PeriodArgs a, co
 #pragma unroll
         for (int s = 0; s < K; ++s) {
             if (f[s]) {
-                int32_t m[C];
-#pragma unroll
-                for (int u = 0; u < C; ++u) {
-                    if constexpr (UNIT)
-                        m[u] = spin[oc[s][u] + RO];
-                    else
-                        m[u] = spin[(oc[s][u] & 0xFFFFu) + RO];
-                }
                 int32_t L = oh[s];
 #pragma unroll
                 for (int u = 0; u < C; ++u) {
                     if constexpr (UNIT)
-                        L += m[u];
+                        L += m[s][u];
                     else
-                        L += (static_cast<int32_t>(oc[s][u]) >> 16) * m[u];
+                        L += (static_cast<int32_t>(oc[s][u]) >> 16) * m[s][u];
                 }
                 for (int32_t x0 = orp[s]; x0 < oend[s]; x0 += 8)
                     L += chunk_field<true>(x0, oend[s], pk, nullptr, nullptr, spin + RO, []() {}, []() {});
