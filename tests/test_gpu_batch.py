@@ -294,3 +294,36 @@ def test_dense_step_at_bench_size_sampled_trials(psa, ctx):
         E, C = oracle.energy_cut(n, u, v, -w, None, spins[i])
         np.testing.assert_array_equal(ec[i][0], E)
         np.testing.assert_array_equal(ec[i][1], C)
+
+
+def test_dense_identity_list_against_oracle(psa, ctx):
+    """A dense list whose runs all have identity factors and no timing gate
+    takes the identity epilogue (pre-activation I0 (float)L, r blocks of the
+    first eight row/trial pairs drawn during the matrix loop): graphs whose
+    coupling chunks number fewer than eight (n = 700, 1,000) and more (n =
+    2,300), 2-bit and int8 couplings, 64 and 40 trials, stepped in quanta;
+    sampled trials against the oracle, energy and cut of every trial against
+    the oracle's evaluation of the device spins."""
+    S = 24
+    rng = np.random.default_rng(90)
+    specs = [inputs.erdos_renyi(700, 0.2, 91), inputs.erdos_renyi(2300, 0.05, 92)]
+    n3, u3, v3, _ = inputs.erdos_renyi(1000, 0.1, 93)
+    w3 = (rng.integers(1, 4, size=u3.size) * rng.choice([-1, 1], size=u3.size)).astype(np.int32)
+    specs.append((n3, u3, v3, w3))
+    trials = [64, 40, 64]
+    graphs = [psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True) for n, u, v, w in specs]
+    jobs = [psa.Job(ctx, g, S, T, 60 + i, path=psa.PSA_PATH_DENSE) for i, (g, T) in enumerate(zip(graphs, trials))]
+    assert all(j.dense for j in jobs)
+    for _ in range(3):
+        psa.jobs_step_batch(ctx, jobs, S // 3)
+    for i, ((n, u, v, w), T) in enumerate(zip(specs, trials)):
+        i0, _, _ = oracle.schedule_paper(n, u, v, -w, S)
+        lam, dlt, thr = oracle.variability(n, 60 + i, 0.0, 0.0, 0.0, 1.0)
+        spins = jobs[i].read_spins()
+        for k in (0, T // 2, T - 1):
+            ref = oracle.anneal(n, u, v, -w, None, i0, lam, dlt, thr, 60 + i, k, k + 1)
+            np.testing.assert_array_equal(spins[k], ref[0][0], err_msg=f"graph {i} trial {k}")
+        E, C = oracle.energy_cut(n, u, v, -w, None, spins)
+        got_E, got_C = jobs[i].energy_cut()
+        np.testing.assert_array_equal(got_E, E)
+        np.testing.assert_array_equal(got_C, C)
