@@ -4,9 +4,11 @@
 // dense coupling matrix with the spins of all trials,
 //     L[i][k] = h_i + sum_j J_ij m_j,k      (exact integer sums),
 // computed on the matrix cores, followed by the p-bit update of Eq. 6 in the
-// same kernel.  One launch advances one step of every dense run in a work
-// list (run, 256-row group, trial tile); the step loop is on the host,
-// because a step needs the whole previous state of its run.
+// same kernel.  One launch of dense_step_kernel advances one step of every
+// dense run in a work list (run, 256-row group, trial tile), with the step
+// loop on the host, because a step needs the whole previous state of its
+// run; dense_steps_kernel runs all steps of a quantum in one launch instead,
+// each work item waiting on a per-run counter of the previous step.
 //
 // Coupling encodings (per graph, chosen at build time):
 //   kDenseI8  int8 [np][np], row-major, zero padding (any |J| <= 127), with
