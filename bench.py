@@ -76,8 +76,8 @@ HBM_PEAK_GBS = 8000.0
 # and one add per neighbour.  gfx950 forms each 32x32->64 product in one
 # instruction and each three-way XOR in another, so a block takes 40, which is
 # why the lower bound above is the headline count.
-SURVEY_PHILOX_BLOCK_OPS = 100
-SURVEY_FP32_OPS = 20
+PLAN_PHILOX_BLOCK_OPS = 100
+PLAN_FP32_OPS = 20
 
 # Host threads the oracle may use: the CPU share of one GPU on the GPU hosts
 # (16), whatever the machine's core count.
@@ -145,9 +145,9 @@ def measured_issue(workload: str, kernel: str):
     return None
 
 
-def survey_ops_per_update(degree: float, timing: bool) -> float:
+def plan_ops_per_update(degree: float, timing: bool) -> float:
     """The workload table's estimate of VALU lane-operations per update."""
-    return SURVEY_PHILOX_BLOCK_OPS * (0.5 if timing else 0.25) + SURVEY_FP32_OPS + degree
+    return PLAN_PHILOX_BLOCK_OPS * (0.5 if timing else 0.25) + PLAN_FP32_OPS + degree
 
 
 def host_cpu():
@@ -339,7 +339,7 @@ def main():
             print(k, source_digest(k))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: this benchmark measures one GPU only (asked for --gpus {args.gpus}); "
               "trials and jobs shard across GPUs without communication, but no "
               "multi-GPU figure is produced here.", file=sys.stderr)
         sys.exit(2)
@@ -437,7 +437,7 @@ def main():
     # the three operation counts side by side (plain pSA in probability mode)
     op_counts = {"gfx950_lower_bound": opu}
     if args.algorithm == "psa" and not args.t_res and not job.dense:
-        op_counts["survey_estimate"] = survey_ops_per_update(info["nnz"] / n, timing)
+        op_counts["workload_table_estimate"] = plan_ops_per_update(info["nnz"] / n, timing)
     issue = measured_issue(args.workload, kname) if default_launch else None
     if issue is not None:
         op_counts["issued_measured"] = issue[0]

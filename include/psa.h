@@ -53,7 +53,7 @@ typedef int32_t psa_status;
 #define PSA_EINVAL (-1)       /* bad argument or invalid graph          */
 #define PSA_ENOMEM (-2)       /* host or device allocation failed        */
 #define PSA_EHIP (-3)         /* a HIP runtime call failed               */
-#define PSA_EUNSUPPORTED (-4) /* valid request this build cannot serve   */
+#define PSA_EUNSUPPORTED (-4) /* valid request the library cannot serve  */
 #define PSA_EAGAIN (-5)       /* server queue full: submit again later   */
 #define PSA_ECANCELED (-6)    /* the job was canceled                    */
 #define PSA_ETIMEDOUT (-7)    /* a wait ended before the job finished    */

@@ -60,11 +60,11 @@ def test_issue_row_matches_only_its_digest(tmp_path, monkeypatch):
     assert bench.measured_issue("c3", "anneal_kernel") is None
 
 
-def test_survey_op_count_reproduces_the_workload_table():
+def test_plan_op_count_reproduces_the_workload_table():
     """The workload table's estimates: 74 lane-operations per update on the
     torus (degree 4, timing on), 76 on the n = 2,000 graph (degree 6)."""
-    assert bench.survey_ops_per_update(4.0, True) == 74.0
-    assert bench.survey_ops_per_update(6.0, True) == 76.0
+    assert bench.plan_ops_per_update(4.0, True) == 74.0
+    assert bench.plan_ops_per_update(6.0, True) == 76.0
     # the gfx950 lower bound of the same updates
     assert bench.ops_per_update(4 * bench.OPS_EDGE_FOUR_TRIALS, True) == 41.25
     assert bench.ops_per_update(6 * bench.OPS_EDGE_ONE_TRIAL, True) == 43.25
