@@ -540,16 +540,17 @@ def bench_batch(args):
         if rb["path"] == psa.PSA_PATH_DENSE:
             dense_jobs += 1
             dense_valu += ops_per_update(0.0, False) * upd
-            enc = jobs[-1].info()["dense_encoding"]
-            # matrix work in int8-peak equivalents: 2-bit couplings run as
-            # fp4 x fp4 at twice the int8 rate
-            mfma_ops += 2.0 * n * n * sp["trials"] * sp["steps"] * (0.5 if enc == 2 else 1.0)
+            enc = jobs[-1].info()["dense_encoding"]   # 1 int8, 2 two-bit, 3 one-bit
+            fp4 = enc in (2, 3)
+            # matrix work in int8-peak equivalents: 1- and 2-bit couplings run
+            # as fp4 x fp4 at twice the int8 rate
+            mfma_ops += 2.0 * n * n * sp["trials"] * sp["steps"] * (0.5 if fp4 else 1.0)
             # algorithmic bytes per step: the encoded couplings once per
             # 64-trial tile, the spins (fp4 or int8) read and written once
-            np_ = (n + 255) // 256 * 256 if enc == 2 else (n + 127) // 128 * 128
+            np_ = (n + 255) // 256 * 256 if fp4 else (n + 127) // 128 * 128
             tiles = (sp["trials"] + 63) // 64
-            dense_bytes += (np_ * np_ * (0.25 if enc == 2 else 1.0) * tiles
-                            + 2 * n * sp["trials"] * (0.5 if enc == 2 else 1.0)) * sp["steps"]
+            dense_bytes += (np_ * np_ * {1: 1.0, 2: 0.25, 3: 0.125}[enc] * tiles
+                            + 2 * n * sp["trials"] * (0.5 if fp4 else 1.0)) * sp["steps"]
         else:
             valu_ops += ops_per_update(info["nnz"] / n * edge_ops(jobs[-1].info()), False) * upd
     S = max(sp["steps"] for sp in specs)
@@ -656,7 +657,7 @@ def bench_batch(args):
 
 def bench_dense(args):
     """The dense step alone: 48 G(n, p) graphs, n ~ U{2000..4000}, p ~ U[0.04, 0.1],
-    +1 weights (2-bit couplings), 64 trials each, all on the matrix-core path,
+    +1 weights (1-bit couplings), 64 trials each, all on the matrix-core path,
     advanced together (one launch per step); 20 warm-up steps, then
     --steps x 30 steps timed with HIP events on the dense stream.  Reports
     the dense step's fractions of the matrix-core, vector and HBM peaks."""
@@ -688,10 +689,11 @@ def bench_dense(args):
     n_arr = np.array([sp[0] for sp in specs], float)
     npad = np.ceil(n_arr / 256) * 256
     upd = float(n_arr.sum() * 64)
-    # 2-bit couplings: fp4 x fp4 products against the fp4 matrix peak; bytes:
-    # the couplings once per 64-trial tile, fp4 spins read and written
+    # +1 weights (every coupling -1): 1-bit couplings, fp4 x fp4 products
+    # against the fp4 matrix peak; bytes: the couplings once per 64-trial
+    # tile, fp4 spins read and written
     mfma = (2 * n_arr ** 2 * 64).sum() / (per_us * 1e-6) / 1e12
-    hbm = (npad ** 2 / 4 + n_arr * 64).sum() / (per_us * 1e-6) / 1e9
+    hbm = (npad ** 2 / 8 + n_arr * 64).sum() / (per_us * 1e-6) / 1e9
     valu = ops_per_update(0.0, False) * upd / (per_us * 1e-6) / 1e12
     fr = {"mfma": mfma / MFMA_F4_PEAK_TOPS, "alu": valu / VALU_PEAK_TOPS, "hbm": hbm / HBM_PEAK_GBS}
     bound = max(fr, key=fr.get)
@@ -700,7 +702,7 @@ def bench_dense(args):
         "value": upd * steps / wall, "unit": "p-bit updates/s", "n_gpus": 1,
         "steps": steps, "warmup": 20, "ms_per_step": wall / steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp4 couplings (2-bit encoded) x fp4 spins -> f32 field (exact integers)",
+        "dtype": "fp4 couplings (1-bit encoded) x fp4 spins -> f32 field (exact integers)",
         "data": "synthetic",
         "config": {"workload": "c4-dense", "graphs": 48, "trials": 64, "n_range": [2000, 4000],
                    "p_range": [0.04, 0.1]},

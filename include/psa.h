@@ -363,7 +363,8 @@ typedef struct psa_job_info {
     int32_t trials_per_group;  /* CSR: trials per workgroup (1 or 4)          */
     int32_t lanes_per_task;    /* CSR, one trial per workgroup: 1, 2 or 4     */
     int32_t block;             /* CSR: threads per workgroup                  */
-    int32_t dense_encoding;    /* dense: 1 = int8 entries, 2 = 2-bit fields   */
+    int32_t dense_encoding;    /* dense: 1 = int8 entries, 2 = 2-bit fields,
+                                  3 = 1-bit fields (one coupling value)       */
     uint32_t algorithm;        /* PSA_ALG_*                                   */
     int64_t device_bytes;      /* device memory the job holds (run arrays,
                                   spin state, input-stage state, staging);

@@ -867,7 +867,7 @@ psa_status psa_job_get_info(const psa_job *job, psa_job_info *out) {
         out->trials_per_group = job->plan.dense ? 0 : job->plan.tpw;
         out->lanes_per_task = job->plan.dense ? 0 : job->plan.lpt;
         out->block = job->plan.dense ? 256 : job->plan.block;
-        out->dense_encoding = job->plan.dense ? (job->g->dense_enc == psa::kDenseT2 ? 2 : 1) : 0;
+        out->dense_encoding = job->plan.dense ? job->g->dense_enc + 1 : 0;
         out->algorithm = job->run.ring ? PSA_ALG_TAPSA : (job->run.xs ? PSA_ALG_SPSA : PSA_ALG_PSA);
         out->device_bytes = static_cast<int64_t>(job->dev_bytes);
         out->period_classes = job->pplan.nclass;

@@ -92,12 +92,13 @@ double csr_step_seconds(const DevGraph &g, const DevRun &run, const AnnealPlan &
     return static_cast<double>(g.n) * run.t4 * (60.0 + per_edge * d) / kValuOpsPerSecond;
 }
 
-double dense_step_seconds(int32_t n, int32_t t4, bool two_bit) {
+double dense_step_seconds(int32_t n, int32_t t4, bool two_bit, bool one_bit) {
+    two_bit = two_bit || one_bit;
     const double np = two_bit ? (n + 255) / 256 * 256 : (n + 127) / 128 * 128;
     const int32_t nb = t4 >= 64 ? 4 : (t4 >= 32 ? 2 : 1);
     const double tp = std::ceil(t4 / (16.0 * nb)) * 16.0 * nb;
     const double mfma = 2.0 * np * np * tp / (0.5 * (two_bit ? kMfmaF4OpsPerSecond : kMfmaI8OpsPerSecond));
-    const double bytes = np * np * (two_bit ? 0.25 : 1.0) * (tp / (16.0 * nb)) / kHbmBytesPerSecond;
+    const double bytes = np * np * (one_bit ? 0.125 : (two_bit ? 0.25 : 1.0)) * (tp / (16.0 * nb)) / kHbmBytesPerSecond;
     return std::max(mfma, bytes) + static_cast<double>(n) * t4 * 60.0 / kValuOpsPerSecond;
 }
 
@@ -105,10 +106,16 @@ bool dense_two_bit(const psa_graph *g) {
     int32_t mag = 0;
     for (int32_t v : g->val_host) {
         const int32_t a = v < 0 ? -v : v;
+        if (a == 0) return false;
         if (mag == 0) mag = a;
         if (a != mag) return false;
     }
     return true;
+}
+
+bool dense_one_bit(const psa_graph *g) {
+    if (g->val_host.empty() || g->val_host[0] == 0) return false;
+    return std::all_of(g->val_host.begin(), g->val_host.end(), [&](int32_t v) { return v == g->val_host[0]; });
 }
 
 bool prefer_dense(const psa_graph *g, const DevRun &run, const AnnealPlan &plan) {
@@ -117,7 +124,7 @@ bool prefer_dense(const psa_graph *g, const DevRun &run, const AnnealPlan &plan)
     if (!two_bit && std::any_of(g->val_host.begin(), g->val_host.end(),
                                 [](int32_t v) { return v < -127 || v > 127; }))
         return false;
-    return dense_step_seconds(g->info.n, run.t4, two_bit) < 0.7 * csr_step_seconds(g->dev, run, plan);
+    return dense_step_seconds(g->info.n, run.t4, two_bit, dense_one_bit(g)) < 0.7 * csr_step_seconds(g->dev, run, plan);
 }
 
 // Work list of the dense runs `idx` of `table` (one encoding): items (job,
@@ -233,10 +240,11 @@ static void dense_task_list(const std::vector<DenseJob> &table, const std::vecto
 psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, int32_t k, double share) {
     std::vector<psa::DenseJob> table;
     std::vector<psa_job *> live;
-    std::vector<int32_t> by_enc[2];
-    int32_t max_steps = 0, nb[2] = {4, 4};
-    bool plain[2] = {true, true};     // every run of the encoding is plain pSA
-    bool identity[2] = {true, true};  // ... with identity factors and no gate
+    constexpr int kE = kDenseEncodings;
+    std::vector<int32_t> by_enc[kE];
+    int32_t max_steps = 0, nb[kE] = {4, 4, 4};
+    bool plain[kE] = {true, true, true};     // every run of the encoding is plain pSA
+    bool identity[kE] = {true, true, true};  // ... with identity factors and no gate
     for (int32_t j = 0; j < count; ++j) {
         psa_job *job = jobs[j];
         const psa_graph *g = job->g;
@@ -267,7 +275,7 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
         d.ring = job->run.ring;
         d.alpha = job->run.alpha;
         d.t_res = job->run.t_res;
-        const int32_t e = g->dense_enc == kDenseT2 ? 1 : 0;
+        const int32_t e = g->dense_enc;
         plain[e] = plain[e] && d.xs == nullptr && d.ring == nullptr && d.t_res == 0;
         identity[e] = identity[e] && job->identity_factors;
         by_enc[e].push_back(static_cast<int32_t>(table.size()));
@@ -279,9 +287,9 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
     if (live.empty()) return PSA_OK;
     const int32_t how = max_steps >= kDenseGraphMinSteps ? ctx->dense_launch : kDenseLaunchSteps;
     std::vector<int4> work, part;
-    size_t off[2] = {0, 0}, len[2] = {0, 0};
-    DenseQueues queues[2] = {};
-    for (int e = 0; e < 2; ++e) {
+    size_t off[kE] = {0, 0, 0}, len[kE] = {0, 0, 0};
+    DenseQueues queues[kE] = {};
+    for (int e = 0; e < kE; ++e) {
         if (by_enc[e].empty()) continue;
         if (how == kDenseLaunchPersistent && plain[e])
             dense_task_list(table, by_enc[e], nb[e], &part, &queues[e]);
@@ -294,8 +302,8 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
     for (const int4 &w : work)
         if (w.x >= 0) ++table[static_cast<size_t>(w.x)].items;
     PSA_HIP(hipStreamSynchronize(ctx->stream2), "hipStreamSynchronize");
-    if (ctx->h_dense_err && (ctx->h_dense_err[0] | ctx->h_dense_err[1])) {
-        ctx->h_dense_err[0] = ctx->h_dense_err[1] = 0u;
+    if (ctx->h_dense_err && (ctx->h_dense_err[0] | ctx->h_dense_err[1] | ctx->h_dense_err[2])) {
+        ctx->h_dense_err[0] = ctx->h_dense_err[1] = ctx->h_dense_err[2] = 0u;
         set_error("dense step sequence: a workgroup waited past its limit for another work item of its run; "
                   "the spins of that quantum are not valid");
         return PSA_EHIP;
@@ -308,14 +316,15 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
     const int32_t sync_words = dense_sync_words(static_cast<int32_t>(table.size()));
     if (how == kDenseLaunchPersistent) {
         void *p = ctx->d_dense_sync;
-        if ((st = ensure(&p, &ctx->dense_sync_cap, 2 * static_cast<size_t>(sync_words) * sizeof(uint32_t))) != PSA_OK)
+        if ((st = ensure(&p, &ctx->dense_sync_cap, kE * static_cast<size_t>(sync_words) * sizeof(uint32_t))) !=
+            PSA_OK)
             return st;
         ctx->d_dense_sync = static_cast<uint32_t *>(p);
         if (!ctx->h_dense_err) {
             void *h = nullptr;
-            PSA_HIP(hipHostMalloc(&h, 2 * sizeof(uint32_t), hipHostMallocDefault), "hipHostMalloc");
+            PSA_HIP(hipHostMalloc(&h, kE * sizeof(uint32_t), hipHostMallocDefault), "hipHostMalloc");
             ctx->h_dense_err = static_cast<uint32_t *>(h);
-            ctx->h_dense_err[0] = ctx->h_dense_err[1] = 0u;
+            ctx->h_dense_err[0] = ctx->h_dense_err[1] = ctx->h_dense_err[2] = 0u;
         }
     }
     ctx->h_dense_table = table;
@@ -337,9 +346,9 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
     hipEvent_t ev = nullptr;
     if ((st = time_begin(ctx, ctx->stream2, &ev)) != PSA_OK) return st;
     int64_t launches = 0, replayed = 0;
-    for (int e = 0; e < 2; ++e) {
+    for (int e = 0; e < kE; ++e) {
         if (len[e] == 0) continue;
-        const int32_t enc = e == 1 ? kDenseT2 : kDenseI8;
+        const int32_t enc = e;
         const int32_t mode = plain[e] ? (identity[e] ? 2 : 1) : 0;
         if (how == kDenseLaunchPersistent && mode != 0) {
             uint32_t *sync = ctx->d_dense_sync + static_cast<size_t>(e) * sync_words;
@@ -411,7 +420,8 @@ psa_status psa_jobs_step_batch(psa_ctx *ctx, int32_t count, psa_job *const *jobs
             if (te <= job->t) continue;
             if (job->plan.dense) {
                 dense_jobs.push_back(job);
-                dense_s += psa::dense_step_seconds(job->g->info.n, job->run.t4, job->g->dense_enc == psa::kDenseT2) *
+                dense_s += psa::dense_step_seconds(job->g->info.n, job->run.t4, job->g->dense_enc == psa::kDenseT2,
+                                                   job->g->dense_enc == psa::kDenseB1) *
                            (te - job->t);
                 continue;
             }

@@ -23,6 +23,16 @@
 //             bound), so the f32 sums are the exact integers.  Four times
 //             fewer coupling bytes than int8, and twice the depth per matrix
 //             instruction at the int8 instruction's issue cost.
+//   kDenseB1  1-bit fields f in {0, 1} with J = scale * f, for graphs whose
+//             couplings all have one value (+1-weight MAX-CUT, all
+//             ferromagnetic): the fp4 path with half the coupling bytes of
+//             kDenseT2 (np a multiple of 256).  B1 words: one 32-bit word per
+//             lane, row block and 128-column k-step holds the lane's 32
+//             columns, column 32 g + 8 d + q in bit 4q + d, so that operand
+//             dword d is w shifted by 1 - d and masked with 0x22222222 (fp4
+//             1.0 where the bit is set); per 64-row tile and 256-column chunk,
+//             2 KB as two 1 KB halves (one per k-step) of [64 lanes][4 row
+//             blocks], two 16-byte loads per lane and chunk.
 //   T2 words: the fp4 operand of one lane is four dwords d = 0..3 whose
 //   nibble q is column 32 g + 8 d + q of the 128-column k-step (g = lane /
 //   16); one 32-bit word w holds two of them, dword 2 v in bits 4q + 1 (set:
@@ -92,6 +102,8 @@ struct Enc<kDenseT2> {
     static constexpr uint32_t kUp = 0x2u, kDown = 0xAu;
     using Acc = v4f;
 };
+template <>
+struct Enc<kDenseB1> : Enc<kDenseT2> {};
 
 // One pair word of 2-bit fields -> two fp4 dwords (see the T2 layout).
 constexpr uint32_t kF4Mask = 0xAAAAAAAAu;
@@ -100,6 +112,12 @@ __device__ __forceinline__ v8i f4_operand(uint32_t w0, uint32_t w1) {
                static_cast<int>(w1 & kF4Mask), static_cast<int>((w1 << 1) & kF4Mask), 0, 0, 0, 0};
 }
 __device__ __forceinline__ v8i f4_widen(const v4i b) { return v8i{b.x, b.y, b.z, b.w, 0, 0, 0, 0}; }
+// One word of 1-bit fields -> the four fp4 dwords (see the B1 layout).
+constexpr uint32_t kB1Mask = 0x22222222u;
+__device__ __forceinline__ v8i b1_operand(uint32_t w) {
+    return v8i{static_cast<int>((w << 1) & kB1Mask), static_cast<int>(w & kB1Mask),
+               static_cast<int>((w >> 1) & kB1Mask), static_cast<int>((w >> 2) & kB1Mask), 0, 0, 0, 0};
+}
 
 // Device-global views of pointers read from the job table (so that loads
 // are global, not flat, and do not wait on LDS traffic).
@@ -119,6 +137,10 @@ struct AFrag<kDenseI8> {
 template <>
 struct AFrag<kDenseT2> {
     v4i q[4];  // quarter Q, word j: row block 2 (Q % 2) + j / 2, k-step Q / 2, pair j % 2
+};
+template <>
+struct AFrag<kDenseB1> {
+    v4i h[2];  // half H = k-step, word j = row block
 };
 
 // NB = 16-trial blocks per workgroup (trial tile = 16 NB).  MODE: what every
@@ -144,6 +166,7 @@ __device__ __forceinline__ void dense_task(const DenseJob *__restrict__ jobs, co
                                            int8_t (*__restrict__ bt)[16 * NB * kLdsStride]) {
     using E = Enc<ENC>;
     using Acc = typename E::Acc;
+    constexpr bool kFp4 = ENC != kDenseI8;
     constexpr bool PLAIN = MODE != kDenseAny;
     constexpr int kTrials = 16 * NB;
     constexpr int kBVec = kTrials * (kChunkBytes / 16);  // 16-byte pieces of one spin chunk
@@ -216,11 +239,16 @@ __device__ __forceinline__ void dense_task(const DenseJob *__restrict__ jobs, co
                     const size_t row = static_cast<size_t>(arow0 + rb * 16 + lr);
                     dst.v[kt][rb] = *as_global<v4i>(J + row * np + kc * E::kCols + kt * 64 + kgrp);
                 }
-        } else {
+        } else if constexpr (ENC == kDenseT2) {
             const gptr<v4i> J = as_global<v4i>(jb.J);
             const size_t tile = (static_cast<size_t>(arow0 / kWaveRows) * nkc + kc) * 4;
 #pragma unroll
             for (int qq = 0; qq < 4; ++qq) dst.q[qq] = J[(tile + qq) * 64 + lane];
+        } else {
+            const gptr<v4i> J = as_global<v4i>(jb.J);
+            const size_t tile = (static_cast<size_t>(arow0 / kWaveRows) * nkc + kc) * 2;
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) dst.h[hh] = J[(tile + hh) * 64 + lane];
         }
     };
 
@@ -246,9 +274,14 @@ __device__ __forceinline__ void dense_task(const DenseJob *__restrict__ jobs, co
                     for (int nb = 0; nb < NB; ++nb)
                         acc[rb][nb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af.v[kt][rb], b[nb], acc[rb][nb], 0, 0, 0);
                 } else {
-                    const v4i &qw = af.q[kt * 2 + (rb >> 1)];
-                    const v8i a = f4_operand(static_cast<uint32_t>(qw[(rb & 1) * 2]),
-                                             static_cast<uint32_t>(qw[(rb & 1) * 2 + 1]));
+                    v8i a;
+                    if constexpr (ENC == kDenseT2) {
+                        const v4i &qw = af.q[kt * 2 + (rb >> 1)];
+                        a = f4_operand(static_cast<uint32_t>(qw[(rb & 1) * 2]),
+                                       static_cast<uint32_t>(qw[(rb & 1) * 2 + 1]));
+                    } else {
+                        a = b1_operand(static_cast<uint32_t>(af.h[kt][rb]));
+                    }
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb)
                         acc[rb][nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
@@ -295,22 +328,22 @@ __device__ __forceinline__ void dense_task(const DenseJob *__restrict__ jobs, co
     };
     auto store4 = [&](uint32_t k, int32_t i0, uint32_t out) {
         const int32_t off = spin_off(k, i0);
-        if constexpr (COH && ENC == kDenseT2)
+        if constexpr (COH && kFp4)
             __builtin_amdgcn_raw_buffer_store_b16(static_cast<uint16_t>(out), rnxt, off, 0, kCohAux);
         else if constexpr (COH)
             __builtin_amdgcn_raw_buffer_store_b32(out, rnxt, off, 0, kCohAux);
-        else if constexpr (ENC == kDenseT2)
+        else if constexpr (kFp4)
             *reinterpret_cast<uint16_t *>(nxt + off) = static_cast<uint16_t>(out);
         else
             *reinterpret_cast<uint32_t *>(nxt + off) = out;
     };
     auto load4 = [&](uint32_t k, int32_t i0) -> uint32_t {
         const int32_t off = spin_off(k, i0);
-        if constexpr (COH && ENC == kDenseT2)
+        if constexpr (COH && kFp4)
             return __builtin_amdgcn_raw_buffer_load_b16(rcur, off, 0, kCohAux);
         else if constexpr (COH)
             return __builtin_amdgcn_raw_buffer_load_b32(rcur, off, 0, kCohAux);
-        else if constexpr (ENC == kDenseT2)
+        else if constexpr (kFp4)
             return *reinterpret_cast<const uint16_t *>(cur + off);
         else
             return *reinterpret_cast<const uint32_t *>(cur + off);
@@ -332,8 +365,8 @@ __device__ __forceinline__ void dense_task(const DenseJob *__restrict__ jobs, co
         const PhiloxKeys keys = philox_keys(jb.k0, jb.k1);
         const gptr<v4i> hvec = as_global<v4i>(jb.h);
         // codes of four up spins, and the bits that turn a code into down
-        constexpr uint32_t kUp4 = ENC == kDenseT2 ? 0x2222u : 0x01010101u;
-        constexpr uint32_t kFlip = ENC == kDenseT2 ? 0x8u : 0xFEu;
+        constexpr uint32_t kUp4 = kFp4 ? 0x2222u : 0x01010101u;
+        constexpr uint32_t kFlip = kFp4 ? 0x8u : 0xFEu;
 #pragma unroll
         for (int e = 0; e < 4 * NB; ++e) {
             const int rb = e / NB, nb = e % NB;
@@ -349,7 +382,7 @@ __device__ __forceinline__ void dense_task(const DenseJob *__restrict__ jobs, co
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
                 float Lf;
-                if constexpr (ENC == kDenseT2)
+                if constexpr (kFp4)
                     Lf = fmaf(scalef, acc[rb][nb][p], static_cast<float>(hv[p]));
                 else
                     Lf = static_cast<float>(hv[p] + scale * acc[rb][nb][p]);
@@ -455,7 +488,7 @@ __device__ __forceinline__ void dense_task(const DenseJob *__restrict__ jobs, co
 }
 
 template <int NB, int ENC, int MODE>
-__global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kernel(const DenseJob *__restrict__ jobs,
+__global__ __launch_bounds__(256, ENC != kDenseI8 ? 3 : 2) void dense_step_kernel(const DenseJob *__restrict__ jobs,
                                                          const int4 *__restrict__ work, int32_t t_off) {
     __shared__ __align__(16) int8_t bt[2][16 * NB * kLdsStride];
     dense_task<NB, ENC, MODE, false>(jobs, work[blockIdx.x], t_off, bt);
@@ -484,7 +517,7 @@ __global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_step_kerne
 //   max_polls times; past that, or once another workgroup has set the error
 //   flag, the workgroup sets the flag and leaves (the host reports it).
 template <int NB, int ENC, int MODE>
-__global__ __launch_bounds__(256, ENC == kDenseT2 ? 3 : 2) void dense_steps_kernel(
+__global__ __launch_bounds__(256, ENC != kDenseI8 ? 3 : 2) void dense_steps_kernel(
     const DenseJob *__restrict__ jobs, const int4 *__restrict__ work, DenseQueues queues, int32_t steps,
     uint32_t *__restrict__ sync, uint32_t max_polls) {
     __shared__ __align__(16) int8_t bt[2][16 * NB * kLdsStride];
@@ -631,8 +664,9 @@ hipError_t launch_dense_steps(hipStream_t stream, const DenseJob *jobs, const in
                               int32_t nwork, int32_t nb, int32_t enc, int32_t mode, int32_t steps) {
     if (nwork <= 0) return hipSuccess;
     for (int32_t s = 0; s < steps; ++s) {
-        const hipError_t e = enc == kDenseT2 ? launch_dense_mode<kDenseT2>(stream, jobs, work, nwork, nb, mode, s)
-                                             : launch_dense_mode<kDenseI8>(stream, jobs, work, nwork, nb, mode, s);
+        const hipError_t e = enc == kDenseB1   ? launch_dense_mode<kDenseB1>(stream, jobs, work, nwork, nb, mode, s)
+                             : enc == kDenseT2 ? launch_dense_mode<kDenseT2>(stream, jobs, work, nwork, nb, mode, s)
+                                               : launch_dense_mode<kDenseI8>(stream, jobs, work, nwork, nb, mode, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -677,14 +711,16 @@ hipError_t launch_dense_persistent(hipStream_t stream, const DenseJob *jobs, con
             default: return hipErrorInvalidValue;
         }
     };
-    return enc == kDenseT2 ? go(std::integral_constant<int, kDenseT2>{}) : go(std::integral_constant<int, kDenseI8>{});
+    return enc == kDenseB1   ? go(std::integral_constant<int, kDenseB1>{})
+           : enc == kDenseT2 ? go(std::integral_constant<int, kDenseT2>{})
+                             : go(std::integral_constant<int, kDenseI8>{});
 }
 
 hipError_t launch_to_dense(hipStream_t stream, int32_t enc, int32_t n, int32_t t4, int32_t np, int32_t tp,
                            const int8_t *spins, int8_t *m) {
-    const int64_t items = static_cast<int64_t>(tp) * (enc == kDenseT2 ? np / 2 : np);
+    const int64_t items = static_cast<int64_t>(tp) * (dense_fp4(enc) ? np / 2 : np);
     const dim3 grid(static_cast<unsigned>((items + 255) / 256));
-    if (enc == kDenseT2)
+    if (dense_fp4(enc))
         hipLaunchKernelGGL(to_dense_f4_kernel, grid, dim3(256), 0, stream, n, t4, np, tp, spins,
                            reinterpret_cast<uint8_t *>(m));
     else
@@ -696,7 +732,7 @@ hipError_t launch_from_dense(hipStream_t stream, int32_t enc, int32_t n, int32_t
                              const int8_t *m, int8_t *spins) {
     const int64_t items = static_cast<int64_t>(n) * t4;
     const dim3 grid(static_cast<unsigned>((items + 255) / 256));
-    if (enc == kDenseT2)
+    if (dense_fp4(enc))
         hipLaunchKernelGGL(from_dense_f4_kernel, grid, dim3(256), 0, stream, n, t4, np,
                            reinterpret_cast<const uint8_t *>(m), spins);
     else

@@ -194,9 +194,12 @@ struct BatchJob {
 };
 
 // Encodings of the dense coupling matrix (dense.hip): int8 entries (np a
-// multiple of 128, int8 spins), or 2-bit fields f in {0, +1, -1} with J =
-// scale * f (np a multiple of 256, fp4 spins).
-enum : int32_t { kDenseI8 = 0, kDenseT2 = 1 };
+// multiple of 128, int8 spins), 2-bit fields f in {0, +1, -1} with J =
+// scale * f, or 1-bit fields f in {0, 1} with J = scale * f (every coupling
+// the same value; np a multiple of 256 and fp4 spins for both).
+enum : int32_t { kDenseI8 = 0, kDenseT2 = 1, kDenseB1 = 2 };
+constexpr int32_t kDenseEncodings = 3;
+constexpr bool dense_fp4(int32_t enc) { return enc != kDenseI8; }
 
 // One run of the dense matrix-core path (dense.hip), as the step kernel reads
 // it.  J is the encoded [np][np] coupling matrix; m0 / m1 are the two spin
@@ -393,11 +396,13 @@ constexpr double kMfmaI8OpsPerSecond = 5.0e15;                // dense int8
 constexpr double kMfmaF4OpsPerSecond = 10.1e15;               // dense fp4
 constexpr double kHbmBytesPerSecond = 8.0e12;
 // Modelled seconds per step of the CSR sweep (with the given plan) and of the
-// dense matrix-core step (2-bit or int8 couplings).
+// dense matrix-core step (1-bit, 2-bit or int8 couplings).
 double csr_step_seconds(const DevGraph &g, const DevRun &run, const AnnealPlan &plan);
-double dense_step_seconds(int32_t n, int32_t t4, bool two_bit);
+double dense_step_seconds(int32_t n, int32_t t4, bool two_bit, bool one_bit);
 // True when every stored coupling has one magnitude (the 2-bit encoding).
 bool dense_two_bit(const psa_graph *g);
+// Every stored coupling the same nonzero value (the 1-bit dense encoding).
+bool dense_one_bit(const psa_graph *g);
 // Cost model of the automatic path choice: dense when the rows are long
 // enough that the matrix-core product beats the CSR walk, and the couplings
 // have a dense encoding.
@@ -470,14 +475,14 @@ struct psa_ctx {
     std::vector<int4> h_dense_work;
     // how dense quanta are launched (psa_ctx_set_dense_launch); captured
     // step sequences (batch.cpp), most recently used last; the persistent
-    // launch's counters (two regions of 2 + table words) and the pinned copy
+    // launch's counters (one region per encoding) and the pinned copy
     // of their error flags, checked at the next dense quantum
     int32_t dense_launch = psa::kDenseLaunchSteps;
     uint32_t dense_max_polls = psa::kDenseMaxPolls;
     std::vector<psa::DenseGraph> dense_graph_cache;
     uint32_t *d_dense_sync = nullptr;
     size_t dense_sync_cap = 0;
-    uint32_t *h_dense_err = nullptr;  // [2], pinned
+    uint32_t *h_dense_err = nullptr;  // [kDenseEncodings], pinned
     // per-family device timing (psa_ctx_set_timing): event pairs awaiting
     // resolution, by family 0 anneal, 1 batch, 2 dense
     bool timing = false;
@@ -514,7 +519,7 @@ struct psa_graph {
     std::vector<int32_t> col_host, val_host;  // for the dense matrix, on demand
     void *d_dense = nullptr;            // encoded [np][np] couplings, built on first use
     int32_t np = 0;                     // n rounded up to 128
-    int32_t dense_enc = 0;              // kDenseI8 or kDenseT2
+    int32_t dense_enc = 0;              // kDenseI8, kDenseT2 or kDenseB1
     int32_t dense_scale = 1;            // J = dense_scale * entry
     size_t dev_bytes = 0;               // device bytes of the CSR and its encodings
     size_t dense_bytes = 0;             // device bytes of d_dense

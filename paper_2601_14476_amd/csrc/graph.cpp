@@ -208,17 +208,49 @@ void graph_unref(psa_graph *g) {
 psa_status ensure_dense_matrix(psa_graph *g) {
     if (g->d_dense) return PSA_OK;
     const int32_t n = g->info.n;
-    // one shared magnitude -> 2-bit fields; otherwise int8 entries
-    int32_t mag = 0;
-    bool one_mag = true;
+    // one shared value -> 1-bit fields; one shared magnitude -> 2-bit fields;
+    // otherwise int8 entries
+    // (a stored zero coupling takes the int8 encoding, which keeps it zero)
+    int32_t mag = 0, val0 = 0;
+    bool one_mag = true, one_val = true, first = true;
     for (int32_t v : g->val_host) {
+        if (v == 0) {
+            one_mag = one_val = false;
+            continue;
+        }
         const int32_t a = v < 0 ? -v : v;
-        if (mag == 0) mag = a;
+        if (first) mag = a, val0 = v, first = false;
         one_mag = one_mag && a == mag;
+        one_val = one_val && v == val0;
     }
     const int32_t np = one_mag ? (n + 255) / 256 * 256 : (n + 127) / 128 * 128;
     psa_status st;
-    if (one_mag) {
+    if (one_val && !g->val_host.empty()) {
+        // 1-bit fields (J = val0 * f), tiled for the step kernel: for each
+        // 64-row tile and 256-column chunk, 2 KB in the order the 64 lanes of
+        // a wave load them (two 16-byte loads per lane, each load 1 KB
+        // contiguous).  Lane l, half H, word j holds row 64 rt + 16 j + l % 16
+        // and, of k-step H of the chunk, columns 32 (l / 16) + 0..31: column
+        // 32 g + 8 d + q (d = 0..3, q = 0..7) in bit 4q + d, so that operand
+        // dword d is (w >> d) & 0x11111111 moved to bit 4q + 1 (fp4 1.0).
+        const int32_t nchunks = np / 256;
+        std::vector<uint32_t> words(static_cast<size_t>(np) * np / 32, 0u);
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t p = g->row_ptr_host[i]; p < g->row_ptr_host[i + 1]; ++p) {
+                const int32_t k = g->col_host[p];
+                const int32_t rt = i >> 6, rb = (i >> 4) & 3, lr = i & 15;
+                const int32_t c = k >> 8, ks = (k >> 7) & 1, grp = (k >> 5) & 3;
+                const int32_t d = (k >> 3) & 3, q = k & 7;
+                const int32_t lane = grp * 16 + lr;
+                const size_t at = ((((static_cast<size_t>(rt) * nchunks + c) * 2 + ks) * 64 + lane) * 4) + rb;
+                words[at] |= 1u << (4 * q + d);
+            }
+        uint32_t *dev = nullptr;
+        if ((st = upload(&dev, words, &g->dense_bytes)) != PSA_OK) return st;
+        g->d_dense = dev;
+        g->dense_enc = kDenseB1;
+        g->dense_scale = val0;
+    } else if (one_mag) {
         // 2-bit fields that two masks turn into fp4 operands, tiled for the
         // step kernel: for each 64-row tile and 256-column chunk, 4 KB in the
         // order the 64 lanes of a wave load them (four 16-byte loads per

@@ -42,7 +42,7 @@ bool dense_encodable(const psa_graph *g) {
 TuneKey tune_key(const psa_graph *g, int32_t trials, uint32_t mode, uint32_t algorithm) {
     const double n = std::max(g->info.n, 1);
     const double d = static_cast<double>(g->info.nnz) / n;
-    const int64_t enc = dense_two_bit(g) ? 2 : (dense_encodable(g) ? 1 : 0);
+    const int64_t enc = dense_one_bit(g) ? 3 : (dense_two_bit(g) ? 2 : (dense_encodable(g) ? 1 : 0));
     // batched mode times copies of the run that fill the chip, so the trial
     // count matters by its magnitude: half-octave classes; alone, exactly
     const int64_t tkey = mode == PSA_TUNE_BATCH
@@ -161,7 +161,8 @@ psa_status psa_autotune(psa_ctx *ctx, const psa_graph *g, const psa_run_desc *de
                 ? 1e6 * psa::csr_step_seconds(g->dev, mrun, mplan)
                 : -1.0;
         const double model_dense =
-            dense_ok ? 1e6 * psa::dense_step_seconds(g->info.n, mrun.t4, psa::dense_two_bit(g)) : -1.0;
+            dense_ok ? 1e6 * psa::dense_step_seconds(g->info.n, mrun.t4, psa::dense_two_bit(g), psa::dense_one_bit(g))
+                     : -1.0;
         const bool prune_dense = g->info.n > 4096 && model_csr > 0.0 && model_dense > 2.0 * model_csr;
         if (dense_ok && !prune_dense) cands.push_back({PSA_PATH_DENSE, 0, 0});
 
