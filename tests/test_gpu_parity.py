@@ -367,21 +367,28 @@ def test_edge_encodings_match_oracle(psa, ctx, kind, tpw, lpt):
 @pytest.mark.parametrize("n,trials,kind", [(1, 3, "unit"), (63, 7, "int"), (64, 16, "unit"),
                                            (65, 33, "int"), (300, 64, "unit"), (1000, 100, "int"),
                                            (257, 1, "unit"), (129, 5, "scaled"), (700, 40, "one"),
-                                           (1300, 130, "one"), (385, 64, "scaled")])
+                                           (1300, 130, "one"), (385, 64, "scaled"), (520, 70, "ferro"),
+                                           (333, 64, "zeros")])
 def test_dense_path_matches_oracle(psa, ctx, n, trials, kind):
     """Dense matrix-core path against the oracle and against the CSR path:
-    identical spins, energies and cuts.  "unit" (+-1), "one" (all +1) and
-    "scaled" (+-3) couplings take the 2-bit encoding, "int" (|J| <= 5) the
-    int8 one; sizes span several 256-row groups, 128-column chunks and trial
-    tiles with ragged tails."""
-    if kind in ("unit", "one", "scaled"):
+    identical spins, energies and cuts.  "one" (+1 weights: every J = -1) and
+    "ferro" (every J = +2) take the 1-bit encoding, "unit" (+-1) and "scaled"
+    (+-3) the 2-bit one, "int" (|J| <= 5) and "zeros" (+-1 with some stored
+    zero couplings) the int8 one; sizes span several 256-row groups, coupling
+    chunks and trial tiles with ragged tails."""
+    if kind in ("unit", "one", "scaled", "ferro", "zeros"):
         if n > 1:
-            p = 0.3 if kind != "one" else 0.08
-            _, u, v, w = inputs.erdos_renyi(n, p, 40 + n, weights="one" if kind == "one" else "pm1")
+            p = 0.3 if kind not in ("one", "ferro") else 0.08
+            _, u, v, w = inputs.erdos_renyi(n, p, 40 + n, weights="one" if kind in ("one", "ferro") else "pm1")
         else:
             u = v = w = np.zeros(0, np.int32)
         if kind == "scaled":
             w = 3 * w
+        if kind == "ferro":
+            w = -2 * w
+        if kind == "zeros":
+            w = w.copy()
+            w[::7] = 0
         j, h = -w, None
     else:
         n, u, v, j, h = _random_ising(n, 4 * n, 41 + n, jmax=5)
@@ -390,6 +397,8 @@ def test_dense_path_matches_oracle(psa, ctx, n, trials, kind):
     i0 = oracle.schedule(S, 0.01, 0.4)
     kw = dict(i0=i0, sigma_lambda=0.1, sigma_delta=0.2, sigma_nu=0.1, p_mean=0.8)
     dense = psa.Job(ctx, g, S, trials, 7, path=psa.PSA_PATH_DENSE, **kw)
+    expect = {"one": 3, "ferro": 3, "unit": 2, "scaled": 2, "int": 1, "zeros": 1}[kind]
+    assert dense.info()["dense_encoding"] == expect
     csr = psa.Job(ctx, g, S, trials, 7, path=psa.PSA_PATH_CSR, **kw)
     dense.step(7)
     dense.step(13)
@@ -406,7 +415,7 @@ def test_dense_path_matches_oracle(psa, ctx, n, trials, kind):
 
 def test_dense_path_rejects_wide_couplings(psa, ctx):
     """Couplings of several magnitudes, one above int8, have no dense encoding
-    (a single magnitude, however large, takes the 2-bit one)."""
+    (a single magnitude, however large, takes the 2-bit or 1-bit one)."""
     g = psa.Graph.from_edges(ctx, 3, np.array([0, 1], np.int32), np.array([1, 2], np.int32),
                              np.array([300, 1], np.int32), maxcut=False)
     with pytest.raises(psa.PsaError) as e:
