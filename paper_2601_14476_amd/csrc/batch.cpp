@@ -77,19 +77,28 @@ void build_work_list(const std::vector<int32_t> &trials, const std::vector<doubl
         for (size_t s = 0; s < queue[x].size(); ++s) (*work)[s * kXcds + x] = queue[x][s];
 }
 
-// Automatic path choice.  Whole-device estimates per step: the CSR walk
-// issues ~60 + 3 d lane-operations per update (d = mean degree) at 39.3 T
-// lane-ops/s; the dense product costs 2 np^2 tp operations at half the int8
-// (or, 2-bit couplings, fp4) matrix peak, or the bytes of J once per trial
-// tile at the HBM peak, whichever is larger, plus ~60 lane-operations of
-// epilogue per update.
+// Automatic path choice.  Whole-device estimates per step (above the floors
+// below): the CSR walk issues ~60 + 3 d lane-operations per update (d = mean
+// degree) at 39.3 T lane-ops/s; the dense product costs 2 np^2 tp operations
+// at half the int8 (or, 1- and 2-bit couplings, fp4) matrix peak, or the
+// bytes of J once per trial tile at the HBM peak, whichever is larger, plus
+// ~60 lane-operations of epilogue per update.
+// Latency floors of a step: the CSR sweep's step is a barrier and a chain of
+// LDS reads inside one persistent launch; the dense step is a launch of its
+// own.  They decide for small runs, whose throughput terms are tiny (a G1-
+// sized run of 10 trials: 2 us per CSR step measured, several times that per
+// dense step).
+constexpr double kCsrStepFloorSeconds = 1.5e-6;
+constexpr double kDenseStepFloorSeconds = 6.0e-6;
+
 double csr_step_seconds(const DevGraph &g, const DevRun &run, const AnnealPlan &plan) {
     // lane-ops per update: RNG, activation and decision (about 60), plus a
     // gather per edge: a few ops from LDS, tens when the rows stream from
     // memory (latency-bound gathers of one trial per workgroup)
     const double d = g.nnz / static_cast<double>(std::max(g.n, 1));
     const double per_edge = plan.csr_lds ? 3.0 : 40.0;
-    return static_cast<double>(g.n) * run.t4 * (60.0 + per_edge * d) / kValuOpsPerSecond;
+    return std::max(kCsrStepFloorSeconds,
+                    static_cast<double>(g.n) * run.t4 * (60.0 + per_edge * d) / kValuOpsPerSecond);
 }
 
 double dense_step_seconds(int32_t n, int32_t t4, bool two_bit, bool one_bit) {
@@ -99,7 +108,7 @@ double dense_step_seconds(int32_t n, int32_t t4, bool two_bit, bool one_bit) {
     const double tp = std::ceil(t4 / (16.0 * nb)) * 16.0 * nb;
     const double mfma = 2.0 * np * np * tp / (0.5 * (two_bit ? kMfmaF4OpsPerSecond : kMfmaI8OpsPerSecond));
     const double bytes = np * np * (one_bit ? 0.125 : (two_bit ? 0.25 : 1.0)) * (tp / (16.0 * nb)) / kHbmBytesPerSecond;
-    return std::max(mfma, bytes) + static_cast<double>(n) * t4 * 60.0 / kValuOpsPerSecond;
+    return kDenseStepFloorSeconds + std::max(mfma, bytes) + static_cast<double>(n) * t4 * 60.0 / kValuOpsPerSecond;
 }
 
 bool dense_two_bit(const psa_graph *g) {
