@@ -88,10 +88,11 @@ ISSUE_TABLE = os.path.join(ROOT, "profiles", "valu_issue_by_workload.md")
 
 
 # The sources each measured kernel is compiled from: its own file, the
-# per-update arithmetic and the argument structures it reads.
+# per-update arithmetic and the argument structures it reads (and, for the
+# dense step, the host file that cuts its launch into work items).
 KERNEL_SOURCES = {
     "anneal_kernel": ["anneal.hip", "device_math.hpp", "engine.hpp"],
-    "dense_step_kernel": ["dense.hip", "device_math.hpp", "engine.hpp"],
+    "dense_step_kernel": ["dense.hip", "device_math.hpp", "engine.hpp", "batch.cpp"],
     "period_kernel": ["period.hip", "device_math.hpp", "engine.hpp"],
 }
 
@@ -327,6 +328,9 @@ def main():
                     help="c4, c4-dense, c5: how a dense quantum is launched (one launch per step, "
                          "one persistent launch, or per-step launches replayed from a captured "
                          "graph)")
+    ap.add_argument("--dense-weights", choices=["one", "pm1"], default="one",
+                    help="c4-dense: +1 weights (1-bit couplings, the workload) or +-1 weights "
+                         "(2-bit couplings)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times); "
                          "used to scale the HBM traffic counters")
@@ -657,7 +661,7 @@ def bench_batch(args):
 
 def bench_dense(args):
     """The dense step alone: 48 G(n, p) graphs, n ~ U{2000..4000}, p ~ U[0.04, 0.1],
-    +1 weights (1-bit couplings), 64 trials each, all on the matrix-core path,
+    +1 weights (1-bit couplings; +-1 and 2-bit with --dense-weights pm1), 64 trials each, all on the matrix-core path,
     advanced together (one launch per step); 20 warm-up steps, then
     --steps x 30 steps timed with HIP events on the dense stream.  Reports
     the dense step's fractions of the matrix-core, vector and HBM peaks."""
@@ -669,7 +673,7 @@ def bench_dense(args):
     for g in range(48):
         n = int(rng.integers(2000, 4000))
         p = float(rng.uniform(0.04, 0.1))
-        specs.append(inputs.erdos_renyi(n, p, 500 + g))
+        specs.append(inputs.erdos_renyi(n, p, 500 + g, weights=args.dense_weights))
     ctx = psa.Context(0)
     ctx.set_dense_launch(DENSE_LAUNCH[args.dense_launch])
     graphs = [psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True) for n, u, v, w in specs]
@@ -689,11 +693,12 @@ def bench_dense(args):
     n_arr = np.array([sp[0] for sp in specs], float)
     npad = np.ceil(n_arr / 256) * 256
     upd = float(n_arr.sum() * 64)
-    # +1 weights (every coupling -1): 1-bit couplings, fp4 x fp4 products
-    # against the fp4 matrix peak; bytes: the couplings once per 64-trial
-    # tile, fp4 spins read and written
+    # +1 weights (every coupling -1): 1-bit couplings, +-1: 2-bit; fp4 x fp4
+    # products against the fp4 matrix peak; bytes: the couplings once per
+    # 64 trials, fp4 spins read and written
+    one_bit = args.dense_weights == "one"
     mfma = (2 * n_arr ** 2 * 64).sum() / (per_us * 1e-6) / 1e12
-    hbm = (npad ** 2 / 8 + n_arr * 64).sum() / (per_us * 1e-6) / 1e9
+    hbm = (npad ** 2 / (8 if one_bit else 4) + n_arr * 64).sum() / (per_us * 1e-6) / 1e9
     valu = ops_per_update(0.0, False) * upd / (per_us * 1e-6) / 1e12
     fr = {"mfma": mfma / MFMA_F4_PEAK_TOPS, "alu": valu / VALU_PEAK_TOPS, "hbm": hbm / HBM_PEAK_GBS}
     bound = max(fr, key=fr.get)
@@ -702,15 +707,16 @@ def bench_dense(args):
         "value": upd * steps / wall, "unit": "p-bit updates/s", "n_gpus": 1,
         "steps": steps, "warmup": 20, "ms_per_step": wall / steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp4 couplings (1-bit encoded) x fp4 spins -> f32 field (exact integers)",
+        "dtype": "fp4 couplings (%s encoded) x fp4 spins -> f32 field (exact integers)"
+                 % ("1-bit" if one_bit else "2-bit"),
         "data": "synthetic",
         "config": {"workload": "c4-dense", "graphs": 48, "trials": 64, "n_range": [2000, 4000],
-                   "p_range": [0.04, 0.1]},
+                   "p_range": [0.04, 0.1], "weights": "+1" if one_bit else "+-1"},
         "roofline": {"bound": bound, "kernel": "dense_step_kernel",
                      "achieved": {"mfma": mfma, "alu": valu, "hbm": hbm}[bound],
                      "peak": {"mfma": MFMA_F4_PEAK_TOPS, "alu": VALU_PEAK_TOPS, "hbm": HBM_PEAK_GBS}[bound],
                      "unit": "GB/s" if bound == "hbm" else "TOP/s", "frac": fr[bound],
-                     "traffic": measured_traffic("c4-dense", "dense_step_kernel"),
+                     "traffic": measured_traffic("c4-dense", "dense_step_kernel") if one_bit else None,
                      "kernel_us_per_step": per_us, "dense_fracs": fr},
     }
     print(json.dumps(line), flush=True)

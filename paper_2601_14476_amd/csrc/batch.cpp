@@ -137,11 +137,13 @@ bool prefer_dense(const psa_graph *g, const DevRun &run, const AnnealPlan &plan)
 }
 
 // Work list of the dense runs `idx` of `table` (one encoding): items (job,
-// 256-row group, trial tile) in chunks of up to 16 consecutive row groups of
-// one trial tile, each chunk given whole to the least loaded of the 8 XCDs,
-// heaviest runs first.  Workgroup b of a launch runs on XCD b % 8, so slot b
-// takes item b / 8 of that XCD's queue (or an empty slot): a run's chunk
-// shares its spin tile in one L2.
+// 256-row group, trial tile) in chunks of up to 16 items -- consecutive row
+// groups, each with its trial tiles next to each other -- each chunk given
+// whole to the least loaded of the 8 XCDs, heaviest runs first.  Workgroup b
+// of a launch runs on XCD b % 8, so slot b takes item b / 8 of that XCD's
+// queue (or an empty slot): a chunk's items share their spin tiles in one L2,
+// and the trial tiles of a row group read its couplings at about the same
+// time there.
 static void dense_work_list(const std::vector<DenseJob> &table, const std::vector<int32_t> &idx,
                             int32_t nb, std::vector<int4> *out) {
     constexpr int32_t kXcd = 8, kChunk = 16;
@@ -155,13 +157,14 @@ static void dense_work_list(const std::vector<DenseJob> &table, const std::vecto
     for (int32_t j : order) {
         const DenseJob &d = table[j];
         const int32_t groups = (d.np + 255) / 256, tiles = d.tp / (16 * nb);
-        for (int32_t tt = 0; tt < tiles; ++tt)
-            for (int32_t g0 = 0; g0 < groups; g0 += kChunk) {
-                const int32_t g1 = std::min(groups, g0 + kChunk);
-                const int32_t x = static_cast<int32_t>(std::min_element(load.begin(), load.end()) - load.begin());
-                for (int32_t g = g0; g < g1; ++g) bins[x].push_back(make_int4(j, g, tt, 0));
-                load[x] += static_cast<double>(g1 - g0) * d.np;
-            }
+        const int32_t span = std::max(1, kChunk / tiles);  // row groups per chunk
+        for (int32_t g0 = 0; g0 < groups; g0 += span) {
+            const int32_t g1 = std::min(groups, g0 + span);
+            const int32_t x = static_cast<int32_t>(std::min_element(load.begin(), load.end()) - load.begin());
+            for (int32_t g = g0; g < g1; ++g)
+                for (int32_t tt = 0; tt < tiles; ++tt) bins[x].push_back(make_int4(j, g, tt, 0));
+            load[x] += static_cast<double>(g1 - g0) * tiles * d.np;
+        }
     }
     size_t len = 0;
     for (const auto &b : bins) len = std::max(len, b.size());
@@ -219,7 +222,7 @@ static psa_status dense_sequence(psa_ctx *ctx, const DenseJob *table, const int4
 
 // Task list of the persistent launch: whole runs dealt to kDenseQueues queues
 // (heaviest first, each to the least loaded queue), each queue's items run by
-// run (trial tile, then 256-row group), no empty slots; q->off the queues'
+// run (256-row group, then trial tile), no empty slots; q->off the queues'
 // bounds in the list.
 static void dense_task_list(const std::vector<DenseJob> &table, const std::vector<int32_t> &idx, int32_t nb,
                             std::vector<int4> *out, DenseQueues *q) {
@@ -239,8 +242,8 @@ static void dense_task_list(const std::vector<DenseJob> &table, const std::vecto
         for (int32_t j : queue[x]) {
             const DenseJob &d = table[j];
             const int32_t groups = (d.np + 255) / 256, tiles = d.tp / (16 * nb);
-            for (int32_t tt = 0; tt < tiles; ++tt)
-                for (int32_t g = 0; g < groups; ++g) out->push_back(make_int4(j, g, tt, 0));
+            for (int32_t g = 0; g < groups; ++g)
+                for (int32_t tt = 0; tt < tiles; ++tt) out->push_back(make_int4(j, g, tt, 0));
         }
     }
     q->off[kDenseQueues] = static_cast<int32_t>(out->size());
@@ -294,6 +297,18 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
         max_steps = std::max(max_steps, (te - job->t) * std::max(job->run.t_res, 1));
     }
     if (live.empty()) return PSA_OK;
+    // fp4 couplings: trial tiles of at most 32 trials.  The two tiles of a
+    // 64-trial row group read the same couplings (the second mostly from L2,
+    // the work list keeping them together), and twice the items per launch
+    // both outnumber the resident workgroup slots, so that items start in
+    // waves and their coupling and epilogue phases overlap, and even out the
+    // items per compute unit in the vector-bound epilogue (48 runs of n
+    // 2,000-4,000 at 64 trials, 1-bit couplings: 25.1-25.5 against 26.8-26.9
+    // us per step, the second tile's coupling reads adding 4.5 MB of HBM
+    // traffic to 70 MB; 16-trial tiles 30.7 us; 2-bit couplings 32.5 us
+    // either way).
+    for (int e = 0; e < kE; ++e)
+        if (dense_fp4(e)) nb[e] = std::min(nb[e], 2);
     const int32_t how = max_steps >= kDenseGraphMinSteps ? ctx->dense_launch : kDenseLaunchSteps;
     std::vector<int4> work, part;
     size_t off[kE] = {0, 0, 0}, len[kE] = {0, 0, 0};
