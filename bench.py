@@ -567,8 +567,7 @@ def bench_batch(args):
         psa.jobs_step_batch(ctx, jobs, S)
         if ev is not None:
             ev[1].record(stream)
-        for j, (E, C) in zip(jobs, outs):
-            j.energy_cut(E, C)
+        psa.jobs_energy_cut(ctx, jobs, [E for E, _ in outs], [C for _, C in outs])
 
     def sequential():
         for j, (E, C) in zip(alone, outs):

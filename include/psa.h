@@ -403,6 +403,18 @@ psa_status psa_job_local_field(psa_job *job, int32_t *out, uint32_t flags);
 psa_status psa_job_energy_cut(psa_job *job, int64_t *energy, int64_t *cut,
                               uint32_t flags);
 
+/* psa_job_energy_cut of `count` jobs of ctx (Eq. 2 energy and cut of each
+ * job's current spins) in two launches on the context's stream instead of
+ * two per job, so that many small read-outs fill the device together.
+ * energy[j], cut[j]: int64 [trials of jobs[j]], all host or all device
+ * memory per flags (PSA_OUT_DEVICE: written in stream order, no wait; host:
+ * returns when written).  Values identical to psa_job_energy_cut's.  A job
+ * may be listed more than once.  EINVAL for a NULL job or output, a job of
+ * another context, or more than 2^31 - 1 partial-sum workgroups or trials in
+ * total; ENOMEM when a job's read-out staging cannot be allocated. */
+psa_status psa_jobs_energy_cut(psa_ctx *ctx, int32_t count, psa_job *const *jobs,
+                               int64_t *const *energy, int64_t *const *cut, uint32_t flags);
+
 void psa_job_destroy(psa_job *job);
 
 /* Whole anneal: create, all steps, energy and cut, read-out.  spins_out

@@ -345,6 +345,7 @@ void ctx_release(psa_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->stream2) (void)hipStreamSynchronize(ctx->stream2);
     if (ctx->d_batch_table) (void)hipFree(ctx->d_batch_table);
+    if (ctx->d_energy_table) (void)hipFree(ctx->d_energy_table);
     if (ctx->d_batch_work) (void)hipFree(ctx->d_batch_work);
     if (ctx->d_dense_table) (void)hipFree(ctx->d_dense_table);
     if (ctx->d_dense_work) (void)hipFree(ctx->d_dense_work);
@@ -998,6 +999,89 @@ psa_status psa_job_energy_cut(psa_job *job, int64_t *energy, int64_t *cut, uint3
                                job->ctx->stream),
                 "copy-out");
         PSA_HIP(hipStreamSynchronize(job->ctx->stream), "hipStreamSynchronize");
+        return PSA_OK;
+    });
+}
+
+psa_status psa_jobs_energy_cut(psa_ctx *ctx, int32_t count, psa_job *const *jobs, int64_t *const *energy,
+                               int64_t *const *cut, uint32_t flags) {
+    return psa::guarded("psa_jobs_energy_cut", [&]() -> psa_status {
+        if (!ctx || count < 0 || (count > 0 && (!jobs || !energy || !cut)) || (flags & ~PSA_OUT_DEVICE) != 0) {
+            set_error("psa_jobs_energy_cut: invalid arguments");
+            return PSA_EINVAL;
+        }
+        for (int32_t j = 0; j < count; ++j)
+            if (!jobs[j] || jobs[j]->ctx != ctx || !energy[j] || !cut[j]) {
+                set_error("psa_jobs_energy_cut: job " + std::to_string(j) +
+                          " is NULL, belongs to another context, or has no outputs");
+                return PSA_EINVAL;
+            }
+        if (count == 0) return PSA_OK;
+        PSA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+        const bool device = (flags & PSA_OUT_DEVICE) != 0;
+        std::vector<psa::EnergyJob> table(static_cast<size_t>(count));
+        int64_t wgs = 0, trials = 0;
+        for (int32_t j = 0; j < count; ++j) {
+            psa_job *job = jobs[j];
+            // each run's partial sums (and host staging) in its own scratch,
+            // laid out as psa_job_energy_cut lays them out
+            const size_t bytes = static_cast<size_t>(job->run.trials) * sizeof(int64_t);
+            const psa_status st =
+                ensure_scratch(job, 2 * bytes + psa::energy_partial_bytes(job->g->info.n, job->run.t4));
+            if (st != PSA_OK) return st;
+            int64_t *tmp = static_cast<int64_t *>(job->d_scratch);
+            psa::EnergyJob &e = table[static_cast<size_t>(j)];
+            e.n = job->g->info.n;
+            e.t4 = job->run.t4;
+            e.trials = job->run.trials;
+            e.blocks = (e.n + 255) / 256;
+            e.wg0 = static_cast<int32_t>(wgs);
+            e.k0 = static_cast<int32_t>(trials);
+            e.w2 = job->g->dev.w2;
+            e.row_ptr = job->g->dev.row_ptr;
+            e.col = job->g->dev.col;
+            e.val = job->g->dev.val;
+            e.h = job->g->dev.h;
+            e.spins = job->run.spins;
+            e.part = tmp + 2 * job->run.trials;
+            e.energy = device ? energy[j] : tmp;
+            e.cut = device ? cut[j] : tmp + job->run.trials;
+            wgs += psa::energy_batch_wgs(e.n, e.t4);
+            trials += e.trials;
+            if (wgs > std::numeric_limits<int32_t>::max() || trials > std::numeric_limits<int32_t>::max()) {
+                set_error("psa_jobs_energy_cut: too many runs for one read-out");
+                return PSA_EINVAL;
+            }
+        }
+        // the table buffer is reused: the previous read-out must be done
+        PSA_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        const size_t tbytes = table.size() * sizeof(psa::EnergyJob);
+        if (ctx->energy_table_cap < tbytes) {
+            if (ctx->d_energy_table) (void)hipFree(ctx->d_energy_table);
+            ctx->d_energy_table = nullptr;
+            ctx->energy_table_cap = 0;
+            if (hipMalloc(&ctx->d_energy_table, tbytes) != hipSuccess) {
+                ctx->d_energy_table = nullptr;
+                set_error("psa_jobs_energy_cut: device allocation failed");
+                return PSA_ENOMEM;
+            }
+            ctx->energy_table_cap = tbytes;
+        }
+        ctx->h_energy_table = std::move(table);
+        PSA_HIP(hipMemcpyAsync(ctx->d_energy_table, ctx->h_energy_table.data(), tbytes, hipMemcpyHostToDevice,
+                               ctx->stream),
+                "energy table upload");
+        PSA_HIP(psa::launch_energy_cut_batch(ctx->stream, static_cast<const psa::EnergyJob *>(ctx->d_energy_table),
+                                             count, static_cast<int32_t>(wgs), static_cast<int32_t>(trials)),
+                "energy/cut");
+        if (device) return PSA_OK;
+        for (int32_t j = 0; j < count; ++j) {
+            const psa::EnergyJob &e = ctx->h_energy_table[static_cast<size_t>(j)];
+            const size_t bytes = static_cast<size_t>(e.trials) * sizeof(int64_t);
+            PSA_HIP(hipMemcpyAsync(energy[j], e.energy, bytes, hipMemcpyDeviceToHost, ctx->stream), "copy-out");
+            PSA_HIP(hipMemcpyAsync(cut[j], e.cut, bytes, hipMemcpyDeviceToHost, ctx->stream), "copy-out");
+        }
+        PSA_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
         return PSA_OK;
     });
 }

@@ -347,6 +347,27 @@ hipError_t launch_local_field(hipStream_t stream, const DevGraph &g,
 size_t energy_partial_bytes(int32_t n, int32_t t4);
 hipError_t launch_energy_cut(hipStream_t stream, const DevGraph &g, const DevRun &run,
                              int64_t *part, int64_t *energy, int64_t *cut);
+// One run of a batched energy / cut read-out: its graph and spins, its share
+// of the partial-sum buffer (energy_partial_bytes of it) and its outputs.
+// wg0: its first workgroup of the partial pass (energy_batch_wgs of them);
+// k0: its first thread of the final pass (one per trial).
+struct EnergyJob {
+    int32_t n = 0, t4 = 0, trials = 0, blocks = 0;
+    int32_t wg0 = 0, k0 = 0;
+    int64_t w2 = 0;
+    const int32_t *row_ptr = nullptr, *col = nullptr, *val = nullptr, *h = nullptr;
+    const int8_t *spins = nullptr;
+    int64_t *part = nullptr;
+    int64_t *energy = nullptr, *cut = nullptr;
+};
+// The read-outs of `count` runs (a device table, wg0 and k0 ascending) in two
+// launches: wgs = the runs' partial workgroups, trials = their trials.
+hipError_t launch_energy_cut_batch(hipStream_t stream, const EnergyJob *jobs, int32_t count, int32_t wgs,
+                                   int32_t trials);
+// Workgroups of one run's batched partial pass: row blocks x chunks of 16 trials.
+inline int64_t energy_batch_wgs(int32_t n, int32_t t4) {
+    return static_cast<int64_t>((n + 255) / 256) * ((t4 / 4 + 3) / 4);
+}
 hipError_t launch_spins_to_tn(hipStream_t stream, int32_t n, const DevRun &run,
                               int8_t *out_tn);
 hipError_t launch_spins_from_tn(hipStream_t stream, int32_t n, const DevRun &run,
@@ -466,6 +487,10 @@ struct psa_ctx {
     size_t batch_table_cap = 0, batch_work_cap = 0;
     std::vector<psa::BatchJob> h_batch_table;
     std::vector<int2> h_batch_work;
+    // batched energy / cut read-outs: the run table (grow-only)
+    void *d_energy_table = nullptr;
+    size_t energy_table_cap = 0;
+    std::vector<psa::EnergyJob> h_energy_table;
     // dense-path launches run on a second stream, joined with events
     hipStream_t stream2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;

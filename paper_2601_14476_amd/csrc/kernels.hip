@@ -92,12 +92,12 @@ constexpr int kEnergyBlock = 256;
 // row terms m_i sum_j J_ij m_j and h_i m_i of the four trials of q; thread
 // per row.  part[(block * groups + q) * 8 + c]: c < 4 the S terms of trial
 // 4q + c, c >= 4 the h terms.
-__global__ __launch_bounds__(kEnergyBlock) void energy_partial_kernel(
-    int32_t n, int32_t t4, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-    const int32_t *__restrict__ val, const int32_t *__restrict__ h,
-    const int8_t *__restrict__ spins, int64_t *__restrict__ part) {
-    const int32_t q = blockIdx.y;
-    const int32_t i = blockIdx.x * kEnergyBlock + threadIdx.x;
+__device__ __forceinline__ void energy_partial(int32_t n, int32_t t4, const int32_t *__restrict__ row_ptr,
+                                               const int32_t *__restrict__ col, const int32_t *__restrict__ val,
+                                               const int32_t *__restrict__ h, const int8_t *__restrict__ spins,
+                                               int64_t *__restrict__ part, int32_t blk, int32_t q) {
+    const int32_t groups = t4 / 4;
+    const int32_t i = blk * kEnergyBlock + threadIdx.x;
     int64_t s[4] = {0, 0, 0, 0};
     int64_t hm[4] = {0, 0, 0, 0};
     if (i < n) {
@@ -139,18 +139,23 @@ __global__ __launch_bounds__(kEnergyBlock) void energy_partial_kernel(
     if (threadIdx.x < 8) {
         int64_t v = 0;
         for (int w = 0; w < kEnergyBlock / 64; ++w) v += red[w][threadIdx.x];
-        part[(static_cast<size_t>(blockIdx.x) * gridDim.y + q) * 8 + threadIdx.x] = v;
+        part[(static_cast<size_t>(blk) * groups + q) * 8 + threadIdx.x] = v;
     }
+}
+
+__global__ __launch_bounds__(kEnergyBlock) void energy_partial_kernel(
+    int32_t n, int32_t t4, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const int32_t *__restrict__ val, const int32_t *__restrict__ h,
+    const int8_t *__restrict__ spins, int64_t *__restrict__ part) {
+    energy_partial(n, t4, row_ptr, col, val, h, spins, part, blockIdx.x, blockIdx.y);
 }
 
 // Pass 2: thread per trial k sums the row blocks' terms:
 //   E_k   = -sum_i h_i m_i - S_k / 2
 //   cut_k = sum_{i<j} w_ij [m_i != m_j] = (S_k - W2) / 4     (w = -J)
-__global__ void energy_finish_kernel(int32_t blocks, int32_t groups, int32_t trials, int64_t w2,
-                                     const int64_t *__restrict__ part, int64_t *__restrict__ energy,
-                                     int64_t *__restrict__ cut) {
-    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= trials) return;
+__device__ __forceinline__ void energy_finish(int32_t blocks, int32_t groups, int32_t k, int64_t w2,
+                                              const int64_t *__restrict__ part, int64_t *__restrict__ energy,
+                                              int64_t *__restrict__ cut) {
     const int32_t q = k >> 2, c = k & 3;
     int64_t S = 0, H = 0;
     for (int32_t b = 0; b < blocks; ++b) {
@@ -159,6 +164,135 @@ __global__ void energy_finish_kernel(int32_t blocks, int32_t groups, int32_t tri
     }
     energy[k] = -H - S / 2;
     cut[k] = (S - w2) / 4;
+}
+
+__global__ void energy_finish_kernel(int32_t blocks, int32_t groups, int32_t trials, int64_t w2,
+                                     const int64_t *__restrict__ part, int64_t *__restrict__ energy,
+                                     int64_t *__restrict__ cut) {
+    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= trials) return;
+    energy_finish(blocks, groups, k, w2, part, energy, cut);
+}
+
+// The run of a batched read-out that index x (a workgroup of the partial
+// pass, or a trial of the final pass) belongs to: the last run whose first
+// index is at most x (first indices ascending, the first one 0).
+template <bool WG>
+__device__ __forceinline__ int32_t energy_run_of(const EnergyJob *__restrict__ jobs, int32_t count, int32_t x) {
+    int32_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if ((WG ? jobs[mid].wg0 : jobs[mid].k0) <= x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Batched partial pass, sixteen trials per thread: workgroup (row block,
+// chunk y of four trial groups) sums the terms of groups 4y..4y+3 (those below
+// t4 / 4) into the same part entries as energy_partial, reading each edge's
+// column and coupling once per 16 trials and, when t4 is a multiple of 16,
+// the neighbour's 16 spins in one load.  A row term is below 2^24 in
+// magnitude (the field bound), so a wavefront's sum of 64 fits int32; the
+// wavefronts' sums are added in int64.
+constexpr int kEnergyQuads = 4;
+
+__device__ __forceinline__ void energy_partial16(const EnergyJob &e, int32_t blk, int32_t y) {
+    constexpr int Q = kEnergyQuads;
+    const int32_t t4 = e.t4;
+    const int32_t groups = t4 / 4;
+    const int32_t q0 = y * Q;
+    const int32_t nq = groups - q0 < Q ? groups - q0 : Q;  // workgroup-uniform
+    const bool vec = (t4 & 15) == 0 && (reinterpret_cast<uintptr_t>(e.spins) & 15) == 0;
+    const int32_t i = blk * kEnergyBlock + threadIdx.x;
+    int32_t s[Q][4] = {}, hm[Q][4] = {};
+    if (i < e.n) {
+        int32_t L[Q][4] = {};
+        const int32_t e1 = e.row_ptr[i + 1];
+#pragma unroll 2
+        for (int32_t x = e.row_ptr[i]; x < e1; ++x) {
+            const int32_t j = e.col[x];
+            const int32_t J = e.val[x];
+            uint32_t w[Q] = {0u, 0u, 0u, 0u};
+            if (vec) {
+                const uint4 v4 = *reinterpret_cast<const uint4 *>(e.spins + static_cast<size_t>(j) * t4 + 4 * q0);
+                w[0] = v4.x;
+                w[1] = v4.y;
+                w[2] = v4.z;
+                w[3] = v4.w;
+            } else {
+#pragma unroll
+                for (int qq = 0; qq < Q; ++qq)
+                    if (qq < nq) w[qq] = load_word(e.spins, t4, j, q0 + qq);
+            }
+#pragma unroll
+            for (int qq = 0; qq < Q; ++qq)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) L[qq][k] += J * spin_of(w[qq], k);
+        }
+#pragma unroll
+        for (int qq = 0; qq < Q; ++qq) {
+            if (qq < nq) {
+                const uint32_t wi = load_word(e.spins, t4, i, q0 + qq);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int32_t mi = spin_of(wi, k);
+                    s[qq][k] = mi * L[qq][k];
+                    hm[qq][k] = mi * e.h[i];
+                }
+            }
+        }
+    }
+    __shared__ int64_t red[kEnergyBlock / 64][Q][8];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int qq = 0; qq < Q; ++qq)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            for (int off = 32; off > 0; off >>= 1) {
+                s[qq][k] += __shfl_down(s[qq][k], off, 64);
+                hm[qq][k] += __shfl_down(hm[qq][k], off, 64);
+            }
+    if (lane == 0) {
+#pragma unroll
+        for (int qq = 0; qq < Q; ++qq)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                red[wave][qq][k] = s[qq][k];
+                red[wave][qq][4 + k] = hm[qq][k];
+            }
+    }
+    __syncthreads();
+    if (threadIdx.x < 8 * Q) {
+        const int qq = threadIdx.x >> 3, c = threadIdx.x & 7;
+        if (qq < nq) {
+            int64_t v = 0;
+            for (int wv = 0; wv < kEnergyBlock / 64; ++wv) v += red[wv][qq][c];
+            e.part[(static_cast<size_t>(blk) * groups + q0 + qq) * 8 + c] = v;
+        }
+    }
+}
+
+// Batched partial pass: workgroup b is (row block, chunk of four trial
+// groups) b - wg0 of its run, row block major.
+__global__ __launch_bounds__(kEnergyBlock) void energy_partial_batch_kernel(const EnergyJob *__restrict__ jobs,
+                                                                            int32_t count) {
+    const int32_t b = blockIdx.x;
+    const EnergyJob &e = jobs[energy_run_of<true>(jobs, count, b)];
+    const int32_t chunks = (e.t4 / 4 + kEnergyQuads - 1) / kEnergyQuads;
+    const int32_t local = b - e.wg0;
+    energy_partial16(e, local / chunks, local % chunks);
+}
+
+// Batched final pass: thread x is trial x - k0 of its run.
+__global__ void energy_finish_batch_kernel(const EnergyJob *__restrict__ jobs, int32_t count, int32_t trials) {
+    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= trials) return;
+    const EnergyJob &e = jobs[energy_run_of<false>(jobs, count, x)];
+    energy_finish(e.blocks, e.t4 / 4, x - e.k0, e.w2, e.part, e.energy, e.cut);
 }
 
 // [n][t4] -> [trials][n]
@@ -244,6 +378,17 @@ hipError_t launch_energy_cut(hipStream_t stream, const DevGraph &g, const DevRun
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(energy_finish_kernel, dim3(grid_for(run.trials, 256)), dim3(256), 0, stream,
                        blocks, groups, run.trials, g.w2, part, energy, cut);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_cut_batch(hipStream_t stream, const EnergyJob *jobs, int32_t count, int32_t wgs,
+                                   int32_t trials) {
+    if (count <= 0 || wgs <= 0 || trials <= 0) return hipSuccess;
+    hipLaunchKernelGGL(energy_partial_batch_kernel, dim3(wgs), dim3(kEnergyBlock), 0, stream, jobs, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(energy_finish_batch_kernel, dim3(grid_for(trials, 256)), dim3(256), 0, stream, jobs, count,
+                       trials);
     return hipGetLastError();
 }
 

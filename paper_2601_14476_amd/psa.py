@@ -142,6 +142,8 @@ _SIGNATURES = [
     ("psa_anneal", _i32, [_P, _P, ctypes.POINTER(psa_run_desc), _P, _P, _P, _u32]),
     ("psa_anneal_noalloc", _i32, [_P, _P, ctypes.POINTER(psa_run_desc), _P, _P, _P]),
     ("psa_jobs_step_batch", _i32, [_P, _i32, ctypes.POINTER(_P), _i32]),
+    ("psa_jobs_energy_cut", _i32, [_P, _i32, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                   ctypes.POINTER(_P), _u32]),
     ("psa_anneal_batch", _i32, [_P, _i32, ctypes.POINTER(psa_batch_item), _u32]),
     ("psa_autotune", _i32, [_P, _P, ctypes.POINTER(psa_run_desc), _i32, _u32,
                             ctypes.POINTER(psa_tune_result)]),
@@ -566,6 +568,24 @@ def jobs_step_batch(ctx, jobs, k):
     """Advance several jobs by up to k steps each in one batched launch."""
     arr = (_P * len(jobs))(*[j.handle for j in jobs])
     _check(_lib.psa_jobs_step_batch(ctx.handle, len(jobs), arr, int(k)), "psa_jobs_step_batch")
+
+
+def jobs_energy_cut(ctx, jobs, energies=None, cuts=None):
+    """Energy and cut of several jobs in one batched read-out.  energies,
+    cuts: one int64 [trials] buffer per job (all host numpy or all device
+    torch), or None for new host arrays.  Returns (energies, cuts)."""
+    if energies is None:
+        energies = [np.zeros(j.trials, np.int64) for j in jobs]
+        cuts = [np.zeros(j.trials, np.int64) for j in jobs]
+    if len(energies) != len(jobs) or len(cuts) != len(jobs):
+        raise ValueError("one energy and one cut buffer per job")
+    flags = _flags_for(*energies, *cuts) if jobs else PSA_OUT_HOST
+    count = len(jobs)
+    arr = (_P * count)(*[j.handle for j in jobs])
+    ep = (_P * count)(*[_ptr(e) for e in energies])
+    cp = (_P * count)(*[_ptr(c) for c in cuts])
+    _check(_lib.psa_jobs_energy_cut(ctx.handle, count, arr, ep, cp, flags), "psa_jobs_energy_cut")
+    return energies, cuts
 
 
 def anneal_batch(ctx, items, sequential=False, spins=False):

@@ -327,3 +327,52 @@ def test_dense_identity_list_against_oracle(psa, ctx):
         got_E, got_C = jobs[i].energy_cut()
         np.testing.assert_array_equal(got_E, E)
         np.testing.assert_array_equal(got_C, C)
+
+
+def test_jobs_energy_cut_matches_each_job_and_oracle(psa, ctx):
+    """The batched energy / cut read-out of the mixed batch (uneven n and
+    trial counts, integer and large couplings, fields h) plus dense-path
+    jobs gives each job's own read-out, host and device outputs alike, and
+    the oracle's energy and cut of the same spins (a job listed twice, an
+    empty list)."""
+    import torch
+    mix = _mix()
+    jobs, edges = [], []
+    for n, u, v, j, h, T, S, seed, sig in mix:
+        g = psa.Graph.from_edges(ctx, n, u, v, j, h=h, maxcut=False)
+        i0 = _schedule(int(np.abs(j).max()) > 1000, S)
+        jobs.append(psa.Job(ctx, g, S, T, seed, i0=i0, sigma_lambda=sig[0], sigma_delta=sig[1],
+                            sigma_nu=sig[2], p_mean=sig[3]))
+        edges.append((n, u, v, j, h))
+    for (n, u, v, w), T in [(inputs.erdos_renyi(700, 0.2, 61), 64), (inputs.erdos_renyi(300, 0.3, 62), 6)]:
+        g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
+        jobs.append(psa.Job(ctx, g, 30, T, 7, path=psa.PSA_PATH_DENSE))
+        edges.append((n, u, v, -w, None))
+    psa.jobs_step_batch(ctx, jobs, 13)
+    listed = jobs + [jobs[3]]
+    hE, hC = psa.jobs_energy_cut(ctx, listed)
+    dE = [torch.zeros(j.trials, dtype=torch.int64, device="cuda") for j in listed]
+    dC = [torch.zeros(j.trials, dtype=torch.int64, device="cuda") for j in listed]
+    psa.jobs_energy_cut(ctx, listed, dE, dC)
+    ctx.synchronize()
+    for idx, job in enumerate(listed):
+        E, C = job.energy_cut()
+        np.testing.assert_array_equal(hE[idx], E, err_msg=f"job {idx}")
+        np.testing.assert_array_equal(hC[idx], C, err_msg=f"job {idx}")
+        np.testing.assert_array_equal(dE[idx].cpu().numpy(), E, err_msg=f"job {idx}")
+        np.testing.assert_array_equal(dC[idx].cpu().numpy(), C, err_msg=f"job {idx}")
+    for idx, job in enumerate(jobs):
+        n, u, v, j, h = edges[idx]
+        oE, oC = oracle.energy_cut(n, u, v, j, h, job.read_spins())
+        np.testing.assert_array_equal(hE[idx], oE, err_msg=f"job {idx}")
+        np.testing.assert_array_equal(hC[idx], oC, err_msg=f"job {idx}")
+    assert psa.jobs_energy_cut(ctx, []) == ([], [])
+    other = psa.Context(0)
+    n, u, v, w = inputs.torus(6, 7, 63)
+    g2 = psa.Graph.from_edges(other, n, u, v, w, maxcut=True)
+    j2 = psa.Job(other, g2, 10, 4, 1)
+    with pytest.raises(psa.PsaError):
+        psa.jobs_energy_cut(ctx, [jobs[0], j2])
+    j2.close()
+    g2.close()
+    other.close()
