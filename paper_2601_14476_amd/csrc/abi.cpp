@@ -1035,6 +1035,10 @@ psa_status psa_jobs_energy_cut(psa_ctx *ctx, int32_t count, psa_job *const *jobs
             e.t4 = job->run.t4;
             e.trials = job->run.trials;
             e.blocks = (e.n + 255) / 256;
+            // rows of mean degree 48 or more are read by 16 lanes, of 12 or
+            // more by 4 (contiguous column reads), sparser rows by one lane
+            const int64_t deg = e.n > 0 ? job->g->dev.nnz / e.n : 0;
+            e.lpr = deg >= 48 ? 16 : deg >= 12 ? 4 : 1;
             e.wg0 = static_cast<int32_t>(wgs);
             e.k0 = static_cast<int32_t>(trials);
             e.w2 = job->g->dev.w2;

@@ -350,10 +350,11 @@ hipError_t launch_energy_cut(hipStream_t stream, const DevGraph &g, const DevRun
 // One run of a batched energy / cut read-out: its graph and spins, its share
 // of the partial-sum buffer (energy_partial_bytes of it) and its outputs.
 // wg0: its first workgroup of the partial pass (energy_batch_wgs of them);
-// k0: its first thread of the final pass (one per trial).
+// k0: its first thread of the final pass (one per trial); lpr: lanes that
+// share a row in the partial pass (1, 4 or 16, by the mean degree).
 struct EnergyJob {
     int32_t n = 0, t4 = 0, trials = 0, blocks = 0;
-    int32_t wg0 = 0, k0 = 0;
+    int32_t wg0 = 0, k0 = 0, lpr = 1;
     int64_t w2 = 0;
     const int32_t *row_ptr = nullptr, *col = nullptr, *val = nullptr, *h = nullptr;
     const int8_t *spins = nullptr;

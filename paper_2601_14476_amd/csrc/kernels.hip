@@ -190,29 +190,38 @@ __device__ __forceinline__ int32_t energy_run_of(const EnergyJob *__restrict__ j
     return lo;
 }
 
-// Batched partial pass, sixteen trials per thread: workgroup (row block,
-// chunk y of four trial groups) sums the terms of groups 4y..4y+3 (those below
-// t4 / 4) into the same part entries as energy_partial, reading each edge's
+// Batched partial pass, sixteen trials per lane: workgroup (row block, chunk
+// y of four trial groups) sums the terms of groups 4y..4y+3 (those below
+// t4 / 4) into the same part entries as energy_partial.  LPR lanes share a
+// row: lane `sub` of a group takes the row's edges sub, sub + LPR, ... (so
+// the group's column and coupling reads are contiguous), reading each edge's
 // column and coupling once per 16 trials and, when t4 is a multiple of 16,
-// the neighbour's 16 spins in one load.  A row term is below 2^24 in
-// magnitude (the field bound), so a wavefront's sum of 64 fits int32; the
-// wavefronts' sums are added in int64.
+// the neighbour's 16 spins in one load.  Because S = sum_i m_i sum_j J_ij m_j
+// is linear in each row's inner sum, every lane multiplies its share of the
+// inner sum by m_i and keeps the products; the h terms are taken by lane 0 of
+// the group.  A group's rows are g, g + 256 / LPR, ... of the block.  A row's
+// terms are below 2^24 in magnitude (the field bound), so a lane's sum over
+// its LPR <= 16 rows fits int32; sums across lanes are taken in int64.
 constexpr int kEnergyQuads = 4;
 
+template <int LPR>
 __device__ __forceinline__ void energy_partial16(const EnergyJob &e, int32_t blk, int32_t y) {
     constexpr int Q = kEnergyQuads;
+    constexpr int kGroups = kEnergyBlock / LPR;
     const int32_t t4 = e.t4;
     const int32_t groups = t4 / 4;
     const int32_t q0 = y * Q;
     const int32_t nq = groups - q0 < Q ? groups - q0 : Q;  // workgroup-uniform
     const bool vec = (t4 & 15) == 0 && (reinterpret_cast<uintptr_t>(e.spins) & 15) == 0;
-    const int32_t i = blk * kEnergyBlock + threadIdx.x;
-    int32_t s[Q][4] = {}, hm[Q][4] = {};
-    if (i < e.n) {
+    const int32_t sub = threadIdx.x % LPR, grp = threadIdx.x / LPR;
+    int32_t s32[Q][4] = {}, hm32[Q][4] = {};
+    for (int32_t r = 0; r < LPR; ++r) {
+        const int32_t i = blk * kEnergyBlock + grp + kGroups * r;
+        if (i >= e.n) break;
         int32_t L[Q][4] = {};
         const int32_t e1 = e.row_ptr[i + 1];
 #pragma unroll 2
-        for (int32_t x = e.row_ptr[i]; x < e1; ++x) {
+        for (int32_t x = e.row_ptr[i] + sub; x < e1; x += LPR) {
             const int32_t j = e.col[x];
             const int32_t J = e.val[x];
             uint32_t w[Q] = {0u, 0u, 0u, 0u};
@@ -232,6 +241,7 @@ __device__ __forceinline__ void energy_partial16(const EnergyJob &e, int32_t blk
 #pragma unroll
                 for (int k = 0; k < 4; ++k) L[qq][k] += J * spin_of(w[qq], k);
         }
+        const int32_t hi = sub == 0 ? e.h[i] : 0;
 #pragma unroll
         for (int qq = 0; qq < Q; ++qq) {
             if (qq < nq) {
@@ -239,12 +249,20 @@ __device__ __forceinline__ void energy_partial16(const EnergyJob &e, int32_t blk
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const int32_t mi = spin_of(wi, k);
-                    s[qq][k] = mi * L[qq][k];
-                    hm[qq][k] = mi * e.h[i];
+                    s32[qq][k] += mi * L[qq][k];
+                    hm32[qq][k] += mi * hi;
                 }
             }
         }
     }
+    int64_t s[Q][4], hm[Q][4];
+#pragma unroll
+    for (int qq = 0; qq < Q; ++qq)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            s[qq][k] = s32[qq][k];
+            hm[qq][k] = hm32[qq][k];
+        }
     __shared__ int64_t red[kEnergyBlock / 64][Q][8];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -277,14 +295,20 @@ __device__ __forceinline__ void energy_partial16(const EnergyJob &e, int32_t blk
 }
 
 // Batched partial pass: workgroup b is (row block, chunk of four trial
-// groups) b - wg0 of its run, row block major.
+// groups) b - wg0 of its run, row block major; the run's lanes per row
+// (1, 4 or 16) pick the variant, uniform over the workgroup.
 __global__ __launch_bounds__(kEnergyBlock) void energy_partial_batch_kernel(const EnergyJob *__restrict__ jobs,
                                                                             int32_t count) {
     const int32_t b = blockIdx.x;
     const EnergyJob &e = jobs[energy_run_of<true>(jobs, count, b)];
     const int32_t chunks = (e.t4 / 4 + kEnergyQuads - 1) / kEnergyQuads;
     const int32_t local = b - e.wg0;
-    energy_partial16(e, local / chunks, local % chunks);
+    if (e.lpr >= 16)
+        energy_partial16<16>(e, local / chunks, local % chunks);
+    else if (e.lpr >= 4)
+        energy_partial16<4>(e, local / chunks, local % chunks);
+    else
+        energy_partial16<1>(e, local / chunks, local % chunks);
 }
 
 // Batched final pass: thread x is trial x - k0 of its run.

@@ -348,6 +348,16 @@ def test_jobs_energy_cut_matches_each_job_and_oracle(psa, ctx):
         g = psa.Graph.from_edges(ctx, n, u, v, w, maxcut=True)
         jobs.append(psa.Job(ctx, g, 30, T, 7, path=psa.PSA_PATH_DENSE))
         edges.append((n, u, v, -w, None))
+    # integer couplings and fields on rows of mean degree 30 and 93 (read by
+    # 4 and 16 lanes a row), the second with large couplings
+    rng = np.random.default_rng(64)
+    for n, m, scale, T in [(200, 3000, 1, 20), (150, 7000, 30000, 16)]:
+        _, u, v, _ = inputs.gnm(n, m, 64 + n)
+        j = (rng.integers(1, 4, size=u.size) * rng.choice([-1, 1], size=u.size) * scale).astype(np.int32)
+        h = (rng.integers(-5, 6, size=n) * max(1, scale // 15)).astype(np.int32)
+        g = psa.Graph.from_edges(ctx, n, u, v, j, h=h, maxcut=False)
+        jobs.append(psa.Job(ctx, g, 30, T, 9, i0=_schedule(scale > 1, 30)))
+        edges.append((n, u, v, j, h))
     psa.jobs_step_batch(ctx, jobs, 13)
     listed = jobs + [jobs[3]]
     hE, hC = psa.jobs_energy_cut(ctx, listed)
