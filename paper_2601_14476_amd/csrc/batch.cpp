@@ -566,8 +566,19 @@ psa_status psa_anneal_batch(psa_ctx *ctx, int32_t count, const psa_batch_item *i
             if ((st = psa_jobs_step_batch(ctx, count, jobs.data(), max_steps)) != PSA_OK) return st;
         }
         const uint32_t out = flags & PSA_OUT_DEVICE;
+        if (!(flags & PSA_BATCH_SEQUENTIAL)) {
+            // the batch's read-outs in two launches
+            std::vector<int64_t *> energy(static_cast<size_t>(count)), cut(static_cast<size_t>(count));
+            for (int32_t j = 0; j < count; ++j) {
+                energy[static_cast<size_t>(j)] = items[j].energy_out;
+                cut[static_cast<size_t>(j)] = items[j].cut_out;
+            }
+            if ((st = psa_jobs_energy_cut(ctx, count, jobs.data(), energy.data(), cut.data(), out)) != PSA_OK)
+                return st;
+        }
         for (int32_t j = 0; j < count; ++j) {
-            if ((st = psa_job_energy_cut(jobs[j], items[j].energy_out, items[j].cut_out, out)) != PSA_OK)
+            if ((flags & PSA_BATCH_SEQUENTIAL) &&
+                (st = psa_job_energy_cut(jobs[j], items[j].energy_out, items[j].cut_out, out)) != PSA_OK)
                 return st;
             if (items[j].spins_out &&
                 (st = psa_job_read_spins(jobs[j], items[j].spins_out, out)) != PSA_OK)

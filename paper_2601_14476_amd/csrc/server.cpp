@@ -214,11 +214,18 @@ psa_status admit_job(psa_server *s, ServerJob *j) {
     return PSA_OK;
 }
 
-// Results into the client's buffers (called without the lock).
-psa_status finish_job(ServerJob *j) {
-    psa_status st = psa_job_energy_cut(j->job, j->energy_out, j->cut_out, PSA_OUT_HOST);
-    if (st == PSA_OK && j->spins_out) st = psa_job_read_spins(j->job, j->spins_out, PSA_OUT_HOST);
-    return st;
+// Energies and cuts of the jobs that finished in one quantum into the
+// clients' buffers, in one batched read-out (called without the lock).
+psa_status finish_jobs(psa_server *s, const std::vector<ServerJob *> &done) {
+    std::vector<psa_job *> jobs;
+    std::vector<int64_t *> energy, cut;
+    for (ServerJob *j : done) {
+        jobs.push_back(j->job);
+        energy.push_back(j->energy_out);
+        cut.push_back(j->cut_out);
+    }
+    return psa_jobs_energy_cut(s->ctx, static_cast<int32_t>(jobs.size()), jobs.data(), energy.data(), cut.data(),
+                               PSA_OUT_HOST);
 }
 
 void scheduler_loop(psa_server *s) {
@@ -330,6 +337,7 @@ void scheduler_loop(psa_server *s) {
         std::string qmsg = st == PSA_OK ? "" : psa_last_error();
         // retire finished (or failed / canceled) jobs
         std::vector<std::pair<ServerJob *, psa_status>> retired;
+        std::vector<ServerJob *> finished;
         for (ServerJob *j : batch) {
             int32_t t = 0;
             psa_job_position(j->job, &t);
@@ -343,9 +351,18 @@ void scheduler_loop(psa_server *s) {
             } else if (cancel) {
                 retired.emplace_back(j, PSA_ECANCELED);
             } else if (t >= j->desc.steps) {
-                const psa_status fs = finish_job(j);
-                if (fs != PSA_OK) qmsg = psa_last_error();
-                retired.emplace_back(j, fs);
+                finished.push_back(j);
+            }
+        }
+        if (!finished.empty()) {
+            const psa_status fs = finish_jobs(s, finished);
+            if (fs != PSA_OK) qmsg = psa_last_error();
+            for (ServerJob *j : finished) {
+                psa_status js = fs;
+                if (js == PSA_OK && j->spins_out &&
+                    (js = psa_job_read_spins(j->job, j->spins_out, PSA_OUT_HOST)) != PSA_OK)
+                    qmsg = psa_last_error();
+                retired.emplace_back(j, js);
             }
         }
         for (auto &r : retired) release_device(r.first);
