@@ -364,6 +364,12 @@ __global__ __launch_bounds__(BLOCK) void period_resident_kernel(PeriodArgs a, co
             wmask |= upto & ~((1ull << lo) - 1ull);
         }
     }
+    // the mask is the same in every lane (built from lane reads of the
+    // wavefront's own slots); read it back through the scalar unit so that
+    // the per-sub-step test below is a scalar branch, not a divergent one
+    // with the execution mask saved and merged around the barrier
+    wmask = (static_cast<uint64_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(wmask >> 32))) << 32) |
+            static_cast<uint64_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(wmask)));
     __syncthreads();
     uint64_t prev = 0;  // the classes of the previous firing sub-step
     bool pf[K];
