@@ -463,8 +463,9 @@ psa_status psa_anneal_noalloc(psa_ctx *ctx, const psa_graph *g, const psa_run_de
  * kernel on the context's stream: one work item per (job, trial) -- or per
  * (job, group of four trials) for jobs created with trials_per_group 4 --
  * each workgroup dispatching to the kernel variant its job needs.  Jobs on
- * the dense path advance on a second stream, joined before return.  The
- * results are identical to stepping each job alone. */
+ * the dense path advance on a second stream (launched step by step, a second
+ * coupling encoding's jobs on a third stream beside it), joined before
+ * return.  The results are identical to stepping each job alone. */
 psa_status psa_jobs_step_batch(psa_ctx *ctx, int32_t count, psa_job *const *jobs,
                                int32_t k);
 

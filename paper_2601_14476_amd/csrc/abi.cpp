@@ -207,6 +207,9 @@ psa_status psa_ctx_create(int32_t device, void *hip_stream, psa_ctx **out) {
         PSA_HIP(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking), "hipStreamCreate");
         PSA_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "hipEventCreate");
         PSA_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "hipEventCreate");
+        PSA_HIP(hipStreamCreateWithFlags(&c->stream3, hipStreamNonBlocking), "hipStreamCreate");
+        PSA_HIP(hipEventCreateWithFlags(&c->ev_fork3, hipEventDisableTiming), "hipEventCreate");
+        PSA_HIP(hipEventCreateWithFlags(&c->ev_join3, hipEventDisableTiming), "hipEventCreate");
         *out = c.release();
         return PSA_OK;
     });
@@ -344,6 +347,7 @@ void ctx_release(psa_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->stream2) (void)hipStreamSynchronize(ctx->stream2);
+    if (ctx->stream3) (void)hipStreamSynchronize(ctx->stream3);
     if (ctx->d_batch_table) (void)hipFree(ctx->d_batch_table);
     if (ctx->d_energy_table) (void)hipFree(ctx->d_energy_table);
     if (ctx->d_batch_work) (void)hipFree(ctx->d_batch_work);
@@ -360,6 +364,9 @@ void ctx_release(psa_ctx *ctx) {
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->stream2) (void)hipStreamDestroy(ctx->stream2);
+    if (ctx->ev_fork3) (void)hipEventDestroy(ctx->ev_fork3);
+    if (ctx->ev_join3) (void)hipEventDestroy(ctx->ev_join3);
+    if (ctx->stream3) (void)hipStreamDestroy(ctx->stream3);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }

@@ -173,17 +173,17 @@ static void dense_work_list(const std::vector<DenseJob> &table, const std::vecto
         for (size_t q = 0; q < bins[x].size(); ++q) (*out)[q * kXcd + x] = bins[x][q];
 }
 
-// One dense step sequence on the context's second stream, launched step by
-// step: replayed from a captured graph of the same shape, captured now
-// (evicting the least recently used graph past kDenseGraphCache, after the
-// stream has drained), or -- use_graph false, or a single step -- launched one
-// by one.  *graph: it ran as a graph.
-static psa_status dense_sequence(psa_ctx *ctx, const DenseJob *table, const int4 *work, int32_t nwork,
-                                 int32_t nb, int32_t enc, int32_t mode, int32_t steps, bool use_graph,
-                                 bool *graph) {
+// One dense step sequence on stream s, launched step by step: replayed from a
+// captured graph of the same shape, captured now (evicting the least recently
+// used graph past kDenseGraphCache, after the stream has drained), or --
+// use_graph false, or a single step -- launched one by one.  *graph: it ran
+// as a graph.
+static psa_status dense_sequence(psa_ctx *ctx, hipStream_t s, const DenseJob *table, const int4 *work,
+                                 int32_t nwork, int32_t nb, int32_t enc, int32_t mode, int32_t steps,
+                                 bool use_graph, bool *graph) {
     *graph = false;
     if (!use_graph || steps < kDenseGraphMinSteps) {
-        PSA_HIP(launch_dense_steps(ctx->stream2, table, work, nwork, nb, enc, mode, steps), "dense step launch");
+        PSA_HIP(launch_dense_steps(s, table, work, nwork, nb, enc, mode, steps), "dense step launch");
         return PSA_OK;
     }
     auto &cache = ctx->dense_graph_cache;
@@ -192,10 +192,10 @@ static psa_status dense_sequence(psa_ctx *ctx, const DenseJob *table, const int4
                d.mode == mode && d.steps == steps;
     });
     if (it == cache.end()) {
-        PSA_HIP(hipStreamBeginCapture(ctx->stream2, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
-        const hipError_t le = launch_dense_steps(ctx->stream2, table, work, nwork, nb, enc, mode, steps);
+        PSA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+        const hipError_t le = launch_dense_steps(s, table, work, nwork, nb, enc, mode, steps);
         hipGraph_t g = nullptr;
-        const hipError_t ce = hipStreamEndCapture(ctx->stream2, &g);
+        const hipError_t ce = hipStreamEndCapture(s, &g);
         if (le != hipSuccess || ce != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
             PSA_HIP(le != hipSuccess ? le : ce, "dense step capture");
@@ -205,7 +205,7 @@ static psa_status dense_sequence(psa_ctx *ctx, const DenseJob *table, const int4
         (void)hipGraphDestroy(g);
         PSA_HIP(ie, "hipGraphInstantiate");
         if (cache.size() >= kDenseGraphCache) {
-            PSA_HIP(hipStreamSynchronize(ctx->stream2), "hipStreamSynchronize");
+            PSA_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
             (void)hipGraphExecDestroy(cache.front().exec);
             cache.erase(cache.begin());
         }
@@ -215,7 +215,7 @@ static psa_status dense_sequence(psa_ctx *ctx, const DenseJob *table, const int4
         std::rotate(it, it + 1, cache.end());  // most recently used last
         it = cache.end() - 1;
     }
-    PSA_HIP(hipGraphLaunch(it->exec, ctx->stream2), "hipGraphLaunch");
+    PSA_HIP(hipGraphLaunch(it->exec, s), "hipGraphLaunch");
     *graph = true;
     return PSA_OK;
 }
@@ -370,6 +370,19 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
     hipEvent_t ev = nullptr;
     if ((st = time_begin(ctx, ctx->stream2, &ev)) != PSA_OK) return st;
     int64_t launches = 0, replayed = 0;
+    // launched step by step, the sequences of a second (and third) encoding
+    // run on the third stream beside the first encoding's: a few runs of one
+    // encoding take latency-bound steps that would otherwise follow the
+    // other encoding's whole sequence (c4: 10 runs of 2-bit couplings, 10.6
+    // ms per 1,000 steps alone, after 67 ms of 126 runs of 1-bit ones)
+    int32_t present = 0;
+    for (int e = 0; e < kE; ++e) present += len[e] > 0 ? 1 : 0;
+    const bool side = how == kDenseLaunchSteps && present > 1;
+    if (side) {
+        PSA_HIP(hipEventRecord(ctx->ev_fork3, ctx->stream2), "hipEventRecord");
+        PSA_HIP(hipStreamWaitEvent(ctx->stream3, ctx->ev_fork3, 0), "hipStreamWaitEvent");
+    }
+    bool first = true;
     for (int e = 0; e < kE; ++e) {
         if (len[e] == 0) continue;
         const int32_t enc = e;
@@ -388,11 +401,17 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
             continue;
         }
         bool graph = false;
-        if ((st = dense_sequence(ctx, dtable, dwork + off[e], static_cast<int32_t>(len[e]), nb[e], enc, mode,
+        hipStream_t s = side && !first ? ctx->stream3 : ctx->stream2;
+        first = false;
+        if ((st = dense_sequence(ctx, s, dtable, dwork + off[e], static_cast<int32_t>(len[e]), nb[e], enc, mode,
                                  max_steps, how == kDenseLaunchGraph, &graph)) != PSA_OK)
             return st;
         launches += max_steps;
         replayed += graph ? max_steps : 0;
+    }
+    if (side) {
+        PSA_HIP(hipEventRecord(ctx->ev_join3, ctx->stream3), "hipEventRecord");
+        PSA_HIP(hipStreamWaitEvent(ctx->stream2, ctx->ev_join3, 0), "hipStreamWaitEvent");
     }
     if (ev) ctx->timed_graph_launches += replayed;
     if ((st = time_end(ctx, ctx->stream2, kTimeDense, ev, launches)) != PSA_OK) return st;

@@ -495,6 +495,10 @@ struct psa_ctx {
     // dense-path launches run on a second stream, joined with events
     hipStream_t stream2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // a second coupling encoding's step-by-step sequence runs on a third
+    // stream beside the first encoding's, forked from and joined to stream2
+    hipStream_t stream3 = nullptr;
+    hipEvent_t ev_fork3 = nullptr, ev_join3 = nullptr;
     void *d_dense_table = nullptr, *d_dense_work = nullptr;
     size_t dense_table_cap = 0, dense_work_cap = 0;
     std::vector<psa::DenseJob> h_dense_table;
