@@ -189,28 +189,43 @@ psa_status psa_ctx_create(int32_t device, void *hip_stream, psa_ctx **out) {
         // the static scratch of psa_anneal_noalloc: its address on this device
         psa_status sst = psa::noalloc_scratch_init(device);
         if (sst != PSA_OK) return sst;
-        std::unique_ptr<psa_ctx> c(new psa_ctx());
-        c->device = device;
-        PSA_HIP(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device),
-                "hipDeviceGetAttribute");
-        int lds = 0;
-        PSA_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device),
-                "hipDeviceGetAttribute");
-        c->max_lds = static_cast<size_t>(lds);
-        if (hip_stream) {
-            c->stream = static_cast<hipStream_t>(hip_stream);
-            c->own_stream = false;
-        } else {
-            PSA_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "hipStreamCreate");
-            c->own_stream = true;
+        psa_ctx *c = new psa_ctx();
+        // a failure part-way releases the streams and events made so far
+        auto init = [&]() -> psa_status {
+            c->device = device;
+            PSA_HIP(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device),
+                    "hipDeviceGetAttribute");
+            int lds = 0;
+            PSA_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device),
+                    "hipDeviceGetAttribute");
+            c->max_lds = static_cast<size_t>(lds);
+            if (hip_stream) {
+                c->stream = static_cast<hipStream_t>(hip_stream);
+                c->own_stream = false;
+            } else {
+                PSA_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "hipStreamCreate");
+                c->own_stream = true;
+            }
+            PSA_HIP(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking), "hipStreamCreate");
+            PSA_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "hipEventCreate");
+            PSA_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "hipEventCreate");
+            PSA_HIP(hipStreamCreateWithFlags(&c->stream3, hipStreamNonBlocking), "hipStreamCreate");
+            PSA_HIP(hipEventCreateWithFlags(&c->ev_fork3, hipEventDisableTiming), "hipEventCreate");
+            PSA_HIP(hipEventCreateWithFlags(&c->ev_join3, hipEventDisableTiming), "hipEventCreate");
+            return PSA_OK;
+        };
+        psa_status ist;
+        try {
+            ist = init();
+        } catch (...) {
+            psa::ctx_release(c);
+            throw;
         }
-        PSA_HIP(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking), "hipStreamCreate");
-        PSA_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "hipEventCreate");
-        PSA_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "hipEventCreate");
-        PSA_HIP(hipStreamCreateWithFlags(&c->stream3, hipStreamNonBlocking), "hipStreamCreate");
-        PSA_HIP(hipEventCreateWithFlags(&c->ev_fork3, hipEventDisableTiming), "hipEventCreate");
-        PSA_HIP(hipEventCreateWithFlags(&c->ev_join3, hipEventDisableTiming), "hipEventCreate");
-        *out = c.release();
+        if (ist != PSA_OK) {
+            psa::ctx_release(c);
+            return ist;
+        }
+        *out = c;
         return PSA_OK;
     });
 }
