@@ -373,8 +373,9 @@ psa_status dense_step_jobs(psa_ctx *ctx, psa_job *const *jobs, int32_t count, in
     // launched step by step, the sequences of a second (and third) encoding
     // run on the third stream beside the first encoding's: a few runs of one
     // encoding take latency-bound steps that would otherwise follow the
-    // other encoding's whole sequence (c4: 10 runs of 2-bit couplings, 10.6
-    // ms per 1,000 steps alone, after 67 ms of 126 runs of 1-bit ones)
+    // other encoding's whole sequence (in a mix of 256 graphs, 24 runs of
+    // 2-bit couplings took 15 ms per 1,000 steps alone, 127 runs of 1-bit
+    // ones 62-64 ms, and the two 72.7 ms side by side)
     int32_t present = 0;
     for (int e = 0; e < kE; ++e) present += len[e] > 0 ? 1 : 0;
     const bool side = how == kDenseLaunchSteps && present > 1;
