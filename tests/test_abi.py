@@ -170,3 +170,24 @@ def test_host_allocation_failure_is_a_status_not_a_crash(psa):
     assert int(st) == psa.PSA_ENOMEM, res.stdout
     assert "psa_graph_check_edges" in " ".join(msg) and "allocation" in " ".join(msg)
     assert int(st2) == psa.PSA_OK and int(edges) == 2
+
+
+def test_batched_calls_reject_a_null_context_on_the_host(psa):
+    """The batched step and read-out check their arguments before any device
+    call: a NULL context (with or without jobs, with a negative count or
+    unknown flags) is EINVAL with an error text naming the call, and an
+    empty list on a NULL context is still an error."""
+    lib = psa._lib
+    P = ctypes.c_void_p
+    cases = [
+        ("psa_jobs_energy_cut", lambda: lib.psa_jobs_energy_cut(None, 0, None, None, None, 0)),
+        ("psa_jobs_energy_cut", lambda: lib.psa_jobs_energy_cut(None, -1, None, None, None, 0)),
+        ("psa_jobs_energy_cut", lambda: lib.psa_jobs_energy_cut(None, 0, None, None, None, 0x80)),
+        ("psa_jobs_energy_cut", lambda: lib.psa_jobs_energy_cut(
+            None, 1, (P * 1)(None), (P * 1)(None), (P * 1)(None), 0)),
+        ("psa_jobs_step_batch", lambda: lib.psa_jobs_step_batch(None, 0, None, 1)),
+        ("psa_jobs_step_batch", lambda: lib.psa_jobs_step_batch(None, 1, (P * 1)(None), 1)),
+    ]
+    for name, call in cases:
+        assert call() == psa.PSA_EINVAL, name
+        assert name in lib.psa_last_error().decode()
